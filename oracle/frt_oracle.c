@@ -1,0 +1,709 @@
+/*
+ * FP64 CPU oracle for one time step of adaptive ray tracing of ionizing
+ * photon packets through a uniform Cartesian grid (Cain & D'Aloisio,
+ * "FlexRT I", §3 "Adaptive Ray Tracing Implementation" and §4.1 "Standard
+ * Mode"), with the backward-Euler hydrogen update and photon ledger that the
+ * GPU path also implements.
+ *
+ * TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may build, load or call this file.  It shares no code,
+ * header, table or helper with the HIP library; the two see the same seeded
+ * inputs and nothing else.
+ *
+ * Everything is IEEE double in cgs units (cm, s, photons), compiled without
+ * fast-math.  Nothing is blocked, fused or reordered beyond what the method
+ * states; rays are marched depth-first one at a time, which is one valid
+ * order of an order-independent sum.
+ *
+ * What pins each function (the tests under tests/test_oracle_*.py):
+ *   healpix_nest_center   count 12*4^l (Eq. Nray), nesting of children
+ *                         4p+i (Eq. lhpx), ring latitudes and equal area
+ *                         (Gorski et al. 2005), base-pixel golden table.
+ *   shoemake_rotation     orthonormality, det=+1, equality with the
+ *                         quaternion sandwich product, Haar angle law.
+ *   march_one_ray         per-cell path lengths and deposits against an
+ *                         independent slab-intersection computation and
+ *                         exact exp(-tau) transmission; optically thin limit
+ *                         (Eq. gamma_initial_subgrid); split radius against
+ *                         the footprint definition (Eq. r_split).
+ *   chemistry_be          residual of the implicit equation, alpha=0 closed
+ *                         form, Gamma=0 recombination, dt->inf equilibrium
+ *                         (Eq. equilibrium_condition), convergence to an
+ *                         ODE solver (Eq. ion_balance_eqn).
+ *   orc_step              photon ledger closure, Stromgren I-front
+ *                         (Eqs. r_of_t, rS, trec), checkpoint equality.
+ *   Whole-field values beyond these properties: parity unpinned (the paper
+ *   prints no per-cell numbers).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MAX_BINS 8
+
+/* ---------------------------------------------------------------- params */
+typedef struct {
+    int nx, ny, nz;          /* cells per axis */
+    double dx;               /* cell edge, cm */
+    int n_bins;              /* frequency bins, 1..8 */
+    double sigma[ORC_MAX_BINS]; /* HI cross-section per bin, cm^2 */
+    double alpha_B;          /* case-B recombination coefficient, cm^3/s */
+    double coll_ion;         /* collisional ionization coefficient, cm^3/s */
+    int base_level;          /* HEALPix level of cast rays (l_hpx) */
+    int max_level;           /* rays at this level never split */
+    double n_ray_min;        /* N_ray^min of Eq. r_split */
+    double flux_floor;       /* drop when sum N < floor * sum N_init; 0 = off */
+    double max_dist;         /* drop at this distance from the source, cm; 0 = off */
+    double c_ray;            /* packet speed, cm/s; +inf = finish within the step */
+    int n_chunks;            /* fixed source chunking for a deterministic sum */
+} orc_params;
+
+typedef struct {
+    double emitted, absorbed_HI, absorbed_sub, escaped, dropped, in_flight;
+    long long crossings, rays_emitted, splits, n_escaped, n_dropped, n_in_flight;
+} orc_ledger;
+
+/* Photon totals are sums of up to ~1e9 terms; they are accumulated with
+ * Neumaier's compensated summation so that the ledger closes to rounding
+ * level whatever the number of rays. */
+typedef struct { double s, c; } csum;
+
+static void csum_add(csum* a, double v)
+{
+    double t = a->s + v;
+    if (fabs(a->s) >= fabs(v)) a->c += (a->s - t) + v;
+    else a->c += (v - t) + a->s;
+    a->s = t;
+}
+
+static double csum_get(const csum* a) { return a->s + a->c; }
+
+typedef struct {
+    csum emitted, absorbed_HI, absorbed_sub, escaped, dropped;
+    long long crossings, rays_emitted, splits, n_escaped, n_dropped, n_in_flight;
+} chunk_ledger;
+
+/* One ray (photon packet).  Its position is always src + r * dir: children
+ * are re-centred on their own pixel directions at the split radius
+ * (§3.2), so the distance from the source fully fixes the position. */
+typedef struct {
+    int src;
+    int level;
+    long long pix;
+    double dir[3];
+    double R[9];             /* rotation of the emitting step, inherited (§3.1, §3.2) */
+    double r;                /* distance travelled from the source, cm */
+    double r_stop;           /* distance at which this step's travel budget ends */
+    double N[ORC_MAX_BINS];      /* photons carried per bin */
+    double Ninit[ORC_MAX_BINS];  /* photons at casting, divided by 4 per split */
+} orc_ray;
+
+typedef struct {
+    orc_ray* v;
+    long long n, cap;
+} orc_vec;
+
+typedef struct {
+    orc_params p;
+    long long ncell;
+    double* nH;              /* cm^-3 */
+    double* kappa;           /* sub-grid absorption coefficient, 1/cm */
+    double* x;               /* neutral fraction x_HI */
+    double* gamma;           /* last step's photo-ionization rate, 1/s */
+    int nsrc;
+    double* src_pos;         /* nsrc*3, cm */
+    double* ndot;            /* nsrc*n_bins, photons/s */
+    orc_vec* flight;         /* per-source in-flight packets carried between steps */
+    orc_ledger L;
+    long long step;
+    long long last_crossings;
+} orc_state;
+
+/* ------------------------------------------------------------- vectors */
+static int vec_push(orc_vec* a, const orc_ray* r)
+{
+    if (a->n == a->cap) {
+        long long nc = a->cap ? 2 * a->cap : 64;
+        orc_ray* nv = (orc_ray*)realloc(a->v, (size_t)nc * sizeof(orc_ray));
+        if (!nv) return -1;
+        a->v = nv;
+        a->cap = nc;
+    }
+    a->v[a->n++] = *r;
+    return 0;
+}
+
+/* ------------------------------------------------------------- HEALPix */
+/* Face layout of the 12 base pixels (Gorski et al. 2005, Fig. 3): the ring
+ * coordinate of each face's southern vertex in units of Nside, and the
+ * longitude of its centre in units of pi/4. */
+static const int FACE_RING[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
+static const int FACE_LON[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
+
+/* Take every second bit of v starting at bit `first` (0 or 1). */
+static long long take_alternate_bits(long long v, int first)
+{
+    long long out = 0;
+    int k = 0;
+    for (int b = first; b < 62; b += 2, k++)
+        if ((v >> b) & 1LL) out |= (1LL << k);
+    return out;
+}
+
+/* Map continuous face coordinates (a, b) in [0,1]^2 of face f onto the unit
+ * sphere.  rho = FACE_RING[f] - a - b is the ring coordinate (0 at the north
+ * pole, 4 at the south pole, in units of Nside); the polar caps (rho<1,
+ * rho>3) and the equatorial belt use the two HEALPix projections. */
+static void face_to_sphere(int f, double a, double b, double out[3])
+{
+    double rho = FACE_RING[f] - a - b;
+    double z, width;
+    if (rho < 1.0) {
+        z = 1.0 - rho * rho / 3.0;
+        width = rho;
+    } else if (rho > 3.0) {
+        double s = 4.0 - rho;
+        z = s * s / 3.0 - 1.0;
+        width = s;
+    } else {
+        z = (2.0 - rho) * 2.0 / 3.0;
+        width = 1.0;
+    }
+    double phi = (M_PI / 4.0) * (FACE_LON[f] + (a - b) / width);
+    double st = sqrt((1.0 - z) * (1.0 + z));
+    out[0] = st * cos(phi);
+    out[1] = st * sin(phi);
+    out[2] = z;
+}
+
+/* Unit vector of the centre of NESTED pixel p at level l (Nside = 2^l). */
+void healpix_nest_center(int level, long long p, double out[3])
+{
+    long long nside = 1LL << level;
+    long long per_face = nside * nside;
+    int f = (int)(p / per_face);
+    long long q = p % per_face;
+    long long ia = take_alternate_bits(q, 0);
+    long long ib = take_alternate_bits(q, 1);
+    face_to_sphere(f, (ia + 0.5) / (double)nside, (ib + 0.5) / (double)nside, out);
+}
+
+/* Inverse map for tests: the NESTED pixel containing unit vector v.  Each of
+ * the 12 faces is tried; the one whose face coordinates fall in [0,1)^2
+ * holds the point. */
+long long healpix_nest_pixel(int level, const double v[3])
+{
+    long long nside = 1LL << level;
+    double z = v[2];
+    double phi = atan2(v[1], v[0]);
+    if (phi < 0) phi += 2.0 * M_PI;
+    double rho, width;
+    if (z > 2.0 / 3.0) {
+        rho = sqrt(3.0 * (1.0 - z));
+        width = rho;
+    } else if (z < -2.0 / 3.0) {
+        width = sqrt(3.0 * (1.0 + z));
+        rho = 4.0 - width;
+    } else {
+        rho = 2.0 - 1.5 * z;
+        width = 1.0;
+    }
+    for (int f = 0; f < 12; f++) {
+        double lon = phi / (M_PI / 4.0) - FACE_LON[f];
+        while (lon >= 4.0) lon -= 8.0;
+        while (lon < -4.0) lon += 8.0;
+        double s = FACE_RING[f] - rho;     /* a + b */
+        double d = lon * width;            /* a - b */
+        double a = 0.5 * (s + d), b = 0.5 * (s - d);
+        if (a >= 0.0 && a < 1.0 && b >= 0.0 && b < 1.0) {
+            long long ia = (long long)floor(a * nside), ib = (long long)floor(b * nside);
+            long long q = 0;
+            for (int k = 0; k < 31; k++) {
+                q |= ((ia >> k) & 1LL) << (2 * k);
+                q |= ((ib >> k) & 1LL) << (2 * k + 1);
+            }
+            return (long long)f * nside * nside + q;
+        }
+    }
+    return -1;
+}
+
+/* ------------------------------------------------------------ rotation */
+/* Uniform random rotation from three uniforms (Shoemake 1992, "Uniform
+ * random rotations", Graphics Gems III): unit quaternion
+ *   x = sqrt(1-u1) sin(2 pi u2), y = sqrt(1-u1) cos(2 pi u2),
+ *   z = sqrt(u1) sin(2 pi u3),   w = sqrt(u1) cos(2 pi u3),
+ * turned into the row-major matrix of v -> q v q*.  §3.1 rotates each
+ * source's sphere by random angles every step; children keep them (§3.2). */
+void shoemake_rotation(const double u[3], double R[9])
+{
+    double s1 = sqrt(1.0 - u[0]), s2 = sqrt(u[0]);
+    double x = s1 * sin(2.0 * M_PI * u[1]);
+    double y = s1 * cos(2.0 * M_PI * u[1]);
+    double z = s2 * sin(2.0 * M_PI * u[2]);
+    double w = s2 * cos(2.0 * M_PI * u[2]);
+    R[0] = 1.0 - 2.0 * (y * y + z * z);
+    R[1] = 2.0 * (x * y - w * z);
+    R[2] = 2.0 * (x * z + w * y);
+    R[3] = 2.0 * (x * y + w * z);
+    R[4] = 1.0 - 2.0 * (x * x + z * z);
+    R[5] = 2.0 * (y * z - w * x);
+    R[6] = 2.0 * (x * z - w * y);
+    R[7] = 2.0 * (y * z + w * x);
+    R[8] = 1.0 - 2.0 * (x * x + y * y);
+}
+
+static void set_direction(orc_ray* ray)
+{
+    double n[3];
+    healpix_nest_center(ray->level, ray->pix, n);
+    for (int i = 0; i < 3; i++)
+        ray->dir[i] = ray->R[3 * i] * n[0] + ray->R[3 * i + 1] * n[1] + ray->R[3 * i + 2] * n[2];
+}
+
+/* ------------------------------------------------------------ geometry */
+/* Eq. r_split: distance from the source at which a level-l ray splits. */
+double split_radius(double dx, int level, double n_ray_min)
+{
+    return dx * ldexp(1.0, level) * sqrt(3.0 / (M_PI * n_ray_min));
+}
+
+/* Cell holding point `pos` for a ray moving along `dir`: floor per axis, and
+ * a point exactly on a cell face belongs to the cell the ray is entering. */
+static void locate(const orc_params* P, const double pos[3], const double dir[3], long long c[3])
+{
+    for (int a = 0; a < 3; a++) {
+        double u = pos[a] / P->dx;
+        double f = floor(u);
+        if (u == f && dir[a] < 0.0) f -= 1.0;
+        c[a] = (long long)f;
+    }
+}
+
+static int inside(const orc_params* P, const long long c[3])
+{
+    return c[0] >= 0 && c[0] < P->nx && c[1] >= 0 && c[1] < P->ny && c[2] >= 0 && c[2] < P->nz;
+}
+
+static double sum_bins(const double* v, int n)
+{
+    double s = 0.0;
+    for (int i = 0; i < n; i++) s += v[i];
+    return s;
+}
+
+/* ---------------------------------------------------------------- march */
+typedef struct {
+    const orc_state* S;
+    const double* nHI;       /* start-of-step neutral density snapshot */
+    double* gamma;           /* this chunk's photo-ionization accumulator */
+    chunk_ledger* L;
+    orc_vec* stack;          /* depth-first work list */
+    orc_vec* flight_out;     /* packets that end the step in flight */
+    double inv_vdt;          /* 1 / (V_cell dt) */
+} march_ctx;
+
+/* March one ray from its current radius until it is absorbed below the floor,
+ * reaches the distance cap, splits, leaves the box, or spends its travel
+ * budget (§3.1 packets, §3.2 splitting, §4.1 deposition).  Per segment of
+ * length ds in cell i and bin nu:
+ *   tau     = (n_HI sigma_nu + kappa) ds                    (Eq. tau_cell)
+ *   N_out   = N_in exp(-tau)
+ *   Gamma_i += N_in sigma_nu ds phi(tau) / (V dt),  phi(t) = (1 - e^-t)/t
+ * which equals N_in (1 - e^-tau)/(n_HI V dt) x (HI share of tau), i.e.
+ * Eq. gamma_initial_standard when kappa = 0 and Eq. gamma_avg_subgrid with
+ * lambda = 1/(n_HI sigma + kappa), and tends to Eq. gamma_initial_subgrid
+ * as tau -> 0. */
+static void march_one_ray(march_ctx* M, orc_ray* ray)
+{
+    const orc_params* P = &M->S->p;
+    const int nb = P->n_bins;
+    const double* o = M->S->src_pos + 3 * ray->src;
+    const double r_split = (ray->level < P->max_level) ? split_radius(P->dx, ray->level, P->n_ray_min) : INFINITY;
+    const double r_cap = (P->max_dist > 0.0) ? P->max_dist : INFINITY;
+    double pos[3];
+    long long c[3];
+    for (int a = 0; a < 3; a++) pos[a] = o[a] + ray->r * ray->dir[a];
+    locate(P, pos, ray->dir, c);
+    if (!inside(P, c)) {
+        csum_add(&M->L->escaped, sum_bins(ray->N, nb));
+        M->L->n_escaped++;
+        return;
+    }
+    for (;;) {
+        /* distance from the source to the face through which the ray leaves
+         * the current cell; lowest axis first on ties */
+        double r_face = INFINITY;
+        int axis = -1;
+        for (int a = 0; a < 3; a++) {
+            double rf = INFINITY;
+            if (ray->dir[a] > 0.0) rf = ((double)(c[a] + 1) * P->dx - o[a]) / ray->dir[a];
+            else if (ray->dir[a] < 0.0) rf = ((double)c[a] * P->dx - o[a]) / ray->dir[a];
+            if (rf < r_face) { r_face = rf; axis = a; }
+        }
+        double r_end = r_face;
+        if (r_split < r_end) r_end = r_split;
+        if (r_cap < r_end) r_end = r_cap;
+        if (ray->r_stop < r_end) r_end = ray->r_stop;
+        if (r_end < ray->r) r_end = ray->r;
+        double ds = r_end - ray->r;
+        if (ds > 0.0) {
+            long long i = c[0] + (long long)P->nx * (c[1] + (long long)P->ny * c[2]);
+            double nhi = M->nHI[i], kap = M->S->kappa[i];
+            double g = 0.0;
+            for (int k = 0; k < nb; k++) {
+                double tau_h = nhi * P->sigma[k] * ds;
+                double tau = tau_h + kap * ds;
+                double Nin = ray->N[k];
+                double Nout = Nin * exp(-tau);
+                double phi = (tau > 0.0) ? -expm1(-tau) / tau : 1.0;
+                g += Nin * P->sigma[k] * ds * phi;
+                double dA = Nin - Nout;
+                if (tau > 0.0) {
+                    csum_add(&M->L->absorbed_HI, dA * (tau_h / tau));
+                    csum_add(&M->L->absorbed_sub, dA * ((kap * ds) / tau));
+                }
+                ray->N[k] = Nout;
+            }
+            M->gamma[i] += g * M->inv_vdt;
+            M->L->crossings++;
+        }
+        ray->r = r_end;
+        /* end states, in this order */
+        if (ray->r >= r_cap) {
+            csum_add(&M->L->dropped, sum_bins(ray->N, nb));
+            M->L->n_dropped++;
+            return;
+        }
+        if (P->flux_floor > 0.0 && sum_bins(ray->N, nb) < P->flux_floor * sum_bins(ray->Ninit, nb)) {
+            csum_add(&M->L->dropped, sum_bins(ray->N, nb));
+            M->L->n_dropped++;
+            return;
+        }
+        if (ray->r >= r_split) {
+            /* four children (Eq. lhpx), photons shared equally, re-centred on
+             * their own pixel directions at this radius, same rotation */
+            M->L->splits++;
+            for (int k = 3; k >= 0; k--) {
+                orc_ray ch = *ray;
+                ch.level = ray->level + 1;
+                ch.pix = 4 * ray->pix + k;
+                for (int b = 0; b < nb; b++) {
+                    ch.N[b] = ray->N[b] / 4.0;
+                    ch.Ninit[b] = ray->Ninit[b] / 4.0;
+                }
+                set_direction(&ch);
+                vec_push(M->stack, &ch);
+            }
+            return;
+        }
+        if (ray->r >= r_face) {
+            c[axis] += (ray->dir[axis] > 0.0) ? 1 : -1;
+            if (!inside(P, c)) {
+                csum_add(&M->L->escaped, sum_bins(ray->N, nb));
+                M->L->n_escaped++;
+                return;
+            }
+        }
+        if (ray->r >= ray->r_stop) {
+            M->L->n_in_flight++;
+            vec_push(M->flight_out, ray);
+            return;
+        }
+    }
+}
+
+static void drain(march_ctx* M)
+{
+    while (M->stack->n > 0) {
+        orc_ray ray = M->stack->v[--M->stack->n];
+        march_one_ray(M, &ray);
+    }
+}
+
+/* ----------------------------------------------------------- chemistry */
+/* Backward-Euler update of the neutral fraction x = n_HI/n_H for pure H with
+ * n_e = n_HII = n_H (1-x), discretizing Eq. ion_balance_eqn (collisional
+ * term read as C n_e n_HI):
+ *   x' - x = dt [ -Gamma x' - C n_H (1-x') x' + alpha n_H (1-x')^2 ]
+ * i.e. a x'^2 + b x' + c = 0 with a = dt n_H (alpha + C),
+ * b = -(1 + dt (Gamma + 2 alpha n_H + C n_H)), c = x + alpha n_H dt.
+ * The root in [0,1] is the smaller one, written as 2c / (-b + sqrt(b^2-4ac))
+ * so that it stays accurate when x << 1 and when a = 0. */
+double chemistry_be(double x, double gamma, double nH, double alpha, double coll, double dt)
+{
+    double a = dt * nH * (alpha + coll);
+    double b = -(1.0 + dt * (gamma + 2.0 * alpha * nH + coll * nH));
+    double c = x + alpha * nH * dt;
+    double disc = b * b - 4.0 * a * c;
+    if (disc < 0.0) disc = 0.0;
+    return 2.0 * c / (-b + sqrt(disc));
+}
+
+/* ------------------------------------------------------------ state API */
+orc_state* orc_create(const orc_params* P, const float* nH, const float* kappa, const double* x0)
+{
+    if (!P || P->nx < 1 || P->ny < 1 || P->nz < 1 || P->n_bins < 1 || P->n_bins > ORC_MAX_BINS) return NULL;
+    orc_state* S = (orc_state*)calloc(1, sizeof(orc_state));
+    if (!S) return NULL;
+    S->p = *P;
+    if (S->p.n_chunks < 1) S->p.n_chunks = 16;
+    S->ncell = (long long)P->nx * P->ny * P->nz;
+    S->nH = (double*)malloc(sizeof(double) * S->ncell);
+    S->kappa = (double*)malloc(sizeof(double) * S->ncell);
+    S->x = (double*)malloc(sizeof(double) * S->ncell);
+    S->gamma = (double*)calloc(S->ncell, sizeof(double));
+    if (!S->nH || !S->kappa || !S->x || !S->gamma) return NULL;
+    for (long long i = 0; i < S->ncell; i++) {
+        S->nH[i] = nH[i];
+        S->kappa[i] = kappa ? kappa[i] : 0.0;
+        S->x[i] = x0 ? x0[i] : 1.0;
+    }
+    return S;
+}
+
+void orc_destroy(orc_state* S)
+{
+    if (!S) return;
+    if (S->flight) {
+        for (int s = 0; s < S->nsrc; s++) free(S->flight[s].v);
+        free(S->flight);
+    }
+    free(S->nH); free(S->kappa); free(S->x); free(S->gamma);
+    free(S->src_pos); free(S->ndot);
+    free(S);
+}
+
+int orc_set_sources(orc_state* S, int nsrc, const double* pos, const double* ndot)
+{
+    if (S->flight) {
+        for (int s = 0; s < S->nsrc; s++) free(S->flight[s].v);
+        free(S->flight);
+    }
+    free(S->src_pos); free(S->ndot);
+    S->nsrc = nsrc;
+    S->src_pos = (double*)malloc(sizeof(double) * 3 * (nsrc > 0 ? nsrc : 1));
+    S->ndot = (double*)malloc(sizeof(double) * S->p.n_bins * (nsrc > 0 ? nsrc : 1));
+    S->flight = (orc_vec*)calloc(nsrc > 0 ? nsrc : 1, sizeof(orc_vec));
+    if (!S->src_pos || !S->ndot || !S->flight) return -1;
+    memcpy(S->src_pos, pos, sizeof(double) * 3 * nsrc);
+    memcpy(S->ndot, ndot, sizeof(double) * S->p.n_bins * nsrc);
+    return 0;
+}
+
+/* One step of length dt.  u holds three uniforms per source for this step's
+ * sphere rotation.  Order: opacity snapshot, casting, march of every packet
+ * (carried and new), chemistry, ledger.  Sources are cut into n_chunks
+ * fixed chunks, each with its own Gamma buffer and ledger, summed in chunk
+ * order, so the result does not depend on the thread count. */
+int orc_step(orc_state* S, double dt, const double* u, int nthreads)
+{
+    const orc_params* P = &S->p;
+    const int nb = P->n_bins;
+    const int K = P->n_chunks;
+    const long long N = S->ncell;
+    double* nHI = (double*)malloc(sizeof(double) * N);
+    double* gk = (double*)calloc((size_t)K * N, sizeof(double));
+    chunk_ledger* Lk = (chunk_ledger*)calloc(K, sizeof(chunk_ledger));
+    orc_vec* new_flight = (orc_vec*)calloc(S->nsrc > 0 ? S->nsrc : 1, sizeof(orc_vec));
+    if (!nHI || !gk || !Lk || !new_flight) return -1;
+    for (long long i = 0; i < N; i++) nHI[i] = S->nH[i] * S->x[i];
+    const double V = P->dx * P->dx * P->dx;
+    const long long ncast = 12LL << (2 * P->base_level);
+    if (nthreads < 1) nthreads = 1;
+
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int k = 0; k < K; k++) {
+        orc_vec stack = {0, 0, 0};
+        march_ctx M;
+        M.S = S; M.nHI = nHI; M.gamma = gk + (size_t)k * N; M.L = Lk + k;
+        M.stack = &stack; M.inv_vdt = 1.0 / (V * dt);
+        int s0 = (int)(((long long)S->nsrc * k) / K), s1 = (int)(((long long)S->nsrc * (k + 1)) / K);
+        for (int s = s0; s < s1; s++) {
+            M.flight_out = &new_flight[s];
+            /* packets carried from the previous step get a fresh budget */
+            for (long long j = 0; j < S->flight[s].n; j++) {
+                orc_ray ray = S->flight[s].v[j];
+                ray.r_stop = ray.r + P->c_ray * dt;
+                march_one_ray(&M, &ray);
+                drain(&M);
+            }
+            /* casting on this step's rotated sphere (§3.1, Eq. Nray) */
+            double R[9];
+            shoemake_rotation(u + 3 * s, R);
+            for (long long p = 0; p < ncast; p++) {
+                orc_ray ray;
+                memset(&ray, 0, sizeof(ray));
+                ray.src = s; ray.level = P->base_level; ray.pix = p;
+                memcpy(ray.R, R, sizeof(R));
+                set_direction(&ray);
+                ray.r = 0.0;
+                ray.r_stop = P->c_ray * dt;
+                for (int b = 0; b < nb; b++) {
+                    ray.N[b] = S->ndot[(size_t)s * nb + b] * dt / (double)ncast;
+                    ray.Ninit[b] = ray.N[b];
+                    csum_add(&M.L->emitted, ray.N[b]);
+                }
+                M.L->rays_emitted++;
+                march_one_ray(&M, &ray);
+                drain(&M);
+            }
+        }
+        free(stack.v);
+    }
+
+    /* deterministic chunk-ordered reduction */
+    long long cross = 0;
+    for (long long i = 0; i < N; i++) {
+        double g = 0.0;
+        for (int k = 0; k < K; k++) g += gk[(size_t)k * N + i];
+        S->gamma[i] = g;
+    }
+    csum tot[5];
+    {
+        const double prev[5] = {S->L.emitted, S->L.absorbed_HI, S->L.absorbed_sub, S->L.escaped, S->L.dropped};
+        for (int j = 0; j < 5; j++) { tot[j].s = prev[j]; tot[j].c = 0.0; }
+    }
+    for (int k = 0; k < K; k++) {
+        csum_add(&tot[0], csum_get(&Lk[k].emitted));
+        csum_add(&tot[1], csum_get(&Lk[k].absorbed_HI));
+        csum_add(&tot[2], csum_get(&Lk[k].absorbed_sub));
+        csum_add(&tot[3], csum_get(&Lk[k].escaped));
+        csum_add(&tot[4], csum_get(&Lk[k].dropped));
+        S->L.crossings += Lk[k].crossings;
+        S->L.rays_emitted += Lk[k].rays_emitted;
+        S->L.splits += Lk[k].splits;
+        S->L.n_escaped += Lk[k].n_escaped;
+        S->L.n_dropped += Lk[k].n_dropped;
+        cross += Lk[k].crossings;
+    }
+    S->L.emitted = csum_get(&tot[0]);
+    S->L.absorbed_HI = csum_get(&tot[1]);
+    S->L.absorbed_sub = csum_get(&tot[2]);
+    S->L.escaped = csum_get(&tot[3]);
+    S->L.dropped = csum_get(&tot[4]);
+    S->last_crossings = cross;
+
+    /* carried packets replace the old list */
+    csum inflight = {0.0, 0.0};
+    long long nfl = 0;
+    for (int s = 0; s < S->nsrc; s++) {
+        free(S->flight[s].v);
+        S->flight[s] = new_flight[s];
+        for (long long j = 0; j < S->flight[s].n; j++) csum_add(&inflight, sum_bins(S->flight[s].v[j].N, nb));
+        nfl += S->flight[s].n;
+    }
+    S->L.in_flight = csum_get(&inflight);
+    S->L.n_in_flight = nfl;
+
+    /* chemistry closes the step */
+    for (long long i = 0; i < N; i++)
+        S->x[i] = chemistry_be(S->x[i], S->gamma[i], S->nH[i], P->alpha_B, P->coll_ion, dt);
+
+    S->step++;
+    free(nHI); free(gk); free(Lk); free(new_flight);
+    return 0;
+}
+
+/* Per-bin transmitted photons of one ray through the current field (no
+ * floor, no cap, no split), for the exact exp(-tau) test. */
+int orc_debug_transmit(orc_state* S, const double o[3], const double d[3], const double* N, double dt,
+                       double* gamma_out, double* N_exit)
+{
+    const orc_params* P = &S->p;
+    orc_state T = *S;
+    T.p.max_level = 0;
+    T.p.base_level = 0;
+    T.p.flux_floor = 0.0;
+    T.p.max_dist = 0.0;
+    double src[3] = {o[0], o[1], o[2]};
+    T.src_pos = src;
+    T.nsrc = 1;
+    double* nHI = (double*)malloc(sizeof(double) * S->ncell);
+    if (!nHI) return -1;
+    for (long long i = 0; i < S->ncell; i++) nHI[i] = S->nH[i] * S->x[i];
+    orc_vec stack = {0, 0, 0}, fl = {0, 0, 0};
+    chunk_ledger L;
+    memset(&L, 0, sizeof(L));
+    march_ctx M;
+    M.S = &T; M.nHI = nHI; M.gamma = gamma_out; M.L = &L; M.stack = &stack; M.flight_out = &fl;
+    M.inv_vdt = 1.0 / (P->dx * P->dx * P->dx * dt);
+    orc_ray ray;
+    memset(&ray, 0, sizeof(ray));
+    for (int a = 0; a < 3; a++) ray.dir[a] = d[a];
+    ray.r = 0.0; ray.r_stop = INFINITY;
+    for (int b = 0; b < P->n_bins; b++) { ray.N[b] = N[b]; ray.Ninit[b] = N[b]; }
+    /* march with the exit photons captured per bin */
+    orc_vec out = {0, 0, 0};
+    M.flight_out = &out;
+    march_one_ray(&M, &ray);
+    /* the ray object holds the photons it carried when it stopped */
+    for (int b = 0; b < P->n_bins; b++) N_exit[b] = ray.N[b];
+    free(stack.v); free(fl.v); free(out.v); free(nHI);
+    return (int)L.crossings;
+}
+
+/* ------------------------------------------------------------- readout */
+void orc_read(const orc_state* S, double* x, double* gamma)
+{
+    if (x) memcpy(x, S->x, sizeof(double) * S->ncell);
+    if (gamma) memcpy(gamma, S->gamma, sizeof(double) * S->ncell);
+}
+
+void orc_ledger_get(const orc_state* S, orc_ledger* L) { *L = S->L; }
+long long orc_last_crossings(const orc_state* S) { return S->last_crossings; }
+long long orc_step_index(const orc_state* S) { return S->step; }
+
+/* Checkpoint: neutral fraction, carried packets, ledger, step index. */
+long long orc_state_bytes(const orc_state* S)
+{
+    long long n = sizeof(long long) * 2 + sizeof(orc_ledger) + sizeof(double) * S->ncell;
+    for (int s = 0; s < S->nsrc; s++) n += sizeof(long long) + sizeof(orc_ray) * S->flight[s].n;
+    return n;
+}
+
+int orc_save(const orc_state* S, unsigned char* buf)
+{
+    unsigned char* p = buf;
+    long long hdr[2] = {S->step, S->nsrc};
+    memcpy(p, hdr, sizeof(hdr)); p += sizeof(hdr);
+    memcpy(p, &S->L, sizeof(orc_ledger)); p += sizeof(orc_ledger);
+    memcpy(p, S->x, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
+    for (int s = 0; s < S->nsrc; s++) {
+        long long n = S->flight[s].n;
+        memcpy(p, &n, sizeof(n)); p += sizeof(n);
+        memcpy(p, S->flight[s].v, sizeof(orc_ray) * n); p += sizeof(orc_ray) * n;
+    }
+    return 0;
+}
+
+int orc_load(orc_state* S, const unsigned char* buf)
+{
+    const unsigned char* p = buf;
+    long long hdr[2];
+    memcpy(hdr, p, sizeof(hdr)); p += sizeof(hdr);
+    if (hdr[1] != S->nsrc) return -1;
+    S->step = hdr[0];
+    memcpy(&S->L, p, sizeof(orc_ledger)); p += sizeof(orc_ledger);
+    memcpy(S->x, p, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
+    for (int s = 0; s < S->nsrc; s++) {
+        long long n;
+        memcpy(&n, p, sizeof(n)); p += sizeof(n);
+        free(S->flight[s].v);
+        S->flight[s].v = NULL; S->flight[s].n = 0; S->flight[s].cap = 0;
+        for (long long j = 0; j < n; j++) {
+            orc_ray r;
+            memcpy(&r, p, sizeof(r)); p += sizeof(r);
+            vec_push(&S->flight[s], &r);
+        }
+    }
+    return 0;
+}
+
+int orc_sizeof_ray(void) { return (int)sizeof(orc_ray); }
+int orc_sizeof_ledger(void) { return (int)sizeof(orc_ledger); }
+int orc_sizeof_params(void) { return (int)sizeof(orc_params); }

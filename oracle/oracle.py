@@ -1,0 +1,208 @@
+"""ctypes wrapper of the FP64 CPU oracle (oracle/frt_oracle.c).
+
+TEST INFRASTRUCTURE: only the tests, ``__graft_entry__.smoke()`` and the
+``cpu_baseline`` leg of ``bench.py`` may import this module.  It imports
+nothing from the GPU package; both sides receive the same seeded inputs.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "frt_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+MAX_BINS = 8
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc: -O2, OpenMP, IEEE double (no fast-math)."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-fno-fast-math", "-ffp-contract=off",
+                               "-fopenmp", "-fPIC", "-shared", "-D_DEFAULT_SOURCE",
+                               SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+class Params(C.Structure):
+    _fields_ = [("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int), ("dx", C.c_double),
+                ("n_bins", C.c_int), ("sigma", C.c_double * MAX_BINS),
+                ("alpha_B", C.c_double), ("coll_ion", C.c_double),
+                ("base_level", C.c_int), ("max_level", C.c_int), ("n_ray_min", C.c_double),
+                ("flux_floor", C.c_double), ("max_dist", C.c_double), ("c_ray", C.c_double),
+                ("n_chunks", C.c_int)]
+
+
+class Ledger(C.Structure):
+    _fields_ = [("emitted", C.c_double), ("absorbed_HI", C.c_double), ("absorbed_sub", C.c_double),
+                ("escaped", C.c_double), ("dropped", C.c_double), ("in_flight", C.c_double),
+                ("crossings", C.c_longlong), ("rays_emitted", C.c_longlong), ("splits", C.c_longlong),
+                ("n_escaped", C.c_longlong), ("n_dropped", C.c_longlong), ("n_in_flight", C.c_longlong)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        L = C.CDLL(LIB)
+        dp = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        fp = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+        L.orc_create.restype = C.c_void_p
+        L.orc_create.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_sources.argtypes = [C.c_void_p, C.c_int, dp, dp]
+        L.orc_step.argtypes = [C.c_void_p, C.c_double, dp, C.c_int]
+        L.orc_read.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
+        L.orc_ledger_get.argtypes = [C.c_void_p, C.POINTER(Ledger)]
+        L.orc_last_crossings.restype = C.c_longlong
+        L.orc_last_crossings.argtypes = [C.c_void_p]
+        L.orc_state_bytes.restype = C.c_longlong
+        L.orc_state_bytes.argtypes = [C.c_void_p]
+        L.orc_save.argtypes = [C.c_void_p, C.c_void_p]
+        L.orc_load.argtypes = [C.c_void_p, C.c_void_p]
+        L.healpix_nest_center.argtypes = [C.c_int, C.c_longlong, dp]
+        L.healpix_nest_pixel.restype = C.c_longlong
+        L.healpix_nest_pixel.argtypes = [C.c_int, dp]
+        L.shoemake_rotation.argtypes = [dp, dp]
+        L.split_radius.restype = C.c_double
+        L.split_radius.argtypes = [C.c_double, C.c_int, C.c_double]
+        L.chemistry_be.restype = C.c_double
+        L.chemistry_be.argtypes = [C.c_double] * 6
+        L.orc_debug_transmit.restype = C.c_int
+        L.orc_debug_transmit.argtypes = [C.c_void_p, dp, dp, dp, C.c_double, dp, dp]
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------- primitives
+def healpix_center(level: int, pix: int) -> np.ndarray:
+    out = np.zeros(3)
+    lib().healpix_nest_center(level, pix, out)
+    return out
+
+
+def healpix_centers(level: int) -> np.ndarray:
+    n = 12 * 4 ** level
+    return np.stack([healpix_center(level, p) for p in range(n)])
+
+
+def healpix_pixel(level: int, v) -> int:
+    return int(lib().healpix_nest_pixel(level, np.ascontiguousarray(v, dtype=np.float64)))
+
+
+def rotation(u) -> np.ndarray:
+    R = np.zeros(9)
+    lib().shoemake_rotation(np.ascontiguousarray(u, dtype=np.float64), R)
+    return R.reshape(3, 3)
+
+
+def split_radius(dx: float, level: int, n_ray_min: float) -> float:
+    return float(lib().split_radius(dx, level, n_ray_min))
+
+
+def chemistry(x, gamma, nH, alpha, coll, dt) -> float:
+    return float(lib().chemistry_be(x, gamma, nH, alpha, coll, dt))
+
+
+# ------------------------------------------------------------- the solver
+class Oracle:
+    """One RT problem on the CPU: grid, sources, carried packets, ledger."""
+
+    def __init__(self, shape, dx_cm, sigma_bins, alpha_B, n_H, kappa=None, x_HI0=None,
+                 coll_ion=0.0, base_level=0, max_level=12, n_ray_min=1.0, flux_floor=0.0,
+                 max_dist_cm=0.0, c_ray=np.inf, n_chunks=16):
+        nz, ny, nx = shape
+        sig = list(sigma_bins)
+        P = Params()
+        P.nx, P.ny, P.nz, P.dx = nx, ny, nz, dx_cm
+        P.n_bins = len(sig)
+        for i, s in enumerate(sig):
+            P.sigma[i] = s
+        P.alpha_B, P.coll_ion = alpha_B, coll_ion
+        P.base_level, P.max_level, P.n_ray_min = base_level, max_level, n_ray_min
+        P.flux_floor, P.max_dist, P.c_ray, P.n_chunks = flux_floor, max_dist_cm, c_ray, n_chunks
+        self.P = P
+        self.shape = (nz, ny, nx)
+        self.ncell = nx * ny * nz
+        self.n_bins = len(sig)
+        self._nH = np.ascontiguousarray(n_H, dtype=np.float32).reshape(-1)
+        self._kap = None if kappa is None else np.ascontiguousarray(kappa, dtype=np.float32).reshape(-1)
+        self._x0 = None if x_HI0 is None else np.ascontiguousarray(x_HI0, dtype=np.float64).reshape(-1)
+        assert self._nH.size == self.ncell
+        self.h = lib().orc_create(C.byref(P), self._nH.ctypes.data,
+                                  None if self._kap is None else self._kap.ctypes.data,
+                                  None if self._x0 is None else self._x0.ctypes.data)
+        if not self.h:
+            raise ValueError("oracle: invalid parameters")
+        self.n_src = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().orc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_sources(self, pos_cm, ndot_bins):
+        pos = np.ascontiguousarray(pos_cm, dtype=np.float64).reshape(-1, 3)
+        nd = np.ascontiguousarray(ndot_bins, dtype=np.float64).reshape(pos.shape[0], self.n_bins)
+        self.n_src = pos.shape[0]
+        if lib().orc_set_sources(self.h, self.n_src, pos.reshape(-1), nd.reshape(-1)) != 0:
+            raise MemoryError("oracle: set_sources")
+
+    def step(self, dt_s, uniforms, threads=None):
+        u = np.ascontiguousarray(uniforms, dtype=np.float64).reshape(-1)
+        assert u.size == 3 * self.n_src
+        if threads is None:
+            threads = os.cpu_count() or 1
+        if lib().orc_step(self.h, dt_s, u if u.size else np.zeros(3), int(threads)) != 0:
+            raise MemoryError("oracle: step")
+
+    def fields(self):
+        x = np.empty(self.ncell)
+        g = np.empty(self.ncell)
+        lib().orc_read(self.h, x.ctypes.data, g.ctypes.data)
+        return x.reshape(self.shape), g.reshape(self.shape)
+
+    def ledger(self) -> dict:
+        L = Ledger()
+        lib().orc_ledger_get(self.h, C.byref(L))
+        return L.as_dict()
+
+    def last_crossings(self) -> int:
+        return int(lib().orc_last_crossings(self.h))
+
+    def save(self) -> bytes:
+        n = int(lib().orc_state_bytes(self.h))
+        buf = C.create_string_buffer(n)
+        lib().orc_save(self.h, buf)
+        return buf.raw
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        if lib().orc_load(self.h, buf) != 0:
+            raise ValueError("oracle: state does not match this problem")
+
+    def transmit(self, origin_cm, direction, N_bins, dt_s=1.0):
+        """March one ray (no split, floor or cap) through the current field.
+        Returns (photons left per bin when it leaves the box, Gamma field, crossings)."""
+        g = np.zeros(self.ncell)
+        out = np.zeros(MAX_BINS)
+        N = np.zeros(MAX_BINS)
+        N[: self.n_bins] = N_bins
+        nc = lib().orc_debug_transmit(self.h, np.ascontiguousarray(origin_cm, dtype=np.float64),
+                                      np.ascontiguousarray(direction, dtype=np.float64), N, dt_s, g, out)
+        return out[: self.n_bins], g.reshape(self.shape), nc
