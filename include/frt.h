@@ -1,0 +1,171 @@
+/*
+ * frt.h — C ABI of the MI355X ray-tracing library (libfrt.so).
+ *
+ * Adaptive ray tracing of ionizing photon packets from point sources
+ * through a uniform Cartesian grid, after Cain & D'Aloisio, "FlexRT I"
+ * (§3 ray casting, transport and splitting; §4.1 deposition and the
+ * hydrogen ionization balance).  One step of length dt:
+ *   1. every source casts 12 * 4^L0 packets on its HEALPix sphere, rotated
+ *      at random each step (§3.1, Eq. Nray); packets carried from earlier
+ *      steps resume;
+ *   2. each packet walks cell by cell, losing exp(-tau) per cell with
+ *      tau = (n_HI sigma_nu + kappa_sub) ds (§4.1, Eq. tau_cell) and
+ *      depositing its absorbed photons into the cell's photo-ionization rate
+ *      (Eqs. gamma_initial_standard / gamma_avg_subgrid);
+ *   3. a packet splits into four children at r_split(l) (§3.2, Eqs. r_split,
+ *      lhpx), and ends when it leaves the box, falls below the flux floor,
+ *      reaches the distance cap, or has travelled c_ray * dt this step;
+ *   4. a backward-Euler update of the neutral fraction x_HI per cell closes
+ *      the step (Eq. ion_balance_eqn discretized implicitly).
+ *
+ * Conventions
+ *   - Every function returns an int status: FRT_OK (0) or a negative
+ *     FRT_E* code; frt_last_error() gives the calling thread's message for
+ *     the last failure.  No exception crosses the ABI.
+ *   - Grids are C order [z][y][x] (x fastest): cell (i,j,k) has index
+ *     i + nx*(j + ny*k) and spans [i dx, (i+1) dx) on x, etc.  Cells are
+ *     cubes of edge dx = box_cm / nx.
+ *   - Units are cgs: cm, s, cm^-3, cm^2, photons.
+ *   - ptr_kind FRT_HOST means host memory, FRT_DEVICE means memory of the
+ *     context's HIP device.  Inputs are always copied into buffers the
+ *     library owns; the caller keeps ownership of its arrays.
+ *   - Work is enqueued on the solve's HIP stream (the one given at
+ *     creation, else a stream the library creates).  Device-side failures
+ *     (queue overflow) surface at the next frt_sync / frt_read_* call.
+ *   - A solve handle is not thread-safe; different solves may be driven from
+ *     different threads.
+ */
+#ifndef FRT_H
+#define FRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FRT_OK 0
+#define FRT_EINVAL (-1)     /* invalid argument (sizes, NaN/negative input, source outside box) */
+#define FRT_ENOMEM (-2)     /* device or host allocation failed */
+#define FRT_EDEVICE (-3)    /* HIP runtime error */
+#define FRT_EOVERFLOW (-4)  /* ray queue exceeded queue_capacity; the step was not applied */
+#define FRT_ESTATE (-5)     /* call out of order (e.g. step before grid and sources are loaded) */
+
+#define FRT_HOST 0
+#define FRT_DEVICE 1
+
+#define FRT_F32 0           /* FP32 march, Kahan-compensated tau; FP64 chemistry and ledger */
+#define FRT_F64 1           /* FP64 march (validation) */
+
+#define FRT_MAX_BINS 8
+
+typedef struct frt_ctx_s* frt_ctx;
+typedef struct frt_solve_s* frt_solve;
+
+/* Parameters of one solve.  Set .size = sizeof(frt_params) and start from
+ * frt_params_default(). */
+typedef struct {
+    size_t size;
+    int n_bins;                     /* frequency bins, 1..FRT_MAX_BINS */
+    double sigma_bins[FRT_MAX_BINS];/* HI photo-ionization cross-section per bin, cm^2 (> 0) */
+    double alpha_B;                 /* recombination coefficient at the fixed T, cm^3/s */
+    double coll_ion;                /* collisional ionization coefficient, cm^3/s (default 0) */
+    int base_level;                 /* HEALPix level l_hpx of cast packets (§3.1), 0..8 */
+    int max_level;                  /* packets at this level never split, base_level..13 */
+    double n_ray_min;               /* N_ray^min of Eq. r_split (> 0; default 1) */
+    double flux_floor;              /* drop a packet when its photons fall below this fraction
+                                       of its cast photons (divided by 4 per split); 0 = off */
+    double max_distance_cm;         /* drop packets this far from their source; 0 = off */
+    double c_ray_cm_s;              /* packet speed; +INFINITY finishes every packet within its step */
+    int march_precision;            /* FRT_F32 (default) or FRT_F64 */
+    uint64_t seed;                  /* stream of the per-step random sphere rotations */
+    uint64_t queue_capacity;        /* entries per ray queue; 0 = sized automatically and grown
+                                       (the step is re-run) when a step overflows */
+} frt_params;
+
+/* Cumulative photon ledger (photons) and counters of one solve.  With
+ * E = emitted, the terms satisfy E = absorbed_HI + absorbed_sub + escaped
+ * + dropped + in_flight (+ lost, which is 0 unless a queue overflowed). */
+typedef struct {
+    double emitted, absorbed_HI, absorbed_sub, escaped, dropped, in_flight, lost;
+    uint64_t crossings;             /* cell crossings with ds > 0, all steps */
+    uint64_t ray_visits;            /* packet visits (one per packet per round) */
+    uint64_t splits, n_escaped, n_dropped, n_in_flight, rays_emitted;
+    uint64_t step_crossings;        /* crossings of the last step */
+    uint64_t steps;                 /* steps applied */
+    uint32_t err_flags;             /* device error bits (1 = queue overflow) */
+    uint32_t max_items;             /* largest round (work items) seen */
+} frt_ledger;
+
+/* Fill *p with defaults: 1 bin at 6.3e-18 cm^2, alpha_B = 2.59e-13,
+ * coll_ion = 0, base_level 0, max_level 12, n_ray_min 1, no floor, no cap,
+ * c_ray = speed of light, FRT_F32, seed 0, automatic queues. */
+int frt_params_default(frt_params* p);
+
+/* Context bound to HIP device `hip_device`.  Owns nothing else. */
+int frt_ctx_create(int hip_device, frt_ctx* out);
+int frt_ctx_destroy(frt_ctx ctx);
+
+/* Message of the calling thread's last failing call ("" if none). */
+const char* frt_last_error(void);
+
+/* A solve: one RT problem with its grid, sources, ray queues and ledger
+ * resident in HBM.  `hip_stream` is a hipStream_t to enqueue on, or NULL
+ * for a stream owned by the solve. */
+int frt_solve_create(frt_ctx ctx, const frt_params* params, void* hip_stream, frt_solve* out);
+int frt_solve_destroy(frt_solve s);
+
+/* Load the grid (§4.1 Standard Mode state, §4.2 sub-grid opacity):
+ * nx,ny,nz in 1..2048; box_cm > 0 is the x extent (cells are cubes);
+ * n_H [ncell] cm^-3 (finite, >= 0); T [ncell] K is stored for the caller
+ * and unused while T is fixed (may be NULL); kappa_sub [ncell] 1/cm
+ * (finite, >= 0; NULL = 0); x_HI0 [ncell] in [0,1] (NULL = 1).
+ * Resets the step counter, ledger and carried packets. */
+int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const float* n_H, const float* T,
+                  const float* kappa_sub, const double* x_HI0, int ptr_kind);
+
+/* Load n_src >= 0 point sources: pos_cm [n_src][3] (x,y,z) inside
+ * [0, n*dx] per axis; ndot_bins [n_src][n_bins] photons/s per bin (finite,
+ * >= 0).  Requires the grid.  Sizes the ray queues. */
+int frt_load_sources(frt_solve s, int n_src, const double* pos_cm, const double* ndot_bins, int ptr_kind);
+
+/* Optional table of rotation uniforms in [0,1): uniforms [n_steps][n_src][3]
+ * for steps 0..n_steps-1 (host memory).  Steps beyond the table use the
+ * library's counter-based generator: u = (splitmix64(splitmix64(seed) ^
+ * (step<<32 | src<<2 | k)) >> 11) * 2^-53.  A quaternion (w,x,y,z) =
+ * (sqrt(u0) cos 2pi u2, sqrt(1-u0) sin 2pi u1, sqrt(1-u0) cos 2pi u1,
+ * sqrt(u0) sin 2pi u2) rotates the source's sphere (Shoemake 1992). */
+int frt_set_rotations(frt_solve s, int n_steps, const double* uniforms);
+
+/* Enqueue one step of length dt_s > 0.  With automatic queues the call
+ * waits for the step and re-runs it with larger queues if it overflowed. */
+int frt_step(frt_solve s, double dt_s);
+
+/* Enqueue one step of each of n solves as one set of launches (the solves
+ * must share n_bins and march_precision).  dt_s[i] is solve i's step. */
+int frt_batch_step(frt_solve* solves, int n, const double* dt_s);
+
+/* Wait for the solve's stream; report deferred device errors. */
+int frt_sync(frt_solve s);
+
+/* Copy out x_HI [ncell] (double) and the last step's photo-ionization rate
+ * gamma [ncell] (float, 1/s).  Either pointer may be NULL.  Synchronizes. */
+int frt_read_fields(frt_solve s, double* x_HI, float* gamma, int ptr_kind);
+
+/* Copy out the ledger.  Synchronizes. */
+int frt_read_ledger(frt_solve s, frt_ledger* out);
+
+/* Checkpoint: x_HI, carried packets, ledger, step index and rotation state.
+ * With buf == NULL, *bytes receives the size needed. */
+int frt_save_state(frt_solve s, void* buf, size_t* bytes);
+int frt_load_state(frt_solve s, const void* buf, size_t bytes);
+
+/* Rotation uniforms the library would use for (step, src) — the same
+ * counter-based generator the device runs — for checking a table against. */
+int frt_rotation_uniforms(uint64_t seed, uint32_t step, uint32_t src, double out[3]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FRT_H */

@@ -1,0 +1,254 @@
+"""Thin ctypes binding of libfrt.so (include/frt.h).
+
+Argument marshalling only: every step of the ray-tracing path runs in the
+HIP library.  Arrays may be numpy (host) or torch CUDA tensors (device);
+PyTorch is used only for device memory and streams.  If the library has not
+been built, loading raises instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libfrt.so")
+
+FRT_OK, FRT_EINVAL, FRT_ENOMEM, FRT_EDEVICE, FRT_EOVERFLOW, FRT_ESTATE = 0, -1, -2, -3, -4, -5
+FRT_HOST, FRT_DEVICE = 0, 1
+FRT_F32, FRT_F64 = 0, 1
+MAX_BINS = 8
+
+# Symbols declared in include/frt.h.
+EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_error", "frt_solve_create",
+           "frt_solve_destroy", "frt_load_grid", "frt_load_sources", "frt_set_rotations", "frt_step",
+           "frt_batch_step", "frt_sync", "frt_read_fields", "frt_read_ledger", "frt_save_state",
+           "frt_load_state", "frt_rotation_uniforms")
+
+
+class FrtError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"frt error {code}: {msg}")
+        self.code = code
+
+
+class Params(C.Structure):
+    _fields_ = [("size", C.c_size_t), ("n_bins", C.c_int), ("sigma_bins", C.c_double * MAX_BINS),
+                ("alpha_B", C.c_double), ("coll_ion", C.c_double), ("base_level", C.c_int),
+                ("max_level", C.c_int), ("n_ray_min", C.c_double), ("flux_floor", C.c_double),
+                ("max_distance_cm", C.c_double), ("c_ray_cm_s", C.c_double), ("march_precision", C.c_int),
+                ("seed", C.c_uint64), ("queue_capacity", C.c_uint64)]
+
+
+class Ledger(C.Structure):
+    _fields_ = [("emitted", C.c_double), ("absorbed_HI", C.c_double), ("absorbed_sub", C.c_double),
+                ("escaped", C.c_double), ("dropped", C.c_double), ("in_flight", C.c_double),
+                ("lost", C.c_double), ("crossings", C.c_uint64), ("ray_visits", C.c_uint64),
+                ("splits", C.c_uint64), ("n_escaped", C.c_uint64), ("n_dropped", C.c_uint64),
+                ("n_in_flight", C.c_uint64), ("rays_emitted", C.c_uint64), ("step_crossings", C.c_uint64),
+                ("steps", C.c_uint64), ("err_flags", C.c_uint32), ("max_items", C.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def lib():
+    """Load libfrt.so (built by paper_2409_04521_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                              "(python -m paper_2409_04521_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.frt_last_error.restype = C.c_char_p
+        L.frt_params_default.argtypes = [C.POINTER(Params)]
+        L.frt_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.frt_ctx_destroy.argtypes = [vp]
+        L.frt_solve_create.argtypes = [vp, C.POINTER(Params), vp, C.POINTER(vp)]
+        L.frt_solve_destroy.argtypes = [vp]
+        L.frt_load_grid.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, vp, vp, vp, C.c_int]
+        L.frt_load_sources.argtypes = [vp, C.c_int, vp, vp, C.c_int]
+        L.frt_set_rotations.argtypes = [vp, C.c_int, vp]
+        L.frt_step.argtypes = [vp, C.c_double]
+        L.frt_batch_step.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_double)]
+        L.frt_sync.argtypes = [vp]
+        L.frt_read_fields.argtypes = [vp, vp, vp, C.c_int]
+        L.frt_read_ledger.argtypes = [vp, C.POINTER(Ledger)]
+        L.frt_save_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+        L.frt_load_state.argtypes = [vp, vp, C.c_size_t]
+        L.frt_rotation_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_double)]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != FRT_OK:
+        raise FrtError(rc, lib().frt_last_error().decode())
+
+
+def _ptr(a):
+    """(address, kind, keepalive) for a numpy array or torch tensor; None -> NULL."""
+    if a is None:
+        return None, FRT_HOST, None
+    if isinstance(a, np.ndarray):
+        if not a.flags["C_CONTIGUOUS"]:
+            a = np.ascontiguousarray(a)
+        return a.ctypes.data, FRT_HOST, a
+    import torch  # device tensors
+
+    if isinstance(a, torch.Tensor):
+        t = a.contiguous()
+        return t.data_ptr(), (FRT_DEVICE if t.is_cuda else FRT_HOST), t
+    raise TypeError(f"unsupported array type {type(a)}")
+
+
+def params_default() -> Params:
+    p = Params()
+    _check(lib().frt_params_default(C.byref(p)))
+    return p
+
+
+def rotation_uniforms(seed: int, step: int, src: int):
+    out = (C.c_double * 3)()
+    _check(lib().frt_rotation_uniforms(seed, step, src, out))
+    return np.array(out[:])
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        h = C.c_void_p()
+        _check(lib().frt_ctx_create(device, C.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().frt_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Solve:
+    """One RT problem resident on the device (frt_solve)."""
+
+    def __init__(self, ctx: Context, *, sigma_bins, alpha_B=2.59e-13, coll_ion=0.0, base_level=0,
+                 max_level=12, n_ray_min=1.0, flux_floor=0.0, max_distance_cm=0.0, c_ray=2.99792458e10,
+                 precision="f32", seed=0, queue_capacity=0, stream=None):
+        p = params_default()
+        sig = list(sigma_bins)
+        p.n_bins = len(sig)
+        for i, s in enumerate(sig):
+            p.sigma_bins[i] = s
+        p.alpha_B, p.coll_ion = alpha_B, coll_ion
+        p.base_level, p.max_level, p.n_ray_min = base_level, max_level, n_ray_min
+        p.flux_floor, p.max_distance_cm = flux_floor, max_distance_cm
+        p.c_ray_cm_s = c_ray if c_ray is not None else math.inf
+        p.march_precision = FRT_F64 if precision == "f64" else FRT_F32
+        p.seed, p.queue_capacity = seed, queue_capacity
+        self.ctx = ctx
+        self.params = p
+        self.n_bins = p.n_bins
+        self.shape = None
+        h = C.c_void_p()
+        _check(lib().frt_solve_create(ctx.h, C.byref(p), stream, C.byref(h)))
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().frt_solve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load_grid(self, n_H, box_cm, kappa=None, x_HI0=None, T=None):
+        shape = tuple(n_H.shape)
+        nz, ny, nx = shape
+        pn, kind, k1 = _ptr(n_H)
+        pk, _, k2 = _ptr(kappa)
+        px, _, k3 = _ptr(x_HI0)
+        pt, _, k4 = _ptr(T)
+        _check(lib().frt_load_grid(self.h, nx, ny, nz, box_cm, pn, pt, pk, px, kind))
+        self.shape = shape
+
+    def load_sources(self, pos_cm, ndot_bins):
+        pos = np.ascontiguousarray(pos_cm, dtype=np.float64).reshape(-1, 3) if isinstance(pos_cm, np.ndarray) else pos_cm
+        nd = np.ascontiguousarray(ndot_bins, dtype=np.float64) if isinstance(ndot_bins, np.ndarray) else ndot_bins
+        n = int(pos.shape[0])
+        pp, kind, k1 = _ptr(pos)
+        pd, _, k2 = _ptr(nd)
+        _check(lib().frt_load_sources(self.h, n, pp, pd, kind))
+
+    def set_rotations(self, uniforms):
+        u = np.ascontiguousarray(uniforms, dtype=np.float64)
+        _check(lib().frt_set_rotations(self.h, int(u.shape[0]), u.ctypes.data))
+
+    def step(self, dt_s: float):
+        _check(lib().frt_step(self.h, float(dt_s)))
+
+    def sync(self):
+        _check(lib().frt_sync(self.h))
+
+    def fields(self):
+        n = int(np.prod(self.shape))
+        x = np.empty(n)
+        g = np.empty(n, dtype=np.float32)
+        _check(lib().frt_read_fields(self.h, x.ctypes.data, g.ctypes.data, FRT_HOST))
+        return x.reshape(self.shape), g.reshape(self.shape)
+
+    def fields_into(self, x_dev=None, gamma_dev=None):
+        """Copy fields into device tensors (no host round trip)."""
+        px, kind, k1 = _ptr(x_dev)
+        pg, kind2, k2 = _ptr(gamma_dev)
+        _check(lib().frt_read_fields(self.h, px, pg, FRT_DEVICE))
+
+    def ledger(self) -> dict:
+        L = Ledger()
+        _check(lib().frt_read_ledger(self.h, C.byref(L)))
+        return L.as_dict()
+
+    def save(self) -> bytes:
+        n = C.c_size_t(0)
+        _check(lib().frt_save_state(self.h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().frt_save_state(self.h, buf, C.byref(n)))
+        return buf.raw[: n.value]
+
+    def load(self, blob: bytes):
+        buf = C.create_string_buffer(blob, len(blob))
+        _check(lib().frt_load_state(self.h, buf, len(blob)))
+
+
+def batch_step(solves, dts):
+    arr = (C.c_void_p * len(solves))(*[s.h for s in solves])
+    d = (C.c_double * len(solves))(*[float(x) for x in dts])
+    _check(lib().frt_batch_step(arr, len(solves), d))
+
+
+def solve_from_problem(ctx: Context, prob, precision="f32", use_table=True, **kw) -> Solve:
+    """Create and load a Solve from a workloads.Problem."""
+    s = Solve(ctx, sigma_bins=prob.sigma_bins, alpha_B=prob.alpha_B, coll_ion=prob.coll_ion,
+              base_level=prob.base_level, max_level=prob.max_level, n_ray_min=prob.n_ray_min,
+              flux_floor=prob.flux_floor, max_distance_cm=prob.max_dist_cm, c_ray=prob.c_ray,
+              precision=precision, seed=prob.seed, **kw)
+    nz, ny, nx = prob.shape
+    s.load_grid(prob.n_H, prob.dx_cm * nx, kappa=prob.kappa, x_HI0=prob.x_HI0, T=prob.T)
+    s.load_sources(prob.src_pos_cm, prob.ndot_bins)
+    if use_table and prob.n_src > 0:
+        from .workloads import rotation_table
+        s.set_rotations(rotation_table(prob.seed, 0, prob.n_steps, prob.n_src))
+    return s

@@ -1,0 +1,193 @@
+"""GPU (HIP, gfx950) versus the FP64 oracle on the same seeded inputs.
+
+Tolerances (from the FP32 march with FP64 chemistry): neutral fraction within
+1e-3 absolute in every cell, every photon-ledger term within 1e-4 of the
+emitted photons.  The FP64 march is held to 1e-9.  Every call goes through
+the C ABI (libfrt.so) via the ctypes binding."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2409_04521_amd import frt
+from paper_2409_04521_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TERMS = ("emitted", "absorbed_HI", "absorbed_sub", "escaped", "dropped", "in_flight")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return frt.Context(0)
+
+
+def _oracle(prob, steps):
+    o = O.Oracle(**prob.oracle_kwargs())
+    o.set_sources(prob.src_pos_cm, prob.ndot_bins)
+    for s in range(steps):
+        o.step(prob.dt_s, prob.uniforms(s))
+    return o
+
+
+def _gpu(ctx, prob, steps, precision="f32", use_table=True, **kw):
+    g = frt.solve_from_problem(ctx, prob, precision=precision, use_table=use_table, **kw)
+    for _ in range(steps):
+        g.step(prob.dt_s)
+    return g
+
+
+def _compare(o, g, x_tol, led_tol, label=""):
+    xo, go = o.fields()
+    xg, gg = g.fields()
+    dx = np.abs(xo - xg)
+    Lo, Lg = o.ledger(), g.ledger()
+    E = Lo["emitted"]
+    worst = {k: abs(Lo[k] - Lg[k]) / E for k in TERMS} if E > 0 else {}
+    print(f"[{label}] max|dx_HI| = {dx.max():.3e}  ledger rel = " +
+          ", ".join(f"{k}:{v:.1e}" for k, v in worst.items()) +
+          f"  crossings oracle={Lo['crossings']} gpu={Lg['crossings']}", flush=True)
+    assert dx.max() <= x_tol, f"{label}: neutral fraction differs by {dx.max():.3e} at {np.unravel_index(dx.argmax(), dx.shape)}"
+    for k, v in worst.items():
+        assert v <= led_tol, f"{label}: ledger term {k} differs by {v:.3e} of emitted"
+    closure = abs(Lg["emitted"] - sum(Lg[k] for k in TERMS[1:]) - Lg["lost"]) / max(Lg["emitted"], 1e-300)
+    assert closure <= 1e-9, f"{label}: GPU ledger does not close ({closure:.2e})"
+    assert Lg["err_flags"] == 0 and Lg["lost"] == 0
+    return xo, xg, go, gg
+
+
+@pytest.mark.parametrize("precision,x_tol,led_tol", [("f64", 1e-9, 1e-9), ("f32", 1e-3, 1e-4)])
+def test_stromgren_corner_source(ctx, precision, x_tol, led_tol):
+    p = W.stromgren_c1(n=32, n_steps=12)
+    o = _oracle(p, 12)
+    g = _gpu(ctx, p, 12, precision=precision)
+    xo, xg, go, gg = _compare(o, g, x_tol, led_tol, f"C1 32^3 {precision}")
+    # deposition itself, cell by cell, on the last step (the ABI hands the
+    # rate out as float32, hence 1e-6 for the FP64 march)
+    scale = go.max()
+    err = float(np.abs(go - gg).max())
+    assert err <= (1e-6 if precision == "f64" else 2e-3) * scale, f"gamma differs by {err:.3e} (scale {scale:.3e})"
+
+
+def test_stromgren_full_50_steps_f64(ctx):
+    p = W.stromgren_c1(n=32, n_steps=50)
+    _compare(_oracle(p, 50), _gpu(ctx, p, 50, precision="f64"), 1e-9, 1e-9, "C1 50 steps f64")
+
+
+@pytest.mark.parametrize("n,n_src,steps", [(24, 6, 8), (37, 11, 6)])
+def test_lognormal_subgrid_finite_c(ctx, n, n_src, steps):
+    # finite speed of light (packets carried between steps), 4 bins, kappa_sub,
+    # flux floor; 37^3 is a ragged size
+    p = W.lognormal_c2(n=n, n_src=n_src, n_steps=steps, box_cmpc_h=20.0 * n / 128)
+    _compare(_oracle(p, steps), _gpu(ctx, p, steps), 1e-3, 1e-4, f"C2-like {n}^3")
+
+
+def test_grf_throughput_form(ctx):
+    # highly ionized start, packets finish inside the step, distance cap
+    p = W.grf_c3(n=48, n_src=24, throughput=True, n_steps=2, box_cmpc_h=100.0 * 48 / 256)
+    _compare(_oracle(p, 2), _gpu(ctx, p, 2), 1e-3, 1e-4, "C3b-like 48^3")
+
+
+def test_grf_neutral_finite_c(ctx):
+    p = W.grf_c3(n=40, n_src=16, throughput=False, n_steps=5, box_cmpc_h=100.0 * 40 / 256)
+    _compare(_oracle(p, 5), _gpu(ctx, p, 5), 1e-3, 1e-4, "C3a-like 40^3")
+
+
+def test_non_cubic_grid_levels_and_nmin(ctx):
+    rng = np.random.Generator(np.random.PCG64(77))
+    shape = (13, 29, 21)
+    dx = W.cmpc_h_to_cm(0.15625)
+    nH = W.lognormal_white(rng, shape, 2e-4, 0.8).astype(np.float32)
+    pos = np.array([[3.5, 20.5, 6.5], [17.5, 2.5, 11.5], [0.5, 0.5, 0.5]]) * dx
+    w, sig = W.blackbody_bins(2)
+    ndot = np.array([3e51, 1e50, 4e52])[:, None] * w[None, :]
+    p = W.Problem(name="odd", shape=shape, dx_cm=dx, n_H=nH, x_HI0=np.full(shape, 0.3), kappa=None,
+                  src_pos_cm=pos, ndot_bins=ndot, sigma_bins=sig, dt_s=0.5 * W.MYR, n_steps=4,
+                  c_ray=W.C_LIGHT, flux_floor=1e-3, base_level=1, max_level=5, n_ray_min=2.0, seed=9)
+    _compare(_oracle(p, 4), _gpu(ctx, p, 4), 1e-3, 1e-4, "non-cubic L0=1 Nmin=2")
+
+
+def test_no_sources_is_pure_recombination(ctx):
+    p = W.stromgren_c1(n=8, n_steps=3)
+    p.src_pos_cm = np.zeros((0, 3))
+    p.ndot_bins = np.zeros((0, 1))
+    p.x_HI0 = np.full(p.shape, 0.25)
+    o = _oracle(p, 3)
+    g = _gpu(ctx, p, 3)
+    assert np.abs(o.fields()[0] - g.fields()[0]).max() <= 1e-12
+    assert g.ledger()["emitted"] == 0
+
+
+def test_single_cell_box_and_boundary_source(ctx):
+    shape = (1, 1, 1)
+    dx = 1e21
+    p = W.Problem(name="one", shape=shape, dx_cm=dx, n_H=np.full(shape, 1e-3, np.float32), x_HI0=np.ones(shape),
+                  kappa=None, src_pos_cm=np.array([[dx, 0.5 * dx, 0.25 * dx]]), ndot_bins=np.array([[1e49]]),
+                  sigma_bins=np.array([W.SIGMA_HI_0]), dt_s=1e13, n_steps=2, c_ray=math.inf, seed=4)
+    _compare(_oracle(p, 2), _gpu(ctx, p, 2, precision="f64"), 1e-9, 1e-9, "1-cell box")
+
+
+def test_no_split_when_max_level_is_base(ctx):
+    p = W.lognormal_c2(n=20, n_src=4, n_steps=3, box_cmpc_h=20.0 * 20 / 128)
+    p.max_level = 0
+    _compare(_oracle(p, 3), _gpu(ctx, p, 3), 1e-3, 1e-4, "max_level = 0")
+
+
+def test_internal_generator_equals_table(ctx):
+    p = W.lognormal_c2(n=20, n_src=5, n_steps=3, box_cmpc_h=20.0 * 20 / 128)
+    a = _gpu(ctx, p, 3, use_table=True)
+    b = _gpu(ctx, p, 3, use_table=False)
+    xa, _ = a.fields()
+    xb, _ = b.fields()
+    assert np.abs(xa - xb).max() <= 1e-6
+    assert a.ledger()["crossings"] == b.ledger()["crossings"]
+
+
+def test_checkpoint_resume(ctx):
+    p = W.lognormal_c2(n=20, n_src=5, n_steps=6, box_cmpc_h=20.0 * 20 / 128)
+    a = _gpu(ctx, p, 6)
+    b = _gpu(ctx, p, 3)
+    blob = b.save()
+    c = frt.solve_from_problem(ctx, p)
+    c.load(blob)
+    for _ in range(3):
+        c.step(p.dt_s)
+    assert np.abs(a.fields()[0] - c.fields()[0]).max() <= 1e-5
+    La, Lc = a.ledger(), c.ledger()
+    for k in TERMS:
+        assert abs(La[k] - Lc[k]) <= 1e-6 * La["emitted"]
+    assert La["crossings"] == Lc["crossings"]
+
+
+def test_batched_equals_alone(ctx):
+    boxes = W.batch_c4(n_boxes=5, n_steps=4, sizes=(16, 24, 32), max_src=12, seed=41)
+    alone = [_gpu(ctx, b, 4) for b in boxes]
+    batched = [frt.solve_from_problem(ctx, b) for b in boxes]
+    for _ in range(4):
+        frt.batch_step(batched, [b.dt_s for b in boxes])
+    for b, a, s in zip(boxes, alone, batched):
+        assert np.abs(a.fields()[0] - s.fields()[0]).max() <= 1e-5, b.name
+        La, Ls = a.ledger(), s.ledger()
+        for k in TERMS:
+            assert abs(La[k] - Ls[k]) <= 1e-6 * max(La["emitted"], 1e-300), (b.name, k)
+    # and the batch against the oracle for two of the boxes
+    for b, s in list(zip(boxes, batched))[:2]:
+        _compare(_oracle(b, 4), s, 1e-3, 1e-4, f"batched {b.name}")
+
+
+def test_invalid_inputs_are_rejected(ctx):
+    p = W.stromgren_c1(n=8)
+    s = frt.Solve(ctx, sigma_bins=[W.SIGMA_HI_0])
+    bad = p.n_H.copy()
+    bad[0, 0, 0] = np.nan
+    with pytest.raises(frt.FrtError) as e:
+        s.load_grid(bad, p.dx_cm * 8)
+    assert e.value.code == frt.FRT_EINVAL
+    s.load_grid(p.n_H, p.dx_cm * 8)
+    with pytest.raises(frt.FrtError) as e:
+        s.load_sources(np.array([[-1.0, 0, 0]]), np.array([[1e49]]))
+    assert e.value.code == frt.FRT_EINVAL
+    with pytest.raises(frt.FrtError) as e:
+        s.step(1e13)
+    assert e.value.code == frt.FRT_ESTATE
