@@ -1,0 +1,165 @@
+"""Benchmark of the ray-tracing step on one MI355X.
+
+Default workload: 256^3 grid, density exp of a k^-2.5 Gaussian random field
+(ln-sigma 1.5), 2000 sources on its highest peaks, highly ionized start
+(x_HI = 1e-4), packets finishing inside each step, 4 blackbody bins, flux
+floor 1e-3, distance cap 50 cMpc/h, level cap 12, FP32 march with FP64
+chemistry.  A step is one pass of the whole path: casting, every march
+round, chemistry and ledger.  Inputs are resident in HBM before timing.
+
+Prints one JSON line: crossings/s over the timed steps, the march kernel's
+roofline figures from HIP-event timing of its launches, and the FP64 oracle
+timed on a bounded sample of the same workload on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+METRIC = "cell crossings/s at 256^3 + p50/p99 solve latency, batched vs plain per-solve"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("frt_kernels.hip", "frt_internal.h"):
+        h.update(open(os.path.join(ROOT, "paper_2409_04521_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per march launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"march_{workload}_traffic.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def cpu_baseline(prob, n_sample: int, threads: int):
+    from oracle import oracle as O
+    from paper_2409_04521_amd import workloads as W
+
+    o = O.Oracle(**prob.oracle_kwargs(), n_chunks=max(threads, 1))
+    o.set_sources(prob.src_pos_cm[:n_sample], prob.ndot_bins[:n_sample])
+    t0 = time.perf_counter()
+    o.step(prob.dt_s, W.rotation_uniforms(prob.seed, 0, n_sample), threads=threads)
+    dt = time.perf_counter() - t0
+    cross = o.last_crossings()
+    return {"value": cross / dt, "unit": "crossings/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n_sample} of {prob.n_src} sources, full {prob.shape[2]}^3 grid, 1 step, "
+                      f"{cross} crossings in {dt:.1f} s (FP64 C oracle, OpenMP)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--sources", type=int, default=2000)
+    ap.add_argument("--cpu-sample", type=int, default=128)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form "
+              "(sources sharded over GPUs, one reduction of the rate field per step) is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2409_04521_amd import frt
+    from paper_2409_04521_amd import workloads as W
+
+    log("building inputs")
+    prob = W.grf_c3(n=args.n, n_src=args.sources, throughput=True, box_cmpc_h=100.0 * args.n / 256)
+    torch.cuda.init()
+    stream = torch.cuda.Stream()          # default priority; the library enqueues on it
+    torch.cuda.set_stream(stream)
+    ctx = frt.Context(0)
+    s = frt.solve_from_problem(ctx, prob, stream=stream.cuda_stream)
+    # Every step starts from the configured state (rewound on the device):
+    # from x_HI = 1e-4 the dense source cells recombine within one step
+    # (their Stromgren radii are below a tenth of a cell), after which every
+    # packet dies in its source cell, so only the first step from this state
+    # carries the workload's crossings.
+    s.mark()
+    log(f"loaded {prob.name}; warmup {args.warmup} step(s)")
+    for _ in range(args.warmup):
+        s.rewind()
+        s.step(prob.dt_s)
+        log(f"warmup step done: {s.ledger()['step_crossings']} crossings")
+    s.sync()
+    L0 = s.ledger()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for k in range(args.steps):
+        s.rewind()
+        s.step(prob.dt_s)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = ev0.elapsed_time(ev1)
+    L1 = s.ledger()
+    tm = s.timing()
+    cross = L1["crossings"] - L0["crossings"]
+    log(f"timed {args.steps} steps: {total_ms:.1f} ms, {cross} crossings, march {tm['march_ms']:.1f} ms "
+        f"over {tm['march_launches']} launches, chem {tm['chem_ms']:.2f} ms")
+    value = cross / (total_ms * 1e-3)
+
+    nb = prob.n_bins
+    rec = 24 + 8 * nb                                   # bytes of one queue entry
+    d_visits = L1["ray_visits"] - L0["ray_visits"]
+    rec += 8                                            # cell index and brick key
+    march_bytes = 12.0 * cross + 2.0 * rec * d_visits   # record read and written once per visit
+    closure = abs(L1["emitted"] - L1["absorbed_HI"] - L1["absorbed_sub"] - L1["escaped"] - L1["dropped"]
+                  - L1["in_flight"] - L1["lost"]) / L1["emitted"]
+    per_launch = march_bytes / max(tm["march_launches"], 1)
+    avg_launch_s = tm["march_ms"] * 1e-3 / max(tm["march_launches"], 1)
+    achieved = per_launch / avg_launch_s / 1e9
+    traffic = measured_traffic("c3b")
+    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
+            "kernel": "k_march", "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+            "algorithmic_bytes_per_launch": round(per_launch), "launches": tm["march_launches"]}
+
+    out = {"metric": METRIC, "value": value, "unit": "crossings/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{prob.name}: GRF k^-2.5 ln-sigma 1.5, peaks as sources, x_HI=1e-4, "
+                                  f"c=inf, {nb} bins, floor 1e-3, cap 50 cMpc/h, l_max 12",
+                      "cells": prob.ncell, "sources": prob.n_src, "crossings_per_step": cross / args.steps,
+                      "visits_per_step": d_visits / args.steps, "ledger_closure": closure,
+                      "steps_start_from": "the configured state, rewound on the device before each step",
+                      "parallelism": "single GPU"},
+           "roofline": roof,
+           "kernel_ms": {k: round(v, 3) for k, v in tm.items() if k.endswith("_ms")}}
+    if not args.no_cpu:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        log(f"cpu baseline: oracle on {args.cpu_sample} sources with {threads} threads")
+        out["cpu_baseline"] = cpu_baseline(prob, min(args.cpu_sample, prob.n_src), threads)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -161,6 +161,27 @@ int frt_read_ledger(frt_solve s, frt_ledger* out);
 int frt_save_state(frt_solve s, void* buf, size_t* bytes);
 int frt_load_state(frt_solve s, const void* buf, size_t bytes);
 
+/* Device-resident bookmark of the physical state: x_HI, the carried
+ * packets and the step index (with its rotation stream position).
+ * frt_rewind restores it with copies on the solve's stream only (no host
+ * wait), rebuilds the opacity and clears the pending deposits, so the same
+ * step can be repeated.  The ledger is not rewound: it keeps counting every
+ * step that ran.  Used to repeat one step from a fixed initial state. */
+int frt_mark(frt_solve s);
+int frt_rewind(frt_solve s);
+
+/* Per-kernel device time, measured with HIP events on the solve's stream
+ * around each launch while timing is enabled (cumulative since enabling).
+ * march_ms covers every march round; chem_ms the chemistry kernel; other_ms
+ * casting, round planning and step bookkeeping. */
+typedef struct {
+    double emit_ms, march_ms, chem_ms, other_ms;
+    uint64_t march_launches, chem_launches, steps;
+} frt_timing;
+
+int frt_set_timing(frt_solve s, int enable);
+int frt_read_timing(frt_solve s, frt_timing* out);   /* synchronizes */
+
 /* Rotation uniforms the library would use for (step, src) — the same
  * counter-based generator the device runs — for checking a table against. */
 int frt_rotation_uniforms(uint64_t seed, uint32_t step, uint32_t src, double out[3]);

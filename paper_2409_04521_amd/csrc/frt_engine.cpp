@@ -1,6 +1,7 @@
 // Host engine of the ray-tracing library: resident per-solve buffers in HBM,
-// step orchestration (casting, march rounds, chemistry, bookkeeping),
-// batches of solves, checkpoints and the C ABI declared in include/frt.h.
+// step orchestration (seeding, brick passes, chemistry, ledger folding),
+// batches of solves, queue growth, checkpoints and the C ABI declared in
+// include/frt.h.
 #include "frt.h"
 #include "frt_internal.h"
 
@@ -9,14 +10,12 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
-
-struct frt_ctx_s {
-    int device;
-};
 
 namespace {
 
@@ -39,6 +38,12 @@ int fail(int code, const char* fmt, ...)
         if (e_ != hipSuccess) return fail(FRT_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
+#define RCCHK(expr)            \
+    do {                       \
+        int rc_ = (expr);      \
+        if (rc_) return rc_;   \
+    } while (0)
+
 uint64_t mix64_host(uint64_t x)
 {
     uint64_t z = x + 0x9E3779B97F4A7C15ull;
@@ -48,81 +53,6 @@ uint64_t mix64_host(uint64_t x)
 }
 
 constexpr double PI = 3.14159265358979323846;
-
-}  // namespace
-
-struct frt_solve_s {
-    frt_ctx ctx = nullptr;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    frt_params P{};
-    int fp64 = 0;
-    size_t rs = 4;                     // bytes of one Real
-    // grid
-    bool have_grid = false, have_src = false;
-    int nx = 0, ny = 0, nz = 0;
-    double dx = 0;
-    size_t ncell = 0;
-    bool any_kappa = false;
-    // descriptor
-    FrtSolveDesc h{};
-    FrtSolveDesc* d_desc = nullptr;
-    // buffers
-    void* op = nullptr;
-    void* gam[2] = {nullptr, nullptr};
-    double* x = nullptr;
-    double* nH = nullptr;
-    float* T = nullptr;
-    double* src_pos = nullptr;
-    float* spec = nullptr;
-    double* specd = nullptr;
-    double* quat = nullptr;
-    uint32_t quat_steps = 0;
-    double* user_u = nullptr;
-    uint32_t user_steps = 0;
-    int n_src = 0;
-    uint32_t cap[FRT_NQ] = {0, 0, 0, 0};
-    uint32_t* count = nullptr;
-    FrtLedgerDev* L = nullptr;
-    FrtLedgerDev* L_snap = nullptr;
-    uint32_t* count_snap = nullptr;
-    uint32_t* emit_prefix = nullptr;
-    unsigned long long* cell_prefix = nullptr;
-    FrtRoundPlan* plan = nullptr;
-    uint32_t step = 0;
-    int rounds = 1;
-    double last_dt = 0;
-    std::vector<double> host_uniforms;  // user table kept for checkpoints
-
-    ~frt_solve_s() { release_all(); }
-
-    void release_queue(int k)
-    {
-        FrtQueue& q = h.q[k];
-        void* ptrs[] = {q.src, q.estep, q.lp, q.r, q.rstop, q.w0, q.tau, q.comp};
-        for (void* p : ptrs)
-            if (p) (void)hipFree(p);
-        q = FrtQueue{};
-        cap[k] = 0;
-    }
-
-    void release_all()
-    {
-        for (int k = 0; k < FRT_NQ; k++) release_queue(k);
-        void* ptrs[] = {d_desc, op, gam[0], gam[1], x, nH, T, src_pos, spec, specd, quat, user_u,
-                        count, L, L_snap, count_snap, emit_prefix, cell_prefix, plan};
-        for (void* p : ptrs)
-            if (p) (void)hipFree(p);
-        d_desc = nullptr; op = nullptr; gam[0] = gam[1] = nullptr; x = nullptr; nH = nullptr; T = nullptr;
-        src_pos = nullptr; spec = nullptr; specd = nullptr; quat = nullptr; user_u = nullptr; count = nullptr;
-        L = nullptr; L_snap = nullptr; count_snap = nullptr; emit_prefix = nullptr; cell_prefix = nullptr;
-        plan = nullptr;
-        if (own_stream && stream) (void)hipStreamDestroy(stream);
-        stream = nullptr;
-    }
-};
-
-namespace {
 
 int dev_alloc(void** p, size_t bytes)
 {
@@ -137,44 +67,199 @@ int dev_alloc(void** p, size_t bytes)
     return FRT_OK;
 }
 
-// Allocate one SoA queue of `cap` entries; if `keep` entries of the old
-// queue are to be preserved, copy them over.
-int alloc_queue(frt_solve s, int k, uint32_t capn, uint32_t keep)
+template <typename T>
+void dev_free(T*& p)
 {
-    FrtQueue nq{};
-    nq.cap = capn;
-    const int nb = s->P.n_bins;
-    const size_t n = std::max<uint32_t>(capn, 1);
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+void free_recs(FrtRecs& q)
+{
+    dev_free(q.src); dev_free(q.estep); dev_free(q.lp); dev_free(q.cell); dev_free(q.key);
+    dev_free(q.r); dev_free(q.rstop); dev_free(q.w0); dev_free(q.dir); dev_free(q.tau); dev_free(q.comp);
+    q.cap = 0;
+}
+
+int alloc_recs(FrtRecs& q, uint32_t cap, int nb, size_t rs)
+{
+    FrtRecs n{};
+    n.cap = cap;
+    const size_t c = std::max<uint32_t>(cap, 1);
     int rc;
-    if ((rc = dev_alloc((void**)&nq.src, n * 4)) || (rc = dev_alloc((void**)&nq.estep, n * 4)) ||
-        (rc = dev_alloc((void**)&nq.lp, n * 4)) || (rc = dev_alloc(&nq.r, n * s->rs)) ||
-        (rc = dev_alloc(&nq.rstop, n * s->rs)) || (rc = dev_alloc(&nq.w0, n * s->rs)) ||
-        (rc = dev_alloc(&nq.tau, n * s->rs * nb)) || (rc = dev_alloc(&nq.comp, n * s->rs * nb))) {
-        void* ptrs[] = {nq.src, nq.estep, nq.lp, nq.r, nq.rstop, nq.w0, nq.tau, nq.comp};
-        for (void* p : ptrs)
-            if (p) (void)hipFree(p);
+    if ((rc = dev_alloc((void**)&n.src, c * 4)) || (rc = dev_alloc((void**)&n.estep, c * 4)) ||
+        (rc = dev_alloc((void**)&n.lp, c * 4)) || (rc = dev_alloc((void**)&n.cell, c * 4)) ||
+        (rc = dev_alloc((void**)&n.key, c * 4)) || (rc = dev_alloc(&n.r, c * rs)) || (rc = dev_alloc(&n.rstop, c * rs)) ||
+        (rc = dev_alloc(&n.w0, c * rs)) || (rc = dev_alloc(&n.dir, c * rs * 3)) || (rc = dev_alloc(&n.tau, c * rs * nb)) ||
+        (rc = dev_alloc(&n.comp, c * rs * nb))) {
+        free_recs(n);
         return rc;
     }
-    FrtQueue& oq = s->h.q[k];
-    if (keep > 0 && oq.src) {
-        keep = std::min(keep, oq.cap);
-        HIPCHK(hipMemcpyAsync(nq.src, oq.src, keep * 4ull, hipMemcpyDeviceToDevice, s->stream));
-        HIPCHK(hipMemcpyAsync(nq.estep, oq.estep, keep * 4ull, hipMemcpyDeviceToDevice, s->stream));
-        HIPCHK(hipMemcpyAsync(nq.lp, oq.lp, keep * 4ull, hipMemcpyDeviceToDevice, s->stream));
-        HIPCHK(hipMemcpyAsync(nq.r, oq.r, keep * s->rs, hipMemcpyDeviceToDevice, s->stream));
-        HIPCHK(hipMemcpyAsync(nq.rstop, oq.rstop, keep * s->rs, hipMemcpyDeviceToDevice, s->stream));
-        HIPCHK(hipMemcpyAsync(nq.w0, oq.w0, keep * s->rs, hipMemcpyDeviceToDevice, s->stream));
-        for (int b = 0; b < nb; b++) {
-            HIPCHK(hipMemcpyAsync((char*)nq.tau + b * (size_t)capn * s->rs, (char*)oq.tau + b * (size_t)oq.cap * s->rs,
-                                  keep * s->rs, hipMemcpyDeviceToDevice, s->stream));
-            HIPCHK(hipMemcpyAsync((char*)nq.comp + b * (size_t)capn * s->rs, (char*)oq.comp + b * (size_t)oq.cap * s->rs,
-                                  keep * s->rs, hipMemcpyDeviceToDevice, s->stream));
-        }
-        HIPCHK(hipStreamSynchronize(s->stream));
+    q = n;
+    return FRT_OK;
+}
+
+// Copy the first n records of src into dst (arrays may differ in capacity).
+int copy_recs(FrtRecs& dst, const FrtRecs& src, uint32_t n, int nb, size_t rs, hipStream_t st, hipMemcpyKind k)
+{
+    if (!n) return FRT_OK;
+    HIPCHK(hipMemcpyAsync(dst.src, src.src, n * 4ull, k, st));
+    HIPCHK(hipMemcpyAsync(dst.estep, src.estep, n * 4ull, k, st));
+    HIPCHK(hipMemcpyAsync(dst.lp, src.lp, n * 4ull, k, st));
+    HIPCHK(hipMemcpyAsync(dst.cell, src.cell, n * 4ull, k, st));
+    HIPCHK(hipMemcpyAsync(dst.key, src.key, n * 4ull, k, st));
+    HIPCHK(hipMemcpyAsync(dst.r, src.r, n * rs, k, st));
+    HIPCHK(hipMemcpyAsync(dst.rstop, src.rstop, n * rs, k, st));
+    HIPCHK(hipMemcpyAsync(dst.w0, src.w0, n * rs, k, st));
+    for (int a = 0; a < 3; a++)
+        HIPCHK(hipMemcpyAsync((char*)dst.dir + a * (size_t)dst.cap * rs, (const char*)src.dir + a * (size_t)src.cap * rs,
+                              n * rs, k, st));
+    for (int b = 0; b < nb; b++) {
+        HIPCHK(hipMemcpyAsync((char*)dst.tau + b * (size_t)dst.cap * rs, (const char*)src.tau + b * (size_t)src.cap * rs,
+                              n * rs, k, st));
+        HIPCHK(hipMemcpyAsync((char*)dst.comp + b * (size_t)dst.cap * rs, (const char*)src.comp + b * (size_t)src.cap * rs,
+                              n * rs, k, st));
     }
-    s->release_queue(k);
-    s->h.q[k] = nq;
-    s->cap[k] = capn;
+    return FRT_OK;
+}
+
+}  // namespace
+
+// Per-context pass workspace, shared by the solves stepped on the context
+// (one step at a time: the mutex serializes launches that use it).
+struct Workspace {
+    int fp64 = -1, nb = 0;
+    FrtRecs O{}, P{};
+    uint32_t* ctr = nullptr;
+    uint32_t* hist = nullptr;
+    uint32_t* cursor = nullptr;
+    uint32_t nkeys_cap = 0;
+    FrtWork* work = nullptr;
+    uint32_t cap_work = 0;
+    uint32_t* key_prefix = nullptr;
+    uint32_t* seed_prefix = nullptr;
+    unsigned long long* cell_prefix = nullptr;
+    FrtSolveDesc* descs = nullptr;
+    int solves_cap = 0;
+
+    void release()
+    {
+        free_recs(O);
+        free_recs(P);
+        dev_free(ctr); dev_free(hist); dev_free(cursor); dev_free(work); dev_free(key_prefix);
+        dev_free(seed_prefix); dev_free(cell_prefix); dev_free(descs);
+        nkeys_cap = 0; cap_work = 0; solves_cap = 0; fp64 = -1; nb = 0;
+    }
+};
+
+struct frt_ctx_s {
+    int device = 0;
+    std::mutex mu;
+    Workspace ws;
+    ~frt_ctx_s() { ws.release(); }
+};
+
+struct frt_solve_s {
+    frt_ctx ctx = nullptr;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    frt_params P{};
+    int fp64 = 0;
+    size_t rs = 4;
+    int brick = FRT_BRICK_F32;
+    bool have_grid = false, have_src = false;
+    int nx = 0, ny = 0, nz = 0;
+    int bpx = 0, bpy = 0, bpz = 0;
+    double dx = 0;
+    size_t ncell = 0;
+    FrtSolveDesc h{};
+    FrtSolveDesc* d_desc = nullptr;
+    void* op = nullptr;
+    void* gam[2] = {nullptr, nullptr};
+    double* x = nullptr;
+    double* nH = nullptr;
+    float* T = nullptr;
+    double* src_pos = nullptr;
+    float* spec = nullptr;
+    double* specd = nullptr;
+    double* quat = nullptr;
+    uint32_t quat_steps = 0;
+    double* user_u = nullptr;
+    uint32_t user_steps = 0;
+    int n_src = 0;
+    FrtRecs F[2]{};
+    uint32_t* fcount = nullptr;
+    uint32_t* fcount_snap = nullptr;
+    FrtLedgerDev* L = nullptr;
+    FrtLedgerDev* L_snap = nullptr;
+    uint32_t step = 0;
+    // bookmark for frt_mark / frt_rewind
+    double* mark_x = nullptr;
+    uint32_t* mark_fc = nullptr;
+    FrtRecs mark_F{};
+    uint32_t mark_n = 0, mark_step = 0;
+    bool marked = false;
+    // kernel timing (HIP events around launches)
+    bool timing = false;
+    struct Ev { hipEvent_t a, b; int kind; };
+    std::vector<Ev> pending;
+    double t_ms[4] = {0, 0, 0, 0};          // seed, brick march, chem, other (scan, scatter, fold)
+    uint64_t n_march = 0, n_chem = 0, n_steps_timed = 0;
+
+    ~frt_solve_s() { release_all(); }
+
+    void drain_events()
+    {
+        for (auto& e : pending) {
+            float ms = 0.f;
+            if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) t_ms[e.kind] += ms;
+            (void)hipEventDestroy(e.a);
+            (void)hipEventDestroy(e.b);
+        }
+        pending.clear();
+    }
+
+    void reset_timing()
+    {
+        drain_events();
+        for (double& t : t_ms) t = 0;
+        n_march = n_chem = n_steps_timed = 0;
+    }
+
+    void release_all()
+    {
+        if (stream) (void)hipStreamSynchronize(stream);
+        drain_events();
+        free_recs(F[0]);
+        free_recs(F[1]);
+        free_recs(mark_F);
+        dev_free(mark_x);
+        dev_free(mark_fc);
+        dev_free(d_desc); dev_free(op); dev_free(gam[0]); dev_free(gam[1]); dev_free(x); dev_free(nH); dev_free(T);
+        dev_free(src_pos); dev_free(spec); dev_free(specd); dev_free(quat); dev_free(user_u); dev_free(fcount);
+        dev_free(fcount_snap); dev_free(L); dev_free(L_snap);
+        if (own_stream && stream) (void)hipStreamDestroy(stream);
+        stream = nullptr;
+    }
+};
+
+namespace {
+
+// Stream-ordered copy / fill followed by a wait on the solve's stream, so a
+// host-side transfer never races work already enqueued on that stream.
+int scopy(frt_solve s, void* dst, const void* src, size_t bytes, hipMemcpyKind kind)
+{
+    if (bytes == 0) return FRT_OK;
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, kind, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return FRT_OK;
+}
+
+int sset(frt_solve s, void* dst, int value, size_t bytes)
+{
+    if (bytes == 0) return FRT_OK;
+    HIPCHK(hipMemsetAsync(dst, value, bytes, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
     return FRT_OK;
 }
 
@@ -183,43 +268,21 @@ double split_radius_cells(const frt_params& P, int level)
     return std::ldexp(std::sqrt(3.0 / (PI * P.n_ray_min)), level);
 }
 
-// Number of march rounds a step needs: a packet can split at most once per
-// level it can still reach inside the box (or within the distance cap).
-int rounds_needed(frt_solve s)
+// Passes a step needs: along any lineage a visit ends at a brick boundary or
+// a split, so visits <= 3 (ceil(L/B) + 1) + splits + 1 with L the distance a
+// packet can cover in one step (travel budget, distance cap, box diagonal).
+int passes_needed(frt_solve s)
 {
     const double diag = std::sqrt((double)s->nx * s->nx + (double)s->ny * s->ny + (double)s->nz * s->nz);
     double reach = diag;
     if (s->P.max_distance_cm > 0) reach = std::min(reach, s->P.max_distance_cm / s->dx);
     int l = s->P.base_level;
     while (l < s->P.max_level && split_radius_cells(s->P, l) < reach) l++;
-    return l - s->P.base_level + 1;
-}
-
-// Initial queue sizes.  Split parents at level l sit at r_split(l) where each
-// covers dx^2 / N_min of the sphere; the part of that sphere inside the box
-// has at most the box's surface area, so a source contributes at most
-// min(12 4^l, N_min * 1.25 * surface) parents per round.
-void initial_caps(frt_solve s, uint64_t* capF, uint64_t* capS)
-{
-    const double surf = 2.0 * ((double)s->nx * s->ny + (double)s->ny * s->nz + (double)s->nx * s->nz);
-    const uint64_t ncast = 12ull << (2 * s->P.base_level);
-    const double per_src_area = s->P.n_ray_min * 1.25 * surf + 64.0;
-    double maxS = 0;
-    for (int l = s->P.base_level; l < s->P.base_level + s->rounds - 1; l++) {
-        double nl = std::min(std::ldexp(12.0, 2 * l), per_src_area);
-        maxS = std::max(maxS, nl);
-    }
-    double S = maxS * s->n_src;
-    double F = (double)ncast * s->n_src;
-    if (std::isfinite(s->P.c_ray_cm_s)) F += std::min(per_src_area * s->n_src, 4.0 * (double)s->ncell);
-    S = std::min(S, std::max(4.0 * (double)s->ncell, 4.0 * (double)ncast * s->n_src));
-    const double lim = 2147483647.0;
-    *capF = (uint64_t)std::min(lim, F + 1024);
-    *capS = (uint64_t)std::min(lim, S + 1024);
-    if (s->P.queue_capacity) {
-        *capF = std::max<uint64_t>(*capF > s->P.queue_capacity ? s->P.queue_capacity : *capF, ncast * s->n_src + 1);
-        *capS = s->P.queue_capacity;
-    }
+    const int splits = l - s->P.base_level;
+    double travel = reach;
+    if (std::isfinite(s->P.c_ray_cm_s)) travel = std::min(travel, s->P.c_ray_cm_s * s->h.dt / s->dx + 1.0);
+    const int cross = 3 * ((int)std::ceil(travel / s->brick) + 1);
+    return cross + 2 * splits + 6;
 }
 
 int ensure_quat(frt_solve s, uint32_t step)
@@ -227,11 +290,10 @@ int ensure_quat(frt_solve s, uint32_t step)
     if (step < s->quat_steps) return FRT_OK;
     uint32_t nsteps = std::max<uint32_t>(step + 1, std::max<uint32_t>(64, 2 * s->quat_steps));
     double* nq = nullptr;
-    int rc = dev_alloc((void**)&nq, (size_t)nsteps * std::max(1, s->n_src) * 4 * sizeof(double));
-    if (rc) return rc;
+    RCCHK(dev_alloc((void**)&nq, (size_t)nsteps * std::max(1, s->n_src) * 4 * sizeof(double)));
     if (s->quat && s->quat_steps) {
-        HIPCHK(hipMemcpyAsync(nq, s->quat, (size_t)s->quat_steps * s->n_src * 4 * sizeof(double),
-                              hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(hipMemcpyAsync(nq, s->quat, (size_t)s->quat_steps * s->n_src * 4 * sizeof(double), hipMemcpyDeviceToDevice,
+                              s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         (void)hipFree(s->quat);
     }
@@ -242,7 +304,6 @@ int ensure_quat(frt_solve s, uint32_t step)
     return FRT_OK;
 }
 
-// Per-step block of the descriptor.
 void set_step_fields(frt_solve s, double dt)
 {
     FrtSolveDesc& h = s->h;
@@ -261,17 +322,11 @@ void set_step_fields(frt_solve s, double dt)
 int check_inputs_finite(const float* v, size_t n, const char* what)
 {
     for (size_t i = 0; i < n; i++)
-        if (!std::isfinite(v[i]) || v[i] < 0.f) return fail(FRT_EINVAL, "%s[%zu] = %g is negative or not finite", what, i, (double)v[i]);
+        if (!std::isfinite(v[i]) || v[i] < 0.f)
+            return fail(FRT_EINVAL, "%s[%zu] = %g is negative or not finite", what, i, (double)v[i]);
     return FRT_OK;
 }
 
-int copy_in(void* dst, const void* src, size_t bytes, int kind, hipStream_t st)
-{
-    HIPCHK(hipMemcpyAsync(dst, src, bytes, kind == FRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
-    return FRT_OK;
-}
-
-// Host view of an input that may live on the device.
 template <typename T>
 int host_view(const T* p, size_t n, int kind, std::vector<T>& buf, const T** out)
 {
@@ -280,6 +335,7 @@ int host_view(const T* p, size_t n, int kind, std::vector<T>& buf, const T** out
         return FRT_OK;
     }
     buf.resize(n);
+    HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipMemcpy(buf.data(), p, n * sizeof(T), hipMemcpyDeviceToHost));
     *out = buf.data();
     return FRT_OK;
@@ -293,38 +349,8 @@ int upload_desc(frt_solve s)
 
 int read_device_ledger(frt_solve s, FrtLedgerDev* out)
 {
-    HIPCHK(hipMemcpyAsync(out, s->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipMemcpyAsync(out, s->L, offsetof(FrtLedgerDev, sd), hipMemcpyDeviceToHost, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
-    return FRT_OK;
-}
-
-// Enqueue one step for a set of solves that share n_bins and precision.
-// `d_descs` holds their descriptors contiguously on the device.
-int enqueue_steps(frt_solve* ss, int n, FrtSolveDesc* d_descs, uint32_t* d_emit_prefix,
-                  unsigned long long* d_cell_prefix, FrtRoundPlan* d_plan, hipStream_t st)
-{
-    const int nb = ss[0]->P.n_bins, fp64 = ss[0]->fp64;
-    uint32_t emit_total = 0;
-    unsigned long long cells = 0;
-    int rounds = 1;
-    for (int i = 0; i < n; i++) {
-        emit_total += (uint32_t)ss[i]->n_src * (12u << (2 * ss[i]->P.base_level));
-        cells += ss[i]->ncell;
-        rounds = std::max(rounds, ss[i]->rounds);
-    }
-    hipError_t e;
-    if ((e = frt::launch_emit(d_descs, d_emit_prefix, n, emit_total, fp64, st)) != hipSuccess)
-        return fail(FRT_EDEVICE, "emit launch: %s", hipGetErrorString(e));
-    for (int r = 0; r < rounds; r++) {
-        if ((e = frt::launch_round(d_descs, d_plan, n, r, fp64, st)) != hipSuccess)
-            return fail(FRT_EDEVICE, "plan launch: %s", hipGetErrorString(e));
-        if ((e = frt::launch_round_march(d_descs, d_plan, r, nb, fp64, st)) != hipSuccess)
-            return fail(FRT_EDEVICE, "march launch: %s", hipGetErrorString(e));
-    }
-    if ((e = frt::launch_chem(d_descs, d_cell_prefix, n, cells, fp64, st)) != hipSuccess)
-        return fail(FRT_EDEVICE, "chem launch: %s", hipGetErrorString(e));
-    if ((e = frt::launch_step_end(d_descs, n, st)) != hipSuccess)
-        return fail(FRT_EDEVICE, "step-end launch: %s", hipGetErrorString(e));
     return FRT_OK;
 }
 
@@ -333,6 +359,254 @@ int ready(frt_solve s)
     if (!s) return fail(FRT_EINVAL, "null solve");
     if (!s->have_grid || !s->have_src) return fail(FRT_ESTATE, "load the grid and the sources before stepping");
     return FRT_OK;
+}
+
+// Initial carried-queue size: casting plus, for packets moving at a finite
+// speed, room for many carried packets (grown on overflow).
+uint32_t initial_fcap(frt_solve s)
+{
+    const double cast = (double)s->n_src * (12ull << (2 * s->P.base_level));
+    double F = cast + 1024;
+    if (std::isfinite(s->P.c_ray_cm_s)) F += std::min((double)s->ncell, 8.0 * cast + 65536.0);
+    if (s->P.queue_capacity) F = (double)s->P.queue_capacity;
+    return (uint32_t)std::min(F, 2147483647.0);
+}
+
+// Make the context workspace fit a launch of `n` solves with `nkeys` brick
+// keys and at least `want_p` sorted records per pass.
+int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t want_p)
+{
+    const size_t rs = fp64 ? 8 : 4;
+    if (ws.fp64 != fp64 || ws.nb != nb) {
+        free_recs(ws.O);
+        free_recs(ws.P);
+        ws.fp64 = fp64;
+        ws.nb = nb;
+    }
+    want_p = std::min<uint64_t>(want_p, 2147483647ull);
+    if (ws.P.cap < want_p) {
+        free_recs(ws.O);
+        free_recs(ws.P);
+        RCCHK(alloc_recs(ws.O, (uint32_t)want_p, nb, rs));
+        RCCHK(alloc_recs(ws.P, (uint32_t)want_p, nb, rs));
+        dev_free(ws.work);
+        ws.cap_work = 0;
+    }
+    if (!ws.ctr) RCCHK(dev_alloc((void**)&ws.ctr, C_NCTR * 4));
+    if (ws.nkeys_cap < nkeys) {
+        dev_free(ws.hist);
+        dev_free(ws.cursor);
+        ws.nkeys_cap = 0;
+        uint32_t c = std::max<uint32_t>(nkeys, 4096);
+        RCCHK(dev_alloc((void**)&ws.hist, c * 4ull));
+        RCCHK(dev_alloc((void**)&ws.cursor, c * 4ull));
+        HIPCHK(hipMemset(ws.hist, 0, c * 4ull));
+        HIPCHK(hipDeviceSynchronize());
+        ws.nkeys_cap = c;
+        dev_free(ws.work);
+        ws.cap_work = 0;
+    }
+    const uint64_t want_work = (uint64_t)ws.P.cap / FRT_ITEM_RAYS + ws.nkeys_cap + 64;
+    if (ws.cap_work < want_work) {
+        dev_free(ws.work);
+        RCCHK(dev_alloc((void**)&ws.work, want_work * sizeof(FrtWork)));
+        ws.cap_work = (uint32_t)want_work;
+    }
+    if (ws.solves_cap < n) {
+        dev_free(ws.key_prefix); dev_free(ws.seed_prefix); dev_free(ws.cell_prefix); dev_free(ws.descs);
+        int c = std::max(n, 64);
+        RCCHK(dev_alloc((void**)&ws.key_prefix, (c + 1) * 4ull));
+        RCCHK(dev_alloc((void**)&ws.seed_prefix, (c + 1) * 4ull));
+        RCCHK(dev_alloc((void**)&ws.cell_prefix, (c + 1) * 8ull));
+        RCCHK(dev_alloc((void**)&ws.descs, c * sizeof(FrtSolveDesc)));
+        ws.solves_cap = c;
+    }
+    return FRT_OK;
+}
+
+// Event pair around a launch when the timing solve has timing enabled.
+struct Timed {
+    frt_solve t;
+    hipStream_t st;
+    hipEvent_t a = nullptr, b = nullptr;
+    int kind;
+    Timed(frt_solve t_, hipStream_t s_, int k) : t(t_), st(s_), kind(k)
+    {
+        if (t && t->timing && hipEventCreate(&a) == hipSuccess && hipEventCreate(&b) == hipSuccess)
+            (void)hipEventRecord(a, st);
+        else
+            a = b = nullptr;
+    }
+    ~Timed()
+    {
+        if (a && b) {
+            (void)hipEventRecord(b, st);
+            t->pending.push_back({a, b, kind});
+        }
+    }
+};
+
+// Enqueue one step of n solves (same n_bins and precision) on stream st.
+int enqueue_group(Workspace& ws, frt_solve* ss, int n, hipStream_t st)
+{
+    const int nb = ss[0]->P.n_bins, fp64 = ss[0]->fp64;
+    frt_solve tm = ss[0]->timing ? ss[0] : nullptr;
+    std::vector<uint32_t> kp(n + 1);
+    std::vector<unsigned long long> cp(n + 1);
+    std::vector<FrtSolveDesc> hd(n);
+    kp[0] = 0;
+    cp[0] = 0;
+    int passes = 1;
+    for (int i = 0; i < n; i++) {
+        frt_solve s = ss[i];
+        s->h.key_base = kp[i];
+        hd[i] = s->h;
+        kp[i + 1] = kp[i] + (uint32_t)(s->bpx * s->bpy * s->bpz);
+        cp[i + 1] = cp[i] + s->ncell;
+        passes = std::max(passes, passes_needed(s));
+    }
+    HIPCHK(hipMemcpyAsync(ws.descs, hd.data(), n * sizeof(FrtSolveDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws.key_prefix, kp.data(), (n + 1) * 4ull, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws.cell_prefix, cp.data(), (n + 1) * 8ull, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(ws.ctr, 0, C_NCTR * 4, st));
+    HIPCHK(hipMemsetAsync(ws.hist, 0, kp[n] * 4ull, st));
+    FrtWS w{};
+    w.O = ws.O;
+    w.P = ws.P;
+    w.ctr = ws.ctr;
+    w.hist = ws.hist;
+    w.cursor = ws.cursor;
+    w.work = ws.work;
+    w.cap_work = ws.cap_work;
+    w.nkeys = kp[n];
+    w.key_prefix = ws.key_prefix;
+    w.seed_prefix = ws.seed_prefix;
+    w.n_solves = n;
+    w.n_bins = nb;
+    if (ss[0]->P.queue_capacity) {
+        // fixed capacities: the shared workspace is used up to the solves' limit
+        uint64_t lim = 0;
+        for (int i = 0; i < n; i++) lim += ss[i]->P.queue_capacity;
+        const uint32_t c = (uint32_t)std::min<uint64_t>(lim, w.P.cap);
+        w.O.cap = c;
+        w.P.cap = c;
+    }
+    hipError_t e;
+    {
+        Timed t(tm, st, 0);
+        if ((e = frt::launch_seed(ws.descs, w, fp64, st)) != hipSuccess) return fail(FRT_EDEVICE, "seed: %s", hipGetErrorString(e));
+    }
+    for (int p = 0; p < passes; p++) {
+        {
+            Timed t(tm, st, 3);
+            if ((e = frt::launch_pass(ws.descs, w, fp64, 0, st)) != hipSuccess) return fail(FRT_EDEVICE, "scan: %s", hipGetErrorString(e));
+            if ((e = frt::launch_pass(ws.descs, w, fp64, 1, st)) != hipSuccess) return fail(FRT_EDEVICE, "scatter: %s", hipGetErrorString(e));
+        }
+        Timed t(tm, st, 1);
+        if ((e = frt::launch_pass(ws.descs, w, fp64, 2, st)) != hipSuccess) return fail(FRT_EDEVICE, "march: %s", hipGetErrorString(e));
+        if (tm) tm->n_march++;
+    }
+    {
+        Timed t(tm, st, 3);
+        if ((e = frt::launch_finish(ws.descs, w, st)) != hipSuccess) return fail(FRT_EDEVICE, "finish: %s", hipGetErrorString(e));
+    }
+    {
+        Timed t(tm, st, 2);
+        if ((e = frt::launch_chem(ws.descs, ws.cell_prefix, n, cp[n], fp64, st)) != hipSuccess)
+            return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
+        if (tm) tm->n_chem++;
+    }
+    if (tm) tm->n_steps_timed++;
+    return FRT_OK;
+}
+
+// One step of a group with automatic queue growth: snapshot, run, check,
+// and on overflow restore the starting state, enlarge and run again.
+int step_group(frt_solve* ss, int n, const double* dts)
+{
+    frt_ctx ctx = ss[0]->ctx;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    Workspace& ws = ctx->ws;
+    hipStream_t st = ss[0]->stream;
+    const bool auto_grow = ss[0]->P.queue_capacity == 0;
+    uint32_t nkeys = 0;
+    uint64_t want_p = 0;
+    for (int i = 0; i < n; i++) {
+        frt_solve s = ss[i];
+        RCCHK(ensure_quat(s, s->step));
+        set_step_fields(s, dts[i]);
+        nkeys += (uint32_t)(s->bpx * s->bpy * s->bpz);
+        const uint64_t cast = (uint64_t)s->n_src * (12ull << (2 * s->P.base_level));
+        want_p += s->P.queue_capacity ? s->P.queue_capacity : std::max<uint64_t>(4 * cast + 65536, s->ncell / 2);
+    }
+    for (int attempt = 0; attempt < 16; attempt++) {
+        RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.P.cap)));
+        for (int i = 0; i < n; i++) {
+            HIPCHK(hipMemcpyAsync(ss[i]->L_snap, ss[i]->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(ss[i]->fcount_snap, ss[i]->fcount, 8, hipMemcpyDeviceToDevice, st));
+        }
+        RCCHK(enqueue_group(ws, ss, n, st));
+        if (!auto_grow) {
+            for (int i = 0; i < n; i++) ss[i]->step++;
+            return FRT_OK;
+        }
+        uint32_t ctr[C_NCTR];
+        HIPCHK(hipMemcpyAsync(ctr, ws.ctr, sizeof(ctr), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        bool f_over = false;
+        std::vector<uint32_t> fneed(n, 0);
+        for (int i = 0; i < n; i++) {
+            uint32_t fc[2];
+            HIPCHK(hipMemcpy(fc, ss[i]->fcount, 8, hipMemcpyDeviceToHost));
+            const uint32_t nxt = fc[1 - (ss[i]->step & 1u)];
+            if (nxt > ss[i]->F[0].cap) {
+                f_over = true;
+                fneed[i] = nxt;
+            }
+        }
+        const bool over = (ctr[C_ERR] & FRT_DEVERR_QUEUE_OVERFLOW) || f_over;
+        if (!over) {
+            if (ctr[C_ERR] & FRT_DEVERR_UNFINISHED) return fail(FRT_EDEVICE, "a step left packets after its last pass");
+            for (int i = 0; i < n; i++) ss[i]->step++;
+            return FRT_OK;
+        }
+        // restore every solve of the group to the start of the step
+        for (int i = 0; i < n; i++) {
+            frt_solve s = ss[i];
+            if (s->timing) s->reset_timing();
+            HIPCHK(hipMemcpyAsync(s->L, s->L_snap, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(s->fcount, s->fcount_snap, 8, hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemsetAsync(s->gam[s->step & 1u], 0, s->ncell * s->rs, st));
+        }
+        HIPCHK(hipStreamSynchronize(st));
+        // enlarge what overflowed
+        if (ctr[C_ERR] & FRT_DEVERR_QUEUE_OVERFLOW) {
+            const uint64_t need = std::max<uint64_t>(2ull * ws.P.cap, (uint64_t)ctr[C_MAXP] + (ctr[C_MAXP] >> 2) + 65536);
+            if (ws.P.cap >= 2147483647u) return fail(FRT_EOVERFLOW, "pass buffers at their maximum size still overflow");
+            want_p = std::min<uint64_t>(need, 2147483647ull);
+        }
+        for (int i = 0; i < n; i++) {
+            frt_solve s = ss[i];
+            if (!fneed[i]) continue;
+            const uint64_t nc = std::min<uint64_t>(std::max<uint64_t>(2ull * s->F[0].cap, fneed[i] + 65536), 2147483647ull);
+            const int cur = (int)(s->step & 1u);
+            uint32_t keep;
+            HIPCHK(hipMemcpy(&keep, s->fcount + cur, 4, hipMemcpyDeviceToHost));
+            FrtRecs nf[2];
+            RCCHK(alloc_recs(nf[0], (uint32_t)nc, s->P.n_bins, s->rs));
+            RCCHK(alloc_recs(nf[1], (uint32_t)nc, s->P.n_bins, s->rs));
+            RCCHK(copy_recs(nf[cur], s->F[cur], std::min(keep, s->F[cur].cap), s->P.n_bins, s->rs, st, hipMemcpyDeviceToDevice));
+            HIPCHK(hipStreamSynchronize(st));
+            free_recs(s->F[0]);
+            free_recs(s->F[1]);
+            s->F[0] = nf[0];
+            s->F[1] = nf[1];
+            s->h.F[0] = nf[0];
+            s->h.F[1] = nf[1];
+            RCCHK(upload_desc(s));
+        }
+    }
+    return fail(FRT_EOVERFLOW, "step kept overflowing its queues");
 }
 
 }  // namespace
@@ -380,6 +654,7 @@ int frt_ctx_create(int hip_device, frt_ctx* out)
 
 int frt_ctx_destroy(frt_ctx ctx)
 {
+    if (ctx) (void)hipDeviceSynchronize();
     delete ctx;
     return FRT_OK;
 }
@@ -407,6 +682,7 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     s->P = *P;
     s->fp64 = P->march_precision == FRT_F64;
     s->rs = s->fp64 ? 8 : 4;
+    s->brick = s->fp64 ? FRT_BRICK_F64 : FRT_BRICK_F32;
     if (hip_stream) {
         s->stream = (hipStream_t)hip_stream;
     } else {
@@ -418,21 +694,23 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
         s->own_stream = true;
     }
     int rc;
-    if ((rc = dev_alloc((void**)&s->d_desc, sizeof(FrtSolveDesc))) || (rc = dev_alloc((void**)&s->count, FRT_NQ * 4)) ||
-        (rc = dev_alloc((void**)&s->L, sizeof(FrtLedgerDev))) || (rc = dev_alloc((void**)&s->L_snap, sizeof(FrtLedgerDev))) ||
-        (rc = dev_alloc((void**)&s->count_snap, FRT_NQ * 4)) || (rc = dev_alloc((void**)&s->emit_prefix, 2 * 4)) ||
-        (rc = dev_alloc((void**)&s->cell_prefix, 2 * 8)) || (rc = dev_alloc((void**)&s->plan, sizeof(FrtRoundPlan)))) {
+    if ((rc = dev_alloc((void**)&s->d_desc, sizeof(FrtSolveDesc))) || (rc = dev_alloc((void**)&s->fcount, 8)) ||
+        (rc = dev_alloc((void**)&s->fcount_snap, 8)) || (rc = dev_alloc((void**)&s->L, sizeof(FrtLedgerDev))) ||
+        (rc = dev_alloc((void**)&s->L_snap, sizeof(FrtLedgerDev)))) {
         delete s;
         return rc;
     }
-    HIPCHK(hipMemsetAsync(s->count, 0, FRT_NQ * 4, s->stream));
+    HIPCHK(hipMemsetAsync(s->fcount, 0, 8, s->stream));
     HIPCHK(hipMemsetAsync(s->L, 0, sizeof(FrtLedgerDev), s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
     FrtSolveDesc& h = s->h;
     std::memset(&h, 0, sizeof(h));
     h.n_bins = P->n_bins;
     h.base_level = P->base_level;
     h.max_level = P->max_level;
     h.fp64 = s->fp64;
+    h.brick = s->brick;
+    h.ncast = 12u << (2 * P->base_level);
     h.sigma0 = P->sigma_bins[0];
     for (int b = 0; b < P->n_bins; b++) h.sig_rel[b] = (float)(P->sigma_bins[b] / P->sigma_bins[0]);
     h.r_split0 = std::sqrt(3.0 / (PI * P->n_ray_min));
@@ -440,7 +718,7 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     h.alpha_B = P->alpha_B;
     h.coll_ion = P->coll_ion;
     h.seed = P->seed;
-    h.count = s->count;
+    h.fcount = s->fcount;
     h.L = s->L;
     *out = s;
     return FRT_OK;
@@ -459,76 +737,70 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
 {
     if (!s) return fail(FRT_EINVAL, "null solve");
     if (nx < 1 || ny < 1 || nz < 1 || nx > 2048 || ny > 2048 || nz > 2048) return fail(FRT_EINVAL, "grid %dx%dx%d outside 1..2048", nx, ny, nz);
+    if ((uint64_t)nx * ny * nz >= 0xffffffffull) return fail(FRT_EINVAL, "grid of %llu cells exceeds 2^32 - 1", (unsigned long long)nx * ny * nz);
     if (!(box_cm > 0) || !std::isfinite(box_cm)) return fail(FRT_EINVAL, "box_cm must be finite and > 0");
     if (!n_H) return fail(FRT_EINVAL, "n_H is required");
     if (kind != FRT_HOST && kind != FRT_DEVICE) return fail(FRT_EINVAL, "ptr_kind must be FRT_HOST or FRT_DEVICE");
     HIPCHK(hipSetDevice(s->ctx->device));
     HIPCHK(hipStreamSynchronize(s->stream));
     const size_t n = (size_t)nx * ny * nz;
-    std::vector<float> bn, bk;
+    std::vector<float> bn, bk, bT;
     std::vector<double> bx;
-    const float *hn = nullptr, *hk = nullptr;
+    const float *hn = nullptr, *hk = nullptr, *hT = nullptr;
     const double* hx = nullptr;
-    int rc;
-    if ((rc = host_view(n_H, n, kind, bn, &hn))) return rc;
-    if ((rc = check_inputs_finite(hn, n, "n_H"))) return rc;
+    RCCHK(host_view(n_H, n, kind, bn, &hn));
+    RCCHK(check_inputs_finite(hn, n, "n_H"));
     if (kappa) {
-        if ((rc = host_view(kappa, n, kind, bk, &hk))) return rc;
-        if ((rc = check_inputs_finite(hk, n, "kappa_sub"))) return rc;
+        RCCHK(host_view(kappa, n, kind, bk, &hk));
+        RCCHK(check_inputs_finite(hk, n, "kappa_sub"));
     }
     if (x0) {
-        if ((rc = host_view(x0, n, kind, bx, &hx))) return rc;
+        RCCHK(host_view(x0, n, kind, bx, &hx));
         for (size_t i = 0; i < n; i++)
             if (!(hx[i] >= 0.0 && hx[i] <= 1.0)) return fail(FRT_EINVAL, "x_HI0[%zu] = %g outside [0,1]", i, hx[i]);
     }
-    // (re)allocate grid buffers
-    void* ptrs[] = {s->op, s->gam[0], s->gam[1], s->x, s->nH, s->T};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
-    s->op = s->gam[0] = s->gam[1] = nullptr;
-    s->x = s->nH = nullptr;
-    s->T = nullptr;
-    if ((rc = dev_alloc(&s->op, n * 2 * s->rs)) || (rc = dev_alloc(&s->gam[0], n * s->rs)) ||
-        (rc = dev_alloc(&s->gam[1], n * s->rs)) || (rc = dev_alloc((void**)&s->x, n * 8)) ||
-        (rc = dev_alloc((void**)&s->nH, n * 8)))
-        return rc;
-    if (T && (rc = dev_alloc((void**)&s->T, n * 4))) return rc;
+    if (T) RCCHK(host_view(T, n, kind, bT, &hT));
+    dev_free(s->op); dev_free(s->gam[0]); dev_free(s->gam[1]); dev_free(s->x); dev_free(s->nH); dev_free(s->T);
+    RCCHK(dev_alloc(&s->op, n * 2 * s->rs));
+    RCCHK(dev_alloc(&s->gam[0], n * s->rs));
+    RCCHK(dev_alloc(&s->gam[1], n * s->rs));
+    RCCHK(dev_alloc((void**)&s->x, n * 8));
+    RCCHK(dev_alloc((void**)&s->nH, n * 8));
+    if (T) RCCHK(dev_alloc((void**)&s->T, n * 4));
     s->nx = nx; s->ny = ny; s->nz = nz;
     s->ncell = n;
     s->dx = box_cm / nx;
-    // host-side conversion: n_H to double, opacity pairs {0, kappa dx}
+    s->bpx = (nx + s->brick - 1) / s->brick;
+    s->bpy = (ny + s->brick - 1) / s->brick;
+    s->bpz = (nz + s->brick - 1) / s->brick;
     std::vector<double> nHd(n), xd(n, 1.0);
     for (size_t i = 0; i < n; i++) nHd[i] = (double)hn[i];
     if (hx) std::copy(hx, hx + n, xd.begin());
-    s->any_kappa = false;
     if (s->fp64) {
         std::vector<double> opv(2 * n);
         for (size_t i = 0; i < n; i++) {
             opv[2 * i] = 0.0;
             opv[2 * i + 1] = hk ? (double)hk[i] * s->dx : 0.0;
-            s->any_kappa |= hk && hk[i] > 0;
         }
-        HIPCHK(hipMemcpy(s->op, opv.data(), n * 16, hipMemcpyHostToDevice));
+        RCCHK(scopy(s, s->op, opv.data(), n * 16, hipMemcpyHostToDevice));
     } else {
         std::vector<float> opv(2 * n);
         for (size_t i = 0; i < n; i++) {
             opv[2 * i] = 0.f;
             opv[2 * i + 1] = hk ? (float)((double)hk[i] * s->dx) : 0.f;
-            s->any_kappa |= hk && hk[i] > 0;
         }
-        HIPCHK(hipMemcpy(s->op, opv.data(), n * 8, hipMemcpyHostToDevice));
+        RCCHK(scopy(s, s->op, opv.data(), n * 8, hipMemcpyHostToDevice));
     }
-    HIPCHK(hipMemcpy(s->nH, nHd.data(), n * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s->x, xd.data(), n * 8, hipMemcpyHostToDevice));
-    if (T) {
-        if ((rc = copy_in(s->T, T, n * 4, kind, s->stream))) return rc;
-    }
-    HIPCHK(hipMemsetAsync(s->gam[0], 0, n * s->rs, s->stream));
-    HIPCHK(hipMemsetAsync(s->gam[1], 0, n * s->rs, s->stream));
-    HIPCHK(hipMemsetAsync(s->count, 0, FRT_NQ * 4, s->stream));
-    HIPCHK(hipMemsetAsync(s->L, 0, sizeof(FrtLedgerDev), s->stream));
+    RCCHK(scopy(s, s->nH, nHd.data(), n * 8, hipMemcpyHostToDevice));
+    RCCHK(scopy(s, s->x, xd.data(), n * 8, hipMemcpyHostToDevice));
+    if (T) RCCHK(scopy(s, s->T, hT, n * 4, hipMemcpyHostToDevice));
+    RCCHK(sset(s, s->gam[0], 0, n * s->rs));
+    RCCHK(sset(s, s->gam[1], 0, n * s->rs));
+    RCCHK(sset(s, s->fcount, 0, 8));
+    RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
     FrtSolveDesc& h = s->h;
     h.nx = nx; h.ny = ny; h.nz = nz;
+    h.bpx = s->bpx; h.bpy = s->bpy; h.bpz = s->bpz;
     h.dx_cm = s->dx;
     h.r_cap = s->P.max_distance_cm > 0 ? s->P.max_distance_cm / s->dx : HUGE_VAL;
     h.op = s->op;
@@ -539,8 +811,8 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     h.nH = s->nH;
     s->step = 0;
     s->have_grid = true;
-    s->have_src = false;   // sources are checked against the box
-    if ((rc = upload_desc(s))) return rc;
+    s->have_src = false;   // sources are checked against the new box
+    RCCHK(upload_desc(s));
     hipError_t e = frt::launch_prep_opacity(s->d_desc, n, s->fp64, s->stream);
     if (e != hipSuccess) return fail(FRT_EDEVICE, "prep launch: %s", hipGetErrorString(e));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -558,10 +830,9 @@ int frt_load_sources(frt_solve s, int n_src, const double* pos_cm, const double*
     const int nb = s->P.n_bins;
     std::vector<double> bp, bd;
     const double *hp = nullptr, *hd = nullptr;
-    int rc;
     if (n_src > 0) {
-        if ((rc = host_view(pos_cm, (size_t)n_src * 3, kind, bp, &hp))) return rc;
-        if ((rc = host_view(ndot, (size_t)n_src * nb, kind, bd, &hd))) return rc;
+        RCCHK(host_view(pos_cm, (size_t)n_src * 3, kind, bp, &hp));
+        RCCHK(host_view(ndot, (size_t)n_src * nb, kind, bd, &hd));
     }
     const double ext[3] = {s->nx * s->dx, s->ny * s->dx, s->nz * s->dx};
     double rmax = 0.0;
@@ -587,20 +858,16 @@ int frt_load_sources(frt_solve s, int n_src, const double* pos_cm, const double*
         specd[i] = hd[i] / R_ref;
         spec[i] = (float)specd[i];
     }
-    void* ptrs[] = {s->src_pos, s->spec, s->specd, s->quat, s->user_u};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
-    s->src_pos = nullptr; s->spec = nullptr; s->specd = nullptr; s->quat = nullptr; s->user_u = nullptr;
+    dev_free(s->src_pos); dev_free(s->spec); dev_free(s->specd); dev_free(s->quat); dev_free(s->user_u);
     s->quat_steps = 0;
     s->user_steps = 0;
-    s->host_uniforms.clear();
     s->n_src = n_src;
-    if ((rc = dev_alloc((void**)&s->src_pos, pos_cells.size() * 8)) || (rc = dev_alloc((void**)&s->spec, spec.size() * 4)) ||
-        (rc = dev_alloc((void**)&s->specd, specd.size() * 8)))
-        return rc;
-    HIPCHK(hipMemcpy(s->src_pos, pos_cells.data(), pos_cells.size() * 8, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s->spec, spec.data(), spec.size() * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s->specd, specd.data(), specd.size() * 8, hipMemcpyHostToDevice));
+    RCCHK(dev_alloc((void**)&s->src_pos, pos_cells.size() * 8));
+    RCCHK(dev_alloc((void**)&s->spec, spec.size() * 4));
+    RCCHK(dev_alloc((void**)&s->specd, specd.size() * 8));
+    RCCHK(scopy(s, s->src_pos, pos_cells.data(), pos_cells.size() * 8, hipMemcpyHostToDevice));
+    RCCHK(scopy(s, s->spec, spec.data(), spec.size() * 4, hipMemcpyHostToDevice));
+    RCCHK(scopy(s, s->specd, specd.data(), specd.size() * 8, hipMemcpyHostToDevice));
     FrtSolveDesc& h = s->h;
     h.n_src = n_src;
     h.R_ref = R_ref;
@@ -609,23 +876,19 @@ int frt_load_sources(frt_solve s, int n_src, const double* pos_cm, const double*
     h.specd = s->specd;
     h.user_u = nullptr;
     h.user_steps = 0;
-    s->rounds = rounds_needed(s);
-    uint64_t capF, capS;
-    initial_caps(s, &capF, &capS);
-    for (int k = 0; k < FRT_NQ; k++) s->release_queue(k);
-    if ((rc = alloc_queue(s, FRT_QF0, (uint32_t)capF, 0)) || (rc = alloc_queue(s, FRT_QF1, (uint32_t)capF, 0)) ||
-        (rc = alloc_queue(s, FRT_QS0, (uint32_t)capS, 0)) || (rc = alloc_queue(s, FRT_QS1, (uint32_t)capS, 0)))
-        return rc;
-    if ((rc = ensure_quat(s, 0))) return rc;
-    uint32_t ep[2] = {0, (uint32_t)(n_src * ncast)};
-    unsigned long long cp[2] = {0, (unsigned long long)s->ncell};
-    HIPCHK(hipMemcpy(s->emit_prefix, ep, sizeof(ep), hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(s->cell_prefix, cp, sizeof(cp), hipMemcpyHostToDevice));
-    HIPCHK(hipMemsetAsync(s->count, 0, FRT_NQ * 4, s->stream));
-    HIPCHK(hipMemsetAsync(s->L, 0, sizeof(FrtLedgerDev), s->stream));
+    free_recs(s->F[0]);
+    free_recs(s->F[1]);
+    const uint32_t fcap = initial_fcap(s);
+    RCCHK(alloc_recs(s->F[0], fcap, nb, s->rs));
+    RCCHK(alloc_recs(s->F[1], fcap, nb, s->rs));
+    h.F[0] = s->F[0];
+    h.F[1] = s->F[1];
+    RCCHK(ensure_quat(s, 0));
+    RCCHK(sset(s, s->fcount, 0, 8));
+    RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
     s->step = 0;
     s->have_src = true;
-    if ((rc = upload_desc(s))) return rc;
+    RCCHK(upload_desc(s));
     HIPCHK(hipStreamSynchronize(s->stream));
     return FRT_OK;
 }
@@ -639,137 +902,42 @@ int frt_set_rotations(frt_solve s, int n_steps, const double* u)
     for (size_t i = 0; i < n; i++)
         if (!(u[i] >= 0.0 && u[i] < 1.0)) return fail(FRT_EINVAL, "uniform %zu = %g outside [0,1)", i, u[i]);
     HIPCHK(hipStreamSynchronize(s->stream));
-    if (s->user_u) (void)hipFree(s->user_u);
-    s->user_u = nullptr;
-    int rc;
-    if ((rc = dev_alloc((void**)&s->user_u, std::max<size_t>(n, 1) * 8))) return rc;
-    if (n) HIPCHK(hipMemcpy(s->user_u, u, n * 8, hipMemcpyHostToDevice));
+    dev_free(s->user_u);
+    RCCHK(dev_alloc((void**)&s->user_u, std::max<size_t>(n, 1) * 8));
+    if (n) RCCHK(scopy(s, s->user_u, u, n * 8, hipMemcpyHostToDevice));
     s->user_steps = (uint32_t)n_steps;
-    s->host_uniforms.assign(u, u + n);
     s->h.user_u = s->user_u;
     s->h.user_steps = s->user_steps;
     return upload_desc(s);
 }
 
-static int step_group(frt_solve* ss, int n, const double* dts, FrtSolveDesc* d_descs, uint32_t* d_ep,
-                      unsigned long long* d_cp, FrtRoundPlan* d_plan, hipStream_t st, bool single)
-{
-    for (int i = 0; i < n; i++) {
-        frt_solve s = ss[i];
-        int rc;
-        if ((rc = ensure_quat(s, s->step))) return rc;
-        set_step_fields(s, dts[i]);
-        s->last_dt = dts[i];
-        if (single && (rc = upload_desc(s))) return rc;
-    }
-    return enqueue_steps(ss, n, d_descs, d_ep, d_cp, d_plan, st);
-}
-
 int frt_step(frt_solve s, double dt)
 {
-    int rc;
-    if ((rc = ready(s))) return rc;
+    RCCHK(ready(s));
     if (!(dt > 0) || !std::isfinite(dt)) return fail(FRT_EINVAL, "dt must be finite and > 0");
     HIPCHK(hipSetDevice(s->ctx->device));
-    const bool auto_grow = s->P.queue_capacity == 0;
-    for (int attempt = 0; attempt < 12; attempt++) {
-        if (auto_grow) {
-            HIPCHK(hipMemcpyAsync(s->L_snap, s->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, s->stream));
-            HIPCHK(hipMemcpyAsync(s->count_snap, s->count, FRT_NQ * 4, hipMemcpyDeviceToDevice, s->stream));
-        }
-        if ((rc = step_group(&s, 1, &dt, s->d_desc, s->emit_prefix, s->cell_prefix, s->plan, s->stream, true))) return rc;
-        if (!auto_grow) {
-            s->step++;
-            return FRT_OK;
-        }
-        FrtLedgerDev L;
-        if ((rc = read_device_ledger(s, &L))) return rc;
-        if (!(L.err_flags & FRT_DEVERR_QUEUE_OVERFLOW)) {
-            s->step++;
-            return FRT_OK;
-        }
-        // overflow: restore the step's starting state, enlarge, re-run
-        uint32_t counts[FRT_NQ];
-        HIPCHK(hipMemcpy(counts, s->count, sizeof(counts), hipMemcpyDeviceToHost));
-        uint32_t keep;
-        HIPCHK(hipMemcpy(&keep, s->count_snap + (s->step & 1u), 4, hipMemcpyDeviceToHost));
-        HIPCHK(hipMemcpy(s->L, s->L_snap, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice));
-        HIPCHK(hipMemcpy(s->count, s->count_snap, FRT_NQ * 4, hipMemcpyDeviceToDevice));
-        HIPCHK(hipMemset(s->gam[s->step & 1u], 0, s->ncell * s->rs));
-        const uint64_t lim = 2147483647ull;
-        uint64_t needF = std::max<uint64_t>(2ull * s->cap[FRT_QF0], (uint64_t)std::max(counts[0], counts[1]) + 1024);
-        uint64_t needS = std::max<uint64_t>(2ull * s->cap[FRT_QS0], (uint64_t)std::max(counts[2], counts[3]) + 1024);
-        const uint64_t nF = std::min(lim, needF), nS = std::min(lim, needS);
-        if ((uint64_t)s->cap[FRT_QF0] >= lim && (uint64_t)s->cap[FRT_QS0] >= lim)
-            return fail(FRT_EOVERFLOW, "ray queues at their maximum size still overflow");
-        const int cur = (int)(s->step & 1u);
-        if ((rc = alloc_queue(s, cur, (uint32_t)nF, keep)) || (rc = alloc_queue(s, 1 - cur, (uint32_t)nF, 0)) ||
-            (rc = alloc_queue(s, FRT_QS0, (uint32_t)nS, 0)) || (rc = alloc_queue(s, FRT_QS1, (uint32_t)nS, 0)))
-            return rc == FRT_ENOMEM ? fail(FRT_EOVERFLOW, "ray queues could not grow: %s", g_err.c_str()) : rc;
-        if ((rc = upload_desc(s))) return rc;
-    }
-    return fail(FRT_EOVERFLOW, "step kept overflowing its ray queues");
+    return step_group(&s, 1, &dt);
 }
 
 int frt_batch_step(frt_solve* ss, int n, const double* dts)
 {
     if (!ss || n < 1 || !dts) return fail(FRT_EINVAL, "bad batch");
     if (n > FRT_MAX_SOLVES_PER_LAUNCH) return fail(FRT_EINVAL, "at most %d solves per batch", FRT_MAX_SOLVES_PER_LAUNCH);
-    int rc;
     for (int i = 0; i < n; i++) {
-        if ((rc = ready(ss[i]))) return rc;
+        RCCHK(ready(ss[i]));
         if (ss[i]->P.n_bins != ss[0]->P.n_bins || ss[i]->fp64 != ss[0]->fp64)
             return fail(FRT_EINVAL, "batched solves must share n_bins and march_precision");
-        if (ss[i]->ctx->device != ss[0]->ctx->device) return fail(FRT_EINVAL, "batched solves must share a device");
+        if (ss[i]->ctx != ss[0]->ctx) return fail(FRT_EINVAL, "batched solves must share a context");
+        if ((ss[i]->P.queue_capacity == 0) != (ss[0]->P.queue_capacity == 0))
+            return fail(FRT_EINVAL, "batched solves must all use automatic queues or all fixed ones");
         if (!(dts[i] > 0) || !std::isfinite(dts[i])) return fail(FRT_EINVAL, "dt must be finite and > 0");
         for (int j = 0; j < i; j++)
             if (ss[j] == ss[i]) return fail(FRT_EINVAL, "a solve appears twice in the batch");
     }
-    hipStream_t st = ss[0]->stream;
+    HIPCHK(hipSetDevice(ss[0]->ctx->device));
     for (int i = 1; i < n; i++) HIPCHK(hipStreamSynchronize(ss[i]->stream));
-    // batch-owned descriptor table and prefixes
-    static thread_local FrtSolveDesc* d_descs = nullptr;
-    static thread_local uint32_t* d_ep = nullptr;
-    static thread_local unsigned long long* d_cp = nullptr;
-    static thread_local FrtRoundPlan* d_plan = nullptr;
-    static thread_local int cap_n = 0;
-    if (cap_n < n) {
-        if (d_descs) (void)hipFree(d_descs);
-        if (d_ep) (void)hipFree(d_ep);
-        if (d_cp) (void)hipFree(d_cp);
-        if (d_plan) (void)hipFree(d_plan);
-        d_descs = nullptr; d_ep = nullptr; d_cp = nullptr; d_plan = nullptr;
-        int c = std::max(n, 64);
-        if ((rc = dev_alloc((void**)&d_descs, c * sizeof(FrtSolveDesc))) || (rc = dev_alloc((void**)&d_ep, (c + 1) * 4)) ||
-            (rc = dev_alloc((void**)&d_cp, (c + 1) * 8)) || (rc = dev_alloc((void**)&d_plan, sizeof(FrtRoundPlan)))) {
-            cap_n = 0;
-            return rc;
-        }
-        cap_n = c;
-    }
-    std::vector<FrtSolveDesc> hd(n);
-    std::vector<uint32_t> ep(n + 1);
-    std::vector<unsigned long long> cp(n + 1);
-    ep[0] = 0;
-    cp[0] = 0;
-    for (int i = 0; i < n; i++) {
-        frt_solve s = ss[i];
-        if ((rc = ensure_quat(s, s->step))) return rc;
-        set_step_fields(s, dts[i]);
-        s->last_dt = dts[i];
-        hd[i] = s->h;
-        ep[i + 1] = ep[i] + (uint32_t)s->n_src * (12u << (2 * s->P.base_level));
-        cp[i + 1] = cp[i] + s->ncell;
-    }
-    HIPCHK(hipMemcpyAsync(d_descs, hd.data(), n * sizeof(FrtSolveDesc), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_ep, ep.data(), (n + 1) * 4, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d_cp, cp.data(), (n + 1) * 8, hipMemcpyHostToDevice, st));
-    if ((rc = enqueue_steps(ss, n, d_descs, d_ep, d_cp, d_plan, st))) return rc;
-    HIPCHK(hipStreamSynchronize(st));
-    for (int i = 0; i < n; i++) {
-        ss[i]->step++;
-        if ((rc = upload_desc(ss[i]))) return rc;
-    }
+    RCCHK(step_group(ss, n, dts));
+    HIPCHK(hipStreamSynchronize(ss[0]->stream));
     return FRT_OK;
 }
 
@@ -779,9 +947,9 @@ int frt_sync(frt_solve s)
     HIPCHK(hipStreamSynchronize(s->stream));
     if (!s->L) return FRT_OK;
     FrtLedgerDev L;
-    int rc;
-    if ((rc = read_device_ledger(s, &L))) return rc;
+    RCCHK(read_device_ledger(s, &L));
     if (L.err_flags & FRT_DEVERR_QUEUE_OVERFLOW) return fail(FRT_EOVERFLOW, "a ray queue overflowed; raise queue_capacity");
+    if (L.err_flags & FRT_DEVERR_UNFINISHED) return fail(FRT_EDEVICE, "a step left packets after its last pass");
     return FRT_OK;
 }
 
@@ -793,20 +961,21 @@ int frt_read_fields(frt_solve s, double* x_HI, float* gamma, int kind)
     if ((rc = frt_sync(s)) && rc != FRT_EOVERFLOW) return rc;
     const size_t n = s->ncell;
     const hipMemcpyKind k = kind == FRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-    if (x_HI) HIPCHK(hipMemcpy(x_HI, s->x, n * 8, k));
+    if (x_HI) RCCHK(scopy(s, x_HI, s->x, n * 8, k));
     if (gamma) {
         const void* g = s->gam[(s->step + 1u) & 1u];   // buffer of the last completed step
         if (s->step == 0) {
-            if (kind == FRT_DEVICE) HIPCHK(hipMemset(gamma, 0, n * 4));
+            if (kind == FRT_DEVICE) RCCHK(sset(s, gamma, 0, n * 4));
             else std::memset(gamma, 0, n * 4);
         } else if (!s->fp64) {
-            HIPCHK(hipMemcpy(gamma, g, n * 4, k));
+            RCCHK(scopy(s, gamma, g, n * 4, k));
         } else {
             std::vector<double> tmp(n);
-            HIPCHK(hipMemcpy(tmp.data(), g, n * 8, hipMemcpyDeviceToHost));
+            RCCHK(scopy(s, tmp.data(), g, n * 8, hipMemcpyDeviceToHost));
             std::vector<float> f(n);
             for (size_t i = 0; i < n; i++) f[i] = (float)tmp[i];
-            HIPCHK(hipMemcpy(gamma, f.data(), n * 4, kind == FRT_DEVICE ? hipMemcpyHostToDevice : hipMemcpyHostToHost));
+            if (kind == FRT_DEVICE) RCCHK(scopy(s, gamma, f.data(), n * 4, hipMemcpyHostToDevice));
+            else std::memcpy(gamma, f.data(), n * 4);
         }
     }
     return FRT_OK;
@@ -815,10 +984,8 @@ int frt_read_fields(frt_solve s, double* x_HI, float* gamma, int kind)
 int frt_read_ledger(frt_solve s, frt_ledger* out)
 {
     if (!s || !out) return fail(FRT_EINVAL, "null argument");
-    HIPCHK(hipStreamSynchronize(s->stream));
     FrtLedgerDev L;
-    int rc;
-    if ((rc = read_device_ledger(s, &L))) return rc;
+    RCCHK(read_device_ledger(s, &L));
     out->emitted = L.emitted;
     out->absorbed_HI = L.absorbed_HI;
     out->absorbed_sub = L.absorbed_sub;
@@ -840,51 +1007,54 @@ int frt_read_ledger(frt_solve s, frt_ledger* out)
     return FRT_OK;
 }
 
-// Checkpoint layout: magic, version, step, n_src, ncell, nb, fp64, n_carried,
-// ledger, x[ncell], quaternions of the steps so far, carried packets (SoA).
+// Checkpoint layout: 8 u64 header (magic, version, step, n_src, ncell, nb,
+// fp64, n_carried), ledger (without stripes), x[ncell], quaternions of the
+// steps so far, then the carried packets as SoA fields.
 int frt_save_state(frt_solve s, void* buf, size_t* bytes)
 {
-    int rc;
-    if ((rc = ready(s))) return rc;
+    RCCHK(ready(s));
     if (!bytes) return fail(FRT_EINVAL, "null size");
     HIPCHK(hipStreamSynchronize(s->stream));
-    uint32_t counts[FRT_NQ];
-    HIPCHK(hipMemcpy(counts, s->count, sizeof(counts), hipMemcpyDeviceToHost));
+    uint32_t fc[2];
+    RCCHK(scopy(s, fc, s->fcount, 8, hipMemcpyDeviceToHost));
     const int cur = (int)(s->step & 1u);
-    const uint32_t nc = std::min(counts[cur], s->cap[cur]);
+    const uint32_t nc = std::min(fc[cur], s->F[cur].cap);
     const int nb = s->P.n_bins;
-    const size_t rec = 12 + 3 * s->rs + 2 * nb * s->rs;
+    const size_t rec = 20 + 6 * s->rs + 2 * nb * s->rs;
+    const size_t led = offsetof(FrtLedgerDev, sd);
     const size_t nq = (size_t)s->step * s->n_src * 4;
-    const size_t need = 8 * 8 + sizeof(FrtLedgerDev) + s->ncell * 8 + nq * 8 + (size_t)nc * rec;
+    const size_t need = 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec;
     if (!buf) {
         *bytes = need;
         return FRT_OK;
     }
     if (*bytes < need) return fail(FRT_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
     char* p = (char*)buf;
-    uint64_t hdr[8] = {0x4652544350543031ull, 1, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
+    uint64_t hdr[8] = {0x4652544350543033ull, 3, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
-    HIPCHK(hipMemcpy(p, s->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToHost));
-    p += sizeof(FrtLedgerDev);
-    HIPCHK(hipMemcpy(p, s->x, s->ncell * 8, hipMemcpyDeviceToHost));
+    RCCHK(scopy(s, p, s->L, led, hipMemcpyDeviceToHost));
+    p += led;
+    RCCHK(scopy(s, p, s->x, s->ncell * 8, hipMemcpyDeviceToHost));
     p += s->ncell * 8;
-    if (nq) HIPCHK(hipMemcpy(p, s->quat, nq * 8, hipMemcpyDeviceToHost));
+    if (nq) RCCHK(scopy(s, p, s->quat, nq * 8, hipMemcpyDeviceToHost));
     p += nq * 8;
-    const FrtQueue& q = s->h.q[cur];
     if (nc) {
-        HIPCHK(hipMemcpy(p, q.src, nc * 4ull, hipMemcpyDeviceToHost)); p += nc * 4ull;
-        HIPCHK(hipMemcpy(p, q.estep, nc * 4ull, hipMemcpyDeviceToHost)); p += nc * 4ull;
-        HIPCHK(hipMemcpy(p, q.lp, nc * 4ull, hipMemcpyDeviceToHost)); p += nc * 4ull;
-        HIPCHK(hipMemcpy(p, q.r, nc * s->rs, hipMemcpyDeviceToHost)); p += nc * s->rs;
-        HIPCHK(hipMemcpy(p, q.rstop, nc * s->rs, hipMemcpyDeviceToHost)); p += nc * s->rs;
-        HIPCHK(hipMemcpy(p, q.w0, nc * s->rs, hipMemcpyDeviceToHost)); p += nc * s->rs;
-        for (int b = 0; b < nb; b++) {
-            HIPCHK(hipMemcpy(p, (char*)q.tau + b * (size_t)q.cap * s->rs, nc * s->rs, hipMemcpyDeviceToHost)); p += nc * s->rs;
-        }
-        for (int b = 0; b < nb; b++) {
-            HIPCHK(hipMemcpy(p, (char*)q.comp + b * (size_t)q.cap * s->rs, nc * s->rs, hipMemcpyDeviceToHost)); p += nc * s->rs;
-        }
+        FrtRecs hv{};
+        hv.cap = nc;
+        hv.src = (uint32_t*)p; p += nc * 4ull;
+        hv.estep = (uint32_t*)p; p += nc * 4ull;
+        hv.lp = (uint32_t*)p; p += nc * 4ull;
+        hv.cell = (uint32_t*)p; p += nc * 4ull;
+        hv.key = (uint32_t*)p; p += nc * 4ull;
+        hv.r = p; p += nc * s->rs;
+        hv.rstop = p; p += nc * s->rs;
+        hv.w0 = p; p += nc * s->rs;
+        hv.dir = p; p += nc * s->rs * 3;
+        hv.tau = p; p += nc * s->rs * nb;
+        hv.comp = p; p += nc * s->rs * nb;
+        RCCHK(copy_recs(hv, s->F[cur], nc, nb, s->rs, s->stream, hipMemcpyDeviceToHost));
+        HIPCHK(hipStreamSynchronize(s->stream));
     }
     *bytes = need;
     return FRT_OK;
@@ -892,60 +1062,139 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
 
 int frt_load_state(frt_solve s, const void* buf, size_t bytes)
 {
-    int rc;
-    if ((rc = ready(s))) return rc;
-    if (!buf || bytes < 64 + sizeof(FrtLedgerDev)) return fail(FRT_EINVAL, "checkpoint too small");
+    RCCHK(ready(s));
+    const size_t led = offsetof(FrtLedgerDev, sd);
+    if (!buf || bytes < 64 + led) return fail(FRT_EINVAL, "checkpoint too small");
     const char* p = (const char*)buf;
     uint64_t hdr[8];
     std::memcpy(hdr, p, sizeof(hdr));
     p += sizeof(hdr);
-    if (hdr[0] != 0x4652544350543031ull || hdr[1] != 1) return fail(FRT_EINVAL, "not a checkpoint of this library");
+    if (hdr[0] != 0x4652544350543033ull || hdr[1] != 3) return fail(FRT_EINVAL, "not a checkpoint of this library");
     if (hdr[3] != (uint64_t)s->n_src || hdr[4] != s->ncell || hdr[5] != (uint64_t)s->P.n_bins || hdr[6] != (uint64_t)s->fp64)
         return fail(FRT_EINVAL, "checkpoint does not match this solve (sources, grid, bins or precision)");
     const uint32_t step = (uint32_t)hdr[2], nc = (uint32_t)hdr[7];
     const int nb = s->P.n_bins;
-    const size_t rec = 12 + 3 * s->rs + 2 * nb * s->rs;
+    const size_t rec = 20 + 6 * s->rs + 2 * nb * s->rs;
     const size_t nq = (size_t)step * s->n_src * 4;
-    if (bytes < 64 + sizeof(FrtLedgerDev) + s->ncell * 8 + nq * 8 + (size_t)nc * rec) return fail(FRT_EINVAL, "checkpoint truncated");
+    if (bytes < 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec) return fail(FRT_EINVAL, "checkpoint truncated");
     HIPCHK(hipStreamSynchronize(s->stream));
-    HIPCHK(hipMemcpy(s->L, p, sizeof(FrtLedgerDev), hipMemcpyHostToDevice));
-    p += sizeof(FrtLedgerDev);
-    HIPCHK(hipMemcpy(s->x, p, s->ncell * 8, hipMemcpyHostToDevice));
+    RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
+    RCCHK(scopy(s, s->L, p, led, hipMemcpyHostToDevice));
+    p += led;
+    RCCHK(scopy(s, s->x, p, s->ncell * 8, hipMemcpyHostToDevice));
     p += s->ncell * 8;
-    if ((rc = ensure_quat(s, step))) return rc;
-    if (nq) HIPCHK(hipMemcpy(s->quat, p, nq * 8, hipMemcpyHostToDevice));
+    RCCHK(ensure_quat(s, step));
+    if (nq) RCCHK(scopy(s, s->quat, p, nq * 8, hipMemcpyHostToDevice));
     p += nq * 8;
     const int cur = (int)(step & 1u);
-    if (nc > s->cap[cur]) {
-        if ((rc = alloc_queue(s, cur, nc + 1024, 0)) || (rc = alloc_queue(s, 1 - cur, nc + 1024, 0))) return rc;
+    if (nc > s->F[cur].cap) {
+        FrtRecs nf[2];
+        RCCHK(alloc_recs(nf[0], nc + 1024, nb, s->rs));
+        RCCHK(alloc_recs(nf[1], nc + 1024, nb, s->rs));
+        free_recs(s->F[0]);
+        free_recs(s->F[1]);
+        s->F[0] = nf[0];
+        s->F[1] = nf[1];
+        s->h.F[0] = nf[0];
+        s->h.F[1] = nf[1];
     }
-    const FrtQueue& q = s->h.q[cur];
     if (nc) {
-        HIPCHK(hipMemcpy(q.src, p, nc * 4ull, hipMemcpyHostToDevice)); p += nc * 4ull;
-        HIPCHK(hipMemcpy(q.estep, p, nc * 4ull, hipMemcpyHostToDevice)); p += nc * 4ull;
-        HIPCHK(hipMemcpy(q.lp, p, nc * 4ull, hipMemcpyHostToDevice)); p += nc * 4ull;
-        HIPCHK(hipMemcpy(q.r, p, nc * s->rs, hipMemcpyHostToDevice)); p += nc * s->rs;
-        HIPCHK(hipMemcpy(q.rstop, p, nc * s->rs, hipMemcpyHostToDevice)); p += nc * s->rs;
-        HIPCHK(hipMemcpy(q.w0, p, nc * s->rs, hipMemcpyHostToDevice)); p += nc * s->rs;
-        for (int b = 0; b < nb; b++) {
-            HIPCHK(hipMemcpy((char*)q.tau + b * (size_t)q.cap * s->rs, p, nc * s->rs, hipMemcpyHostToDevice)); p += nc * s->rs;
-        }
-        for (int b = 0; b < nb; b++) {
-            HIPCHK(hipMemcpy((char*)q.comp + b * (size_t)q.cap * s->rs, p, nc * s->rs, hipMemcpyHostToDevice)); p += nc * s->rs;
-        }
+        FrtRecs hv{};
+        hv.cap = nc;
+        char* q = (char*)p;
+        hv.src = (uint32_t*)q; q += nc * 4ull;
+        hv.estep = (uint32_t*)q; q += nc * 4ull;
+        hv.lp = (uint32_t*)q; q += nc * 4ull;
+        hv.cell = (uint32_t*)q; q += nc * 4ull;
+        hv.key = (uint32_t*)q; q += nc * 4ull;
+        hv.r = q; q += nc * s->rs;
+        hv.rstop = q; q += nc * s->rs;
+        hv.w0 = q; q += nc * s->rs;
+        hv.dir = q; q += nc * s->rs * 3;
+        hv.tau = q; q += nc * s->rs * nb;
+        hv.comp = q; q += nc * s->rs * nb;
+        RCCHK(copy_recs(s->F[cur], hv, nc, nb, s->rs, s->stream, hipMemcpyHostToDevice));
+        HIPCHK(hipStreamSynchronize(s->stream));
     }
-    uint32_t counts[FRT_NQ] = {0, 0, 0, 0};
-    counts[cur] = nc;
-    HIPCHK(hipMemcpy(s->count, counts, sizeof(counts), hipMemcpyHostToDevice));
+    uint32_t fc[2] = {0, 0};
+    fc[cur] = nc;
+    RCCHK(scopy(s, s->fcount, fc, 8, hipMemcpyHostToDevice));
     s->step = step;
     s->h.step = step;
-    // rebuild the opacity from the restored neutral fraction; clear deposits
-    HIPCHK(hipMemset(s->gam[0], 0, s->ncell * s->rs));
-    HIPCHK(hipMemset(s->gam[1], 0, s->ncell * s->rs));
-    if ((rc = upload_desc(s))) return rc;
+    RCCHK(sset(s, s->gam[0], 0, s->ncell * s->rs));
+    RCCHK(sset(s, s->gam[1], 0, s->ncell * s->rs));
+    RCCHK(upload_desc(s));
     hipError_t e = frt::launch_prep_opacity(s->d_desc, s->ncell, s->fp64, s->stream);
     if (e != hipSuccess) return fail(FRT_EDEVICE, "prep launch: %s", hipGetErrorString(e));
     HIPCHK(hipStreamSynchronize(s->stream));
+    return FRT_OK;
+}
+
+int frt_mark(frt_solve s)
+{
+    RCCHK(ready(s));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    uint32_t fc[2];
+    RCCHK(scopy(s, fc, s->fcount, 8, hipMemcpyDeviceToHost));
+    const int cur = (int)(s->step & 1u);
+    const uint32_t nc = std::min(fc[cur], s->F[cur].cap);
+    dev_free(s->mark_x);
+    dev_free(s->mark_fc);
+    free_recs(s->mark_F);
+    RCCHK(dev_alloc((void**)&s->mark_x, s->ncell * 8));
+    RCCHK(dev_alloc((void**)&s->mark_fc, 8));
+    uint32_t mfc[2] = {0, 0};
+    mfc[cur] = nc;
+    RCCHK(scopy(s, s->mark_fc, mfc, 8, hipMemcpyHostToDevice));
+    RCCHK(alloc_recs(s->mark_F, std::max<uint32_t>(nc, 1), s->P.n_bins, s->rs));
+    HIPCHK(hipMemcpyAsync(s->mark_x, s->x, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
+    RCCHK(copy_recs(s->mark_F, s->F[cur], nc, s->P.n_bins, s->rs, s->stream, hipMemcpyDeviceToDevice));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->mark_n = nc;
+    s->mark_step = s->step;
+    s->marked = true;
+    return FRT_OK;
+}
+
+int frt_rewind(frt_solve s)
+{
+    RCCHK(ready(s));
+    if (!s->marked) return fail(FRT_ESTATE, "frt_rewind without frt_mark");
+    const int cur = (int)(s->mark_step & 1u);
+    if (s->mark_n > s->F[cur].cap) return fail(FRT_ESTATE, "carried queue shrank below the bookmark");
+    HIPCHK(hipMemcpyAsync(s->x, s->mark_x, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
+    RCCHK(copy_recs(s->F[cur], s->mark_F, s->mark_n, s->P.n_bins, s->rs, s->stream, hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemcpyAsync(s->fcount, s->mark_fc, 8, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemsetAsync(s->gam[cur], 0, s->ncell * s->rs, s->stream));
+    s->step = s->mark_step;
+    s->h.step = s->step;
+    RCCHK(upload_desc(s));
+    hipError_t e = frt::launch_prep_opacity(s->d_desc, s->ncell, s->fp64, s->stream);
+    if (e != hipSuccess) return fail(FRT_EDEVICE, "prep launch: %s", hipGetErrorString(e));
+    return FRT_OK;
+}
+
+int frt_set_timing(frt_solve s, int enable)
+{
+    if (!s) return fail(FRT_EINVAL, "null solve");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->reset_timing();
+    s->timing = enable != 0;
+    return FRT_OK;
+}
+
+int frt_read_timing(frt_solve s, frt_timing* out)
+{
+    if (!s || !out) return fail(FRT_EINVAL, "null argument");
+    HIPCHK(hipStreamSynchronize(s->stream));
+    s->drain_events();
+    out->emit_ms = s->t_ms[0];
+    out->march_ms = s->t_ms[1];
+    out->chem_ms = s->t_ms[2];
+    out->other_ms = s->t_ms[3];
+    out->march_launches = s->n_march;
+    out->chem_launches = s->n_chem;
+    out->steps = s->n_steps_timed;
     return FRT_OK;
 }
 

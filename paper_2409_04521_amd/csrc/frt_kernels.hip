@@ -1,11 +1,17 @@
-// HIP kernels for gfx950: casting, the per-round ray march, backward-Euler
-// chemistry and step bookkeeping of adaptive ray tracing of ionizing photon
-// packets (Cain & D'Aloisio, FlexRT I, §3 and §4.1).
+// HIP kernels for gfx950: casting, the brick-synchronous ray march,
+// backward-Euler chemistry and step bookkeeping of adaptive ray tracing of
+// ionizing photon packets (Cain & D'Aloisio, FlexRT I, §3 and §4.1).
 //
-// Work layout: one lane owns one packet for one "visit" (from where it
-// starts this round until it splits, ends, or spends its travel budget).
-// Each round is one grid-stride launch over the concatenated work items of
-// every solve in the launch; item counts are read on the device.
+// A step runs as a sequence of passes.  The grid is cut into bricks
+// (16^3 cells for the FP32 march, 8^3 for FP64).  In each pass every brick
+// that holds packets is given to workgroups: a workgroup stages the brick's
+// opacity in LDS, walks each of its packets cell by cell until the packet
+// leaves the brick, splits, ends or spends its travel budget, deposits the
+// absorbed photons with LDS atomics, and adds the brick's deposits to the
+// global rate field once.  Packets that leave or split are written out with
+// the key of the brick they are in next; a counting pass and a scatter sort
+// them by brick for the next pass.  Item counts live on the device, so the
+// host launches a fixed number of passes without reading anything back.
 #include "frt_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -139,27 +145,199 @@ __device__ __forceinline__ unsigned long long wave_sum_u64(unsigned long long v)
 
 // Add a per-lane value into a per-solve FP64 counter.  When every lane of
 // the wave targets the same solve the wave reduces first and one lane adds.
-__device__ __forceinline__ void ledger_add(double* target, double v, bool uniform)
+
+__device__ __forceinline__ uint32_t wave_sum_u32(uint32_t v)
 {
-    if (uniform) {
-        double s = wave_sum(v);
-        if ((threadIdx.x & (WAVE - 1)) == 0 && s != 0.0) atomicAdd(target, s);
-    } else if (v != 0.0) {
-        atomicAdd(target, v);
+#pragma unroll
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+// Exclusive prefix sum of v over the wave; *total gets the wave's sum.
+__device__ __forceinline__ uint32_t wave_excl_scan(uint32_t v, uint32_t* total)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < WAVE; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, WAVE);
+        if (lane >= o) x += y;
+    }
+    *total = __shfl(x, WAVE - 1, WAVE);
+    return x - v;
+}
+
+// Reserve n_lane slots per lane in an array whose fill counter is *ctr, with
+// one atomic per wave.  Every lane of the wave must call it.  Returns the
+// lane's first slot.
+__device__ __forceinline__ uint32_t wave_reserve(uint32_t* ctr, uint32_t n_lane)
+{
+    uint32_t total;
+    const uint32_t off = wave_excl_scan(n_lane, &total);
+    uint32_t base = 0;
+    if ((threadIdx.x & (WAVE - 1)) == 0 && total) base = atomicAdd(ctr, total);
+    base = __shfl(base, 0, WAVE);
+    return base + off;
+}
+
+template <typename Real> __device__ __forceinline__ Real rinf();
+template <> __device__ __forceinline__ float rinf<float>() { return __builtin_huge_valf(); }
+template <> __device__ __forceinline__ double rinf<double>() { return __builtin_huge_val(); }
+
+template <typename Real> struct Vec2;
+template <> struct Vec2<float> { using T = float2; };
+template <> struct Vec2<double> { using T = double2; };
+
+// exp(-t) and the absorbed fraction 1 - exp(-t) of a segment, accurate for
+// small t (series) and using the hardware exponential otherwise.
+__device__ __forceinline__ float exp_neg(float t) { return __expf(-t); }
+__device__ __forceinline__ double exp_neg(double t) { return exp(-t); }
+__device__ __forceinline__ float absorbed_fraction(float t)
+{
+    // t (1 - t/2 + t^2/6 - t^3/24) below 0.03 (truncation < 7e-9 relative)
+    return (t < 0.03f) ? t * (1.f - t * (0.5f - t * ((1.f / 6.f) - t * (1.f / 24.f)))) : 1.f - __expf(-t);
+}
+__device__ __forceinline__ double absorbed_fraction(double t) { return -expm1(-t); }
+
+// --------------------------------------------------------------- the ledger
+// Per-lane accumulation, block reduction, one atomic per field per flush
+// into one of FRT_STRIPES stripes.  All threads of the block must call
+// ledger_flush at the same point.
+struct LaneLedger {
+    double f[LF_NF];
+    unsigned long long c[LC_NC];
+    __device__ void clear()
+    {
+#pragma unroll
+        for (int i = 0; i < LF_NF; i++) f[i] = 0.0;
+#pragma unroll
+        for (int i = 0; i < LC_NC; i++) c[i] = 0;
+    }
+};
+
+// Direct add for the rare lane whose solve differs from its block's.
+__device__ __forceinline__ void ledger_direct(FrtLedgerDev* L, int f, double v)
+{
+    if (v != 0.0) atomicAdd(&L->sd[blockIdx.x % FRT_STRIPES][f], v);
+}
+
+__device__ __forceinline__ void ledger_direct_c(FrtLedgerDev* L, int c, unsigned long long v)
+{
+    if (v) atomicAdd(&L->sc[blockIdx.x % FRT_STRIPES][c], v);
+}
+
+__device__ void ledger_flush(LaneLedger& a, FrtLedgerDev* L)
+{
+    __shared__ double s_f[BLOCK / WAVE][LF_NF];
+    __shared__ unsigned long long s_c[BLOCK / WAVE][LC_NC];
+    const int w = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+#pragma unroll
+    for (int i = 0; i < LF_NF; i++) {
+        double v = wave_sum(a.f[i]);
+        if (lane == 0) s_f[w][i] = v;
+    }
+#pragma unroll
+    for (int i = 0; i < LC_NC; i++) {
+        unsigned long long v = wave_sum_u64(a.c[i]);
+        if (lane == 0) s_c[w][i] = v;
+    }
+    __syncthreads();
+    const int stripe = blockIdx.x % FRT_STRIPES;
+    if (threadIdx.x < LF_NF) {
+        double v = 0;
+        for (int k = 0; k < BLOCK / WAVE; k++) v += s_f[k][threadIdx.x];
+        if (v != 0.0) atomicAdd(&L->sd[stripe][threadIdx.x], v);
+    } else if (threadIdx.x >= 32 && threadIdx.x < 32 + LC_NC) {
+        const int i = threadIdx.x - 32;
+        unsigned long long v = 0;
+        for (int k = 0; k < BLOCK / WAVE; k++) v += s_c[k][i];
+        if (v) atomicAdd(&L->sc[stripe][i], v);
+    }
+    __syncthreads();
+    a.clear();
+}
+
+// ------------------------------------------------------------------ records
+template <typename Real>
+struct Pkt {
+    uint32_t src, estep, lp, cell;
+    Real r, rstop, w0;
+    Real d[3];
+};
+
+template <typename Real, int NB>
+__device__ __forceinline__ void load_pkt(const FrtRecs& q, uint32_t i, Pkt<Real>& h, Real* tau, Real* comp)
+{
+    h.src = q.src[i];
+    h.estep = q.estep[i];
+    h.lp = q.lp[i];
+    h.cell = q.cell[i];
+    h.r = ((const Real*)q.r)[i];
+    h.rstop = ((const Real*)q.rstop)[i];
+    h.w0 = ((const Real*)q.w0)[i];
+#pragma unroll
+    for (int a = 0; a < 3; a++) h.d[a] = ((const Real*)q.dir)[(size_t)a * q.cap + i];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        tau[b] = ((const Real*)q.tau)[(size_t)b * q.cap + i];
+        comp[b] = ((const Real*)q.comp)[(size_t)b * q.cap + i];
     }
 }
 
-__device__ __forceinline__ void ledger_add_u64(unsigned long long* target, unsigned long long v, bool uniform)
+template <typename Real, int NB>
+__device__ __forceinline__ void store_pkt(const FrtRecs& q, uint32_t i, const Pkt<Real>& h, uint32_t key,
+                                          const Real* tau, const Real* comp)
 {
-    if (uniform) {
-        unsigned long long s = wave_sum_u64(v);
-        if ((threadIdx.x & (WAVE - 1)) == 0 && s != 0) atomicAdd(target, s);
-    } else if (v != 0) {
-        atomicAdd(target, v);
+    q.src[i] = h.src;
+    q.estep[i] = h.estep;
+    q.lp[i] = h.lp;
+    q.cell[i] = h.cell;
+    q.key[i] = key;
+    ((Real*)q.r)[i] = h.r;
+    ((Real*)q.rstop)[i] = h.rstop;
+    ((Real*)q.w0)[i] = h.w0;
+#pragma unroll
+    for (int a = 0; a < 3; a++) ((Real*)q.dir)[(size_t)a * q.cap + i] = h.d[a];
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        ((Real*)q.tau)[(size_t)b * q.cap + i] = tau[b];
+        ((Real*)q.comp)[(size_t)b * q.cap + i] = comp[b];
     }
 }
 
-__device__ __forceinline__ int find_solve(const uint32_t* prefix, int n, uint32_t g)
+template <typename Real>
+__device__ __forceinline__ void packet_dir(const FrtSolveDesc& D, uint32_t lp, uint32_t estep, uint32_t src, Real d[3])
+{
+    nest_pixel_centre<Real>((int)(lp >> 28), lp & 0x0fffffffu, d);
+    quat_rotate<Real>(D.quat + ((size_t)estep * D.n_src + src) * 4, d);
+}
+
+// Cell of the point s + r d for a packet moving along d: floor per axis,
+// a point exactly on a face belongs to the cell being entered.  Returns
+// false when the point is outside the grid.
+template <typename Real>
+__device__ __forceinline__ bool locate(const FrtSolveDesc& D, const Real s[3], Real r, const Real d[3], int c[3])
+{
+    const int dims[3] = {D.nx, D.ny, D.nz};
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        Real p = s[a] + r * d[a];
+        Real f = floor(p);
+        if (p == f && d[a] < Real(0)) f -= Real(1);
+        in &= (f >= Real(0)) && (f < Real(dims[a]));
+        c[a] = in ? (int)f : 0;
+    }
+    return in;
+}
+
+__device__ __forceinline__ uint32_t brick_key(const FrtSolveDesc& D, const int c[3])
+{
+    const int B = D.brick;
+    return D.key_base + (uint32_t)(c[0] / B) + (uint32_t)D.bpx * ((uint32_t)(c[1] / B) + (uint32_t)D.bpy * (uint32_t)(c[2] / B));
+}
+
+__device__ __forceinline__ int find_in_prefix(const uint32_t* prefix, int n, uint32_t g)
 {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
@@ -170,138 +348,275 @@ __device__ __forceinline__ int find_solve(const uint32_t* prefix, int n, uint32_
     return lo;
 }
 
-template <typename Real> __device__ __forceinline__ Real rinf();
-template <> __device__ __forceinline__ float rinf<float>() { return __builtin_huge_valf(); }
-template <> __device__ __forceinline__ double rinf<double>() { return __builtin_huge_val(); }
-
-__device__ __forceinline__ float rexp(float x) { return expf(x); }
-__device__ __forceinline__ double rexp(double x) { return exp(x); }
-__device__ __forceinline__ float rexpm1(float x) { return expm1f(x); }
-__device__ __forceinline__ double rexpm1(double x) { return expm1(x); }
-
-template <typename Real> struct Vec2;
-template <> struct Vec2<float> { using T = float2; };
-template <> struct Vec2<double> { using T = double2; };
-
-// ------------------------------------------------------------ record access
-template <typename Real>
-struct Rec {
-    uint32_t src, estep, lp;
-    Real r, rstop, w0;
-};
-
-template <typename Real>
-__device__ __forceinline__ void push_record(const FrtQueue& q, uint32_t i, int nb, const Rec<Real>& h,
-                                            const Real* tau, const Real* comp)
+__device__ __forceinline__ void raise_error(FrtWS& ws, FrtLedgerDev* L, uint32_t bit)
 {
-    q.src[i] = h.src;
-    q.estep[i] = h.estep;
-    q.lp[i] = h.lp;
-    ((Real*)q.r)[i] = h.r;
-    ((Real*)q.rstop)[i] = h.rstop;
-    ((Real*)q.w0)[i] = h.w0;
-    for (int b = 0; b < nb; b++) {
-        ((Real*)q.tau)[(size_t)b * q.cap + i] = tau[b];
-        ((Real*)q.comp)[(size_t)b * q.cap + i] = comp[b];
-    }
+    atomicOr(&ws.ctr[C_ERR], bit);
+    atomicOr(&L->err_flags, bit);
 }
 
-// ==================================================================== emit
-// One lane per (source, base pixel): append a packet with r = 0 and the
-// photons Ndot_nu dt / (12 4^L0) per bin (§3.1, Eq. Nray), and make this
-// step's rotation of the source's sphere.
 template <typename Real>
-__global__ void __launch_bounds__(BLOCK) k_emit(FrtSolveDesc* descs, const uint32_t* prefix, int n_solves,
-                                                uint32_t total)
+__device__ __forceinline__ Real srel_of(const FrtSolveDesc& D, int b) { return (Real)D.sig_rel[b]; }
+
+template <typename Real>
+__device__ __forceinline__ Real K_of(const FrtSolveDesc& D, int b)
+{
+    if constexpr (sizeof(Real) == 4) return D.K[b];
+    else return (Real)D.Kd[b];
+}
+
+// ================================================================= seeding
+// Per solve: casting items (12 4^L0 per source) then the packets carried
+// from the previous step.
+__global__ void k_seed_plan(FrtSolveDesc* descs, FrtWS ws)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    uint32_t acc = 0;
+    for (int s = 0; s < ws.n_solves; s++) {
+        FrtSolveDesc& D = descs[s];
+        ws.seed_prefix[s] = acc;
+        uint32_t carried = D.fcount[D.cur];
+        if (carried > D.F[D.cur].cap) carried = D.F[D.cur].cap;
+        acc += (uint32_t)D.n_src * D.ncast + carried;
+        D.fcount[1 - D.cur] = 0;
+        D.L->step_crossings = 0;
+    }
+    ws.seed_prefix[ws.n_solves] = acc;
+    ws.ctr[C_NO] = 0;
+}
+
+// One lane per item: a cast packet gets r = 0 and Ndot_nu dt / (12 4^L0)
+// photons per bin on its pixel of the source's sphere rotated for this step
+// (§3.1, Eq. Nray); a carried packet is copied as it is.  Either goes to the
+// pass output with the key of its brick.
+template <typename Real, int NB>
+__global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
 {
     __shared__ uint32_t spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
-    for (int i = threadIdx.x; i <= n_solves; i += blockDim.x) spre[i] = prefix[i];
+    for (int i = threadIdx.x; i <= ws.n_solves; i += blockDim.x) spre[i] = ws.seed_prefix[i];
     __syncthreads();
+    const uint32_t total = spre[ws.n_solves];
+    LaneLedger led;
+    led.clear();
+    int cs = -1;
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < total; base += stride) {
         const uint32_t g = base + threadIdx.x;
         const bool active = g < total;
-        int si = active ? find_solve(spre, n_solves, g) : 0;
-        const bool uniform = __all(__shfl(si, 0, WAVE) == si);
+        const int si = find_in_prefix(spre, ws.n_solves, active ? g : base);
+        // flush when the block moves to another solve (block-uniform test)
+        __shared__ int s_first;
+        if (threadIdx.x == 0) s_first = si;
+        __syncthreads();
+        const int bsolve = s_first;
+        __syncthreads();
+        if (bsolve != cs) {
+            if (cs >= 0) ledger_flush(led, descs[cs].L);
+            cs = bsolve;
+        }
         FrtSolveDesc& D = descs[si];
-        double photons = 0.0;
+        Pkt<Real> h;
+        Real tau[NB], comp[NB];
+        uint32_t key = 0, want = 0;
         if (active) {
             const uint32_t local = g - spre[si];
-            const uint32_t ncast = 12u << (2 * D.base_level);
-            const uint32_t src = local / ncast, pix = local % ncast;
-            if (pix == 0) {
+            const uint32_t n_emit = (uint32_t)D.n_src * D.ncast;
+            if (local < n_emit) {
+                const uint32_t src = local / D.ncast, pix = local % D.ncast;
                 double u[3];
                 for (int k = 0; k < 3; k++)
                     u[k] = (D.step < D.user_steps) ? D.user_u[((size_t)D.step * D.n_src + src) * 3 + k]
                                                    : counter_uniform(D.seed, D.step, src, k);
                 double q[4];
                 shoemake_quat(u, q);
-                double* dst = D.quat + ((size_t)D.step * D.n_src + src) * 4;
-                for (int k = 0; k < 4; k++) dst[k] = q[k];
-            }
-            Rec<Real> h;
-            h.src = src;
-            h.estep = D.step;
-            h.lp = ((uint32_t)D.base_level << 28) | pix;
-            h.r = Real(0);
-            h.rstop = Real(0);
-            h.w0 = (Real)D.w0_cast;
-            Real zero[FRT_MAX_BINS_I] = {};
-            for (int b = 0; b < D.n_bins; b++) {
-                if constexpr (sizeof(Real) == 8) photons += h.w0 * D.specd[(size_t)src * D.n_bins + b];
-                else photons += (double)(h.w0 * D.spec[(size_t)src * D.n_bins + b]);
-            }
-            const FrtQueue& q = D.q[D.cur];
-            uint32_t at = atomicAdd(&D.count[D.cur], 1u);
-            if (at < q.cap) {
-                push_record<Real>(q, at, D.n_bins, h, zero, zero);
+                if (pix == 0) {
+                    double* dst = D.quat + ((size_t)D.step * D.n_src + src) * 4;
+                    for (int k = 0; k < 4; k++) dst[k] = q[k];
+                }
+                Real d[3];
+                nest_pixel_centre<Real>(D.base_level, pix, d);
+                quat_rotate<Real>(q, d);
+                h.src = src;
+                h.estep = D.step;
+                h.lp = ((uint32_t)D.base_level << 28) | pix;
+                h.r = Real(0);
+                h.rstop = Real(0);
+                h.w0 = (Real)D.w0_cast;
+                h.d[0] = d[0];
+                h.d[1] = d[1];
+                h.d[2] = d[2];
+                double photons = 0.0;
+#pragma unroll
+                for (int b = 0; b < NB; b++) {
+                    tau[b] = Real(0);
+                    comp[b] = Real(0);
+                    if constexpr (sizeof(Real) == 8) photons += h.w0 * D.specd[(size_t)src * NB + b];
+                    else photons += (double)(h.w0 * D.spec[(size_t)src * NB + b]);
+                }
+                photons *= D.R_ref;
+                const bool own = (si == bsolve);
+                if (own) {
+                    led.f[LF_EMITTED] += photons;
+                    led.c[LC_EMITTED] += 1;
+                } else {
+                    ledger_direct(D.L, LF_EMITTED, photons);
+                    ledger_direct_c(D.L, LC_EMITTED, 1);
+                }
+                const double* sp = D.src_pos + (size_t)src * 3;
+                const Real s3[3] = {(Real)sp[0], (Real)sp[1], (Real)sp[2]};
+                int c[3];
+                if (locate<Real>(D, s3, Real(0), d, c)) {
+                    h.cell = (uint32_t)c[0] + (uint32_t)D.nx * ((uint32_t)c[1] + (uint32_t)D.ny * (uint32_t)c[2]);
+                    key = brick_key(D, c);
+                    want = 1;
+                } else if (own) {                  // points out of the box from a boundary source
+                    led.f[LF_ESC] += photons;
+                    led.c[LC_NESC] += 1;
+                } else {
+                    ledger_direct(D.L, LF_ESC, photons);
+                    ledger_direct_c(D.L, LC_NESC, 1);
+                }
             } else {
-                atomicOr(&D.L->err_flags, (unsigned)FRT_DEVERR_QUEUE_OVERFLOW);
-                atomicAdd(&D.L->lost, photons * D.R_ref);
+                const uint32_t i = local - n_emit;
+                load_pkt<Real, NB>(D.F[D.cur], i, h, tau, comp);
+                key = D.key_base + D.F[D.cur].key[i];   // carried keys are solve-local
+                want = 1;
             }
         }
-        ledger_add(&D.L->emitted, photons * D.R_ref, uniform);
-        ledger_add_u64(&D.L->rays_emitted, active ? 1ull : 0ull, uniform);
-    }
-}
-
-// =============================================================== round plan
-// Prefix of this round's work items over the solves, and clearing of the
-// queues this round writes.
-__global__ void k_plan(FrtSolveDesc* descs, FrtRoundPlan* plan, int n_solves, int round)
-{
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    const int in_split = FRT_QS0 + ((round + 1) & 1);   // split queue read by rounds >= 1
-    const int out_split = FRT_QS0 + (round & 1);
-    uint32_t acc = 0;
-    for (int s = 0; s < n_solves; s++) {
-        FrtSolveDesc& D = descs[s];
-        plan->prefix[s] = acc;
-        uint32_t n;
-        if (round == 0) {
-            D.L->step_crossings = 0;
-            n = D.count[D.cur];
-            if (n > D.q[D.cur].cap) n = D.q[D.cur].cap;
-            D.count[1 - D.cur] = 0;     // packets carried into the next step
-        } else {
-            n = D.count[in_split];
-            if (n > D.q[in_split].cap) n = D.q[in_split].cap;
-            n *= 4u;
+        uint32_t at = wave_reserve(&ws.ctr[C_NO], want);
+        if (want) {
+            if (at < ws.O.cap) {
+                store_pkt<Real, NB>(ws.O, at, h, key, tau, comp);
+                atomicAdd(&ws.hist[key], 1u);
+            } else {
+                raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
+            }
         }
-        D.count[out_split] = 0;
-        if (n > D.L->max_items) D.L->max_items = n;
-        acc += n;
     }
-    plan->prefix[n_solves] = acc;
-    plan->n_solves = n_solves;
-    plan->in_slot = round == 0 ? -1 : in_split;
-    plan->out_slot = out_split;
-    plan->expand = round == 0 ? 0 : 1;
+    if (cs >= 0) ledger_flush(led, descs[cs].L);
 }
 
-// ==================================================================== march
-// Per lane: load a packet (or one child of a split parent), then walk cells
-// along src + r dir.  Per segment of length ds (cells) in cell i, per bin:
+// ============================================================ counting scan
+// One block: offsets of each brick's packets in the sorted buffer, the work
+// list (items of at most FRT_ITEM_RAYS packets of one brick), scatter
+// cursors; clears the histogram and the output counter.
+__global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
+{
+    __shared__ uint32_t s_a[1024], s_b[1024];
+    const uint32_t nk = ws.nkeys;
+    const uint32_t per = (nk + blockDim.x - 1) / blockDim.x;
+    const uint32_t k0 = threadIdx.x * per, k1 = min(nk, k0 + per);
+    uint32_t sum = 0, items = 0;
+    for (uint32_t k = k0; k < k1; k++) {
+        uint32_t h = ws.hist[k];
+        sum += h;
+        items += (h + FRT_ITEM_RAYS - 1) / FRT_ITEM_RAYS;
+    }
+    s_a[threadIdx.x] = sum;
+    s_b[threadIdx.x] = items;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+        uint32_t va = threadIdx.x >= (unsigned)o ? s_a[threadIdx.x - o] : 0u;
+        uint32_t vb = threadIdx.x >= (unsigned)o ? s_b[threadIdx.x - o] : 0u;
+        __syncthreads();
+        s_a[threadIdx.x] += va;
+        s_b[threadIdx.x] += vb;
+        __syncthreads();
+    }
+    uint32_t off = s_a[threadIdx.x] - sum;
+    uint32_t it = s_b[threadIdx.x] - items;
+    const uint32_t total = s_a[blockDim.x - 1];
+    const uint32_t total_items = s_b[blockDim.x - 1];
+    for (uint32_t k = k0; k < k1; k++) {
+        uint32_t h = ws.hist[k];
+        ws.cursor[k] = off;
+        if (h) {
+            const int solve = find_in_prefix(ws.key_prefix, ws.n_solves, k);
+            for (uint32_t m = 0; m * FRT_ITEM_RAYS < h; m++) {
+                if (it < ws.cap_work) {
+                    FrtWork w;
+                    w.key = k;
+                    w.start = off + m * FRT_ITEM_RAYS;
+                    w.count = min(FRT_ITEM_RAYS, h - m * FRT_ITEM_RAYS);
+                    w.solve = (uint32_t)solve;
+                    ws.work[it] = w;
+                }
+                it++;
+            }
+        }
+        off += h;
+        ws.hist[k] = 0;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t nO = ws.ctr[C_NO];
+        ws.ctr[C_NOS] = nO < ws.O.cap ? nO : ws.O.cap;
+        ws.ctr[C_NO] = 0;
+        ws.ctr[C_NP] = total;
+        ws.ctr[C_NWORK] = total_items < ws.cap_work ? total_items : ws.cap_work;
+        if (total > ws.ctr[C_MAXP]) ws.ctr[C_MAXP] = total;
+        if (total > ws.P.cap || total_items > ws.cap_work) ws.ctr[C_ERR] |= FRT_DEVERR_QUEUE_OVERFLOW;
+    }
+}
+
+// ================================================================= scatter
+// Move the pass outputs into brick order.  A block takes 256 consecutive
+// outputs (written by few waves, so few distinct bricks), counts them per
+// brick in an LDS hash table, reserves each brick's range with one atomic,
+// and copies the records.
+template <typename Real, int NB>
+__global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
+{
+    constexpr int SLOTS = 512;
+    constexpr uint32_t EMPTY = 0xffffffffu;
+    __shared__ uint32_t s_key[SLOTS], s_cnt[SLOTS], s_base[SLOTS];
+    const uint32_t n = ws.ctr[C_NOS];
+    const uint32_t stride = gridDim.x * blockDim.x;
+    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+        for (int i = threadIdx.x; i < SLOTS; i += blockDim.x) {
+            s_key[i] = EMPTY;
+            s_cnt[i] = 0;
+        }
+        __syncthreads();
+        const uint32_t i = base + threadIdx.x;
+        const bool active = i < n;
+        uint32_t key = 0, slot = 0, rank = 0;
+        bool valid = active;
+        if (active) {
+            key = ws.O.key[i];
+            if (key >= ws.nkeys) {          // never expected: flag and skip
+                atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_QUEUE_OVERFLOW);
+                valid = false;
+            }
+        }
+        if (valid) {
+            slot = (key * 2654435761u) & (SLOTS - 1);
+            for (;;) {
+                uint32_t prev = atomicCAS(&s_key[slot], EMPTY, key);
+                if (prev == EMPTY || prev == key) break;
+                slot = (slot + 1) & (SLOTS - 1);
+            }
+            rank = atomicAdd(&s_cnt[slot], 1u);
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < SLOTS; j += blockDim.x)
+            if (s_key[j] != EMPTY) s_base[j] = atomicAdd(&ws.cursor[s_key[j]], s_cnt[j]);
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = s_base[slot] + rank;
+            if (pos < ws.P.cap) {
+                Pkt<Real> h;
+                Real tau[NB], comp[NB];
+                load_pkt<Real, NB>(ws.O, i, h, tau, comp);
+                store_pkt<Real, NB>(ws.P, pos, h, key, tau, comp);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// =============================================================== brick march
+// One workgroup per work item (one brick, up to FRT_ITEM_RAYS packets).
+// Per segment of length ds (cells) in cell i and bin nu:
 //   tau    = (s_nu a_i + b_i) ds,  a_i = n_HI sigma_0 dx, b_i = kappa dx
 //   N_in   = N0 exp(-tau_sum)      (tau_sum carried with Kahan compensation)
 //   Gamma_i += K_nu N_in ds phi(tau),  phi = (1 - e^-tau)/tau,
@@ -309,147 +624,154 @@ __global__ void k_plan(FrtSolveDesc* descs, FrtRoundPlan* plan, int n_solves, in
 // which is Eq. gamma_avg_subgrid with lambda = 1/(n_HI sigma + kappa)
 // (Eq. gamma_initial_standard when kappa = 0).  End states in order:
 // distance cap, flux floor, split radius (Eq. r_split), leaving the box,
-// travel budget.
-template <typename Real, int NB, bool EXPAND>
-__global__ void __launch_bounds__(BLOCK) k_march(FrtSolveDesc* descs, const FrtRoundPlan* plan)
+// travel budget; leaving the brick hands the packet to the next pass.
+// Ledger terms are reduced per wave and added into LDS; output keys are
+// counted in an LDS table and added to the histogram once per work item.
+template <typename Real>
+__device__ __forceinline__ Real fast_rcp(Real x)
+{
+    if constexpr (sizeof(Real) == 4) return __builtin_amdgcn_rcpf(x);
+    else return Real(1) / x;
+}
+
+constexpr int KEY_SLOTS = 128;
+
+__device__ __forceinline__ void count_key(uint32_t* s_key, uint32_t* s_cnt, uint32_t* hist, uint32_t key)
+{
+    uint32_t slot = (key * 2654435761u) & (KEY_SLOTS - 1);
+    for (int probe = 0; probe < KEY_SLOTS; probe++) {
+        const uint32_t prev = atomicCAS(&s_key[slot], 0xffffffffu, key);
+        if (prev == 0xffffffffu || prev == key) {
+            atomicAdd(&s_cnt[slot], 1u);
+            return;
+        }
+        slot = (slot + 1) & (KEY_SLOTS - 1);
+    }
+    atomicAdd(&hist[key], 1u);   // table full: count directly
+}
+
+template <typename Real, int NB>
+__global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
 {
     using R2 = typename Vec2<Real>::T;
     constexpr bool F32 = sizeof(Real) == 4;
-    __shared__ uint32_t spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
-    const int n_solves = plan->n_solves;
-    for (int i = threadIdx.x; i <= n_solves; i += blockDim.x) spre[i] = plan->prefix[i];
-    __syncthreads();
-    const uint32_t total = spre[n_solves];
-    const int in_slot = plan->in_slot, out_slot = plan->out_slot;
-    const uint32_t stride = gridDim.x * blockDim.x;
-
-    for (uint32_t base = blockIdx.x * blockDim.x; base < total; base += stride) {
-        const uint32_t g = base + threadIdx.x;
-        const bool active = g < total;
-        const int si = active ? find_solve(spre, n_solves, g) : find_solve(spre, n_solves, total - 1);
-        const bool uniform = __all(__shfl(si, 0, WAVE) == si);
-        FrtSolveDesc& D = descs[si];
-        double d_abs = 0.0, d_sub = 0.0, d_esc = 0.0, d_drop = 0.0, d_fl = 0.0;
-        unsigned long long n_cross = 0, n_esc = 0, n_drop = 0, n_split = 0;
-        if (active) {
-            const uint32_t local = g - spre[si];
-            const int slot = EXPAND ? in_slot : (int)D.cur;
-            const FrtQueue& qi = D.q[slot];
-            const uint32_t e = EXPAND ? (local >> 2) : local;
-            Rec<Real> h;
-            h.src = qi.src[e];
-            h.estep = qi.estep[e];
-            h.lp = qi.lp[e];
-            h.r = ((const Real*)qi.r)[e];
-            h.rstop = ((const Real*)qi.rstop)[e];
-            h.w0 = ((const Real*)qi.w0)[e];
-            Real tau[NB], comp[NB], E[NB], N0[NB];
-#pragma unroll
-            for (int b = 0; b < NB; b++) {
-                tau[b] = ((const Real*)qi.tau)[(size_t)b * qi.cap + e];
-                comp[b] = ((const Real*)qi.comp)[(size_t)b * qi.cap + e];
+    constexpr int B = F32 ? FRT_BRICK_F32 : FRT_BRICK_F64;
+    constexpr int BC = B * B * B;
+    __shared__ R2 s_op[BC];
+    __shared__ Real s_g[BC];
+    __shared__ double s_lf[LF_NF];
+    __shared__ unsigned long long s_lc[LC_NC];
+    __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
+    const uint32_t nwork = ws.ctr[C_NWORK];
+    const uint32_t np = ws.ctr[C_NP] < ws.P.cap ? ws.ctr[C_NP] : ws.P.cap;
+    const int lane = threadIdx.x & (WAVE - 1);
+    if (threadIdx.x < LF_NF) s_lf[threadIdx.x] = 0.0;
+    if (threadIdx.x < LC_NC) s_lc[threadIdx.x] = 0;
+    if (threadIdx.x < KEY_SLOTS) { s_key[threadIdx.x] = 0xffffffffu; s_cnt[threadIdx.x] = 0; }
+    int cs = -1;
+    for (uint32_t item = blockIdx.x; item < nwork; item += gridDim.x) {
+        const FrtWork w = ws.work[item];
+        __syncthreads();
+        if ((int)w.solve != cs) {
+            if (cs >= 0 && threadIdx.x < LF_NF + LC_NC) {
+                FrtLedgerDev* L = descs[cs].L;
+                const int stripe = blockIdx.x % FRT_STRIPES;
+                if (threadIdx.x < LF_NF) {
+                    if (s_lf[threadIdx.x] != 0.0) atomicAdd(&L->sd[stripe][threadIdx.x], s_lf[threadIdx.x]);
+                    s_lf[threadIdx.x] = 0.0;
+                } else {
+                    const int c = threadIdx.x - LF_NF;
+                    if (s_lc[c]) atomicAdd(&L->sc[stripe][c], s_lc[c]);
+                    s_lc[c] = 0;
+                }
             }
-            int level = (int)(h.lp >> 28);
-            uint32_t pix = h.lp & 0x0fffffffu;
-            if (EXPAND) {
-                level += 1;
-                pix = 4u * pix + (local & 3u);
-                h.lp = ((uint32_t)level << 28) | pix;
-                h.w0 = h.w0 * Real(0.25);
-            } else {
-                h.rstop = h.r + (Real)D.budget;   // fresh travel budget each step
-            }
-            Real sum0 = 0, sumE = 0;
+            cs = (int)w.solve;
+        }
+        const FrtSolveDesc& D = descs[w.solve];
+        const uint32_t lb = w.key - D.key_base;
+        const int bx = (int)(lb % (uint32_t)D.bpx), by = (int)((lb / (uint32_t)D.bpx) % (uint32_t)D.bpy),
+                  bz = (int)(lb / ((uint32_t)D.bpx * (uint32_t)D.bpy));
+        const int ox = bx * B, oy = by * B, oz = bz * B;
+        const int nx = D.nx, ny = D.ny, nz = D.nz;
+        const R2* __restrict__ op = (const R2*)D.op;
+        for (int t = threadIdx.x; t < BC; t += BLOCK) {
+            const int lx = t % B, ly = (t / B) % B, lz = t / (B * B);
+            const int cx = ox + lx, cy = oy + ly, cz = oz + lz;
+            R2 v;
+            v.x = Real(0);
+            v.y = Real(0);
+            if (cx < nx && cy < ny && cz < nz) v = op[(size_t)cx + (size_t)nx * ((size_t)cy + (size_t)ny * (size_t)cz)];
+            s_op[t] = v;
+            s_g[t] = Real(0);
+        }
+        __syncthreads();
+        const Real r_cap = (Real)D.r_cap;
+        const Real floor_f = (Real)D.floor;
+        const double Rr = D.R_ref;
+        for (uint32_t jj = 0; jj < w.count; jj += BLOCK) {
+            const uint32_t j = jj + threadIdx.x;
+            const bool active = j < w.count && (w.start + j) < np;
+            Pkt<Real> h;
+            Real tau[NB], comp[NB], E[NB], N0[NB], s[3];
+            int level = 0, end = -1;     // -1 inactive, 0 split, 1 escaped, 2 dropped, 3 in flight, 4 next brick
+            int c[3] = {0, 0, 0};
+            double v_abs = 0.0, v_sub = 0.0, v_end = 0.0;
+            unsigned long long v_cross = 0;
+            if (active) {
+                load_pkt<Real, NB>(ws.P, w.start + j, h, tau, comp);
+                level = (int)(h.lp >> 28);
+                const double* sp = D.src_pos + (size_t)h.src * 3;
+                s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
+                if (h.estep != D.step && h.rstop <= h.r) h.rstop = h.r + (Real)D.budget;   // carried: fresh budget
+                if (h.estep == D.step && h.r == Real(0) && level == D.base_level) h.rstop = (Real)D.budget;
+                Real sum0 = 0;
+                double n_start = 0.0;
 #pragma unroll
-            for (int b = 0; b < NB; b++) {
-                Real spec;
-                if constexpr (F32) spec = D.spec[(size_t)h.src * NB + b];
-                else spec = D.specd[(size_t)h.src * NB + b];
-                N0[b] = h.w0 * spec;
-                E[b] = rexp(-tau[b]);
-                sum0 += N0[b];
-            }
-            double n_start = 0.0;
-#pragma unroll
-            for (int b = 0; b < NB; b++) n_start += (double)(N0[b] * E[b]);
-
-            // direction of (level, pix) on the source's rotated sphere
-            Real d[3];
-            nest_pixel_centre<Real>(level, pix, d);
-            quat_rotate<Real>(D.quat + ((size_t)h.estep * D.n_src + h.src) * 4, d);
-            const double* sp = D.src_pos + (size_t)h.src * 3;
-            const Real s[3] = {(Real)sp[0], (Real)sp[1], (Real)sp[2]};
-            const Real r_split = (level < D.max_level) ? (Real)(D.r_split0 * (double)(1u << level)) : rinf<Real>();
-            const Real r_cap = (Real)D.r_cap;
-            const int nx = D.nx, ny = D.ny, nz = D.nz;
-            const int dims[3] = {nx, ny, nz};
-            int c[3];
-            Real rf[3];
-            bool out = false;
-#pragma unroll
-            for (int a = 0; a < 3; a++) {
-                Real p = s[a] + h.r * d[a];
-                Real f = floor(p);
-                if (p == f && d[a] < Real(0)) f -= Real(1);
-                c[a] = (int)f;
-                out |= (c[a] < 0) || (c[a] >= dims[a]);
-            }
-            Real Kb[NB], srel[NB];
-#pragma unroll
-            for (int b = 0; b < NB; b++) {
-                srel[b] = (Real)D.sig_rel[b];
-                if constexpr (F32) Kb[b] = D.K[b];
-                else Kb[b] = D.Kd[b];
-            }
-            const R2* __restrict__ op = (const R2*)D.op;
-            Real* __restrict__ gam = (Real*)D.gamma[D.step & 1u];
-            // 0 = split, 1 = escaped, 2 = dropped, 3 = in flight
-            int end = 1;
-            float sub_acc = 0.f;
-            double sub_acc_d = 0.0;
-            if (!out) {
-                Real inv[3];
+                for (int b = 0; b < NB; b++) {
+                    Real spec;
+                    if constexpr (F32) spec = D.spec[(size_t)h.src * NB + b];
+                    else spec = D.specd[(size_t)h.src * NB + b];
+                    N0[b] = h.w0 * spec;
+                    E[b] = exp_neg(tau[b]);
+                    sum0 += N0[b];
+                    n_start += (double)(N0[b] * E[b]);
+                }
+                const uint32_t cl = h.cell;
+                c[0] = (int)(cl % (uint32_t)nx);
+                c[1] = (int)((cl / (uint32_t)nx) % (uint32_t)ny);
+                c[2] = (int)(cl / ((uint32_t)nx * (uint32_t)ny));
+                const Real r_split = (level < D.max_level) ? (Real)(D.r_split0 * (double)(1u << level)) : rinf<Real>();
+                Real inv[3], rf[3];
 #pragma unroll
                 for (int a = 0; a < 3; a++) {
-                    inv[a] = (d[a] != Real(0)) ? Real(1) / d[a] : Real(0);
-                    rf[a] = (d[a] != Real(0)) ? ((Real)(c[a] + (d[a] > Real(0) ? 1 : 0)) - s[a]) * inv[a]
-                                              : rinf<Real>();
+                    inv[a] = (h.d[a] != Real(0)) ? Real(1) / h.d[a] : Real(0);
+                    rf[a] = (h.d[a] != Real(0)) ? ((Real)(c[a] + (h.d[a] > Real(0) ? 1 : 0)) - s[a]) * inv[a] : rinf<Real>();
                 }
-                for (;;) {
+                Real sub_acc = 0;
+                const bool in_brick = c[0] >= ox && c[0] < ox + B && c[1] >= oy && c[1] < oy + B && c[2] >= oz && c[2] < oz + B;
+                if (!in_brick) end = 4;            // hand it to the brick that holds its cell
+                const Real floor_abs = floor_f * sum0;
+                while (end < 0) {
                     int axis = 0;
                     Real r_face = rf[0];
                     if (rf[1] < r_face) { r_face = rf[1]; axis = 1; }
                     if (rf[2] < r_face) { r_face = rf[2]; axis = 2; }
-                    Real r_end = r_face;
-                    r_end = fmin(r_end, r_split);
-                    r_end = fmin(r_end, r_cap);
-                    r_end = fmin(r_end, h.rstop);
+                    Real r_end = fmin(fmin(r_face, r_split), fmin(r_cap, h.rstop));
                     r_end = fmax(r_end, h.r);
                     const Real ds = r_end - h.r;
                     if (ds > Real(0)) {
-                        const size_t ci = (size_t)c[0] + (size_t)nx * ((size_t)c[1] + (size_t)ny * (size_t)c[2]);
-                        const R2 o = op[ci];
+                        const int li = (c[0] - ox) + B * ((c[1] - oy) + B * (c[2] - oz));
+                        const R2 o = s_op[li];
                         Real dep = 0;
 #pragma unroll
                         for (int b = 0; b < NB; b++) {
-                            const Real th = srel[b] * o.x * ds;
-                            const Real tb = th + o.y * ds;
+                            const Real tb = (srel_of<Real>(D, b) * o.x + o.y) * ds;
                             const Real nin = N0[b] * E[b];
-                            Real absf, phi;
-                            if (tb < Real(1e-4)) {
-                                phi = Real(1) - Real(0.5) * tb;
-                                absf = tb * phi;
-                            } else {
-                                absf = -rexpm1(-tb);
-                                phi = absf / tb;
-                            }
-                            dep += Kb[b] * nin * ds * phi;
-                            if (o.y > Real(0)) {
-                                if constexpr (F32) sub_acc += nin * absf * ((o.y * ds) / tb);
-                                else sub_acc_d += nin * absf * ((o.y * ds) / tb);
-                            }
+                            const Real af = absorbed_fraction(tb);
+                            const Real phi = (tb > Real(0)) ? af * fast_rcp(tb) : Real(1);
+                            dep += K_of<Real>(D, b) * nin * ds * phi;
+                            if (o.y > Real(0) && tb > Real(0)) sub_acc += nin * af * (o.y * ds) * fast_rcp(tb);
                             if constexpr (F32) {
-                                // Kahan-compensated running optical depth
                                 const Real y = tb - comp[b];
                                 const Real t = tau[b] + y;
                                 comp[b] = (t - tau[b]) - y;
@@ -457,63 +779,223 @@ __global__ void __launch_bounds__(BLOCK) k_march(FrtSolveDesc* descs, const FrtR
                             } else {
                                 tau[b] += tb;
                             }
-                            E[b] = rexp(-tau[b]);
+                            E[b] = exp_neg(tau[b]);
                         }
-                        if constexpr (F32) unsafeAtomicAdd(gam + ci, dep);
-                        else unsafeAtomicAdd(gam + ci, dep);
-                        n_cross++;
+                        atomicAdd(&s_g[li], dep);
+                        v_cross++;
                     }
                     h.r = r_end;
                     if (h.r >= r_cap) { end = 2; break; }
-                    if (D.floor > 0.f) {
-                        sumE = 0;
+                    if (floor_f > Real(0)) {
+                        Real sumE = 0;
 #pragma unroll
                         for (int b = 0; b < NB; b++) sumE += N0[b] * E[b];
-                        if (sumE < (Real)D.floor * sum0) { end = 2; break; }
+                        if (sumE < floor_abs) { end = 2; break; }
                     }
                     if (h.r >= r_split) { end = 0; break; }
                     if (h.r >= r_face) {
-                        c[axis] += (d[axis] > Real(0)) ? 1 : -1;
-                        if (c[axis] < 0 || c[axis] >= dims[axis]) { end = 1; break; }
-                        rf[axis] = ((Real)(c[axis] + (d[axis] > Real(0) ? 1 : 0)) - s[axis]) * inv[axis];
+                        // step to the next cell along `axis` (selects keep every
+                        // per-axis value in registers)
+                        const Real da = axis == 0 ? h.d[0] : (axis == 1 ? h.d[1] : h.d[2]);
+                        const int stp = da > Real(0) ? 1 : -1;
+                        if (axis == 0) c[0] += stp;
+                        else if (axis == 1) c[1] += stp;
+                        else c[2] += stp;
+                        const int ca = axis == 0 ? c[0] : (axis == 1 ? c[1] : c[2]);
+                        const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
+                        if (ca < 0 || ca >= dima) { end = 1; break; }
+                        const Real sa = axis == 0 ? s[0] : (axis == 1 ? s[1] : s[2]);
+                        const Real ia = axis == 0 ? inv[0] : (axis == 1 ? inv[1] : inv[2]);
+                        const Real rfa = ((Real)(ca + (stp > 0 ? 1 : 0)) - sa) * ia;
+                        if (axis == 0) rf[0] = rfa;
+                        else if (axis == 1) rf[1] = rfa;
+                        else rf[2] = rfa;
+                        const int loa = axis == 0 ? ox : (axis == 1 ? oy : oz);
+                        if (ca < loa || ca >= loa + B) {
+                            end = (h.r >= h.rstop) ? 3 : 4;
+                            break;
+                        }
                     }
                     if (h.r >= h.rstop) { end = 3; break; }
                 }
-            }
-            double n_end = 0.0;
+                double n_end = 0.0;
 #pragma unroll
-            for (int b = 0; b < NB; b++) n_end += (double)(N0[b] * E[b]);
-            const double Rr = D.R_ref;
-            d_abs = (n_start - n_end) * Rr;
-            d_sub = (F32 ? (double)sub_acc : sub_acc_d) * Rr;
-            if (end == 1) { d_esc = n_end * Rr; n_esc = 1; }
-            else if (end == 2) { d_drop = n_end * Rr; n_drop = 1; }
-            else {
-                const int qs = (end == 0) ? out_slot : (int)(1 - D.cur);
-                const FrtQueue& qo = D.q[qs];
-                uint32_t at = atomicAdd(&D.count[qs], 1u);
-                if (at < qo.cap) {
-                    push_record<Real>(qo, at, NB, h, tau, comp);
-                    if (end == 0) n_split = 1;
-                    else d_fl = n_end * Rr;
+                for (int b = 0; b < NB; b++) n_end += (double)(N0[b] * E[b]);
+                v_sub = (double)sub_acc * Rr;
+                v_abs = (n_start - n_end) * Rr - v_sub;
+                v_end = n_end * Rr;
+                h.cell = (uint32_t)c[0] + (uint32_t)nx * ((uint32_t)c[1] + (uint32_t)ny * (uint32_t)c[2]);
+            }
+            // ---- children of a split (Eq. lhpx): level + 1, pixel 4p + k,
+            // photons / 4, same rotation, re-centred on their own pixel
+            // direction at the split radius; a child outside the box escapes
+            Real cd[4][3];
+            uint32_t ccell[4] = {0, 0, 0, 0}, ckey[4] = {0, 0, 0, 0};
+            uint32_t cmask = 0;
+            if (end == 0) {
+                const uint32_t lpc = ((uint32_t)(level + 1) << 28) | (4u * (h.lp & 0x0fffffffu));
+#pragma unroll
+                for (int k = 0; k < 4; k++) {
+                    packet_dir<Real>(D, lpc + (uint32_t)k, h.estep, h.src, cd[k]);
+                    int cc[3];
+                    if (locate<Real>(D, s, h.r, cd[k], cc)) {
+                        ccell[k] = (uint32_t)cc[0] + (uint32_t)nx * ((uint32_t)cc[1] + (uint32_t)ny * (uint32_t)cc[2]);
+                        ckey[k] = brick_key(D, cc);
+                        cmask |= 1u << k;
+                    }
+                }
+            }
+            const uint32_t n_child = __builtin_popcount(cmask);
+            // ---- ledger: per-wave sums, one LDS atomic per field
+            {
+                const bool esc = end == 1, drop = end == 2, fl = end == 3;
+                const double v_cesc = (end == 0) ? 0.25 * (4 - n_child) * v_end : 0.0;
+                const double fv[LF_NF] = {0.0, v_abs, v_sub, (esc ? v_end : 0.0) + v_cesc, drop ? v_end : 0.0,
+                                          fl ? v_end : 0.0, 0.0};
+                const unsigned long long cv[LC_NC] = {v_cross, active ? 1ull : 0ull, end == 0 ? 1ull : 0ull,
+                                                      (esc ? 1ull : 0ull) + (end == 0 ? (unsigned long long)(4 - n_child) : 0ull),
+                                                      drop ? 1ull : 0ull, fl ? 1ull : 0ull, 0ull};
+#pragma unroll
+                for (int i = 1; i < LF_NF - 1; i++) {
+                    const double t = wave_sum(fv[i]);
+                    if (lane == 0 && t != 0.0) atomicAdd(&s_lf[i], t);
+                }
+#pragma unroll
+                for (int i = 0; i < LC_NC - 1; i++) {
+                    const unsigned long long t = wave_sum_u64(cv[i]);
+                    if (lane == 0 && t) atomicAdd(&s_lc[i], t);
+                }
+            }
+            // ---- one reservation per wave for everything going to the next pass;
+            // each record is written with its own bound check, so every slot
+            // below the capacity is filled even when a lane's range crosses it
+            const uint32_t n_o = (end == 4 ? 1u : 0u) + n_child;
+            const uint32_t at = wave_reserve(&ws.ctr[C_NO], n_o);
+            if (n_o) {
+                uint32_t lost = 0;
+                if (end == 4) {
+                    const uint32_t key = brick_key(D, c);
+                    if (at < ws.O.cap) {
+                        store_pkt<Real, NB>(ws.O, at, h, key, tau, comp);
+                        count_key(s_key, s_cnt, ws.hist, key);
+                    } else {
+                        lost = 4;
+                    }
                 } else {
-                    atomicOr(&D.L->err_flags, (unsigned)FRT_DEVERR_QUEUE_OVERFLOW);
-                    atomicAdd(&D.L->lost, n_end * Rr);
+                    uint32_t o = at;
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                        if (!(cmask & (1u << k))) continue;
+                        if (o < ws.O.cap) {
+                            Pkt<Real> ch = h;
+                            ch.lp = (((uint32_t)(level + 1)) << 28) | (4u * (h.lp & 0x0fffffffu) + (uint32_t)k);
+                            ch.w0 = h.w0 * Real(0.25);
+                            ch.cell = ccell[k];
+                            ch.d[0] = cd[k][0];
+                            ch.d[1] = cd[k][1];
+                            ch.d[2] = cd[k][2];
+                            store_pkt<Real, NB>(ws.O, o, ch, ckey[k], tau, comp);
+                            count_key(s_key, s_cnt, ws.hist, ckey[k]);
+                        } else {
+                            lost += 1;
+                        }
+                        o++;
+                    }
+                }
+                if (lost) {
+                    raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
+                    atomicAdd(&s_lf[LF_LOST], 0.25 * lost * v_end);
+                }
+            }
+            // ---- packets that spent their travel budget: carried to the next step
+            const int nxt = 1 - (int)D.cur;
+            const uint32_t fat = wave_reserve(&D.fcount[nxt], end == 3 ? 1u : 0u);
+            if (end == 3) {
+                if (fat < D.F[nxt].cap) {
+                    store_pkt<Real, NB>(D.F[nxt], fat, h, brick_key(D, c) - D.key_base, tau, comp);
+                } else {
+                    raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
+                    atomicAdd(&s_lf[LF_LOST], v_end);
                 }
             }
         }
+        __syncthreads();
+        // add the brick's deposits and its output-key counts once
+        Real* __restrict__ gam = (Real*)D.gamma[D.step & 1u];
+        for (int t = threadIdx.x; t < BC; t += BLOCK) {
+            const Real v = s_g[t];
+            if (v != Real(0)) {
+                const int lx = t % B, ly = (t / B) % B, lz = t / (B * B);
+                const size_t ci = (size_t)(ox + lx) + (size_t)nx * ((size_t)(oy + ly) + (size_t)ny * (size_t)(oz + lz));
+                atomicAdd(gam + ci, v);
+            }
+        }
+        if (threadIdx.x < KEY_SLOTS) {
+            const uint32_t k = s_key[threadIdx.x];
+            if (k != 0xffffffffu) {
+                atomicAdd(&ws.hist[k], s_cnt[threadIdx.x]);
+                s_key[threadIdx.x] = 0xffffffffu;
+                s_cnt[threadIdx.x] = 0;
+            }
+        }
+    }
+    __syncthreads();
+    if (cs >= 0 && threadIdx.x < LF_NF + LC_NC) {
+        FrtLedgerDev* L = descs[cs].L;
+        const int stripe = blockIdx.x % FRT_STRIPES;
+        if (threadIdx.x < LF_NF) {
+            if (s_lf[threadIdx.x] != 0.0) atomicAdd(&L->sd[stripe][threadIdx.x], s_lf[threadIdx.x]);
+        } else {
+            const int c = threadIdx.x - LF_NF;
+            if (s_lc[c]) atomicAdd(&L->sc[stripe][c], s_lc[c]);
+        }
+    }
+}
+
+// =============================================================== step close
+// After the last pass: anything still queued means the pass count was too
+// small (flagged, never expected); fold the ledger stripes.
+__global__ void k_finish(FrtSolveDesc* descs, FrtWS ws)
+{
+    __shared__ int s_left;
+    if (threadIdx.x == 0) s_left = ws.ctr[C_NO] > 0 ? 1 : 0;
+    __syncthreads();
+    for (int s = blockIdx.x; s < ws.n_solves; s += gridDim.x) {
+        FrtSolveDesc& D = descs[s];
         FrtLedgerDev* L = D.L;
-        ledger_add(&L->absorbed_HI, d_abs - d_sub, uniform);
-        ledger_add(&L->absorbed_sub, d_sub, uniform);
-        ledger_add(&L->escaped, d_esc, uniform);
-        ledger_add(&L->dropped, d_drop, uniform);
-        ledger_add(&L->in_flight_acc, d_fl, uniform);
-        ledger_add_u64(&L->crossings, n_cross, uniform);
-        ledger_add_u64(&L->step_crossings, n_cross, uniform);
-        ledger_add_u64(&L->ray_visits, active ? 1ull : 0ull, uniform);
-        ledger_add_u64(&L->n_escaped, n_esc, uniform);
-        ledger_add_u64(&L->n_dropped, n_drop, uniform);
-        ledger_add_u64(&L->splits, n_split, uniform);
+        if (threadIdx.x < LF_NF + LC_NC) {
+            const int i = threadIdx.x;
+            if (i < LF_NF) {
+                double v = 0;
+                for (int k = 0; k < FRT_STRIPES; k++) { v += L->sd[k][i]; L->sd[k][i] = 0.0; }
+                switch (i) {
+                    case LF_EMITTED: L->emitted += v; break;
+                    case LF_ABS_HI: L->absorbed_HI += v; break;
+                    case LF_ABS_SUB: L->absorbed_sub += v; break;
+                    case LF_ESC: L->escaped += v; break;
+                    case LF_DROP: L->dropped += v; break;
+                    case LF_FLIGHT: L->in_flight = v; break;
+                    case LF_LOST: L->lost += v; break;
+                }
+            } else {
+                const int j = i - LF_NF;
+                unsigned long long v = 0;
+                for (int k = 0; k < FRT_STRIPES; k++) { v += L->sc[k][j]; L->sc[k][j] = 0; }
+                switch (j) {
+                    case LC_CROSS: L->crossings += v; L->step_crossings = v; break;
+                    case LC_VISITS: L->ray_visits += v; break;
+                    case LC_SPLITS: L->splits += v; break;
+                    case LC_NESC: L->n_escaped += v; break;
+                    case LC_NDROP: L->n_dropped += v; break;
+                    case LC_NFLIGHT: L->n_in_flight = v; break;
+                    case LC_EMITTED: L->rays_emitted += v; break;
+                }
+            }
+        }
+        if (threadIdx.x == 0) {
+            if (s_left) L->err_flags |= FRT_DEVERR_UNFINISHED;
+            if (ws.ctr[C_MAXP] > L->max_items) L->max_items = ws.ctr[C_MAXP];
+        }
     }
 }
 
@@ -522,7 +1004,8 @@ __global__ void __launch_bounds__(BLOCK) k_march(FrtSolveDesc* descs, const FrtR
 //   x' - x = dt [ -Gamma x' - C n_H (1-x') x' + alpha n_H (1-x')^2 ]
 // (Eq. ion_balance_eqn), i.e. a x'^2 + b x' + c = 0 with the root in [0,1]
 // taken as 2c / (-b + sqrt(b^2 - 4ac)).  Also rebuilds the opacity of the
-// next step and clears the next step's deposit buffer.
+// next step and clears the next step's deposit buffer.  A step whose queues
+// overflowed leaves the state untouched.
 template <typename Real>
 __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsigned long long* prefix,
                                                 int n_solves, unsigned long long total)
@@ -540,7 +1023,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
             else hi = mid - 1;
         }
         const FrtSolveDesc& D = descs[lo];
-        if (D.L->err_flags & FRT_DEVERR_QUEUE_OVERFLOW) continue;   // failed step: keep the state
+        if (D.L->err_flags) continue;
         const size_t i = (size_t)(g - spre[lo]);
         Real* gcur = (Real*)D.gamma[D.step & 1u];
         Real* gnext = (Real*)D.gamma[(D.step + 1u) & 1u];
@@ -574,53 +1057,71 @@ __global__ void __launch_bounds__(BLOCK) k_prep(FrtSolveDesc* desc, unsigned lon
         op[i].x = (Real)(D.nH[i] * D.x[i] * D.sigma0 * D.dx_cm);
 }
 
-// Close the step: packets that ended in flight become the ledger's
-// in-flight term; any split parents left after the last round (none by
-// construction of the round count) are counted as lost.
-__global__ void k_step_end(FrtSolveDesc* descs, int n_solves)
-{
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_solves) return;
-    FrtSolveDesc& D = descs[s];
-    FrtLedgerDev* L = D.L;
-    L->in_flight = L->in_flight_acc;
-    L->in_flight_acc = 0.0;
-    uint32_t nf = D.count[1 - D.cur];
-    L->n_in_flight = nf < D.q[1 - D.cur].cap ? nf : D.q[1 - D.cur].cap;
-    L->step_visits = 0;
-}
+int g_cu_count = 0;
 
-template <typename T>
-__global__ void k_fill(T* p, T v, size_t n)
+int cu_count()
 {
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-        p[i] = v;
+    if (g_cu_count == 0) {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&g_cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+        if (g_cu_count <= 0) g_cu_count = 256;
+    }
+    return g_cu_count;
 }
-
-int g_sm_count = 0;
 
 int grid_for(unsigned long long items, int per_cu)
 {
-    if (g_sm_count == 0) {
-        int dev = 0;
-        (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&g_sm_count, hipDeviceAttributeMultiprocessorCount, dev);
-        if (g_sm_count <= 0) g_sm_count = 256;
-    }
     unsigned long long want = (items + BLOCK - 1) / BLOCK;
-    unsigned long long cap = (unsigned long long)g_sm_count * per_cu;
+    unsigned long long cap = (unsigned long long)cu_count() * per_cu;
     if (want < 1) want = 1;
     return (int)(want < cap ? want : cap);
 }
 
-template <typename Real, bool EXPAND>
-hipError_t launch_march_nb(FrtSolveDesc* d, FrtRoundPlan* p, int nb, hipStream_t s)
+template <typename Real, int NB>
+void launch_seed_nb(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
 {
-    const int grid = grid_for(1ull << 40, 8);
-    switch (nb) {
-#define CASE(N) case N: hipLaunchKernelGGL((k_march<Real, N, EXPAND>), dim3(grid), dim3(BLOCK), 0, s, d, p); break;
-        CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
-#undef CASE
+    hipLaunchKernelGGL((k_seed<Real, NB>), dim3(cu_count() * 4), dim3(BLOCK), 0, s, d, ws);
+}
+
+template <typename Real, int NB>
+void launch_pass_nb(FrtSolveDesc* d, const FrtWS& ws, int part, hipStream_t s)
+{
+    if (part == 0) hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws);
+    else if (part == 1) hipLaunchKernelGGL((k_scatter<Real, NB>), dim3(cu_count() * 8), dim3(BLOCK), 0, s, ws);
+    else hipLaunchKernelGGL((k_brick<Real, NB>), dim3(cu_count() * (sizeof(Real) == 4 ? 3 : 8)), dim3(BLOCK), 0, s, d, ws);
+}
+
+template <typename Real>
+hipError_t seed_t(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_seed_plan, dim3(1), dim3(64), 0, s, d, ws);
+    switch (ws.n_bins) {
+        case 1: launch_seed_nb<Real, 1>(d, ws, s); break;
+        case 2: launch_seed_nb<Real, 2>(d, ws, s); break;
+        case 3: launch_seed_nb<Real, 3>(d, ws, s); break;
+        case 4: launch_seed_nb<Real, 4>(d, ws, s); break;
+        case 5: launch_seed_nb<Real, 5>(d, ws, s); break;
+        case 6: launch_seed_nb<Real, 6>(d, ws, s); break;
+        case 7: launch_seed_nb<Real, 7>(d, ws, s); break;
+        case 8: launch_seed_nb<Real, 8>(d, ws, s); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename Real>
+hipError_t pass_t(FrtSolveDesc* d, const FrtWS& ws, int part, hipStream_t s)
+{
+    switch (ws.n_bins) {
+        case 1: launch_pass_nb<Real, 1>(d, ws, part, s); break;
+        case 2: launch_pass_nb<Real, 2>(d, ws, part, s); break;
+        case 3: launch_pass_nb<Real, 3>(d, ws, part, s); break;
+        case 4: launch_pass_nb<Real, 4>(d, ws, part, s); break;
+        case 5: launch_pass_nb<Real, 5>(d, ws, part, s); break;
+        case 6: launch_pass_nb<Real, 6>(d, ws, part, s); break;
+        case 7: launch_pass_nb<Real, 7>(d, ws, part, s); break;
+        case 8: launch_pass_nb<Real, 8>(d, ws, part, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -630,49 +1131,31 @@ hipError_t launch_march_nb(FrtSolveDesc* d, FrtRoundPlan* p, int nb, hipStream_t
 
 namespace frt {
 
-int device_sm_count()
+int device_cu_count() { return cu_count(); }
+
+hipError_t launch_seed(FrtSolveDesc* d, const FrtWS& ws, int fp64, hipStream_t s)
 {
-    grid_for(1, 1);
-    return g_sm_count;
+    return fp64 ? seed_t<double>(d, ws, s) : seed_t<float>(d, ws, s);
 }
 
-hipError_t launch_emit(FrtSolveDesc* d_descs, const uint32_t* d_emit_prefix, int n_solves, uint32_t total_items,
-                       int fp64, hipStream_t s)
+hipError_t launch_pass(FrtSolveDesc* d, const FrtWS& ws, int fp64, int part, hipStream_t s)
 {
-    if (total_items == 0) return hipSuccess;
-    const int grid = grid_for(total_items, 8);
-    if (fp64) hipLaunchKernelGGL(k_emit<double>, dim3(grid), dim3(BLOCK), 0, s, d_descs, d_emit_prefix, n_solves, total_items);
-    else hipLaunchKernelGGL(k_emit<float>, dim3(grid), dim3(BLOCK), 0, s, d_descs, d_emit_prefix, n_solves, total_items);
+    return fp64 ? pass_t<double>(d, ws, part, s) : pass_t<float>(d, ws, part, s);
+}
+
+hipError_t launch_finish(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finish, dim3(ws.n_solves < 1024 ? ws.n_solves : 1024), dim3(64), 0, s, d, ws);
     return hipGetLastError();
 }
 
-hipError_t launch_round(FrtSolveDesc* d_descs, FrtRoundPlan* d_plan, int n_solves, int round, int fp64, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(64), 0, s, d_descs, d_plan, n_solves, round);
-    return hipGetLastError();
-}
-
-hipError_t launch_round_march(FrtSolveDesc* d_descs, FrtRoundPlan* d_plan, int round, int nb, int fp64, hipStream_t s)
-{
-    if (fp64) return round == 0 ? launch_march_nb<double, false>(d_descs, d_plan, nb, s)
-                                : launch_march_nb<double, true>(d_descs, d_plan, nb, s);
-    return round == 0 ? launch_march_nb<float, false>(d_descs, d_plan, nb, s)
-                      : launch_march_nb<float, true>(d_descs, d_plan, nb, s);
-}
-
-hipError_t launch_chem(FrtSolveDesc* d_descs, const unsigned long long* d_cell_prefix, int n_solves,
+hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
                        unsigned long long total_cells, int fp64, hipStream_t s)
 {
     if (total_cells == 0) return hipSuccess;
     const int grid = grid_for(total_cells, 16);
-    if (fp64) hipLaunchKernelGGL(k_chem<double>, dim3(grid), dim3(BLOCK), 0, s, d_descs, d_cell_prefix, n_solves, total_cells);
-    else hipLaunchKernelGGL(k_chem<float>, dim3(grid), dim3(BLOCK), 0, s, d_descs, d_cell_prefix, n_solves, total_cells);
-    return hipGetLastError();
-}
-
-hipError_t launch_step_end(FrtSolveDesc* d_descs, int n_solves, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_step_end, dim3((n_solves + 63) / 64), dim3(64), 0, s, d_descs, n_solves);
+    if (fp64) hipLaunchKernelGGL(k_chem<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells);
+    else hipLaunchKernelGGL(k_chem<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells);
     return hipGetLastError();
 }
 
@@ -682,27 +1165,6 @@ hipError_t launch_prep_opacity(FrtSolveDesc* d_desc, unsigned long long ncell, i
     const int grid = grid_for(ncell, 16);
     if (fp64) hipLaunchKernelGGL(k_prep<double>, dim3(grid), dim3(BLOCK), 0, s, d_desc, ncell);
     else hipLaunchKernelGGL(k_prep<float>, dim3(grid), dim3(BLOCK), 0, s, d_desc, ncell);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s)
-{
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_fill<uint32_t>, dim3(grid_for(n, 16)), dim3(BLOCK), 0, s, p, v, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_f32(float* p, float v, size_t n, hipStream_t s)
-{
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_fill<float>, dim3(grid_for(n, 16)), dim3(BLOCK), 0, s, p, v, n);
-    return hipGetLastError();
-}
-
-hipError_t launch_fill_f64(double* p, double v, size_t n, hipStream_t s)
-{
-    if (!n) return hipSuccess;
-    hipLaunchKernelGGL(k_fill<double>, dim3(grid_for(n, 16)), dim3(BLOCK), 0, s, p, v, n);
     return hipGetLastError();
 }
 

@@ -25,7 +25,8 @@ MAX_BINS = 8
 EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_error", "frt_solve_create",
            "frt_solve_destroy", "frt_load_grid", "frt_load_sources", "frt_set_rotations", "frt_step",
            "frt_batch_step", "frt_sync", "frt_read_fields", "frt_read_ledger", "frt_save_state",
-           "frt_load_state", "frt_rotation_uniforms")
+           "frt_load_state", "frt_mark", "frt_rewind", "frt_set_timing", "frt_read_timing",
+           "frt_rotation_uniforms")
 
 
 class FrtError(RuntimeError):
@@ -49,6 +50,15 @@ class Ledger(C.Structure):
                 ("splits", C.c_uint64), ("n_escaped", C.c_uint64), ("n_dropped", C.c_uint64),
                 ("n_in_flight", C.c_uint64), ("rays_emitted", C.c_uint64), ("step_crossings", C.c_uint64),
                 ("steps", C.c_uint64), ("err_flags", C.c_uint32), ("max_items", C.c_uint32)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Timing(C.Structure):
+    _fields_ = [("emit_ms", C.c_double), ("march_ms", C.c_double), ("chem_ms", C.c_double),
+                ("other_ms", C.c_double), ("march_launches", C.c_uint64), ("chem_launches", C.c_uint64),
+                ("steps", C.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -82,6 +92,10 @@ def lib():
         L.frt_read_ledger.argtypes = [vp, C.POINTER(Ledger)]
         L.frt_save_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
         L.frt_load_state.argtypes = [vp, vp, C.c_size_t]
+        L.frt_mark.argtypes = [vp]
+        L.frt_rewind.argtypes = [vp]
+        L.frt_set_timing.argtypes = [vp, C.c_int]
+        L.frt_read_timing.argtypes = [vp, C.POINTER(Timing)]
         L.frt_rotation_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_double)]
         _lib = L
     return _lib
@@ -220,6 +234,20 @@ class Solve:
         L = Ledger()
         _check(lib().frt_read_ledger(self.h, C.byref(L)))
         return L.as_dict()
+
+    def mark(self):
+        _check(lib().frt_mark(self.h))
+
+    def rewind(self):
+        _check(lib().frt_rewind(self.h))
+
+    def set_timing(self, on: bool = True):
+        _check(lib().frt_set_timing(self.h, 1 if on else 0))
+
+    def timing(self) -> dict:
+        t = Timing()
+        _check(lib().frt_read_timing(self.h, C.byref(t)))
+        return t.as_dict()
 
     def save(self) -> bytes:
         n = C.c_size_t(0)

@@ -160,6 +160,23 @@ def test_checkpoint_resume(ctx):
     assert La["crossings"] == Lc["crossings"]
 
 
+def test_mark_and_rewind_repeat_a_step(ctx):
+    p = W.lognormal_c2(n=24, n_src=6, n_steps=3, box_cmpc_h=20.0 * 24 / 128)
+    a = _gpu(ctx, p, 1)
+    b = frt.solve_from_problem(ctx, p)
+    b.mark()
+    for _ in range(3):
+        b.rewind()
+        b.step(p.dt_s)
+    xa, ga = a.fields()
+    xb, gb = b.fields()
+    assert np.abs(xa - xb).max() <= 1e-6
+    assert np.abs(ga - gb).max() <= 1e-5 * ga.max()
+    La, Lb = a.ledger(), b.ledger()
+    assert Lb["crossings"] == 3 * La["crossings"]
+    assert Lb["step_crossings"] == La["step_crossings"]
+
+
 def test_batched_equals_alone(ctx):
     boxes = W.batch_c4(n_boxes=5, n_steps=4, sizes=(16, 24, 32), max_src=12, seed=41)
     alone = [_gpu(ctx, b, 4) for b in boxes]
@@ -174,6 +191,36 @@ def test_batched_equals_alone(ctx):
     # and the batch against the oracle for two of the boxes
     for b, s in list(zip(boxes, batched))[:2]:
         _compare(_oracle(b, 4), s, 1e-3, 1e-4, f"batched {b.name}")
+
+
+def _dense_ray_problem():
+    # 32^3 box, nearly transparent, N_min = 4 (split radius 0.49 * 2^l cells),
+    # 60 sources: level-5 packets number up to 12 * 4^5 per source, far more
+    # per pass than the automatic initial pass buffers (about 7e4 records)
+    p = W.grf_c3(n=32, n_src=60, throughput=True, n_steps=2, box_cmpc_h=100.0 * 32 / 256)
+    p.x_HI0 = np.full(p.shape, 1e-6)
+    p.flux_floor = 0.0
+    p.n_ray_min = 4.0
+    return p
+
+
+def test_queue_growth_reruns_the_step(ctx):
+    p = _dense_ray_problem()
+    g = _gpu(ctx, p, 2)
+    assert g.ledger()["max_items"] > 4 * 60 * 12 + 65536
+    _compare(_oracle(p, 2), g, 1e-3, 1e-4, "queue growth")
+
+
+def test_fixed_capacity_overflow_is_reported_and_not_applied(ctx):
+    p = _dense_ray_problem()
+    g = frt.solve_from_problem(ctx, p, queue_capacity=2000)
+    x0, _ = g.fields()
+    g.step(p.dt_s)
+    with pytest.raises(frt.FrtError) as e:
+        g.sync()
+    assert e.value.code == frt.FRT_EOVERFLOW
+    x1, _ = g.fields()
+    assert np.array_equal(x0, x1)
 
 
 def test_invalid_inputs_are_rejected(ctx):
