@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--sources", type=int, default=2000)
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=1024,
+                    help="size of a plain device copy run before timing; its hardware byte counters "
+                         "calibrate the march kernel's (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form "
@@ -100,6 +103,13 @@ def main():
     # packet dies in its source cell, so only the first step from this state
     # carries the workload's crossings.
     s.mark()
+    if args.copy_calibration_mib > 0:
+        n = args.copy_calibration_mib * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     log(f"loaded {prob.name}; warmup {args.warmup} step(s)")
     for _ in range(args.warmup):
         s.rewind()
@@ -126,9 +136,8 @@ def main():
     value = cross / (total_ms * 1e-3)
 
     nb = prob.n_bins
-    rec = 24 + 8 * nb                                   # bytes of one queue entry
     d_visits = L1["ray_visits"] - L0["ray_visits"]
-    rec += 8                                            # cell index and brick key
+    rec = 5 * 4 + 10 * 4                                # src, estep, lp, cell, key; r, rstop, w0, dir[3], tau[4]
     march_bytes = 12.0 * cross + 2.0 * rec * d_visits   # record read and written once per visit
     closure = abs(L1["emitted"] - L1["absorbed_HI"] - L1["absorbed_sub"] - L1["escaped"] - L1["dropped"]
                   - L1["in_flight"] - L1["lost"]) / L1["emitted"]

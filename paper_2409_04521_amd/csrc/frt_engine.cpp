@@ -77,7 +77,7 @@ void dev_free(T*& p)
 void free_recs(FrtRecs& q)
 {
     dev_free(q.src); dev_free(q.estep); dev_free(q.lp); dev_free(q.cell); dev_free(q.key);
-    dev_free(q.r); dev_free(q.rstop); dev_free(q.w0); dev_free(q.dir); dev_free(q.tau); dev_free(q.comp);
+    dev_free(q.r); dev_free(q.rstop); dev_free(q.w0); dev_free(q.dir); dev_free(q.tau);
     q.cap = 0;
 }
 
@@ -90,8 +90,7 @@ int alloc_recs(FrtRecs& q, uint32_t cap, int nb, size_t rs)
     if ((rc = dev_alloc((void**)&n.src, c * 4)) || (rc = dev_alloc((void**)&n.estep, c * 4)) ||
         (rc = dev_alloc((void**)&n.lp, c * 4)) || (rc = dev_alloc((void**)&n.cell, c * 4)) ||
         (rc = dev_alloc((void**)&n.key, c * 4)) || (rc = dev_alloc(&n.r, c * rs)) || (rc = dev_alloc(&n.rstop, c * rs)) ||
-        (rc = dev_alloc(&n.w0, c * rs)) || (rc = dev_alloc(&n.dir, c * rs * 3)) || (rc = dev_alloc(&n.tau, c * rs * nb)) ||
-        (rc = dev_alloc(&n.comp, c * rs * nb))) {
+        (rc = dev_alloc(&n.w0, c * rs)) || (rc = dev_alloc(&n.dir, c * rs * 3)) || (rc = dev_alloc(&n.tau, c * rs * 4))) {
         free_recs(n);
         return rc;
     }
@@ -114,12 +113,10 @@ int copy_recs(FrtRecs& dst, const FrtRecs& src, uint32_t n, int nb, size_t rs, h
     for (int a = 0; a < 3; a++)
         HIPCHK(hipMemcpyAsync((char*)dst.dir + a * (size_t)dst.cap * rs, (const char*)src.dir + a * (size_t)src.cap * rs,
                               n * rs, k, st));
-    for (int b = 0; b < nb; b++) {
+    for (int b = 0; b < 4; b++)
         HIPCHK(hipMemcpyAsync((char*)dst.tau + b * (size_t)dst.cap * rs, (const char*)src.tau + b * (size_t)src.cap * rs,
                               n * rs, k, st));
-        HIPCHK(hipMemcpyAsync((char*)dst.comp + b * (size_t)dst.cap * rs, (const char*)src.comp + b * (size_t)src.cap * rs,
-                              n * rs, k, st));
-    }
+    (void)nb;
     return FRT_OK;
 }
 
@@ -1020,7 +1017,7 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     const int cur = (int)(s->step & 1u);
     const uint32_t nc = std::min(fc[cur], s->F[cur].cap);
     const int nb = s->P.n_bins;
-    const size_t rec = 20 + 6 * s->rs + 2 * nb * s->rs;
+    const size_t rec = 20 + 10 * s->rs;
     const size_t led = offsetof(FrtLedgerDev, sd);
     const size_t nq = (size_t)s->step * s->n_src * 4;
     const size_t need = 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec;
@@ -1030,7 +1027,7 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     }
     if (*bytes < need) return fail(FRT_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
     char* p = (char*)buf;
-    uint64_t hdr[8] = {0x4652544350543033ull, 3, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
+    uint64_t hdr[8] = {0x4652544350543034ull, 4, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
     RCCHK(scopy(s, p, s->L, led, hipMemcpyDeviceToHost));
@@ -1051,8 +1048,7 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
         hv.rstop = p; p += nc * s->rs;
         hv.w0 = p; p += nc * s->rs;
         hv.dir = p; p += nc * s->rs * 3;
-        hv.tau = p; p += nc * s->rs * nb;
-        hv.comp = p; p += nc * s->rs * nb;
+        hv.tau = p; p += nc * s->rs * 4;
         RCCHK(copy_recs(hv, s->F[cur], nc, nb, s->rs, s->stream, hipMemcpyDeviceToHost));
         HIPCHK(hipStreamSynchronize(s->stream));
     }
@@ -1069,12 +1065,12 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     uint64_t hdr[8];
     std::memcpy(hdr, p, sizeof(hdr));
     p += sizeof(hdr);
-    if (hdr[0] != 0x4652544350543033ull || hdr[1] != 3) return fail(FRT_EINVAL, "not a checkpoint of this library");
+    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 4) return fail(FRT_EINVAL, "not a checkpoint of this library");
     if (hdr[3] != (uint64_t)s->n_src || hdr[4] != s->ncell || hdr[5] != (uint64_t)s->P.n_bins || hdr[6] != (uint64_t)s->fp64)
         return fail(FRT_EINVAL, "checkpoint does not match this solve (sources, grid, bins or precision)");
     const uint32_t step = (uint32_t)hdr[2], nc = (uint32_t)hdr[7];
     const int nb = s->P.n_bins;
-    const size_t rec = 20 + 6 * s->rs + 2 * nb * s->rs;
+    const size_t rec = 20 + 10 * s->rs;
     const size_t nq = (size_t)step * s->n_src * 4;
     if (bytes < 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec) return fail(FRT_EINVAL, "checkpoint truncated");
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -1111,8 +1107,7 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
         hv.rstop = q; q += nc * s->rs;
         hv.w0 = q; q += nc * s->rs;
         hv.dir = q; q += nc * s->rs * 3;
-        hv.tau = q; q += nc * s->rs * nb;
-        hv.comp = q; q += nc * s->rs * nb;
+        hv.tau = q; q += nc * s->rs * 4;
         RCCHK(copy_recs(s->F[cur], hv, nc, nb, s->rs, s->stream, hipMemcpyHostToDevice));
         HIPCHK(hipStreamSynchronize(s->stream));
     }

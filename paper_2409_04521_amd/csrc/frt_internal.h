@@ -51,8 +51,9 @@ struct FrtRecs {
     void* rstop;       // distance at which this step's travel budget ends, cells
     void* w0;          // photons scale: N0_nu = w0 * spec[src][nu] (times R_ref)
     void* dir;         // [3][cap] unit direction (rotated pixel centre)
-    void* tau;         // [n_bins][cap] optical depth travelled, per bin
-    void* comp;        // [n_bins][cap] Kahan compensation of tau
+    void* tau;         // [4][cap] optical depth travelled: HI part at sigma_0 (A),
+                       // sub-grid part (K), and their Kahan compensations;
+                       // bin nu has tau_nu = (sigma_nu / sigma_0) A + K
     uint32_t cap;
 };
 

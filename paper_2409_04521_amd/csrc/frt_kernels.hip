@@ -265,8 +265,10 @@ struct Pkt {
     Real d[3];
 };
 
-template <typename Real, int NB>
-__device__ __forceinline__ void load_pkt(const FrtRecs& q, uint32_t i, Pkt<Real>& h, Real* tau, Real* comp)
+// T[0] = A (HI optical depth at sigma_0), T[1] = K (sub-grid optical depth),
+// T[2], T[3] their Kahan compensations.
+template <typename Real>
+__device__ __forceinline__ void load_pkt(const FrtRecs& q, uint32_t i, Pkt<Real>& h, Real* T)
 {
     h.src = q.src[i];
     h.estep = q.estep[i];
@@ -278,15 +280,11 @@ __device__ __forceinline__ void load_pkt(const FrtRecs& q, uint32_t i, Pkt<Real>
 #pragma unroll
     for (int a = 0; a < 3; a++) h.d[a] = ((const Real*)q.dir)[(size_t)a * q.cap + i];
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
-        tau[b] = ((const Real*)q.tau)[(size_t)b * q.cap + i];
-        comp[b] = ((const Real*)q.comp)[(size_t)b * q.cap + i];
-    }
+    for (int b = 0; b < 4; b++) T[b] = ((const Real*)q.tau)[(size_t)b * q.cap + i];
 }
 
-template <typename Real, int NB>
-__device__ __forceinline__ void store_pkt(const FrtRecs& q, uint32_t i, const Pkt<Real>& h, uint32_t key,
-                                          const Real* tau, const Real* comp)
+template <typename Real>
+__device__ __forceinline__ void store_pkt(const FrtRecs& q, uint32_t i, const Pkt<Real>& h, uint32_t key, const Real* T)
 {
     q.src[i] = h.src;
     q.estep[i] = h.estep;
@@ -299,10 +297,7 @@ __device__ __forceinline__ void store_pkt(const FrtRecs& q, uint32_t i, const Pk
 #pragma unroll
     for (int a = 0; a < 3; a++) ((Real*)q.dir)[(size_t)a * q.cap + i] = h.d[a];
 #pragma unroll
-    for (int b = 0; b < NB; b++) {
-        ((Real*)q.tau)[(size_t)b * q.cap + i] = tau[b];
-        ((Real*)q.comp)[(size_t)b * q.cap + i] = comp[b];
-    }
+    for (int b = 0; b < 4; b++) ((Real*)q.tau)[(size_t)b * q.cap + i] = T[b];
 }
 
 template <typename Real>
@@ -415,7 +410,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
         }
         FrtSolveDesc& D = descs[si];
         Pkt<Real> h;
-        Real tau[NB], comp[NB];
+        Real T[4] = {Real(0), Real(0), Real(0), Real(0)};
         uint32_t key = 0, want = 0;
         if (active) {
             const uint32_t local = g - spre[si];
@@ -447,8 +442,6 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
                 double photons = 0.0;
 #pragma unroll
                 for (int b = 0; b < NB; b++) {
-                    tau[b] = Real(0);
-                    comp[b] = Real(0);
                     if constexpr (sizeof(Real) == 8) photons += h.w0 * D.specd[(size_t)src * NB + b];
                     else photons += (double)(h.w0 * D.spec[(size_t)src * NB + b]);
                 }
@@ -477,7 +470,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
                 }
             } else {
                 const uint32_t i = local - n_emit;
-                load_pkt<Real, NB>(D.F[D.cur], i, h, tau, comp);
+                load_pkt<Real>(D.F[D.cur], i, h, T);
                 key = D.key_base + D.F[D.cur].key[i];   // carried keys are solve-local
                 want = 1;
             }
@@ -485,7 +478,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
         uint32_t at = wave_reserve(&ws.ctr[C_NO], want);
         if (want) {
             if (at < ws.O.cap) {
-                store_pkt<Real, NB>(ws.O, at, h, key, tau, comp);
+                store_pkt<Real>(ws.O, at, h, key, T);
                 atomicAdd(&ws.hist[key], 1u);
             } else {
                 raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
@@ -605,9 +598,9 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
             const uint32_t pos = s_base[slot] + rank;
             if (pos < ws.P.cap) {
                 Pkt<Real> h;
-                Real tau[NB], comp[NB];
-                load_pkt<Real, NB>(ws.O, i, h, tau, comp);
-                store_pkt<Real, NB>(ws.P, pos, h, key, tau, comp);
+                Real T[4];
+                load_pkt<Real>(ws.O, i, h, T);
+                store_pkt<Real>(ws.P, pos, h, key, T);
             }
         }
         __syncthreads();
@@ -712,13 +705,13 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
             const uint32_t j = jj + threadIdx.x;
             const bool active = j < w.count && (w.start + j) < np;
             Pkt<Real> h;
-            Real tau[NB], comp[NB], E[NB], N0[NB], s[3];
+            Real T[4], E[NB], N0[NB], s[3];
             int level = 0, end = -1;     // -1 inactive, 0 split, 1 escaped, 2 dropped, 3 in flight, 4 next brick
             int c[3] = {0, 0, 0};
             double v_abs = 0.0, v_sub = 0.0, v_end = 0.0;
             unsigned long long v_cross = 0;
             if (active) {
-                load_pkt<Real, NB>(ws.P, w.start + j, h, tau, comp);
+                load_pkt<Real>(ws.P, w.start + j, h, T);
                 level = (int)(h.lp >> 28);
                 const double* sp = D.src_pos + (size_t)h.src * 3;
                 s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
@@ -732,7 +725,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                     if constexpr (F32) spec = D.spec[(size_t)h.src * NB + b];
                     else spec = D.specd[(size_t)h.src * NB + b];
                     N0[b] = h.w0 * spec;
-                    E[b] = exp_neg(tau[b]);
+                    E[b] = exp_neg(srel_of<Real>(D, b) * T[0] + T[1]);
                     sum0 += N0[b];
                     n_start += (double)(N0[b] * E[b]);
                 }
@@ -762,24 +755,38 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                     if (ds > Real(0)) {
                         const int li = (c[0] - ox) + B * ((c[1] - oy) + B * (c[2] - oz));
                         const R2 o = s_op[li];
+                        const Real ta = o.x * ds, tk = o.y * ds;
                         Real dep = 0;
 #pragma unroll
                         for (int b = 0; b < NB; b++) {
-                            const Real tb = (srel_of<Real>(D, b) * o.x + o.y) * ds;
+                            const Real tb = srel_of<Real>(D, b) * ta + tk;
                             const Real nin = N0[b] * E[b];
-                            const Real af = absorbed_fraction(tb);
-                            const Real phi = (tb > Real(0)) ? af * fast_rcp(tb) : Real(1);
+                            const Real eb = exp_neg(tb);
+                            // absorbed fraction 1 - e^-t, by its series when t is small
+                            Real af;
+                            if constexpr (F32)
+                                af = (tb < Real(0.03)) ? tb * (Real(1) - tb * (Real(0.5) - tb * (Real(1.0 / 6.0) - tb * Real(1.0 / 24.0))))
+                                                       : Real(1) - eb;
+                            else
+                                af = -expm1(-tb);
+                            const Real rt = fast_rcp(tb);
+                            const Real phi = (tb > Real(0)) ? af * rt : Real(1);
                             dep += K_of<Real>(D, b) * nin * ds * phi;
-                            if (o.y > Real(0) && tb > Real(0)) sub_acc += nin * af * (o.y * ds) * fast_rcp(tb);
-                            if constexpr (F32) {
-                                const Real y = tb - comp[b];
-                                const Real t = tau[b] + y;
-                                comp[b] = (t - tau[b]) - y;
-                                tau[b] = t;
-                            } else {
-                                tau[b] += tb;
-                            }
-                            E[b] = exp_neg(tau[b]);
+                            if (tk > Real(0)) sub_acc += nin * af * tk * rt;
+                            E[b] *= eb;
+                        }
+                        // Kahan-compensated optical depth carried by the packet
+                        {
+                            const Real y = ta - T[2];
+                            const Real t = T[0] + y;
+                            T[2] = (t - T[0]) - y;
+                            T[0] = t;
+                        }
+                        if (tk > Real(0)) {
+                            const Real y = tk - T[3];
+                            const Real t = T[1] + y;
+                            T[3] = (t - T[1]) - y;
+                            T[1] = t;
                         }
                         atomicAdd(&s_g[li], dep);
                         v_cross++;
@@ -818,9 +825,14 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                     }
                     if (h.r >= h.rstop) { end = 3; break; }
                 }
+                // photons at the end of the visit from the carried optical
+                // depth, exactly as the next visit will recompute them
                 double n_end = 0.0;
 #pragma unroll
-                for (int b = 0; b < NB; b++) n_end += (double)(N0[b] * E[b]);
+                for (int b = 0; b < NB; b++) {
+                    E[b] = exp_neg(srel_of<Real>(D, b) * T[0] + T[1]);
+                    n_end += (double)(N0[b] * E[b]);
+                }
                 v_sub = (double)sub_acc * Rr;
                 v_abs = (n_start - n_end) * Rr - v_sub;
                 v_end = n_end * Rr;
@@ -876,7 +888,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                 if (end == 4) {
                     const uint32_t key = brick_key(D, c);
                     if (at < ws.O.cap) {
-                        store_pkt<Real, NB>(ws.O, at, h, key, tau, comp);
+                        store_pkt<Real>(ws.O, at, h, key, T);
                         count_key(s_key, s_cnt, ws.hist, key);
                     } else {
                         lost = 4;
@@ -894,7 +906,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                             ch.d[0] = cd[k][0];
                             ch.d[1] = cd[k][1];
                             ch.d[2] = cd[k][2];
-                            store_pkt<Real, NB>(ws.O, o, ch, ckey[k], tau, comp);
+                            store_pkt<Real>(ws.O, o, ch, ckey[k], T);
                             count_key(s_key, s_cnt, ws.hist, ckey[k]);
                         } else {
                             lost += 1;
@@ -912,7 +924,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
             const uint32_t fat = wave_reserve(&D.fcount[nxt], end == 3 ? 1u : 0u);
             if (end == 3) {
                 if (fat < D.F[nxt].cap) {
-                    store_pkt<Real, NB>(D.F[nxt], fat, h, brick_key(D, c) - D.key_base, tau, comp);
+                    store_pkt<Real>(D.F[nxt], fat, h, brick_key(D, c) - D.key_base, T);
                 } else {
                     raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
                     atomicAdd(&s_lf[LF_LOST], v_end);
