@@ -126,7 +126,10 @@ int copy_recs(FrtRecs& dst, const FrtRecs& src, uint32_t n, int nb, size_t rs, h
 // (one step at a time: the mutex serializes launches that use it).
 struct Workspace {
     int fp64 = -1, nb = 0;
-    FrtRecs O{}, P{};
+    FrtRecs O{}, P{}, S{};
+    double* s_phot = nullptr;
+    uint32_t* segc = nullptr;
+    uint32_t* segp = nullptr;
     uint32_t* ctr = nullptr;
     uint32_t* hist = nullptr;
     uint32_t* cursor = nullptr;
@@ -143,6 +146,10 @@ struct Workspace {
     {
         free_recs(O);
         free_recs(P);
+        free_recs(S);
+        dev_free(s_phot);
+        dev_free(segc);
+        dev_free(segp);
         dev_free(ctr); dev_free(hist); dev_free(cursor); dev_free(work); dev_free(key_prefix);
         dev_free(seed_prefix); dev_free(cell_prefix); dev_free(descs);
         nkeys_cap = 0; cap_work = 0; solves_cap = 0; fp64 = -1; nb = 0;
@@ -314,6 +321,8 @@ void set_step_fields(frt_solve s, double dt)
         h.Kd[b] = kb;
         h.K[b] = (float)kb;
     }
+    h.KSd = h.R_ref * s->P.sigma_bins[0] / (s->dx * s->dx * dt);
+    h.KS = (float)h.KSd;
 }
 
 int check_inputs_finite(const float* v, size_t n, const char* what)
@@ -377,6 +386,8 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
     if (ws.fp64 != fp64 || ws.nb != nb) {
         free_recs(ws.O);
         free_recs(ws.P);
+        free_recs(ws.S);
+        dev_free(ws.s_phot);
         ws.fp64 = fp64;
         ws.nb = nb;
     }
@@ -384,12 +395,21 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
     if (ws.P.cap < want_p) {
         free_recs(ws.O);
         free_recs(ws.P);
+        free_recs(ws.S);
+        dev_free(ws.s_phot);
+        // a pass writes four children per split into O, so half of O's
+        // capacity bounds the splits of a pass that does not overflow O
+        const uint32_t scap = (uint32_t)std::max<uint64_t>(want_p / 2, 1024);
         RCCHK(alloc_recs(ws.O, (uint32_t)want_p, nb, rs));
         RCCHK(alloc_recs(ws.P, (uint32_t)want_p, nb, rs));
+        RCCHK(alloc_recs(ws.S, scap, nb, rs));
+        RCCHK(dev_alloc((void**)&ws.s_phot, (size_t)scap * 8));
         dev_free(ws.work);
         ws.cap_work = 0;
     }
     if (!ws.ctr) RCCHK(dev_alloc((void**)&ws.ctr, C_NCTR * 4));
+    if (!ws.segc) RCCHK(dev_alloc((void**)&ws.segc, 2ull * FRT_QSEG * FRT_QSEG_STRIDE * 4));
+    if (!ws.segp) RCCHK(dev_alloc((void**)&ws.segp, (FRT_QSEG + 1) * 4ull));
     if (ws.nkeys_cap < nkeys) {
         dev_free(ws.hist);
         dev_free(ws.cursor);
@@ -470,6 +490,10 @@ int enqueue_group(Workspace& ws, frt_solve* ss, int n, hipStream_t st)
     FrtWS w{};
     w.O = ws.O;
     w.P = ws.P;
+    w.S = ws.S;
+    w.s_phot = ws.s_phot;
+    w.segc = ws.segc;
+    w.segp = ws.segp;
     w.ctr = ws.ctr;
     w.hist = ws.hist;
     w.cursor = ws.cursor;
@@ -480,6 +504,8 @@ int enqueue_group(Workspace& ws, frt_solve* ss, int n, hipStream_t st)
     w.seed_prefix = ws.seed_prefix;
     w.n_solves = n;
     w.n_bins = nb;
+    w.has_sub = 0;
+    for (int i = 0; i < n; i++) w.has_sub |= ss[i]->h.has_sub;
     if (ss[0]->P.queue_capacity) {
         // fixed capacities: the shared workspace is used up to the solves' limit
         uint64_t lim = 0;
@@ -487,6 +513,7 @@ int enqueue_group(Workspace& ws, frt_solve* ss, int n, hipStream_t st)
         const uint32_t c = (uint32_t)std::min<uint64_t>(lim, w.P.cap);
         w.O.cap = c;
         w.P.cap = c;
+        w.S.cap = std::min<uint32_t>(w.S.cap, std::max<uint32_t>(c / 2, 1024));
     }
     hipError_t e;
     {
@@ -499,9 +526,13 @@ int enqueue_group(Workspace& ws, frt_solve* ss, int n, hipStream_t st)
             if ((e = frt::launch_pass(ws.descs, w, fp64, 0, st)) != hipSuccess) return fail(FRT_EDEVICE, "scan: %s", hipGetErrorString(e));
             if ((e = frt::launch_pass(ws.descs, w, fp64, 1, st)) != hipSuccess) return fail(FRT_EDEVICE, "scatter: %s", hipGetErrorString(e));
         }
-        Timed t(tm, st, 1);
-        if ((e = frt::launch_pass(ws.descs, w, fp64, 2, st)) != hipSuccess) return fail(FRT_EDEVICE, "march: %s", hipGetErrorString(e));
-        if (tm) tm->n_march++;
+        {
+            Timed t(tm, st, 1);
+            if ((e = frt::launch_pass(ws.descs, w, fp64, 2, st)) != hipSuccess) return fail(FRT_EDEVICE, "march: %s", hipGetErrorString(e));
+            if (tm) tm->n_march++;
+        }
+        Timed t(tm, st, 3);
+        if ((e = frt::launch_pass(ws.descs, w, fp64, 3, st)) != hipSuccess) return fail(FRT_EDEVICE, "split: %s", hipGetErrorString(e));
     }
     {
         Timed t(tm, st, 3);
@@ -797,6 +828,9 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
     FrtSolveDesc& h = s->h;
     h.nx = nx; h.ny = ny; h.nz = nz;
+    h.has_sub = 0;
+    if (hk)
+        for (size_t i = 0; i < n && !h.has_sub; i++) h.has_sub = hk[i] > 0.f;
     h.bpx = s->bpx; h.bpy = s->bpy; h.bpz = s->bpz;
     h.dx_cm = s->dx;
     h.r_cap = s->P.max_distance_cm > 0 ? s->P.max_distance_cm / s->dx : HUGE_VAL;

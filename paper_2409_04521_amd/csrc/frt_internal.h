@@ -15,6 +15,12 @@ constexpr int FRT_BRICK_F64 = 8;
 constexpr uint32_t FRT_ITEM_RAYS = 1024;
 // Ledger accumulators are striped to keep atomics off a single address.
 constexpr int FRT_STRIPES = 64;
+// The pass output buffers (O and S) are cut into FRT_QSEG equal segments,
+// each with its own fill counter (FRT_QSEG_STRIDE words apart, one cache
+// line each); workgroup b appends to segment b % FRT_QSEG, so appends from
+// different workgroups seldom meet on one counter.
+constexpr int FRT_QSEG = 64;
+constexpr int FRT_QSEG_STRIDE = 32;
 
 // Error bits raised on the device and surfaced by the next sync.
 enum : uint32_t {
@@ -63,6 +69,7 @@ struct FrtRecs {
 struct FrtSolveDesc {
     int nx, ny, nz, n_bins;
     int base_level, max_level, n_src, fp64;
+    int has_sub;                // some cell has kappa > 0
     int bpx, bpy, bpz, brick;   // bricks per axis and brick edge
     uint32_t key_base;          // first global brick key of this solve in the launch
     uint32_t ncast;             // 12 * 4^L0
@@ -78,6 +85,8 @@ struct FrtSolveDesc {
     double budget;              // packet travel per step in cells (+inf = unbounded)
     float K[FRT_MAX_BINS_I];    // deposit constants R_ref sigma_nu / (dx^2 dt)
     double Kd[FRT_MAX_BINS_I];
+    float KS;                   // K_nu / (sigma_nu / sigma_0), the same for every bin
+    double KSd;
     double dt;
     double w0_cast;             // dt / (12 * 4^L0), seconds per cast packet
     // buffers
@@ -104,12 +113,16 @@ struct FrtWork {
     uint32_t key, start, count, solve;
 };
 
-enum { C_NO = 0, C_NOS, C_NP, C_NWORK, C_ERR, C_MAXP, C_NCTR = 8 };
+enum { C_NOS = 0, C_NP, C_NWORK, C_ERR, C_MAXP, C_NCTR = 8 };
 
 // Per-launch workspace: unsorted pass outputs O, packets sorted by brick P,
-// per-key histogram and scatter cursors, the work list, counters.
+// packets that reached their split radius S (with their photons), per-key
+// histogram and scatter cursors, the work list, counters.
 struct FrtWS {
-    FrtRecs O, P;
+    FrtRecs O, P, S;
+    double* s_phot;
+    uint32_t* segc;             // [2][FRT_QSEG][FRT_QSEG_STRIDE] fill counters of O, then of S
+    uint32_t* segp;             // [FRT_QSEG + 1] first O entry of each segment in pass order
     uint32_t* ctr;              // [C_NCTR]
     uint32_t* hist;             // [nkeys]
     uint32_t* cursor;           // [nkeys]
@@ -120,11 +133,13 @@ struct FrtWS {
     uint32_t* seed_prefix;      // [n_solves + 1] seeding items per solve
     int n_solves;
     int n_bins;
+    int has_sub;                // some solve of the launch has sub-grid opacity
 };
 
 namespace frt {
 hipError_t launch_seed(FrtSolveDesc* d, const FrtWS& ws, int fp64, hipStream_t s);
-// part 0: counting scan, 1: scatter into brick order, 2: brick march
+// part 0: counting scan, 1: scatter into brick order, 2: brick march,
+// 3: children of the packets that split
 hipError_t launch_pass(FrtSolveDesc* d, const FrtWS& ws, int fp64, int part, hipStream_t s);
 hipError_t launch_finish(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
 hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,

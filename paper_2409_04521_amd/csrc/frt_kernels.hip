@@ -180,9 +180,27 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t* ctr, uint32_t n_lane)
     return base + off;
 }
 
+// Fill counters and sizes of the output segments (see FRT_QSEG).
+__device__ __forceinline__ uint32_t* o_ctr(const FrtWS& ws, int k) { return ws.segc + k * FRT_QSEG_STRIDE; }
+__device__ __forceinline__ uint32_t* s_ctr(const FrtWS& ws, int k) { return ws.segc + (FRT_QSEG + k) * FRT_QSEG_STRIDE; }
+__device__ __forceinline__ uint32_t seg_cap(uint32_t cap) { return cap / FRT_QSEG; }
+__device__ __forceinline__ int my_seg() { return (int)(blockIdx.x % FRT_QSEG); }
+
 template <typename Real> __device__ __forceinline__ Real rinf();
 template <> __device__ __forceinline__ float rinf<float>() { return __builtin_huge_valf(); }
 template <> __device__ __forceinline__ double rinf<double>() { return __builtin_huge_val(); }
+
+// A wave-uniform value moved into a scalar register, so that it is read once
+// per work item instead of from memory inside divergent loops.
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+__device__ __forceinline__ int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ double uni(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const uint32_t lo = uni((uint32_t)b), hi = uni((uint32_t)(b >> 32));
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 template <typename Real> struct Vec2;
 template <> struct Vec2<float> { using T = float2; };
@@ -376,7 +394,7 @@ __global__ void k_seed_plan(FrtSolveDesc* descs, FrtWS ws)
         D.L->step_crossings = 0;
     }
     ws.seed_prefix[ws.n_solves] = acc;
-    ws.ctr[C_NO] = 0;
+    for (int k = 0; k < 2 * FRT_QSEG; k++) ws.segc[k * FRT_QSEG_STRIDE] = 0;
 }
 
 // One lane per item: a cast packet gets r = 0 and Ndot_nu dt / (12 4^L0)
@@ -475,10 +493,10 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
                 want = 1;
             }
         }
-        uint32_t at = wave_reserve(&ws.ctr[C_NO], want);
+        const uint32_t at = wave_reserve(o_ctr(ws, my_seg()), want);
         if (want) {
-            if (at < ws.O.cap) {
-                store_pkt<Real>(ws.O, at, h, key, T);
+            if (at < seg_cap(ws.O.cap)) {
+                store_pkt<Real>(ws.O, (uint32_t)my_seg() * seg_cap(ws.O.cap) + at, h, key, T);
                 atomicAdd(&ws.hist[key], 1u);
             } else {
                 raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
@@ -519,6 +537,21 @@ __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
     uint32_t it = s_b[threadIdx.x] - items;
     const uint32_t total = s_a[blockDim.x - 1];
     const uint32_t total_items = s_b[blockDim.x - 1];
+    // the previous pass's outputs in segment order; clear the fill counters
+    if (threadIdx.x < WAVE) {
+        const uint32_t cap = seg_cap(ws.O.cap);
+        const uint32_t c = *o_ctr(ws, threadIdx.x);
+        if (c > cap) atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_QUEUE_OVERFLOW);
+        uint32_t tot;
+        const uint32_t ex = wave_excl_scan(c < cap ? c : cap, &tot);
+        ws.segp[threadIdx.x] = ex;
+        if (threadIdx.x == 0) {
+            ws.segp[FRT_QSEG] = tot;
+            ws.ctr[C_NOS] = tot;
+        }
+        *o_ctr(ws, threadIdx.x) = 0;
+        *s_ctr(ws, threadIdx.x) = 0;
+    }
     for (uint32_t k = k0; k < k1; k++) {
         uint32_t h = ws.hist[k];
         ws.cursor[k] = off;
@@ -541,9 +574,6 @@ __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        const uint32_t nO = ws.ctr[C_NO];
-        ws.ctr[C_NOS] = nO < ws.O.cap ? nO : ws.O.cap;
-        ws.ctr[C_NO] = 0;
         ws.ctr[C_NP] = total;
         ws.ctr[C_NWORK] = total_items < ws.cap_work ? total_items : ws.cap_work;
         if (total > ws.ctr[C_MAXP]) ws.ctr[C_MAXP] = total;
@@ -562,7 +592,10 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
     constexpr int SLOTS = 512;
     constexpr uint32_t EMPTY = 0xffffffffu;
     __shared__ uint32_t s_key[SLOTS], s_cnt[SLOTS], s_base[SLOTS];
+    __shared__ uint32_t s_sp[FRT_QSEG + 1];
+    for (int i = threadIdx.x; i <= FRT_QSEG; i += blockDim.x) s_sp[i] = ws.segp[i];
     const uint32_t n = ws.ctr[C_NOS];
+    const uint32_t scap = seg_cap(ws.O.cap);
     const uint32_t stride = gridDim.x * blockDim.x;
     for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
         for (int i = threadIdx.x; i < SLOTS; i += blockDim.x) {
@@ -570,8 +603,13 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
             s_cnt[i] = 0;
         }
         __syncthreads();
-        const uint32_t i = base + threadIdx.x;
-        const bool active = i < n;
+        const uint32_t v = base + threadIdx.x;
+        const bool active = v < n;
+        uint32_t i = 0;
+        if (active) {
+            const int sg = find_in_prefix(s_sp, FRT_QSEG, v);
+            i = (uint32_t)sg * scap + (v - s_sp[sg]);
+        }
         uint32_t key = 0, slot = 0, rank = 0;
         bool valid = active;
         if (active) {
@@ -632,7 +670,7 @@ constexpr int KEY_SLOTS = 128;
 __device__ __forceinline__ void count_key(uint32_t* s_key, uint32_t* s_cnt, uint32_t* hist, uint32_t key)
 {
     uint32_t slot = (key * 2654435761u) & (KEY_SLOTS - 1);
-    for (int probe = 0; probe < KEY_SLOTS; probe++) {
+    for (int probe = 0; probe < 16; probe++) {
         const uint32_t prev = atomicCAS(&s_key[slot], 0xffffffffu, key);
         if (prev == 0xffffffffu || prev == key) {
             atomicAdd(&s_cnt[slot], 1u);
@@ -640,21 +678,95 @@ __device__ __forceinline__ void count_key(uint32_t* s_key, uint32_t* s_cnt, uint
         }
         slot = (slot + 1) & (KEY_SLOTS - 1);
     }
-    atomicAdd(&hist[key], 1u);   // table full: count directly
+    atomicAdd(&hist[key], 1u);   // table crowded: count directly
 }
 
-template <typename Real, int NB>
+// Lane-ordered prefix of a wave ballot: the number of set bits below the
+// calling lane.
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long m)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// wave_reserve for n_lane < 8, with three ballots in place of a shuffle scan.
+__device__ __forceinline__ uint32_t wave_reserve_small(uint32_t* ctr, uint32_t n_lane)
+{
+    const unsigned long long m0 = __ballot(n_lane & 1u), m1 = __ballot(n_lane & 2u), m2 = __ballot(n_lane & 4u);
+    const uint32_t total = (uint32_t)__popcll(m0) + 2u * (uint32_t)__popcll(m1) + 4u * (uint32_t)__popcll(m2);
+    if (total == 0) return 0;
+    uint32_t base = 0;
+    if ((threadIdx.x & (WAVE - 1)) == 0) base = atomicAdd(ctr, total);
+    base = __shfl(base, 0, WAVE);
+    return base + lanes_below(m0) + 2u * lanes_below(m1) + 4u * lanes_below(m2);
+}
+
+// Crossings a packet is expected to make in the brick [o, o + B) this visit
+// (distance to the first of brick exit, split radius, distance cap and
+// travel budget, times |d|_1), used only to order the packets of a work
+// item so that the lanes of a wave march similar lengths.  0 for a packet
+// whose cell lies outside the brick.
+template <typename Real, int B>
+__device__ __forceinline__ uint32_t visit_estimate(const FrtSolveDesc& D, const FrtRecs& q, uint32_t i, int ox, int oy, int oz)
+{
+    const uint32_t cl = q.cell[i], lp = q.lp[i], estep = q.estep[i];
+    const double* sp = D.src_pos + (size_t)q.src[i] * 3;
+    Real r = ((const Real*)q.r)[i], rstop = ((const Real*)q.rstop)[i];
+    Real d[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) d[a] = ((const Real*)q.dir)[(size_t)a * q.cap + i];
+    const int level = (int)(lp >> 28);
+    if (estep != D.step && rstop <= r) rstop = r + (Real)D.budget;
+    if (estep == D.step && r == Real(0) && level == D.base_level) rstop = (Real)D.budget;
+    const int c0 = (int)(cl % (uint32_t)D.nx), c1 = (int)((cl / (uint32_t)D.nx) % (uint32_t)D.ny),
+              c2 = (int)(cl / ((uint32_t)D.nx * (uint32_t)D.ny));
+    if (c0 < ox || c0 >= ox + B || c1 < oy || c1 >= oy + B || c2 < oz || c2 >= oz + B) return 0;
+    const Real r_split = (level < D.max_level) ? (Real)(D.r_split0 * (double)(1u << level)) : rinf<Real>();
+    Real lim = fmin(fmin(r_split, (Real)D.r_cap), rstop);
+    const int lo[3] = {ox, oy, oz};
+    const int hi[3] = {min(ox + B, D.nx), min(oy + B, D.ny), min(oz + B, D.nz)};
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        if (d[a] > Real(0)) lim = fmin(lim, ((Real)hi[a] - (Real)sp[a]) / d[a]);
+        else if (d[a] < Real(0)) lim = fmin(lim, ((Real)lo[a] - (Real)sp[a]) / d[a]);
+    }
+    const Real len = fmax(lim - r, Real(0)) * (fabs(d[0]) + fabs(d[1]) + fabs(d[2]));
+    return (uint32_t)fmin(len, Real(61)) + 1u;
+}
+
+// One workgroup per work item (one brick, up to FRT_ITEM_RAYS packets).
+// The item's packets are first ordered by their expected crossings (a
+// counting sort in LDS), then each lane walks one packet cell by cell.
+// Per segment of length ds (cells) in cell i and bin nu:
+//   tau    = (s_nu a_i + b_i) ds,  a_i = n_HI sigma_0 dx, b_i = kappa dx
+//   N_in   = N0 exp(-tau_sum)      (tau_sum carried with Kahan compensation)
+//   Gamma_i += K_nu N_in ds phi(tau),  phi = (1 - e^-tau)/tau,
+//   K_nu = R_ref sigma_nu / (dx^2 dt)
+// which is Eq. gamma_avg_subgrid with lambda = 1/(n_HI sigma + kappa)
+// (Eq. gamma_initial_standard when kappa = 0).  Without sub-grid opacity
+// (SUB = false) K_nu ds phi = (K_nu / s_nu) (1 - e^-tau) / a_i, and
+// K_nu / s_nu is the same for every bin, so the deposit is one constant
+// times the absorbed photons over a_i.  End states in order: distance cap,
+// flux floor, split radius (Eq. r_split), leaving the box, travel budget;
+// leaving the brick hands the packet to the next pass.  Ledger terms are
+// reduced per wave and added into LDS; output keys are counted in an LDS
+// table and added to the histogram once per work item.
+template <typename Real, int NB, bool SUB>
 __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
 {
     using R2 = typename Vec2<Real>::T;
     constexpr bool F32 = sizeof(Real) == 4;
     constexpr int B = F32 ? FRT_BRICK_F32 : FRT_BRICK_F64;
     constexpr int BC = B * B * B;
+    constexpr int PER = FRT_ITEM_RAYS / BLOCK;
+    constexpr int NBIN = 64;
     __shared__ R2 s_op[BC];
     __shared__ Real s_g[BC];
     __shared__ double s_lf[LF_NF];
     __shared__ unsigned long long s_lc[LC_NC];
     __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
+    __shared__ uint32_t s_bin[NBIN];
+    __shared__ uint16_t s_order[FRT_ITEM_RAYS];
+    __shared__ uint32_t s_nv;
     const uint32_t nwork = ws.ctr[C_NWORK];
     const uint32_t np = ws.ctr[C_NP] < ws.P.cap ? ws.ctr[C_NP] : ws.P.cap;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -663,7 +775,11 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
     if (threadIdx.x < KEY_SLOTS) { s_key[threadIdx.x] = 0xffffffffu; s_cnt[threadIdx.x] = 0; }
     int cs = -1;
     for (uint32_t item = blockIdx.x; item < nwork; item += gridDim.x) {
-        const FrtWork w = ws.work[item];
+        FrtWork w = ws.work[item];
+        w.key = uni(w.key);
+        w.start = uni(w.start);
+        w.count = uni(w.count);
+        w.solve = uni(w.solve);
         __syncthreads();
         if ((int)w.solve != cs) {
             if (cs >= 0 && threadIdx.x < LF_NF + LC_NC) {
@@ -681,11 +797,19 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
             cs = (int)w.solve;
         }
         const FrtSolveDesc& D = descs[w.solve];
-        const uint32_t lb = w.key - D.key_base;
+        // per-solve constants of the march, held in scalar registers
+        Real srel[NB], Kb[NB];
+#pragma unroll
+        for (int b = 0; b < NB; b++) {
+            srel[b] = uni(srel_of<Real>(D, b));
+            Kb[b] = uni(K_of<Real>(D, b));
+        }
+        const Real KS = uni(F32 ? (Real)D.KS : (Real)D.KSd);
+        const uint32_t lb = w.key - uni(D.key_base);
         const int bx = (int)(lb % (uint32_t)D.bpx), by = (int)((lb / (uint32_t)D.bpx) % (uint32_t)D.bpy),
                   bz = (int)(lb / ((uint32_t)D.bpx * (uint32_t)D.bpy));
         const int ox = bx * B, oy = by * B, oz = bz * B;
-        const int nx = D.nx, ny = D.ny, nz = D.nz;
+        const int nx = uni(D.nx), ny = uni(D.ny), nz = uni(D.nz);
         const R2* __restrict__ op = (const R2*)D.op;
         for (int t = threadIdx.x; t < BC; t += BLOCK) {
             const int lx = t % B, ly = (t / B) % B, lz = t / (B * B);
@@ -697,26 +821,57 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
             s_op[t] = v;
             s_g[t] = Real(0);
         }
+        if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
         __syncthreads();
-        const Real r_cap = (Real)D.r_cap;
-        const Real floor_f = (Real)D.floor;
-        const double Rr = D.R_ref;
+        // ---- order the item's packets by expected crossings
+        uint32_t slot_of[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const uint32_t j = (uint32_t)q * BLOCK + threadIdx.x;
+            slot_of[q] = 0xffffffffu;
+            if (j < w.count && w.start + j < np) {
+                const uint32_t e = visit_estimate<Real, B>(D, ws.P, w.start + j, ox, oy, oz);
+                slot_of[q] = (e << 16) | atomicAdd(&s_bin[e], 1u);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x < WAVE) {
+            uint32_t tot;
+            const uint32_t v = s_bin[threadIdx.x];
+            s_bin[threadIdx.x] = wave_excl_scan(v, &tot);
+            if (threadIdx.x == 0) s_nv = tot;
+        }
+        __syncthreads();
+        const uint32_t n_valid = s_nv;
+#pragma unroll
+        for (int q = 0; q < PER; q++)
+            if (slot_of[q] != 0xffffffffu)
+                s_order[s_bin[slot_of[q] >> 16] + (slot_of[q] & 0xffffu)] = (uint16_t)((uint32_t)q * BLOCK + threadIdx.x);
+        __syncthreads();
+        const Real r_cap = uni((Real)D.r_cap);
+        const Real floor_f = uni((Real)D.floor);
+        const double Rr = uni(D.R_ref);
+        const int max_level = uni(D.max_level), base_level = uni(D.base_level);
+        const double r_split0 = uni(D.r_split0);
+        const Real budget = uni((Real)D.budget);
+        const uint32_t step = uni(D.step);
         for (uint32_t jj = 0; jj < w.count; jj += BLOCK) {
-            const uint32_t j = jj + threadIdx.x;
-            const bool active = j < w.count && (w.start + j) < np;
+            const uint32_t p = jj + threadIdx.x;
+            const bool active = p < n_valid;
+            const uint32_t j = active ? (uint32_t)s_order[p] : 0u;
             Pkt<Real> h;
             Real T[4], E[NB], N0[NB], s[3];
             int level = 0, end = -1;     // -1 inactive, 0 split, 1 escaped, 2 dropped, 3 in flight, 4 next brick
             int c[3] = {0, 0, 0};
             double v_abs = 0.0, v_sub = 0.0, v_end = 0.0;
-            unsigned long long v_cross = 0;
+            uint32_t v_cross = 0;
             if (active) {
                 load_pkt<Real>(ws.P, w.start + j, h, T);
                 level = (int)(h.lp >> 28);
                 const double* sp = D.src_pos + (size_t)h.src * 3;
                 s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
-                if (h.estep != D.step && h.rstop <= h.r) h.rstop = h.r + (Real)D.budget;   // carried: fresh budget
-                if (h.estep == D.step && h.r == Real(0) && level == D.base_level) h.rstop = (Real)D.budget;
+                if (h.estep != step && h.rstop <= h.r) h.rstop = h.r + budget;   // carried: fresh budget
+                if (h.estep == step && h.r == Real(0) && level == base_level) h.rstop = budget;
                 Real sum0 = 0;
                 double n_start = 0.0;
 #pragma unroll
@@ -725,7 +880,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                     if constexpr (F32) spec = D.spec[(size_t)h.src * NB + b];
                     else spec = D.specd[(size_t)h.src * NB + b];
                     N0[b] = h.w0 * spec;
-                    E[b] = exp_neg(srel_of<Real>(D, b) * T[0] + T[1]);
+                    E[b] = SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0]);
                     sum0 += N0[b];
                     n_start += (double)(N0[b] * E[b]);
                 }
@@ -733,7 +888,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                 c[0] = (int)(cl % (uint32_t)nx);
                 c[1] = (int)((cl / (uint32_t)nx) % (uint32_t)ny);
                 c[2] = (int)(cl / ((uint32_t)nx * (uint32_t)ny));
-                const Real r_split = (level < D.max_level) ? (Real)(D.r_split0 * (double)(1u << level)) : rinf<Real>();
+                const Real r_split = (level < max_level) ? (Real)(r_split0 * (double)(1u << level)) : rinf<Real>();
                 Real inv[3], rf[3];
 #pragma unroll
                 for (int a = 0; a < 3; a++) {
@@ -755,25 +910,59 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                     if (ds > Real(0)) {
                         const int li = (c[0] - ox) + B * ((c[1] - oy) + B * (c[2] - oz));
                         const R2 o = s_op[li];
-                        const Real ta = o.x * ds, tk = o.y * ds;
+                        const Real ta = o.x * ds;
                         Real dep = 0;
+                        if constexpr (SUB) {
+                            const Real tk = o.y * ds;
 #pragma unroll
-                        for (int b = 0; b < NB; b++) {
-                            const Real tb = srel_of<Real>(D, b) * ta + tk;
-                            const Real nin = N0[b] * E[b];
-                            const Real eb = exp_neg(tb);
-                            // absorbed fraction 1 - e^-t, by its series when t is small
-                            Real af;
-                            if constexpr (F32)
-                                af = (tb < Real(0.03)) ? tb * (Real(1) - tb * (Real(0.5) - tb * (Real(1.0 / 6.0) - tb * Real(1.0 / 24.0))))
-                                                       : Real(1) - eb;
-                            else
-                                af = -expm1(-tb);
-                            const Real rt = fast_rcp(tb);
-                            const Real phi = (tb > Real(0)) ? af * rt : Real(1);
-                            dep += K_of<Real>(D, b) * nin * ds * phi;
-                            if (tk > Real(0)) sub_acc += nin * af * tk * rt;
-                            E[b] *= eb;
+                            for (int b = 0; b < NB; b++) {
+                                const Real tb = srel[b] * ta + tk;
+                                const Real nin = N0[b] * E[b];
+                                const Real eb = exp_neg(tb);
+                                // absorbed fraction 1 - e^-t, by its series when t is small
+                                Real af;
+                                if constexpr (F32)
+                                    af = (tb < Real(0.03)) ? tb * (Real(1) - tb * (Real(0.5) - tb * (Real(1.0 / 6.0) - tb * Real(1.0 / 24.0))))
+                                                           : Real(1) - eb;
+                                else
+                                    af = -expm1(-tb);
+                                const Real rt = fast_rcp(tb);
+                                const Real phi = (tb > Real(0)) ? af * rt : Real(1);
+                                dep += Kb[b] * nin * ds * phi;
+                                if (tk > Real(0)) sub_acc += nin * af * tk * rt;
+                                E[b] *= eb;
+                            }
+                            if (tk > Real(0)) {
+                                const Real y = tk - T[3];
+                                const Real t = T[1] + y;
+                                T[3] = (t - T[1]) - y;
+                                T[1] = t;
+                            }
+                        } else {
+                            Real absd = 0;
+#pragma unroll
+                            for (int b = 0; b < NB; b++) {
+                                const Real tb = srel[b] * ta;
+                                const Real nin = N0[b] * E[b];
+                                const Real eb = exp_neg(tb);
+                                Real af;
+                                if constexpr (F32)
+                                    af = (tb < Real(0.03)) ? tb * (Real(1) - tb * (Real(0.5) - tb * (Real(1.0 / 6.0) - tb * Real(1.0 / 24.0))))
+                                                           : Real(1) - eb;
+                                else
+                                    af = -expm1(-tb);
+                                absd += nin * af;
+                                E[b] *= eb;
+                            }
+                            if (o.x > Real(0)) {
+                                dep = KS * absd * fast_rcp(o.x);
+                            } else {
+                                // no neutral hydrogen: nothing absorbed, optically thin rate
+                                // (E is unchanged by the segment)
+#pragma unroll
+                                for (int b = 0; b < NB; b++) dep += Kb[b] * N0[b] * E[b];
+                                dep *= ds;
+                            }
                         }
                         // Kahan-compensated optical depth carried by the packet
                         {
@@ -781,12 +970,6 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                             const Real t = T[0] + y;
                             T[2] = (t - T[0]) - y;
                             T[0] = t;
-                        }
-                        if (tk > Real(0)) {
-                            const Real y = tk - T[3];
-                            const Real t = T[1] + y;
-                            T[3] = (t - T[1]) - y;
-                            T[1] = t;
                         }
                         atomicAdd(&s_g[li], dep);
                         v_cross++;
@@ -830,104 +1013,81 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                 double n_end = 0.0;
 #pragma unroll
                 for (int b = 0; b < NB; b++) {
-                    E[b] = exp_neg(srel_of<Real>(D, b) * T[0] + T[1]);
+                    E[b] = SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0]);
                     n_end += (double)(N0[b] * E[b]);
                 }
-                v_sub = (double)sub_acc * Rr;
+                if constexpr (SUB) v_sub = (double)sub_acc * Rr;
                 v_abs = (n_start - n_end) * Rr - v_sub;
                 v_end = n_end * Rr;
                 h.cell = (uint32_t)c[0] + (uint32_t)nx * ((uint32_t)c[1] + (uint32_t)ny * (uint32_t)c[2]);
             }
-            // ---- children of a split (Eq. lhpx): level + 1, pixel 4p + k,
-            // photons / 4, same rotation, re-centred on their own pixel
-            // direction at the split radius; a child outside the box escapes
-            Real cd[4][3];
-            uint32_t ccell[4] = {0, 0, 0, 0}, ckey[4] = {0, 0, 0, 0};
-            uint32_t cmask = 0;
-            if (end == 0) {
-                const uint32_t lpc = ((uint32_t)(level + 1) << 28) | (4u * (h.lp & 0x0fffffffu));
-#pragma unroll
-                for (int k = 0; k < 4; k++) {
-                    packet_dir<Real>(D, lpc + (uint32_t)k, h.estep, h.src, cd[k]);
-                    int cc[3];
-                    if (locate<Real>(D, s, h.r, cd[k], cc)) {
-                        ccell[k] = (uint32_t)cc[0] + (uint32_t)nx * ((uint32_t)cc[1] + (uint32_t)ny * (uint32_t)cc[2]);
-                        ckey[k] = brick_key(D, cc);
-                        cmask |= 1u << k;
-                    }
-                }
-            }
-            const uint32_t n_child = __builtin_popcount(cmask);
-            // ---- ledger: per-wave sums, one LDS atomic per field
+            // ---- ledger: counts from ballots, photon terms from wave sums
+            // taken only when some lane of the wave has one
             {
                 const bool esc = end == 1, drop = end == 2, fl = end == 3;
-                const double v_cesc = (end == 0) ? 0.25 * (4 - n_child) * v_end : 0.0;
-                const double fv[LF_NF] = {0.0, v_abs, v_sub, (esc ? v_end : 0.0) + v_cesc, drop ? v_end : 0.0,
-                                          fl ? v_end : 0.0, 0.0};
-                const unsigned long long cv[LC_NC] = {v_cross, active ? 1ull : 0ull, end == 0 ? 1ull : 0ull,
-                                                      (esc ? 1ull : 0ull) + (end == 0 ? (unsigned long long)(4 - n_child) : 0ull),
-                                                      drop ? 1ull : 0ull, fl ? 1ull : 0ull, 0ull};
-#pragma unroll
-                for (int i = 1; i < LF_NF - 1; i++) {
-                    const double t = wave_sum(fv[i]);
-                    if (lane == 0 && t != 0.0) atomicAdd(&s_lf[i], t);
-                }
-#pragma unroll
-                for (int i = 0; i < LC_NC - 1; i++) {
-                    const unsigned long long t = wave_sum_u64(cv[i]);
-                    if (lane == 0 && t) atomicAdd(&s_lc[i], t);
+                const unsigned long long m_act = __ballot(active), m_split = __ballot(end == 0),
+                                         m_esc = __ballot(esc), m_drop = __ballot(drop), m_fl = __ballot(fl);
+                const double t_abs = wave_sum(v_abs);
+                const uint32_t t_cross = wave_sum_u32(v_cross);
+                double t_sub = 0.0, t_esc = 0.0, t_drop = 0.0, t_fl = 0.0;
+                if constexpr (SUB) t_sub = wave_sum(v_sub);
+                if (m_esc) t_esc = wave_sum(esc ? v_end : 0.0);
+                if (m_drop) t_drop = wave_sum(drop ? v_end : 0.0);
+                if (m_fl) t_fl = wave_sum(fl ? v_end : 0.0);
+                if (lane == 0) {
+                    if (t_abs != 0.0) atomicAdd(&s_lf[LF_ABS_HI], t_abs);
+                    if (t_sub != 0.0) atomicAdd(&s_lf[LF_ABS_SUB], t_sub);
+                    if (t_esc != 0.0) atomicAdd(&s_lf[LF_ESC], t_esc);
+                    if (t_drop != 0.0) atomicAdd(&s_lf[LF_DROP], t_drop);
+                    if (t_fl != 0.0) atomicAdd(&s_lf[LF_FLIGHT], t_fl);
+                    if (t_cross) atomicAdd(&s_lc[LC_CROSS], (unsigned long long)t_cross);
+                    if (m_act) atomicAdd(&s_lc[LC_VISITS], (unsigned long long)__popcll(m_act));
+                    if (m_split) atomicAdd(&s_lc[LC_SPLITS], (unsigned long long)__popcll(m_split));
+                    if (m_esc) atomicAdd(&s_lc[LC_NESC], (unsigned long long)__popcll(m_esc));
+                    if (m_drop) atomicAdd(&s_lc[LC_NDROP], (unsigned long long)__popcll(m_drop));
+                    if (m_fl) atomicAdd(&s_lc[LC_NFLIGHT], (unsigned long long)__popcll(m_fl));
                 }
             }
-            // ---- one reservation per wave for everything going to the next pass;
-            // each record is written with its own bound check, so every slot
-            // below the capacity is filled even when a lane's range crosses it
-            const uint32_t n_o = (end == 4 ? 1u : 0u) + n_child;
-            const uint32_t at = wave_reserve(&ws.ctr[C_NO], n_o);
-            if (n_o) {
-                uint32_t lost = 0;
+            // ---- packets entering another brick go to the next pass
+            if (__ballot(end == 4)) {
+                const uint32_t at = wave_reserve_small(o_ctr(ws, my_seg()), end == 4 ? 1u : 0u);
                 if (end == 4) {
                     const uint32_t key = brick_key(D, c);
-                    if (at < ws.O.cap) {
-                        store_pkt<Real>(ws.O, at, h, key, T);
+                    if (at < seg_cap(ws.O.cap)) {
+                        store_pkt<Real>(ws.O, (uint32_t)my_seg() * seg_cap(ws.O.cap) + at, h, key, T);
                         count_key(s_key, s_cnt, ws.hist, key);
                     } else {
-                        lost = 4;
-                    }
-                } else {
-                    uint32_t o = at;
-#pragma unroll
-                    for (int k = 0; k < 4; k++) {
-                        if (!(cmask & (1u << k))) continue;
-                        if (o < ws.O.cap) {
-                            Pkt<Real> ch = h;
-                            ch.lp = (((uint32_t)(level + 1)) << 28) | (4u * (h.lp & 0x0fffffffu) + (uint32_t)k);
-                            ch.w0 = h.w0 * Real(0.25);
-                            ch.cell = ccell[k];
-                            ch.d[0] = cd[k][0];
-                            ch.d[1] = cd[k][1];
-                            ch.d[2] = cd[k][2];
-                            store_pkt<Real>(ws.O, o, ch, ckey[k], T);
-                            count_key(s_key, s_cnt, ws.hist, ckey[k]);
-                        } else {
-                            lost += 1;
-                        }
-                        o++;
+                        raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
+                        atomicAdd(&s_lf[LF_LOST], v_end);
                     }
                 }
-                if (lost) {
-                    raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
-                    atomicAdd(&s_lf[LF_LOST], 0.25 * lost * v_end);
+            }
+            // ---- packets at their split radius, with their photons, go to the
+            // split kernel, which writes the children (all lanes busy there)
+            if (__ballot(end == 0)) {
+                const uint32_t at = wave_reserve_small(s_ctr(ws, my_seg()), end == 0 ? 1u : 0u);
+                if (end == 0) {
+                    if (at < seg_cap(ws.S.cap)) {
+                        const uint32_t o = (uint32_t)my_seg() * seg_cap(ws.S.cap) + at;
+                        store_pkt<Real>(ws.S, o, h, brick_key(D, c), T);
+                        ws.s_phot[o] = v_end;
+                    } else {
+                        raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
+                        atomicAdd(&s_lf[LF_LOST], v_end);
+                    }
                 }
             }
             // ---- packets that spent their travel budget: carried to the next step
-            const int nxt = 1 - (int)D.cur;
-            const uint32_t fat = wave_reserve(&D.fcount[nxt], end == 3 ? 1u : 0u);
-            if (end == 3) {
-                if (fat < D.F[nxt].cap) {
-                    store_pkt<Real>(D.F[nxt], fat, h, brick_key(D, c) - D.key_base, T);
-                } else {
-                    raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
-                    atomicAdd(&s_lf[LF_LOST], v_end);
+            if (__ballot(end == 3)) {
+                const int nxt = 1 - (int)D.cur;
+                const uint32_t fat = wave_reserve_small(&D.fcount[nxt], end == 3 ? 1u : 0u);
+                if (end == 3) {
+                    if (fat < D.F[nxt].cap) {
+                        store_pkt<Real>(D.F[nxt], fat, h, brick_key(D, c) - D.key_base, T);
+                    } else {
+                        raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
+                        atomicAdd(&s_lf[LF_LOST], v_end);
+                    }
                 }
             }
         }
@@ -964,13 +1124,119 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
     }
 }
 
+// ================================================================ splitting
+// Children of the packets that reached their split radius this pass
+// (Eq. lhpx): level + 1, NESTED pixels 4p .. 4p + 3, a quarter of the
+// photons each, the parent's rotation, placed on their own pixel direction
+// at the split radius.  A child whose position is outside the box has
+// escaped.  One lane per parent.
+template <typename Real>
+__global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
+{
+    __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
+    __shared__ uint32_t s_sp[FRT_QSEG + 1];
+    if (threadIdx.x < KEY_SLOTS) { s_key[threadIdx.x] = 0xffffffffu; s_cnt[threadIdx.x] = 0; }
+    const uint32_t scap = seg_cap(ws.S.cap);
+    if (threadIdx.x < WAVE) {
+        const uint32_t c = *s_ctr(ws, threadIdx.x);
+        uint32_t tot;
+        s_sp[threadIdx.x] = wave_excl_scan(c < scap ? c : scap, &tot);
+        if (threadIdx.x == 0) s_sp[FRT_QSEG] = tot;
+    }
+    __syncthreads();
+    const uint32_t ns = s_sp[FRT_QSEG];
+    const uint32_t ocap = seg_cap(ws.O.cap);
+    for (uint32_t base = blockIdx.x * BLOCK; base < ns; base += gridDim.x * BLOCK) {
+        const uint32_t v = base + threadIdx.x;
+        const bool act = v < ns;
+        uint32_t i = 0;
+        if (act) {
+            const int sg = find_in_prefix(s_sp, FRT_QSEG, v);
+            i = (uint32_t)sg * scap + (v - s_sp[sg]);
+        }
+        Pkt<Real> h;
+        Real T[4], s[3], cd[4][3];
+        uint32_t ccell[4] = {0, 0, 0, 0}, ckey[4] = {0, 0, 0, 0}, cmask = 0;
+        int solve = 0;
+        double ph = 0.0;
+        if (act) {
+            load_pkt<Real>(ws.S, i, h, T);
+            ph = ws.s_phot[i];
+            solve = find_in_prefix(ws.key_prefix, ws.n_solves, ws.S.key[i]);
+            const FrtSolveDesc& D = descs[solve];
+            const double* sp = D.src_pos + (size_t)h.src * 3;
+            s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
+            const uint32_t lpc = ((h.lp >> 28) + 1u) << 28 | (4u * (h.lp & 0x0fffffffu));
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                packet_dir<Real>(D, lpc + (uint32_t)k, h.estep, h.src, cd[k]);
+                int cc[3];
+                if (locate<Real>(D, s, h.r, cd[k], cc)) {
+                    ccell[k] = (uint32_t)cc[0] + (uint32_t)D.nx * ((uint32_t)cc[1] + (uint32_t)D.ny * (uint32_t)cc[2]);
+                    ckey[k] = brick_key(D, cc);
+                    cmask |= 1u << k;
+                }
+            }
+        }
+        const uint32_t n_child = __builtin_popcount(cmask);
+        const uint32_t at = wave_reserve_small(o_ctr(ws, my_seg()), n_child);
+        uint32_t lost = 0;
+        if (n_child) {
+            uint32_t o = at;
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+                if (!(cmask & (1u << k))) continue;
+                if (o < ocap) {
+                    Pkt<Real> ch = h;
+                    ch.lp = (((h.lp >> 28) + 1u) << 28) | (4u * (h.lp & 0x0fffffffu) + (uint32_t)k);
+                    ch.w0 = h.w0 * Real(0.25);
+                    ch.cell = ccell[k];
+                    ch.d[0] = cd[k][0];
+                    ch.d[1] = cd[k][1];
+                    ch.d[2] = cd[k][2];
+                    store_pkt<Real>(ws.O, (uint32_t)my_seg() * ocap + o, ch, ckey[k], T);
+                    count_key(s_key, s_cnt, ws.hist, ckey[k]);
+                } else {
+                    lost += 1;
+                }
+                o++;
+            }
+        }
+        if (act && (n_child < 4 || lost)) {
+            FrtLedgerDev* L = descs[solve].L;
+            if (n_child < 4) {
+                ledger_direct(L, LF_ESC, 0.25 * (double)(4 - n_child) * ph);
+                ledger_direct_c(L, LC_NESC, 4ull - n_child);
+            }
+            if (lost) {
+                raise_error(ws, L, FRT_DEVERR_QUEUE_OVERFLOW);
+                ledger_direct(L, LF_LOST, 0.25 * (double)lost * ph);
+            }
+        }
+        // children of neighbouring parents share few bricks: add the block's
+        // key counts to the histogram once per round
+        __syncthreads();
+        if (threadIdx.x < KEY_SLOTS) {
+            const uint32_t k = s_key[threadIdx.x];
+            if (k != 0xffffffffu) {
+                atomicAdd(&ws.hist[k], s_cnt[threadIdx.x]);
+                s_key[threadIdx.x] = 0xffffffffu;
+                s_cnt[threadIdx.x] = 0;
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // =============================================================== step close
 // After the last pass: anything still queued means the pass count was too
 // small (flagged, never expected); fold the ledger stripes.
 __global__ void k_finish(FrtSolveDesc* descs, FrtWS ws)
 {
     __shared__ int s_left;
-    if (threadIdx.x == 0) s_left = ws.ctr[C_NO] > 0 ? 1 : 0;
+    if (threadIdx.x == 0) s_left = 0;
+    __syncthreads();
+    if (threadIdx.x < FRT_QSEG && *o_ctr(ws, threadIdx.x) > 0) s_left = 1;
     __syncthreads();
     for (int s = blockIdx.x; s < ws.n_solves; s += gridDim.x) {
         FrtSolveDesc& D = descs[s];
@@ -1099,9 +1365,12 @@ void launch_seed_nb(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
 template <typename Real, int NB>
 void launch_pass_nb(FrtSolveDesc* d, const FrtWS& ws, int part, hipStream_t s)
 {
+    const dim3 grid(cu_count() * (sizeof(Real) == 4 ? 3 : 8));
     if (part == 0) hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws);
     else if (part == 1) hipLaunchKernelGGL((k_scatter<Real, NB>), dim3(cu_count() * 8), dim3(BLOCK), 0, s, ws);
-    else hipLaunchKernelGGL((k_brick<Real, NB>), dim3(cu_count() * (sizeof(Real) == 4 ? 3 : 8)), dim3(BLOCK), 0, s, d, ws);
+    else if (part == 3) hipLaunchKernelGGL((k_split<Real>), dim3(cu_count() * 4), dim3(BLOCK), 0, s, d, ws);
+    else if (ws.has_sub) hipLaunchKernelGGL((k_brick<Real, NB, true>), grid, dim3(BLOCK), 0, s, d, ws);
+    else hipLaunchKernelGGL((k_brick<Real, NB, false>), grid, dim3(BLOCK), 0, s, d, ws);
 }
 
 template <typename Real>
