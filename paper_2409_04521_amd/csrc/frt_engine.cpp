@@ -557,16 +557,19 @@ int step_group(frt_solve* ss, int n, const double* dts)
     Workspace& ws = ctx->ws;
     hipStream_t st = ss[0]->stream;
     const bool auto_grow = ss[0]->P.queue_capacity == 0;
-    uint32_t nkeys = 0;
+    uint64_t nkeys64 = 0;
     uint64_t want_p = 0;
     for (int i = 0; i < n; i++) {
         frt_solve s = ss[i];
         RCCHK(ensure_quat(s, s->step));
         set_step_fields(s, dts[i]);
-        nkeys += (uint32_t)(s->bpx * s->bpy * s->bpz);
+        nkeys64 += (uint64_t)s->bpx * s->bpy * s->bpz;
         const uint64_t cast = (uint64_t)s->n_src * (12ull << (2 * s->P.base_level));
         want_p += s->P.queue_capacity ? s->P.queue_capacity : std::max<uint64_t>(4 * cast + 65536, s->ncell / 2);
     }
+    if (nkeys64 > FRT_KEY_MASK)
+        return fail(FRT_EINVAL, "the solves of one launch hold %llu bricks, more than %u", (unsigned long long)nkeys64, FRT_KEY_MASK);
+    const uint32_t nkeys = (uint32_t)nkeys64;
     for (int attempt = 0; attempt < 16; attempt++) {
         RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.P.cap)));
         for (int i = 0; i < n; i++) {

@@ -20,6 +20,11 @@ constexpr int FRT_STRIPES = 64;
 // line each); workgroup b appends to segment b % FRT_QSEG, so appends from
 // different workgroups seldom meet on one counter.
 constexpr int FRT_QSEG = 64;
+// Pass-output keys: brick key in the low FRT_KEY_BITS bits, the packet's
+// expected crossings in the next brick (0 .. FRT_KEY_BINS - 1) above them.
+constexpr int FRT_KEY_BITS = 26;
+constexpr uint32_t FRT_KEY_MASK = (1u << FRT_KEY_BITS) - 1u;
+constexpr int FRT_KEY_BINS = 64;
 constexpr int FRT_QSEG_STRIDE = 32;
 
 // Error bits raised on the device and surfaced by the next sync.
@@ -52,7 +57,8 @@ struct FrtRecs {
     uint32_t* estep;   // step in which the packet's root was cast (rotation lookup)
     uint32_t* lp;      // level << 28 | NESTED pixel
     uint32_t* cell;    // linear cell index x + nx (y + ny z)
-    uint32_t* key;     // global brick key (outputs and carried packets)
+    uint32_t* key;     // pass outputs: global brick key and crossing bin (FRT_KEY_BITS);
+                       // sorted packets: the crossing bin; carried packets: solve-local key
     void* r;           // distance travelled from the source, cells
     void* rstop;       // distance at which this step's travel budget ends, cells
     void* w0;          // photons scale: N0_nu = w0 * spec[src][nu] (times R_ref)

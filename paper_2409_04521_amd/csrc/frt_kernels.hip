@@ -18,6 +18,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace {
 
 constexpr int WAVE = 64;
@@ -206,16 +208,9 @@ template <typename Real> struct Vec2;
 template <> struct Vec2<float> { using T = float2; };
 template <> struct Vec2<double> { using T = double2; };
 
-// exp(-t) and the absorbed fraction 1 - exp(-t) of a segment, accurate for
-// small t (series) and using the hardware exponential otherwise.
+// exp(-t): the hardware exponential in FP32.
 __device__ __forceinline__ float exp_neg(float t) { return __expf(-t); }
 __device__ __forceinline__ double exp_neg(double t) { return exp(-t); }
-__device__ __forceinline__ float absorbed_fraction(float t)
-{
-    // t (1 - t/2 + t^2/6 - t^3/24) below 0.03 (truncation < 7e-9 relative)
-    return (t < 0.03f) ? t * (1.f - t * (0.5f - t * ((1.f / 6.f) - t * (1.f / 24.f)))) : 1.f - __expf(-t);
-}
-__device__ __forceinline__ double absorbed_fraction(double t) { return -expm1(-t); }
 
 // --------------------------------------------------------------- the ledger
 // Per-lane accumulation, block reduction, one atomic per field per flush
@@ -377,6 +372,31 @@ __device__ __forceinline__ Real K_of(const FrtSolveDesc& D, int b)
     else return (Real)D.Kd[b];
 }
 
+// Crossings a packet at s + r d in cell c is expected to make in the brick
+// holding c on its next visit: the distance to the first of brick exit,
+// split radius, distance cap and the end of its travel budget (rstop),
+// times |d|_1.  Only used to order the packets of a work item so that the
+// lanes of a wave march similar lengths; stored in the key's top bits.
+template <typename Real>
+__device__ __forceinline__ uint32_t crossing_bin(const FrtSolveDesc& D, const int c[3], const Real s[3], const Real d[3],
+                                                 Real r, Real rstop, int level)
+{
+    const int B = D.brick;
+    const int dims[3] = {D.nx, D.ny, D.nz};
+    const Real r_split = (level < D.max_level) ? (Real)(D.r_split0 * (double)(1u << level)) : rinf<Real>();
+    Real lim = fmin(fmin(r_split, (Real)D.r_cap), rstop);
+#pragma unroll
+    for (int a = 0; a < 3; a++) {
+        const int lo = (c[a] / B) * B, hi = min(lo + B, dims[a]);
+        if (d[a] > Real(0)) lim = fmin(lim, ((Real)hi - s[a]) / d[a]);
+        else if (d[a] < Real(0)) lim = fmin(lim, ((Real)lo - s[a]) / d[a]);
+    }
+    const Real len = fmax(lim - r, Real(0)) * (fabs(d[0]) + fabs(d[1]) + fabs(d[2]));
+    return (uint32_t)fmin(len, Real(FRT_KEY_BINS - 3)) + 1u;
+}
+
+__device__ __forceinline__ uint32_t key_with_bin(uint32_t key, uint32_t bin) { return key | (bin << FRT_KEY_BITS); }
+
 // ================================================================= seeding
 // Per solve: casting items (12 4^L0 per source) then the packets carried
 // from the previous step.
@@ -429,7 +449,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
         FrtSolveDesc& D = descs[si];
         Pkt<Real> h;
         Real T[4] = {Real(0), Real(0), Real(0), Real(0)};
-        uint32_t key = 0, want = 0;
+        uint32_t key = 0, want = 0, bin = 0;
         if (active) {
             const uint32_t local = g - spre[si];
             const uint32_t n_emit = (uint32_t)D.n_src * D.ncast;
@@ -478,6 +498,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
                 if (locate<Real>(D, s3, Real(0), d, c)) {
                     h.cell = (uint32_t)c[0] + (uint32_t)D.nx * ((uint32_t)c[1] + (uint32_t)D.ny * (uint32_t)c[2]);
                     key = brick_key(D, c);
+                    bin = crossing_bin<Real>(D, c, s3, h.d, Real(0), (Real)D.budget, D.base_level);
                     want = 1;
                 } else if (own) {                  // points out of the box from a boundary source
                     led.f[LF_ESC] += photons;
@@ -490,13 +511,19 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
                 const uint32_t i = local - n_emit;
                 load_pkt<Real>(D.F[D.cur], i, h, T);
                 key = D.key_base + D.F[D.cur].key[i];   // carried keys are solve-local
+                const double* sp = D.src_pos + (size_t)h.src * 3;
+                const Real s3[3] = {(Real)sp[0], (Real)sp[1], (Real)sp[2]};
+                const int c[3] = {(int)(h.cell % (uint32_t)D.nx), (int)((h.cell / (uint32_t)D.nx) % (uint32_t)D.ny),
+                                  (int)(h.cell / ((uint32_t)D.nx * (uint32_t)D.ny))};
+                const Real rs = h.rstop <= h.r ? h.r + (Real)D.budget : h.rstop;   // fresh budget this step
+                bin = crossing_bin<Real>(D, c, s3, h.d, h.r, rs, (int)(h.lp >> 28));
                 want = 1;
             }
         }
         const uint32_t at = wave_reserve(o_ctr(ws, my_seg()), want);
         if (want) {
             if (at < seg_cap(ws.O.cap)) {
-                store_pkt<Real>(ws.O, (uint32_t)my_seg() * seg_cap(ws.O.cap) + at, h, key, T);
+                store_pkt<Real>(ws.O, (uint32_t)my_seg() * seg_cap(ws.O.cap) + at, h, key_with_bin(key, bin), T);
                 atomicAdd(&ws.hist[key], 1u);
             } else {
                 raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
@@ -612,8 +639,11 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
         }
         uint32_t key = 0, slot = 0, rank = 0;
         bool valid = active;
+        uint32_t bin = 0;
         if (active) {
             key = ws.O.key[i];
+            bin = key >> FRT_KEY_BITS;
+            key &= FRT_KEY_MASK;
             if (key >= ws.nkeys) {          // never expected: flag and skip
                 atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_QUEUE_OVERFLOW);
                 valid = false;
@@ -638,7 +668,7 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
                 Pkt<Real> h;
                 Real T[4];
                 load_pkt<Real>(ws.O, i, h, T);
-                store_pkt<Real>(ws.P, pos, h, key, T);
+                store_pkt<Real>(ws.P, pos, h, bin, T);   // sorted records keep only the crossing bin
             }
         }
         __syncthreads();
@@ -646,23 +676,27 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
 }
 
 // =============================================================== brick march
-// One workgroup per work item (one brick, up to FRT_ITEM_RAYS packets).
-// Per segment of length ds (cells) in cell i and bin nu:
-//   tau    = (s_nu a_i + b_i) ds,  a_i = n_HI sigma_0 dx, b_i = kappa dx
-//   N_in   = N0 exp(-tau_sum)      (tau_sum carried with Kahan compensation)
-//   Gamma_i += K_nu N_in ds phi(tau),  phi = (1 - e^-tau)/tau,
-//   K_nu = R_ref sigma_nu / (dx^2 dt)
-// which is Eq. gamma_avg_subgrid with lambda = 1/(n_HI sigma + kappa)
-// (Eq. gamma_initial_standard when kappa = 0).  End states in order:
-// distance cap, flux floor, split radius (Eq. r_split), leaving the box,
-// travel budget; leaving the brick hands the packet to the next pass.
-// Ledger terms are reduced per wave and added into LDS; output keys are
-// counted in an LDS table and added to the histogram once per work item.
 template <typename Real>
 __device__ __forceinline__ Real fast_rcp(Real x)
 {
     if constexpr (sizeof(Real) == 4) return __builtin_amdgcn_rcpf(x);
     else return Real(1) / x;
+}
+
+// Absorbed fraction 1 - e^-t of a segment given eb = e^-t: the series
+// t (1 - t/2 + t^2/6 - t^3/24) below t = 0.03 (truncation < 7e-9
+// relative), 1 - eb above.  Both forms are evaluated and one selected,
+// which costs less than a branch per bin.
+template <typename Real>
+__device__ __forceinline__ Real absorbed(Real t, Real eb)
+{
+    if constexpr (sizeof(Real) == 4) {
+        const Real ser = t * (Real(1) - t * (Real(0.5) - t * (Real(1.0 / 6.0) - t * Real(1.0 / 24.0))));
+        const Real dif = Real(1) - eb;
+        return t < Real(0.03) ? ser : dif;
+    } else {
+        return -expm1(-t);
+    }
 }
 
 constexpr int KEY_SLOTS = 128;
@@ -700,39 +734,6 @@ __device__ __forceinline__ uint32_t wave_reserve_small(uint32_t* ctr, uint32_t n
     return base + lanes_below(m0) + 2u * lanes_below(m1) + 4u * lanes_below(m2);
 }
 
-// Crossings a packet is expected to make in the brick [o, o + B) this visit
-// (distance to the first of brick exit, split radius, distance cap and
-// travel budget, times |d|_1), used only to order the packets of a work
-// item so that the lanes of a wave march similar lengths.  0 for a packet
-// whose cell lies outside the brick.
-template <typename Real, int B>
-__device__ __forceinline__ uint32_t visit_estimate(const FrtSolveDesc& D, const FrtRecs& q, uint32_t i, int ox, int oy, int oz)
-{
-    const uint32_t cl = q.cell[i], lp = q.lp[i], estep = q.estep[i];
-    const double* sp = D.src_pos + (size_t)q.src[i] * 3;
-    Real r = ((const Real*)q.r)[i], rstop = ((const Real*)q.rstop)[i];
-    Real d[3];
-#pragma unroll
-    for (int a = 0; a < 3; a++) d[a] = ((const Real*)q.dir)[(size_t)a * q.cap + i];
-    const int level = (int)(lp >> 28);
-    if (estep != D.step && rstop <= r) rstop = r + (Real)D.budget;
-    if (estep == D.step && r == Real(0) && level == D.base_level) rstop = (Real)D.budget;
-    const int c0 = (int)(cl % (uint32_t)D.nx), c1 = (int)((cl / (uint32_t)D.nx) % (uint32_t)D.ny),
-              c2 = (int)(cl / ((uint32_t)D.nx * (uint32_t)D.ny));
-    if (c0 < ox || c0 >= ox + B || c1 < oy || c1 >= oy + B || c2 < oz || c2 >= oz + B) return 0;
-    const Real r_split = (level < D.max_level) ? (Real)(D.r_split0 * (double)(1u << level)) : rinf<Real>();
-    Real lim = fmin(fmin(r_split, (Real)D.r_cap), rstop);
-    const int lo[3] = {ox, oy, oz};
-    const int hi[3] = {min(ox + B, D.nx), min(oy + B, D.ny), min(oz + B, D.nz)};
-#pragma unroll
-    for (int a = 0; a < 3; a++) {
-        if (d[a] > Real(0)) lim = fmin(lim, ((Real)hi[a] - (Real)sp[a]) / d[a]);
-        else if (d[a] < Real(0)) lim = fmin(lim, ((Real)lo[a] - (Real)sp[a]) / d[a]);
-    }
-    const Real len = fmax(lim - r, Real(0)) * (fabs(d[0]) + fabs(d[1]) + fabs(d[2]));
-    return (uint32_t)fmin(len, Real(61)) + 1u;
-}
-
 // One workgroup per work item (one brick, up to FRT_ITEM_RAYS packets).
 // The item's packets are first ordered by their expected crossings (a
 // counting sort in LDS), then each lane walks one packet cell by cell.
@@ -751,15 +752,17 @@ __device__ __forceinline__ uint32_t visit_estimate(const FrtSolveDesc& D, const 
 // reduced per wave and added into LDS; output keys are counted in an LDS
 // table and added to the histogram once per work item.
 template <typename Real, int NB, bool SUB>
-__global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
+__device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
 {
     using R2 = typename Vec2<Real>::T;
     constexpr bool F32 = sizeof(Real) == 4;
     constexpr int B = F32 ? FRT_BRICK_F32 : FRT_BRICK_F64;
     constexpr int BC = B * B * B;
     constexpr int PER = FRT_ITEM_RAYS / BLOCK;
-    constexpr int NBIN = 64;
-    __shared__ R2 s_op[BC];
+    constexpr int NBIN = FRT_KEY_BINS;
+    // staged opacity: {a_i, b_i} with sub-grid opacity, a_i alone without
+    using OpT = typename std::conditional<SUB, R2, Real>::type;
+    __shared__ OpT s_op[BC];
     __shared__ Real s_g[BC];
     __shared__ double s_lf[LF_NF];
     __shared__ unsigned long long s_lc[LC_NC];
@@ -818,7 +821,8 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
             v.x = Real(0);
             v.y = Real(0);
             if (cx < nx && cy < ny && cz < nz) v = op[(size_t)cx + (size_t)nx * ((size_t)cy + (size_t)ny * (size_t)cz)];
-            s_op[t] = v;
+            if constexpr (SUB) s_op[t] = v;
+            else s_op[t] = v.x;
             s_g[t] = Real(0);
         }
         if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
@@ -830,7 +834,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
             const uint32_t j = (uint32_t)q * BLOCK + threadIdx.x;
             slot_of[q] = 0xffffffffu;
             if (j < w.count && w.start + j < np) {
-                const uint32_t e = visit_estimate<Real, B>(D, ws.P, w.start + j, ox, oy, oz);
+                const uint32_t e = ws.P.key[w.start + j] & (uint32_t)(NBIN - 1);
                 slot_of[q] = (e << 16) | atomicAdd(&s_bin[e], 1u);
             }
         }
@@ -909,7 +913,13 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                     const Real ds = r_end - h.r;
                     if (ds > Real(0)) {
                         const int li = (c[0] - ox) + B * ((c[1] - oy) + B * (c[2] - oz));
-                        const R2 o = s_op[li];
+                        R2 o;
+                        if constexpr (SUB) {
+                            o = s_op[li];
+                        } else {
+                            o.x = s_op[li];
+                            o.y = Real(0);
+                        }
                         const Real ta = o.x * ds;
                         Real dep = 0;
                         if constexpr (SUB) {
@@ -919,13 +929,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                                 const Real tb = srel[b] * ta + tk;
                                 const Real nin = N0[b] * E[b];
                                 const Real eb = exp_neg(tb);
-                                // absorbed fraction 1 - e^-t, by its series when t is small
-                                Real af;
-                                if constexpr (F32)
-                                    af = (tb < Real(0.03)) ? tb * (Real(1) - tb * (Real(0.5) - tb * (Real(1.0 / 6.0) - tb * Real(1.0 / 24.0))))
-                                                           : Real(1) - eb;
-                                else
-                                    af = -expm1(-tb);
+                                const Real af = absorbed<Real>(tb, eb);
                                 const Real rt = fast_rcp(tb);
                                 const Real phi = (tb > Real(0)) ? af * rt : Real(1);
                                 dep += Kb[b] * nin * ds * phi;
@@ -945,12 +949,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
                                 const Real tb = srel[b] * ta;
                                 const Real nin = N0[b] * E[b];
                                 const Real eb = exp_neg(tb);
-                                Real af;
-                                if constexpr (F32)
-                                    af = (tb < Real(0.03)) ? tb * (Real(1) - tb * (Real(0.5) - tb * (Real(1.0 / 6.0) - tb * Real(1.0 / 24.0))))
-                                                           : Real(1) - eb;
-                                else
-                                    af = -expm1(-tb);
+                                const Real af = absorbed<Real>(tb, eb);
                                 absd += nin * af;
                                 E[b] *= eb;
                             }
@@ -1052,10 +1051,10 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
             if (__ballot(end == 4)) {
                 const uint32_t at = wave_reserve_small(o_ctr(ws, my_seg()), end == 4 ? 1u : 0u);
                 if (end == 4) {
-                    const uint32_t key = brick_key(D, c);
+                    const uint32_t key = key_with_bin(brick_key(D, c), crossing_bin<Real>(D, c, s, h.d, h.r, h.rstop, level));
                     if (at < seg_cap(ws.O.cap)) {
                         store_pkt<Real>(ws.O, (uint32_t)my_seg() * seg_cap(ws.O.cap) + at, h, key, T);
-                        count_key(s_key, s_cnt, ws.hist, key);
+                        count_key(s_key, s_cnt, ws.hist, key & FRT_KEY_MASK);
                     } else {
                         raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
                         atomicAdd(&s_lf[LF_LOST], v_end);
@@ -1124,6 +1123,21 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
     }
 }
 
+template <typename Real, int NB, bool SUB>
+__global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
+{
+    brick_march<Real, NB, SUB>(descs, ws);
+}
+
+// The same kernel held to 128 registers, so that four workgroups (16
+// waves) share a CU: used where the LDS of four fits and the registers do
+// without spilling (FP32 march, no sub-grid opacity, up to 4 bins).
+template <typename Real, int NB, bool SUB>
+__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) k_brick_w4(FrtSolveDesc* descs, FrtWS ws)
+{
+    brick_march<Real, NB, SUB>(descs, ws);
+}
+
 // ================================================================ splitting
 // Children of the packets that reached their split radius this pass
 // (Eq. lhpx): level + 1, NESTED pixels 4p .. 4p + 3, a quarter of the
@@ -1173,7 +1187,7 @@ __global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
                 int cc[3];
                 if (locate<Real>(D, s, h.r, cd[k], cc)) {
                     ccell[k] = (uint32_t)cc[0] + (uint32_t)D.nx * ((uint32_t)cc[1] + (uint32_t)D.ny * (uint32_t)cc[2]);
-                    ckey[k] = brick_key(D, cc);
+                    ckey[k] = key_with_bin(brick_key(D, cc), crossing_bin<Real>(D, cc, s, cd[k], h.r, h.rstop, (int)(h.lp >> 28) + 1));
                     cmask |= 1u << k;
                 }
             }
@@ -1195,7 +1209,7 @@ __global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
                     ch.d[1] = cd[k][1];
                     ch.d[2] = cd[k][2];
                     store_pkt<Real>(ws.O, (uint32_t)my_seg() * ocap + o, ch, ckey[k], T);
-                    count_key(s_key, s_cnt, ws.hist, ckey[k]);
+                    count_key(s_key, s_cnt, ws.hist, ckey[k] & FRT_KEY_MASK);
                 } else {
                     lost += 1;
                 }
@@ -1362,15 +1376,30 @@ void launch_seed_nb(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
     hipLaunchKernelGGL((k_seed<Real, NB>), dim3(cu_count() * 4), dim3(BLOCK), 0, s, d, ws);
 }
 
+// Resident workgroups per CU of a kernel (at least 1), queried once.
+template <typename K>
+int blocks_per_cu(K kernel)
+{
+    static int n = 0;
+    if (n == 0) {
+        int b = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, BLOCK, 0) != hipSuccess || b < 1) b = 1;
+        n = b;
+    }
+    return n;
+}
+
 template <typename Real, int NB>
 void launch_pass_nb(FrtSolveDesc* d, const FrtWS& ws, int part, hipStream_t s)
 {
-    const dim3 grid(cu_count() * (sizeof(Real) == 4 ? 3 : 8));
+    void (*brick)(FrtSolveDesc*, FrtWS);
+    if constexpr (sizeof(Real) == 4 && NB <= 4) brick = ws.has_sub ? k_brick<Real, NB, true> : k_brick_w4<Real, NB, false>;
+    else brick = ws.has_sub ? k_brick<Real, NB, true> : k_brick<Real, NB, false>;
+    const dim3 grid(cu_count() * blocks_per_cu(brick));
     if (part == 0) hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws);
     else if (part == 1) hipLaunchKernelGGL((k_scatter<Real, NB>), dim3(cu_count() * 8), dim3(BLOCK), 0, s, ws);
     else if (part == 3) hipLaunchKernelGGL((k_split<Real>), dim3(cu_count() * 4), dim3(BLOCK), 0, s, d, ws);
-    else if (ws.has_sub) hipLaunchKernelGGL((k_brick<Real, NB, true>), grid, dim3(BLOCK), 0, s, d, ws);
-    else hipLaunchKernelGGL((k_brick<Real, NB, false>), grid, dim3(BLOCK), 0, s, d, ws);
+    else hipLaunchKernelGGL(brick, grid, dim3(BLOCK), 0, s, d, ws);
 }
 
 template <typename Real>
