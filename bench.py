@@ -137,7 +137,7 @@ def main():
 
     nb = prob.n_bins
     d_visits = L1["ray_visits"] - L0["ray_visits"]
-    rec = 5 * 4 + 10 * 4                                # src, estep, lp, cell, key; r, rstop, w0, dir[3], tau[4]
+    rec = 64                                            # one packet record (FrtRec<float>)
     march_bytes = 12.0 * cross + 2.0 * rec * d_visits   # record read and written once per visit
     closure = abs(L1["emitted"] - L1["absorbed_HI"] - L1["absorbed_sub"] - L1["escaped"] - L1["dropped"]
                   - L1["in_flight"] - L1["lost"]) / L1["emitted"]

@@ -74,49 +74,31 @@ void dev_free(T*& p)
     p = nullptr;
 }
 
+// Bytes of one packet record.
+size_t rec_bytes(size_t rs) { return rs == 8 ? sizeof(FrtRec<double>) : sizeof(FrtRec<float>); }
+
 void free_recs(FrtRecs& q)
 {
-    dev_free(q.src); dev_free(q.estep); dev_free(q.lp); dev_free(q.cell); dev_free(q.key);
-    dev_free(q.r); dev_free(q.rstop); dev_free(q.w0); dev_free(q.dir); dev_free(q.tau);
+    dev_free(q.rec);
     q.cap = 0;
 }
 
 int alloc_recs(FrtRecs& q, uint32_t cap, int nb, size_t rs)
 {
+    (void)nb;
     FrtRecs n{};
     n.cap = cap;
-    const size_t c = std::max<uint32_t>(cap, 1);
-    int rc;
-    if ((rc = dev_alloc((void**)&n.src, c * 4)) || (rc = dev_alloc((void**)&n.estep, c * 4)) ||
-        (rc = dev_alloc((void**)&n.lp, c * 4)) || (rc = dev_alloc((void**)&n.cell, c * 4)) ||
-        (rc = dev_alloc((void**)&n.key, c * 4)) || (rc = dev_alloc(&n.r, c * rs)) || (rc = dev_alloc(&n.rstop, c * rs)) ||
-        (rc = dev_alloc(&n.w0, c * rs)) || (rc = dev_alloc(&n.dir, c * rs * 3)) || (rc = dev_alloc(&n.tau, c * rs * 4))) {
-        free_recs(n);
-        return rc;
-    }
+    RCCHK(dev_alloc(&n.rec, (size_t)std::max<uint32_t>(cap, 1) * rec_bytes(rs)));
     q = n;
     return FRT_OK;
 }
 
-// Copy the first n records of src into dst (arrays may differ in capacity).
+// Copy the first n records of src into dst.
 int copy_recs(FrtRecs& dst, const FrtRecs& src, uint32_t n, int nb, size_t rs, hipStream_t st, hipMemcpyKind k)
 {
-    if (!n) return FRT_OK;
-    HIPCHK(hipMemcpyAsync(dst.src, src.src, n * 4ull, k, st));
-    HIPCHK(hipMemcpyAsync(dst.estep, src.estep, n * 4ull, k, st));
-    HIPCHK(hipMemcpyAsync(dst.lp, src.lp, n * 4ull, k, st));
-    HIPCHK(hipMemcpyAsync(dst.cell, src.cell, n * 4ull, k, st));
-    HIPCHK(hipMemcpyAsync(dst.key, src.key, n * 4ull, k, st));
-    HIPCHK(hipMemcpyAsync(dst.r, src.r, n * rs, k, st));
-    HIPCHK(hipMemcpyAsync(dst.rstop, src.rstop, n * rs, k, st));
-    HIPCHK(hipMemcpyAsync(dst.w0, src.w0, n * rs, k, st));
-    for (int a = 0; a < 3; a++)
-        HIPCHK(hipMemcpyAsync((char*)dst.dir + a * (size_t)dst.cap * rs, (const char*)src.dir + a * (size_t)src.cap * rs,
-                              n * rs, k, st));
-    for (int b = 0; b < 4; b++)
-        HIPCHK(hipMemcpyAsync((char*)dst.tau + b * (size_t)dst.cap * rs, (const char*)src.tau + b * (size_t)src.cap * rs,
-                              n * rs, k, st));
     (void)nb;
+    if (!n) return FRT_OK;
+    HIPCHK(hipMemcpyAsync(dst.rec, src.rec, (size_t)n * rec_bytes(rs), k, st));
     return FRT_OK;
 }
 
@@ -1043,7 +1025,7 @@ int frt_read_ledger(frt_solve s, frt_ledger* out)
 
 // Checkpoint layout: 8 u64 header (magic, version, step, n_src, ncell, nb,
 // fp64, n_carried), ledger (without stripes), x[ncell], quaternions of the
-// steps so far, then the carried packets as SoA fields.
+// steps so far, then the carried packets as FrtRec structs.
 int frt_save_state(frt_solve s, void* buf, size_t* bytes)
 {
     RCCHK(ready(s));
@@ -1054,7 +1036,7 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     const int cur = (int)(s->step & 1u);
     const uint32_t nc = std::min(fc[cur], s->F[cur].cap);
     const int nb = s->P.n_bins;
-    const size_t rec = 20 + 10 * s->rs;
+    const size_t rec = rec_bytes(s->rs);
     const size_t led = offsetof(FrtLedgerDev, sd);
     const size_t nq = (size_t)s->step * s->n_src * 4;
     const size_t need = 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec;
@@ -1064,7 +1046,7 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     }
     if (*bytes < need) return fail(FRT_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
     char* p = (char*)buf;
-    uint64_t hdr[8] = {0x4652544350543034ull, 4, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
+    uint64_t hdr[8] = {0x4652544350543034ull, 5, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
     RCCHK(scopy(s, p, s->L, led, hipMemcpyDeviceToHost));
@@ -1076,16 +1058,7 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     if (nc) {
         FrtRecs hv{};
         hv.cap = nc;
-        hv.src = (uint32_t*)p; p += nc * 4ull;
-        hv.estep = (uint32_t*)p; p += nc * 4ull;
-        hv.lp = (uint32_t*)p; p += nc * 4ull;
-        hv.cell = (uint32_t*)p; p += nc * 4ull;
-        hv.key = (uint32_t*)p; p += nc * 4ull;
-        hv.r = p; p += nc * s->rs;
-        hv.rstop = p; p += nc * s->rs;
-        hv.w0 = p; p += nc * s->rs;
-        hv.dir = p; p += nc * s->rs * 3;
-        hv.tau = p; p += nc * s->rs * 4;
+        hv.rec = p;
         RCCHK(copy_recs(hv, s->F[cur], nc, nb, s->rs, s->stream, hipMemcpyDeviceToHost));
         HIPCHK(hipStreamSynchronize(s->stream));
     }
@@ -1102,12 +1075,12 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     uint64_t hdr[8];
     std::memcpy(hdr, p, sizeof(hdr));
     p += sizeof(hdr);
-    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 4) return fail(FRT_EINVAL, "not a checkpoint of this library");
+    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 5) return fail(FRT_EINVAL, "not a checkpoint of this library");
     if (hdr[3] != (uint64_t)s->n_src || hdr[4] != s->ncell || hdr[5] != (uint64_t)s->P.n_bins || hdr[6] != (uint64_t)s->fp64)
         return fail(FRT_EINVAL, "checkpoint does not match this solve (sources, grid, bins or precision)");
     const uint32_t step = (uint32_t)hdr[2], nc = (uint32_t)hdr[7];
     const int nb = s->P.n_bins;
-    const size_t rec = 20 + 10 * s->rs;
+    const size_t rec = rec_bytes(s->rs);
     const size_t nq = (size_t)step * s->n_src * 4;
     if (bytes < 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec) return fail(FRT_EINVAL, "checkpoint truncated");
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -1134,17 +1107,7 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     if (nc) {
         FrtRecs hv{};
         hv.cap = nc;
-        char* q = (char*)p;
-        hv.src = (uint32_t*)q; q += nc * 4ull;
-        hv.estep = (uint32_t*)q; q += nc * 4ull;
-        hv.lp = (uint32_t*)q; q += nc * 4ull;
-        hv.cell = (uint32_t*)q; q += nc * 4ull;
-        hv.key = (uint32_t*)q; q += nc * 4ull;
-        hv.r = q; q += nc * s->rs;
-        hv.rstop = q; q += nc * s->rs;
-        hv.w0 = q; q += nc * s->rs;
-        hv.dir = q; q += nc * s->rs * 3;
-        hv.tau = q; q += nc * s->rs * 4;
+        hv.rec = (void*)p;
         RCCHK(copy_recs(s->F[cur], hv, nc, nb, s->rs, s->stream, hipMemcpyHostToDevice));
         HIPCHK(hipStreamSynchronize(s->stream));
     }

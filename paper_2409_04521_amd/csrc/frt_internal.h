@@ -48,24 +48,34 @@ struct FrtLedgerDev {
     unsigned long long sc[FRT_STRIPES][LC_NC];
 };
 
-// Structure-of-arrays packet records.  A packet is always at src + r * dir
+// Packet records, one 16-byte-aligned struct per packet (64 bytes in FP32,
+// 112 in FP64), so that a packet is read or written with four (seven)
+// 16-byte accesses wherever it sits.  A packet is always at src + r * dir
 // (children are re-centred on their own pixel directions at the split
 // radius), and `cell` is the cell it is in, so a visit resumes exactly where
-// the last one stopped.  Real-typed arrays hold float (FP32 march) or double.
-struct FrtRecs {
-    uint32_t* src;     // source index within the solve
-    uint32_t* estep;   // step in which the packet's root was cast (rotation lookup)
-    uint32_t* lp;      // level << 28 | NESTED pixel
-    uint32_t* cell;    // linear cell index x + nx (y + ny z)
-    uint32_t* key;     // pass outputs: global brick key and crossing bin (FRT_KEY_BITS);
+// the last one stopped.
+template <typename Real>
+struct alignas(16) FrtRec {
+    uint32_t src;      // source index within the solve
+    uint32_t estep;    // step in which the packet's root was cast (rotation lookup)
+    uint32_t lp;       // level << 28 | NESTED pixel
+    uint32_t cell;     // linear cell index x + nx (y + ny z)
+    uint32_t key;      // pass outputs: global brick key and crossing bin (FRT_KEY_BITS);
                        // sorted packets: the crossing bin; carried packets: solve-local key
-    void* r;           // distance travelled from the source, cells
-    void* rstop;       // distance at which this step's travel budget ends, cells
-    void* w0;          // photons scale: N0_nu = w0 * spec[src][nu] (times R_ref)
-    void* dir;         // [3][cap] unit direction (rotated pixel centre)
-    void* tau;         // [4][cap] optical depth travelled: HI part at sigma_0 (A),
-                       // sub-grid part (K), and their Kahan compensations;
-                       // bin nu has tau_nu = (sigma_nu / sigma_0) A + K
+    Real r;            // distance travelled from the source, cells
+    Real rstop;        // distance at which this step's travel budget ends, cells
+    Real w0;           // photons scale: N0_nu = w0 * spec[src][nu] (times R_ref)
+    Real dir[3];       // unit direction (rotated pixel centre)
+    Real tau[4];       // optical depth travelled: HI part at sigma_0 (A), sub-grid
+                       // part (K), and their Kahan compensations; bin nu has
+                       // tau_nu = (sigma_nu / sigma_0) A + K
+};
+static_assert(sizeof(FrtRec<float>) == 64, "FP32 packet record is 64 bytes");
+static_assert(sizeof(FrtRec<double>) == 112, "FP64 packet record is 112 bytes");
+
+// A queue of packet records (FrtRec<float> or FrtRec<double>).
+struct FrtRecs {
+    void* rec;
     uint32_t cap;
 };
 

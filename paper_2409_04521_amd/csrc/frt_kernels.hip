@@ -281,36 +281,42 @@ struct Pkt {
 // T[0] = A (HI optical depth at sigma_0), T[1] = K (sub-grid optical depth),
 // T[2], T[3] their Kahan compensations.
 template <typename Real>
+__device__ __forceinline__ FrtRec<Real>* recs(const FrtRecs& q) { return (FrtRec<Real>*)q.rec; }
+
+template <typename Real>
 __device__ __forceinline__ void load_pkt(const FrtRecs& q, uint32_t i, Pkt<Real>& h, Real* T)
 {
-    h.src = q.src[i];
-    h.estep = q.estep[i];
-    h.lp = q.lp[i];
-    h.cell = q.cell[i];
-    h.r = ((const Real*)q.r)[i];
-    h.rstop = ((const Real*)q.rstop)[i];
-    h.w0 = ((const Real*)q.w0)[i];
+    const FrtRec<Real> x = recs<Real>(q)[i];
+    h.src = x.src;
+    h.estep = x.estep;
+    h.lp = x.lp;
+    h.cell = x.cell;
+    h.r = x.r;
+    h.rstop = x.rstop;
+    h.w0 = x.w0;
 #pragma unroll
-    for (int a = 0; a < 3; a++) h.d[a] = ((const Real*)q.dir)[(size_t)a * q.cap + i];
+    for (int a = 0; a < 3; a++) h.d[a] = x.dir[a];
 #pragma unroll
-    for (int b = 0; b < 4; b++) T[b] = ((const Real*)q.tau)[(size_t)b * q.cap + i];
+    for (int b = 0; b < 4; b++) T[b] = x.tau[b];
 }
 
 template <typename Real>
 __device__ __forceinline__ void store_pkt(const FrtRecs& q, uint32_t i, const Pkt<Real>& h, uint32_t key, const Real* T)
 {
-    q.src[i] = h.src;
-    q.estep[i] = h.estep;
-    q.lp[i] = h.lp;
-    q.cell[i] = h.cell;
-    q.key[i] = key;
-    ((Real*)q.r)[i] = h.r;
-    ((Real*)q.rstop)[i] = h.rstop;
-    ((Real*)q.w0)[i] = h.w0;
+    FrtRec<Real> x;
+    x.src = h.src;
+    x.estep = h.estep;
+    x.lp = h.lp;
+    x.cell = h.cell;
+    x.key = key;
+    x.r = h.r;
+    x.rstop = h.rstop;
+    x.w0 = h.w0;
 #pragma unroll
-    for (int a = 0; a < 3; a++) ((Real*)q.dir)[(size_t)a * q.cap + i] = h.d[a];
+    for (int a = 0; a < 3; a++) x.dir[a] = h.d[a];
 #pragma unroll
-    for (int b = 0; b < 4; b++) ((Real*)q.tau)[(size_t)b * q.cap + i] = T[b];
+    for (int b = 0; b < 4; b++) x.tau[b] = T[b];
+    recs<Real>(q)[i] = x;
 }
 
 template <typename Real>
@@ -510,7 +516,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
             } else {
                 const uint32_t i = local - n_emit;
                 load_pkt<Real>(D.F[D.cur], i, h, T);
-                key = D.key_base + D.F[D.cur].key[i];   // carried keys are solve-local
+                key = D.key_base + recs<Real>(D.F[D.cur])[i].key;   // carried keys are solve-local
                 const double* sp = D.src_pos + (size_t)h.src * 3;
                 const Real s3[3] = {(Real)sp[0], (Real)sp[1], (Real)sp[2]};
                 const int c[3] = {(int)(h.cell % (uint32_t)D.nx), (int)((h.cell / (uint32_t)D.nx) % (uint32_t)D.ny),
@@ -616,59 +622,61 @@ __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
 template <typename Real, int NB>
 __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
 {
-    constexpr int SLOTS = 512;
+    // PER outputs per thread and round; the table has a slot for every
+    // output of the round, so an insertion always finds one
+    constexpr int PER = 4;
+    constexpr int SLOTS = PER * BLOCK;
     constexpr uint32_t EMPTY = 0xffffffffu;
     __shared__ uint32_t s_key[SLOTS], s_cnt[SLOTS], s_base[SLOTS];
     __shared__ uint32_t s_sp[FRT_QSEG + 1];
     for (int i = threadIdx.x; i <= FRT_QSEG; i += blockDim.x) s_sp[i] = ws.segp[i];
     const uint32_t n = ws.ctr[C_NOS];
     const uint32_t scap = seg_cap(ws.O.cap);
-    const uint32_t stride = gridDim.x * blockDim.x;
-    for (uint32_t base = blockIdx.x * blockDim.x; base < n; base += stride) {
+    FrtRec<Real>* __restrict__ O = recs<Real>(ws.O);
+    FrtRec<Real>* __restrict__ P = recs<Real>(ws.P);
+    for (uint32_t base = blockIdx.x * SLOTS; base < n; base += gridDim.x * SLOTS) {
         for (int i = threadIdx.x; i < SLOTS; i += blockDim.x) {
             s_key[i] = EMPTY;
             s_cnt[i] = 0;
         }
         __syncthreads();
-        const uint32_t v = base + threadIdx.x;
-        const bool active = v < n;
-        uint32_t i = 0;
-        if (active) {
+        uint32_t idx[PER], slot[PER], rank[PER], bin[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const uint32_t v = base + (uint32_t)q * BLOCK + threadIdx.x;
+            idx[q] = 0xffffffffu;
+            if (v >= n) continue;
             const int sg = find_in_prefix(s_sp, FRT_QSEG, v);
-            i = (uint32_t)sg * scap + (v - s_sp[sg]);
-        }
-        uint32_t key = 0, slot = 0, rank = 0;
-        bool valid = active;
-        uint32_t bin = 0;
-        if (active) {
-            key = ws.O.key[i];
-            bin = key >> FRT_KEY_BITS;
+            const uint32_t i = (uint32_t)sg * scap + (v - s_sp[sg]);
+            uint32_t key = O[i].key;
+            bin[q] = key >> FRT_KEY_BITS;
             key &= FRT_KEY_MASK;
             if (key >= ws.nkeys) {          // never expected: flag and skip
                 atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_QUEUE_OVERFLOW);
-                valid = false;
+                continue;
             }
-        }
-        if (valid) {
-            slot = (key * 2654435761u) & (SLOTS - 1);
+            idx[q] = i;
+            uint32_t sl = (key * 2654435761u) & (SLOTS - 1);
             for (;;) {
-                uint32_t prev = atomicCAS(&s_key[slot], EMPTY, key);
+                const uint32_t prev = atomicCAS(&s_key[sl], EMPTY, key);
                 if (prev == EMPTY || prev == key) break;
-                slot = (slot + 1) & (SLOTS - 1);
+                sl = (sl + 1) & (SLOTS - 1);
             }
-            rank = atomicAdd(&s_cnt[slot], 1u);
+            slot[q] = sl;
+            rank[q] = atomicAdd(&s_cnt[sl], 1u);
         }
         __syncthreads();
         for (int j = threadIdx.x; j < SLOTS; j += blockDim.x)
             if (s_key[j] != EMPTY) s_base[j] = atomicAdd(&ws.cursor[s_key[j]], s_cnt[j]);
         __syncthreads();
-        if (valid) {
-            const uint32_t pos = s_base[slot] + rank;
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            if (idx[q] == 0xffffffffu) continue;
+            const uint32_t pos = s_base[slot[q]] + rank[q];
             if (pos < ws.P.cap) {
-                Pkt<Real> h;
-                Real T[4];
-                load_pkt<Real>(ws.O, i, h, T);
-                store_pkt<Real>(ws.P, pos, h, bin, T);   // sorted records keep only the crossing bin
+                FrtRec<Real> x = O[idx[q]];
+                x.key = bin[q];            // sorted records keep only the crossing bin
+                P[pos] = x;
             }
         }
         __syncthreads();
@@ -834,7 +842,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
             const uint32_t j = (uint32_t)q * BLOCK + threadIdx.x;
             slot_of[q] = 0xffffffffu;
             if (j < w.count && w.start + j < np) {
-                const uint32_t e = ws.P.key[w.start + j] & (uint32_t)(NBIN - 1);
+                const uint32_t e = recs<Real>(ws.P)[w.start + j].key & (uint32_t)(NBIN - 1);
                 slot_of[q] = (e << 16) | atomicAdd(&s_bin[e], 1u);
             }
         }
@@ -1176,7 +1184,7 @@ __global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
         if (act) {
             load_pkt<Real>(ws.S, i, h, T);
             ph = ws.s_phot[i];
-            solve = find_in_prefix(ws.key_prefix, ws.n_solves, ws.S.key[i]);
+            solve = find_in_prefix(ws.key_prefix, ws.n_solves, recs<Real>(ws.S)[i].key);
             const FrtSolveDesc& D = descs[solve];
             const double* sp = D.src_pos + (size_t)h.src * 3;
             s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
