@@ -51,6 +51,49 @@ def measured_traffic(workload: str):
     return d.get("bytes_per_launch")
 
 
+def _pmc_per_dispatch(db_dir: str):
+    """(kernel name, {counter: value}) per dispatch, in dispatch order, from
+    a rocprofv3 --pmc run's SQLite output."""
+    import glob
+    import sqlite3
+    dbs = glob.glob(os.path.join(db_dir, "**", "*.db"), recursive=True)
+    if not dbs:
+        raise FileNotFoundError(f"no rocprofv3 database under {db_dir}")
+    con = sqlite3.connect(dbs[0])
+    per = {}
+    q = "select dispatch_id, name, counter_name, counter_value from pmc_events order by dispatch_id"
+    for did, name, cname, val in con.execute(q):
+        d = per.setdefault(did, [name, {}])
+        d[1][cname] = d[1].get(cname, 0.0) + val
+    return [per[k] for k in sorted(per)]
+
+
+def pmc_summary(fetch_dir: str, write_dir: str, copy_mib: int, out_path: str):
+    """HBM bytes per march launch of the last timed step, from FETCH_SIZE and
+    WRITE_SIZE runs (KiB per dispatch) scaled by what the same counters read
+    for the plain copy of copy_mib MiB made before timing."""
+    res = {}
+    for tag, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        ds = _pmc_per_dispatch(d)
+        copies = [c[counter] for n, c in ds if "copyBuffer" in n and counter in c]
+        if not copies:
+            raise RuntimeError(f"{d}: no calibration copy found")
+        scale = copy_mib * 1024.0 / max(copies)
+        last_seed = max(i for i, (n, _) in enumerate(ds) if "k_seed<" in n)
+        brick = [c[counter] for n, c in ds[last_seed:] if "k_brick" in n]
+        res[tag] = {"kib_per_step": sum(brick), "launches": len(brick), "scale": scale}
+    n = res["fetch"]["launches"]
+    per_launch = (res["fetch"]["kib_per_step"] * res["fetch"]["scale"]
+                  + res["write"]["kib_per_step"] * res["write"]["scale"]) * 1024.0 / max(n, 1)
+    out = {"kernel": "k_brick (march)", "kernel_source_hash": kernel_source_hash(),
+           "bytes_per_launch": per_launch, "launches_per_step": n,
+           "fetch_kib_per_step": res["fetch"]["kib_per_step"], "write_kib_per_step": res["write"]["kib_per_step"],
+           "fetch_scale": res["fetch"]["scale"], "write_scale": res["write"]["scale"]}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def cpu_baseline(prob, n_sample: int, threads: int):
     from oracle import oracle as O
     from paper_2409_04521_amd import workloads as W
@@ -78,7 +121,14 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=1024,
                     help="size of a plain device copy run before timing; its hardware byte counters "
                          "calibrate the march kernel's (0 = skip)")
+    ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/march_c3b_traffic.json from two rocprofv3 --pmc runs of this "
+                         "benchmark (FETCH_SIZE, WRITE_SIZE) and exit")
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_calibration_mib,
+                    os.path.join(ROOT, "profiles", "march_c3b_traffic.json"))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU form "
               "(sources sharded over GPUs, one reduction of the rate field per step) is not built.",
@@ -96,7 +146,11 @@ def main():
     stream = torch.cuda.Stream()          # default priority; the library enqueues on it
     torch.cuda.set_stream(stream)
     ctx = frt.Context(0)
-    s = frt.solve_from_problem(ctx, prob, stream=stream.cuda_stream)
+    # first size of the pass queues: the largest pass of this workload holds
+    # 2.72e8 packets (reported as max_pass_packets); with a third more the
+    # warm-up step never overflows and re-runs (64-byte records: 23 GB per queue)
+    hint = int(3.6e8 * (args.n / 256) ** 3 * args.sources / 2000)
+    s = frt.solve_from_problem(ctx, prob, stream=stream.cuda_stream, queue_hint=hint)
     # Every step starts from the configured state (rewound on the device):
     # from x_HI = 1e-4 the dense source cells recombine within one step
     # (their Stromgren radii are below a tenth of a cell), after which every
@@ -147,7 +201,7 @@ def main():
     traffic = measured_traffic("c3b")
     roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-            "kernel": "k_march", "avg_launch_ms": round(avg_launch_s * 1e3, 4),
+            "kernel": "k_brick", "avg_launch_ms": round(avg_launch_s * 1e3, 4),
             "algorithmic_bytes_per_launch": round(per_launch), "launches": tm["march_launches"]}
 
     out = {"metric": METRIC, "value": value, "unit": "crossings/s", "n_gpus": 1, "steps": args.steps,
@@ -157,6 +211,7 @@ def main():
                                   f"c=inf, {nb} bins, floor 1e-3, cap 50 cMpc/h, l_max 12",
                       "cells": prob.ncell, "sources": prob.n_src, "crossings_per_step": cross / args.steps,
                       "visits_per_step": d_visits / args.steps, "ledger_closure": closure,
+                      "max_pass_packets": L1["max_items"],
                       "steps_start_from": "the configured state, rewound on the device before each step",
                       "parallelism": "single GPU"},
            "roofline": roof,

@@ -72,7 +72,7 @@ typedef struct {
     double alpha_B;                 /* recombination coefficient at the fixed T, cm^3/s */
     double coll_ion;                /* collisional ionization coefficient, cm^3/s (default 0) */
     int base_level;                 /* HEALPix level l_hpx of cast packets (§3.1), 0..8 */
-    int max_level;                  /* packets at this level never split, base_level..13 */
+    int max_level;                  /* packets at this level never split, base_level..12 */
     double n_ray_min;               /* N_ray^min of Eq. r_split (> 0; default 1) */
     double flux_floor;              /* drop a packet when its photons fall below this fraction
                                        of its cast photons (divided by 4 per split); 0 = off */
@@ -81,7 +81,11 @@ typedef struct {
     int march_precision;            /* FRT_F32 (default) or FRT_F64 */
     uint64_t seed;                  /* stream of the per-step random sphere rotations */
     uint64_t queue_capacity;        /* entries per ray queue; 0 = sized automatically and grown
-                                       (the step is re-run) when a step overflows */
+                                       (the step is re-run) when a step overflows.  A fixed
+                                       capacity is cut into 64 equal segments, one per group
+                                       of workgroups, and a full segment is an overflow */
+    uint64_t queue_hint;            /* automatic sizing only: first size of the pass queues in
+                                       entries (0 = from the grid and source counts) */
 } frt_params;
 
 /* Cumulative photon ledger (photons) and counters of one solve.  With
@@ -100,7 +104,7 @@ typedef struct {
 
 /* Fill *p with defaults: 1 bin at 6.3e-18 cm^2, alpha_B = 2.59e-13,
  * coll_ion = 0, base_level 0, max_level 12, n_ray_min 1, no floor, no cap,
- * c_ray = speed of light, FRT_F32, seed 0, automatic queues. */
+ * c_ray = speed of light, FRT_F32, seed 0, automatic queues, no hint. */
 int frt_params_default(frt_params* p);
 
 /* Context bound to HIP device `hip_device`.  Owns nothing else. */

@@ -547,7 +547,8 @@ int step_group(frt_solve* ss, int n, const double* dts)
         set_step_fields(s, dts[i]);
         nkeys64 += (uint64_t)s->bpx * s->bpy * s->bpz;
         const uint64_t cast = (uint64_t)s->n_src * (12ull << (2 * s->P.base_level));
-        want_p += s->P.queue_capacity ? s->P.queue_capacity : std::max<uint64_t>(4 * cast + 65536, s->ncell / 2);
+        want_p += s->P.queue_capacity ? s->P.queue_capacity
+                                      : (s->P.queue_hint ? s->P.queue_hint : std::max<uint64_t>(4 * cast + 65536, s->ncell / 2));
     }
     if (nkeys64 > FRT_KEY_MASK)
         return fail(FRT_EINVAL, "the solves of one launch hold %llu bricks, more than %u", (unsigned long long)nkeys64, FRT_KEY_MASK);
@@ -647,6 +648,7 @@ int frt_params_default(frt_params* p)
     p->march_precision = FRT_F32;
     p->seed = 0;
     p->queue_capacity = 0;
+    p->queue_hint = 0;
     return FRT_OK;
 }
 
@@ -680,7 +682,7 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     for (int b = 0; b < P->n_bins; b++)
         if (!(P->sigma_bins[b] > 0) || !std::isfinite(P->sigma_bins[b])) return fail(FRT_EINVAL, "sigma_bins[%d] must be finite and > 0", b);
     if (P->base_level < 0 || P->base_level > 8) return fail(FRT_EINVAL, "base_level %d outside 0..8", P->base_level);
-    if (P->max_level < P->base_level || P->max_level > 13) return fail(FRT_EINVAL, "max_level %d outside base_level..13", P->max_level);
+    if (P->max_level < P->base_level || P->max_level > 12) return fail(FRT_EINVAL, "max_level %d outside base_level..12", P->max_level);
     if (!(P->n_ray_min > 0) || !std::isfinite(P->n_ray_min)) return fail(FRT_EINVAL, "n_ray_min must be finite and > 0");
     if (!(P->alpha_B >= 0) || !(P->coll_ion >= 0) || !std::isfinite(P->alpha_B) || !std::isfinite(P->coll_ion))
         return fail(FRT_EINVAL, "alpha_B and coll_ion must be finite and >= 0");

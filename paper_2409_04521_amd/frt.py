@@ -40,7 +40,7 @@ class Params(C.Structure):
                 ("alpha_B", C.c_double), ("coll_ion", C.c_double), ("base_level", C.c_int),
                 ("max_level", C.c_int), ("n_ray_min", C.c_double), ("flux_floor", C.c_double),
                 ("max_distance_cm", C.c_double), ("c_ray_cm_s", C.c_double), ("march_precision", C.c_int),
-                ("seed", C.c_uint64), ("queue_capacity", C.c_uint64)]
+                ("seed", C.c_uint64), ("queue_capacity", C.c_uint64), ("queue_hint", C.c_uint64)]
 
 
 class Ledger(C.Structure):
@@ -158,7 +158,7 @@ class Solve:
 
     def __init__(self, ctx: Context, *, sigma_bins, alpha_B=2.59e-13, coll_ion=0.0, base_level=0,
                  max_level=12, n_ray_min=1.0, flux_floor=0.0, max_distance_cm=0.0, c_ray=2.99792458e10,
-                 precision="f32", seed=0, queue_capacity=0, stream=None):
+                 precision="f32", seed=0, queue_capacity=0, queue_hint=0, stream=None):
         p = params_default()
         sig = list(sigma_bins)
         p.n_bins = len(sig)
@@ -169,7 +169,7 @@ class Solve:
         p.flux_floor, p.max_distance_cm = flux_floor, max_distance_cm
         p.c_ray_cm_s = c_ray if c_ray is not None else math.inf
         p.march_precision = FRT_F64 if precision == "f64" else FRT_F32
-        p.seed, p.queue_capacity = seed, queue_capacity
+        p.seed, p.queue_capacity, p.queue_hint = seed, queue_capacity, queue_hint
         self.ctx = ctx
         self.params = p
         self.n_bins = p.n_bins
