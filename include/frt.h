@@ -150,6 +150,40 @@ int frt_step(frt_solve s, double dt_s);
  * must share n_bins and march_precision).  dt_s[i] is solve i's step. */
 int frt_batch_step(frt_solve* solves, int n, const double* dt_s);
 
+/* n_steps steps of each of n solves (as n_steps calls of frt_batch_step).
+ * With use_graph != 0 one step of the group is captured into a HIP graph
+ * and replayed n_steps times: the descriptors and rotation tables are
+ * prepared before the capture, and the step index advances on the device.
+ * Each replay is checked; with automatic queues an overflowed step is
+ * restored, the queues grow, the step is captured again and repeated, and
+ * with fixed queues the call returns FRT_EOVERFLOW with the failed step not
+ * applied.  dt_s[i] is solve i's step for every step of the run. */
+int frt_batch_run(frt_solve* solves, int n, const double* dt_s, int n_steps, int use_graph);
+
+/* Launch shape of the passes, shared by the solves stepped on a context. */
+typedef struct {
+    size_t size;                    /* sizeof(frt_tuning) */
+    int item_rays;                  /* packets per march work item (the ray tile):
+                                       a multiple of 64 in 64..1024 */
+    int scatter_blocks_per_cu;      /* workgroups per CU of the pass that sorts the
+                                       queue by brick (queue chunking), 1..16 */
+    int split_blocks_per_cu;        /* workgroups per CU of the pass that writes
+                                       split children, 1..16 */
+} frt_tuning;
+
+/* Defaults: 1024 packets per item, 8 and 4 workgroups per CU. */
+int frt_tuning_default(frt_tuning* t);
+int frt_ctx_set_tuning(frt_ctx ctx, const frt_tuning* t);
+int frt_ctx_get_tuning(frt_ctx ctx, frt_tuning* t);
+
+/* Autotuner: times one step of the n solves (as frt_batch_step runs it)
+ * under each candidate launch shape (item_rays 256/512/1024 x scatter 4/8
+ * x split 2/4 workgroups per CU), after one untimed step that sizes the
+ * queues; sets the fastest on the context and returns it in *best.  Every
+ * solve is put back exactly as it was (fields, carried packets, ledger,
+ * step index, last rate field), so the call changes no result. */
+int frt_autotune(frt_solve* solves, int n, const double* dt_s, frt_tuning* best);
+
 /* Wait for the solve's stream; report deferred device errors. */
 int frt_sync(frt_solve s);
 

@@ -112,6 +112,8 @@ struct Workspace {
     double* s_phot = nullptr;
     uint32_t* segc = nullptr;
     uint32_t* segp = nullptr;
+    uint32_t* ctr_host = nullptr;   // pinned copy of the counters
+    frt_tuning tune{sizeof(frt_tuning), (int)FRT_ITEM_RAYS, 8, 4};
     uint32_t* ctr = nullptr;
     uint32_t* hist = nullptr;
     uint32_t* cursor = nullptr;
@@ -132,6 +134,8 @@ struct Workspace {
         dev_free(s_phot);
         dev_free(segc);
         dev_free(segp);
+        if (ctr_host) (void)hipHostFree(ctr_host);
+        ctr_host = nullptr;
         dev_free(ctr); dev_free(hist); dev_free(cursor); dev_free(work); dev_free(key_prefix);
         dev_free(seed_prefix); dev_free(cell_prefix); dev_free(descs);
         nkeys_cap = 0; cap_work = 0; solves_cap = 0; fp64 = -1; nb = 0;
@@ -390,6 +394,10 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
         ws.cap_work = 0;
     }
     if (!ws.ctr) RCCHK(dev_alloc((void**)&ws.ctr, C_NCTR * 4));
+    if (!ws.ctr_host && hipHostMalloc((void**)&ws.ctr_host, C_NCTR * 4, hipHostMallocDefault) != hipSuccess) {
+        ws.ctr_host = nullptr;
+        return fail(FRT_ENOMEM, "pinned counter buffer");
+    }
     if (!ws.segc) RCCHK(dev_alloc((void**)&ws.segc, 2ull * FRT_QSEG * FRT_QSEG_STRIDE * 4));
     if (!ws.segp) RCCHK(dev_alloc((void**)&ws.segp, (FRT_QSEG + 1) * 4ull));
     if (ws.nkeys_cap < nkeys) {
@@ -405,7 +413,7 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
         dev_free(ws.work);
         ws.cap_work = 0;
     }
-    const uint64_t want_work = (uint64_t)ws.P.cap / FRT_ITEM_RAYS + ws.nkeys_cap + 64;
+    const uint64_t want_work = (uint64_t)ws.P.cap / (uint64_t)ws.tune.item_rays + ws.nkeys_cap + 64;
     if (ws.cap_work < want_work) {
         dev_free(ws.work);
         RCCHK(dev_alloc((void**)&ws.work, want_work * sizeof(FrtWork)));
@@ -445,31 +453,33 @@ struct Timed {
     }
 };
 
-// Enqueue one step of n solves (same n_bins and precision) on stream st.
-int enqueue_group(Workspace& ws, frt_solve* ss, int n, hipStream_t st)
-{
-    const int nb = ss[0]->P.n_bins, fp64 = ss[0]->fp64;
-    frt_solve tm = ss[0]->timing ? ss[0] : nullptr;
-    std::vector<uint32_t> kp(n + 1);
-    std::vector<unsigned long long> cp(n + 1);
-    std::vector<FrtSolveDesc> hd(n);
-    kp[0] = 0;
-    cp[0] = 0;
+// Host side of one step of a group of solves (same n_bins and precision):
+// brick-key bases, descriptors, prefixes, the pass count and the launch
+// workspace.
+struct Group {
+    std::vector<uint32_t> kp;
+    std::vector<unsigned long long> cp;
+    std::vector<FrtSolveDesc> hd;
     int passes = 1;
+    FrtWS w{};
+};
+
+void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
+{
+    g.kp.assign(n + 1, 0);
+    g.cp.assign(n + 1, 0);
+    g.hd.resize(n);
+    g.passes = 1;
     for (int i = 0; i < n; i++) {
         frt_solve s = ss[i];
-        s->h.key_base = kp[i];
-        hd[i] = s->h;
-        kp[i + 1] = kp[i] + (uint32_t)(s->bpx * s->bpy * s->bpz);
-        cp[i + 1] = cp[i] + s->ncell;
-        passes = std::max(passes, passes_needed(s));
+        s->h.key_base = g.kp[i];
+        g.hd[i] = s->h;
+        g.kp[i + 1] = g.kp[i] + (uint32_t)(s->bpx * s->bpy * s->bpz);
+        g.cp[i + 1] = g.cp[i] + s->ncell;
+        g.passes = std::max(g.passes, passes_needed(s));
     }
-    HIPCHK(hipMemcpyAsync(ws.descs, hd.data(), n * sizeof(FrtSolveDesc), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ws.key_prefix, kp.data(), (n + 1) * 4ull, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(ws.cell_prefix, cp.data(), (n + 1) * 8ull, hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemsetAsync(ws.ctr, 0, C_NCTR * 4, st));
-    HIPCHK(hipMemsetAsync(ws.hist, 0, kp[n] * 4ull, st));
-    FrtWS w{};
+    FrtWS& w = g.w;
+    w = FrtWS{};
     w.O = ws.O;
     w.P = ws.P;
     w.S = ws.S;
@@ -481,13 +491,16 @@ int enqueue_group(Workspace& ws, frt_solve* ss, int n, hipStream_t st)
     w.cursor = ws.cursor;
     w.work = ws.work;
     w.cap_work = ws.cap_work;
-    w.nkeys = kp[n];
+    w.nkeys = g.kp[n];
     w.key_prefix = ws.key_prefix;
     w.seed_prefix = ws.seed_prefix;
     w.n_solves = n;
-    w.n_bins = nb;
+    w.n_bins = ss[0]->P.n_bins;
     w.has_sub = 0;
     for (int i = 0; i < n; i++) w.has_sub |= ss[i]->h.has_sub;
+    w.item_rays = (uint32_t)ws.tune.item_rays;
+    w.scatter_bpc = ws.tune.scatter_blocks_per_cu;
+    w.split_bpc = ws.tune.split_blocks_per_cu;
     if (ss[0]->P.queue_capacity) {
         // fixed capacities: the shared workspace is used up to the solves' limit
         uint64_t lim = 0;
@@ -497,12 +510,39 @@ int enqueue_group(Workspace& ws, frt_solve* ss, int n, hipStream_t st)
         w.P.cap = c;
         w.S.cap = std::min<uint32_t>(w.S.cap, std::max<uint32_t>(c / 2, 1024));
     }
+}
+
+// Descriptors and prefixes to the device (pageable host memory: never
+// inside a stream capture).
+int upload_group(Workspace& ws, const Group& g, int n, hipStream_t st)
+{
+    HIPCHK(hipMemcpyAsync(ws.descs, g.hd.data(), n * sizeof(FrtSolveDesc), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws.key_prefix, g.kp.data(), (n + 1) * 4ull, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(ws.cell_prefix, g.cp.data(), (n + 1) * 8ull, hipMemcpyHostToDevice, st));
+    return FRT_OK;
+}
+
+// Enqueue one step of a planned group on st.  With `graph` the step is
+// being captured: it starts by saving each solve's ledger and carried count
+// (for a re-run after an overflow) and ends by advancing the step index on
+// the device; nothing in it reads host memory or records events.
+int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_t st, bool graph)
+{
+    const int fp64 = ss[0]->fp64;
+    const FrtWS& w = g.w;
+    frt_solve tm = (!graph && ss[0]->timing) ? ss[0] : nullptr;
     hipError_t e;
+    if (graph)
+        for (int i = 0; i < n; i++) {
+            HIPCHK(hipMemcpyAsync(ss[i]->L_snap, ss[i]->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
+            HIPCHK(hipMemcpyAsync(ss[i]->fcount_snap, ss[i]->fcount, 8, hipMemcpyDeviceToDevice, st));
+        }
     {
         Timed t(tm, st, 0);
+        if ((e = frt::launch_clear(w, st)) != hipSuccess) return fail(FRT_EDEVICE, "clear: %s", hipGetErrorString(e));
         if ((e = frt::launch_seed(ws.descs, w, fp64, st)) != hipSuccess) return fail(FRT_EDEVICE, "seed: %s", hipGetErrorString(e));
     }
-    for (int p = 0; p < passes; p++) {
+    for (int p = 0; p < g.passes; p++) {
         {
             Timed t(tm, st, 3);
             if ((e = frt::launch_pass(ws.descs, w, fp64, 0, st)) != hipSuccess) return fail(FRT_EDEVICE, "scan: %s", hipGetErrorString(e));
@@ -522,105 +562,310 @@ int enqueue_group(Workspace& ws, frt_solve* ss, int n, hipStream_t st)
     }
     {
         Timed t(tm, st, 2);
-        if ((e = frt::launch_chem(ws.descs, ws.cell_prefix, n, cp[n], fp64, st)) != hipSuccess)
+        if ((e = frt::launch_chem(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, st)) != hipSuccess)
             return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         if (tm) tm->n_chem++;
     }
+    if (graph && (e = frt::launch_advance(ws.descs, w, st)) != hipSuccess)
+        return fail(FRT_EDEVICE, "advance: %s", hipGetErrorString(e));
     if (tm) tm->n_steps_timed++;
+    return FRT_OK;
+}
+
+// Queue sizes of a group step before anything grew: brick keys and the
+// first size of the pass queues.
+int group_sizes(frt_solve* ss, int n, uint32_t* nkeys, uint64_t* want_p)
+{
+    uint64_t nk = 0, wp = 0;
+    for (int i = 0; i < n; i++) {
+        frt_solve s = ss[i];
+        nk += (uint64_t)s->bpx * s->bpy * s->bpz;
+        const uint64_t cast = (uint64_t)s->n_src * (12ull << (2 * s->P.base_level));
+        wp += s->P.queue_capacity ? s->P.queue_capacity
+                                  : (s->P.queue_hint ? s->P.queue_hint : std::max<uint64_t>(4 * cast + 65536, s->ncell / 2));
+    }
+    if (nk > FRT_KEY_MASK)
+        return fail(FRT_EINVAL, "the solves of one launch hold %llu bricks, more than %u", (unsigned long long)nk, FRT_KEY_MASK);
+    *nkeys = (uint32_t)nk;
+    *want_p = wp;
+    return FRT_OK;
+}
+
+// After a step that overflowed: put every solve back to the start of the
+// step (ledger, carried count, this step's rate buffer; the chemistry of an
+// overflowed step does not run) and enlarge what overflowed.
+int recover_overflow(Workspace& ws, frt_solve* ss, int n, const uint32_t* ctr, uint64_t* want_p, hipStream_t st)
+{
+    // packets each solve tried to carry into the next step (the counter
+    // counts every reservation, also those past the capacity)
+    std::vector<uint32_t> fneed(n, 0);
+    if (ctr[C_ERR] & FRT_DEVERR_CARRY_OVERFLOW) {
+        HIPCHK(hipStreamSynchronize(st));
+        for (int i = 0; i < n; i++) {
+            uint32_t fc[2];
+            HIPCHK(hipMemcpy(fc, ss[i]->fcount, 8, hipMemcpyDeviceToHost));
+            const uint32_t nxt = fc[1 - (ss[i]->step & 1u)];
+            if (nxt > ss[i]->F[0].cap) fneed[i] = nxt;
+        }
+    }
+    for (int i = 0; i < n; i++) {
+        frt_solve s = ss[i];
+        if (s->timing) s->reset_timing();
+        HIPCHK(hipMemcpyAsync(s->L, s->L_snap, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->fcount, s->fcount_snap, 8, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemsetAsync(s->gam[s->step & 1u], 0, s->ncell * s->rs, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    if (ctr[C_ERR] & FRT_DEVERR_QUEUE_OVERFLOW) {
+        if (ws.P.cap >= 2147483647u) return fail(FRT_EOVERFLOW, "pass buffers at their maximum size still overflow");
+        const uint64_t need = std::max<uint64_t>(2ull * ws.P.cap, (uint64_t)ctr[C_MAXP] + (ctr[C_MAXP] >> 2) + 65536);
+        *want_p = std::min<uint64_t>(need, 2147483647ull);
+    }
+    for (int i = 0; i < n; i++) {
+        frt_solve s = ss[i];
+        if (!fneed[i]) continue;
+        const uint64_t nc = std::min<uint64_t>(std::max<uint64_t>(2ull * s->F[0].cap, fneed[i] + 65536ull), 2147483647ull);
+        const int cur = (int)(s->step & 1u);
+        uint32_t keep;
+        HIPCHK(hipMemcpy(&keep, s->fcount + cur, 4, hipMemcpyDeviceToHost));
+        FrtRecs nf[2];
+        RCCHK(alloc_recs(nf[0], (uint32_t)nc, s->P.n_bins, s->rs));
+        RCCHK(alloc_recs(nf[1], (uint32_t)nc, s->P.n_bins, s->rs));
+        RCCHK(copy_recs(nf[cur], s->F[cur], std::min(keep, s->F[cur].cap), s->P.n_bins, s->rs, st, hipMemcpyDeviceToDevice));
+        HIPCHK(hipStreamSynchronize(st));
+        free_recs(s->F[0]);
+        free_recs(s->F[1]);
+        s->F[0] = nf[0];
+        s->F[1] = nf[1];
+        s->h.F[0] = nf[0];
+        s->h.F[1] = nf[1];
+        RCCHK(upload_desc(s));
+    }
+    return FRT_OK;
+}
+
+int read_counters(Workspace& ws, hipStream_t st, uint32_t* out)
+{
+    HIPCHK(hipMemcpyAsync(ws.ctr_host, ws.ctr, C_NCTR * 4, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(out, ws.ctr_host, C_NCTR * 4);
     return FRT_OK;
 }
 
 // One step of a group with automatic queue growth: snapshot, run, check,
 // and on overflow restore the starting state, enlarge and run again.
-int step_group(frt_solve* ss, int n, const double* dts)
+// The caller holds the context lock.
+int step_group_locked(frt_solve* ss, int n, const double* dts)
 {
-    frt_ctx ctx = ss[0]->ctx;
-    std::lock_guard<std::mutex> lock(ctx->mu);
-    Workspace& ws = ctx->ws;
+    Workspace& ws = ss[0]->ctx->ws;
     hipStream_t st = ss[0]->stream;
     const bool auto_grow = ss[0]->P.queue_capacity == 0;
-    uint64_t nkeys64 = 0;
+    uint32_t nkeys = 0;
     uint64_t want_p = 0;
+    RCCHK(group_sizes(ss, n, &nkeys, &want_p));
     for (int i = 0; i < n; i++) {
-        frt_solve s = ss[i];
-        RCCHK(ensure_quat(s, s->step));
-        set_step_fields(s, dts[i]);
-        nkeys64 += (uint64_t)s->bpx * s->bpy * s->bpz;
-        const uint64_t cast = (uint64_t)s->n_src * (12ull << (2 * s->P.base_level));
-        want_p += s->P.queue_capacity ? s->P.queue_capacity
-                                      : (s->P.queue_hint ? s->P.queue_hint : std::max<uint64_t>(4 * cast + 65536, s->ncell / 2));
+        RCCHK(ensure_quat(ss[i], ss[i]->step));
+        set_step_fields(ss[i], dts[i]);
     }
-    if (nkeys64 > FRT_KEY_MASK)
-        return fail(FRT_EINVAL, "the solves of one launch hold %llu bricks, more than %u", (unsigned long long)nkeys64, FRT_KEY_MASK);
-    const uint32_t nkeys = (uint32_t)nkeys64;
     for (int attempt = 0; attempt < 16; attempt++) {
         RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.P.cap)));
         for (int i = 0; i < n; i++) {
             HIPCHK(hipMemcpyAsync(ss[i]->L_snap, ss[i]->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
             HIPCHK(hipMemcpyAsync(ss[i]->fcount_snap, ss[i]->fcount, 8, hipMemcpyDeviceToDevice, st));
         }
-        RCCHK(enqueue_group(ws, ss, n, st));
+        Group g;
+        plan_group(ws, ss, n, g);
+        RCCHK(upload_group(ws, g, n, st));
+        RCCHK(enqueue_step(ws, ss, n, g, st, false));
         if (!auto_grow) {
             for (int i = 0; i < n; i++) ss[i]->step++;
             return FRT_OK;
         }
         uint32_t ctr[C_NCTR];
-        HIPCHK(hipMemcpyAsync(ctr, ws.ctr, sizeof(ctr), hipMemcpyDeviceToHost, st));
-        HIPCHK(hipStreamSynchronize(st));
-        bool f_over = false;
-        std::vector<uint32_t> fneed(n, 0);
-        for (int i = 0; i < n; i++) {
-            uint32_t fc[2];
-            HIPCHK(hipMemcpy(fc, ss[i]->fcount, 8, hipMemcpyDeviceToHost));
-            const uint32_t nxt = fc[1 - (ss[i]->step & 1u)];
-            if (nxt > ss[i]->F[0].cap) {
-                f_over = true;
-                fneed[i] = nxt;
-            }
-        }
-        const bool over = (ctr[C_ERR] & FRT_DEVERR_QUEUE_OVERFLOW) || f_over;
-        if (!over) {
+        RCCHK(read_counters(ws, st, ctr));
+        if (!(ctr[C_ERR] & (FRT_DEVERR_QUEUE_OVERFLOW | FRT_DEVERR_CARRY_OVERFLOW))) {
             if (ctr[C_ERR] & FRT_DEVERR_UNFINISHED) return fail(FRT_EDEVICE, "a step left packets after its last pass");
             for (int i = 0; i < n; i++) ss[i]->step++;
             return FRT_OK;
         }
-        // restore every solve of the group to the start of the step
-        for (int i = 0; i < n; i++) {
-            frt_solve s = ss[i];
-            if (s->timing) s->reset_timing();
-            HIPCHK(hipMemcpyAsync(s->L, s->L_snap, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync(s->fcount, s->fcount_snap, 8, hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemsetAsync(s->gam[s->step & 1u], 0, s->ncell * s->rs, st));
-        }
-        HIPCHK(hipStreamSynchronize(st));
-        // enlarge what overflowed
-        if (ctr[C_ERR] & FRT_DEVERR_QUEUE_OVERFLOW) {
-            const uint64_t need = std::max<uint64_t>(2ull * ws.P.cap, (uint64_t)ctr[C_MAXP] + (ctr[C_MAXP] >> 2) + 65536);
-            if (ws.P.cap >= 2147483647u) return fail(FRT_EOVERFLOW, "pass buffers at their maximum size still overflow");
-            want_p = std::min<uint64_t>(need, 2147483647ull);
-        }
-        for (int i = 0; i < n; i++) {
-            frt_solve s = ss[i];
-            if (!fneed[i]) continue;
-            const uint64_t nc = std::min<uint64_t>(std::max<uint64_t>(2ull * s->F[0].cap, fneed[i] + 65536), 2147483647ull);
-            const int cur = (int)(s->step & 1u);
-            uint32_t keep;
-            HIPCHK(hipMemcpy(&keep, s->fcount + cur, 4, hipMemcpyDeviceToHost));
-            FrtRecs nf[2];
-            RCCHK(alloc_recs(nf[0], (uint32_t)nc, s->P.n_bins, s->rs));
-            RCCHK(alloc_recs(nf[1], (uint32_t)nc, s->P.n_bins, s->rs));
-            RCCHK(copy_recs(nf[cur], s->F[cur], std::min(keep, s->F[cur].cap), s->P.n_bins, s->rs, st, hipMemcpyDeviceToDevice));
-            HIPCHK(hipStreamSynchronize(st));
-            free_recs(s->F[0]);
-            free_recs(s->F[1]);
-            s->F[0] = nf[0];
-            s->F[1] = nf[1];
-            s->h.F[0] = nf[0];
-            s->h.F[1] = nf[1];
-            RCCHK(upload_desc(s));
-        }
+        RCCHK(recover_overflow(ws, ss, n, ctr, &want_p, st));
     }
     return fail(FRT_EOVERFLOW, "step kept overflowing its queues");
+}
+
+int step_group(frt_solve* ss, int n, const double* dts)
+{
+    std::lock_guard<std::mutex> lock(ss[0]->ctx->mu);
+    return step_group_locked(ss, n, dts);
+}
+
+// A HIP graph of one step of a group, destroyed with the object.
+struct StepGraph {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void reset()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+    }
+    ~StepGraph() { reset(); }
+};
+
+// n_steps steps of a group; each step is one replay of a captured graph.
+// Every replay is checked: an overflow restores the step's start, grows the
+// queues, captures again and repeats the step.  The caller holds the lock.
+int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps)
+{
+    Workspace& ws = ss[0]->ctx->ws;
+    hipStream_t st = ss[0]->stream;
+    const bool auto_grow = ss[0]->P.queue_capacity == 0;
+    uint32_t nkeys = 0;
+    uint64_t want_p = 0;
+    RCCHK(group_sizes(ss, n, &nkeys, &want_p));
+    int has_sub = 0;
+    for (int i = 0; i < n; i++) {
+        // rotations of every step of the run exist before the capture
+        RCCHK(ensure_quat(ss[i], ss[i]->step + (uint32_t)n_steps));
+        has_sub |= ss[i]->h.has_sub;
+    }
+    frt::prime_launch_shapes(ss[0]->fp64, ss[0]->P.n_bins, has_sub);
+    StepGraph sg;
+    Group g;
+    int done = 0, retries = 0;
+    while (done < n_steps) {
+        if (!sg.exec) {
+            for (int i = 0; i < n; i++) set_step_fields(ss[i], dts[i]);
+            RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.P.cap)));
+            plan_group(ws, ss, n, g);
+            RCCHK(upload_group(ws, g, n, st));
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            const int rc = enqueue_step(ws, ss, n, g, st, true);
+            hipGraph_t graph = nullptr;
+            const hipError_t ec = hipStreamEndCapture(st, &graph);
+            sg.graph = graph;
+            if (rc != FRT_OK) return rc;
+            if (ec != hipSuccess) return fail(FRT_EDEVICE, "graph capture: %s", hipGetErrorString(ec));
+            HIPCHK(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(sg.exec, st));
+        uint32_t ctr[C_NCTR];
+        RCCHK(read_counters(ws, st, ctr));
+        if (ctr[C_ERR] & (FRT_DEVERR_QUEUE_OVERFLOW | FRT_DEVERR_CARRY_OVERFLOW)) {
+            if (!auto_grow) {
+                // fixed capacities: the step is not applied
+                for (int i = 0; i < n; i++) {
+                    HIPCHK(hipMemcpyAsync(ss[i]->L, ss[i]->L_snap, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
+                    HIPCHK(hipMemcpyAsync(ss[i]->fcount, ss[i]->fcount_snap, 8, hipMemcpyDeviceToDevice, st));
+                    HIPCHK(hipMemsetAsync(ss[i]->gam[ss[i]->step & 1u], 0, ss[i]->ncell * ss[i]->rs, st));
+                }
+                HIPCHK(hipStreamSynchronize(st));
+                return fail(FRT_EOVERFLOW, "a ray queue overflowed at step %u; raise queue_capacity", ss[0]->step);
+            }
+            if (++retries > 16) return fail(FRT_EOVERFLOW, "step kept overflowing its queues");
+            RCCHK(recover_overflow(ws, ss, n, ctr, &want_p, st));
+            sg.reset();
+            continue;
+        }
+        if (ctr[C_ERR] & FRT_DEVERR_UNFINISHED) return fail(FRT_EDEVICE, "a step left packets after its last pass");
+        retries = 0;
+        for (int i = 0; i < n; i++) ss[i]->step++;
+        done++;
+    }
+    for (int i = 0; i < n; i++) {
+        ss[i]->h.step = ss[i]->step;
+        ss[i]->h.cur = ss[i]->step & 1u;
+        RCCHK(upload_desc(ss[i]));
+    }
+    return FRT_OK;
+}
+
+// Device copy of everything a step changes in a solve, for the autotuner.
+struct SolveSnap {
+    double* x = nullptr;
+    void* gam_last = nullptr;
+    FrtRecs F{};
+    FrtLedgerDev* L = nullptr;
+    uint32_t fc[2] = {0, 0};
+    uint32_t step = 0;
+    void release()
+    {
+        dev_free(x);
+        dev_free(gam_last);
+        free_recs(F);
+        dev_free(L);
+    }
+};
+
+int snap_take(frt_solve s, SolveSnap& p)
+{
+    HIPCHK(hipStreamSynchronize(s->stream));
+    RCCHK(scopy(s, p.fc, s->fcount, 8, hipMemcpyDeviceToHost));
+    const int cur = (int)(s->step & 1u);
+    const uint32_t nc = std::min(p.fc[cur], s->F[cur].cap);
+    RCCHK(dev_alloc((void**)&p.x, s->ncell * 8));
+    RCCHK(dev_alloc(&p.gam_last, s->ncell * s->rs));
+    RCCHK(dev_alloc((void**)&p.L, sizeof(FrtLedgerDev)));
+    RCCHK(alloc_recs(p.F, std::max<uint32_t>(nc, 1), s->P.n_bins, s->rs));
+    HIPCHK(hipMemcpyAsync(p.x, s->x, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(p.gam_last, s->gam[cur ^ 1], s->ncell * s->rs, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(p.L, s->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, s->stream));
+    RCCHK(copy_recs(p.F, s->F[cur], nc, s->P.n_bins, s->rs, s->stream, hipMemcpyDeviceToDevice));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    p.step = s->step;
+    return FRT_OK;
+}
+
+int snap_restore(frt_solve s, const SolveSnap& p)
+{
+    const int cur = (int)(p.step & 1u);
+    const uint32_t nc = std::min(p.fc[cur], p.F.cap);
+    if (nc > s->F[cur].cap) return fail(FRT_ESTATE, "carried queue shrank during tuning");
+    HIPCHK(hipMemcpyAsync(s->x, p.x, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemcpyAsync(s->gam[cur ^ 1], p.gam_last, s->ncell * s->rs, hipMemcpyDeviceToDevice, s->stream));
+    HIPCHK(hipMemsetAsync(s->gam[cur], 0, s->ncell * s->rs, s->stream));
+    HIPCHK(hipMemcpyAsync(s->L, p.L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, s->stream));
+    RCCHK(copy_recs(s->F[cur], p.F, nc, s->P.n_bins, s->rs, s->stream, hipMemcpyDeviceToDevice));
+    HIPCHK(hipMemcpyAsync(s->fcount, p.fc, 8, hipMemcpyHostToDevice, s->stream));
+    s->step = p.step;
+    s->h.step = p.step;
+    s->h.cur = p.step & 1u;
+    RCCHK(upload_desc(s));
+    hipError_t e = frt::launch_prep_opacity(s->d_desc, s->ncell, s->fp64, s->stream);
+    if (e != hipSuccess) return fail(FRT_EDEVICE, "prep launch: %s", hipGetErrorString(e));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return FRT_OK;
+}
+
+int check_batch(frt_solve* ss, int n, const double* dts)
+{
+    if (!ss || n < 1 || !dts) return fail(FRT_EINVAL, "bad batch");
+    if (n > FRT_MAX_SOLVES_PER_LAUNCH) return fail(FRT_EINVAL, "at most %d solves per batch", FRT_MAX_SOLVES_PER_LAUNCH);
+    for (int i = 0; i < n; i++) {
+        RCCHK(ready(ss[i]));
+        if (ss[i]->P.n_bins != ss[0]->P.n_bins || ss[i]->fp64 != ss[0]->fp64)
+            return fail(FRT_EINVAL, "batched solves must share n_bins and march_precision");
+        if (ss[i]->ctx != ss[0]->ctx) return fail(FRT_EINVAL, "batched solves must share a context");
+        if ((ss[i]->P.queue_capacity == 0) != (ss[0]->P.queue_capacity == 0))
+            return fail(FRT_EINVAL, "batched solves must all use automatic queues or all fixed ones");
+        if (!(dts[i] > 0) || !std::isfinite(dts[i])) return fail(FRT_EINVAL, "dt must be finite and > 0");
+        for (int j = 0; j < i; j++)
+            if (ss[j] == ss[i]) return fail(FRT_EINVAL, "a solve appears twice in the batch");
+    }
+    return FRT_OK;
+}
+
+int check_tuning(const frt_tuning* t)
+{
+    if (!t || t->size != sizeof(frt_tuning)) return fail(FRT_EINVAL, "frt_tuning.size must be sizeof(frt_tuning)");
+    if (t->item_rays < 64 || t->item_rays > (int)FRT_ITEM_RAYS || t->item_rays % 64)
+        return fail(FRT_EINVAL, "item_rays %d must be a multiple of 64 in 64..%u", t->item_rays, FRT_ITEM_RAYS);
+    if (t->scatter_blocks_per_cu < 1 || t->scatter_blocks_per_cu > 16 || t->split_blocks_per_cu < 1 ||
+        t->split_blocks_per_cu > 16)
+        return fail(FRT_EINVAL, "workgroups per CU must be in 1..16");
+    return FRT_OK;
 }
 
 }  // namespace
@@ -939,23 +1184,124 @@ int frt_step(frt_solve s, double dt)
 
 int frt_batch_step(frt_solve* ss, int n, const double* dts)
 {
-    if (!ss || n < 1 || !dts) return fail(FRT_EINVAL, "bad batch");
-    if (n > FRT_MAX_SOLVES_PER_LAUNCH) return fail(FRT_EINVAL, "at most %d solves per batch", FRT_MAX_SOLVES_PER_LAUNCH);
-    for (int i = 0; i < n; i++) {
-        RCCHK(ready(ss[i]));
-        if (ss[i]->P.n_bins != ss[0]->P.n_bins || ss[i]->fp64 != ss[0]->fp64)
-            return fail(FRT_EINVAL, "batched solves must share n_bins and march_precision");
-        if (ss[i]->ctx != ss[0]->ctx) return fail(FRT_EINVAL, "batched solves must share a context");
-        if ((ss[i]->P.queue_capacity == 0) != (ss[0]->P.queue_capacity == 0))
-            return fail(FRT_EINVAL, "batched solves must all use automatic queues or all fixed ones");
-        if (!(dts[i] > 0) || !std::isfinite(dts[i])) return fail(FRT_EINVAL, "dt must be finite and > 0");
-        for (int j = 0; j < i; j++)
-            if (ss[j] == ss[i]) return fail(FRT_EINVAL, "a solve appears twice in the batch");
-    }
+    RCCHK(check_batch(ss, n, dts));
     HIPCHK(hipSetDevice(ss[0]->ctx->device));
     for (int i = 1; i < n; i++) HIPCHK(hipStreamSynchronize(ss[i]->stream));
     RCCHK(step_group(ss, n, dts));
     HIPCHK(hipStreamSynchronize(ss[0]->stream));
+    return FRT_OK;
+}
+
+int frt_batch_run(frt_solve* ss, int n, const double* dts, int n_steps, int use_graph)
+{
+    RCCHK(check_batch(ss, n, dts));
+    if (n_steps < 0) return fail(FRT_EINVAL, "n_steps must be >= 0");
+    if (n_steps == 0) return FRT_OK;
+    HIPCHK(hipSetDevice(ss[0]->ctx->device));
+    for (int i = 0; i < n; i++) HIPCHK(hipStreamSynchronize(ss[i]->stream));
+    if (!use_graph) {
+        for (int k = 0; k < n_steps; k++) RCCHK(step_group(ss, n, dts));
+    } else {
+        std::lock_guard<std::mutex> lock(ss[0]->ctx->mu);
+        RCCHK(run_group_graph_locked(ss, n, dts, n_steps));
+    }
+    HIPCHK(hipStreamSynchronize(ss[0]->stream));
+    return FRT_OK;
+}
+
+int frt_tuning_default(frt_tuning* t)
+{
+    if (!t) return fail(FRT_EINVAL, "null tuning");
+    t->size = sizeof(frt_tuning);
+    t->item_rays = (int)FRT_ITEM_RAYS;
+    t->scatter_blocks_per_cu = 8;
+    t->split_blocks_per_cu = 4;
+    return FRT_OK;
+}
+
+int frt_ctx_set_tuning(frt_ctx ctx, const frt_tuning* t)
+{
+    if (!ctx) return fail(FRT_EINVAL, "null context");
+    RCCHK(check_tuning(t));
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    if (t->item_rays < ctx->ws.tune.item_rays) {
+        // smaller items need a longer work list: let ensure_ws size it again
+        dev_free(ctx->ws.work);
+        ctx->ws.cap_work = 0;
+    }
+    ctx->ws.tune = *t;
+    return FRT_OK;
+}
+
+int frt_ctx_get_tuning(frt_ctx ctx, frt_tuning* t)
+{
+    if (!ctx || !t) return fail(FRT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    *t = ctx->ws.tune;
+    return FRT_OK;
+}
+
+int frt_autotune(frt_solve* ss, int n, const double* dts, frt_tuning* best)
+{
+    RCCHK(check_batch(ss, n, dts));
+    if (!best) return fail(FRT_EINVAL, "null output");
+    frt_ctx ctx = ss[0]->ctx;
+    HIPCHK(hipSetDevice(ctx->device));
+    for (int i = 0; i < n; i++) HIPCHK(hipStreamSynchronize(ss[i]->stream));
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    std::vector<SolveSnap> snaps(n);
+    struct Release {
+        std::vector<SolveSnap>& v;
+        ~Release() { for (auto& p : v) p.release(); }
+    } rel{snaps};
+    for (int i = 0; i < n; i++) RCCHK(snap_take(ss[i], snaps[i]));
+    const frt_tuning keep = ctx->ws.tune;
+    std::vector<frt_tuning> cand;
+    for (int item : {256, 512, 1024})
+        for (int sc : {4, 8})
+            for (int sp : {2, 4}) cand.push_back(frt_tuning{sizeof(frt_tuning), item, sc, sp});
+    hipStream_t st = ss[0]->stream;
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    auto restore_all = [&]() -> int {
+        for (int i = 0; i < n; i++) RCCHK(snap_restore(ss[i], snaps[i]));
+        return FRT_OK;
+    };
+    // a first step grows the queues to this group's size
+    int rc = step_group_locked(ss, n, dts);
+    if (rc == FRT_OK) rc = restore_all();
+    float best_ms = -1.f;
+    frt_tuning pick = keep;
+    for (size_t c = 0; c < cand.size() && rc == FRT_OK; c++) {
+        ctx->ws.tune = cand[c];
+        if (cand[c].item_rays < keep.item_rays) {
+            dev_free(ctx->ws.work);
+            ctx->ws.cap_work = 0;
+        }
+        (void)hipEventRecord(a, st);
+        rc = step_group_locked(ss, n, dts);
+        (void)hipEventRecord(b, st);
+        if (rc != FRT_OK) break;
+        (void)hipEventSynchronize(b);
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, a, b);
+        if (best_ms < 0.f || ms < best_ms) {
+            best_ms = ms;
+            pick = cand[c];
+        }
+        rc = restore_all();
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    ctx->ws.tune = rc == FRT_OK ? pick : keep;
+    dev_free(ctx->ws.work);
+    ctx->ws.cap_work = 0;
+    if (rc != FRT_OK) {
+        (void)restore_all();
+        return rc;
+    }
+    *best = pick;
     return FRT_OK;
 }
 
@@ -966,7 +1312,8 @@ int frt_sync(frt_solve s)
     if (!s->L) return FRT_OK;
     FrtLedgerDev L;
     RCCHK(read_device_ledger(s, &L));
-    if (L.err_flags & FRT_DEVERR_QUEUE_OVERFLOW) return fail(FRT_EOVERFLOW, "a ray queue overflowed; raise queue_capacity");
+    if (L.err_flags & (FRT_DEVERR_QUEUE_OVERFLOW | FRT_DEVERR_CARRY_OVERFLOW))
+        return fail(FRT_EOVERFLOW, "a ray queue overflowed; raise queue_capacity");
     if (L.err_flags & FRT_DEVERR_UNFINISHED) return fail(FRT_EDEVICE, "a step left packets after its last pass");
     return FRT_OK;
 }

@@ -11,7 +11,8 @@
 // plus float deposits is 48 KiB of LDS; the FP64 march uses 8^3 bricks.
 constexpr int FRT_BRICK_F32 = 16;
 constexpr int FRT_BRICK_F64 = 8;
-// Packets handed to one workgroup per work item.
+// Largest number of packets handed to one workgroup per work item (the
+// launch's item size, a tunable, is at most this).
 constexpr uint32_t FRT_ITEM_RAYS = 1024;
 // Ledger accumulators are striped to keep atomics off a single address.
 constexpr int FRT_STRIPES = 64;
@@ -29,8 +30,9 @@ constexpr int FRT_QSEG_STRIDE = 32;
 
 // Error bits raised on the device and surfaced by the next sync.
 enum : uint32_t {
-    FRT_DEVERR_QUEUE_OVERFLOW = 1u << 0,
-    FRT_DEVERR_UNFINISHED = 1u << 1,
+    FRT_DEVERR_QUEUE_OVERFLOW = 1u << 0,   // a pass queue (O, P, S, work list) was too small
+    FRT_DEVERR_UNFINISHED = 1u << 1,       // packets left after the last pass (never expected)
+    FRT_DEVERR_CARRY_OVERFLOW = 1u << 2,   // a solve's carried-packet queue was too small
 };
 
 // Photon terms (double) and counters (u64) accumulated during a step.
@@ -150,6 +152,10 @@ struct FrtWS {
     int n_solves;
     int n_bins;
     int has_sub;                // some solve of the launch has sub-grid opacity
+    // launch shape (tunable)
+    uint32_t item_rays;         // packets per work item, 64..FRT_ITEM_RAYS
+    int scatter_bpc;            // workgroups per CU of the scatter pass
+    int split_bpc;              // workgroups per CU of the split pass
 };
 
 namespace frt {
@@ -161,5 +167,13 @@ hipError_t launch_finish(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
 hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
                        unsigned long long total_cells, int fp64, hipStream_t s);
 hipError_t launch_prep_opacity(FrtSolveDesc* d_desc, unsigned long long ncell, int fp64, hipStream_t s);
+// Clear the launch counters and brick histogram (a kernel, so that a step
+// captured in a HIP graph holds no memset node).
+hipError_t launch_clear(const FrtWS& ws, hipStream_t s);
+// Advance every solve's step index on the device unless the step raised an
+// error (used by steps replayed from a HIP graph).
+hipError_t launch_advance(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
+// Query launch shapes once, outside any stream capture.
+void prime_launch_shapes(int fp64, int n_bins, int has_sub);
 int device_cu_count();
 }  // namespace frt

@@ -19,6 +19,9 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <mutex>
+#include <unordered_map>
+#include <utility>
 
 namespace {
 
@@ -541,7 +544,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
 
 // ============================================================ counting scan
 // One block: offsets of each brick's packets in the sorted buffer, the work
-// list (items of at most FRT_ITEM_RAYS packets of one brick), scatter
+// list (items of at most item_rays packets of one brick), scatter
 // cursors; clears the histogram and the output counter.
 __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
 {
@@ -553,7 +556,7 @@ __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
     for (uint32_t k = k0; k < k1; k++) {
         uint32_t h = ws.hist[k];
         sum += h;
-        items += (h + FRT_ITEM_RAYS - 1) / FRT_ITEM_RAYS;
+        items += (h + ws.item_rays - 1) / ws.item_rays;
     }
     s_a[threadIdx.x] = sum;
     s_b[threadIdx.x] = items;
@@ -590,12 +593,12 @@ __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
         ws.cursor[k] = off;
         if (h) {
             const int solve = find_in_prefix(ws.key_prefix, ws.n_solves, k);
-            for (uint32_t m = 0; m * FRT_ITEM_RAYS < h; m++) {
+            for (uint32_t m = 0; m * ws.item_rays < h; m++) {
                 if (it < ws.cap_work) {
                     FrtWork w;
                     w.key = k;
-                    w.start = off + m * FRT_ITEM_RAYS;
-                    w.count = min(FRT_ITEM_RAYS, h - m * FRT_ITEM_RAYS);
+                    w.start = off + m * ws.item_rays;
+                    w.count = min(ws.item_rays, h - m * ws.item_rays);
                     w.solve = (uint32_t)solve;
                     ws.work[it] = w;
                 }
@@ -1092,7 +1095,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                     if (fat < D.F[nxt].cap) {
                         store_pkt<Real>(D.F[nxt], fat, h, brick_key(D, c) - D.key_base, T);
                     } else {
-                        raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
+                        raise_error(ws, D.L, FRT_DEVERR_CARRY_OVERFLOW);
                         atomicAdd(&s_lf[LF_LOST], v_end);
                     }
                 }
@@ -1250,6 +1253,24 @@ __global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
     }
 }
 
+// ============================================================ bookkeeping
+__global__ void k_clear(FrtWS ws)
+{
+    const uint32_t stride = gridDim.x * blockDim.x;
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < C_NCTR) ws.ctr[t] = 0;
+    for (uint32_t k = t; k < ws.nkeys; k += stride) ws.hist[k] = 0;
+}
+
+__global__ void k_advance(FrtSolveDesc* descs, FrtWS ws)
+{
+    if (ws.ctr[C_ERR] != 0) return;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ws.n_solves; i += gridDim.x * blockDim.x) {
+        descs[i].step += 1u;
+        descs[i].cur ^= 1u;
+    }
+}
+
 // =============================================================== step close
 // After the last pass: anything still queued means the pass count was too
 // small (flagged, never expected); fold the ledger stripes.
@@ -1293,7 +1314,10 @@ __global__ void k_finish(FrtSolveDesc* descs, FrtWS ws)
             }
         }
         if (threadIdx.x == 0) {
-            if (s_left) L->err_flags |= FRT_DEVERR_UNFINISHED;
+            if (s_left) {
+                L->err_flags |= FRT_DEVERR_UNFINISHED;
+                atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_UNFINISHED);
+            }
             if (ws.ctr[C_MAXP] > L->max_items) L->max_items = ws.ctr[C_MAXP];
         }
     }
@@ -1384,29 +1408,47 @@ void launch_seed_nb(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
     hipLaunchKernelGGL((k_seed<Real, NB>), dim3(cu_count() * 4), dim3(BLOCK), 0, s, d, ws);
 }
 
-// Resident workgroups per CU of a kernel (at least 1), queried once.
-template <typename K>
-int blocks_per_cu(K kernel)
+// Resident workgroups per CU of a kernel (at least 1), queried once per
+// kernel.
+int blocks_per_cu(void (*kernel)(FrtSolveDesc*, FrtWS))
 {
-    static int n = 0;
-    if (n == 0) {
-        int b = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, BLOCK, 0) != hipSuccess || b < 1) b = 1;
-        n = b;
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> known;
+    std::lock_guard<std::mutex> lock(mu);
+    const auto it = known.find((const void*)kernel);
+    if (it != known.end()) return it->second;
+    int b = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, BLOCK, 0) != hipSuccess || b < 1) b = 1;
+    known[(const void*)kernel] = b;
+    return b;
+}
+
+// The march kernel of a launch and its grid (resident workgroups on every
+// CU; the occupancy query runs on the first call).
+template <typename Real, int NB>
+std::pair<void (*)(FrtSolveDesc*, FrtWS), int> brick_kernel(const FrtWS& ws)
+{
+    void (*brick)(FrtSolveDesc*, FrtWS);
+    int bpc;
+    if constexpr (sizeof(Real) == 4 && NB <= 4) {
+        if (ws.has_sub) { brick = k_brick<Real, NB, true>; bpc = blocks_per_cu(k_brick<Real, NB, true>); }
+        else { brick = k_brick_w4<Real, NB, false>; bpc = blocks_per_cu(k_brick_w4<Real, NB, false>); }
+    } else {
+        if (ws.has_sub) { brick = k_brick<Real, NB, true>; bpc = blocks_per_cu(k_brick<Real, NB, true>); }
+        else { brick = k_brick<Real, NB, false>; bpc = blocks_per_cu(k_brick<Real, NB, false>); }
     }
-    return n;
+    return {brick, bpc};
 }
 
 template <typename Real, int NB>
 void launch_pass_nb(FrtSolveDesc* d, const FrtWS& ws, int part, hipStream_t s)
 {
-    void (*brick)(FrtSolveDesc*, FrtWS);
-    if constexpr (sizeof(Real) == 4 && NB <= 4) brick = ws.has_sub ? k_brick<Real, NB, true> : k_brick_w4<Real, NB, false>;
-    else brick = ws.has_sub ? k_brick<Real, NB, true> : k_brick<Real, NB, false>;
-    const dim3 grid(cu_count() * blocks_per_cu(brick));
+    const auto bk = brick_kernel<Real, NB>(ws);
+    void (*brick)(FrtSolveDesc*, FrtWS) = bk.first;
+    const dim3 grid(cu_count() * bk.second);
     if (part == 0) hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws);
-    else if (part == 1) hipLaunchKernelGGL((k_scatter<Real, NB>), dim3(cu_count() * 8), dim3(BLOCK), 0, s, ws);
-    else if (part == 3) hipLaunchKernelGGL((k_split<Real>), dim3(cu_count() * 4), dim3(BLOCK), 0, s, d, ws);
+    else if (part == 1) hipLaunchKernelGGL((k_scatter<Real, NB>), dim3(cu_count() * ws.scatter_bpc), dim3(BLOCK), 0, s, ws);
+    else if (part == 3) hipLaunchKernelGGL((k_split<Real>), dim3(cu_count() * ws.split_bpc), dim3(BLOCK), 0, s, d, ws);
     else hipLaunchKernelGGL(brick, grid, dim3(BLOCK), 0, s, d, ws);
 }
 
@@ -1475,6 +1517,43 @@ hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix,
     if (fp64) hipLaunchKernelGGL(k_chem<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells);
     else hipLaunchKernelGGL(k_chem<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells);
     return hipGetLastError();
+}
+
+hipError_t launch_clear(const FrtWS& ws, hipStream_t s)
+{
+    const uint32_t n = ws.nkeys > C_NCTR ? ws.nkeys : C_NCTR;
+    hipLaunchKernelGGL(k_clear, dim3(grid_for(n, 4)), dim3(BLOCK), 0, s, ws);
+    return hipGetLastError();
+}
+
+hipError_t launch_advance(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_advance, dim3(1), dim3(64), 0, s, d, ws);
+    return hipGetLastError();
+}
+
+void prime_launch_shapes(int fp64, int n_bins, int has_sub)
+{
+    (void)cu_count();
+    FrtWS w{};
+    w.n_bins = n_bins;
+    w.has_sub = has_sub;
+    auto prime = [&](auto tag) {
+        using Real = decltype(tag);
+        switch (n_bins) {
+            case 1: brick_kernel<Real, 1>(w); break;
+            case 2: brick_kernel<Real, 2>(w); break;
+            case 3: brick_kernel<Real, 3>(w); break;
+            case 4: brick_kernel<Real, 4>(w); break;
+            case 5: brick_kernel<Real, 5>(w); break;
+            case 6: brick_kernel<Real, 6>(w); break;
+            case 7: brick_kernel<Real, 7>(w); break;
+            case 8: brick_kernel<Real, 8>(w); break;
+            default: break;
+        }
+    };
+    if (fp64) prime(double{});
+    else prime(float{});
 }
 
 hipError_t launch_prep_opacity(FrtSolveDesc* d_desc, unsigned long long ncell, int fp64, hipStream_t s)

@@ -26,7 +26,8 @@ EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_
            "frt_solve_destroy", "frt_load_grid", "frt_load_sources", "frt_set_rotations", "frt_step",
            "frt_batch_step", "frt_sync", "frt_read_fields", "frt_read_ledger", "frt_save_state",
            "frt_load_state", "frt_mark", "frt_rewind", "frt_set_timing", "frt_read_timing",
-           "frt_rotation_uniforms")
+           "frt_rotation_uniforms", "frt_batch_run", "frt_tuning_default", "frt_ctx_set_tuning",
+           "frt_ctx_get_tuning", "frt_autotune")
 
 
 class FrtError(RuntimeError):
@@ -64,6 +65,14 @@ class Timing(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Tuning(C.Structure):
+    _fields_ = [("size", C.c_size_t), ("item_rays", C.c_int), ("scatter_blocks_per_cu", C.c_int),
+                ("split_blocks_per_cu", C.c_int)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
+
+
 _lib = None
 
 
@@ -97,6 +106,11 @@ def lib():
         L.frt_set_timing.argtypes = [vp, C.c_int]
         L.frt_read_timing.argtypes = [vp, C.POINTER(Timing)]
         L.frt_rotation_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_double)]
+        L.frt_batch_run.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_double), C.c_int, C.c_int]
+        L.frt_tuning_default.argtypes = [C.POINTER(Tuning)]
+        L.frt_ctx_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.frt_ctx_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
+        L.frt_autotune.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_double), C.POINTER(Tuning)]
         _lib = L
     return _lib
 
@@ -140,6 +154,24 @@ class Context:
         _check(lib().frt_ctx_create(device, C.byref(h)))
         self.h = h
         self.device = device
+
+    def tuning(self) -> dict:
+        t = Tuning()
+        t.size = C.sizeof(Tuning)
+        _check(lib().frt_ctx_get_tuning(self.h, C.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, item_rays=None, scatter_blocks_per_cu=None, split_blocks_per_cu=None):
+        t = Tuning()
+        t.size = C.sizeof(Tuning)
+        _check(lib().frt_ctx_get_tuning(self.h, C.byref(t)))
+        if item_rays is not None:
+            t.item_rays = item_rays
+        if scatter_blocks_per_cu is not None:
+            t.scatter_blocks_per_cu = scatter_blocks_per_cu
+        if split_blocks_per_cu is not None:
+            t.split_blocks_per_cu = split_blocks_per_cu
+        _check(lib().frt_ctx_set_tuning(self.h, C.byref(t)))
 
     def close(self):
         if self.h:
@@ -261,10 +293,32 @@ class Solve:
         _check(lib().frt_load_state(self.h, buf, len(blob)))
 
 
-def batch_step(solves, dts):
+def _group(solves, dts):
     arr = (C.c_void_p * len(solves))(*[s.h for s in solves])
     d = (C.c_double * len(solves))(*[float(x) for x in dts])
+    return arr, d
+
+
+def batch_step(solves, dts):
+    arr, d = _group(solves, dts)
     _check(lib().frt_batch_step(arr, len(solves), d))
+
+
+def batch_run(solves, dts, n_steps: int, graph: bool = True):
+    """n_steps steps of every solve, one captured HIP graph replayed per step
+    (graph=True) or launched step by step."""
+    arr, d = _group(solves, dts)
+    _check(lib().frt_batch_run(arr, len(solves), d, int(n_steps), 1 if graph else 0))
+
+
+def autotune(solves, dts) -> dict:
+    """Time the candidate launch shapes on one step of these solves (their
+    state is restored), set the fastest on their context and return it."""
+    arr, d = _group(solves, dts)
+    t = Tuning()
+    t.size = C.sizeof(Tuning)
+    _check(lib().frt_autotune(arr, len(solves), d, C.byref(t)))
+    return t.as_dict()
 
 
 def solve_from_problem(ctx: Context, prob, precision="f32", use_table=True, **kw) -> Solve:

@@ -79,10 +79,15 @@ def test_binding_marshals_every_call(monkeypatch):
     s = frt.solve_from_problem(ctx, p)
     s.step(p.dt_s)
     frt.batch_step([s], [p.dt_s])
+    frt.batch_run([s], [p.dt_s], 2, graph=True)
+    frt.autotune([s], [p.dt_s])
+    ctx.set_tuning(item_rays=512)
+    ctx.tuning()
     s.sync()
     s.fields()
     s.ledger()
     s.load(b"x" * 16)
     for name in ("frt_ctx_create", "frt_solve_create", "frt_load_grid", "frt_load_sources", "frt_set_rotations",
-                 "frt_step", "frt_batch_step", "frt_sync", "frt_read_fields", "frt_read_ledger", "frt_load_state"):
+                 "frt_step", "frt_batch_step", "frt_sync", "frt_read_fields", "frt_read_ledger", "frt_load_state",
+                 "frt_batch_run", "frt_autotune", "frt_ctx_set_tuning", "frt_ctx_get_tuning"):
         assert name in stub.calls, name
