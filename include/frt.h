@@ -220,6 +220,89 @@ typedef struct {
 int frt_set_timing(frt_solve s, int enable);
 int frt_read_timing(frt_solve s, frt_timing* out);   /* synchronizes */
 
+/* ------------------------------------------------------------- serving
+ * A server admits solves as they arrive and steps every admitted solve
+ * together (one batched step per tick over all solves in flight, grouped by
+ * n_bins and march_precision), so that requests arriving while others run
+ * join the next tick: continuous batching.  A request is admitted, in
+ * arrival order, when a slot is free and its estimated device bytes
+ * (frt_request_bytes) fit in what the budget has left; its grid, packets and
+ * ledger then stay resident until its last step, after which its results
+ * are copied to host memory and its device memory is released.  One worker
+ * thread per server drives the device; submit, poll, wait and take may be
+ * called from any thread. */
+typedef struct frt_server_s* frt_server;
+
+typedef struct {
+    size_t size;                    /* sizeof(frt_request) */
+    frt_params params;              /* as for frt_solve_create */
+    int nx, ny, nz;                 /* grid, as for frt_load_grid */
+    double box_cm;
+    const float* n_H;               /* [ncell], required */
+    const float* T;                 /* [ncell] or NULL */
+    const float* kappa_sub;         /* [ncell] or NULL */
+    const double* x_HI0;            /* [ncell] or NULL */
+    int n_src;                      /* sources, as for frt_load_sources */
+    const double* pos_cm;           /* [n_src][3] */
+    const double* ndot_bins;        /* [n_src][n_bins] */
+    int rotation_steps;             /* optional table of rotation uniforms, as for */
+    const double* rotation_uniforms;/* frt_set_rotations (0 / NULL: the generator) */
+    int n_steps;                    /* steps to run, >= 0 */
+    double dt_s;                    /* step length, > 0 */
+    int ptr_kind;                   /* FRT_HOST or FRT_DEVICE for every array above */
+} frt_request;
+
+#define FRT_REQ_QUEUED 0
+#define FRT_REQ_RUNNING 1
+#define FRT_REQ_DONE 2
+#define FRT_REQ_FAILED 3
+
+/* Device bytes a request holds while admitted: its resident fields
+ * (36 bytes per cell in FP32, 52 in FP64), its carried-packet queues, its
+ * sources and rotations, and its share of the pass queues at their first
+ * size.  Host-side arithmetic only; the same estimate the server admits by. */
+int frt_request_bytes(const frt_request* req, size_t* bytes);
+
+/* hbm_budget_bytes: device bytes the admitted requests may hold together
+ * (a request larger than the budget fails at admission); max_slots: most
+ * requests in flight, 1..1024.  The server owns a HIP stream on ctx's
+ * device and uses ctx's pass queues, which grow as the batches need. */
+int frt_server_create(frt_ctx ctx, size_t hbm_budget_bytes, int max_slots, frt_server* out);
+
+/* Copy the request's inputs (validated as by frt_load_grid and
+ * frt_load_sources) and queue it; *req_id identifies it.  Non-blocking. */
+int frt_server_submit(frt_server srv, const frt_request* req, uint64_t* req_id);
+
+/* *state = FRT_REQ_QUEUED, _RUNNING, _DONE or _FAILED. */
+int frt_server_poll(frt_server srv, uint64_t req_id, int* state);
+
+/* Wait until the request is done or failed, or timeout_s seconds passed
+ * (timeout_s < 0: no limit); *state as for frt_server_poll. */
+int frt_server_wait(frt_server srv, uint64_t req_id, double timeout_s, int* state);
+
+/* Results of a finished request: x_HI [ncell] (host, may be NULL) and its
+ * ledger (may be NULL); the request is then forgotten.  A failed request
+ * returns its error code and message; an unfinished one FRT_ESTATE. */
+int frt_server_take(frt_server srv, uint64_t req_id, double* x_HI, frt_ledger* ledger);
+
+/* Seconds since the server's creation at which the request was submitted,
+ * admitted and finished (t[2] = -1 while unfinished). */
+int frt_server_times(frt_server srv, uint64_t req_id, double t[3]);
+
+typedef struct {
+    uint64_t submitted, completed, failed;
+    uint64_t ticks;                 /* batched steps run */
+    uint64_t solve_steps;           /* request steps run (sum over ticks of solves stepped) */
+    uint32_t max_in_flight;         /* most requests admitted at once */
+    uint64_t bytes_in_use, peak_bytes;
+} frt_server_stats;
+
+int frt_server_get_stats(frt_server srv, frt_server_stats* out);
+
+/* Stop the worker (requests still queued or running are dropped) and free
+ * everything the server holds. */
+int frt_server_destroy(frt_server srv);
+
 /* Rotation uniforms the library would use for (step, src) — the same
  * counter-based generator the device runs — for checking a table against. */
 int frt_rotation_uniforms(uint64_t seed, uint32_t step, uint32_t src, double out[3]);

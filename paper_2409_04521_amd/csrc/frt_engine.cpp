@@ -870,6 +870,36 @@ int check_tuning(const frt_tuning* t)
 
 }  // namespace
 
+namespace frt {
+
+int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+int ctx_device(frt_ctx ctx) { return ctx->device; }
+
+uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T, uint64_t* pass_records)
+{
+    const uint64_t rs = P.march_precision == FRT_F64 ? 8 : 4;
+    const uint64_t rec = rec_bytes(rs);
+    const uint64_t cast = (uint64_t)n_src * (12ull << (2 * P.base_level));
+    // resident fields: opacity pair, two rate buffers, x_HI, n_H, T
+    uint64_t b = ncell * (4 * rs + 16 + (with_T ? 4 : 0));
+    // carried-packet queues (as first sized)
+    double F = (double)cast + 1024;
+    if (std::isfinite(P.c_ray_cm_s)) F += std::min((double)ncell, 8.0 * cast + 65536.0);
+    if (P.queue_capacity) F = (double)P.queue_capacity;
+    b += 2 * (uint64_t)F * rec;
+    // sources, photon rates, 64 steps of rotations, ledgers
+    b += (uint64_t)n_src * (24 + 12 * (uint64_t)P.n_bins) + 64ull * n_src * 32 + 2 * sizeof(FrtLedgerDev);
+    // share of the pass queues: O and P, S at half size with its photons, work list
+    const uint64_t wp = P.queue_capacity ? P.queue_capacity
+                                         : (P.queue_hint ? P.queue_hint : std::max<uint64_t>(4 * cast + 65536, ncell / 2));
+    if (pass_records) *pass_records = wp;
+    b += wp * (2 * rec + rec / 2 + 4) + wp / 64 * sizeof(FrtWork);
+    return b;
+}
+
+}  // namespace frt
+
 // =====================================================================  ABI
 extern "C" {
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <cstdint>
 
+#include "frt.h"
+
 #define FRT_MAX_BINS_I 8
 #define FRT_MAX_SOLVES_PER_LAUNCH 1024
 
@@ -176,4 +178,11 @@ hipError_t launch_advance(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
 // Query launch shapes once, outside any stream capture.
 void prime_launch_shapes(int fp64, int n_bins, int has_sub);
 int device_cu_count();
+// Set the calling thread's error message (returned by frt_last_error) and
+// return code; for the serving layer, which sits above the ABI.
+int set_error(int code, const char* msg);
+int ctx_device(frt_ctx ctx);
+// Device bytes a solve with these parameters and sizes holds, and the first
+// pass-queue size it asks for (records).
+uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T, uint64_t* pass_records);
 }  // namespace frt

@@ -1,0 +1,404 @@
+// Serving layer of the ray-tracing library (include/frt.h, "serving"):
+// requests arrive with their inputs, wait in arrival order until a slot
+// and enough of the device-memory budget are free, are loaded as solves and
+// then advance one step per tick together with every other admitted solve
+// (one batched step per tick and per n_bins/precision group).  A finished
+// request's x_HI and ledger are copied to host memory and its solve is
+// destroyed, which frees its share of the budget for the next arrivals.
+// The layer uses only the public C ABI of the library.
+#include "frt.h"
+#include "frt_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+    uint64_t id = 0;
+    int state = FRT_REQ_QUEUED;
+    int err = FRT_OK;
+    std::string msg;
+    frt_params params{};
+    int nx = 0, ny = 0, nz = 0, n_src = 0, rot_steps = 0, n_steps = 0;
+    double box_cm = 0.0, dt = 0.0;
+    std::vector<float> nH, T, kappa;
+    std::vector<double> x0, pos, ndot, rot;
+    size_t bytes = 0;
+    frt_solve solve = nullptr;
+    int steps_done = 0;
+    std::vector<double> x_out;
+    frt_ledger led{};
+    double t_submit = 0.0, t_start = -1.0, t_done = -1.0;
+
+    void free_inputs()
+    {
+        std::vector<float>().swap(nH);
+        std::vector<float>().swap(T);
+        std::vector<float>().swap(kappa);
+        std::vector<double>().swap(x0);
+        std::vector<double>().swap(pos);
+        std::vector<double>().swap(ndot);
+        std::vector<double>().swap(rot);
+    }
+};
+
+template <typename T>
+int copy_in(const T* p, size_t n, int kind, std::vector<T>& out)
+{
+    out.resize(n);
+    if (!n) return FRT_OK;
+    if (kind == FRT_HOST) {
+        std::memcpy(out.data(), p, n * sizeof(T));
+        return FRT_OK;
+    }
+    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(out.data(), p, n * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess)
+        return frt::set_error(FRT_EDEVICE, "copying a request's device input failed");
+    return FRT_OK;
+}
+
+int validate(const frt_request* r)
+{
+    if (!r || r->size != sizeof(frt_request)) return frt::set_error(FRT_EINVAL, "frt_request.size must be sizeof(frt_request)");
+    if (r->params.size != sizeof(frt_params)) return frt::set_error(FRT_EINVAL, "frt_request.params.size must be sizeof(frt_params)");
+    if (r->nx < 1 || r->ny < 1 || r->nz < 1 || r->nx > 2048 || r->ny > 2048 || r->nz > 2048)
+        return frt::set_error(FRT_EINVAL, "request grid outside 1..2048 per axis");
+    if (!r->n_H) return frt::set_error(FRT_EINVAL, "request without n_H");
+    if (r->n_src < 0 || (r->n_src > 0 && (!r->pos_cm || !r->ndot_bins)))
+        return frt::set_error(FRT_EINVAL, "request sources incomplete");
+    if (r->n_steps < 0 || !(r->dt_s > 0) || !std::isfinite(r->dt_s))
+        return frt::set_error(FRT_EINVAL, "request needs n_steps >= 0 and a finite dt_s > 0");
+    if (r->params.n_bins < 1 || r->params.n_bins > FRT_MAX_BINS) return frt::set_error(FRT_EINVAL, "request n_bins outside 1..8");
+    if (r->ptr_kind != FRT_HOST && r->ptr_kind != FRT_DEVICE) return frt::set_error(FRT_EINVAL, "bad ptr_kind");
+    if (r->rotation_steps < 0 || (r->rotation_steps > 0 && !r->rotation_uniforms))
+        return frt::set_error(FRT_EINVAL, "rotation table incomplete");
+    return FRT_OK;
+}
+
+double seconds_since(Clock::time_point t0) { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+
+}  // namespace
+
+struct frt_server_s {
+    frt_ctx ctx = nullptr;
+    int device = 0;
+    size_t budget = 0;
+    int max_slots = 1;
+    hipStream_t stream = nullptr;
+    Clock::time_point t0;
+    std::mutex mu;
+    std::condition_variable cv;       // worker: work arrived or stop
+    std::condition_variable done_cv;  // waiters: a request finished
+    std::deque<Req*> queue;
+    std::unordered_map<uint64_t, std::unique_ptr<Req>> all;
+    std::vector<Req*> active;         // worker thread only
+    uint64_t next_id = 1;
+    bool stop = false;
+    frt_server_stats st{};
+    std::thread worker;
+
+    void finish(Req* r, int state)
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        r->state = state;
+        r->t_done = seconds_since(t0);
+        st.bytes_in_use -= r->bytes;
+        if (state == FRT_REQ_DONE) st.completed++;
+        else st.failed++;
+        done_cv.notify_all();
+    }
+
+    void fail_req(Req* r, int code)
+    {
+        r->err = code;
+        r->msg = frt_last_error();
+        if (r->solve) {
+            frt_solve_destroy(r->solve);
+            r->solve = nullptr;
+        }
+        r->free_inputs();
+        finish(r, FRT_REQ_FAILED);
+    }
+
+    int load(Req* r)
+    {
+        int rc;
+        if ((rc = frt_solve_create(ctx, &r->params, stream, &r->solve))) return rc;
+        if ((rc = frt_load_grid(r->solve, r->nx, r->ny, r->nz, r->box_cm, r->nH.data(), r->T.empty() ? nullptr : r->T.data(),
+                                r->kappa.empty() ? nullptr : r->kappa.data(), r->x0.empty() ? nullptr : r->x0.data(),
+                                FRT_HOST)))
+            return rc;
+        if ((rc = frt_load_sources(r->solve, r->n_src, r->pos.data(), r->ndot.data(), FRT_HOST))) return rc;
+        if (r->rot_steps > 0 && (rc = frt_set_rotations(r->solve, r->rot_steps, r->rot.data()))) return rc;
+        return FRT_OK;
+    }
+
+    void complete(Req* r)
+    {
+        const size_t ncell = (size_t)r->nx * r->ny * r->nz;
+        r->x_out.resize(ncell);
+        int rc = frt_read_fields(r->solve, r->x_out.data(), nullptr, FRT_HOST);
+        if (rc == FRT_OK) rc = frt_read_ledger(r->solve, &r->led);
+        if (rc != FRT_OK) {
+            fail_req(r, rc);
+            return;
+        }
+        frt_solve_destroy(r->solve);
+        r->solve = nullptr;
+        r->free_inputs();
+        finish(r, FRT_REQ_DONE);
+    }
+
+    void run()
+    {
+        (void)hipSetDevice(device);
+        for (;;) {
+            std::vector<Req*> admit;
+            {
+                std::unique_lock<std::mutex> lock(mu);
+                cv.wait(lock, [&] { return stop || !queue.empty() || !active.empty(); });
+                if (stop) break;
+                // admission in arrival order: a slot and the request's bytes
+                while (!queue.empty() && (int)(active.size() + admit.size()) < max_slots) {
+                    Req* r = queue.front();
+                    if (r->bytes > budget) {
+                        queue.pop_front();
+                        r->err = FRT_ENOMEM;
+                        r->msg = "request needs more device memory than the server's whole budget";
+                        r->state = FRT_REQ_FAILED;
+                        r->t_done = seconds_since(t0);
+                        r->free_inputs();
+                        st.failed++;
+                        done_cv.notify_all();
+                        continue;
+                    }
+                    if (st.bytes_in_use + r->bytes > budget) break;
+                    queue.pop_front();
+                    st.bytes_in_use += r->bytes;
+                    st.peak_bytes = std::max(st.peak_bytes, st.bytes_in_use);
+                    r->state = FRT_REQ_RUNNING;
+                    r->t_start = seconds_since(t0);
+                    admit.push_back(r);
+                }
+            }
+            for (Req* r : admit) {
+                const int rc = load(r);
+                if (rc != FRT_OK) {
+                    fail_req(r, rc);
+                    continue;
+                }
+                r->free_inputs();
+                if (r->n_steps == 0) complete(r);
+                else active.push_back(r);
+            }
+            {
+                std::lock_guard<std::mutex> lock(mu);
+                st.max_in_flight = std::max<uint32_t>(st.max_in_flight, (uint32_t)active.size());
+            }
+            if (active.empty()) continue;
+            // one tick: a batched step per (n_bins, precision) group
+            std::map<std::pair<int, int>, std::vector<Req*>> groups;
+            for (Req* r : active) groups[{r->params.n_bins, r->params.march_precision}].push_back(r);
+            for (auto& kv : groups) {
+                std::vector<Req*>& g = kv.second;
+                for (size_t at = 0; at < g.size(); at += FRT_MAX_SOLVES_PER_LAUNCH) {
+                    const size_t n = std::min<size_t>(FRT_MAX_SOLVES_PER_LAUNCH, g.size() - at);
+                    std::vector<frt_solve> ss(n);
+                    std::vector<double> dts(n);
+                    for (size_t i = 0; i < n; i++) {
+                        ss[i] = g[at + i]->solve;
+                        dts[i] = g[at + i]->dt;
+                    }
+                    const int rc = frt_batch_step(ss.data(), (int)n, dts.data());
+                    for (size_t i = 0; i < n; i++) {
+                        Req* r = g[at + i];
+                        if (rc != FRT_OK) fail_req(r, rc);
+                        else r->steps_done++;
+                    }
+                    std::lock_guard<std::mutex> lock(mu);
+                    st.ticks++;
+                    if (rc == FRT_OK) st.solve_steps += n;
+                }
+            }
+            std::vector<Req*> still;
+            for (Req* r : active) {
+                if (r->state == FRT_REQ_FAILED) continue;
+                if (r->steps_done >= r->n_steps) complete(r);
+                else still.push_back(r);
+            }
+            active.swap(still);
+        }
+        for (Req* r : active)
+            if (r->solve) {
+                frt_solve_destroy(r->solve);
+                r->solve = nullptr;
+            }
+        active.clear();
+    }
+};
+
+extern "C" {
+
+int frt_request_bytes(const frt_request* req, size_t* bytes)
+{
+    if (!bytes) return frt::set_error(FRT_EINVAL, "null output");
+    int rc = validate(req);
+    if (rc) return rc;
+    const uint64_t ncell = (uint64_t)req->nx * req->ny * req->nz;
+    *bytes = (size_t)frt::solve_bytes(req->params, ncell, req->n_src, req->T != nullptr, nullptr);
+    return FRT_OK;
+}
+
+int frt_server_create(frt_ctx ctx, size_t hbm_budget_bytes, int max_slots, frt_server* out)
+{
+    if (!ctx || !out) return frt::set_error(FRT_EINVAL, "null argument");
+    if (max_slots < 1 || max_slots > FRT_MAX_SOLVES_PER_LAUNCH) return frt::set_error(FRT_EINVAL, "max_slots outside 1..1024");
+    if (hbm_budget_bytes == 0) return frt::set_error(FRT_EINVAL, "zero memory budget");
+    const int dev = frt::ctx_device(ctx);
+    if (hipSetDevice(dev) != hipSuccess) return frt::set_error(FRT_EDEVICE, "cannot select the context's device");
+    std::unique_ptr<frt_server_s> s(new frt_server_s());
+    s->ctx = ctx;
+    s->device = dev;
+    s->budget = hbm_budget_bytes;
+    s->max_slots = max_slots;
+    s->t0 = Clock::now();
+    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
+        return frt::set_error(FRT_EDEVICE, "server stream");
+    frt_server_s* raw = s.get();
+    s->worker = std::thread([raw] { raw->run(); });
+    *out = s.release();
+    return FRT_OK;
+}
+
+int frt_server_submit(frt_server srv, const frt_request* req, uint64_t* req_id)
+{
+    if (!srv || !req_id) return frt::set_error(FRT_EINVAL, "null argument");
+    int rc = validate(req);
+    if (rc) return rc;
+    std::unique_ptr<Req> r(new Req());
+    r->params = req->params;
+    r->nx = req->nx;
+    r->ny = req->ny;
+    r->nz = req->nz;
+    r->box_cm = req->box_cm;
+    r->n_src = req->n_src;
+    r->n_steps = req->n_steps;
+    r->dt = req->dt_s;
+    r->rot_steps = req->rotation_steps;
+    const size_t ncell = (size_t)req->nx * req->ny * req->nz;
+    const size_t nb = (size_t)req->params.n_bins;
+    if ((rc = copy_in(req->n_H, ncell, req->ptr_kind, r->nH))) return rc;
+    if (req->T && (rc = copy_in(req->T, ncell, req->ptr_kind, r->T))) return rc;
+    if (req->kappa_sub && (rc = copy_in(req->kappa_sub, ncell, req->ptr_kind, r->kappa))) return rc;
+    if (req->x_HI0 && (rc = copy_in(req->x_HI0, ncell, req->ptr_kind, r->x0))) return rc;
+    if ((rc = copy_in(req->pos_cm, (size_t)req->n_src * 3, req->ptr_kind, r->pos))) return rc;
+    if ((rc = copy_in(req->ndot_bins, (size_t)req->n_src * nb, req->ptr_kind, r->ndot))) return rc;
+    if (req->rotation_steps > 0 &&
+        (rc = copy_in(req->rotation_uniforms, (size_t)req->rotation_steps * req->n_src * 3, req->ptr_kind, r->rot)))
+        return rc;
+    r->bytes = (size_t)frt::solve_bytes(req->params, ncell, req->n_src, req->T != nullptr, nullptr);
+    std::lock_guard<std::mutex> lock(srv->mu);
+    r->id = srv->next_id++;
+    r->t_submit = seconds_since(srv->t0);
+    *req_id = r->id;
+    srv->queue.push_back(r.get());
+    srv->all[r->id] = std::move(r);
+    srv->st.submitted++;
+    srv->cv.notify_all();
+    return FRT_OK;
+}
+
+int frt_server_poll(frt_server srv, uint64_t req_id, int* state)
+{
+    if (!srv || !state) return frt::set_error(FRT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lock(srv->mu);
+    auto it = srv->all.find(req_id);
+    if (it == srv->all.end()) return frt::set_error(FRT_EINVAL, "unknown request");
+    *state = it->second->state;
+    return FRT_OK;
+}
+
+int frt_server_wait(frt_server srv, uint64_t req_id, double timeout_s, int* state)
+{
+    if (!srv || !state) return frt::set_error(FRT_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lock(srv->mu);
+    auto it = srv->all.find(req_id);
+    if (it == srv->all.end()) return frt::set_error(FRT_EINVAL, "unknown request");
+    Req* r = it->second.get();
+    auto done = [&] { return r->state == FRT_REQ_DONE || r->state == FRT_REQ_FAILED; };
+    if (timeout_s < 0) srv->done_cv.wait(lock, done);
+    else srv->done_cv.wait_for(lock, std::chrono::duration<double>(timeout_s), done);
+    *state = r->state;
+    return FRT_OK;
+}
+
+int frt_server_take(frt_server srv, uint64_t req_id, double* x_HI, frt_ledger* ledger)
+{
+    if (!srv) return frt::set_error(FRT_EINVAL, "null server");
+    std::lock_guard<std::mutex> lock(srv->mu);
+    auto it = srv->all.find(req_id);
+    if (it == srv->all.end()) return frt::set_error(FRT_EINVAL, "unknown request");
+    Req* r = it->second.get();
+    if (r->state == FRT_REQ_FAILED) {
+        const int code = r->err ? r->err : FRT_EDEVICE;
+        const std::string msg = r->msg;
+        srv->all.erase(it);
+        return frt::set_error(code, msg.c_str());
+    }
+    if (r->state != FRT_REQ_DONE) return frt::set_error(FRT_ESTATE, "request not finished");
+    if (x_HI) std::memcpy(x_HI, r->x_out.data(), r->x_out.size() * sizeof(double));
+    if (ledger) *ledger = r->led;
+    srv->all.erase(it);
+    return FRT_OK;
+}
+
+int frt_server_times(frt_server srv, uint64_t req_id, double t[3])
+{
+    if (!srv || !t) return frt::set_error(FRT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lock(srv->mu);
+    auto it = srv->all.find(req_id);
+    if (it == srv->all.end()) return frt::set_error(FRT_EINVAL, "unknown request");
+    t[0] = it->second->t_submit;
+    t[1] = it->second->t_start;
+    t[2] = it->second->t_done;
+    return FRT_OK;
+}
+
+int frt_server_get_stats(frt_server srv, frt_server_stats* out)
+{
+    if (!srv || !out) return frt::set_error(FRT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lock(srv->mu);
+    *out = srv->st;
+    return FRT_OK;
+}
+
+int frt_server_destroy(frt_server srv)
+{
+    if (!srv) return FRT_OK;
+    {
+        std::lock_guard<std::mutex> lock(srv->mu);
+        srv->stop = true;
+        srv->cv.notify_all();
+    }
+    if (srv->worker.joinable()) srv->worker.join();
+    if (srv->stream) (void)hipStreamDestroy(srv->stream);
+    delete srv;
+    return FRT_OK;
+}
+
+}  // extern "C"

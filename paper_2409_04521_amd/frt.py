@@ -27,7 +27,10 @@ EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_
            "frt_batch_step", "frt_sync", "frt_read_fields", "frt_read_ledger", "frt_save_state",
            "frt_load_state", "frt_mark", "frt_rewind", "frt_set_timing", "frt_read_timing",
            "frt_rotation_uniforms", "frt_batch_run", "frt_tuning_default", "frt_ctx_set_tuning",
-           "frt_ctx_get_tuning", "frt_autotune")
+           "frt_ctx_get_tuning", "frt_autotune", "frt_request_bytes", "frt_server_create", "frt_server_submit",
+           "frt_server_poll", "frt_server_wait", "frt_server_take", "frt_server_times", "frt_server_get_stats",
+           "frt_server_destroy")
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
 class FrtError(RuntimeError):
@@ -73,6 +76,23 @@ class Tuning(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
 
 
+class Request(C.Structure):
+    _fields_ = [("size", C.c_size_t), ("params", Params), ("nx", C.c_int), ("ny", C.c_int), ("nz", C.c_int),
+                ("box_cm", C.c_double), ("n_H", C.c_void_p), ("T", C.c_void_p), ("kappa_sub", C.c_void_p),
+                ("x_HI0", C.c_void_p), ("n_src", C.c_int), ("pos_cm", C.c_void_p), ("ndot_bins", C.c_void_p),
+                ("rotation_steps", C.c_int), ("rotation_uniforms", C.c_void_p), ("n_steps", C.c_int),
+                ("dt_s", C.c_double), ("ptr_kind", C.c_int)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_uint64), ("completed", C.c_uint64), ("failed", C.c_uint64),
+                ("ticks", C.c_uint64), ("solve_steps", C.c_uint64), ("max_in_flight", C.c_uint32),
+                ("bytes_in_use", C.c_uint64), ("peak_bytes", C.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 _lib = None
 
 
@@ -111,6 +131,15 @@ def lib():
         L.frt_ctx_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.frt_ctx_get_tuning.argtypes = [vp, C.POINTER(Tuning)]
         L.frt_autotune.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_double), C.POINTER(Tuning)]
+        L.frt_request_bytes.argtypes = [C.POINTER(Request), C.POINTER(C.c_size_t)]
+        L.frt_server_create.argtypes = [vp, C.c_size_t, C.c_int, C.POINTER(vp)]
+        L.frt_server_submit.argtypes = [vp, C.POINTER(Request), C.POINTER(C.c_uint64)]
+        L.frt_server_poll.argtypes = [vp, C.c_uint64, C.POINTER(C.c_int)]
+        L.frt_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(C.c_int)]
+        L.frt_server_take.argtypes = [vp, C.c_uint64, vp, C.POINTER(Ledger)]
+        L.frt_server_times.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double)]
+        L.frt_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+        L.frt_server_destroy.argtypes = [vp]
         _lib = L
     return _lib
 
@@ -319,6 +348,127 @@ def autotune(solves, dts) -> dict:
     t.size = C.sizeof(Tuning)
     _check(lib().frt_autotune(arr, len(solves), d, C.byref(t)))
     return t.as_dict()
+
+
+def _params_for(prob, precision="f32", **kw) -> Params:
+    p = params_default()
+    sig = list(prob.sigma_bins)
+    p.n_bins = len(sig)
+    for i, v in enumerate(sig):
+        p.sigma_bins[i] = v
+    p.alpha_B, p.coll_ion = prob.alpha_B, prob.coll_ion
+    p.base_level, p.max_level, p.n_ray_min = prob.base_level, prob.max_level, prob.n_ray_min
+    p.flux_floor, p.max_distance_cm = prob.flux_floor, prob.max_dist_cm
+    p.c_ray_cm_s = prob.c_ray if prob.c_ray is not None else math.inf
+    p.march_precision = FRT_F64 if precision == "f64" else FRT_F32
+    p.seed = prob.seed
+    p.queue_capacity = kw.get("queue_capacity", 0)
+    p.queue_hint = kw.get("queue_hint", 0)
+    return p
+
+
+def request_from_problem(prob, n_steps: int, precision="f32", use_table=True, **kw):
+    """(frt_request, keepalive) for a workloads.Problem: host arrays, the
+    problem's parameters and, with use_table, its rotation uniforms."""
+    import numpy as np
+    r = Request()
+    r.size = C.sizeof(Request)
+    r.params = _params_for(prob, precision, **kw)
+    nz, ny, nx = prob.shape
+    r.nx, r.ny, r.nz = nx, ny, nz
+    r.box_cm = prob.dx_cm * nx
+    keep = []
+
+    def host(a, dt):
+        if a is None:
+            return None
+        a = np.ascontiguousarray(a, dtype=dt)
+        keep.append(a)
+        return a.ctypes.data
+
+    r.n_H = host(prob.n_H, np.float32)
+    r.T = host(prob.T, np.float32)
+    r.kappa_sub = host(prob.kappa, np.float32)
+    r.x_HI0 = host(prob.x_HI0, np.float64)
+    r.n_src = prob.n_src
+    r.pos_cm = host(prob.src_pos_cm, np.float64)
+    r.ndot_bins = host(prob.ndot_bins, np.float64)
+    if use_table and prob.n_src > 0 and n_steps > 0:
+        from .workloads import rotation_table
+        r.rotation_steps = n_steps
+        r.rotation_uniforms = host(rotation_table(prob.seed, 0, n_steps, prob.n_src), np.float64)
+    r.n_steps = n_steps
+    r.dt_s = prob.dt_s
+    r.ptr_kind = FRT_HOST
+    return r, keep
+
+
+def request_bytes(prob, n_steps: int, **kw) -> int:
+    r, keep = request_from_problem(prob, n_steps, **kw)
+    b = C.c_size_t()
+    _check(lib().frt_request_bytes(C.byref(r), C.byref(b)))
+    return b.value
+
+
+class Server:
+    """Continuous-batching server (frt_server): admits solves by memory
+    budget and slots, steps every admitted solve once per tick."""
+
+    def __init__(self, ctx: Context, budget_bytes: int, max_slots: int = 64):
+        h = C.c_void_p()
+        _check(lib().frt_server_create(ctx.h, int(budget_bytes), int(max_slots), C.byref(h)))
+        self.h = h
+        self.open = True
+        self.ctx = ctx
+        self.shapes = {}
+
+    def submit(self, prob, n_steps: int, **kw) -> int:
+        r, keep = request_from_problem(prob, n_steps, **kw)
+        rid = C.c_uint64()
+        _check(lib().frt_server_submit(self.h, C.byref(r), C.byref(rid)))
+        self.shapes[rid.value] = prob.shape
+        return rid.value
+
+    def poll(self, rid: int) -> int:
+        st = C.c_int()
+        _check(lib().frt_server_poll(self.h, rid, C.byref(st)))
+        return st.value
+
+    def wait(self, rid: int, timeout_s: float = -1.0) -> int:
+        st = C.c_int()
+        _check(lib().frt_server_wait(self.h, rid, float(timeout_s), C.byref(st)))
+        return st.value
+
+    def take(self, rid: int):
+        """(x_HI, ledger dict) of a finished request."""
+        import numpy as np
+        x = np.empty(self.shapes[rid], dtype=np.float64)
+        L = Ledger()
+        _check(lib().frt_server_take(self.h, rid, x.ctypes.data, C.byref(L)))
+        self.shapes.pop(rid, None)
+        return x, L.as_dict()
+
+    def times(self, rid: int):
+        t = (C.c_double * 3)()
+        _check(lib().frt_server_times(self.h, rid, t))
+        return tuple(t)
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(lib().frt_server_get_stats(self.h, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "open", False):
+            lib().frt_server_destroy(self.h)
+            self.open = False
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def solve_from_problem(ctx: Context, prob, precision="f32", use_table=True, **kw) -> Solve:

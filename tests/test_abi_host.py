@@ -83,11 +83,56 @@ def test_binding_marshals_every_call(monkeypatch):
     frt.autotune([s], [p.dt_s])
     ctx.set_tuning(item_rays=512)
     ctx.tuning()
+    srv = frt.Server(ctx, 1 << 30, 4)
+    rid = srv.submit(p, 2)
+    srv.poll(rid)
+    srv.wait(rid, 1.0)
+    srv.take(rid)
+    srv.times(rid)
+    srv.stats()
+    srv.close()
     s.sync()
     s.fields()
     s.ledger()
     s.load(b"x" * 16)
     for name in ("frt_ctx_create", "frt_solve_create", "frt_load_grid", "frt_load_sources", "frt_set_rotations",
                  "frt_step", "frt_batch_step", "frt_sync", "frt_read_fields", "frt_read_ledger", "frt_load_state",
-                 "frt_batch_run", "frt_autotune", "frt_ctx_set_tuning", "frt_ctx_get_tuning"):
+                 "frt_batch_run", "frt_autotune", "frt_ctx_set_tuning", "frt_ctx_get_tuning",
+                 "frt_server_create", "frt_server_submit", "frt_server_poll", "frt_server_wait", "frt_server_take",
+                 "frt_server_times", "frt_server_get_stats", "frt_server_destroy"):
         assert name in stub.calls, name
+
+
+def _request(n=8, n_src=3, steps=2):
+    p = W.lognormal_c2(n=n, n_src=n_src, n_steps=steps, box_cmpc_h=1.25 * n / 8)
+    return p, frt.request_from_problem(p, steps)
+
+
+def test_request_bytes_is_host_arithmetic_and_grows_with_the_problem():
+    # no device needed: the estimate the server admits by
+    p, (r, keep) = _request(8, 3)
+    b = C.c_size_t()
+    assert frt.lib().frt_request_bytes(C.byref(r), C.byref(b)) == frt.FRT_OK
+    small = b.value
+    ncell = 8 ** 3
+    # resident fields alone are 36 bytes per cell (FP32 march, no T)
+    assert small > 36 * ncell
+    _, (r2, keep2) = _request(16, 3)
+    assert frt.lib().frt_request_bytes(C.byref(r2), C.byref(b)) == frt.FRT_OK
+    assert b.value > small
+    _, (r3, keep3) = _request(8, 30)
+    assert frt.lib().frt_request_bytes(C.byref(r3), C.byref(b)) == frt.FRT_OK
+    assert b.value > small
+
+
+def test_request_validation_errors():
+    p, (r, keep) = _request()
+    b = C.c_size_t()
+    r.size = 3
+    assert frt.lib().frt_request_bytes(C.byref(r), C.byref(b)) == frt.FRT_EINVAL
+    r.size = C.sizeof(frt.Request)
+    r.n_steps = -1
+    assert frt.lib().frt_request_bytes(C.byref(r), C.byref(b)) == frt.FRT_EINVAL
+    r.n_steps = 2
+    r.nx = 0
+    assert frt.lib().frt_request_bytes(C.byref(r), C.byref(b)) == frt.FRT_EINVAL
