@@ -109,6 +109,129 @@ def cpu_baseline(prob, n_sample: int, threads: int):
                       f"{cross} crossings in {dt:.1f} s (FP64 C oracle, OpenMP)"}
 
 
+def batched_leg(frt, W, n_boxes: int, steps: int, warmup: int, stream):
+    """The uneven-box batch: the same boxes stepped one solve at a time
+    (the plain per-solve path) and as one batch replayed from a HIP graph
+    with the autotuned launch shape.  Returns whole-run crossings/s of both
+    and the largest x_HI difference between them."""
+    import numpy as np
+    import torch
+
+    boxes = W.batch_c4(n_boxes=n_boxes, n_steps=warmup + steps)
+    dts = [b.dt_s for b in boxes]
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    ctx = frt.Context(0)
+    plain = [frt.solve_from_problem(ctx, b, stream=stream.cuda_stream) for b in boxes]
+    for s, dt in zip(plain, dts):
+        for _ in range(warmup):
+            s.step(dt)
+    c0 = sum(s.ledger()["crossings"] for s in plain)
+
+    def run_plain():
+        for s, dt in zip(plain, dts):
+            for _ in range(steps):
+                s.step(dt)
+            s.sync()
+    t_plain = timed(run_plain)
+    c_plain = sum(s.ledger()["crossings"] for s in plain) - c0
+    x_plain = [s.fields()[0] for s in plain]
+    for s in plain:
+        s.close()
+    del plain
+
+    ctx_b = frt.Context(0)
+    batch = [frt.solve_from_problem(ctx_b, b, stream=stream.cuda_stream) for b in boxes]
+    frt.batch_run(batch, dts, warmup, graph=True)
+    tuning = frt.autotune(batch, dts)
+    c0 = sum(s.ledger()["crossings"] for s in batch)
+    t_batch = timed(lambda: frt.batch_run(batch, dts, steps, graph=True))
+    c_batch = sum(s.ledger()["crossings"] for s in batch) - c0
+    dx = max(float(np.abs(a - s.fields()[0]).max()) for a, s in zip(x_plain, batch))
+    cells = sum(int(np.prod(b.shape)) for b in boxes)
+    srcs = sum(b.n_src for b in boxes)
+    for s in batch:
+        s.close()
+    return {"workload": f"{n_boxes} boxes, edges 32-128, {cells} cells, {srcs} sources, 3 bins, c, dt 1 Myr",
+            "steps": steps, "warmup": warmup,
+            "plain_crossings_per_s": c_plain / t_plain, "plain_s": t_plain,
+            "batched_crossings_per_s": c_batch / t_batch, "batched_s": t_batch,
+            "speedup": (c_batch / t_batch) / (c_plain / t_plain) if c_plain else None,
+            "crossings": c_batch, "max_abs_dx_HI_batched_vs_plain": dx,
+            "batched_form": "one launch sequence per step over all boxes, replayed from a HIP graph",
+            "tuning": tuning}
+
+
+def served_leg(frt, W, n_req: int, steps: int, rate: float, budget_bytes: int, slots: int):
+    """The Poisson request trace served two ways on one GPU: the plain
+    per-solve path taking requests one at a time in arrival order (FIFO), and
+    the continuous-batching server.  Latency = finish - arrival."""
+    import numpy as np
+
+    reqs = W.served_c5(n_requests=n_req, rate_per_s=rate, n_steps=steps)
+
+    def pct(v, q):
+        return float(np.percentile(np.asarray(v), q))
+
+    def fifo(arrivals):
+        ctx = frt.Context(0)
+        lat = []
+        t0 = time.perf_counter()
+        for r, a in zip(reqs, arrivals):
+            wait = a - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            s = frt.solve_from_problem(ctx, r.problem)
+            for _ in range(steps):
+                s.step(r.problem.dt_s)
+            s.fields()
+            s.close()
+            lat.append(time.perf_counter() - t0 - a)
+        t = time.perf_counter() - t0
+        ctx.close()
+        return lat, t
+
+    def served(arrivals):
+        ctx = frt.Context(0)
+        srv = frt.Server(ctx, budget_bytes, slots)
+        t0 = time.perf_counter()
+        ids = []
+        for r, a in zip(reqs, arrivals):
+            wait = a - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(wait)
+            ids.append(srv.submit(r.problem, steps))
+        lat = []
+        for rid in ids:
+            if srv.wait(rid, 600.0) != frt.REQ_DONE:
+                raise RuntimeError(f"served request {rid} did not finish")
+            ts = srv.times(rid)
+            lat.append(ts[2] - ts[0])
+            srv.take(rid)
+        t = time.perf_counter() - t0
+        st = srv.stats()
+        srv.close()
+        ctx.close()
+        return lat, t, st
+
+    out = {"workload": f"{n_req} Poisson requests at {rate}/s, edges 64-256, 16-2000 sources, {steps} steps each, "
+                       "4 bins, sub-grid opacity, c", "budget_bytes": budget_bytes, "slots": slots}
+    for tag, arrivals in (("trace", [r.arrival_s for r in reqs]), ("burst", [0.0] * len(reqs))):
+        lf, tf = fifo(arrivals)
+        ls, ts, st = served(arrivals)
+        out[tag] = {"fifo_p50_s": pct(lf, 50), "fifo_p99_s": pct(lf, 99), "fifo_solves_per_s": n_req / tf,
+                    "served_p50_s": pct(ls, 50), "served_p99_s": pct(ls, 99), "served_solves_per_s": n_req / ts,
+                    "max_in_flight": st["max_in_flight"], "peak_bytes": st["peak_bytes"], "ticks": st["ticks"]}
+    out["burst"]["arrivals"] = "all requests at t = 0"
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -118,6 +241,16 @@ def main():
     ap.add_argument("--sources", type=int, default=2000)
     ap.add_argument("--cpu-sample", type=int, default=128)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the uneven-box batch leg")
+    ap.add_argument("--batched-boxes", type=int, default=64)
+    ap.add_argument("--batched-steps", type=int, default=49)
+    ap.add_argument("--batched-warmup", type=int, default=1)
+    ap.add_argument("--no-served", action="store_true", help="skip the served (request trace) leg")
+    ap.add_argument("--served-requests", type=int, default=32)
+    ap.add_argument("--served-steps", type=int, default=50)
+    ap.add_argument("--served-rate", type=float, default=4.0)
+    ap.add_argument("--served-budget-gb", type=float, default=64.0)
+    ap.add_argument("--served-slots", type=int, default=64)
     ap.add_argument("--copy-calibration-mib", type=int, default=1024,
                     help="size of a plain device copy run before timing; its hardware byte counters "
                          "calibrate the march kernel's (0 = skip)")
@@ -216,6 +349,22 @@ def main():
                       "parallelism": "single GPU"},
            "roofline": roof,
            "kernel_ms": {k: round(v, 3) for k, v in tm.items() if k.endswith("_ms")}}
+    s.close()
+    ctx.close()
+    if not args.no_batched:
+        log(f"batched leg: {args.batched_boxes} boxes, {args.batched_steps} steps")
+        out["batched"] = batched_leg(frt, W, args.batched_boxes, args.batched_steps, args.batched_warmup, stream)
+        log(f"batched: {out['batched']['batched_crossings_per_s']:.3e} crossings/s vs plain "
+            f"{out['batched']['plain_crossings_per_s']:.3e} (x{out['batched']['speedup']:.2f})")
+    if not args.no_served:
+        log(f"served leg: {args.served_requests} requests, {args.served_steps} steps each")
+        out["served"] = served_leg(frt, W, args.served_requests, args.served_steps, args.served_rate,
+                                   int(args.served_budget_gb * (1 << 30)), args.served_slots)
+        for tag in ("trace", "burst"):
+            sv = out["served"][tag]
+            log(f"served ({tag}) p50/p99 {sv['served_p50_s']:.2f}/{sv['served_p99_s']:.2f} s, "
+                f"{sv['served_solves_per_s']:.2f} solves/s vs FIFO {sv['fifo_p50_s']:.2f}/{sv['fifo_p99_s']:.2f} s, "
+                f"{sv['fifo_solves_per_s']:.2f} solves/s")
     if not args.no_cpu:
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         log(f"cpu baseline: oracle on {args.cpu_sample} sources with {threads} threads")

@@ -228,9 +228,9 @@ int frt_read_timing(frt_solve s, frt_timing* out);   /* synchronizes */
  * arrival order, when a slot is free and its estimated device bytes
  * (frt_request_bytes) fit in what the budget has left; its grid, packets and
  * ledger then stay resident until its last step, after which its results
- * are copied to host memory and its device memory is released.  One worker
- * thread per server drives the device; submit, poll, wait and take may be
- * called from any thread. */
+ * are copied to host memory and its device memory is released.  A worker
+ * and a loader thread per server drive the device; submit, poll, wait and
+ * take may be called from any thread. */
 typedef struct frt_server_s* frt_server;
 
 typedef struct {
@@ -265,8 +265,9 @@ int frt_request_bytes(const frt_request* req, size_t* bytes);
 
 /* hbm_budget_bytes: device bytes the admitted requests may hold together
  * (a request larger than the budget fails at admission); max_slots: most
- * requests in flight, 1..1024.  The server owns a HIP stream on ctx's
- * device and uses ctx's pass queues, which grow as the batches need. */
+ * requests in flight, 1..1024.  A loader thread uploads admitted requests,
+ * each solve on a HIP stream of its own, while the worker thread steps the
+ * others; the solves use ctx's pass queues, which grow as the batches need. */
 int frt_server_create(frt_ctx ctx, size_t hbm_budget_bytes, int max_slots, frt_server* out);
 
 /* Copy the request's inputs (validated as by frt_load_grid and

@@ -1,11 +1,13 @@
 // Serving layer of the ray-tracing library (include/frt.h, "serving"):
 // requests arrive with their inputs, wait in arrival order until a slot
-// and enough of the device-memory budget are free, are loaded as solves and
-// then advance one step per tick together with every other admitted solve
-// (one batched step per tick and per n_bins/precision group).  A finished
-// request's x_HI and ledger are copied to host memory and its solve is
-// destroyed, which frees its share of the budget for the next arrivals.
-// The layer uses only the public C ABI of the library.
+// and enough of the device-memory budget are free, are loaded as solves by
+// a loader thread (each solve on its own stream, so uploads overlap the
+// running steps) and then advance one step per tick together with every
+// other admitted solve (one batched step per tick and per n_bins/precision
+// group, driven by the worker thread).  A finished request's x_HI and ledger
+// are copied to host memory and its solve is destroyed, which frees its
+// share of the budget for the next arrivals.  The layer uses only the
+// public C ABI of the library.
 #include "frt.h"
 #include "frt_internal.h"
 
@@ -99,18 +101,21 @@ struct frt_server_s {
     int device = 0;
     size_t budget = 0;
     int max_slots = 1;
-    hipStream_t stream = nullptr;
     Clock::time_point t0;
     std::mutex mu;
-    std::condition_variable cv;       // worker: work arrived or stop
+    std::condition_variable cv;       // worker: work arrived, a solve loaded, or stop
+    std::condition_variable load_cv;  // loader: a request was admitted, or stop
     std::condition_variable done_cv;  // waiters: a request finished
-    std::deque<Req*> queue;
+    std::deque<Req*> queue;           // submitted, not admitted
+    std::deque<Req*> to_load;         // admitted, waiting for the loader
+    std::vector<Req*> ready;          // loaded, joining the next tick
+    int loading = 0;                  // admitted requests not yet in `active`
     std::unordered_map<uint64_t, std::unique_ptr<Req>> all;
     std::vector<Req*> active;         // worker thread only
     uint64_t next_id = 1;
     bool stop = false;
     frt_server_stats st{};
-    std::thread worker;
+    std::thread worker, loader;
 
     void finish(Req* r, int state)
     {
@@ -138,14 +143,42 @@ struct frt_server_s {
     int load(Req* r)
     {
         int rc;
-        if ((rc = frt_solve_create(ctx, &r->params, stream, &r->solve))) return rc;
+        // a stream of its own: the upload overlaps the steps of the others
+        if ((rc = frt_solve_create(ctx, &r->params, nullptr, &r->solve))) return rc;
         if ((rc = frt_load_grid(r->solve, r->nx, r->ny, r->nz, r->box_cm, r->nH.data(), r->T.empty() ? nullptr : r->T.data(),
                                 r->kappa.empty() ? nullptr : r->kappa.data(), r->x0.empty() ? nullptr : r->x0.data(),
                                 FRT_HOST)))
             return rc;
         if ((rc = frt_load_sources(r->solve, r->n_src, r->pos.data(), r->ndot.data(), FRT_HOST))) return rc;
         if (r->rot_steps > 0 && (rc = frt_set_rotations(r->solve, r->rot_steps, r->rot.data()))) return rc;
-        return FRT_OK;
+        return frt_sync(r->solve);
+    }
+
+    void run_loader()
+    {
+        (void)hipSetDevice(device);
+        for (;;) {
+            Req* r = nullptr;
+            {
+                std::unique_lock<std::mutex> lock(mu);
+                load_cv.wait(lock, [&] { return stop || !to_load.empty(); });
+                if (stop) break;
+                r = to_load.front();
+                to_load.pop_front();
+            }
+            const int rc = load(r);
+            r->free_inputs();
+            if (rc != FRT_OK) {
+                fail_req(r, rc);
+                std::lock_guard<std::mutex> lock(mu);
+                loading--;
+                cv.notify_all();
+                continue;
+            }
+            std::lock_guard<std::mutex> lock(mu);
+            ready.push_back(r);
+            cv.notify_all();
+        }
     }
 
     void complete(Req* r)
@@ -168,13 +201,13 @@ struct frt_server_s {
     {
         (void)hipSetDevice(device);
         for (;;) {
-            std::vector<Req*> admit;
+            std::vector<Req*> joined;
             {
                 std::unique_lock<std::mutex> lock(mu);
-                cv.wait(lock, [&] { return stop || !queue.empty() || !active.empty(); });
+                cv.wait(lock, [&] { return stop || !queue.empty() || !active.empty() || !ready.empty(); });
                 if (stop) break;
                 // admission in arrival order: a slot and the request's bytes
-                while (!queue.empty() && (int)(active.size() + admit.size()) < max_slots) {
+                while (!queue.empty() && (int)active.size() + loading < max_slots) {
                     Req* r = queue.front();
                     if (r->bytes > budget) {
                         queue.pop_front();
@@ -193,16 +226,20 @@ struct frt_server_s {
                     st.peak_bytes = std::max(st.peak_bytes, st.bytes_in_use);
                     r->state = FRT_REQ_RUNNING;
                     r->t_start = seconds_since(t0);
-                    admit.push_back(r);
+                    to_load.push_back(r);
+                    loading++;
+                    load_cv.notify_all();
                 }
-            }
-            for (Req* r : admit) {
-                const int rc = load(r);
-                if (rc != FRT_OK) {
-                    fail_req(r, rc);
+                joined.swap(ready);
+                loading -= (int)joined.size();
+                if (active.empty() && joined.empty()) {
+                    // nothing to step yet: wait for a load (or a finish freeing room)
+                    cv.wait(lock, [&] { return stop || !ready.empty() || (loading == 0 && !queue.empty()); });
+                    if (stop) break;
                     continue;
                 }
-                r->free_inputs();
+            }
+            for (Req* r : joined) {
                 if (r->n_steps == 0) complete(r);
                 else active.push_back(r);
             }
@@ -250,6 +287,17 @@ struct frt_server_s {
             }
         active.clear();
     }
+
+    // after both threads stopped: solves that were loaded but never stepped
+    void drop_ready()
+    {
+        for (Req* r : ready)
+            if (r->solve) {
+                frt_solve_destroy(r->solve);
+                r->solve = nullptr;
+            }
+        ready.clear();
+    }
 };
 
 extern "C" {
@@ -277,10 +325,9 @@ int frt_server_create(frt_ctx ctx, size_t hbm_budget_bytes, int max_slots, frt_s
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
     s->t0 = Clock::now();
-    if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess)
-        return frt::set_error(FRT_EDEVICE, "server stream");
     frt_server_s* raw = s.get();
     s->worker = std::thread([raw] { raw->run(); });
+    s->loader = std::thread([raw] { raw->run_loader(); });
     *out = s.release();
     return FRT_OK;
 }
@@ -394,9 +441,11 @@ int frt_server_destroy(frt_server srv)
         std::lock_guard<std::mutex> lock(srv->mu);
         srv->stop = true;
         srv->cv.notify_all();
+        srv->load_cv.notify_all();
     }
     if (srv->worker.joinable()) srv->worker.join();
-    if (srv->stream) (void)hipStreamDestroy(srv->stream);
+    if (srv->loader.joinable()) srv->loader.join();
+    srv->drop_ready();
     delete srv;
     return FRT_OK;
 }
