@@ -171,14 +171,14 @@ typedef struct {
                                        split children, 1..16 */
 } frt_tuning;
 
-/* Defaults: 1024 packets per item, 8 and 4 workgroups per CU. */
+/* Defaults: 1024 packets per item, 8 and 8 workgroups per CU. */
 int frt_tuning_default(frt_tuning* t);
 int frt_ctx_set_tuning(frt_ctx ctx, const frt_tuning* t);
 int frt_ctx_get_tuning(frt_ctx ctx, frt_tuning* t);
 
 /* Autotuner: times one step of the n solves (as frt_batch_step runs it)
  * under each candidate launch shape (item_rays 256/512/1024 x scatter 4/8
- * x split 2/4 workgroups per CU), after one untimed step that sizes the
+ * x split 4/8 workgroups per CU), after one untimed step that sizes the
  * queues; sets the fastest on the context and returns it in *best.  Every
  * solve is put back exactly as it was (fields, carried packets, ledger,
  * step index, last rate field), so the call changes no result. */

@@ -113,7 +113,7 @@ struct Workspace {
     uint32_t* segc = nullptr;
     uint32_t* segp = nullptr;
     uint32_t* ctr_host = nullptr;   // pinned copy of the counters
-    frt_tuning tune{sizeof(frt_tuning), (int)FRT_ITEM_RAYS, 8, 4};
+    frt_tuning tune{sizeof(frt_tuning), (int)FRT_ITEM_RAYS, 8, 8};
     uint32_t* ctr = nullptr;
     uint32_t* hist = nullptr;
     uint32_t* cursor = nullptr;
@@ -1066,19 +1066,17 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     std::vector<double> nHd(n), xd(n, 1.0);
     for (size_t i = 0; i < n; i++) nHd[i] = (double)hn[i];
     if (hx) std::copy(hx, hx + n, xd.begin());
+    // opacity: the HI part (first n values) is built from x_HI on the device;
+    // the sub-grid part (next n values) is fixed
     if (s->fp64) {
-        std::vector<double> opv(2 * n);
-        for (size_t i = 0; i < n; i++) {
-            opv[2 * i] = 0.0;
-            opv[2 * i + 1] = hk ? (double)hk[i] * s->dx : 0.0;
-        }
+        std::vector<double> opv(2 * n, 0.0);
+        if (hk)
+            for (size_t i = 0; i < n; i++) opv[n + i] = (double)hk[i] * s->dx;
         RCCHK(scopy(s, s->op, opv.data(), n * 16, hipMemcpyHostToDevice));
     } else {
-        std::vector<float> opv(2 * n);
-        for (size_t i = 0; i < n; i++) {
-            opv[2 * i] = 0.f;
-            opv[2 * i + 1] = hk ? (float)((double)hk[i] * s->dx) : 0.f;
-        }
+        std::vector<float> opv(2 * n, 0.f);
+        if (hk)
+            for (size_t i = 0; i < n; i++) opv[n + i] = (float)((double)hk[i] * s->dx);
         RCCHK(scopy(s, s->op, opv.data(), n * 8, hipMemcpyHostToDevice));
     }
     RCCHK(scopy(s, s->nH, nHd.data(), n * 8, hipMemcpyHostToDevice));
@@ -1096,8 +1094,9 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     h.bpx = s->bpx; h.bpy = s->bpy; h.bpz = s->bpz;
     h.dx_cm = s->dx;
     h.r_cap = s->P.max_distance_cm > 0 ? s->P.max_distance_cm / s->dx : HUGE_VAL;
-    h.op = s->op;
-    h.op_w = s->op;
+    h.op_a = s->op;
+    h.op_b = (const char*)s->op + n * s->rs;
+    h.op_aw = s->op;
     h.gamma[0] = s->gam[0];
     h.gamma[1] = s->gam[1];
     h.x = s->x;
@@ -1245,7 +1244,7 @@ int frt_tuning_default(frt_tuning* t)
     t->size = sizeof(frt_tuning);
     t->item_rays = (int)FRT_ITEM_RAYS;
     t->scatter_blocks_per_cu = 8;
-    t->split_blocks_per_cu = 4;
+    t->split_blocks_per_cu = 8;
     return FRT_OK;
 }
 
@@ -1289,7 +1288,7 @@ int frt_autotune(frt_solve* ss, int n, const double* dts, frt_tuning* best)
     std::vector<frt_tuning> cand;
     for (int item : {256, 512, 1024})
         for (int sc : {4, 8})
-            for (int sp : {2, 4}) cand.push_back(frt_tuning{sizeof(frt_tuning), item, sc, sp});
+            for (int sp : {4, 8}) cand.push_back(frt_tuning{sizeof(frt_tuning), item, sc, sp});
     hipStream_t st = ss[0]->stream;
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));

@@ -2,6 +2,7 @@
 // ray-tracing library.  Not part of the public C ABI (include/frt.h).
 #pragma once
 #include <hip/hip_runtime.h>
+#include <cstddef>
 #include <cstdint>
 
 #include "frt.h"
@@ -63,7 +64,7 @@ struct alignas(16) FrtRec {
     uint32_t src;      // source index within the solve
     uint32_t estep;    // step in which the packet's root was cast (rotation lookup)
     uint32_t lp;       // level << 28 | NESTED pixel
-    uint32_t cell;     // linear cell index x + nx (y + ny z)
+    uint32_t cell;     // cell coordinates x | y << 11 | z << 22
     uint32_t key;      // pass outputs: global brick key and crossing bin (FRT_KEY_BITS);
                        // sorted packets: the crossing bin; carried packets: solve-local key
     Real r;            // distance travelled from the source, cells
@@ -76,6 +77,8 @@ struct alignas(16) FrtRec {
 };
 static_assert(sizeof(FrtRec<float>) == 64, "FP32 packet record is 64 bytes");
 static_assert(sizeof(FrtRec<double>) == 112, "FP64 packet record is 112 bytes");
+static_assert(offsetof(FrtRec<float>, key) == 16 && offsetof(FrtRec<double>, key) == 16,
+              "the key is the first word of a record's second 16 bytes");
 
 // A queue of packet records (FrtRec<float> or FrtRec<double>).
 struct FrtRecs {
@@ -110,8 +113,9 @@ struct FrtSolveDesc {
     double dt;
     double w0_cast;             // dt / (12 * 4^L0), seconds per cast packet
     // buffers
-    const void* op;             // per cell {n_HI sigma_0 dx, kappa dx}: float2 or double2
-    void* op_w;
+    const void* op_a;           // per cell n_HI sigma_0 dx (float or double)
+    const void* op_b;           // per cell kappa dx (float or double)
+    void* op_aw;                // op_a, written by the chemistry
     void* gamma[2];             // deposit accumulators, alternating by step
     double* x;                  // neutral fraction
     const double* nH;           // hydrogen density, cm^-3

@@ -283,6 +283,20 @@ struct Pkt {
 
 // T[0] = A (HI optical depth at sigma_0), T[1] = K (sub-grid optical depth),
 // T[2], T[3] their Kahan compensations.
+// A packet's cell as packed coordinates x | y << 11 | z << 22 (grids have at
+// most 2048 cells per axis), so that no division recovers them.
+__device__ __forceinline__ uint32_t pack_cell(const int c[3])
+{
+    return (uint32_t)c[0] | ((uint32_t)c[1] << 11) | ((uint32_t)c[2] << 22);
+}
+
+__device__ __forceinline__ void unpack_cell(uint32_t p, int c[3])
+{
+    c[0] = (int)(p & 2047u);
+    c[1] = (int)((p >> 11) & 2047u);
+    c[2] = (int)(p >> 22);
+}
+
 template <typename Real>
 __device__ __forceinline__ FrtRec<Real>* recs(const FrtRecs& q) { return (FrtRec<Real>*)q.rec; }
 
@@ -350,8 +364,9 @@ __device__ __forceinline__ bool locate(const FrtSolveDesc& D, const Real s[3], R
 
 __device__ __forceinline__ uint32_t brick_key(const FrtSolveDesc& D, const int c[3])
 {
-    const int B = D.brick;
-    return D.key_base + (uint32_t)(c[0] / B) + (uint32_t)D.bpx * ((uint32_t)(c[1] / B) + (uint32_t)D.bpy * (uint32_t)(c[2] / B));
+    const int sh = __builtin_ctz((unsigned)D.brick);   // bricks are 2^k cells on a side
+    return D.key_base + (uint32_t)(c[0] >> sh) +
+           (uint32_t)D.bpx * ((uint32_t)(c[1] >> sh) + (uint32_t)D.bpy * (uint32_t)(c[2] >> sh));
 }
 
 __device__ __forceinline__ int find_in_prefix(const uint32_t* prefix, int n, uint32_t g)
@@ -381,6 +396,14 @@ __device__ __forceinline__ Real K_of(const FrtSolveDesc& D, int b)
     else return (Real)D.Kd[b];
 }
 
+// 1/x: the hardware reciprocal in FP32 (about 1 ulp), a division in FP64.
+template <typename Real>
+__device__ __forceinline__ Real fast_rcp(Real x)
+{
+    if constexpr (sizeof(Real) == 4) return __builtin_amdgcn_rcpf(x);
+    else return Real(1) / x;
+}
+
 // Crossings a packet at s + r d in cell c is expected to make in the brick
 // holding c on its next visit: the distance to the first of brick exit,
 // split radius, distance cap and the end of its travel budget (rstop),
@@ -397,8 +420,8 @@ __device__ __forceinline__ uint32_t crossing_bin(const FrtSolveDesc& D, const in
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const int lo = (c[a] / B) * B, hi = min(lo + B, dims[a]);
-        if (d[a] > Real(0)) lim = fmin(lim, ((Real)hi - s[a]) / d[a]);
-        else if (d[a] < Real(0)) lim = fmin(lim, ((Real)lo - s[a]) / d[a]);
+        if (d[a] > Real(0)) lim = fmin(lim, ((Real)hi - s[a]) * fast_rcp(d[a]));
+        else if (d[a] < Real(0)) lim = fmin(lim, ((Real)lo - s[a]) * fast_rcp(d[a]));
     }
     const Real len = fmax(lim - r, Real(0)) * (fabs(d[0]) + fabs(d[1]) + fabs(d[2]));
     return (uint32_t)fmin(len, Real(FRT_KEY_BINS - 3)) + 1u;
@@ -505,7 +528,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
                 const Real s3[3] = {(Real)sp[0], (Real)sp[1], (Real)sp[2]};
                 int c[3];
                 if (locate<Real>(D, s3, Real(0), d, c)) {
-                    h.cell = (uint32_t)c[0] + (uint32_t)D.nx * ((uint32_t)c[1] + (uint32_t)D.ny * (uint32_t)c[2]);
+                    h.cell = pack_cell(c);
                     key = brick_key(D, c);
                     bin = crossing_bin<Real>(D, c, s3, h.d, Real(0), (Real)D.budget, D.base_level);
                     want = 1;
@@ -522,8 +545,8 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
                 key = D.key_base + recs<Real>(D.F[D.cur])[i].key;   // carried keys are solve-local
                 const double* sp = D.src_pos + (size_t)h.src * 3;
                 const Real s3[3] = {(Real)sp[0], (Real)sp[1], (Real)sp[2]};
-                const int c[3] = {(int)(h.cell % (uint32_t)D.nx), (int)((h.cell / (uint32_t)D.nx) % (uint32_t)D.ny),
-                                  (int)(h.cell / ((uint32_t)D.nx * (uint32_t)D.ny))};
+                int c[3];
+                unpack_cell(h.cell, c);
                 const Real rs = h.rstop <= h.r ? h.r + (Real)D.budget : h.rstop;   // fresh budget this step
                 bin = crossing_bin<Real>(D, c, s3, h.d, h.r, rs, (int)(h.lp >> 28));
                 want = 1;
@@ -635,65 +658,93 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
     for (int i = threadIdx.x; i <= FRT_QSEG; i += blockDim.x) s_sp[i] = ws.segp[i];
     const uint32_t n = ws.ctr[C_NOS];
     const uint32_t scap = seg_cap(ws.O.cap);
-    FrtRec<Real>* __restrict__ O = recs<Real>(ws.O);
-    FrtRec<Real>* __restrict__ P = recs<Real>(ws.P);
+    const int lane = threadIdx.x & (WAVE - 1);
+    const unsigned long long upto = (lane == WAVE - 1) ? ~0ull : ((2ull << lane) - 1ull);
+    // records move as 16-byte words; the key is the low word of the second
+    constexpr int NW = (int)(sizeof(FrtRec<Real>) / 16);
+    const uint4* __restrict__ O = (const uint4*)ws.O.rec;
+    uint4* __restrict__ P = (uint4*)ws.P.rec;
     for (uint32_t base = blockIdx.x * SLOTS; base < n; base += gridDim.x * SLOTS) {
         for (int i = threadIdx.x; i < SLOTS; i += blockDim.x) {
             s_key[i] = EMPTY;
             s_cnt[i] = 0;
         }
         __syncthreads();
-        uint32_t idx[PER], slot[PER], rank[PER], bin[PER];
+        // PER separate items (not an array) keep the records in registers
+        struct Item {
+            uint4 w[NW];
+            uint32_t slot, rank, bin;
+            bool ok;
+        };
+        auto gather = [&](Item& it, uint32_t v) {
+            uint32_t key = EMPTY;
+            it.ok = false;
+            it.bin = 0;
+            if (v < n) {
+                const int sg = find_in_prefix(s_sp, FRT_QSEG, v);
+                const size_t at = ((size_t)sg * scap + (v - s_sp[sg])) * NW;
 #pragma unroll
-        for (int q = 0; q < PER; q++) {
-            const uint32_t v = base + (uint32_t)q * BLOCK + threadIdx.x;
-            idx[q] = 0xffffffffu;
-            if (v >= n) continue;
-            const int sg = find_in_prefix(s_sp, FRT_QSEG, v);
-            const uint32_t i = (uint32_t)sg * scap + (v - s_sp[sg]);
-            uint32_t key = O[i].key;
-            bin[q] = key >> FRT_KEY_BITS;
-            key &= FRT_KEY_MASK;
-            if (key >= ws.nkeys) {          // never expected: flag and skip
-                atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_QUEUE_OVERFLOW);
-                continue;
+                for (int w = 0; w < NW; w++) it.w[w] = O[at + w];
+                it.bin = it.w[1].x >> FRT_KEY_BITS;
+                key = it.w[1].x & FRT_KEY_MASK;
+                if (key >= ws.nkeys) {          // never expected: flag and skip
+                    atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_QUEUE_OVERFLOW);
+                    key = EMPTY;
+                }
+                it.ok = key != EMPTY;
             }
-            idx[q] = i;
-            uint32_t sl = (key * 2654435761u) & (SLOTS - 1);
-            for (;;) {
-                const uint32_t prev = atomicCAS(&s_key[sl], EMPTY, key);
-                if (prev == EMPTY || prev == key) break;
-                sl = (sl + 1) & (SLOTS - 1);
+            // lanes with equal keys next to each other (outputs of one wave of
+            // the march mostly are) count as one run: its first lane inserts
+            // the key once and reserves the run's ranks with one LDS atomic
+            const uint32_t prev = __shfl_up(key, 1, WAVE);
+            const bool head = lane == 0 || prev != key;
+            const unsigned long long heads = __ballot(head);
+            const int start = 63 - __clzll(heads & upto);
+            uint32_t sl = 0, r0 = 0;
+            if (head && key != EMPTY) {
+                const unsigned long long after = heads & ~upto;
+                const uint32_t len = (after ? (uint32_t)__ffsll(after) - 1u : (uint32_t)WAVE) - (uint32_t)lane;
+                sl = (key * 2654435761u) & (SLOTS - 1);
+                for (;;) {
+                    const uint32_t prv = atomicCAS(&s_key[sl], EMPTY, key);
+                    if (prv == EMPTY || prv == key) break;
+                    sl = (sl + 1) & (SLOTS - 1);
+                }
+                r0 = atomicAdd(&s_cnt[sl], len);
             }
-            slot[q] = sl;
-            rank[q] = atomicAdd(&s_cnt[sl], 1u);
-        }
+            it.slot = __shfl(sl, start, WAVE);
+            it.rank = __shfl(r0, start, WAVE) + (uint32_t)(lane - start);
+        };
+        auto put = [&](Item& it) {
+            if (!it.ok) return;
+            const uint32_t pos = s_base[it.slot] + it.rank;
+            if (pos < ws.P.cap) {
+                uint4* dst = P + (size_t)pos * NW;
+                dst[0] = it.w[0];
+                dst[1] = make_uint4(it.bin, it.w[1].y, it.w[1].z, it.w[1].w);   // sorted records keep only the crossing bin
+#pragma unroll
+                for (int w = 2; w < NW; w++) dst[w] = it.w[w];
+            }
+        };
+        static_assert(PER == 4, "four items per thread");
+        Item i0, i1, i2, i3;
+        gather(i0, base + threadIdx.x);
+        gather(i1, base + BLOCK + threadIdx.x);
+        gather(i2, base + 2 * BLOCK + threadIdx.x);
+        gather(i3, base + 3 * BLOCK + threadIdx.x);
         __syncthreads();
         for (int j = threadIdx.x; j < SLOTS; j += blockDim.x)
             if (s_key[j] != EMPTY) s_base[j] = atomicAdd(&ws.cursor[s_key[j]], s_cnt[j]);
         __syncthreads();
-#pragma unroll
-        for (int q = 0; q < PER; q++) {
-            if (idx[q] == 0xffffffffu) continue;
-            const uint32_t pos = s_base[slot[q]] + rank[q];
-            if (pos < ws.P.cap) {
-                FrtRec<Real> x = O[idx[q]];
-                x.key = bin[q];            // sorted records keep only the crossing bin
-                P[pos] = x;
-            }
-        }
+        put(i0);
+        put(i1);
+        put(i2);
+        put(i3);
         __syncthreads();
     }
 }
 
 // =============================================================== brick march
-template <typename Real>
-__device__ __forceinline__ Real fast_rcp(Real x)
-{
-    if constexpr (sizeof(Real) == 4) return __builtin_amdgcn_rcpf(x);
-    else return Real(1) / x;
-}
-
 // Absorbed fraction 1 - e^-t of a segment given eb = e^-t: the series
 // t (1 - t/2 + t^2/6 - t^3/24) below t = 0.03 (truncation < 7e-9
 // relative), 1 - eb above.  Both forms are evaluated and one selected,
@@ -712,18 +763,33 @@ __device__ __forceinline__ Real absorbed(Real t, Real eb)
 
 constexpr int KEY_SLOTS = 128;
 
-__device__ __forceinline__ void count_key(uint32_t* s_key, uint32_t* s_cnt, uint32_t* hist, uint32_t key)
+__device__ __forceinline__ void count_key(uint32_t* s_key, uint32_t* s_cnt, uint32_t* hist, uint32_t key, uint32_t n)
 {
     uint32_t slot = (key * 2654435761u) & (KEY_SLOTS - 1);
     for (int probe = 0; probe < 16; probe++) {
         const uint32_t prev = atomicCAS(&s_key[slot], 0xffffffffu, key);
         if (prev == 0xffffffffu || prev == key) {
-            atomicAdd(&s_cnt[slot], 1u);
+            atomicAdd(&s_cnt[slot], n);
             return;
         }
         slot = (slot + 1) & (KEY_SLOTS - 1);
     }
-    atomicAdd(&hist[key], 1u);   // table crowded: count directly
+    atomicAdd(&hist[key], n);   // table crowded: count directly
+}
+
+// count_key for the lanes of a wave with `valid` set: one table update per
+// distinct key of the wave.  Every lane of the wave must call it.
+__device__ __forceinline__ void count_keys_wave(uint32_t* s_key, uint32_t* s_cnt, uint32_t* hist, uint32_t key, bool valid)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    unsigned long long todo = __ballot(valid);
+    while (todo) {
+        const int leader = __ffsll(todo) - 1;
+        const uint32_t k = __shfl(key, leader, WAVE);
+        const unsigned long long same = __ballot(valid && key == k);
+        if (lane == leader) count_key(s_key, s_cnt, hist, k, (uint32_t)__popcll(same));
+        todo &= ~same;
+    }
 }
 
 // Lane-ordered prefix of a wave ballot: the number of set bits below the
@@ -744,6 +810,20 @@ __device__ __forceinline__ uint32_t wave_reserve_small(uint32_t* ctr, uint32_t n
     base = __shfl(base, 0, WAVE);
     return base + lanes_below(m0) + 2u * lanes_below(m1) + 4u * lanes_below(m2);
 }
+
+// wave_reserve_small in two halves, so that other work can run while the
+// atomic is in flight: begin issues it (its result lands in lane 0's *raw)
+// and returns the lane's offset; end broadcasts the base.
+__device__ __forceinline__ uint32_t reserve_begin(uint32_t* ctr, uint32_t n_lane, uint32_t* raw)
+{
+    const unsigned long long m0 = __ballot(n_lane & 1u), m1 = __ballot(n_lane & 2u), m2 = __ballot(n_lane & 4u);
+    const uint32_t total = (uint32_t)__popcll(m0) + 2u * (uint32_t)__popcll(m1) + 4u * (uint32_t)__popcll(m2);
+    *raw = 0;
+    if ((threadIdx.x & (WAVE - 1)) == 0 && total) *raw = atomicAdd(ctr, total);
+    return lanes_below(m0) + 2u * lanes_below(m1) + 4u * lanes_below(m2);
+}
+
+__device__ __forceinline__ uint32_t reserve_end(uint32_t raw, uint32_t off) { return __shfl(raw, 0, WAVE) + off; }
 
 // One workgroup per work item (one brick, up to FRT_ITEM_RAYS packets).
 // The item's packets are first ordered by their expected crossings (a
@@ -780,7 +860,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
     __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
     __shared__ uint32_t s_bin[NBIN];
     __shared__ uint16_t s_order[FRT_ITEM_RAYS];
-    __shared__ uint32_t s_nv;
+    __shared__ uint32_t s_nv, s_chunk;
     const uint32_t nwork = ws.ctr[C_NWORK];
     const uint32_t np = ws.ctr[C_NP] < ws.P.cap ? ws.ctr[C_NP] : ws.P.cap;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -816,7 +896,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
 #pragma unroll
         for (int b = 0; b < NB; b++) {
             srel[b] = uni(srel_of<Real>(D, b));
-            Kb[b] = uni(K_of<Real>(D, b));
+            Kb[b] = SUB ? uni(K_of<Real>(D, b)) : Real(0);
         }
         const Real KS = uni(F32 ? (Real)D.KS : (Real)D.KSd);
         const uint32_t lb = w.key - uni(D.key_base);
@@ -824,19 +904,25 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                   bz = (int)(lb / ((uint32_t)D.bpx * (uint32_t)D.bpy));
         const int ox = bx * B, oy = by * B, oz = bz * B;
         const int nx = uni(D.nx), ny = uni(D.ny), nz = uni(D.nz);
-        const R2* __restrict__ op = (const R2*)D.op;
+        const Real* __restrict__ opa = (const Real*)D.op_a;
+        const Real* __restrict__ opb = (const Real*)D.op_b;
         for (int t = threadIdx.x; t < BC; t += BLOCK) {
             const int lx = t % B, ly = (t / B) % B, lz = t / (B * B);
             const int cx = ox + lx, cy = oy + ly, cz = oz + lz;
             R2 v;
             v.x = Real(0);
             v.y = Real(0);
-            if (cx < nx && cy < ny && cz < nz) v = op[(size_t)cx + (size_t)nx * ((size_t)cy + (size_t)ny * (size_t)cz)];
+            if (cx < nx && cy < ny && cz < nz) {
+                const size_t ci = (size_t)cx + (size_t)nx * ((size_t)cy + (size_t)ny * (size_t)cz);
+                v.x = opa[ci];
+                if constexpr (SUB) v.y = opb[ci];
+            }
             if constexpr (SUB) s_op[t] = v;
             else s_op[t] = v.x;
             s_g[t] = Real(0);
         }
         if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
+        if (threadIdx.x == 0) s_chunk = 0;
         __syncthreads();
         // ---- order the item's packets by expected crossings
         uint32_t slot_of[PER];
@@ -870,8 +956,15 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
         const double r_split0 = uni(D.r_split0);
         const Real budget = uni((Real)D.budget);
         const uint32_t step = uni(D.step);
-        for (uint32_t jj = 0; jj < w.count; jj += BLOCK) {
-            const uint32_t p = jj + threadIdx.x;
+        // waves take chunks of 64 sorted packets as they finish, longest
+        // chunks first, so that the four waves of the workgroup end together
+        const uint32_t n_chunks = (n_valid + WAVE - 1) / WAVE;
+        for (;;) {
+            uint32_t chunk = 0;
+            if (lane == 0) chunk = atomicAdd(&s_chunk, 1u);
+            chunk = __shfl(chunk, 0, WAVE);
+            if (chunk >= n_chunks) break;
+            const uint32_t p = (n_chunks - 1u - chunk) * WAVE + (uint32_t)lane;
             const bool active = p < n_valid;
             const uint32_t j = active ? (uint32_t)s_order[p] : 0u;
             Pkt<Real> h;
@@ -899,31 +992,39 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                     sum0 += N0[b];
                     n_start += (double)(N0[b] * E[b]);
                 }
-                const uint32_t cl = h.cell;
-                c[0] = (int)(cl % (uint32_t)nx);
-                c[1] = (int)((cl / (uint32_t)nx) % (uint32_t)ny);
-                c[2] = (int)(cl / ((uint32_t)nx * (uint32_t)ny));
+                unpack_cell(h.cell, c);
                 const Real r_split = (level < max_level) ? (Real)(r_split0 * (double)(1u << level)) : rinf<Real>();
+                // the nearest of split radius, distance cap and budget end
+                const Real r_lim = fmin(fmin(r_split, r_cap), h.rstop);
                 Real inv[3], rf[3];
+                int stp[3];
 #pragma unroll
                 for (int a = 0; a < 3; a++) {
-                    inv[a] = (h.d[a] != Real(0)) ? Real(1) / h.d[a] : Real(0);
+                    inv[a] = (h.d[a] != Real(0)) ? fast_rcp(h.d[a]) : Real(0);
+                    stp[a] = h.d[a] > Real(0) ? 1 : -1;
                     rf[a] = (h.d[a] != Real(0)) ? ((Real)(c[a] + (h.d[a] > Real(0) ? 1 : 0)) - s[a]) * inv[a] : rinf<Real>();
                 }
+                // cell within the brick, and the change of its LDS index per step
+                int lc[3] = {c[0] - ox, c[1] - oy, c[2] - oz};
+                const int inc[3] = {stp[0], stp[1] * B, stp[2] * B * B};
+                int li = lc[0] + B * (lc[1] + B * lc[2]);
                 Real sub_acc = 0;
-                const bool in_brick = c[0] >= ox && c[0] < ox + B && c[1] >= oy && c[1] < oy + B && c[2] >= oz && c[2] < oz + B;
+                const bool in_brick = lc[0] >= 0 && lc[0] < B && lc[1] >= 0 && lc[1] < B && lc[2] >= 0 && lc[2] < B;
                 if (!in_brick) end = 4;            // hand it to the brick that holds its cell
                 const Real floor_abs = floor_f * sum0;
+                // photons left (in units of the cast weight), kept by
+                // subtracting each segment's absorption, for the flux floor
+                Real sumE = 0;
+#pragma unroll
+                for (int b = 0; b < NB; b++) sumE += N0[b] * E[b];
                 while (end < 0) {
                     int axis = 0;
                     Real r_face = rf[0];
                     if (rf[1] < r_face) { r_face = rf[1]; axis = 1; }
                     if (rf[2] < r_face) { r_face = rf[2]; axis = 2; }
-                    Real r_end = fmin(fmin(r_face, r_split), fmin(r_cap, h.rstop));
-                    r_end = fmax(r_end, h.r);
+                    const Real r_end = fmax(fmin(r_face, r_lim), h.r);
                     const Real ds = r_end - h.r;
                     if (ds > Real(0)) {
-                        const int li = (c[0] - ox) + B * ((c[1] - oy) + B * (c[2] - oz));
                         R2 o;
                         if constexpr (SUB) {
                             o = s_op[li];
@@ -932,7 +1033,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                             o.y = Real(0);
                         }
                         const Real ta = o.x * ds;
-                        Real dep = 0;
+                        Real dep = 0, absd = 0;
                         if constexpr (SUB) {
                             const Real tk = o.y * ds;
 #pragma unroll
@@ -944,6 +1045,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                                 const Real rt = fast_rcp(tb);
                                 const Real phi = (tb > Real(0)) ? af * rt : Real(1);
                                 dep += Kb[b] * nin * ds * phi;
+                                absd += nin * af;
                                 if (tk > Real(0)) sub_acc += nin * af * tk * rt;
                                 E[b] *= eb;
                             }
@@ -954,7 +1056,6 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                                 T[1] = t;
                             }
                         } else {
-                            Real absd = 0;
 #pragma unroll
                             for (int b = 0; b < NB; b++) {
                                 const Real tb = srel[b] * ta;
@@ -964,16 +1065,11 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                                 absd += nin * af;
                                 E[b] *= eb;
                             }
-                            if (o.x > Real(0)) {
-                                dep = KS * absd * fast_rcp(o.x);
-                            } else {
-                                // no neutral hydrogen: nothing absorbed, optically thin rate
-                                // (E is unchanged by the segment)
-#pragma unroll
-                                for (int b = 0; b < NB; b++) dep += Kb[b] * N0[b] * E[b];
-                                dep *= ds;
-                            }
+                            // a_i > 0 everywhere (the opacity has a tiny floor), so the
+                            // optically thin limit is this same expression
+                            dep = KS * absd * fast_rcp(o.x);
                         }
+                        sumE -= absd;
                         // Kahan-compensated optical depth carried by the packet
                         {
                             const Real y = ta - T[2];
@@ -985,36 +1081,37 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                         v_cross++;
                     }
                     h.r = r_end;
-                    if (h.r >= r_cap) { end = 2; break; }
-                    if (floor_f > Real(0)) {
-                        Real sumE = 0;
-#pragma unroll
-                        for (int b = 0; b < NB; b++) sumE += N0[b] * E[b];
-                        if (sumE < floor_abs) { end = 2; break; }
+                    if (h.r >= r_lim) {
+                        // end states in order: distance cap, flux floor, split,
+                        // then the budget (a face reached with it is crossed first)
+                        if (h.r >= r_cap) { end = 2; break; }
+                        if (floor_f > Real(0) && sumE < floor_abs) { end = 2; break; }
+                        if (h.r >= r_split) { end = 0; break; }
+                        if (h.r < r_face) { end = 3; break; }
+                    } else if (floor_f > Real(0) && sumE < floor_abs) {
+                        end = 2;
+                        break;
                     }
-                    if (h.r >= r_split) { end = 0; break; }
-                    if (h.r >= r_face) {
-                        // step to the next cell along `axis` (selects keep every
-                        // per-axis value in registers)
-                        const Real da = axis == 0 ? h.d[0] : (axis == 1 ? h.d[1] : h.d[2]);
-                        const int stp = da > Real(0) ? 1 : -1;
-                        if (axis == 0) c[0] += stp;
-                        else if (axis == 1) c[1] += stp;
-                        else c[2] += stp;
-                        const int ca = axis == 0 ? c[0] : (axis == 1 ? c[1] : c[2]);
-                        const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
-                        if (ca < 0 || ca >= dima) { end = 1; break; }
-                        const Real sa = axis == 0 ? s[0] : (axis == 1 ? s[1] : s[2]);
-                        const Real ia = axis == 0 ? inv[0] : (axis == 1 ? inv[1] : inv[2]);
-                        const Real rfa = ((Real)(ca + (stp > 0 ? 1 : 0)) - sa) * ia;
-                        if (axis == 0) rf[0] = rfa;
-                        else if (axis == 1) rf[1] = rfa;
-                        else rf[2] = rfa;
-                        const int loa = axis == 0 ? ox : (axis == 1 ? oy : oz);
-                        if (ca < loa || ca >= loa + B) {
-                            end = (h.r >= h.rstop) ? 3 : 4;
-                            break;
-                        }
+                    // step to the next cell along `axis` (selects keep every
+                    // per-axis value in registers)
+                    const int st = axis == 0 ? stp[0] : (axis == 1 ? stp[1] : stp[2]);
+                    if (axis == 0) { c[0] += st; lc[0] += st; }
+                    else if (axis == 1) { c[1] += st; lc[1] += st; }
+                    else { c[2] += st; lc[2] += st; }
+                    li += axis == 0 ? inc[0] : (axis == 1 ? inc[1] : inc[2]);
+                    const int ca = axis == 0 ? c[0] : (axis == 1 ? c[1] : c[2]);
+                    const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
+                    if (ca < 0 || ca >= dima) { end = 1; break; }
+                    const Real sa = axis == 0 ? s[0] : (axis == 1 ? s[1] : s[2]);
+                    const Real ia = axis == 0 ? inv[0] : (axis == 1 ? inv[1] : inv[2]);
+                    const Real rfa = ((Real)(ca + (st > 0 ? 1 : 0)) - sa) * ia;
+                    if (axis == 0) rf[0] = rfa;
+                    else if (axis == 1) rf[1] = rfa;
+                    else rf[2] = rfa;
+                    const int la = axis == 0 ? lc[0] : (axis == 1 ? lc[1] : lc[2]);
+                    if (la < 0 || la >= B) {
+                        end = (h.r >= h.rstop) ? 3 : 4;
+                        break;
                     }
                     if (h.r >= h.rstop) { end = 3; break; }
                 }
@@ -1029,8 +1126,15 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 if constexpr (SUB) v_sub = (double)sub_acc * Rr;
                 v_abs = (n_start - n_end) * Rr - v_sub;
                 v_end = n_end * Rr;
-                h.cell = (uint32_t)c[0] + (uint32_t)nx * ((uint32_t)c[1] + (uint32_t)ny * (uint32_t)c[2]);
+                h.cell = pack_cell(c);
             }
+            // ---- slots in the next pass's queues (O for packets entering
+            // another brick, S for packets at their split radius), reserved
+            // before the ledger reductions, which run while the atomics fly
+            const bool to_o = __ballot(end == 4) != 0, to_s = __ballot(end == 0) != 0;
+            uint32_t o_raw = 0, o_off = 0, s_raw = 0, s_off = 0;
+            if (to_o) o_off = reserve_begin(o_ctr(ws, my_seg()), end == 4 ? 1u : 0u, &o_raw);
+            if (to_s) s_off = reserve_begin(s_ctr(ws, my_seg()), end == 0 ? 1u : 0u, &s_raw);
             // ---- ledger: counts from ballots, photon terms from wave sums
             // taken only when some lane of the wave has one
             {
@@ -1059,23 +1163,26 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 }
             }
             // ---- packets entering another brick go to the next pass
-            if (__ballot(end == 4)) {
-                const uint32_t at = wave_reserve_small(o_ctr(ws, my_seg()), end == 4 ? 1u : 0u);
+            if (to_o) {
+                const uint32_t at = reserve_end(o_raw, o_off);
+                uint32_t key = 0;
+                bool stored = false;
                 if (end == 4) {
-                    const uint32_t key = key_with_bin(brick_key(D, c), crossing_bin<Real>(D, c, s, h.d, h.r, h.rstop, level));
+                    key = key_with_bin(brick_key(D, c), crossing_bin<Real>(D, c, s, h.d, h.r, h.rstop, level));
                     if (at < seg_cap(ws.O.cap)) {
                         store_pkt<Real>(ws.O, (uint32_t)my_seg() * seg_cap(ws.O.cap) + at, h, key, T);
-                        count_key(s_key, s_cnt, ws.hist, key & FRT_KEY_MASK);
+                        stored = true;
                     } else {
                         raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
                         atomicAdd(&s_lf[LF_LOST], v_end);
                     }
                 }
+                count_keys_wave(s_key, s_cnt, ws.hist, key & FRT_KEY_MASK, stored);
             }
             // ---- packets at their split radius, with their photons, go to the
             // split kernel, which writes the children (all lanes busy there)
-            if (__ballot(end == 0)) {
-                const uint32_t at = wave_reserve_small(s_ctr(ws, my_seg()), end == 0 ? 1u : 0u);
+            if (to_s) {
+                const uint32_t at = reserve_end(s_raw, s_off);
                 if (end == 0) {
                     if (at < seg_cap(ws.S.cap)) {
                         const uint32_t o = (uint32_t)my_seg() * seg_cap(ws.S.cap) + at;
@@ -1154,10 +1261,11 @@ __global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4)))
 // (Eq. lhpx): level + 1, NESTED pixels 4p .. 4p + 3, a quarter of the
 // photons each, the parent's rotation, placed on their own pixel direction
 // at the split radius.  A child whose position is outside the box has
-// escaped.  One lane per parent.
+// escaped.  Four lanes per parent, one child each.
 template <typename Real>
 __global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
 {
+    constexpr uint32_t PARENTS = BLOCK / 4;
     __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
     __shared__ uint32_t s_sp[FRT_QSEG + 1];
     if (threadIdx.x < KEY_SLOTS) { s_key[threadIdx.x] = 0xffffffffu; s_cnt[threadIdx.x] = 0; }
@@ -1171,85 +1279,67 @@ __global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
     __syncthreads();
     const uint32_t ns = s_sp[FRT_QSEG];
     const uint32_t ocap = seg_cap(ws.O.cap);
-    for (uint32_t base = blockIdx.x * BLOCK; base < ns; base += gridDim.x * BLOCK) {
-        const uint32_t v = base + threadIdx.x;
+    const uint32_t k = threadIdx.x & 3u;
+    for (uint32_t base = blockIdx.x * PARENTS; base < ns; base += gridDim.x * PARENTS) {
+        const uint32_t v = base + threadIdx.x / 4u;
         const bool act = v < ns;
-        uint32_t i = 0;
-        if (act) {
-            const int sg = find_in_prefix(s_sp, FRT_QSEG, v);
-            i = (uint32_t)sg * scap + (v - s_sp[sg]);
-        }
         Pkt<Real> h;
-        Real T[4], s[3], cd[4][3];
-        uint32_t ccell[4] = {0, 0, 0, 0}, ckey[4] = {0, 0, 0, 0}, cmask = 0;
+        Real T[4], cd[3];
+        uint32_t ccell = 0, ckey = 0;
+        bool inside = false;
         int solve = 0;
         double ph = 0.0;
         if (act) {
+            const int sg = find_in_prefix(s_sp, FRT_QSEG, v);
+            const uint32_t i = (uint32_t)sg * scap + (v - s_sp[sg]);
             load_pkt<Real>(ws.S, i, h, T);
             ph = ws.s_phot[i];
-            solve = find_in_prefix(ws.key_prefix, ws.n_solves, recs<Real>(ws.S)[i].key);
+            solve = ws.n_solves > 1 ? find_in_prefix(ws.key_prefix, ws.n_solves, recs<Real>(ws.S)[i].key) : 0;
             const FrtSolveDesc& D = descs[solve];
             const double* sp = D.src_pos + (size_t)h.src * 3;
-            s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
-            const uint32_t lpc = ((h.lp >> 28) + 1u) << 28 | (4u * (h.lp & 0x0fffffffu));
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                packet_dir<Real>(D, lpc + (uint32_t)k, h.estep, h.src, cd[k]);
-                int cc[3];
-                if (locate<Real>(D, s, h.r, cd[k], cc)) {
-                    ccell[k] = (uint32_t)cc[0] + (uint32_t)D.nx * ((uint32_t)cc[1] + (uint32_t)D.ny * (uint32_t)cc[2]);
-                    ckey[k] = key_with_bin(brick_key(D, cc), crossing_bin<Real>(D, cc, s, cd[k], h.r, h.rstop, (int)(h.lp >> 28) + 1));
-                    cmask |= 1u << k;
-                }
+            const Real s[3] = {(Real)sp[0], (Real)sp[1], (Real)sp[2]};
+            const int level = (int)(h.lp >> 28) + 1;
+            h.lp = ((uint32_t)level << 28) | (4u * (h.lp & 0x0fffffffu) + k);
+            packet_dir<Real>(D, h.lp, h.estep, h.src, cd);
+            int cc[3];
+            inside = locate<Real>(D, s, h.r, cd, cc);
+            if (inside) {
+                ccell = pack_cell(cc);
+                ckey = key_with_bin(brick_key(D, cc), crossing_bin<Real>(D, cc, s, cd, h.r, h.rstop, level));
             }
         }
-        const uint32_t n_child = __builtin_popcount(cmask);
-        const uint32_t at = wave_reserve_small(o_ctr(ws, my_seg()), n_child);
-        uint32_t lost = 0;
-        if (n_child) {
-            uint32_t o = at;
-#pragma unroll
-            for (int k = 0; k < 4; k++) {
-                if (!(cmask & (1u << k))) continue;
-                if (o < ocap) {
-                    Pkt<Real> ch = h;
-                    ch.lp = (((h.lp >> 28) + 1u) << 28) | (4u * (h.lp & 0x0fffffffu) + (uint32_t)k);
-                    ch.w0 = h.w0 * Real(0.25);
-                    ch.cell = ccell[k];
-                    ch.d[0] = cd[k][0];
-                    ch.d[1] = cd[k][1];
-                    ch.d[2] = cd[k][2];
-                    store_pkt<Real>(ws.O, (uint32_t)my_seg() * ocap + o, ch, ckey[k], T);
-                    count_key(s_key, s_cnt, ws.hist, ckey[k] & FRT_KEY_MASK);
-                } else {
-                    lost += 1;
-                }
-                o++;
+        const uint32_t at = wave_reserve_small(o_ctr(ws, my_seg()), inside ? 1u : 0u);
+        bool lost = false;
+        if (inside) {
+            if (at < ocap) {
+                h.w0 *= Real(0.25);
+                h.cell = ccell;
+                h.d[0] = cd[0];
+                h.d[1] = cd[1];
+                h.d[2] = cd[2];
+                store_pkt<Real>(ws.O, (uint32_t)my_seg() * ocap + at, h, ckey, T);
+            } else {
+                lost = true;
             }
         }
-        if (act && (n_child < 4 || lost)) {
+        count_keys_wave(s_key, s_cnt, ws.hist, ckey & FRT_KEY_MASK, inside && !lost);
+        if (act && (!inside || lost)) {
             FrtLedgerDev* L = descs[solve].L;
-            if (n_child < 4) {
-                ledger_direct(L, LF_ESC, 0.25 * (double)(4 - n_child) * ph);
-                ledger_direct_c(L, LC_NESC, 4ull - n_child);
-            }
-            if (lost) {
+            if (!inside) {
+                ledger_direct(L, LF_ESC, 0.25 * ph);
+                ledger_direct_c(L, LC_NESC, 1ull);
+            } else {
                 raise_error(ws, L, FRT_DEVERR_QUEUE_OVERFLOW);
-                ledger_direct(L, LF_LOST, 0.25 * (double)lost * ph);
+                ledger_direct(L, LF_LOST, 0.25 * ph);
             }
         }
-        // children of neighbouring parents share few bricks: add the block's
-        // key counts to the histogram once per round
-        __syncthreads();
-        if (threadIdx.x < KEY_SLOTS) {
-            const uint32_t k = s_key[threadIdx.x];
-            if (k != 0xffffffffu) {
-                atomicAdd(&ws.hist[k], s_cnt[threadIdx.x]);
-                s_key[threadIdx.x] = 0xffffffffu;
-                s_cnt[threadIdx.x] = 0;
-            }
-        }
-        __syncthreads();
+    }
+    // the block's key counts go to the histogram once (keys that did not
+    // find room in the table were counted directly)
+    __syncthreads();
+    if (threadIdx.x < KEY_SLOTS) {
+        const uint32_t kk = s_key[threadIdx.x];
+        if (kk != 0xffffffffu) atomicAdd(&ws.hist[kk], s_cnt[threadIdx.x]);
     }
 }
 
@@ -1323,6 +1413,17 @@ __global__ void k_finish(FrtSolveDesc* descs, FrtWS ws)
     }
 }
 
+// HI opacity per cell width, n_HI sigma_0 dx, with a floor far below any
+// value that changes a result (1e-30 in FP32, 1e-300 in FP64): every cell
+// then has a_i > 0, and the deposit K ds phi(tau) = (K / s) (1 - e^-tau) / a_i
+// needs no separate form for a cell without neutral hydrogen.
+template <typename Real>
+__device__ __forceinline__ Real hi_opacity(double v)
+{
+    constexpr double lo = sizeof(Real) == 4 ? 1e-30 : 1e-300;
+    return (Real)(v > lo ? v : lo);
+}
+
 // ================================================================ chemistry
 // Backward Euler for x = n_HI / n_H, pure H, n_e = n_HII = n_H (1 - x):
 //   x' - x = dt [ -Gamma x' - C n_H (1-x') x' + alpha n_H (1-x')^2 ]
@@ -1334,7 +1435,6 @@ template <typename Real>
 __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsigned long long* prefix,
                                                 int n_solves, unsigned long long total)
 {
-    using R2 = typename Vec2<Real>::T;
     __shared__ unsigned long long spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
     for (int i = threadIdx.x; i <= n_solves; i += blockDim.x) spre[i] = prefix[i];
     __syncthreads();
@@ -1362,8 +1462,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
         disc = disc > 0.0 ? disc : 0.0;
         const double xn = 2.0 * cq / (-bq + sqrt(disc));
         D.x[i] = xn;
-        R2* op = (R2*)D.op_w;
-        op[i].x = (Real)(nH * xn * D.sigma0 * D.dx_cm);
+        ((Real*)D.op_aw)[i] = hi_opacity<Real>(nH * xn * D.sigma0 * D.dx_cm);
         gnext[i] = Real(0);
     }
 }
@@ -1373,12 +1472,11 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
 template <typename Real>
 __global__ void __launch_bounds__(BLOCK) k_prep(FrtSolveDesc* desc, unsigned long long n)
 {
-    using R2 = typename Vec2<Real>::T;
     const FrtSolveDesc& D = *desc;
-    R2* op = (R2*)D.op_w;
+    Real* op = (Real*)D.op_aw;
     for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (unsigned long long)gridDim.x * blockDim.x)
-        op[i].x = (Real)(D.nH[i] * D.x[i] * D.sigma0 * D.dx_cm);
+        op[i] = hi_opacity<Real>(D.nH[i] * D.x[i] * D.sigma0 * D.dx_cm);
 }
 
 int g_cu_count = 0;
