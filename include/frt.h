@@ -171,7 +171,7 @@ typedef struct {
                                        split children, 1..16 */
 } frt_tuning;
 
-/* Defaults: 1024 packets per item, 8 and 8 workgroups per CU. */
+/* Defaults: 1024 packets per item, 8 and 4 workgroups per CU. */
 int frt_tuning_default(frt_tuning* t);
 int frt_ctx_set_tuning(frt_ctx ctx, const frt_tuning* t);
 int frt_ctx_get_tuning(frt_ctx ctx, frt_tuning* t);

@@ -113,7 +113,7 @@ struct Workspace {
     uint32_t* segc = nullptr;
     uint32_t* segp = nullptr;
     uint32_t* ctr_host = nullptr;   // pinned copy of the counters
-    frt_tuning tune{sizeof(frt_tuning), (int)FRT_ITEM_RAYS, 8, 8};
+    frt_tuning tune{sizeof(frt_tuning), (int)FRT_ITEM_RAYS, 8, 4};
     uint32_t* ctr = nullptr;
     uint32_t* hist = nullptr;
     uint32_t* cursor = nullptr;
@@ -1244,7 +1244,7 @@ int frt_tuning_default(frt_tuning* t)
     t->size = sizeof(frt_tuning);
     t->item_rays = (int)FRT_ITEM_RAYS;
     t->scatter_blocks_per_cu = 8;
-    t->split_blocks_per_cu = 8;
+    t->split_blocks_per_cu = 4;
     return FRT_OK;
 }
 

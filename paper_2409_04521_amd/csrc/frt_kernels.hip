@@ -761,6 +761,17 @@ __device__ __forceinline__ Real absorbed(Real t, Real eb)
     }
 }
 
+// The same in terms of u = -log2(e) t (so that e^-t = 2^u): with
+// v = -u ln 2 = t, the series v (1 - v/2 + v^2/6 - v^3/24) written in u,
+// used while t < 0.03 (u > -0.03 / ln 2).
+__device__ __forceinline__ float absorbed_u(float u, float eb)
+{
+    constexpr float c1 = -0.69314718f, c2 = -0.24022651f, c3 = -0.05550411f, c4 = -0.00961813f;
+    const float ser = u * (c1 + u * (c2 + u * (c3 + u * c4)));
+    const float dif = 1.f - eb;
+    return u > -0.043280851f ? ser : dif;
+}
+
 constexpr int KEY_SLOTS = 128;
 
 __device__ __forceinline__ void count_key(uint32_t* s_key, uint32_t* s_cnt, uint32_t* hist, uint32_t key, uint32_t n)
@@ -823,7 +834,7 @@ __device__ __forceinline__ uint32_t reserve_begin(uint32_t* ctr, uint32_t n_lane
     return lanes_below(m0) + 2u * lanes_below(m1) + 4u * lanes_below(m2);
 }
 
-__device__ __forceinline__ uint32_t reserve_end(uint32_t raw, uint32_t off) { return __shfl(raw, 0, WAVE) + off; }
+__device__ __forceinline__ uint32_t reserve_end(uint32_t raw, uint32_t off) { return uni(raw) + off; }
 
 // One workgroup per work item (one brick, up to FRT_ITEM_RAYS packets).
 // The item's packets are first ordered by their expected crossings (a
@@ -892,11 +903,12 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
         }
         const FrtSolveDesc& D = descs[w.solve];
         // per-solve constants of the march, held in scalar registers
-        Real srel[NB], Kb[NB];
+        Real srel[NB], Kb[NB], sl2[NB];
 #pragma unroll
         for (int b = 0; b < NB; b++) {
             srel[b] = uni(srel_of<Real>(D, b));
             Kb[b] = SUB ? uni(K_of<Real>(D, b)) : Real(0);
+            sl2[b] = srel[b] * Real(-1.4426950408889634);   // -log2(e) s_nu
         }
         const Real KS = uni(F32 ? (Real)D.KS : (Real)D.KSd);
         const uint32_t lb = w.key - uni(D.key_base);
@@ -959,16 +971,20 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
         // waves take chunks of 64 sorted packets as they finish, longest
         // chunks first, so that the four waves of the workgroup end together
         const uint32_t n_chunks = (n_valid + WAVE - 1) / WAVE;
+        // absorbed photons and crossings of this lane's packets, reduced
+        // over the wave once per item
+        double acc_abs = 0.0;
+        uint32_t acc_cross = 0;
         for (;;) {
             uint32_t chunk = 0;
             if (lane == 0) chunk = atomicAdd(&s_chunk, 1u);
-            chunk = __shfl(chunk, 0, WAVE);
+            chunk = uni(chunk);
             if (chunk >= n_chunks) break;
             const uint32_t p = (n_chunks - 1u - chunk) * WAVE + (uint32_t)lane;
             const bool active = p < n_valid;
             const uint32_t j = active ? (uint32_t)s_order[p] : 0u;
             Pkt<Real> h;
-            Real T[4], E[NB], N0[NB], s[3];
+            Real T[4], NE[NB], N0[NB], s[3];   // NE: photons of each bin (units of the cast weight)
             int level = 0, end = -1;     // -1 inactive, 0 split, 1 escaped, 2 dropped, 3 in flight, 4 next brick
             int c[3] = {0, 0, 0};
             double v_abs = 0.0, v_sub = 0.0, v_end = 0.0;
@@ -988,9 +1004,9 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                     if constexpr (F32) spec = D.spec[(size_t)h.src * NB + b];
                     else spec = D.specd[(size_t)h.src * NB + b];
                     N0[b] = h.w0 * spec;
-                    E[b] = SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0]);
+                    NE[b] = N0[b] * (SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0]));
                     sum0 += N0[b];
-                    n_start += (double)(N0[b] * E[b]);
+                    n_start += (double)NE[b];
                 }
                 unpack_cell(h.cell, c);
                 const Real r_split = (level < max_level) ? (Real)(r_split0 * (double)(1u << level)) : rinf<Real>();
@@ -1016,7 +1032,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 // subtracting each segment's absorption, for the flux floor
                 Real sumE = 0;
 #pragma unroll
-                for (int b = 0; b < NB; b++) sumE += N0[b] * E[b];
+                for (int b = 0; b < NB; b++) sumE += NE[b];
                 while (end < 0) {
                     int axis = 0;
                     Real r_face = rf[0];
@@ -1039,7 +1055,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
 #pragma unroll
                             for (int b = 0; b < NB; b++) {
                                 const Real tb = srel[b] * ta + tk;
-                                const Real nin = N0[b] * E[b];
+                                const Real nin = NE[b];
                                 const Real eb = exp_neg(tb);
                                 const Real af = absorbed<Real>(tb, eb);
                                 const Real rt = fast_rcp(tb);
@@ -1047,7 +1063,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                                 dep += Kb[b] * nin * ds * phi;
                                 absd += nin * af;
                                 if (tk > Real(0)) sub_acc += nin * af * tk * rt;
-                                E[b] *= eb;
+                                NE[b] *= eb;
                             }
                             if (tk > Real(0)) {
                                 const Real y = tk - T[3];
@@ -1058,12 +1074,18 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                         } else {
 #pragma unroll
                             for (int b = 0; b < NB; b++) {
-                                const Real tb = srel[b] * ta;
-                                const Real nin = N0[b] * E[b];
-                                const Real eb = exp_neg(tb);
-                                const Real af = absorbed<Real>(tb, eb);
-                                absd += nin * af;
-                                E[b] *= eb;
+                                if constexpr (F32) {
+                                    // u = -log2(e) tau: e^-tau = 2^u
+                                    const Real u = sl2[b] * ta;
+                                    const Real eb = __builtin_amdgcn_exp2f(u);
+                                    absd += NE[b] * absorbed_u(u, eb);
+                                    NE[b] *= eb;
+                                } else {
+                                    const Real tb = srel[b] * ta;
+                                    const Real eb = exp_neg(tb);
+                                    absd += NE[b] * absorbed<Real>(tb, eb);
+                                    NE[b] *= eb;
+                                }
                             }
                             // a_i > 0 everywhere (the opacity has a tiny floor), so the
                             // optically thin limit is this same expression
@@ -1120,8 +1142,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 double n_end = 0.0;
 #pragma unroll
                 for (int b = 0; b < NB; b++) {
-                    E[b] = SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0]);
-                    n_end += (double)(N0[b] * E[b]);
+                    n_end += (double)(N0[b] * (SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0])));
                 }
                 if constexpr (SUB) v_sub = (double)sub_acc * Rr;
                 v_abs = (n_start - n_end) * Rr - v_sub;
@@ -1141,20 +1162,18 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 const bool esc = end == 1, drop = end == 2, fl = end == 3;
                 const unsigned long long m_act = __ballot(active), m_split = __ballot(end == 0),
                                          m_esc = __ballot(esc), m_drop = __ballot(drop), m_fl = __ballot(fl);
-                const double t_abs = wave_sum(v_abs);
-                const uint32_t t_cross = wave_sum_u32(v_cross);
+                acc_abs += v_abs;
+                acc_cross += v_cross;
                 double t_sub = 0.0, t_esc = 0.0, t_drop = 0.0, t_fl = 0.0;
                 if constexpr (SUB) t_sub = wave_sum(v_sub);
                 if (m_esc) t_esc = wave_sum(esc ? v_end : 0.0);
                 if (m_drop) t_drop = wave_sum(drop ? v_end : 0.0);
                 if (m_fl) t_fl = wave_sum(fl ? v_end : 0.0);
                 if (lane == 0) {
-                    if (t_abs != 0.0) atomicAdd(&s_lf[LF_ABS_HI], t_abs);
                     if (t_sub != 0.0) atomicAdd(&s_lf[LF_ABS_SUB], t_sub);
                     if (t_esc != 0.0) atomicAdd(&s_lf[LF_ESC], t_esc);
                     if (t_drop != 0.0) atomicAdd(&s_lf[LF_DROP], t_drop);
                     if (t_fl != 0.0) atomicAdd(&s_lf[LF_FLIGHT], t_fl);
-                    if (t_cross) atomicAdd(&s_lc[LC_CROSS], (unsigned long long)t_cross);
                     if (m_act) atomicAdd(&s_lc[LC_VISITS], (unsigned long long)__popcll(m_act));
                     if (m_split) atomicAdd(&s_lc[LC_SPLITS], (unsigned long long)__popcll(m_split));
                     if (m_esc) atomicAdd(&s_lc[LC_NESC], (unsigned long long)__popcll(m_esc));
@@ -1206,6 +1225,14 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                         atomicAdd(&s_lf[LF_LOST], v_end);
                     }
                 }
+            }
+        }
+        {
+            const double t_abs = wave_sum(acc_abs);
+            const uint32_t t_cross = wave_sum_u32(acc_cross);
+            if (lane == 0) {
+                if (t_abs != 0.0) atomicAdd(&s_lf[LF_ABS_HI], t_abs);
+                if (t_cross) atomicAdd(&s_lc[LC_CROSS], (unsigned long long)t_cross);
             }
         }
         __syncthreads();
@@ -1333,13 +1360,18 @@ __global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
                 ledger_direct(L, LF_LOST, 0.25 * ph);
             }
         }
-    }
-    // the block's key counts go to the histogram once (keys that did not
-    // find room in the table were counted directly)
-    __syncthreads();
-    if (threadIdx.x < KEY_SLOTS) {
-        const uint32_t kk = s_key[threadIdx.x];
-        if (kk != 0xffffffffu) atomicAdd(&ws.hist[kk], s_cnt[threadIdx.x]);
+        // children of neighbouring parents share few bricks: add the block's
+        // key counts to the histogram once per round, before the table fills
+        __syncthreads();
+        if (threadIdx.x < KEY_SLOTS) {
+            const uint32_t kk = s_key[threadIdx.x];
+            if (kk != 0xffffffffu) {
+                atomicAdd(&ws.hist[kk], s_cnt[threadIdx.x]);
+                s_key[threadIdx.x] = 0xffffffffu;
+                s_cnt[threadIdx.x] = 0;
+            }
+        }
+        __syncthreads();
     }
 }
 
