@@ -156,7 +156,7 @@ struct frt_solve_s {
     frt_params P{};
     int fp64 = 0;
     size_t rs = 4;
-    int brick = FRT_BRICK_F32;
+    int bsh[3] = {FRT_BRICK_LOG_SUB[0], FRT_BRICK_LOG_SUB[1], FRT_BRICK_LOG_SUB[2]};   // log2 brick edges
     bool have_grid = false, have_src = false;
     int nx = 0, ny = 0, nz = 0;
     int bpx = 0, bpy = 0, bpz = 0;
@@ -271,7 +271,8 @@ int passes_needed(frt_solve s)
     const int splits = l - s->P.base_level;
     double travel = reach;
     if (std::isfinite(s->P.c_ray_cm_s)) travel = std::min(travel, s->P.c_ray_cm_s * s->h.dt / s->dx + 1.0);
-    const int cross = 3 * ((int)std::ceil(travel / s->brick) + 1);
+    int cross = 0;
+    for (int a = 0; a < 3; a++) cross += (int)std::ceil(travel / (double)(1 << s->bsh[a])) + 1;
     return cross + 2 * splits + 6;
 }
 
@@ -498,7 +499,9 @@ void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
     w.n_bins = ss[0]->P.n_bins;
     w.has_sub = 0;
     for (int i = 0; i < n; i++) w.has_sub |= ss[i]->h.has_sub;
-    w.item_rays = (uint32_t)ws.tune.item_rays;
+    // the 1024-thread march (FP32 without sub-grid opacity) takes four
+    // times the tuned item size
+    w.item_rays = (uint32_t)ws.tune.item_rays * ((!ss[0]->fp64 && !w.has_sub) ? 4u : 1u);
     w.scatter_bpc = ws.tune.scatter_blocks_per_cu;
     w.split_bpc = ws.tune.split_blocks_per_cu;
     if (ss[0]->P.queue_capacity) {
@@ -652,11 +655,47 @@ int read_counters(Workspace& ws, hipStream_t st, uint32_t* out)
     return FRT_OK;
 }
 
+// Solves of one launch share a brick shape; a batch mixing shapes (FP32
+// solves with and without sub-grid opacity) runs as one launch sequence per
+// shape.  Returns true and fills the parts when ss holds more than one.
+bool split_by_shape(frt_solve* ss, int n, const double* dts, std::vector<std::vector<frt_solve>>& parts,
+                    std::vector<std::vector<double>>& pdts)
+{
+    auto shape = [](frt_solve s) { return s->bsh[0] * 100 + s->bsh[1] * 10 + s->bsh[2]; };
+    bool mixed = false;
+    for (int i = 1; i < n; i++) mixed |= shape(ss[i]) != shape(ss[0]);
+    if (!mixed) return false;
+    std::vector<int> keys;
+    for (int i = 0; i < n; i++) {
+        const int k = shape(ss[i]);
+        size_t at = std::find(keys.begin(), keys.end(), k) - keys.begin();
+        if (at == keys.size()) {
+            keys.push_back(k);
+            parts.emplace_back();
+            pdts.emplace_back();
+        }
+        parts[at].push_back(ss[i]);
+        pdts[at].push_back(dts[i]);
+    }
+    return true;
+}
+
+int step_group_locked(frt_solve* ss, int n, const double* dts);
+
 // One step of a group with automatic queue growth: snapshot, run, check,
 // and on overflow restore the starting state, enlarge and run again.
 // The caller holds the context lock.
 int step_group_locked(frt_solve* ss, int n, const double* dts)
 {
+    {
+        std::vector<std::vector<frt_solve>> parts;
+        std::vector<std::vector<double>> pdts;
+        if (split_by_shape(ss, n, dts, parts, pdts)) {
+            for (size_t k = 0; k < parts.size(); k++)
+                RCCHK(step_group_locked(parts[k].data(), (int)parts[k].size(), pdts[k].data()));
+            return FRT_OK;
+        }
+    }
     Workspace& ws = ss[0]->ctx->ws;
     hipStream_t st = ss[0]->stream;
     const bool auto_grow = ss[0]->P.queue_capacity == 0;
@@ -718,6 +757,15 @@ struct StepGraph {
 // queues, captures again and repeats the step.  The caller holds the lock.
 int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps)
 {
+    {
+        std::vector<std::vector<frt_solve>> parts;
+        std::vector<std::vector<double>> pdts;
+        if (split_by_shape(ss, n, dts, parts, pdts)) {
+            for (size_t k = 0; k < parts.size(); k++)
+                RCCHK(run_group_graph_locked(parts[k].data(), (int)parts[k].size(), pdts[k].data(), n_steps));
+            return FRT_OK;
+        }
+    }
     Workspace& ws = ss[0]->ctx->ws;
     hipStream_t st = ss[0]->stream;
     const bool auto_grow = ss[0]->P.queue_capacity == 0;
@@ -972,7 +1020,6 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     s->P = *P;
     s->fp64 = P->march_precision == FRT_F64;
     s->rs = s->fp64 ? 8 : 4;
-    s->brick = s->fp64 ? FRT_BRICK_F64 : FRT_BRICK_F32;
     if (hip_stream) {
         s->stream = (hipStream_t)hip_stream;
     } else {
@@ -999,7 +1046,7 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     h.base_level = P->base_level;
     h.max_level = P->max_level;
     h.fp64 = s->fp64;
-    h.brick = s->brick;
+    for (int a = 0; a < 3; a++) h.bsh[a] = s->bsh[a];
     h.ncast = 12u << (2 * P->base_level);
     h.sigma0 = P->sigma_bins[0];
     for (int b = 0; b < P->n_bins; b++) h.sig_rel[b] = (float)(P->sigma_bins[b] / P->sigma_bins[0]);
@@ -1060,9 +1107,14 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     s->nx = nx; s->ny = ny; s->nz = nz;
     s->ncell = n;
     s->dx = box_cm / nx;
-    s->bpx = (nx + s->brick - 1) / s->brick;
-    s->bpy = (ny + s->brick - 1) / s->brick;
-    s->bpz = (nz + s->brick - 1) / s->brick;
+    // brick shape: 8^3 in FP64; in FP32 16^3 with sub-grid opacity, else
+    // 32 x 32 x 16 (the 1024-thread march)
+    const bool any_kappa = hk && std::any_of(hk, hk + n, [](float v) { return v > 0.f; });
+    const int* lg = s->fp64 ? FRT_BRICK_LOG_F64 : (any_kappa ? FRT_BRICK_LOG_SUB : FRT_BRICK_LOG_BIG);
+    for (int a = 0; a < 3; a++) s->bsh[a] = lg[a];
+    s->bpx = (nx + (1 << s->bsh[0]) - 1) >> s->bsh[0];
+    s->bpy = (ny + (1 << s->bsh[1]) - 1) >> s->bsh[1];
+    s->bpz = (nz + (1 << s->bsh[2]) - 1) >> s->bsh[2];
     std::vector<double> nHd(n), xd(n, 1.0);
     for (size_t i = 0; i < n; i++) nHd[i] = (double)hn[i];
     if (hx) std::copy(hx, hx + n, xd.begin());
@@ -1092,6 +1144,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     if (hk)
         for (size_t i = 0; i < n && !h.has_sub; i++) h.has_sub = hk[i] > 0.f;
     h.bpx = s->bpx; h.bpy = s->bpy; h.bpz = s->bpz;
+    for (int a = 0; a < 3; a++) h.bsh[a] = s->bsh[a];
     h.dx_cm = s->dx;
     h.r_cap = s->P.max_distance_cm > 0 ? s->P.max_distance_cm / s->dx : HUGE_VAL;
     h.op_a = s->op;

@@ -10,13 +10,19 @@
 #define FRT_MAX_BINS_I 8
 #define FRT_MAX_SOLVES_PER_LAUNCH 1024
 
-// Brick edge (cells) of the LDS-staged march: 16^3 cells of float2 opacity
-// plus float deposits is 48 KiB of LDS; the FP64 march uses 8^3 bricks.
-constexpr int FRT_BRICK_F32 = 16;
-constexpr int FRT_BRICK_F64 = 8;
-// Largest number of packets handed to one workgroup per work item (the
-// launch's item size, a tunable, is at most this).
+// Bricks of the LDS-staged march, edges 2^l per axis (x, y, z).  The FP32
+// march without sub-grid opacity stages 32 x 32 x 16 cells (64 KiB of HI
+// opacity, 64 KiB of deposits) for one 1024-thread workgroup per CU; with
+// sub-grid opacity 16^3 cells (both opacity parts and the deposits, 48 KiB)
+// for 256-thread workgroups; the FP64 march 8^3.
+constexpr int FRT_BRICK_LOG_BIG[3] = {5, 5, 4};
+constexpr int FRT_BRICK_LOG_SUB[3] = {4, 4, 4};
+constexpr int FRT_BRICK_LOG_F64[3] = {3, 3, 3};
+// Packets handed to a 256-thread march workgroup per work item, at most (the
+// launch's item size is a tunable); the 1024-thread workgroup takes four
+// times as many.
 constexpr uint32_t FRT_ITEM_RAYS = 1024;
+constexpr uint32_t FRT_ITEM_MAX = 4 * FRT_ITEM_RAYS;
 // Ledger accumulators are striped to keep atomics off a single address.
 constexpr int FRT_STRIPES = 64;
 // The pass output buffers (O and S) are cut into FRT_QSEG equal segments,
@@ -93,7 +99,8 @@ struct FrtSolveDesc {
     int nx, ny, nz, n_bins;
     int base_level, max_level, n_src, fp64;
     int has_sub;                // some cell has kappa > 0
-    int bpx, bpy, bpz, brick;   // bricks per axis and brick edge
+    int bpx, bpy, bpz;          // bricks per axis
+    int bsh[3];                 // log2 of the brick edge per axis
     uint32_t key_base;          // first global brick key of this solve in the launch
     uint32_t ncast;             // 12 * 4^L0
     double dx_cm, sigma0, R_ref;

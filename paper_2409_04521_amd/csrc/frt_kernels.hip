@@ -364,9 +364,8 @@ __device__ __forceinline__ bool locate(const FrtSolveDesc& D, const Real s[3], R
 
 __device__ __forceinline__ uint32_t brick_key(const FrtSolveDesc& D, const int c[3])
 {
-    const int sh = __builtin_ctz((unsigned)D.brick);   // bricks are 2^k cells on a side
-    return D.key_base + (uint32_t)(c[0] >> sh) +
-           (uint32_t)D.bpx * ((uint32_t)(c[1] >> sh) + (uint32_t)D.bpy * (uint32_t)(c[2] >> sh));
+    return D.key_base + (uint32_t)(c[0] >> D.bsh[0]) +
+           (uint32_t)D.bpx * ((uint32_t)(c[1] >> D.bsh[1]) + (uint32_t)D.bpy * (uint32_t)(c[2] >> D.bsh[2]));
 }
 
 __device__ __forceinline__ int find_in_prefix(const uint32_t* prefix, int n, uint32_t g)
@@ -413,13 +412,12 @@ template <typename Real>
 __device__ __forceinline__ uint32_t crossing_bin(const FrtSolveDesc& D, const int c[3], const Real s[3], const Real d[3],
                                                  Real r, Real rstop, int level)
 {
-    const int B = D.brick;
     const int dims[3] = {D.nx, D.ny, D.nz};
     const Real r_split = (level < D.max_level) ? (Real)(D.r_split0 * (double)(1u << level)) : rinf<Real>();
     Real lim = fmin(fmin(r_split, (Real)D.r_cap), rstop);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
-        const int lo = (c[a] / B) * B, hi = min(lo + B, dims[a]);
+        const int lo = (c[a] >> D.bsh[a]) << D.bsh[a], hi = min(lo + (1 << D.bsh[a]), dims[a]);
         if (d[a] > Real(0)) lim = fmin(lim, ((Real)hi - s[a]) * fast_rcp(d[a]));
         else if (d[a] < Real(0)) lim = fmin(lim, ((Real)lo - s[a]) * fast_rcp(d[a]));
     }
@@ -853,14 +851,15 @@ __device__ __forceinline__ uint32_t reserve_end(uint32_t raw, uint32_t off) { re
 // leaving the brick hands the packet to the next pass.  Ledger terms are
 // reduced per wave and added into LDS; output keys are counted in an LDS
 // table and added to the histogram once per work item.
-template <typename Real, int NB, bool SUB>
+template <typename Real, int NB, bool SUB, int LX, int LY, int LZ, int BT>
 __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
 {
     using R2 = typename Vec2<Real>::T;
     constexpr bool F32 = sizeof(Real) == 4;
-    constexpr int B = F32 ? FRT_BRICK_F32 : FRT_BRICK_F64;
-    constexpr int BC = B * B * B;
-    constexpr int PER = FRT_ITEM_RAYS / BLOCK;
+    constexpr int BX = 1 << LX, BY = 1 << LY, BZ = 1 << LZ;
+    constexpr int BC = BX * BY * BZ;
+    constexpr int PER = 4;                   // packets per thread in a full item
+    constexpr int ITEM = PER * BT;
     constexpr int NBIN = FRT_KEY_BINS;
     // staged opacity: {a_i, b_i} with sub-grid opacity, a_i alone without
     using OpT = typename std::conditional<SUB, R2, Real>::type;
@@ -870,7 +869,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
     __shared__ unsigned long long s_lc[LC_NC];
     __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
     __shared__ uint32_t s_bin[NBIN];
-    __shared__ uint16_t s_order[FRT_ITEM_RAYS];
+    __shared__ uint16_t s_order[ITEM];
     __shared__ uint32_t s_nv, s_chunk;
     const uint32_t nwork = ws.ctr[C_NWORK];
     const uint32_t np = ws.ctr[C_NP] < ws.P.cap ? ws.ctr[C_NP] : ws.P.cap;
@@ -914,12 +913,12 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
         const uint32_t lb = w.key - uni(D.key_base);
         const int bx = (int)(lb % (uint32_t)D.bpx), by = (int)((lb / (uint32_t)D.bpx) % (uint32_t)D.bpy),
                   bz = (int)(lb / ((uint32_t)D.bpx * (uint32_t)D.bpy));
-        const int ox = bx * B, oy = by * B, oz = bz * B;
+        const int ox = bx * BX, oy = by * BY, oz = bz * BZ;
         const int nx = uni(D.nx), ny = uni(D.ny), nz = uni(D.nz);
         const Real* __restrict__ opa = (const Real*)D.op_a;
         const Real* __restrict__ opb = (const Real*)D.op_b;
-        for (int t = threadIdx.x; t < BC; t += BLOCK) {
-            const int lx = t % B, ly = (t / B) % B, lz = t / (B * B);
+        for (int t = threadIdx.x; t < BC; t += BT) {
+            const int lx = t & (BX - 1), ly = (t >> LX) & (BY - 1), lz = t >> (LX + LY);
             const int cx = ox + lx, cy = oy + ly, cz = oz + lz;
             R2 v;
             v.x = Real(0);
@@ -940,7 +939,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
         uint32_t slot_of[PER];
 #pragma unroll
         for (int q = 0; q < PER; q++) {
-            const uint32_t j = (uint32_t)q * BLOCK + threadIdx.x;
+            const uint32_t j = (uint32_t)q * BT + threadIdx.x;
             slot_of[q] = 0xffffffffu;
             if (j < w.count && w.start + j < np) {
                 const uint32_t e = recs<Real>(ws.P)[w.start + j].key & (uint32_t)(NBIN - 1);
@@ -959,7 +958,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
 #pragma unroll
         for (int q = 0; q < PER; q++)
             if (slot_of[q] != 0xffffffffu)
-                s_order[s_bin[slot_of[q] >> 16] + (slot_of[q] & 0xffffu)] = (uint16_t)((uint32_t)q * BLOCK + threadIdx.x);
+                s_order[s_bin[slot_of[q] >> 16] + (slot_of[q] & 0xffffu)] = (uint16_t)((uint32_t)q * BT + threadIdx.x);
         __syncthreads();
         const Real r_cap = uni((Real)D.r_cap);
         const Real floor_f = uni((Real)D.floor);
@@ -1022,10 +1021,10 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 }
                 // cell within the brick, and the change of its LDS index per step
                 int lc[3] = {c[0] - ox, c[1] - oy, c[2] - oz};
-                const int inc[3] = {stp[0], stp[1] * B, stp[2] * B * B};
-                int li = lc[0] + B * (lc[1] + B * lc[2]);
+                const int inc[3] = {stp[0], stp[1] * BX, stp[2] * BX * BY};
+                int li = lc[0] + BX * (lc[1] + BY * lc[2]);
                 Real sub_acc = 0;
-                const bool in_brick = lc[0] >= 0 && lc[0] < B && lc[1] >= 0 && lc[1] < B && lc[2] >= 0 && lc[2] < B;
+                const bool in_brick = lc[0] >= 0 && lc[0] < BX && lc[1] >= 0 && lc[1] < BY && lc[2] >= 0 && lc[2] < BZ;
                 if (!in_brick) end = 4;            // hand it to the brick that holds its cell
                 const Real floor_abs = floor_f * sum0;
                 // photons left (in units of the cast weight), kept by
@@ -1131,7 +1130,8 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                     else if (axis == 1) rf[1] = rfa;
                     else rf[2] = rfa;
                     const int la = axis == 0 ? lc[0] : (axis == 1 ? lc[1] : lc[2]);
-                    if (la < 0 || la >= B) {
+                    const int ba = axis == 0 ? BX : (axis == 1 ? BY : BZ);
+                    if (la < 0 || la >= ba) {
                         end = (h.r >= h.rstop) ? 3 : 4;
                         break;
                     }
@@ -1238,10 +1238,10 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
         __syncthreads();
         // add the brick's deposits and its output-key counts once
         Real* __restrict__ gam = (Real*)D.gamma[D.step & 1u];
-        for (int t = threadIdx.x; t < BC; t += BLOCK) {
+        for (int t = threadIdx.x; t < BC; t += BT) {
             const Real v = s_g[t];
             if (v != Real(0)) {
-                const int lx = t % B, ly = (t / B) % B, lz = t / (B * B);
+                const int lx = t & (BX - 1), ly = (t >> LX) & (BY - 1), lz = t >> (LX + LY);
                 const size_t ci = (size_t)(ox + lx) + (size_t)nx * ((size_t)(oy + ly) + (size_t)ny * (size_t)(oz + lz));
                 atomicAdd(gam + ci, v);
             }
@@ -1268,19 +1268,22 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
     }
 }
 
+// 256-thread march on 16^3 (FP32 with sub-grid opacity) or 8^3 (FP64) bricks
 template <typename Real, int NB, bool SUB>
 __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
 {
-    brick_march<Real, NB, SUB>(descs, ws);
+    if constexpr (sizeof(Real) == 4)
+        brick_march<Real, NB, SUB, FRT_BRICK_LOG_SUB[0], FRT_BRICK_LOG_SUB[1], FRT_BRICK_LOG_SUB[2], BLOCK>(descs, ws);
+    else
+        brick_march<Real, NB, SUB, FRT_BRICK_LOG_F64[0], FRT_BRICK_LOG_F64[1], FRT_BRICK_LOG_F64[2], BLOCK>(descs, ws);
 }
 
-// The same kernel held to 128 registers, so that four workgroups (16
-// waves) share a CU: used where the LDS of four fits and the registers do
-// without spilling (FP32 march, no sub-grid opacity, up to 4 bins).
-template <typename Real, int NB, bool SUB>
-__global__ void __launch_bounds__(BLOCK) __attribute__((amdgpu_waves_per_eu(4))) k_brick_w4(FrtSolveDesc* descs, FrtWS ws)
+// 1024-thread march on 32 x 32 x 16 bricks (FP32 without sub-grid opacity):
+// one workgroup of 16 waves per CU, 128 registers each
+template <typename Real, int NB>
+__global__ void __launch_bounds__(4 * BLOCK) k_brick_big(FrtSolveDesc* descs, FrtWS ws)
 {
-    brick_march<Real, NB, SUB>(descs, ws);
+    brick_march<Real, NB, false, FRT_BRICK_LOG_BIG[0], FRT_BRICK_LOG_BIG[1], FRT_BRICK_LOG_BIG[2], 4 * BLOCK>(descs, ws);
 }
 
 // ================================================================ splitting
@@ -1540,7 +1543,7 @@ void launch_seed_nb(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
 
 // Resident workgroups per CU of a kernel (at least 1), queried once per
 // kernel.
-int blocks_per_cu(void (*kernel)(FrtSolveDesc*, FrtWS))
+int blocks_per_cu(void (*kernel)(FrtSolveDesc*, FrtWS), int threads)
 {
     static std::mutex mu;
     static std::unordered_map<const void*, int> known;
@@ -1548,38 +1551,47 @@ int blocks_per_cu(void (*kernel)(FrtSolveDesc*, FrtWS))
     const auto it = known.find((const void*)kernel);
     if (it != known.end()) return it->second;
     int b = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, BLOCK, 0) != hipSuccess || b < 1) b = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, kernel, threads, 0) != hipSuccess || b < 1) b = 1;
     known[(const void*)kernel] = b;
     return b;
 }
 
-// The march kernel of a launch and its grid (resident workgroups on every
-// CU; the occupancy query runs on the first call).
+// The march kernel of a launch, its workgroup size and its grid (resident
+// workgroups on every CU; the occupancy query runs on the first call).
+struct BrickLaunch {
+    void (*kernel)(FrtSolveDesc*, FrtWS);
+    int threads, per_cu;
+};
+
 template <typename Real, int NB>
-std::pair<void (*)(FrtSolveDesc*, FrtWS), int> brick_kernel(const FrtWS& ws)
+BrickLaunch brick_kernel(const FrtWS& ws)
 {
-    void (*brick)(FrtSolveDesc*, FrtWS);
-    int bpc;
-    if constexpr (sizeof(Real) == 4 && NB <= 4) {
-        if (ws.has_sub) { brick = k_brick<Real, NB, true>; bpc = blocks_per_cu(k_brick<Real, NB, true>); }
-        else { brick = k_brick_w4<Real, NB, false>; bpc = blocks_per_cu(k_brick_w4<Real, NB, false>); }
+    BrickLaunch b;
+    if constexpr (sizeof(Real) == 4) {
+        if (!ws.has_sub) {
+            b.kernel = k_brick_big<Real, NB>;
+            b.threads = 4 * BLOCK;
+        } else {
+            b.kernel = k_brick<Real, NB, true>;
+            b.threads = BLOCK;
+        }
     } else {
-        if (ws.has_sub) { brick = k_brick<Real, NB, true>; bpc = blocks_per_cu(k_brick<Real, NB, true>); }
-        else { brick = k_brick<Real, NB, false>; bpc = blocks_per_cu(k_brick<Real, NB, false>); }
+        b.kernel = ws.has_sub ? k_brick<Real, NB, true> : k_brick<Real, NB, false>;
+        b.threads = BLOCK;
     }
-    return {brick, bpc};
+    b.per_cu = blocks_per_cu(b.kernel, b.threads);
+    return b;
 }
 
 template <typename Real, int NB>
 void launch_pass_nb(FrtSolveDesc* d, const FrtWS& ws, int part, hipStream_t s)
 {
-    const auto bk = brick_kernel<Real, NB>(ws);
-    void (*brick)(FrtSolveDesc*, FrtWS) = bk.first;
-    const dim3 grid(cu_count() * bk.second);
+    const BrickLaunch bk = brick_kernel<Real, NB>(ws);
+    const dim3 grid(cu_count() * bk.per_cu);
     if (part == 0) hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws);
     else if (part == 1) hipLaunchKernelGGL((k_scatter<Real, NB>), dim3(cu_count() * ws.scatter_bpc), dim3(BLOCK), 0, s, ws);
     else if (part == 3) hipLaunchKernelGGL((k_split<Real>), dim3(cu_count() * ws.split_bpc), dim3(BLOCK), 0, s, d, ws);
-    else hipLaunchKernelGGL(brick, grid, dim3(BLOCK), 0, s, d, ws);
+    else hipLaunchKernelGGL(bk.kernel, grid, dim3(bk.threads), 0, s, d, ws);
 }
 
 template <typename Real>
