@@ -499,9 +499,9 @@ void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
     w.n_bins = ss[0]->P.n_bins;
     w.has_sub = 0;
     for (int i = 0; i < n; i++) w.has_sub |= ss[i]->h.has_sub;
-    // the 1024-thread march (FP32 without sub-grid opacity) takes four
-    // times the tuned item size
-    w.item_rays = (uint32_t)ws.tune.item_rays * ((!ss[0]->fp64 && !w.has_sub) ? 4u : 1u);
+    // the 1024-thread march (FP32 without sub-grid opacity) takes
+    // FRT_BIG_ITEM_SCALE times the tuned item size
+    w.item_rays = (uint32_t)ws.tune.item_rays * ((!ss[0]->fp64 && !w.has_sub) ? FRT_BIG_ITEM_SCALE : 1u);
     w.scatter_bpc = ws.tune.scatter_blocks_per_cu;
     w.split_bpc = ws.tune.split_blocks_per_cu;
     if (ss[0]->P.queue_capacity) {

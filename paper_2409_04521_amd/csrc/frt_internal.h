@@ -19,10 +19,11 @@ constexpr int FRT_BRICK_LOG_BIG[3] = {5, 5, 4};
 constexpr int FRT_BRICK_LOG_SUB[3] = {4, 4, 4};
 constexpr int FRT_BRICK_LOG_F64[3] = {3, 3, 3};
 // Packets handed to a 256-thread march workgroup per work item, at most (the
-// launch's item size is a tunable); the 1024-thread workgroup takes four
-// times as many.
+// launch's item size is a tunable); the 1024-thread workgroup takes
+// FRT_BIG_ITEM_SCALE times as many.
 constexpr uint32_t FRT_ITEM_RAYS = 1024;
-constexpr uint32_t FRT_ITEM_MAX = 4 * FRT_ITEM_RAYS;
+constexpr uint32_t FRT_BIG_ITEM_SCALE = 8;
+constexpr uint32_t FRT_ITEM_MAX = FRT_BIG_ITEM_SCALE * FRT_ITEM_RAYS;
 // Ledger accumulators are striped to keep atomics off a single address.
 constexpr int FRT_STRIPES = 64;
 // The pass output buffers (O and S) are cut into FRT_QSEG equal segments,
@@ -144,7 +145,7 @@ struct FrtWork {
     uint32_t key, start, count, solve;
 };
 
-enum { C_NOS = 0, C_NP, C_NWORK, C_ERR, C_MAXP, C_NCTR = 8 };
+enum { C_NOS = 0, C_NP, C_NWORK, C_ERR, C_MAXP, C_NEXT, C_NCTR = 8 };
 
 // Per-launch workspace: unsorted pass outputs O, packets sorted by brick P,
 // packets that reached their split radius S (with their photons), per-key

@@ -566,7 +566,8 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
 // ============================================================ counting scan
 // One block: offsets of each brick's packets in the sorted buffer, the work
 // list (items of at most item_rays packets of one brick), scatter
-// cursors; clears the histogram and the output counter.
+// cursors; clears the histogram, the output counters and the counter the
+// march workgroups take items from.
 __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
 {
     __shared__ uint32_t s_a[1024], s_b[1024];
@@ -633,6 +634,7 @@ __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
     if (threadIdx.x == 0) {
         ws.ctr[C_NP] = total;
         ws.ctr[C_NWORK] = total_items < ws.cap_work ? total_items : ws.cap_work;
+        ws.ctr[C_NEXT] = 0;
         if (total > ws.ctr[C_MAXP]) ws.ctr[C_MAXP] = total;
         if (total > ws.P.cap || total_items > ws.cap_work) ws.ctr[C_ERR] |= FRT_DEVERR_QUEUE_OVERFLOW;
     }
@@ -858,8 +860,11 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
     constexpr bool F32 = sizeof(Real) == 4;
     constexpr int BX = 1 << LX, BY = 1 << LY, BZ = 1 << LZ;
     constexpr int BC = BX * BY * BZ;
-    constexpr int PER = 4;                   // packets per thread in a full item
-    constexpr int ITEM = PER * BT;
+    // a full item: FRT_ITEM_RAYS packets for 256 threads, FRT_ITEM_MAX for 1024
+    constexpr int ITEM = BT >= 1024 ? (int)FRT_ITEM_MAX : (int)FRT_ITEM_RAYS;
+    constexpr int PER = ITEM / BT;           // packets per thread in a full item
+    constexpr int NST = BC / BT;             // brick cells staged per thread
+    static_assert(BC % BT == 0 && ITEM % BT == 0 && ITEM <= 65536 && FRT_KEY_BINS == 64, "brick and item shapes");
     constexpr int NBIN = FRT_KEY_BINS;
     // staged opacity: {a_i, b_i} with sub-grid opacity, a_i alone without
     using OpT = typename std::conditional<SUB, R2, Real>::type;
@@ -870,7 +875,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
     __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
     __shared__ uint32_t s_bin[NBIN];
     __shared__ uint16_t s_order[ITEM];
-    __shared__ uint32_t s_nv, s_chunk;
+    __shared__ uint32_t s_nv, s_chunk, s_next;
     const uint32_t nwork = ws.ctr[C_NWORK];
     const uint32_t np = ws.ctr[C_NP] < ws.P.cap ? ws.ctr[C_NP] : ws.P.cap;
     const int lane = threadIdx.x & (WAVE - 1);
@@ -878,7 +883,11 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
     if (threadIdx.x < LC_NC) s_lc[threadIdx.x] = 0;
     if (threadIdx.x < KEY_SLOTS) { s_key[threadIdx.x] = 0xffffffffu; s_cnt[threadIdx.x] = 0; }
     int cs = -1;
-    for (uint32_t item = blockIdx.x; item < nwork; item += gridDim.x) {
+    // workgroups take items in list order from a counter as they finish
+    // one; the next index is fetched while the current item runs
+    if (threadIdx.x == 0) s_next = atomicAdd(&ws.ctr[C_NEXT], 1u);
+    __syncthreads();
+    for (uint32_t item = uni(s_next); item < nwork; item = uni(s_next)) {
         FrtWork w = ws.work[item];
         w.key = uni(w.key);
         w.start = uni(w.start);
@@ -917,35 +926,63 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
         const int nx = uni(D.nx), ny = uni(D.ny), nz = uni(D.nz);
         const Real* __restrict__ opa = (const Real*)D.op_a;
         const Real* __restrict__ opb = (const Real*)D.op_b;
-        for (int t = threadIdx.x; t < BC; t += BT) {
+        // all of the item's loads at once: its packets' crossing bins (NBIN
+        // marks no packet), then the brick's opacities
+        uint32_t eq[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const uint32_t j = (uint32_t)q * BT + threadIdx.x;
+            eq[q] = NBIN;
+            if (j < w.count && w.start + j < np) eq[q] = recs<Real>(ws.P)[w.start + j].key & (uint32_t)(NBIN - 1);
+        }
+        R2 st[NST];
+#pragma unroll
+        for (int k = 0; k < NST; k++) {
+            const int t = k * BT + (int)threadIdx.x;
             const int lx = t & (BX - 1), ly = (t >> LX) & (BY - 1), lz = t >> (LX + LY);
             const int cx = ox + lx, cy = oy + ly, cz = oz + lz;
-            R2 v;
-            v.x = Real(0);
-            v.y = Real(0);
+            st[k].x = Real(0);
+            st[k].y = Real(0);
             if (cx < nx && cy < ny && cz < nz) {
                 const size_t ci = (size_t)cx + (size_t)nx * ((size_t)cy + (size_t)ny * (size_t)cz);
-                v.x = opa[ci];
-                if constexpr (SUB) v.y = opb[ci];
+                st[k].x = opa[ci];
+                if constexpr (SUB) st[k].y = opb[ci];
             }
-            if constexpr (SUB) s_op[t] = v;
-            else s_op[t] = v.x;
+        }
+        // the next item's index, fetched while these loads are in flight
+        uint32_t next_raw = 0;
+        if (threadIdx.x == 0) next_raw = atomicAdd(&ws.ctr[C_NEXT], 1u);
+#pragma unroll
+        for (int k = 0; k < NST; k++) {
+            const int t = k * BT + (int)threadIdx.x;
+            if constexpr (SUB) s_op[t] = st[k];
+            else s_op[t] = st[k].x;
             s_g[t] = Real(0);
         }
         if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
         if (threadIdx.x == 0) s_chunk = 0;
         __syncthreads();
-        // ---- order the item's packets by expected crossings
+        // ---- order the item's packets by expected crossings: a counting
+        // sort whose bin counts are taken once per distinct bin of a wave
         uint32_t slot_of[PER];
 #pragma unroll
         for (int q = 0; q < PER; q++) {
-            const uint32_t j = (uint32_t)q * BT + threadIdx.x;
-            slot_of[q] = 0xffffffffu;
-            if (j < w.count && w.start + j < np) {
-                const uint32_t e = recs<Real>(ws.P)[w.start + j].key & (uint32_t)(NBIN - 1);
-                slot_of[q] = (e << 16) | atomicAdd(&s_bin[e], 1u);
+            const uint32_t e = eq[q];
+            const bool valid = e < (uint32_t)NBIN;
+            unsigned long long peers = __ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 6; b++) {
+                const bool bit = (e >> b) & 1u;
+                const unsigned long long m = __ballot(bit);
+                peers &= bit ? m : ~m;
             }
+            const int leader = valid ? __ffsll(peers) - 1 : lane;
+            uint32_t base = 0;
+            if (valid && lane == leader) base = atomicAdd(&s_bin[e], (uint32_t)__popcll(peers));
+            base = (uint32_t)__shfl((int)base, leader, WAVE);
+            slot_of[q] = valid ? ((e << 16) | (base + lanes_below(peers))) : 0xffffffffu;
         }
+        if (threadIdx.x == 0) s_next = next_raw;   // read once this item is done
         __syncthreads();
         if (threadIdx.x < WAVE) {
             uint32_t tot;
