@@ -343,7 +343,11 @@ def main():
            "config": {"workload": f"{prob.name}: GRF k^-2.5 ln-sigma 1.5, peaks as sources, x_HI=1e-4, "
                                   f"c=inf, {nb} bins, floor 1e-3, cap 50 cMpc/h, l_max 12",
                       "cells": prob.ncell, "sources": prob.n_src, "crossings_per_step": cross / args.steps,
-                      "visits_per_step": d_visits / args.steps, "ledger_closure": closure,
+                      "visits_per_step": d_visits / args.steps,
+                      "splits_per_step": (L1["splits"] - L0["splits"]) / args.steps,
+                      "escapes_per_step": (L1["n_escaped"] - L0["n_escaped"]) / args.steps,
+                      "drops_per_step": (L1["n_dropped"] - L0["n_dropped"]) / args.steps,
+                      "ledger_closure": closure,
                       "max_pass_packets": L1["max_items"],
                       "steps_start_from": "the configured state, rewound on the device before each step",
                       "parallelism": "single GPU"},

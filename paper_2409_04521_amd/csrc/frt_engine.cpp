@@ -108,7 +108,13 @@ int copy_recs(FrtRecs& dst, const FrtRecs& src, uint32_t n, int nb, size_t rs, h
 // (one step at a time: the mutex serializes launches that use it).
 struct Workspace {
     int fp64 = -1, nb = 0;
-    FrtRecs O{}, P{}, S{};
+    // pass outputs (two buffers used in turn, with each record's key), the
+    // sorted input index of a pass, the split queue and its photons
+    FrtRecs O[2] = {};
+    uint32_t* okey[2] = {nullptr, nullptr};
+    uint2* sorted = nullptr;
+    uint32_t pcap = 0;              // records per output buffer and sorted entries
+    FrtRecs S{};
     double* s_phot = nullptr;
     uint32_t* segc = nullptr;
     uint32_t* segp = nullptr;
@@ -126,12 +132,21 @@ struct Workspace {
     FrtSolveDesc* descs = nullptr;
     int solves_cap = 0;
 
-    void release()
+    void free_pass()
     {
-        free_recs(O);
-        free_recs(P);
+        for (int k = 0; k < 2; k++) {
+            free_recs(O[k]);
+            dev_free(okey[k]);
+        }
+        dev_free(sorted);
+        pcap = 0;
         free_recs(S);
         dev_free(s_phot);
+    }
+
+    void release()
+    {
+        free_pass();
         dev_free(segc);
         dev_free(segp);
         if (ctr_host) (void)hipHostFree(ctr_host);
@@ -371,24 +386,23 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
 {
     const size_t rs = fp64 ? 8 : 4;
     if (ws.fp64 != fp64 || ws.nb != nb) {
-        free_recs(ws.O);
-        free_recs(ws.P);
-        free_recs(ws.S);
-        dev_free(ws.s_phot);
+        ws.free_pass();
         ws.fp64 = fp64;
         ws.nb = nb;
     }
     want_p = std::min<uint64_t>(want_p, 2147483647ull);
-    if (ws.P.cap < want_p) {
-        free_recs(ws.O);
-        free_recs(ws.P);
-        free_recs(ws.S);
-        dev_free(ws.s_phot);
-        // a pass writes four children per split into O, so half of O's
-        // capacity bounds the splits of a pass that does not overflow O
+    if (ws.pcap < want_p) {
+        ws.free_pass();
+        // a pass writes four children per split into its output, so half of
+        // the output capacity bounds the splits of a pass that does not
+        // overflow it
         const uint32_t scap = (uint32_t)std::max<uint64_t>(want_p / 2, 1024);
-        RCCHK(alloc_recs(ws.O, (uint32_t)want_p, nb, rs));
-        RCCHK(alloc_recs(ws.P, (uint32_t)want_p, nb, rs));
+        for (int k = 0; k < 2; k++) {
+            RCCHK(alloc_recs(ws.O[k], (uint32_t)want_p, nb, rs));
+            RCCHK(dev_alloc((void**)&ws.okey[k], (size_t)want_p * 4));
+        }
+        RCCHK(dev_alloc((void**)&ws.sorted, (size_t)want_p * sizeof(uint2)));
+        ws.pcap = (uint32_t)want_p;
         RCCHK(alloc_recs(ws.S, scap, nb, rs));
         RCCHK(dev_alloc((void**)&ws.s_phot, (size_t)scap * 8));
         dev_free(ws.work);
@@ -414,7 +428,7 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
         dev_free(ws.work);
         ws.cap_work = 0;
     }
-    const uint64_t want_work = (uint64_t)ws.P.cap / (uint64_t)ws.tune.item_rays + ws.nkeys_cap + 64;
+    const uint64_t want_work = (uint64_t)ws.pcap / (uint64_t)ws.tune.item_rays + ws.nkeys_cap + 64;
     if (ws.cap_work < want_work) {
         dev_free(ws.work);
         RCCHK(dev_alloc((void**)&ws.work, want_work * sizeof(FrtWork)));
@@ -481,8 +495,13 @@ void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
     }
     FrtWS& w = g.w;
     w = FrtWS{};
-    w.O = ws.O;
-    w.P = ws.P;
+    for (int k = 0; k < 2; k++) {
+        w.buf[k] = ws.O[k];
+        w.bkey[k] = ws.okey[k];
+    }
+    w.out = 0;
+    w.sorted = ws.sorted;
+    w.pcap = ws.pcap;
     w.S = ws.S;
     w.s_phot = ws.s_phot;
     w.segc = ws.segc;
@@ -508,9 +527,10 @@ void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
         // fixed capacities: the shared workspace is used up to the solves' limit
         uint64_t lim = 0;
         for (int i = 0; i < n; i++) lim += ss[i]->P.queue_capacity;
-        const uint32_t c = (uint32_t)std::min<uint64_t>(lim, w.P.cap);
-        w.O.cap = c;
-        w.P.cap = c;
+        const uint32_t c = (uint32_t)std::min<uint64_t>(lim, w.pcap);
+        w.buf[0].cap = c;
+        w.buf[1].cap = c;
+        w.pcap = c;
         w.S.cap = std::min<uint32_t>(w.S.cap, std::max<uint32_t>(c / 2, 1024));
     }
 }
@@ -532,7 +552,7 @@ int upload_group(Workspace& ws, const Group& g, int n, hipStream_t st)
 int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_t st, bool graph)
 {
     const int fp64 = ss[0]->fp64;
-    const FrtWS& w = g.w;
+    FrtWS w = g.w;
     frt_solve tm = (!graph && ss[0]->timing) ? ss[0] : nullptr;
     hipError_t e;
     if (graph)
@@ -542,10 +562,12 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
         }
     {
         Timed t(tm, st, 0);
+        w.out = 0;   // seeds fill buffer 0, the input of the first pass
         if ((e = frt::launch_clear(w, st)) != hipSuccess) return fail(FRT_EDEVICE, "clear: %s", hipGetErrorString(e));
         if ((e = frt::launch_seed(ws.descs, w, fp64, st)) != hipSuccess) return fail(FRT_EDEVICE, "seed: %s", hipGetErrorString(e));
     }
     for (int p = 0; p < g.passes; p++) {
+        w.out = (p + 1) & 1;   // pass p reads buffer p & 1 and fills the other
         {
             Timed t(tm, st, 3);
             if ((e = frt::launch_pass(ws.descs, w, fp64, 0, st)) != hipSuccess) return fail(FRT_EDEVICE, "scan: %s", hipGetErrorString(e));
@@ -620,8 +642,8 @@ int recover_overflow(Workspace& ws, frt_solve* ss, int n, const uint32_t* ctr, u
     }
     HIPCHK(hipStreamSynchronize(st));
     if (ctr[C_ERR] & FRT_DEVERR_QUEUE_OVERFLOW) {
-        if (ws.P.cap >= 2147483647u) return fail(FRT_EOVERFLOW, "pass buffers at their maximum size still overflow");
-        const uint64_t need = std::max<uint64_t>(2ull * ws.P.cap, (uint64_t)ctr[C_MAXP] + (ctr[C_MAXP] >> 2) + 65536);
+        if (ws.pcap >= 2147483647u) return fail(FRT_EOVERFLOW, "pass buffers at their maximum size still overflow");
+        const uint64_t need = std::max<uint64_t>(2ull * ws.pcap, (uint64_t)ctr[C_MAXP] + (ctr[C_MAXP] >> 2) + 65536);
         *want_p = std::min<uint64_t>(need, 2147483647ull);
     }
     for (int i = 0; i < n; i++) {
@@ -707,7 +729,7 @@ int step_group_locked(frt_solve* ss, int n, const double* dts)
         set_step_fields(ss[i], dts[i]);
     }
     for (int attempt = 0; attempt < 16; attempt++) {
-        RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.P.cap)));
+        RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.pcap)));
         for (int i = 0; i < n; i++) {
             HIPCHK(hipMemcpyAsync(ss[i]->L_snap, ss[i]->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
             HIPCHK(hipMemcpyAsync(ss[i]->fcount_snap, ss[i]->fcount, 8, hipMemcpyDeviceToDevice, st));
@@ -785,7 +807,7 @@ int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps)
     while (done < n_steps) {
         if (!sg.exec) {
             for (int i = 0; i < n; i++) set_step_fields(ss[i], dts[i]);
-            RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.P.cap)));
+            RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.pcap)));
             plan_group(ws, ss, n, g);
             RCCHK(upload_group(ws, g, n, st));
             HIPCHK(hipStreamSynchronize(st));
@@ -938,11 +960,12 @@ uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T,
     b += 2 * (uint64_t)F * rec;
     // sources, photon rates, 64 steps of rotations, ledgers
     b += (uint64_t)n_src * (24 + 12 * (uint64_t)P.n_bins) + 64ull * n_src * 32 + 2 * sizeof(FrtLedgerDev);
-    // share of the pass queues: O and P, S at half size with its photons, work list
+    // share of the pass queues: two output buffers with their keys, the
+    // sorted index, S at half size with its photons, work list
     const uint64_t wp = P.queue_capacity ? P.queue_capacity
                                          : (P.queue_hint ? P.queue_hint : std::max<uint64_t>(4 * cast + 65536, ncell / 2));
     if (pass_records) *pass_records = wp;
-    b += wp * (2 * rec + rec / 2 + 4) + wp / 64 * sizeof(FrtWork);
+    b += wp * (2 * rec + 8 + sizeof(uint2) + rec / 2 + 4) + wp / 64 * sizeof(FrtWork);
     return b;
 }
 

@@ -151,10 +151,18 @@ enum { C_NOS = 0, C_NP, C_NWORK, C_ERR, C_MAXP, C_NEXT, C_NCTR = 8 };
 // packets that reached their split radius S (with their photons), per-key
 // histogram and scatter cursors, the work list, counters.
 struct FrtWS {
-    FrtRecs O, P, S;
+    // pass outputs, double-buffered: a launch appends to buf[out] (records,
+    // and each record's key in bkey[out]) and reads the previous pass's
+    // outputs from buf[out ^ 1] through `sorted`
+    FrtRecs buf[2];
+    uint32_t* bkey[2];
+    int out;
+    uint2* sorted;              // [pcap] (record index in the input buffer, crossing bin) in brick order
+    uint32_t pcap;
+    FrtRecs S;
     double* s_phot;
     uint32_t* segc;             // [2][FRT_QSEG][FRT_QSEG_STRIDE] fill counters of O, then of S
-    uint32_t* segp;             // [FRT_QSEG + 1] first O entry of each segment in pass order
+    uint32_t* segp;             // [FRT_QSEG + 1] first input entry of each segment in pass order
     uint32_t* ctr;              // [C_NCTR]
     uint32_t* hist;             // [nkeys]
     uint32_t* cursor;           // [nkeys]

@@ -3,15 +3,18 @@
 // ionizing photon packets (Cain & D'Aloisio, FlexRT I, §3 and §4.1).
 //
 // A step runs as a sequence of passes.  The grid is cut into bricks
-// (16^3 cells for the FP32 march, 8^3 for FP64).  In each pass every brick
-// that holds packets is given to workgroups: a workgroup stages the brick's
-// opacity in LDS, walks each of its packets cell by cell until the packet
-// leaves the brick, splits, ends or spends its travel budget, deposits the
-// absorbed photons with LDS atomics, and adds the brick's deposits to the
-// global rate field once.  Packets that leave or split are written out with
-// the key of the brick they are in next; a counting pass and a scatter sort
-// them by brick for the next pass.  Item counts live on the device, so the
-// host launches a fixed number of passes without reading anything back.
+// (32 x 32 x 16 cells for the FP32 march without sub-grid opacity, 16^3 with
+// it, 8^3 for FP64).  In each pass every brick that holds packets is given
+// to workgroups: a workgroup stages the brick's opacity in LDS, walks each
+// of its packets cell by cell until the packet leaves the brick, splits,
+// ends or spends its travel budget, deposits the absorbed photons with LDS
+// atomics, and adds the brick's deposits to the global rate field once.
+// Packets that leave or split are appended to the pass's output buffer with
+// the key of the brick they are in next; a counting pass and a scatter put
+// their indices in brick order, and the next pass reads the records through
+// them (the two output buffers alternate).  Item counts live on the device,
+// so the host launches a fixed number of passes without reading anything
+// back.
 #include "frt_internal.h"
 
 #include <hip/hip_runtime.h>
@@ -300,6 +303,12 @@ __device__ __forceinline__ void unpack_cell(uint32_t p, int c[3])
 template <typename Real>
 __device__ __forceinline__ FrtRec<Real>* recs(const FrtRecs& q) { return (FrtRec<Real>*)q.rec; }
 
+// The pass buffer a launch appends to and the one holding its input (both
+// have the same capacity), and their key arrays.
+__device__ __forceinline__ FrtRecs out_recs(const FrtWS& ws) { return FrtRecs{ws.out ? ws.buf[1].rec : ws.buf[0].rec, ws.buf[0].cap}; }
+__device__ __forceinline__ FrtRecs in_recs(const FrtWS& ws) { return FrtRecs{ws.out ? ws.buf[0].rec : ws.buf[1].rec, ws.buf[0].cap}; }
+__device__ __forceinline__ const uint32_t* in_keys(const FrtWS& ws) { return ws.out ? ws.bkey[0] : ws.bkey[1]; }
+
 template <typename Real>
 __device__ __forceinline__ void load_pkt(const FrtRecs& q, uint32_t i, Pkt<Real>& h, Real* T)
 {
@@ -334,6 +343,14 @@ __device__ __forceinline__ void store_pkt(const FrtRecs& q, uint32_t i, const Pk
 #pragma unroll
     for (int b = 0; b < 4; b++) x.tau[b] = T[b];
     recs<Real>(q)[i] = x;
+}
+
+// Append slot i of the launch's output buffer: the record and its key.
+template <typename Real>
+__device__ __forceinline__ void store_out(const FrtWS& ws, uint32_t i, const Pkt<Real>& h, uint32_t key, const Real* T)
+{
+    store_pkt<Real>(out_recs(ws), i, h, key, T);
+    (ws.out ? ws.bkey[1] : ws.bkey[0])[i] = key;
 }
 
 template <typename Real>
@@ -552,8 +569,8 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
         }
         const uint32_t at = wave_reserve(o_ctr(ws, my_seg()), want);
         if (want) {
-            if (at < seg_cap(ws.O.cap)) {
-                store_pkt<Real>(ws.O, (uint32_t)my_seg() * seg_cap(ws.O.cap) + at, h, key_with_bin(key, bin), T);
+            if (at < seg_cap(ws.buf[0].cap)) {
+                store_out<Real>(ws, (uint32_t)my_seg() * seg_cap(ws.buf[0].cap) + at, h, key_with_bin(key, bin), T);
                 atomicAdd(&ws.hist[key], 1u);
             } else {
                 raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
@@ -597,7 +614,7 @@ __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
     const uint32_t total_items = s_b[blockDim.x - 1];
     // the previous pass's outputs in segment order; clear the fill counters
     if (threadIdx.x < WAVE) {
-        const uint32_t cap = seg_cap(ws.O.cap);
+        const uint32_t cap = seg_cap(ws.buf[0].cap);
         const uint32_t c = *o_ctr(ws, threadIdx.x);
         if (c > cap) atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_QUEUE_OVERFLOW);
         uint32_t tot;
@@ -636,16 +653,16 @@ __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
         ws.ctr[C_NWORK] = total_items < ws.cap_work ? total_items : ws.cap_work;
         ws.ctr[C_NEXT] = 0;
         if (total > ws.ctr[C_MAXP]) ws.ctr[C_MAXP] = total;
-        if (total > ws.P.cap || total_items > ws.cap_work) ws.ctr[C_ERR] |= FRT_DEVERR_QUEUE_OVERFLOW;
+        if (total > ws.pcap || total_items > ws.cap_work) ws.ctr[C_ERR] |= FRT_DEVERR_QUEUE_OVERFLOW;
     }
 }
 
 // ================================================================= scatter
-// Move the pass outputs into brick order.  A block takes 256 consecutive
-// outputs (written by few waves, so few distinct bricks), counts them per
-// brick in an LDS hash table, reserves each brick's range with one atomic,
-// and copies the records.
-template <typename Real, int NB>
+// Put the previous pass's outputs in brick order without moving them: a
+// block takes SLOTS consecutive outputs (written by few waves, so few
+// distinct bricks), counts them per brick in an LDS hash table, reserves
+// each brick's range with one atomic, and writes (record index, crossing
+// bin) there.  Only the keys are read.
 __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
 {
     // PER outputs per thread and round; the table has a slot for every
@@ -657,42 +674,39 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
     __shared__ uint32_t s_sp[FRT_QSEG + 1];
     for (int i = threadIdx.x; i <= FRT_QSEG; i += blockDim.x) s_sp[i] = ws.segp[i];
     const uint32_t n = ws.ctr[C_NOS];
-    const uint32_t scap = seg_cap(ws.O.cap);
+    const uint32_t scap = seg_cap(ws.buf[0].cap);
+    const uint32_t* __restrict__ keys = in_keys(ws);
     const int lane = threadIdx.x & (WAVE - 1);
     const unsigned long long upto = (lane == WAVE - 1) ? ~0ull : ((2ull << lane) - 1ull);
-    // records move as 16-byte words; the key is the low word of the second
-    constexpr int NW = (int)(sizeof(FrtRec<Real>) / 16);
-    const uint4* __restrict__ O = (const uint4*)ws.O.rec;
-    uint4* __restrict__ P = (uint4*)ws.P.rec;
+    __syncthreads();
     for (uint32_t base = blockIdx.x * SLOTS; base < n; base += gridDim.x * SLOTS) {
         for (int i = threadIdx.x; i < SLOTS; i += blockDim.x) {
             s_key[i] = EMPTY;
             s_cnt[i] = 0;
         }
-        __syncthreads();
-        // PER separate items (not an array) keep the records in registers
-        struct Item {
-            uint4 w[NW];
-            uint32_t slot, rank, bin;
-            bool ok;
-        };
-        auto gather = [&](Item& it, uint32_t v) {
-            uint32_t key = EMPTY;
-            it.ok = false;
-            it.bin = 0;
+        // the round's keys, all loads issued together
+        uint32_t idx[PER], kw[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            const uint32_t v = base + (uint32_t)q * BLOCK + threadIdx.x;
+            idx[q] = EMPTY;
+            kw[q] = EMPTY;
             if (v < n) {
                 const int sg = find_in_prefix(s_sp, FRT_QSEG, v);
-                const size_t at = ((size_t)sg * scap + (v - s_sp[sg])) * NW;
-#pragma unroll
-                for (int w = 0; w < NW; w++) it.w[w] = O[at + w];
-                it.bin = it.w[1].x >> FRT_KEY_BITS;
-                key = it.w[1].x & FRT_KEY_MASK;
-                if (key >= ws.nkeys) {          // never expected: flag and skip
-                    atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_QUEUE_OVERFLOW);
-                    key = EMPTY;
-                }
-                it.ok = key != EMPTY;
+                idx[q] = (uint32_t)sg * scap + (v - s_sp[sg]);
+                kw[q] = keys[idx[q]];
             }
+        }
+        __syncthreads();
+        uint32_t slot[PER], rank[PER];
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            uint32_t key = idx[q] == EMPTY ? EMPTY : (kw[q] & FRT_KEY_MASK);
+            if (key != EMPTY && key >= ws.nkeys) {      // never expected: flag and skip
+                atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_QUEUE_OVERFLOW);
+                key = EMPTY;
+            }
+            if (key == EMPTY) idx[q] = EMPTY;
             // lanes with equal keys next to each other (outputs of one wave of
             // the march mostly are) count as one run: its first lane inserts
             // the key once and reserves the run's ranks with one LDS atomic
@@ -712,34 +726,19 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
                 }
                 r0 = atomicAdd(&s_cnt[sl], len);
             }
-            it.slot = __shfl(sl, start, WAVE);
-            it.rank = __shfl(r0, start, WAVE) + (uint32_t)(lane - start);
-        };
-        auto put = [&](Item& it) {
-            if (!it.ok) return;
-            const uint32_t pos = s_base[it.slot] + it.rank;
-            if (pos < ws.P.cap) {
-                uint4* dst = P + (size_t)pos * NW;
-                dst[0] = it.w[0];
-                dst[1] = make_uint4(it.bin, it.w[1].y, it.w[1].z, it.w[1].w);   // sorted records keep only the crossing bin
-#pragma unroll
-                for (int w = 2; w < NW; w++) dst[w] = it.w[w];
-            }
-        };
-        static_assert(PER == 4, "four items per thread");
-        Item i0, i1, i2, i3;
-        gather(i0, base + threadIdx.x);
-        gather(i1, base + BLOCK + threadIdx.x);
-        gather(i2, base + 2 * BLOCK + threadIdx.x);
-        gather(i3, base + 3 * BLOCK + threadIdx.x);
+            slot[q] = __shfl(sl, start, WAVE);
+            rank[q] = __shfl(r0, start, WAVE) + (uint32_t)(lane - start);
+        }
         __syncthreads();
         for (int j = threadIdx.x; j < SLOTS; j += blockDim.x)
             if (s_key[j] != EMPTY) s_base[j] = atomicAdd(&ws.cursor[s_key[j]], s_cnt[j]);
         __syncthreads();
-        put(i0);
-        put(i1);
-        put(i2);
-        put(i3);
+#pragma unroll
+        for (int q = 0; q < PER; q++) {
+            if (idx[q] == EMPTY) continue;
+            const uint32_t pos = s_base[slot[q]] + rank[q];
+            if (pos < ws.pcap) ws.sorted[pos] = make_uint2(idx[q], kw[q] >> FRT_KEY_BITS);
+        }
         __syncthreads();
     }
 }
@@ -877,7 +876,8 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
     __shared__ uint16_t s_order[ITEM];
     __shared__ uint32_t s_nv, s_chunk, s_next;
     const uint32_t nwork = ws.ctr[C_NWORK];
-    const uint32_t np = ws.ctr[C_NP] < ws.P.cap ? ws.ctr[C_NP] : ws.P.cap;
+    const uint32_t np = ws.ctr[C_NP] < ws.pcap ? ws.ctr[C_NP] : ws.pcap;
+    const FrtRecs in_q = in_recs(ws);
     const int lane = threadIdx.x & (WAVE - 1);
     if (threadIdx.x < LF_NF) s_lf[threadIdx.x] = 0.0;
     if (threadIdx.x < LC_NC) s_lc[threadIdx.x] = 0;
@@ -933,7 +933,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
         for (int q = 0; q < PER; q++) {
             const uint32_t j = (uint32_t)q * BT + threadIdx.x;
             eq[q] = NBIN;
-            if (j < w.count && w.start + j < np) eq[q] = recs<Real>(ws.P)[w.start + j].key & (uint32_t)(NBIN - 1);
+            if (j < w.count && w.start + j < np) eq[q] = ws.sorted[w.start + j].y;
         }
         R2 st[NST];
 #pragma unroll
@@ -1026,7 +1026,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
             double v_abs = 0.0, v_sub = 0.0, v_end = 0.0;
             uint32_t v_cross = 0;
             if (active) {
-                load_pkt<Real>(ws.P, w.start + j, h, T);
+                load_pkt<Real>(in_q, ws.sorted[w.start + j].x, h, T);
                 level = (int)(h.lp >> 28);
                 const double* sp = D.src_pos + (size_t)h.src * 3;
                 s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
@@ -1069,19 +1069,25 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 Real sumE = 0;
 #pragma unroll
                 for (int b = 0; b < NB; b++) sumE += NE[b];
+                // the opacity of the current cell; each step reads the next
+                // cell's one iteration ahead (an index outside the brick, for a
+                // packet about to leave it, reads cell 0 and is not used)
+                OpT o_cur = s_op[(uint32_t)li < (uint32_t)BC ? li : 0];
                 while (end < 0) {
                     int axis = 0;
                     Real r_face = rf[0];
                     if (rf[1] < r_face) { r_face = rf[1]; axis = 1; }
                     if (rf[2] < r_face) { r_face = rf[2]; axis = 2; }
+                    const int li_n = li + (axis == 0 ? inc[0] : (axis == 1 ? inc[1] : inc[2]));
+                    const OpT o_next = s_op[(uint32_t)li_n < (uint32_t)BC ? li_n : 0];
                     const Real r_end = fmax(fmin(r_face, r_lim), h.r);
                     const Real ds = r_end - h.r;
                     if (ds > Real(0)) {
                         R2 o;
                         if constexpr (SUB) {
-                            o = s_op[li];
+                            o = o_cur;
                         } else {
-                            o.x = s_op[li];
+                            o.x = o_cur;
                             o.y = Real(0);
                         }
                         const Real ta = o.x * ds;
@@ -1156,7 +1162,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                     if (axis == 0) { c[0] += st; lc[0] += st; }
                     else if (axis == 1) { c[1] += st; lc[1] += st; }
                     else { c[2] += st; lc[2] += st; }
-                    li += axis == 0 ? inc[0] : (axis == 1 ? inc[1] : inc[2]);
+                    li = li_n;
                     const int ca = axis == 0 ? c[0] : (axis == 1 ? c[1] : c[2]);
                     const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
                     if (ca < 0 || ca >= dima) { end = 1; break; }
@@ -1173,6 +1179,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                         break;
                     }
                     if (h.r >= h.rstop) { end = 3; break; }
+                    o_cur = o_next;
                 }
                 // photons at the end of the visit from the carried optical
                 // depth, exactly as the next visit will recompute them
@@ -1225,8 +1232,8 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 bool stored = false;
                 if (end == 4) {
                     key = key_with_bin(brick_key(D, c), crossing_bin<Real>(D, c, s, h.d, h.r, h.rstop, level));
-                    if (at < seg_cap(ws.O.cap)) {
-                        store_pkt<Real>(ws.O, (uint32_t)my_seg() * seg_cap(ws.O.cap) + at, h, key, T);
+                    if (at < seg_cap(ws.buf[0].cap)) {
+                        store_out<Real>(ws, (uint32_t)my_seg() * seg_cap(ws.buf[0].cap) + at, h, key, T);
                         stored = true;
                     } else {
                         raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
@@ -1345,7 +1352,7 @@ __global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
     }
     __syncthreads();
     const uint32_t ns = s_sp[FRT_QSEG];
-    const uint32_t ocap = seg_cap(ws.O.cap);
+    const uint32_t ocap = seg_cap(ws.buf[0].cap);
     const uint32_t k = threadIdx.x & 3u;
     for (uint32_t base = blockIdx.x * PARENTS; base < ns; base += gridDim.x * PARENTS) {
         const uint32_t v = base + threadIdx.x / 4u;
@@ -1384,7 +1391,7 @@ __global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
                 h.d[0] = cd[0];
                 h.d[1] = cd[1];
                 h.d[2] = cd[2];
-                store_pkt<Real>(ws.O, (uint32_t)my_seg() * ocap + at, h, ckey, T);
+                store_out<Real>(ws, (uint32_t)my_seg() * ocap + at, h, ckey, T);
             } else {
                 lost = true;
             }
@@ -1626,7 +1633,7 @@ void launch_pass_nb(FrtSolveDesc* d, const FrtWS& ws, int part, hipStream_t s)
     const BrickLaunch bk = brick_kernel<Real, NB>(ws);
     const dim3 grid(cu_count() * bk.per_cu);
     if (part == 0) hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws);
-    else if (part == 1) hipLaunchKernelGGL((k_scatter<Real, NB>), dim3(cu_count() * ws.scatter_bpc), dim3(BLOCK), 0, s, ws);
+    else if (part == 1) hipLaunchKernelGGL(k_scatter, dim3(cu_count() * ws.scatter_bpc), dim3(BLOCK), 0, s, ws);
     else if (part == 3) hipLaunchKernelGGL((k_split<Real>), dim3(cu_count() * ws.split_bpc), dim3(BLOCK), 0, s, d, ws);
     else hipLaunchKernelGGL(bk.kernel, grid, dim3(bk.threads), 0, s, d, ws);
 }
