@@ -325,7 +325,10 @@ def main():
     nb = prob.n_bins
     d_visits = L1["ray_visits"] - L0["ray_visits"]
     rec = 64                                            # one packet record (FrtRec<float>)
-    march_bytes = 12.0 * cross + 2.0 * rec * d_visits   # record read and written once per visit
+    # per crossing: opacity gather and one FP32 deposit; per visit: the sorted
+    # entry (8 B) and the record read, the record and its key (4 B) written
+    # once (by the march, as a continuing packet or a split child)
+    march_bytes = 12.0 * cross + (2.0 * rec + 12.0) * d_visits
     closure = abs(L1["emitted"] - L1["absorbed_HI"] - L1["absorbed_sub"] - L1["escaped"] - L1["dropped"]
                   - L1["in_flight"] - L1["lost"]) / L1["emitted"]
     per_launch = march_bytes / max(tm["march_launches"], 1)

@@ -164,21 +164,24 @@ int frt_batch_run(frt_solve* solves, int n, const double* dt_s, int n_steps, int
 typedef struct {
     size_t size;                    /* sizeof(frt_tuning) */
     int item_rays;                  /* packets per march work item (the ray tile):
-                                       a multiple of 64 in 64..1024 */
+                                       a multiple of 64 in 64..1024; the
+                                       1024-thread march (FP32 without sub-grid
+                                       opacity) takes 8 times as many */
     int scatter_blocks_per_cu;      /* workgroups per CU of the pass that sorts the
                                        queue by brick (queue chunking), 1..16 */
-    int split_blocks_per_cu;        /* workgroups per CU of the pass that writes
-                                       split children, 1..16 */
+    int split_blocks_per_cu;        /* 1..16; validated and kept, but unused: the
+                                       march writes the split children itself */
 } frt_tuning;
 
-/* Defaults: 1024 packets per item, 8 and 4 workgroups per CU. */
+/* Defaults: 1024 packets per item, 8 scatter workgroups per CU (and 4 in
+ * the unused split field). */
 int frt_tuning_default(frt_tuning* t);
 int frt_ctx_set_tuning(frt_ctx ctx, const frt_tuning* t);
 int frt_ctx_get_tuning(frt_ctx ctx, frt_tuning* t);
 
 /* Autotuner: times one step of the n solves (as frt_batch_step runs it)
  * under each candidate launch shape (item_rays 256/512/1024 x scatter 4/8
- * x split 4/8 workgroups per CU), after one untimed step that sizes the
+ * workgroups per CU), after one untimed step that sizes the
  * queues; sets the fastest on the context and returns it in *best.  Every
  * solve is put back exactly as it was (fields, carried packets, ledger,
  * step index, last rate field), so the call changes no result. */

@@ -108,14 +108,12 @@ int copy_recs(FrtRecs& dst, const FrtRecs& src, uint32_t n, int nb, size_t rs, h
 // (one step at a time: the mutex serializes launches that use it).
 struct Workspace {
     int fp64 = -1, nb = 0;
-    // pass outputs (two buffers used in turn, with each record's key), the
-    // sorted input index of a pass, the split queue and its photons
+    // pass outputs (two buffers used in turn, with each record's key) and
+    // the sorted input index of a pass
     FrtRecs O[2] = {};
     uint32_t* okey[2] = {nullptr, nullptr};
     uint2* sorted = nullptr;
     uint32_t pcap = 0;              // records per output buffer and sorted entries
-    FrtRecs S{};
-    double* s_phot = nullptr;
     uint32_t* segc = nullptr;
     uint32_t* segp = nullptr;
     uint32_t* ctr_host = nullptr;   // pinned copy of the counters
@@ -140,8 +138,6 @@ struct Workspace {
         }
         dev_free(sorted);
         pcap = 0;
-        free_recs(S);
-        dev_free(s_phot);
     }
 
     void release()
@@ -393,18 +389,12 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
     want_p = std::min<uint64_t>(want_p, 2147483647ull);
     if (ws.pcap < want_p) {
         ws.free_pass();
-        // a pass writes four children per split into its output, so half of
-        // the output capacity bounds the splits of a pass that does not
-        // overflow it
-        const uint32_t scap = (uint32_t)std::max<uint64_t>(want_p / 2, 1024);
         for (int k = 0; k < 2; k++) {
             RCCHK(alloc_recs(ws.O[k], (uint32_t)want_p, nb, rs));
             RCCHK(dev_alloc((void**)&ws.okey[k], (size_t)want_p * 4));
         }
         RCCHK(dev_alloc((void**)&ws.sorted, (size_t)want_p * sizeof(uint2)));
         ws.pcap = (uint32_t)want_p;
-        RCCHK(alloc_recs(ws.S, scap, nb, rs));
-        RCCHK(dev_alloc((void**)&ws.s_phot, (size_t)scap * 8));
         dev_free(ws.work);
         ws.cap_work = 0;
     }
@@ -413,7 +403,7 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
         ws.ctr_host = nullptr;
         return fail(FRT_ENOMEM, "pinned counter buffer");
     }
-    if (!ws.segc) RCCHK(dev_alloc((void**)&ws.segc, 2ull * FRT_QSEG * FRT_QSEG_STRIDE * 4));
+    if (!ws.segc) RCCHK(dev_alloc((void**)&ws.segc, (size_t)FRT_QSEG * FRT_QSEG_STRIDE * 4));
     if (!ws.segp) RCCHK(dev_alloc((void**)&ws.segp, (FRT_QSEG + 1) * 4ull));
     if (ws.nkeys_cap < nkeys) {
         dev_free(ws.hist);
@@ -502,8 +492,6 @@ void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
     w.out = 0;
     w.sorted = ws.sorted;
     w.pcap = ws.pcap;
-    w.S = ws.S;
-    w.s_phot = ws.s_phot;
     w.segc = ws.segc;
     w.segp = ws.segp;
     w.ctr = ws.ctr;
@@ -531,7 +519,6 @@ void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
         w.buf[0].cap = c;
         w.buf[1].cap = c;
         w.pcap = c;
-        w.S.cap = std::min<uint32_t>(w.S.cap, std::max<uint32_t>(c / 2, 1024));
     }
 }
 
@@ -578,8 +565,6 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
             if ((e = frt::launch_pass(ws.descs, w, fp64, 2, st)) != hipSuccess) return fail(FRT_EDEVICE, "march: %s", hipGetErrorString(e));
             if (tm) tm->n_march++;
         }
-        Timed t(tm, st, 3);
-        if ((e = frt::launch_pass(ws.descs, w, fp64, 3, st)) != hipSuccess) return fail(FRT_EDEVICE, "split: %s", hipGetErrorString(e));
     }
     {
         Timed t(tm, st, 3);
@@ -961,11 +946,11 @@ uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T,
     // sources, photon rates, 64 steps of rotations, ledgers
     b += (uint64_t)n_src * (24 + 12 * (uint64_t)P.n_bins) + 64ull * n_src * 32 + 2 * sizeof(FrtLedgerDev);
     // share of the pass queues: two output buffers with their keys, the
-    // sorted index, S at half size with its photons, work list
+    // sorted index, work list
     const uint64_t wp = P.queue_capacity ? P.queue_capacity
                                          : (P.queue_hint ? P.queue_hint : std::max<uint64_t>(4 * cast + 65536, ncell / 2));
     if (pass_records) *pass_records = wp;
-    b += wp * (2 * rec + 8 + sizeof(uint2) + rec / 2 + 4) + wp / 64 * sizeof(FrtWork);
+    b += wp * (2 * rec + 8 + sizeof(uint2)) + wp / 64 * sizeof(FrtWork);
     return b;
 }
 
@@ -1363,8 +1348,7 @@ int frt_autotune(frt_solve* ss, int n, const double* dts, frt_tuning* best)
     const frt_tuning keep = ctx->ws.tune;
     std::vector<frt_tuning> cand;
     for (int item : {256, 512, 1024})
-        for (int sc : {4, 8})
-            for (int sp : {4, 8}) cand.push_back(frt_tuning{sizeof(frt_tuning), item, sc, sp});
+        for (int sc : {4, 8}) cand.push_back(frt_tuning{sizeof(frt_tuning), item, sc, keep.split_blocks_per_cu});
     hipStream_t st = ss[0]->stream;
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));

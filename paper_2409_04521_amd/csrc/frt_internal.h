@@ -26,7 +26,7 @@ constexpr uint32_t FRT_BIG_ITEM_SCALE = 8;
 constexpr uint32_t FRT_ITEM_MAX = FRT_BIG_ITEM_SCALE * FRT_ITEM_RAYS;
 // Ledger accumulators are striped to keep atomics off a single address.
 constexpr int FRT_STRIPES = 64;
-// The pass output buffers (O and S) are cut into FRT_QSEG equal segments,
+// The pass output buffers are cut into FRT_QSEG equal segments,
 // each with its own fill counter (FRT_QSEG_STRIDE words apart, one cache
 // line each); workgroup b appends to segment b % FRT_QSEG, so appends from
 // different workgroups seldom meet on one counter.
@@ -159,9 +159,7 @@ struct FrtWS {
     int out;
     uint2* sorted;              // [pcap] (record index in the input buffer, crossing bin) in brick order
     uint32_t pcap;
-    FrtRecs S;
-    double* s_phot;
-    uint32_t* segc;             // [2][FRT_QSEG][FRT_QSEG_STRIDE] fill counters of O, then of S
+    uint32_t* segc;             // [FRT_QSEG][FRT_QSEG_STRIDE] fill counters of the output segments
     uint32_t* segp;             // [FRT_QSEG + 1] first input entry of each segment in pass order
     uint32_t* ctr;              // [C_NCTR]
     uint32_t* hist;             // [nkeys]
@@ -177,13 +175,13 @@ struct FrtWS {
     // launch shape (tunable)
     uint32_t item_rays;         // packets per work item, 64..FRT_ITEM_RAYS
     int scatter_bpc;            // workgroups per CU of the scatter pass
-    int split_bpc;              // workgroups per CU of the split pass
+    int split_bpc;              // accepted for compatibility; no kernel uses it
 };
 
 namespace frt {
 hipError_t launch_seed(FrtSolveDesc* d, const FrtWS& ws, int fp64, hipStream_t s);
-// part 0: counting scan, 1: scatter into brick order, 2: brick march,
-// 3: children of the packets that split
+// part 0: counting scan, 1: scatter into brick order, 2: brick march
+// (which also writes the children of the packets that split)
 hipError_t launch_pass(FrtSolveDesc* d, const FrtWS& ws, int fp64, int part, hipStream_t s);
 hipError_t launch_finish(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
 hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,

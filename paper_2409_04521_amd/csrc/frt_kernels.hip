@@ -190,7 +190,6 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t* ctr, uint32_t n_lane)
 
 // Fill counters and sizes of the output segments (see FRT_QSEG).
 __device__ __forceinline__ uint32_t* o_ctr(const FrtWS& ws, int k) { return ws.segc + k * FRT_QSEG_STRIDE; }
-__device__ __forceinline__ uint32_t* s_ctr(const FrtWS& ws, int k) { return ws.segc + (FRT_QSEG + k) * FRT_QSEG_STRIDE; }
 __device__ __forceinline__ uint32_t seg_cap(uint32_t cap) { return cap / FRT_QSEG; }
 __device__ __forceinline__ int my_seg() { return (int)(blockIdx.x % FRT_QSEG); }
 
@@ -461,7 +460,7 @@ __global__ void k_seed_plan(FrtSolveDesc* descs, FrtWS ws)
         D.L->step_crossings = 0;
     }
     ws.seed_prefix[ws.n_solves] = acc;
-    for (int k = 0; k < 2 * FRT_QSEG; k++) ws.segc[k * FRT_QSEG_STRIDE] = 0;
+    for (int k = 0; k < FRT_QSEG; k++) ws.segc[k * FRT_QSEG_STRIDE] = 0;
 }
 
 // One lane per item: a cast packet gets r = 0 and Ndot_nu dt / (12 4^L0)
@@ -625,7 +624,6 @@ __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
             ws.ctr[C_NOS] = tot;
         }
         *o_ctr(ws, threadIdx.x) = 0;
-        *s_ctr(ws, threadIdx.x) = 0;
     }
     for (uint32_t k = k0; k < k1; k++) {
         uint32_t h = ws.hist[k];
@@ -875,10 +873,12 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
     __shared__ uint32_t s_bin[NBIN];
     __shared__ uint16_t s_order[ITEM];
     __shared__ uint32_t s_nv, s_chunk, s_next;
+    __shared__ uint8_t s_par[BT / WAVE][16];   // lanes of a round's split parents, per wave
     const uint32_t nwork = ws.ctr[C_NWORK];
     const uint32_t np = ws.ctr[C_NP] < ws.pcap ? ws.ctr[C_NP] : ws.pcap;
     const FrtRecs in_q = in_recs(ws);
     const int lane = threadIdx.x & (WAVE - 1);
+    const int wv = threadIdx.x / WAVE;
     if (threadIdx.x < LF_NF) s_lf[threadIdx.x] = 0.0;
     if (threadIdx.x < LC_NC) s_lc[threadIdx.x] = 0;
     if (threadIdx.x < KEY_SLOTS) { s_key[threadIdx.x] = 0xffffffffu; s_cnt[threadIdx.x] = 0; }
@@ -1193,13 +1193,12 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 v_end = n_end * Rr;
                 h.cell = pack_cell(c);
             }
-            // ---- slots in the next pass's queues (O for packets entering
-            // another brick, S for packets at their split radius), reserved
-            // before the ledger reductions, which run while the atomics fly
-            const bool to_o = __ballot(end == 4) != 0, to_s = __ballot(end == 0) != 0;
-            uint32_t o_raw = 0, o_off = 0, s_raw = 0, s_off = 0;
+            // ---- slots in the next pass's input for packets entering another
+            // brick, reserved before the ledger reductions, which run while
+            // the atomic flies
+            const bool to_o = __ballot(end == 4) != 0;
+            uint32_t o_raw = 0, o_off = 0;
             if (to_o) o_off = reserve_begin(o_ctr(ws, my_seg()), end == 4 ? 1u : 0u, &o_raw);
-            if (to_s) s_off = reserve_begin(s_ctr(ws, my_seg()), end == 0 ? 1u : 0u, &s_raw);
             // ---- ledger: counts from ballots, photon terms from wave sums
             // taken only when some lane of the wave has one
             {
@@ -1242,20 +1241,69 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 }
                 count_keys_wave(s_key, s_cnt, ws.hist, key & FRT_KEY_MASK, stored);
             }
-            // ---- packets at their split radius, with their photons, go to the
-            // split kernel, which writes the children (all lanes busy there)
-            if (to_s) {
-                const uint32_t at = reserve_end(s_raw, s_off);
-                if (end == 0) {
-                    if (at < seg_cap(ws.S.cap)) {
-                        const uint32_t o = (uint32_t)my_seg() * seg_cap(ws.S.cap) + at;
-                        store_pkt<Real>(ws.S, o, h, brick_key(D, c), T);
-                        ws.s_phot[o] = v_end;
-                    } else {
-                        raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
-                        atomicAdd(&s_lf[LF_LOST], v_end);
+            // ---- children of the packets at their split radius (Eq. lhpx):
+            // level + 1, NESTED pixels 4p .. 4p + 3, a quarter of the photons
+            // each, the parent's rotation, placed on their own pixel direction
+            // at the split radius; a child whose position is outside the box
+            // has escaped.  Up to 16 parents a round, four lanes per parent
+            // and one child per lane, so that the wave's lanes stay busy.
+            for (unsigned long long todo = __ballot(end == 0); todo;) {
+                const bool mine = ((todo >> lane) & 1ull) != 0;
+                const uint32_t rk = lanes_below(todo);
+                const bool now = mine && rk < 16u;
+                const uint32_t npar = min((uint32_t)__popcll(todo), 16u);
+                if (now) s_par[wv][rk] = (uint8_t)lane;
+                const uint32_t q = (uint32_t)lane >> 2, kq = (uint32_t)lane & 3u;
+                const bool cact = q < npar;
+                const int pl = cact ? (int)s_par[wv][q] : lane;
+                Pkt<Real> ch;
+                Real cT[4], cs[3];
+                ch.src = (uint32_t)__shfl((int)h.src, pl, WAVE);
+                ch.estep = (uint32_t)__shfl((int)h.estep, pl, WAVE);
+                const uint32_t plp = (uint32_t)__shfl((int)h.lp, pl, WAVE);
+                ch.r = __shfl(h.r, pl, WAVE);
+                ch.rstop = __shfl(h.rstop, pl, WAVE);
+                ch.w0 = __shfl(h.w0, pl, WAVE) * Real(0.25);
+#pragma unroll
+                for (int b = 0; b < 4; b++) cT[b] = __shfl(T[b], pl, WAVE);
+#pragma unroll
+                for (int a = 0; a < 3; a++) cs[a] = __shfl(s[a], pl, WAVE);
+                const double cph = 0.25 * __shfl(v_end, pl, WAVE);
+                const int clev = (int)(plp >> 28) + 1;
+                ch.lp = ((uint32_t)clev << 28) | (4u * (plp & 0x0fffffffu) + kq);
+                bool inside = false;
+                uint32_t ckey = 0;
+                if (cact) {
+                    packet_dir<Real>(D, ch.lp, ch.estep, ch.src, ch.d);
+                    int cc[3];
+                    inside = locate<Real>(D, cs, ch.r, ch.d, cc);
+                    if (inside) {
+                        ch.cell = pack_cell(cc);
+                        ckey = key_with_bin(brick_key(D, cc), crossing_bin<Real>(D, cc, cs, ch.d, ch.r, ch.rstop, clev));
                     }
                 }
+                const uint32_t at = wave_reserve_small(o_ctr(ws, my_seg()), inside ? 1u : 0u);
+                bool stored = false;
+                if (inside) {
+                    if (at < seg_cap(ws.buf[0].cap)) {
+                        store_out<Real>(ws, (uint32_t)my_seg() * seg_cap(ws.buf[0].cap) + at, ch, ckey, cT);
+                        stored = true;
+                    } else {
+                        raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
+                        atomicAdd(&s_lf[LF_LOST], cph);
+                    }
+                }
+                count_keys_wave(s_key, s_cnt, ws.hist, ckey & FRT_KEY_MASK, stored);
+                const bool cesc = cact && !inside;
+                const unsigned long long m_cesc = __ballot(cesc);
+                if (m_cesc) {
+                    const double t_cesc = wave_sum(cesc ? cph : 0.0);
+                    if (lane == 0) {
+                        atomicAdd(&s_lf[LF_ESC], t_cesc);
+                        atomicAdd(&s_lc[LC_NESC], (unsigned long long)__popcll(m_cesc));
+                    }
+                }
+                todo &= ~__ballot(now);
             }
             // ---- packets that spent their travel budget: carried to the next step
             if (__ballot(end == 3)) {
@@ -1328,98 +1376,6 @@ template <typename Real, int NB>
 __global__ void __launch_bounds__(4 * BLOCK) k_brick_big(FrtSolveDesc* descs, FrtWS ws)
 {
     brick_march<Real, NB, false, FRT_BRICK_LOG_BIG[0], FRT_BRICK_LOG_BIG[1], FRT_BRICK_LOG_BIG[2], 4 * BLOCK>(descs, ws);
-}
-
-// ================================================================ splitting
-// Children of the packets that reached their split radius this pass
-// (Eq. lhpx): level + 1, NESTED pixels 4p .. 4p + 3, a quarter of the
-// photons each, the parent's rotation, placed on their own pixel direction
-// at the split radius.  A child whose position is outside the box has
-// escaped.  Four lanes per parent, one child each.
-template <typename Real>
-__global__ void __launch_bounds__(BLOCK) k_split(FrtSolveDesc* descs, FrtWS ws)
-{
-    constexpr uint32_t PARENTS = BLOCK / 4;
-    __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
-    __shared__ uint32_t s_sp[FRT_QSEG + 1];
-    if (threadIdx.x < KEY_SLOTS) { s_key[threadIdx.x] = 0xffffffffu; s_cnt[threadIdx.x] = 0; }
-    const uint32_t scap = seg_cap(ws.S.cap);
-    if (threadIdx.x < WAVE) {
-        const uint32_t c = *s_ctr(ws, threadIdx.x);
-        uint32_t tot;
-        s_sp[threadIdx.x] = wave_excl_scan(c < scap ? c : scap, &tot);
-        if (threadIdx.x == 0) s_sp[FRT_QSEG] = tot;
-    }
-    __syncthreads();
-    const uint32_t ns = s_sp[FRT_QSEG];
-    const uint32_t ocap = seg_cap(ws.buf[0].cap);
-    const uint32_t k = threadIdx.x & 3u;
-    for (uint32_t base = blockIdx.x * PARENTS; base < ns; base += gridDim.x * PARENTS) {
-        const uint32_t v = base + threadIdx.x / 4u;
-        const bool act = v < ns;
-        Pkt<Real> h;
-        Real T[4], cd[3];
-        uint32_t ccell = 0, ckey = 0;
-        bool inside = false;
-        int solve = 0;
-        double ph = 0.0;
-        if (act) {
-            const int sg = find_in_prefix(s_sp, FRT_QSEG, v);
-            const uint32_t i = (uint32_t)sg * scap + (v - s_sp[sg]);
-            load_pkt<Real>(ws.S, i, h, T);
-            ph = ws.s_phot[i];
-            solve = ws.n_solves > 1 ? find_in_prefix(ws.key_prefix, ws.n_solves, recs<Real>(ws.S)[i].key) : 0;
-            const FrtSolveDesc& D = descs[solve];
-            const double* sp = D.src_pos + (size_t)h.src * 3;
-            const Real s[3] = {(Real)sp[0], (Real)sp[1], (Real)sp[2]};
-            const int level = (int)(h.lp >> 28) + 1;
-            h.lp = ((uint32_t)level << 28) | (4u * (h.lp & 0x0fffffffu) + k);
-            packet_dir<Real>(D, h.lp, h.estep, h.src, cd);
-            int cc[3];
-            inside = locate<Real>(D, s, h.r, cd, cc);
-            if (inside) {
-                ccell = pack_cell(cc);
-                ckey = key_with_bin(brick_key(D, cc), crossing_bin<Real>(D, cc, s, cd, h.r, h.rstop, level));
-            }
-        }
-        const uint32_t at = wave_reserve_small(o_ctr(ws, my_seg()), inside ? 1u : 0u);
-        bool lost = false;
-        if (inside) {
-            if (at < ocap) {
-                h.w0 *= Real(0.25);
-                h.cell = ccell;
-                h.d[0] = cd[0];
-                h.d[1] = cd[1];
-                h.d[2] = cd[2];
-                store_out<Real>(ws, (uint32_t)my_seg() * ocap + at, h, ckey, T);
-            } else {
-                lost = true;
-            }
-        }
-        count_keys_wave(s_key, s_cnt, ws.hist, ckey & FRT_KEY_MASK, inside && !lost);
-        if (act && (!inside || lost)) {
-            FrtLedgerDev* L = descs[solve].L;
-            if (!inside) {
-                ledger_direct(L, LF_ESC, 0.25 * ph);
-                ledger_direct_c(L, LC_NESC, 1ull);
-            } else {
-                raise_error(ws, L, FRT_DEVERR_QUEUE_OVERFLOW);
-                ledger_direct(L, LF_LOST, 0.25 * ph);
-            }
-        }
-        // children of neighbouring parents share few bricks: add the block's
-        // key counts to the histogram once per round, before the table fills
-        __syncthreads();
-        if (threadIdx.x < KEY_SLOTS) {
-            const uint32_t kk = s_key[threadIdx.x];
-            if (kk != 0xffffffffu) {
-                atomicAdd(&ws.hist[kk], s_cnt[threadIdx.x]);
-                s_key[threadIdx.x] = 0xffffffffu;
-                s_cnt[threadIdx.x] = 0;
-            }
-        }
-        __syncthreads();
-    }
 }
 
 // ============================================================ bookkeeping
@@ -1634,8 +1590,7 @@ void launch_pass_nb(FrtSolveDesc* d, const FrtWS& ws, int part, hipStream_t s)
     const dim3 grid(cu_count() * bk.per_cu);
     if (part == 0) hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, ws);
     else if (part == 1) hipLaunchKernelGGL(k_scatter, dim3(cu_count() * ws.scatter_bpc), dim3(BLOCK), 0, s, ws);
-    else if (part == 3) hipLaunchKernelGGL((k_split<Real>), dim3(cu_count() * ws.split_bpc), dim3(BLOCK), 0, s, d, ws);
-    else hipLaunchKernelGGL(bk.kernel, grid, dim3(bk.threads), 0, s, d, ws);
+    else if (part == 2) hipLaunchKernelGGL(bk.kernel, grid, dim3(bk.threads), 0, s, d, ws);
 }
 
 template <typename Real>
