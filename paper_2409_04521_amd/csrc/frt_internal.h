@@ -35,6 +35,8 @@ constexpr int FRT_QSEG = 64;
 // expected crossings in the next brick (0 .. FRT_KEY_BINS - 1) above them.
 constexpr int FRT_KEY_BITS = 26;
 constexpr uint32_t FRT_KEY_MASK = (1u << FRT_KEY_BITS) - 1u;
+// Key of an output slot that holds no packet (a split child that escaped).
+constexpr uint32_t FRT_KEY_NONE = 0xffffffffu;
 constexpr int FRT_KEY_BINS = 64;
 constexpr int FRT_QSEG_STRIDE = 32;
 

@@ -699,7 +699,8 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
         uint32_t slot[PER], rank[PER];
 #pragma unroll
         for (int q = 0; q < PER; q++) {
-            uint32_t key = idx[q] == EMPTY ? EMPTY : (kw[q] & FRT_KEY_MASK);
+            // empty slots (escaped split children) are skipped
+            uint32_t key = (idx[q] == EMPTY || kw[q] == FRT_KEY_NONE) ? EMPTY : (kw[q] & FRT_KEY_MASK);
             if (key != EMPTY && key >= ws.nkeys) {      // never expected: flag and skip
                 atomicOr(&ws.ctr[C_ERR], (uint32_t)FRT_DEVERR_QUEUE_OVERFLOW);
                 key = EMPTY;
@@ -1193,12 +1194,17 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                 v_end = n_end * Rr;
                 h.cell = pack_cell(c);
             }
-            // ---- slots in the next pass's input for packets entering another
-            // brick, reserved before the ledger reductions, which run while
-            // the atomic flies
-            const bool to_o = __ballot(end == 4) != 0;
-            uint32_t o_raw = 0, o_off = 0;
-            if (to_o) o_off = reserve_begin(o_ctr(ws, my_seg()), end == 4 ? 1u : 0u, &o_raw);
+            // ---- slots in the next pass's input: packets entering another
+            // brick, then four per split packet (a child that escapes leaves
+            // its slot empty), reserved with one atomic before the ledger
+            // reductions and the children, which run while it flies
+            const unsigned long long m_next = __ballot(end == 4), m_par = __ballot(end == 0);
+            const uint32_t n_next = (uint32_t)__popcll(m_next);
+            const uint32_t n_out = n_next + 4u * (uint32_t)__popcll(m_par);
+            uint32_t o_raw = 0;
+            if (lane == 0 && n_out) o_raw = atomicAdd(o_ctr(ws, my_seg()), n_out);
+            const uint32_t ocap_seg = seg_cap(ws.buf[0].cap);
+            const uint32_t oseg0 = (uint32_t)my_seg() * ocap_seg;
             // ---- ledger: counts from ballots, photon terms from wave sums
             // taken only when some lane of the wave has one
             {
@@ -1224,22 +1230,25 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                     if (m_fl) atomicAdd(&s_lc[LC_NFLIGHT], (unsigned long long)__popcll(m_fl));
                 }
             }
+            // keys of the packets entering another brick, computed while the
+            // reservation flies
+            uint32_t key = 0;
+            if (end == 4) key = key_with_bin(brick_key(D, c), crossing_bin<Real>(D, c, s, h.d, h.r, h.rstop, level));
+            const uint32_t o_base = n_out ? reserve_end(o_raw, 0u) : 0u;
             // ---- packets entering another brick go to the next pass
-            if (to_o) {
-                const uint32_t at = reserve_end(o_raw, o_off);
-                uint32_t key = 0;
+            {
                 bool stored = false;
                 if (end == 4) {
-                    key = key_with_bin(brick_key(D, c), crossing_bin<Real>(D, c, s, h.d, h.r, h.rstop, level));
-                    if (at < seg_cap(ws.buf[0].cap)) {
-                        store_out<Real>(ws, (uint32_t)my_seg() * seg_cap(ws.buf[0].cap) + at, h, key, T);
+                    const uint32_t at = o_base + lanes_below(m_next);
+                    if (at < ocap_seg) {
+                        store_out<Real>(ws, oseg0 + at, h, key, T);
                         stored = true;
                     } else {
                         raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
                         atomicAdd(&s_lf[LF_LOST], v_end);
                     }
                 }
-                count_keys_wave(s_key, s_cnt, ws.hist, key & FRT_KEY_MASK, stored);
+                if (m_next) count_keys_wave(s_key, s_cnt, ws.hist, key & FRT_KEY_MASK, stored);
             }
             // ---- children of the packets at their split radius (Eq. lhpx):
             // level + 1, NESTED pixels 4p .. 4p + 3, a quarter of the photons
@@ -1247,7 +1256,8 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
             // at the split radius; a child whose position is outside the box
             // has escaped.  Up to 16 parents a round, four lanes per parent
             // and one child per lane, so that the wave's lanes stay busy.
-            for (unsigned long long todo = __ballot(end == 0); todo;) {
+            uint32_t done = 0;   // parents whose children are written
+            for (unsigned long long todo = m_par; todo;) {
                 const bool mine = ((todo >> lane) & 1ull) != 0;
                 const uint32_t rk = lanes_below(todo);
                 const bool now = mine && rk < 16u;
@@ -1282,13 +1292,18 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                         ckey = key_with_bin(brick_key(D, cc), crossing_bin<Real>(D, cc, cs, ch.d, ch.r, ch.rstop, clev));
                     }
                 }
-                const uint32_t at = wave_reserve_small(o_ctr(ws, my_seg()), inside ? 1u : 0u);
+                // child kq of the parent ranked `done + q` in the wave
+                const uint32_t at = o_base + n_next + 4u * (done + q) + kq;
                 bool stored = false;
-                if (inside) {
-                    if (at < seg_cap(ws.buf[0].cap)) {
-                        store_out<Real>(ws, (uint32_t)my_seg() * seg_cap(ws.buf[0].cap) + at, ch, ckey, cT);
-                        stored = true;
-                    } else {
+                if (cact) {
+                    if (at < ocap_seg) {
+                        if (inside) {
+                            store_out<Real>(ws, oseg0 + at, ch, ckey, cT);
+                            stored = true;
+                        } else {
+                            (ws.out ? ws.bkey[1] : ws.bkey[0])[oseg0 + at] = FRT_KEY_NONE;
+                        }
+                    } else if (inside) {
                         raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
                         atomicAdd(&s_lf[LF_LOST], cph);
                     }
@@ -1304,6 +1319,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                     }
                 }
                 todo &= ~__ballot(now);
+                done += npar;
             }
             // ---- packets that spent their travel budget: carried to the next step
             if (__ballot(end == 3)) {
