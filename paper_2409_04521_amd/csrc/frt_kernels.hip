@@ -52,14 +52,17 @@ __device__ __forceinline__ uint32_t squeeze_even_bits(uint32_t v)
 template <typename Real>
 __device__ void nest_pixel_centre(int level, uint32_t pix, Real v[3])
 {
-    const int jr_face[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
-    const int jp_face[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
     const int nside = 1 << level;
     const uint32_t face = pix >> (2 * level);
+    // ring of the face's southern corner (in units of Nside) and its
+    // longitude index: faces 0-3 are the northern row, 4-7 the equatorial
+    // row (shifted by half a face), 8-11 the southern row
+    const int jr_face = (int)(face >> 2) + 2;
+    const int jp_face = 2 * (int)(face & 3u) + ((face >> 2) == 1u ? 0 : 1);
     const uint32_t sub = pix & ((1u << (2 * level)) - 1u);
     const int ix = (int)squeeze_even_bits(sub);
     const int iy = (int)squeeze_even_bits(sub >> 1);
-    const int j = jr_face[face] * nside - ix - iy - 1;
+    const int j = jr_face * nside - ix - iy - 1;
     int nr;
     Real z, st;
     const Real inv3n2 = Real(1) / (Real(3) * Real(nside) * Real(nside));
@@ -78,7 +81,7 @@ __device__ void nest_pixel_centre(int level, uint32_t pix, Real v[3])
         z = Real(2 * nside - j) * (Real(2) / Real(3 * nside));
         st = sqrt((Real(1) - z) * (Real(1) + z));
     }
-    int k = jp_face[face] * nr + ix - iy;
+    int k = jp_face * nr + ix - iy;
     if (k < 0) k += 8 * nr;
     else if (k >= 8 * nr) k -= 8 * nr;
     // phi = (pi/4) k / nr, evaluated as sincospi(k / (4 nr))
@@ -846,13 +849,15 @@ __device__ __forceinline__ uint32_t reserve_end(uint32_t raw, uint32_t off) { re
 // (Eq. gamma_initial_standard when kappa = 0).  Without sub-grid opacity
 // (SUB = false) K_nu ds phi = (K_nu / s_nu) (1 - e^-tau) / a_i, and
 // K_nu / s_nu is the same for every bin, so the deposit is one constant
-// times the absorbed photons over a_i.  End states in order: distance cap,
+// times the absorbed photons over a_i: the march adds up each cell's
+// absorbed photons and the sum is scaled once when the brick's deposits are
+// added (a_i > 0 everywhere: the opacity has a tiny floor).  End states in order: distance cap,
 // flux floor, split radius (Eq. r_split), leaving the box, travel budget;
 // leaving the brick hands the packet to the next pass.  Ledger terms are
 // reduced per wave and added into LDS; output keys are counted in an LDS
 // table and added to the histogram once per work item.
 template <typename Real, int NB, bool SUB, int LX, int LY, int LZ, int BT>
-__device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
+__device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ descs, FrtWS& ws)
 {
     using R2 = typename Vec2<Real>::T;
     constexpr bool F32 = sizeof(Real) == 4;
@@ -1130,9 +1135,9 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
                                     NE[b] *= eb;
                                 }
                             }
-                            // a_i > 0 everywhere (the opacity has a tiny floor), so the
-                            // optically thin limit is this same expression
-                            dep = KS * absd * fast_rcp(o.x);
+                            // the cell's absorbed photons; times KS / a_i when the
+                            // brick's deposits are added
+                            dep = absd;
                         }
                         sumE -= absd;
                         // Kahan-compensated optical depth carried by the packet
@@ -1347,8 +1352,9 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
         // add the brick's deposits and its output-key counts once
         Real* __restrict__ gam = (Real*)D.gamma[D.step & 1u];
         for (int t = threadIdx.x; t < BC; t += BT) {
-            const Real v = s_g[t];
+            Real v = s_g[t];
             if (v != Real(0)) {
+                if constexpr (!SUB) v = v * (KS * fast_rcp<Real>(s_op[t]));
                 const int lx = t & (BX - 1), ly = (t >> LX) & (BY - 1), lz = t >> (LX + LY);
                 const size_t ci = (size_t)(ox + lx) + (size_t)nx * ((size_t)(oy + ly) + (size_t)ny * (size_t)(oz + lz));
                 atomicAdd(gam + ci, v);
@@ -1378,7 +1384,7 @@ __device__ __forceinline__ void brick_march(FrtSolveDesc* descs, FrtWS& ws)
 
 // 256-thread march on 16^3 (FP32 with sub-grid opacity) or 8^3 (FP64) bricks
 template <typename Real, int NB, bool SUB>
-__global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
+__global__ void __launch_bounds__(BLOCK) k_brick(const FrtSolveDesc* __restrict__ descs, FrtWS ws)
 {
     if constexpr (sizeof(Real) == 4)
         brick_march<Real, NB, SUB, FRT_BRICK_LOG_SUB[0], FRT_BRICK_LOG_SUB[1], FRT_BRICK_LOG_SUB[2], BLOCK>(descs, ws);
@@ -1389,7 +1395,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(FrtSolveDesc* descs, FrtWS ws)
 // 1024-thread march on 32 x 32 x 16 bricks (FP32 without sub-grid opacity):
 // one workgroup of 16 waves per CU, 128 registers each
 template <typename Real, int NB>
-__global__ void __launch_bounds__(4 * BLOCK) k_brick_big(FrtSolveDesc* descs, FrtWS ws)
+__global__ void __launch_bounds__(4 * BLOCK) k_brick_big(const FrtSolveDesc* __restrict__ descs, FrtWS ws)
 {
     brick_march<Real, NB, false, FRT_BRICK_LOG_BIG[0], FRT_BRICK_LOG_BIG[1], FRT_BRICK_LOG_BIG[2], 4 * BLOCK>(descs, ws);
 }
@@ -1559,7 +1565,7 @@ void launch_seed_nb(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
 
 // Resident workgroups per CU of a kernel (at least 1), queried once per
 // kernel.
-int blocks_per_cu(void (*kernel)(FrtSolveDesc*, FrtWS), int threads)
+int blocks_per_cu(void (*kernel)(const FrtSolveDesc*, FrtWS), int threads)
 {
     static std::mutex mu;
     static std::unordered_map<const void*, int> known;
@@ -1575,7 +1581,7 @@ int blocks_per_cu(void (*kernel)(FrtSolveDesc*, FrtWS), int threads)
 // The march kernel of a launch, its workgroup size and its grid (resident
 // workgroups on every CU; the occupancy query runs on the first call).
 struct BrickLaunch {
-    void (*kernel)(FrtSolveDesc*, FrtWS);
+    void (*kernel)(const FrtSolveDesc*, FrtWS);
     int threads, per_cu;
 };
 
