@@ -114,6 +114,7 @@ struct Workspace {
     uint32_t* okey[2] = {nullptr, nullptr};
     uint2* sorted = nullptr;
     uint32_t pcap = 0;              // records per output buffer and sorted entries
+    FrtRecs X{};                    // march scratch records (split children kept in their brick)
     uint32_t* segc = nullptr;
     uint32_t* segp = nullptr;
     uint32_t* ctr_host = nullptr;   // pinned copy of the counters
@@ -143,6 +144,7 @@ struct Workspace {
     void release()
     {
         free_pass();
+        free_recs(X);
         dev_free(segc);
         dev_free(segp);
         if (ctr_host) (void)hipHostFree(ctr_host);
@@ -383,6 +385,7 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
     const size_t rs = fp64 ? 8 : 4;
     if (ws.fp64 != fp64 || ws.nb != nb) {
         ws.free_pass();
+        free_recs(ws.X);
         ws.fp64 = fp64;
         ws.nb = nb;
     }
@@ -398,6 +401,7 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
         dev_free(ws.work);
         ws.cap_work = 0;
     }
+    if (!ws.X.rec) RCCHK(alloc_recs(ws.X, (uint32_t)frt::device_cu_count() * FRT_XREC_PER_CU, nb, rs));
     if (!ws.ctr) RCCHK(dev_alloc((void**)&ws.ctr, C_NCTR * 4));
     if (!ws.ctr_host && hipHostMalloc((void**)&ws.ctr_host, C_NCTR * 4, hipHostMallocDefault) != hipSuccess) {
         ws.ctr_host = nullptr;
@@ -492,6 +496,8 @@ void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
     w.out = 0;
     w.sorted = ws.sorted;
     w.pcap = ws.pcap;
+    w.xrec = ws.X.rec;
+    w.xrec_cap = ws.X.cap;
     w.segc = ws.segc;
     w.segp = ws.segp;
     w.ctr = ws.ctr;

@@ -24,6 +24,9 @@ constexpr int FRT_BRICK_LOG_F64[3] = {3, 3, 3};
 constexpr uint32_t FRT_ITEM_RAYS = 1024;
 constexpr uint32_t FRT_BIG_ITEM_SCALE = 8;
 constexpr uint32_t FRT_ITEM_MAX = FRT_BIG_ITEM_SCALE * FRT_ITEM_RAYS;
+// March scratch records per CU: room for the split children a workgroup keeps
+// in its brick, twice the largest work item (more go to the next pass).
+constexpr uint32_t FRT_XREC_PER_CU = 2 * FRT_ITEM_MAX;
 // Ledger accumulators are striped to keep atomics off a single address.
 constexpr int FRT_STRIPES = 64;
 // The pass output buffers are cut into FRT_QSEG equal segments,
@@ -161,6 +164,8 @@ struct FrtWS {
     int out;
     uint2* sorted;              // [pcap] (record index in the input buffer, crossing bin) in brick order
     uint32_t pcap;
+    void* xrec;                 // [xrec_cap] march scratch: split children kept in their parent's brick,
+    uint32_t xrec_cap;          // an equal share per workgroup
     uint32_t* segc;             // [FRT_QSEG][FRT_QSEG_STRIDE] fill counters of the output segments
     uint32_t* segp;             // [FRT_QSEG + 1] first input entry of each segment in pass order
     uint32_t* ctr;              // [C_NCTR]

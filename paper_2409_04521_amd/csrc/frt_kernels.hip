@@ -878,11 +878,15 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
     __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
     __shared__ uint32_t s_bin[NBIN];
     __shared__ uint16_t s_order[ITEM];
-    __shared__ uint32_t s_nv, s_chunk, s_next;
+    __shared__ uint32_t s_nv, s_chunk, s_next, s_xn;
     __shared__ uint8_t s_par[BT / WAVE][16];   // lanes of a round's split parents, per wave
     const uint32_t nwork = ws.ctr[C_NWORK];
     const uint32_t np = ws.ctr[C_NP] < ws.pcap ? ws.ctr[C_NP] : ws.pcap;
     const FrtRecs in_q = in_recs(ws);
+    // this workgroup's scratch records for split children kept in the brick
+    const uint32_t x_cap = min((uint32_t)(2 * ITEM), ws.xrec_cap / gridDim.x);
+    const uint32_t x_base = blockIdx.x * x_cap;
+    const FrtRecs x_q{ws.xrec, ws.xrec_cap};
     const int lane = threadIdx.x & (WAVE - 1);
     const int wv = threadIdx.x / WAVE;
     if (threadIdx.x < LF_NF) s_lf[threadIdx.x] = 0.0;
@@ -966,7 +970,10 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             s_g[t] = Real(0);
         }
         if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
-        if (threadIdx.x == 0) s_chunk = 0;
+        if (threadIdx.x == 0) {
+            s_chunk = 0;
+            s_xn = 0;
+        }
         __syncthreads();
         // ---- order the item's packets by expected crossings: a counting
         // sort whose bin counts are taken once per distinct bin of a wave
@@ -1010,335 +1017,359 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         const double r_split0 = uni(D.r_split0);
         const Real budget = uni((Real)D.budget);
         const uint32_t step = uni(D.step);
-        // waves take chunks of 64 sorted packets as they finish, longest
-        // chunks first, so that the four waves of the workgroup end together
-        const uint32_t n_chunks = (n_valid + WAVE - 1) / WAVE;
         // absorbed photons and crossings of this lane's packets, reduced
         // over the wave once per item
         double acc_abs = 0.0;
         uint32_t acc_cross = 0;
-        for (;;) {
-            uint32_t chunk = 0;
-            if (lane == 0) chunk = atomicAdd(&s_chunk, 1u);
-            chunk = uni(chunk);
-            if (chunk >= n_chunks) break;
-            const uint32_t p = (n_chunks - 1u - chunk) * WAVE + (uint32_t)lane;
-            const bool active = p < n_valid;
-            const uint32_t j = active ? (uint32_t)s_order[p] : 0u;
-            Pkt<Real> h;
-            Real T[4], NE[NB], N0[NB], s[3];   // NE: photons of each bin (units of the cast weight)
-            int level = 0, end = -1;     // -1 inactive, 0 split, 1 escaped, 2 dropped, 3 in flight, 4 next brick
-            int c[3] = {0, 0, 0};
-            double v_abs = 0.0, v_sub = 0.0, v_end = 0.0;
-            uint32_t v_cross = 0;
-            if (active) {
-                load_pkt<Real>(in_q, ws.sorted[w.start + j].x, h, T);
-                level = (int)(h.lp >> 28);
-                const double* sp = D.src_pos + (size_t)h.src * 3;
-                s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
-                if (h.estep != step && h.rstop <= h.r) h.rstop = h.r + budget;   // carried: fresh budget
-                if (h.estep == step && h.r == Real(0) && level == base_level) h.rstop = budget;
-                Real sum0 = 0;
-                double n_start = 0.0;
-#pragma unroll
-                for (int b = 0; b < NB; b++) {
-                    Real spec;
-                    if constexpr (F32) spec = D.spec[(size_t)h.src * NB + b];
-                    else spec = D.specd[(size_t)h.src * NB + b];
-                    N0[b] = h.w0 * spec;
-                    NE[b] = N0[b] * (SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0]));
-                    sum0 += N0[b];
-                    n_start += (double)NE[b];
-                }
-                unpack_cell(h.cell, c);
-                const Real r_split = (level < max_level) ? (Real)(r_split0 * (double)(1u << level)) : rinf<Real>();
-                // the nearest of split radius, distance cap and budget end
-                const Real r_lim = fmin(fmin(r_split, r_cap), h.rstop);
-                Real inv[3], rf[3];
-                int stp[3];
-#pragma unroll
-                for (int a = 0; a < 3; a++) {
-                    inv[a] = (h.d[a] != Real(0)) ? fast_rcp(h.d[a]) : Real(0);
-                    stp[a] = h.d[a] > Real(0) ? 1 : -1;
-                    rf[a] = (h.d[a] != Real(0)) ? ((Real)(c[a] + (h.d[a] > Real(0) ? 1 : 0)) - s[a]) * inv[a] : rinf<Real>();
-                }
-                // cell within the brick, and the change of its LDS index per step
-                int lc[3] = {c[0] - ox, c[1] - oy, c[2] - oz};
-                const int inc[3] = {stp[0], stp[1] * BX, stp[2] * BX * BY};
-                int li = lc[0] + BX * (lc[1] + BY * lc[2]);
-                Real sub_acc = 0;
-                const bool in_brick = lc[0] >= 0 && lc[0] < BX && lc[1] >= 0 && lc[1] < BY && lc[2] >= 0 && lc[2] < BZ;
-                if (!in_brick) end = 4;            // hand it to the brick that holds its cell
-                const Real floor_abs = floor_f * sum0;
-                // photons left (in units of the cast weight), kept by
-                // subtracting each segment's absorption, for the flux floor
-                Real sumE = 0;
-#pragma unroll
-                for (int b = 0; b < NB; b++) sumE += NE[b];
-                // the opacity of the current cell; each step reads the next
-                // cell's one iteration ahead (an index outside the brick, for a
-                // packet about to leave it, reads cell 0 and is not used)
-                OpT o_cur = s_op[(uint32_t)li < (uint32_t)BC ? li : 0];
-                while (end < 0) {
-                    int axis = 0;
-                    Real r_face = rf[0];
-                    if (rf[1] < r_face) { r_face = rf[1]; axis = 1; }
-                    if (rf[2] < r_face) { r_face = rf[2]; axis = 2; }
-                    const int li_n = li + (axis == 0 ? inc[0] : (axis == 1 ? inc[1] : inc[2]));
-                    const OpT o_next = s_op[(uint32_t)li_n < (uint32_t)BC ? li_n : 0];
-                    const Real r_end = fmax(fmin(r_face, r_lim), h.r);
-                    const Real ds = r_end - h.r;
-                    if (ds > Real(0)) {
-                        R2 o;
-                        if constexpr (SUB) {
-                            o = o_cur;
-                        } else {
-                            o.x = o_cur;
-                            o.y = Real(0);
-                        }
-                        const Real ta = o.x * ds;
-                        Real dep = 0, absd = 0;
-                        if constexpr (SUB) {
-                            const Real tk = o.y * ds;
-#pragma unroll
-                            for (int b = 0; b < NB; b++) {
-                                const Real tb = srel[b] * ta + tk;
-                                const Real nin = NE[b];
-                                const Real eb = exp_neg(tb);
-                                const Real af = absorbed<Real>(tb, eb);
-                                const Real rt = fast_rcp(tb);
-                                const Real phi = (tb > Real(0)) ? af * rt : Real(1);
-                                dep += Kb[b] * nin * ds * phi;
-                                absd += nin * af;
-                                if (tk > Real(0)) sub_acc += nin * af * tk * rt;
-                                NE[b] *= eb;
+        // Generation 0 marches the item's packets; split children that start
+        // in this brick are kept in the workgroup's scratch records and
+        // marched by the next generation while the brick is still staged
+        // (their own children likewise), the rest go to the next pass.
+        uint32_t g_lo = 0, g_hi = 0;   // scratch records of the current generation
+        for (int gen = 0;; gen++) {
+            // waves take chunks of 64 packets as they finish: in generation 0
+            // sorted, longest chunks first, so that the waves end together
+            const uint32_t n_chunks = gen == 0 ? (n_valid + WAVE - 1) / WAVE : (g_hi - g_lo + WAVE - 1) / WAVE;
+            for (;;) {
+                uint32_t chunk = 0;
+                if (lane == 0) chunk = atomicAdd(&s_chunk, 1u);
+                chunk = uni(chunk);
+                if (chunk >= n_chunks) break;
+                const uint32_t p = gen == 0 ? (n_chunks - 1u - chunk) * WAVE + (uint32_t)lane : g_lo + chunk * WAVE + (uint32_t)lane;
+                const bool active = gen == 0 ? p < n_valid : p < g_hi;
+                Pkt<Real> h;
+                Real T[4], NE[NB], N0[NB], s[3];   // NE: photons of each bin (units of the cast weight)
+                int level = 0, end = -1;     // -1 inactive, 0 split, 1 escaped, 2 dropped, 3 in flight, 4 next brick
+                int c[3] = {0, 0, 0};
+                double v_abs = 0.0, v_sub = 0.0, v_end = 0.0;
+                uint32_t v_cross = 0;
+                if (active) {
+                    if (gen == 0) load_pkt<Real>(in_q, ws.sorted[w.start + s_order[p]].x, h, T);
+                    else load_pkt<Real>(x_q, x_base + p, h, T);
+                    level = (int)(h.lp >> 28);
+                    const double* sp = D.src_pos + (size_t)h.src * 3;
+                    s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
+                    if (h.estep != step && h.rstop <= h.r) h.rstop = h.r + budget;   // carried: fresh budget
+                    if (h.estep == step && h.r == Real(0) && level == base_level) h.rstop = budget;
+                    Real sum0 = 0;
+                    double n_start = 0.0;
+    #pragma unroll
+                    for (int b = 0; b < NB; b++) {
+                        Real spec;
+                        if constexpr (F32) spec = D.spec[(size_t)h.src * NB + b];
+                        else spec = D.specd[(size_t)h.src * NB + b];
+                        N0[b] = h.w0 * spec;
+                        NE[b] = N0[b] * (SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0]));
+                        sum0 += N0[b];
+                        n_start += (double)NE[b];
+                    }
+                    unpack_cell(h.cell, c);
+                    const Real r_split = (level < max_level) ? (Real)(r_split0 * (double)(1u << level)) : rinf<Real>();
+                    // the nearest of split radius, distance cap and budget end
+                    const Real r_lim = fmin(fmin(r_split, r_cap), h.rstop);
+                    Real inv[3], rf[3];
+                    int stp[3];
+    #pragma unroll
+                    for (int a = 0; a < 3; a++) {
+                        inv[a] = (h.d[a] != Real(0)) ? fast_rcp(h.d[a]) : Real(0);
+                        stp[a] = h.d[a] > Real(0) ? 1 : -1;
+                        rf[a] = (h.d[a] != Real(0)) ? ((Real)(c[a] + (h.d[a] > Real(0) ? 1 : 0)) - s[a]) * inv[a] : rinf<Real>();
+                    }
+                    // cell within the brick, and the change of its LDS index per step
+                    int lc[3] = {c[0] - ox, c[1] - oy, c[2] - oz};
+                    const int inc[3] = {stp[0], stp[1] * BX, stp[2] * BX * BY};
+                    int li = lc[0] + BX * (lc[1] + BY * lc[2]);
+                    Real sub_acc = 0;
+                    const bool in_brick = lc[0] >= 0 && lc[0] < BX && lc[1] >= 0 && lc[1] < BY && lc[2] >= 0 && lc[2] < BZ;
+                    if (!in_brick) end = 4;            // hand it to the brick that holds its cell
+                    const Real floor_abs = floor_f * sum0;
+                    // photons left (in units of the cast weight), kept by
+                    // subtracting each segment's absorption, for the flux floor
+                    Real sumE = 0;
+    #pragma unroll
+                    for (int b = 0; b < NB; b++) sumE += NE[b];
+                    // the opacity of the current cell; each step reads the next
+                    // cell's one iteration ahead (an index outside the brick, for a
+                    // packet about to leave it, reads cell 0 and is not used)
+                    OpT o_cur = s_op[(uint32_t)li < (uint32_t)BC ? li : 0];
+                    while (end < 0) {
+                        int axis = 0;
+                        Real r_face = rf[0];
+                        if (rf[1] < r_face) { r_face = rf[1]; axis = 1; }
+                        if (rf[2] < r_face) { r_face = rf[2]; axis = 2; }
+                        const int li_n = li + (axis == 0 ? inc[0] : (axis == 1 ? inc[1] : inc[2]));
+                        const OpT o_next = s_op[(uint32_t)li_n < (uint32_t)BC ? li_n : 0];
+                        const Real r_end = fmax(fmin(r_face, r_lim), h.r);
+                        const Real ds = r_end - h.r;
+                        if (ds > Real(0)) {
+                            R2 o;
+                            if constexpr (SUB) {
+                                o = o_cur;
+                            } else {
+                                o.x = o_cur;
+                                o.y = Real(0);
                             }
-                            if (tk > Real(0)) {
-                                const Real y = tk - T[3];
-                                const Real t = T[1] + y;
-                                T[3] = (t - T[1]) - y;
-                                T[1] = t;
-                            }
-                        } else {
-#pragma unroll
-                            for (int b = 0; b < NB; b++) {
-                                if constexpr (F32) {
-                                    // u = -log2(e) tau: e^-tau = 2^u
-                                    const Real u = sl2[b] * ta;
-                                    const Real eb = __builtin_amdgcn_exp2f(u);
-                                    absd += NE[b] * absorbed_u(u, eb);
-                                    NE[b] *= eb;
-                                } else {
-                                    const Real tb = srel[b] * ta;
+                            const Real ta = o.x * ds;
+                            Real dep = 0, absd = 0;
+                            if constexpr (SUB) {
+                                const Real tk = o.y * ds;
+    #pragma unroll
+                                for (int b = 0; b < NB; b++) {
+                                    const Real tb = srel[b] * ta + tk;
+                                    const Real nin = NE[b];
                                     const Real eb = exp_neg(tb);
-                                    absd += NE[b] * absorbed<Real>(tb, eb);
+                                    const Real af = absorbed<Real>(tb, eb);
+                                    const Real rt = fast_rcp(tb);
+                                    const Real phi = (tb > Real(0)) ? af * rt : Real(1);
+                                    dep += Kb[b] * nin * ds * phi;
+                                    absd += nin * af;
+                                    if (tk > Real(0)) sub_acc += nin * af * tk * rt;
                                     NE[b] *= eb;
                                 }
+                                if (tk > Real(0)) {
+                                    const Real y = tk - T[3];
+                                    const Real t = T[1] + y;
+                                    T[3] = (t - T[1]) - y;
+                                    T[1] = t;
+                                }
+                            } else {
+    #pragma unroll
+                                for (int b = 0; b < NB; b++) {
+                                    if constexpr (F32) {
+                                        // u = -log2(e) tau: e^-tau = 2^u
+                                        const Real u = sl2[b] * ta;
+                                        const Real eb = __builtin_amdgcn_exp2f(u);
+                                        absd += NE[b] * absorbed_u(u, eb);
+                                        NE[b] *= eb;
+                                    } else {
+                                        const Real tb = srel[b] * ta;
+                                        const Real eb = exp_neg(tb);
+                                        absd += NE[b] * absorbed<Real>(tb, eb);
+                                        NE[b] *= eb;
+                                    }
+                                }
+                                // the cell's absorbed photons; times KS / a_i when the
+                                // brick's deposits are added
+                                dep = absd;
                             }
-                            // the cell's absorbed photons; times KS / a_i when the
-                            // brick's deposits are added
-                            dep = absd;
+                            sumE -= absd;
+                            // Kahan-compensated optical depth carried by the packet
+                            {
+                                const Real y = ta - T[2];
+                                const Real t = T[0] + y;
+                                T[2] = (t - T[0]) - y;
+                                T[0] = t;
+                            }
+                            atomicAdd(&s_g[li], dep);
+                            v_cross++;
                         }
-                        sumE -= absd;
-                        // Kahan-compensated optical depth carried by the packet
-                        {
-                            const Real y = ta - T[2];
-                            const Real t = T[0] + y;
-                            T[2] = (t - T[0]) - y;
-                            T[0] = t;
+                        h.r = r_end;
+                        if (h.r >= r_lim) {
+                            // end states in order: distance cap, flux floor, split,
+                            // then the budget (a face reached with it is crossed first)
+                            if (h.r >= r_cap) { end = 2; break; }
+                            if (floor_f > Real(0) && sumE < floor_abs) { end = 2; break; }
+                            if (h.r >= r_split) { end = 0; break; }
+                            if (h.r < r_face) { end = 3; break; }
+                        } else if (floor_f > Real(0) && sumE < floor_abs) {
+                            end = 2;
+                            break;
                         }
-                        atomicAdd(&s_g[li], dep);
-                        v_cross++;
+                        // step to the next cell along `axis` (selects keep every
+                        // per-axis value in registers)
+                        const int st = axis == 0 ? stp[0] : (axis == 1 ? stp[1] : stp[2]);
+                        if (axis == 0) { c[0] += st; lc[0] += st; }
+                        else if (axis == 1) { c[1] += st; lc[1] += st; }
+                        else { c[2] += st; lc[2] += st; }
+                        li = li_n;
+                        const int ca = axis == 0 ? c[0] : (axis == 1 ? c[1] : c[2]);
+                        const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
+                        if (ca < 0 || ca >= dima) { end = 1; break; }
+                        const Real sa = axis == 0 ? s[0] : (axis == 1 ? s[1] : s[2]);
+                        const Real ia = axis == 0 ? inv[0] : (axis == 1 ? inv[1] : inv[2]);
+                        const Real rfa = ((Real)(ca + (st > 0 ? 1 : 0)) - sa) * ia;
+                        if (axis == 0) rf[0] = rfa;
+                        else if (axis == 1) rf[1] = rfa;
+                        else rf[2] = rfa;
+                        const int la = axis == 0 ? lc[0] : (axis == 1 ? lc[1] : lc[2]);
+                        const int ba = axis == 0 ? BX : (axis == 1 ? BY : BZ);
+                        if (la < 0 || la >= ba) {
+                            end = (h.r >= h.rstop) ? 3 : 4;
+                            break;
+                        }
+                        if (h.r >= h.rstop) { end = 3; break; }
+                        o_cur = o_next;
                     }
-                    h.r = r_end;
-                    if (h.r >= r_lim) {
-                        // end states in order: distance cap, flux floor, split,
-                        // then the budget (a face reached with it is crossed first)
-                        if (h.r >= r_cap) { end = 2; break; }
-                        if (floor_f > Real(0) && sumE < floor_abs) { end = 2; break; }
-                        if (h.r >= r_split) { end = 0; break; }
-                        if (h.r < r_face) { end = 3; break; }
-                    } else if (floor_f > Real(0) && sumE < floor_abs) {
-                        end = 2;
-                        break;
+                    // photons at the end of the visit from the carried optical
+                    // depth, exactly as the next visit will recompute them
+                    double n_end = 0.0;
+    #pragma unroll
+                    for (int b = 0; b < NB; b++) {
+                        n_end += (double)(N0[b] * (SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0])));
                     }
-                    // step to the next cell along `axis` (selects keep every
-                    // per-axis value in registers)
-                    const int st = axis == 0 ? stp[0] : (axis == 1 ? stp[1] : stp[2]);
-                    if (axis == 0) { c[0] += st; lc[0] += st; }
-                    else if (axis == 1) { c[1] += st; lc[1] += st; }
-                    else { c[2] += st; lc[2] += st; }
-                    li = li_n;
-                    const int ca = axis == 0 ? c[0] : (axis == 1 ? c[1] : c[2]);
-                    const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
-                    if (ca < 0 || ca >= dima) { end = 1; break; }
-                    const Real sa = axis == 0 ? s[0] : (axis == 1 ? s[1] : s[2]);
-                    const Real ia = axis == 0 ? inv[0] : (axis == 1 ? inv[1] : inv[2]);
-                    const Real rfa = ((Real)(ca + (st > 0 ? 1 : 0)) - sa) * ia;
-                    if (axis == 0) rf[0] = rfa;
-                    else if (axis == 1) rf[1] = rfa;
-                    else rf[2] = rfa;
-                    const int la = axis == 0 ? lc[0] : (axis == 1 ? lc[1] : lc[2]);
-                    const int ba = axis == 0 ? BX : (axis == 1 ? BY : BZ);
-                    if (la < 0 || la >= ba) {
-                        end = (h.r >= h.rstop) ? 3 : 4;
-                        break;
-                    }
-                    if (h.r >= h.rstop) { end = 3; break; }
-                    o_cur = o_next;
+                    if constexpr (SUB) v_sub = (double)sub_acc * Rr;
+                    v_abs = (n_start - n_end) * Rr - v_sub;
+                    v_end = n_end * Rr;
+                    h.cell = pack_cell(c);
                 }
-                // photons at the end of the visit from the carried optical
-                // depth, exactly as the next visit will recompute them
-                double n_end = 0.0;
-#pragma unroll
-                for (int b = 0; b < NB; b++) {
-                    n_end += (double)(N0[b] * (SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0])));
-                }
-                if constexpr (SUB) v_sub = (double)sub_acc * Rr;
-                v_abs = (n_start - n_end) * Rr - v_sub;
-                v_end = n_end * Rr;
-                h.cell = pack_cell(c);
-            }
-            // ---- slots in the next pass's input: packets entering another
-            // brick, then four per split packet (a child that escapes leaves
-            // its slot empty), reserved with one atomic before the ledger
-            // reductions and the children, which run while it flies
-            const unsigned long long m_next = __ballot(end == 4), m_par = __ballot(end == 0);
-            const uint32_t n_next = (uint32_t)__popcll(m_next);
-            const uint32_t n_out = n_next + 4u * (uint32_t)__popcll(m_par);
-            uint32_t o_raw = 0;
-            if (lane == 0 && n_out) o_raw = atomicAdd(o_ctr(ws, my_seg()), n_out);
-            const uint32_t ocap_seg = seg_cap(ws.buf[0].cap);
-            const uint32_t oseg0 = (uint32_t)my_seg() * ocap_seg;
-            // ---- ledger: counts from ballots, photon terms from wave sums
-            // taken only when some lane of the wave has one
-            {
-                const bool esc = end == 1, drop = end == 2, fl = end == 3;
-                const unsigned long long m_act = __ballot(active), m_split = __ballot(end == 0),
-                                         m_esc = __ballot(esc), m_drop = __ballot(drop), m_fl = __ballot(fl);
-                acc_abs += v_abs;
-                acc_cross += v_cross;
-                double t_sub = 0.0, t_esc = 0.0, t_drop = 0.0, t_fl = 0.0;
-                if constexpr (SUB) t_sub = wave_sum(v_sub);
-                if (m_esc) t_esc = wave_sum(esc ? v_end : 0.0);
-                if (m_drop) t_drop = wave_sum(drop ? v_end : 0.0);
-                if (m_fl) t_fl = wave_sum(fl ? v_end : 0.0);
-                if (lane == 0) {
-                    if (t_sub != 0.0) atomicAdd(&s_lf[LF_ABS_SUB], t_sub);
-                    if (t_esc != 0.0) atomicAdd(&s_lf[LF_ESC], t_esc);
-                    if (t_drop != 0.0) atomicAdd(&s_lf[LF_DROP], t_drop);
-                    if (t_fl != 0.0) atomicAdd(&s_lf[LF_FLIGHT], t_fl);
-                    if (m_act) atomicAdd(&s_lc[LC_VISITS], (unsigned long long)__popcll(m_act));
-                    if (m_split) atomicAdd(&s_lc[LC_SPLITS], (unsigned long long)__popcll(m_split));
-                    if (m_esc) atomicAdd(&s_lc[LC_NESC], (unsigned long long)__popcll(m_esc));
-                    if (m_drop) atomicAdd(&s_lc[LC_NDROP], (unsigned long long)__popcll(m_drop));
-                    if (m_fl) atomicAdd(&s_lc[LC_NFLIGHT], (unsigned long long)__popcll(m_fl));
-                }
-            }
-            // keys of the packets entering another brick, computed while the
-            // reservation flies
-            uint32_t key = 0;
-            if (end == 4) key = key_with_bin(brick_key(D, c), crossing_bin<Real>(D, c, s, h.d, h.r, h.rstop, level));
-            const uint32_t o_base = n_out ? reserve_end(o_raw, 0u) : 0u;
-            // ---- packets entering another brick go to the next pass
-            {
-                bool stored = false;
-                if (end == 4) {
-                    const uint32_t at = o_base + lanes_below(m_next);
-                    if (at < ocap_seg) {
-                        store_out<Real>(ws, oseg0 + at, h, key, T);
-                        stored = true;
-                    } else {
-                        raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
-                        atomicAdd(&s_lf[LF_LOST], v_end);
+                // ---- slots in the next pass's input for packets entering another
+                // brick, reserved with one atomic before the ledger reductions,
+                // which run while it flies
+                const unsigned long long m_next = __ballot(end == 4), m_par = __ballot(end == 0);
+                const uint32_t n_out = (uint32_t)__popcll(m_next);
+                uint32_t o_raw = 0;
+                if (lane == 0 && n_out) o_raw = atomicAdd(o_ctr(ws, my_seg()), n_out);
+                const uint32_t ocap_seg = seg_cap(ws.buf[0].cap);
+                const uint32_t oseg0 = (uint32_t)my_seg() * ocap_seg;
+                // ---- ledger: counts from ballots, photon terms from wave sums
+                // taken only when some lane of the wave has one
+                {
+                    const bool esc = end == 1, drop = end == 2, fl = end == 3;
+                    const unsigned long long m_act = __ballot(active), m_split = __ballot(end == 0),
+                                             m_esc = __ballot(esc), m_drop = __ballot(drop), m_fl = __ballot(fl);
+                    acc_abs += v_abs;
+                    acc_cross += v_cross;
+                    double t_sub = 0.0, t_esc = 0.0, t_drop = 0.0, t_fl = 0.0;
+                    if constexpr (SUB) t_sub = wave_sum(v_sub);
+                    if (m_esc) t_esc = wave_sum(esc ? v_end : 0.0);
+                    if (m_drop) t_drop = wave_sum(drop ? v_end : 0.0);
+                    if (m_fl) t_fl = wave_sum(fl ? v_end : 0.0);
+                    if (lane == 0) {
+                        if (t_sub != 0.0) atomicAdd(&s_lf[LF_ABS_SUB], t_sub);
+                        if (t_esc != 0.0) atomicAdd(&s_lf[LF_ESC], t_esc);
+                        if (t_drop != 0.0) atomicAdd(&s_lf[LF_DROP], t_drop);
+                        if (t_fl != 0.0) atomicAdd(&s_lf[LF_FLIGHT], t_fl);
+                        if (m_act) atomicAdd(&s_lc[LC_VISITS], (unsigned long long)__popcll(m_act));
+                        if (m_split) atomicAdd(&s_lc[LC_SPLITS], (unsigned long long)__popcll(m_split));
+                        if (m_esc) atomicAdd(&s_lc[LC_NESC], (unsigned long long)__popcll(m_esc));
+                        if (m_drop) atomicAdd(&s_lc[LC_NDROP], (unsigned long long)__popcll(m_drop));
+                        if (m_fl) atomicAdd(&s_lc[LC_NFLIGHT], (unsigned long long)__popcll(m_fl));
                     }
                 }
-                if (m_next) count_keys_wave(s_key, s_cnt, ws.hist, key & FRT_KEY_MASK, stored);
-            }
-            // ---- children of the packets at their split radius (Eq. lhpx):
-            // level + 1, NESTED pixels 4p .. 4p + 3, a quarter of the photons
-            // each, the parent's rotation, placed on their own pixel direction
-            // at the split radius; a child whose position is outside the box
-            // has escaped.  Up to 16 parents a round, four lanes per parent
-            // and one child per lane, so that the wave's lanes stay busy.
-            uint32_t done = 0;   // parents whose children are written
-            for (unsigned long long todo = m_par; todo;) {
-                const bool mine = ((todo >> lane) & 1ull) != 0;
-                const uint32_t rk = lanes_below(todo);
-                const bool now = mine && rk < 16u;
-                const uint32_t npar = min((uint32_t)__popcll(todo), 16u);
-                if (now) s_par[wv][rk] = (uint8_t)lane;
-                const uint32_t q = (uint32_t)lane >> 2, kq = (uint32_t)lane & 3u;
-                const bool cact = q < npar;
-                const int pl = cact ? (int)s_par[wv][q] : lane;
-                Pkt<Real> ch;
-                Real cT[4], cs[3];
-                ch.src = (uint32_t)__shfl((int)h.src, pl, WAVE);
-                ch.estep = (uint32_t)__shfl((int)h.estep, pl, WAVE);
-                const uint32_t plp = (uint32_t)__shfl((int)h.lp, pl, WAVE);
-                ch.r = __shfl(h.r, pl, WAVE);
-                ch.rstop = __shfl(h.rstop, pl, WAVE);
-                ch.w0 = __shfl(h.w0, pl, WAVE) * Real(0.25);
-#pragma unroll
-                for (int b = 0; b < 4; b++) cT[b] = __shfl(T[b], pl, WAVE);
-#pragma unroll
-                for (int a = 0; a < 3; a++) cs[a] = __shfl(s[a], pl, WAVE);
-                const double cph = 0.25 * __shfl(v_end, pl, WAVE);
-                const int clev = (int)(plp >> 28) + 1;
-                ch.lp = ((uint32_t)clev << 28) | (4u * (plp & 0x0fffffffu) + kq);
-                bool inside = false;
-                uint32_t ckey = 0;
-                if (cact) {
-                    packet_dir<Real>(D, ch.lp, ch.estep, ch.src, ch.d);
-                    int cc[3];
-                    inside = locate<Real>(D, cs, ch.r, ch.d, cc);
-                    if (inside) {
-                        ch.cell = pack_cell(cc);
-                        ckey = key_with_bin(brick_key(D, cc), crossing_bin<Real>(D, cc, cs, ch.d, ch.r, ch.rstop, clev));
-                    }
-                }
-                // child kq of the parent ranked `done + q` in the wave
-                const uint32_t at = o_base + n_next + 4u * (done + q) + kq;
-                bool stored = false;
-                if (cact) {
-                    if (at < ocap_seg) {
-                        if (inside) {
-                            store_out<Real>(ws, oseg0 + at, ch, ckey, cT);
+                // keys of the packets entering another brick, computed while the
+                // reservation flies
+                uint32_t key = 0;
+                if (end == 4) key = key_with_bin(brick_key(D, c), crossing_bin<Real>(D, c, s, h.d, h.r, h.rstop, level));
+                const uint32_t o_base = n_out ? reserve_end(o_raw, 0u) : 0u;
+                // ---- packets entering another brick go to the next pass
+                {
+                    bool stored = false;
+                    if (end == 4) {
+                        const uint32_t at = o_base + lanes_below(m_next);
+                        if (at < ocap_seg) {
+                            store_out<Real>(ws, oseg0 + at, h, key, T);
                             stored = true;
                         } else {
-                            (ws.out ? ws.bkey[1] : ws.bkey[0])[oseg0 + at] = FRT_KEY_NONE;
+                            raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
+                            atomicAdd(&s_lf[LF_LOST], v_end);
                         }
-                    } else if (inside) {
-                        raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
-                        atomicAdd(&s_lf[LF_LOST], cph);
+                    }
+                    if (m_next) count_keys_wave(s_key, s_cnt, ws.hist, key & FRT_KEY_MASK, stored);
+                }
+                // ---- children of the packets at their split radius (Eq. lhpx):
+                // level + 1, NESTED pixels 4p .. 4p + 3, a quarter of the photons
+                // each, the parent's rotation, placed on their own pixel direction
+                // at the split radius; a child whose position is outside the box
+                // has escaped.  Up to 16 parents a round, four lanes per parent
+                // and one child per lane, so that the wave's lanes stay busy.
+                for (unsigned long long todo = m_par; todo;) {
+                    const bool mine = ((todo >> lane) & 1ull) != 0;
+                    const uint32_t rk = lanes_below(todo);
+                    const bool now = mine && rk < 16u;
+                    const uint32_t npar = min((uint32_t)__popcll(todo), 16u);
+                    if (now) s_par[wv][rk] = (uint8_t)lane;
+                    const uint32_t q = (uint32_t)lane >> 2, kq = (uint32_t)lane & 3u;
+                    const bool cact = q < npar;
+                    const int pl = cact ? (int)s_par[wv][q] : lane;
+                    Pkt<Real> ch;
+                    Real cT[4], cs[3];
+                    ch.src = (uint32_t)__shfl((int)h.src, pl, WAVE);
+                    ch.estep = (uint32_t)__shfl((int)h.estep, pl, WAVE);
+                    const uint32_t plp = (uint32_t)__shfl((int)h.lp, pl, WAVE);
+                    ch.r = __shfl(h.r, pl, WAVE);
+                    ch.rstop = __shfl(h.rstop, pl, WAVE);
+                    ch.w0 = __shfl(h.w0, pl, WAVE) * Real(0.25);
+    #pragma unroll
+                    for (int b = 0; b < 4; b++) cT[b] = __shfl(T[b], pl, WAVE);
+    #pragma unroll
+                    for (int a = 0; a < 3; a++) cs[a] = __shfl(s[a], pl, WAVE);
+                    const double cph = 0.25 * __shfl(v_end, pl, WAVE);
+                    const int clev = (int)(plp >> 28) + 1;
+                    ch.lp = ((uint32_t)clev << 28) | (4u * (plp & 0x0fffffffu) + kq);
+                    bool inside = false;
+                    uint32_t ckey = 0;
+                    if (cact) {
+                        packet_dir<Real>(D, ch.lp, ch.estep, ch.src, ch.d);
+                        int cc[3];
+                        inside = locate<Real>(D, cs, ch.r, ch.d, cc);
+                        if (inside) {
+                            ch.cell = pack_cell(cc);
+                            ckey = key_with_bin(brick_key(D, cc), crossing_bin<Real>(D, cc, cs, ch.d, ch.r, ch.rstop, clev));
+                        }
+                    }
+                    // a child that starts in this brick is kept for the next
+                    // generation while the scratch records last; the others go to
+                    // the next pass
+                    bool keep = inside && (ckey & FRT_KEY_MASK) == w.key;
+                    const unsigned long long m_keep = __ballot(keep);
+                    if (m_keep) {
+                        uint32_t xb = 0;
+                        if (lane == 0) xb = atomicAdd(&s_xn, (uint32_t)__popcll(m_keep));
+                        const uint32_t xs = uni(xb) + lanes_below(m_keep);
+                        if (keep && xs < x_cap) store_pkt<Real>(x_q, x_base + xs, ch, 0u, cT);
+                        else keep = false;
+                    }
+                    const bool to_o = inside && !keep;
+                    bool stored = false;
+                    if (__ballot(to_o)) {
+                        const uint32_t at = wave_reserve_small(o_ctr(ws, my_seg()), to_o ? 1u : 0u);
+                        if (to_o) {
+                            if (at < ocap_seg) {
+                                store_out<Real>(ws, oseg0 + at, ch, ckey, cT);
+                                stored = true;
+                            } else {
+                                raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
+                                atomicAdd(&s_lf[LF_LOST], cph);
+                            }
+                        }
+                        count_keys_wave(s_key, s_cnt, ws.hist, ckey & FRT_KEY_MASK, stored);
+                    }
+                    const bool cesc = cact && !inside;
+                    const unsigned long long m_cesc = __ballot(cesc);
+                    if (m_cesc) {
+                        const double t_cesc = wave_sum(cesc ? cph : 0.0);
+                        if (lane == 0) {
+                            atomicAdd(&s_lf[LF_ESC], t_cesc);
+                            atomicAdd(&s_lc[LC_NESC], (unsigned long long)__popcll(m_cesc));
+                        }
+                    }
+                    todo &= ~__ballot(now);
+                }
+                // ---- packets that spent their travel budget: carried to the next step
+                if (__ballot(end == 3)) {
+                    const int nxt = 1 - (int)D.cur;
+                    const uint32_t fat = wave_reserve_small(&D.fcount[nxt], end == 3 ? 1u : 0u);
+                    if (end == 3) {
+                        if (fat < D.F[nxt].cap) {
+                            store_pkt<Real>(D.F[nxt], fat, h, brick_key(D, c) - D.key_base, T);
+                        } else {
+                            raise_error(ws, D.L, FRT_DEVERR_CARRY_OVERFLOW);
+                            atomicAdd(&s_lf[LF_LOST], v_end);
+                        }
                     }
                 }
-                count_keys_wave(s_key, s_cnt, ws.hist, ckey & FRT_KEY_MASK, stored);
-                const bool cesc = cact && !inside;
-                const unsigned long long m_cesc = __ballot(cesc);
-                if (m_cesc) {
-                    const double t_cesc = wave_sum(cesc ? cph : 0.0);
-                    if (lane == 0) {
-                        atomicAdd(&s_lf[LF_ESC], t_cesc);
-                        atomicAdd(&s_lc[LC_NESC], (unsigned long long)__popcll(m_cesc));
-                    }
-                }
-                todo &= ~__ballot(now);
-                done += npar;
             }
-            // ---- packets that spent their travel budget: carried to the next step
-            if (__ballot(end == 3)) {
-                const int nxt = 1 - (int)D.cur;
-                const uint32_t fat = wave_reserve_small(&D.fcount[nxt], end == 3 ? 1u : 0u);
-                if (end == 3) {
-                    if (fat < D.F[nxt].cap) {
-                        store_pkt<Real>(D.F[nxt], fat, h, brick_key(D, c) - D.key_base, T);
-                    } else {
-                        raise_error(ws, D.L, FRT_DEVERR_CARRY_OVERFLOW);
-                        atomicAdd(&s_lf[LF_LOST], v_end);
-                    }
-                }
-            }
+            // next generation: the children kept by this one (the scratch
+            // records are written and read by this workgroup only, so the
+            // barrier's workgroup-scope ordering makes them visible)
+            __syncthreads();
+            const uint32_t nx = min(s_xn, x_cap);
+            if (nx <= g_hi) break;
+            g_lo = g_hi;
+            g_hi = nx;
+            __syncthreads();
+            if (threadIdx.x == 0) s_chunk = 0;
+            __syncthreads();
         }
         {
             const double t_abs = wave_sum(acc_abs);
