@@ -975,41 +975,46 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             s_xn = 0;
         }
         __syncthreads();
-        // ---- order the item's packets by expected crossings: a counting
-        // sort whose bin counts are taken once per distinct bin of a wave
-        uint32_t slot_of[PER];
+        // ---- order packets by expected crossings: a counting sort of up to
+        // ITEM packets (bin NBIN: no packet) into s_order, whose bin counts
+        // are taken once per distinct bin of a wave; s_bin starts at zero
+        auto order_by_bin = [&](const uint32_t* eqv) -> uint32_t {
+            uint32_t slot_of[PER];
 #pragma unroll
-        for (int q = 0; q < PER; q++) {
-            const uint32_t e = eq[q];
-            const bool valid = e < (uint32_t)NBIN;
-            unsigned long long peers = __ballot(valid);
+            for (int q = 0; q < PER; q++) {
+                const uint32_t e = eqv[q];
+                const bool valid = e < (uint32_t)NBIN;
+                unsigned long long peers = __ballot(valid);
 #pragma unroll
-            for (int b = 0; b < 6; b++) {
-                const bool bit = (e >> b) & 1u;
-                const unsigned long long m = __ballot(bit);
-                peers &= bit ? m : ~m;
+                for (int b = 0; b < 6; b++) {
+                    const bool bit = (e >> b) & 1u;
+                    const unsigned long long m = __ballot(bit);
+                    peers &= bit ? m : ~m;
+                }
+                const int leader = valid ? __ffsll(peers) - 1 : lane;
+                uint32_t base = 0;
+                if (valid && lane == leader) base = atomicAdd(&s_bin[e], (uint32_t)__popcll(peers));
+                base = (uint32_t)__shfl((int)base, leader, WAVE);
+                slot_of[q] = valid ? ((e << 16) | (base + lanes_below(peers))) : 0xffffffffu;
             }
-            const int leader = valid ? __ffsll(peers) - 1 : lane;
-            uint32_t base = 0;
-            if (valid && lane == leader) base = atomicAdd(&s_bin[e], (uint32_t)__popcll(peers));
-            base = (uint32_t)__shfl((int)base, leader, WAVE);
-            slot_of[q] = valid ? ((e << 16) | (base + lanes_below(peers))) : 0xffffffffu;
-        }
-        if (threadIdx.x == 0) s_next = next_raw;   // read once this item is done
-        __syncthreads();
-        if (threadIdx.x < WAVE) {
-            uint32_t tot;
-            const uint32_t v = s_bin[threadIdx.x];
-            s_bin[threadIdx.x] = wave_excl_scan(v, &tot);
-            if (threadIdx.x == 0) s_nv = tot;
-        }
-        __syncthreads();
-        const uint32_t n_valid = s_nv;
+            __syncthreads();
+            if (threadIdx.x < WAVE) {
+                uint32_t tot;
+                const uint32_t v = s_bin[threadIdx.x];
+                s_bin[threadIdx.x] = wave_excl_scan(v, &tot);
+                if (threadIdx.x == 0) s_nv = tot;
+            }
+            __syncthreads();
+            const uint32_t n = s_nv;
 #pragma unroll
-        for (int q = 0; q < PER; q++)
-            if (slot_of[q] != 0xffffffffu)
-                s_order[s_bin[slot_of[q] >> 16] + (slot_of[q] & 0xffffu)] = (uint16_t)((uint32_t)q * BT + threadIdx.x);
-        __syncthreads();
+            for (int q = 0; q < PER; q++)
+                if (slot_of[q] != 0xffffffffu)
+                    s_order[s_bin[slot_of[q] >> 16] + (slot_of[q] & 0xffffu)] = (uint16_t)((uint32_t)q * BT + threadIdx.x);
+            __syncthreads();
+            return n;
+        };
+        if (threadIdx.x == 0) s_next = next_raw;   // read once this item is done
+        uint32_t n_cur = order_by_bin(eq);         // packets of the current generation
         const Real r_cap = uni((Real)D.r_cap);
         const Real floor_f = uni((Real)D.floor);
         const double Rr = uni(D.R_ref);
@@ -1027,16 +1032,16 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         // (their own children likewise), the rest go to the next pass.
         uint32_t g_lo = 0, g_hi = 0;   // scratch records of the current generation
         for (int gen = 0;; gen++) {
-            // waves take chunks of 64 packets as they finish: in generation 0
-            // sorted, longest chunks first, so that the waves end together
-            const uint32_t n_chunks = gen == 0 ? (n_valid + WAVE - 1) / WAVE : (g_hi - g_lo + WAVE - 1) / WAVE;
+            // waves take chunks of 64 sorted packets as they finish, longest
+            // chunks first, so that the waves end together
+            const uint32_t n_chunks = (n_cur + WAVE - 1) / WAVE;
             for (;;) {
                 uint32_t chunk = 0;
                 if (lane == 0) chunk = atomicAdd(&s_chunk, 1u);
                 chunk = uni(chunk);
                 if (chunk >= n_chunks) break;
-                const uint32_t p = gen == 0 ? (n_chunks - 1u - chunk) * WAVE + (uint32_t)lane : g_lo + chunk * WAVE + (uint32_t)lane;
-                const bool active = gen == 0 ? p < n_valid : p < g_hi;
+                const uint32_t p = (n_chunks - 1u - chunk) * WAVE + (uint32_t)lane;
+                const bool active = p < n_cur;
                 Pkt<Real> h;
                 Real T[4], NE[NB], N0[NB], s[3];   // NE: photons of each bin (units of the cast weight)
                 int level = 0, end = -1;     // -1 inactive, 0 split, 1 escaped, 2 dropped, 3 in flight, 4 next brick
@@ -1045,7 +1050,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                 uint32_t v_cross = 0;
                 if (active) {
                     if (gen == 0) load_pkt<Real>(in_q, ws.sorted[w.start + s_order[p]].x, h, T);
-                    else load_pkt<Real>(x_q, x_base + p, h, T);
+                    else load_pkt<Real>(x_q, x_base + g_lo + s_order[p], h, T);
                     level = (int)(h.lp >> 28);
                     const double* sp = D.src_pos + (size_t)h.src * 3;
                     s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
@@ -1316,7 +1321,9 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         uint32_t xb = 0;
                         if (lane == 0) xb = atomicAdd(&s_xn, (uint32_t)__popcll(m_keep));
                         const uint32_t xs = uni(xb) + lanes_below(m_keep);
-                        if (keep && xs < x_cap) store_pkt<Real>(x_q, x_base + xs, ch, 0u, cT);
+                        // the record keeps the child's crossing bin for the next
+                    // generation's ordering
+                    if (keep && xs < x_cap) store_pkt<Real>(x_q, x_base + xs, ch, ckey >> FRT_KEY_BITS, cT);
                         else keep = false;
                     }
                     const bool to_o = inside && !keep;
@@ -1366,10 +1373,18 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             const uint32_t nx = min(s_xn, x_cap);
             if (nx <= g_hi) break;
             g_lo = g_hi;
-            g_hi = nx;
+            g_hi = min(nx, g_lo + (uint32_t)ITEM);   // the rest in a later round
             __syncthreads();
             if (threadIdx.x == 0) s_chunk = 0;
+            if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
+            uint32_t ex[PER];
+#pragma unroll
+            for (int q = 0; q < PER; q++) {
+                const uint32_t j = (uint32_t)q * BT + threadIdx.x;
+                ex[q] = j < g_hi - g_lo ? recs<Real>(x_q)[x_base + g_lo + j].key : (uint32_t)NBIN;
+            }
             __syncthreads();
+            n_cur = order_by_bin(ex);
         }
         {
             const double t_abs = wave_sum(acc_abs);
