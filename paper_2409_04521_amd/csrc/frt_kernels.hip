@@ -1058,7 +1058,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                     if (h.estep == step && h.r == Real(0) && level == base_level) h.rstop = budget;
                     Real sum0 = 0;
                     double n_start = 0.0;
-    #pragma unroll
+#pragma unroll
                     for (int b = 0; b < NB; b++) {
                         Real spec;
                         if constexpr (F32) spec = D.spec[(size_t)h.src * NB + b];
@@ -1074,7 +1074,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                     const Real r_lim = fmin(fmin(r_split, r_cap), h.rstop);
                     Real inv[3], rf[3];
                     int stp[3];
-    #pragma unroll
+#pragma unroll
                     for (int a = 0; a < 3; a++) {
                         inv[a] = (h.d[a] != Real(0)) ? fast_rcp(h.d[a]) : Real(0);
                         stp[a] = h.d[a] > Real(0) ? 1 : -1;
@@ -1091,7 +1091,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                     // photons left (in units of the cast weight), kept by
                     // subtracting each segment's absorption, for the flux floor
                     Real sumE = 0;
-    #pragma unroll
+#pragma unroll
                     for (int b = 0; b < NB; b++) sumE += NE[b];
                     // the opacity of the current cell; each step reads the next
                     // cell's one iteration ahead (an index outside the brick, for a
@@ -1106,6 +1106,10 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         const OpT o_next = s_op[(uint32_t)li_n < (uint32_t)BC ? li_n : 0];
                         const Real r_end = fmax(fmin(r_face, r_lim), h.r);
                         const Real ds = r_end - h.r;
+                        // the deposit's LDS atomic is issued on every path (adding
+                        // 0 for an empty segment), so that waiting for the next
+                        // cell's prefetched opacity never waits for it
+                        Real dep = 0;
                         if (ds > Real(0)) {
                             R2 o;
                             if constexpr (SUB) {
@@ -1115,10 +1119,10 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                                 o.y = Real(0);
                             }
                             const Real ta = o.x * ds;
-                            Real dep = 0, absd = 0;
+                            Real absd = 0;
                             if constexpr (SUB) {
                                 const Real tk = o.y * ds;
-    #pragma unroll
+#pragma unroll
                                 for (int b = 0; b < NB; b++) {
                                     const Real tb = srel[b] * ta + tk;
                                     const Real nin = NE[b];
@@ -1138,7 +1142,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                                     T[1] = t;
                                 }
                             } else {
-    #pragma unroll
+#pragma unroll
                                 for (int b = 0; b < NB; b++) {
                                     if constexpr (F32) {
                                         // u = -log2(e) tau: e^-tau = 2^u
@@ -1165,9 +1169,9 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                                 T[2] = (t - T[0]) - y;
                                 T[0] = t;
                             }
-                            atomicAdd(&s_g[li], dep);
                             v_cross++;
                         }
+                        atomicAdd(&s_g[li], dep);
                         h.r = r_end;
                         if (h.r >= r_lim) {
                             // end states in order: distance cap, flux floor, split,
@@ -1208,7 +1212,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                     // photons at the end of the visit from the carried optical
                     // depth, exactly as the next visit will recompute them
                     double n_end = 0.0;
-    #pragma unroll
+#pragma unroll
                     for (int b = 0; b < NB; b++) {
                         n_end += (double)(N0[b] * (SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0])));
                     }
@@ -1294,9 +1298,9 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                     ch.r = __shfl(h.r, pl, WAVE);
                     ch.rstop = __shfl(h.rstop, pl, WAVE);
                     ch.w0 = __shfl(h.w0, pl, WAVE) * Real(0.25);
-    #pragma unroll
+#pragma unroll
                     for (int b = 0; b < 4; b++) cT[b] = __shfl(T[b], pl, WAVE);
-    #pragma unroll
+#pragma unroll
                     for (int a = 0; a < 3; a++) cs[a] = __shfl(s[a], pl, WAVE);
                     const double cph = 0.25 * __shfl(v_end, pl, WAVE);
                     const int clev = (int)(plp >> 28) + 1;
