@@ -174,6 +174,7 @@ struct frt_solve_s {
     int nx = 0, ny = 0, nz = 0;
     int bpx = 0, bpy = 0, bpz = 0;
     double dx = 0;
+    double w0_max = 0;                       // largest w0 any held packet can have
     size_t ncell = 0;
     FrtSolveDesc h{};
     FrtSolveDesc* d_desc = nullptr;
@@ -316,6 +317,10 @@ void set_step_fields(frt_solve s, double dt)
     h.dt = dt;
     h.budget = std::isfinite(s->P.c_ray_cm_s) ? s->P.c_ray_cm_s * dt / s->dx : HUGE_VAL;
     h.w0_cast = dt / (double)(12ull << (2 * s->P.base_level));
+    // a packet holds at most w0 photons per bin (the rates are scaled to at
+    // most 1), and no packet's w0 exceeds the largest cast weight so far
+    s->w0_max = std::max(s->w0_max, h.w0_cast);
+    h.dep_scale = (float)(std::ldexp(1.0, 46) / (s->w0_max * s->P.n_bins));
     for (int b = 0; b < FRT_MAX_BINS_I; b++) {
         double kb = b < s->P.n_bins ? h.R_ref * s->P.sigma_bins[b] / (s->dx * s->dx * dt) : 0.0;
         h.Kd[b] = kb;
@@ -1237,6 +1242,7 @@ int frt_load_sources(frt_solve s, int n_src, const double* pos_cm, const double*
     h.user_steps = 0;
     free_recs(s->F[0]);
     free_recs(s->F[1]);
+    s->w0_max = 0;   // no packet is held
     const uint32_t fcap = initial_fcap(s);
     RCCHK(alloc_recs(s->F[0], fcap, nb, s->rs));
     RCCHK(alloc_recs(s->F[1], fcap, nb, s->rs));
@@ -1549,6 +1555,20 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
         s->h.F[1] = nf[1];
     }
     if (nc) {
+        // the carried packets may come from steps with a longer dt
+        for (uint32_t i = 0; i < nc; i++) {
+            double w0;
+            if (s->fp64) {
+                double v;
+                std::memcpy(&v, p + i * rec + offsetof(FrtRec<double>, w0), sizeof(v));
+                w0 = v;
+            } else {
+                float v;
+                std::memcpy(&v, p + i * rec + offsetof(FrtRec<float>, w0), sizeof(v));
+                w0 = v;
+            }
+            if (std::isfinite(w0)) s->w0_max = std::max(s->w0_max, w0);
+        }
         FrtRecs hv{};
         hv.cap = nc;
         hv.rec = (void*)p;

@@ -872,7 +872,12 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
     // staged opacity: {a_i, b_i} with sub-grid opacity, a_i alone without
     using OpT = typename std::conditional<SUB, R2, Real>::type;
     __shared__ OpT s_op[BC];
-    __shared__ Real s_g[BC];
+    // deposits: FP32 without sub-grid opacity as 64-bit fixed point (LDS
+    // integer atomics run at the rate of plain stores here, FP32 LDS atomics
+    // far slower), else in the march precision
+    constexpr bool INTDEP = F32 && !SUB;
+    using GT = typename std::conditional<INTDEP, unsigned long long, Real>::type;
+    __shared__ GT s_g[BC];
     __shared__ double s_lf[LF_NF];
     __shared__ unsigned long long s_lc[LC_NC];
     __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
@@ -929,6 +934,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             sl2[b] = srel[b] * Real(-1.4426950408889634);   // -log2(e) s_nu
         }
         const Real KS = uni(F32 ? (Real)D.KS : (Real)D.KSd);
+        const float dsc = uni(D.dep_scale);   // fixed-point units per photon
         const uint32_t lb = w.key - uni(D.key_base);
         const int bx = (int)(lb % (uint32_t)D.bpx), by = (int)((lb / (uint32_t)D.bpx) % (uint32_t)D.bpy),
                   bz = (int)(lb / ((uint32_t)D.bpx * (uint32_t)D.bpy));
@@ -967,7 +973,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             const int t = k * BT + (int)threadIdx.x;
             if constexpr (SUB) s_op[t] = st[k];
             else s_op[t] = st[k].x;
-            s_g[t] = Real(0);
+            s_g[t] = GT(0);
         }
         if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
@@ -1171,7 +1177,16 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                             }
                             v_cross++;
                         }
-                        atomicAdd(&s_g[li], dep);
+                        if constexpr (INTDEP) {
+                            // whole units of the fixed point (dep <= 2^46 units),
+                            // split exactly into the two words of the 64-bit add
+                            const float x = __builtin_rintf(dep * dsc);
+                            const uint32_t hi = (uint32_t)(x * 0x1p-32f);
+                            const uint32_t lo = (uint32_t)__builtin_fmaf(-(float)hi, 0x1p32f, x);
+                            atomicAdd(&s_g[li], ((unsigned long long)hi << 32) | lo);
+                        } else {
+                            atomicAdd(&s_g[li], dep);
+                        }
                         h.r = r_end;
                         if (h.r >= r_lim) {
                             // end states in order: distance cap, flux floor, split,
@@ -1401,9 +1416,13 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         __syncthreads();
         // add the brick's deposits and its output-key counts once
         Real* __restrict__ gam = (Real*)D.gamma[D.step & 1u];
+        const double dun = 1.0 / (double)dsc;
         for (int t = threadIdx.x; t < BC; t += BT) {
-            Real v = s_g[t];
-            if (v != Real(0)) {
+            const GT q = s_g[t];
+            if (q != GT(0)) {
+                Real v;
+                if constexpr (INTDEP) v = (Real)((double)q * dun);
+                else v = q;
                 if constexpr (!SUB) v = v * (KS * fast_rcp<Real>(s_op[t]));
                 const int lx = t & (BX - 1), ly = (t >> LX) & (BY - 1), lz = t >> (LX + LY);
                 const size_t ci = (size_t)(ox + lx) + (size_t)nx * ((size_t)(oy + ly) + (size_t)ny * (size_t)(oz + lz));
