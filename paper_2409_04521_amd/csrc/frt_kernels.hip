@@ -1188,19 +1188,16 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                             atomicAdd(&s_g[li], dep);
                         }
                         h.r = r_end;
-                        if (h.r >= r_lim) {
-                            // end states in order: distance cap, flux floor, split,
-                            // then the budget (a face reached with it is crossed first)
-                            if (h.r >= r_cap) { end = 2; break; }
-                            if (floor_f > Real(0) && sumE < floor_abs) { end = 2; break; }
-                            if (h.r >= r_split) { end = 0; break; }
-                            if (h.r < r_face) { end = 3; break; }
-                        } else if (floor_f > Real(0) && sumE < floor_abs) {
-                            end = 2;
-                            break;
-                        }
+                        // end states before the step, in order: distance cap, flux
+                        // floor, split, then the budget (a face reached with it is
+                        // crossed first)
+                        const bool floored = floor_f > Real(0) && sumE < floor_abs;
+                        const int e_pre = (h.r >= r_lim)
+                                              ? ((h.r >= r_cap || floored) ? 2 : (h.r >= r_split ? 0 : (h.r < r_face ? 3 : -1)))
+                                              : (floored ? 2 : -1);
                         // step to the next cell along `axis` (selects keep every
-                        // per-axis value in registers)
+                        // per-axis value in registers); undone below for an end
+                        // before the step, so that the loop has a single exit
                         const int st = axis == 0 ? stp[0] : (axis == 1 ? stp[1] : stp[2]);
                         if (axis == 0) { c[0] += st; lc[0] += st; }
                         else if (axis == 1) { c[1] += st; lc[1] += st; }
@@ -1208,7 +1205,6 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         li = li_n;
                         const int ca = axis == 0 ? c[0] : (axis == 1 ? c[1] : c[2]);
                         const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
-                        if (ca < 0 || ca >= dima) { end = 1; break; }
                         const Real sa = axis == 0 ? s[0] : (axis == 1 ? s[1] : s[2]);
                         const Real ia = axis == 0 ? inv[0] : (axis == 1 ? inv[1] : inv[2]);
                         const Real rfa = ((Real)(ca + (st > 0 ? 1 : 0)) - sa) * ia;
@@ -1217,11 +1213,21 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         else rf[2] = rfa;
                         const int la = axis == 0 ? lc[0] : (axis == 1 ? lc[1] : lc[2]);
                         const int ba = axis == 0 ? BX : (axis == 1 ? BY : BZ);
-                        if (la < 0 || la >= ba) {
-                            end = (h.r >= h.rstop) ? 3 : 4;
+                        // after the step: leaving the box, leaving the brick, the
+                        // budget spent
+                        const bool spent = h.r >= h.rstop;
+                        const int e_post = (ca < 0 || ca >= dima) ? 1 : ((la < 0 || la >= ba) ? (spent ? 3 : 4) : (spent ? 3 : -1));
+                        if ((e_pre & e_post) >= 0) {      // either is an end state
+                            if (e_pre >= 0) {
+                                end = e_pre;
+                                if (axis == 0) c[0] -= st;
+                                else if (axis == 1) c[1] -= st;
+                                else c[2] -= st;
+                            } else {
+                                end = e_post;
+                            }
                             break;
                         }
-                        if (h.r >= h.rstop) { end = 3; break; }
                         o_cur = o_next;
                     }
                     // photons at the end of the visit from the carried optical
