@@ -1068,7 +1068,10 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     for (int a = 0; a < 3; a++) h.bsh[a] = s->bsh[a];
     h.ncast = 12u << (2 * P->base_level);
     h.sigma0 = P->sigma_bins[0];
-    for (int b = 0; b < P->n_bins; b++) h.sig_rel[b] = (float)(P->sigma_bins[b] / P->sigma_bins[0]);
+    for (int b = 0; b < P->n_bins; b++) {
+        h.sig_rel[b] = (float)(P->sigma_bins[b] / P->sigma_bins[0]);
+        h.sig_l2[b] = (float)(-1.4426950408889634 * P->sigma_bins[b] / P->sigma_bins[0]);
+    }
     h.r_split0 = std::sqrt(3.0 / (PI * P->n_ray_min));
     h.floor = (float)P->flux_floor;
     h.alpha_B = P->alpha_B;

@@ -114,6 +114,7 @@ struct FrtSolveDesc {
     double r_cap;               // distance cap in cells (+inf = none)
     float floor;                // flux floor (0 = off)
     float sig_rel[FRT_MAX_BINS_I];
+    float sig_l2[FRT_MAX_BINS_I];    // -log2(e) sig_rel: e^-(sig_rel t) = 2^(sig_l2 t)
     double alpha_B, coll_ion;
     // per-step block
     uint32_t step;              // index of the step being computed

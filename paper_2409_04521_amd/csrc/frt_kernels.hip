@@ -931,7 +931,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         for (int b = 0; b < NB; b++) {
             srel[b] = uni(srel_of<Real>(D, b));
             Kb[b] = SUB ? uni(K_of<Real>(D, b)) : Real(0);
-            sl2[b] = srel[b] * Real(-1.4426950408889634);   // -log2(e) s_nu
+            sl2[b] = uni((Real)D.sig_l2[b]);                // -log2(e) s_nu
         }
         const Real KS = uni(F32 ? (Real)D.KS : (Real)D.KSd);
         const float dsc = uni(D.dep_scale);   // fixed-point units per photon
@@ -1078,13 +1078,17 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                     const Real r_split = (level < max_level) ? (Real)(r_split0 * (double)(1u << level)) : rinf<Real>();
                     // the nearest of split radius, distance cap and budget end
                     const Real r_lim = fmin(fmin(r_split, r_cap), h.rstop);
-                    Real inv[3], rf[3];
+                    // distance to the next face along each axis, and the distance
+                    // between faces (Amanatides-Woo): the next face along an axis
+                    // is reached after one more cell's distance along it
+                    Real dtf[3], rf[3];
                     int stp[3];
 #pragma unroll
                     for (int a = 0; a < 3; a++) {
-                        inv[a] = (h.d[a] != Real(0)) ? fast_rcp(h.d[a]) : Real(0);
+                        const Real inv = (h.d[a] != Real(0)) ? fast_rcp(h.d[a]) : Real(0);
                         stp[a] = h.d[a] > Real(0) ? 1 : -1;
-                        rf[a] = (h.d[a] != Real(0)) ? ((Real)(c[a] + (h.d[a] > Real(0) ? 1 : 0)) - s[a]) * inv[a] : rinf<Real>();
+                        dtf[a] = fabs(inv);
+                        rf[a] = (h.d[a] != Real(0)) ? ((Real)(c[a] + (h.d[a] > Real(0) ? 1 : 0)) - s[a]) * inv : rinf<Real>();
                     }
                     // cell within the brick, and the change of its LDS index per step
                     int lc[3] = {c[0] - ox, c[1] - oy, c[2] - oz};
@@ -1110,7 +1114,15 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         if (rf[2] < r_face) { r_face = rf[2]; axis = 2; }
                         const int li_n = li + (axis == 0 ? inc[0] : (axis == 1 ? inc[1] : inc[2]));
                         const OpT o_next = s_op[(uint32_t)li_n < (uint32_t)BC ? li_n : 0];
-                        const Real r_end = fmax(fmin(r_face, r_lim), h.r);
+                        Real r_end;
+                        if constexpr (F32) {
+                            // max(min(r_face, r_lim), r) on the bit patterns: r and
+                            // r_lim are >= +0, so integer order is float order there,
+                            // and a negative r_face (from rounding) loses to r
+                            r_end = __int_as_float(max(min(__float_as_int(r_face), __float_as_int(r_lim)), __float_as_int(h.r)));
+                        } else {
+                            r_end = fmax(fmin(r_face, r_lim), h.r);
+                        }
                         const Real ds = r_end - h.r;
                         // the deposit's LDS atomic is issued on every path (adding
                         // 0 for an empty segment), so that waiting for the next
@@ -1205,9 +1217,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         li = li_n;
                         const int ca = axis == 0 ? c[0] : (axis == 1 ? c[1] : c[2]);
                         const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
-                        const Real sa = axis == 0 ? s[0] : (axis == 1 ? s[1] : s[2]);
-                        const Real ia = axis == 0 ? inv[0] : (axis == 1 ? inv[1] : inv[2]);
-                        const Real rfa = ((Real)(ca + (st > 0 ? 1 : 0)) - sa) * ia;
+                        const Real rfa = r_face + (axis == 0 ? dtf[0] : (axis == 1 ? dtf[1] : dtf[2]));
                         if (axis == 0) rf[0] = rfa;
                         else if (axis == 1) rf[1] = rfa;
                         else rf[2] = rfa;
