@@ -943,7 +943,8 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         const Real* __restrict__ opa = (const Real*)D.op_a;
         const Real* __restrict__ opb = (const Real*)D.op_b;
         // all of the item's loads at once: its packets' crossing bins (NBIN
-        // marks no packet), then the brick's opacities
+        // marks no packet), then the brick's opacities (-1 for cells outside
+        // the grid, which a packet reaching them has left the box through)
         uint32_t eq[PER];
 #pragma unroll
         for (int q = 0; q < PER; q++) {
@@ -957,7 +958,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             const int t = k * BT + (int)threadIdx.x;
             const int lx = t & (BX - 1), ly = (t >> LX) & (BY - 1), lz = t >> (LX + LY);
             const int cx = ox + lx, cy = oy + ly, cz = oz + lz;
-            st[k].x = Real(0);
+            st[k].x = Real(-1);
             st[k].y = Real(0);
             if (cx < nx && cy < ny && cz < nz) {
                 const size_t ci = (size_t)cx + (size_t)nx * ((size_t)cy + (size_t)ny * (size_t)cz);
@@ -1211,34 +1212,47 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         // per-axis value in registers); undone below for an end
                         // before the step, so that the loop has a single exit
                         const int st = axis == 0 ? stp[0] : (axis == 1 ? stp[1] : stp[2]);
-                        if (axis == 0) { c[0] += st; lc[0] += st; }
-                        else if (axis == 1) { c[1] += st; lc[1] += st; }
-                        else { c[2] += st; lc[2] += st; }
+                        if (axis == 0) lc[0] += st;
+                        else if (axis == 1) lc[1] += st;
+                        else lc[2] += st;
                         li = li_n;
-                        const int ca = axis == 0 ? c[0] : (axis == 1 ? c[1] : c[2]);
-                        const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
                         const Real rfa = r_face + (axis == 0 ? dtf[0] : (axis == 1 ? dtf[1] : dtf[2]));
                         if (axis == 0) rf[0] = rfa;
                         else if (axis == 1) rf[1] = rfa;
                         else rf[2] = rfa;
                         const int la = axis == 0 ? lc[0] : (axis == 1 ? lc[1] : lc[2]);
                         const int ba = axis == 0 ? BX : (axis == 1 ? BY : BZ);
-                        // after the step: leaving the box, leaving the brick, the
-                        // budget spent
+                        // after the step: leaving the brick (and the box, when the
+                        // brick's face is the box's), a cell outside the grid
+                        // within the brick (the box left), the budget spent
                         const bool spent = h.r >= h.rstop;
-                        const int e_post = (ca < 0 || ca >= dima) ? 1 : ((la < 0 || la >= ba) ? (spent ? 3 : 4) : (spent ? 3 : -1));
+                        const bool out_brick = la < 0 || la >= ba;
+                        Real o_n;   // HI opacity of the cell entered
+                        if constexpr (SUB) o_n = o_next.x;
+                        else o_n = o_next;
+                        const int e_post = out_brick ? (spent ? 3 : 4) : (o_n < Real(0) ? 1 : (spent ? 3 : -1));
                         if ((e_pre & e_post) >= 0) {      // either is an end state
                             if (e_pre >= 0) {
                                 end = e_pre;
-                                if (axis == 0) c[0] -= st;
-                                else if (axis == 1) c[1] -= st;
-                                else c[2] -= st;
+                                if (axis == 0) lc[0] -= st;
+                                else if (axis == 1) lc[1] -= st;
+                                else lc[2] -= st;
                             } else {
                                 end = e_post;
+                                if (out_brick) {
+                                    const int ca = (axis == 0 ? ox : (axis == 1 ? oy : oz)) + la;
+                                    const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
+                                    if (ca < 0 || ca >= dima) end = 1;
+                                }
                             }
                             break;
                         }
                         o_cur = o_next;
+                    }
+                    if (in_brick) {
+                        c[0] = ox + lc[0];
+                        c[1] = oy + lc[1];
+                        c[2] = oz + lc[2];
                     }
                     // photons at the end of the visit from the carried optical
                     // depth, exactly as the next visit will recompute them
