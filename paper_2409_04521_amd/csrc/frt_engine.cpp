@@ -328,6 +328,13 @@ void set_step_fields(frt_solve s, double dt)
     }
     h.KSd = h.R_ref * s->P.sigma_bins[0] / (s->dx * s->dx * dt);
     h.KS = (float)h.KSd;
+    if (h.has_sub) {
+        // with sub-grid opacity a crossing deposits K_nu N_nu ds phi, at most
+        // the largest K_nu times the packet's photons times sqrt(3) < 2
+        double kmax = 0.0;
+        for (int b = 0; b < s->P.n_bins; b++) kmax = std::max(kmax, h.Kd[b]);
+        h.dep_scale = (float)(std::ldexp(1.0, 46) / (2.0 * kmax * s->w0_max * s->P.n_bins));
+    }
 }
 
 int check_inputs_finite(const float* v, size_t n, const char* what)

@@ -14,7 +14,8 @@
 // march without sub-grid opacity stages 32 x 16 x 16 cells (32 KiB of HI
 // opacity, 64 KiB of 64-bit fixed-point deposits) for one 1024-thread
 // workgroup per CU; with sub-grid opacity 16^3 cells (both opacity parts and
-// FP32 deposits, 48 KiB) for 256-thread workgroups; the FP64 march 8^3.
+// the fixed-point deposits, 64 KiB) for 256-thread workgroups; the FP64
+// march 8^3.
 constexpr int FRT_BRICK_LOG_BIG[3] = {5, 4, 4};
 constexpr int FRT_BRICK_LOG_SUB[3] = {4, 4, 4};
 constexpr int FRT_BRICK_LOG_F64[3] = {3, 3, 3};
@@ -126,8 +127,10 @@ struct FrtSolveDesc {
     double KSd;
     double dt;
     double w0_cast;             // dt / (12 * 4^L0), seconds per cast packet
-    float dep_scale;            // fixed-point deposit units per photon: 2^46 over the photons of the
-                                // brightest packet the solve can hold (n_bins times the largest w0)
+    float dep_scale;            // fixed-point deposit units per unit deposit: 2^46 over the largest
+                                // deposit of one crossing (the photons of the brightest packet the
+                                // solve can hold, n_bins times the largest w0; with sub-grid
+                                // opacity times 2 max K_nu)
     // buffers
     const void* op_a;           // per cell n_HI sigma_0 dx (float or double)
     const void* op_b;           // per cell kappa dx (float or double)

@@ -872,10 +872,10 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
     // staged opacity: {a_i, b_i} with sub-grid opacity, a_i alone without
     using OpT = typename std::conditional<SUB, R2, Real>::type;
     __shared__ OpT s_op[BC];
-    // deposits: FP32 without sub-grid opacity as 64-bit fixed point (LDS
-    // integer atomics run at the rate of plain stores here, FP32 LDS atomics
-    // far slower), else in the march precision
-    constexpr bool INTDEP = F32 && !SUB;
+    // deposits: in the FP32 march as 64-bit fixed point (LDS integer atomics
+    // run at the rate of plain stores here, FP32 LDS atomics far slower),
+    // in the FP64 march as FP64
+    constexpr bool INTDEP = F32;
     using GT = typename std::conditional<INTDEP, unsigned long long, Real>::type;
     __shared__ GT s_g[BC];
     __shared__ double s_lf[LF_NF];
