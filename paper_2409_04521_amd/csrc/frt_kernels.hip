@@ -446,6 +446,39 @@ __device__ __forceinline__ uint32_t crossing_bin(const FrtSolveDesc& D, const in
 
 __device__ __forceinline__ uint32_t key_with_bin(uint32_t key, uint32_t bin) { return key | (bin << FRT_KEY_BITS); }
 
+// Output-key counts: an LDS table of KEY_SLOTS keys per workgroup, added to
+// the histogram once per key.
+constexpr int KEY_SLOTS = 128;
+
+__device__ __forceinline__ void count_key(uint32_t* s_key, uint32_t* s_cnt, uint32_t* hist, uint32_t key, uint32_t n)
+{
+    uint32_t slot = (key * 2654435761u) & (KEY_SLOTS - 1);
+    for (int probe = 0; probe < 16; probe++) {
+        const uint32_t prev = atomicCAS(&s_key[slot], 0xffffffffu, key);
+        if (prev == 0xffffffffu || prev == key) {
+            atomicAdd(&s_cnt[slot], n);
+            return;
+        }
+        slot = (slot + 1) & (KEY_SLOTS - 1);
+    }
+    atomicAdd(&hist[key], n);   // table crowded: count directly
+}
+
+// count_key for the lanes of a wave with `valid` set: one table update per
+// distinct key of the wave.  Every lane of the wave must call it.
+__device__ __forceinline__ void count_keys_wave(uint32_t* s_key, uint32_t* s_cnt, uint32_t* hist, uint32_t key, bool valid)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    unsigned long long todo = __ballot(valid);
+    while (todo) {
+        const int leader = __ffsll(todo) - 1;
+        const uint32_t k = __shfl(key, leader, WAVE);
+        const unsigned long long same = __ballot(valid && key == k);
+        if (lane == leader) count_key(s_key, s_cnt, hist, k, (uint32_t)__popcll(same));
+        todo &= ~same;
+    }
+}
+
 // ================================================================= seeding
 // Per solve: casting items (12 4^L0 per source) then the packets carried
 // from the previous step.
@@ -474,7 +507,9 @@ template <typename Real, int NB>
 __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
 {
     __shared__ uint32_t spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
+    __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];   // output keys counted per round
     for (int i = threadIdx.x; i <= ws.n_solves; i += blockDim.x) spre[i] = ws.seed_prefix[i];
+    if (threadIdx.x < KEY_SLOTS) { s_key[threadIdx.x] = 0xffffffffu; s_cnt[threadIdx.x] = 0; }
     __syncthreads();
     const uint32_t total = spre[ws.n_solves];
     LaneLedger led;
@@ -485,12 +520,9 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
         const uint32_t g = base + threadIdx.x;
         const bool active = g < total;
         const int si = find_in_prefix(spre, ws.n_solves, active ? g : base);
-        // flush when the block moves to another solve (block-uniform test)
-        __shared__ int s_first;
-        if (threadIdx.x == 0) s_first = si;
-        __syncthreads();
-        const int bsolve = s_first;
-        __syncthreads();
+        // flush when the block moves to another solve (the solve of the
+        // round's first item: block-uniform)
+        const int bsolve = find_in_prefix(spre, ws.n_solves, base);
         if (bsolve != cs) {
             if (cs >= 0) ledger_flush(led, descs[cs].L);
             cs = bsolve;
@@ -570,14 +602,27 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
             }
         }
         const uint32_t at = wave_reserve(o_ctr(ws, my_seg()), want);
+        bool stored = false;
         if (want) {
             if (at < seg_cap(ws.buf[0].cap)) {
                 store_out<Real>(ws, (uint32_t)my_seg() * seg_cap(ws.buf[0].cap) + at, h, key_with_bin(key, bin), T);
-                atomicAdd(&ws.hist[key], 1u);
+                stored = true;
             } else {
                 raise_error(ws, D.L, FRT_DEVERR_QUEUE_OVERFLOW);
             }
         }
+        // the round's brick counts go to the histogram once per distinct key
+        count_keys_wave(s_key, s_cnt, ws.hist, key, stored);
+        __syncthreads();
+        if (threadIdx.x < KEY_SLOTS) {
+            const uint32_t k = s_key[threadIdx.x];
+            if (k != 0xffffffffu) {
+                atomicAdd(&ws.hist[k], s_cnt[threadIdx.x]);
+                s_key[threadIdx.x] = 0xffffffffu;
+                s_cnt[threadIdx.x] = 0;
+            }
+        }
+        __syncthreads();
     }
     if (cs >= 0) ledger_flush(led, descs[cs].L);
 }
@@ -773,36 +818,6 @@ __device__ __forceinline__ float absorbed_u(float u, float eb)
     return u > -0.043280851f ? ser : dif;
 }
 
-constexpr int KEY_SLOTS = 128;
-
-__device__ __forceinline__ void count_key(uint32_t* s_key, uint32_t* s_cnt, uint32_t* hist, uint32_t key, uint32_t n)
-{
-    uint32_t slot = (key * 2654435761u) & (KEY_SLOTS - 1);
-    for (int probe = 0; probe < 16; probe++) {
-        const uint32_t prev = atomicCAS(&s_key[slot], 0xffffffffu, key);
-        if (prev == 0xffffffffu || prev == key) {
-            atomicAdd(&s_cnt[slot], n);
-            return;
-        }
-        slot = (slot + 1) & (KEY_SLOTS - 1);
-    }
-    atomicAdd(&hist[key], n);   // table crowded: count directly
-}
-
-// count_key for the lanes of a wave with `valid` set: one table update per
-// distinct key of the wave.  Every lane of the wave must call it.
-__device__ __forceinline__ void count_keys_wave(uint32_t* s_key, uint32_t* s_cnt, uint32_t* hist, uint32_t key, bool valid)
-{
-    const int lane = threadIdx.x & (WAVE - 1);
-    unsigned long long todo = __ballot(valid);
-    while (todo) {
-        const int leader = __ffsll(todo) - 1;
-        const uint32_t k = __shfl(key, leader, WAVE);
-        const unsigned long long same = __ballot(valid && key == k);
-        if (lane == leader) count_key(s_key, s_cnt, hist, k, (uint32_t)__popcll(same));
-        todo &= ~same;
-    }
-}
 
 // Lane-ordered prefix of a wave ballot: the number of set bits below the
 // calling lane.
