@@ -1036,7 +1036,15 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             return n;
         };
         if (threadIdx.x == 0) s_next = next_raw;   // read once this item is done
-        uint32_t n_cur = order_by_bin(eq);         // packets of the current generation
+        // packets of the current generation (one wave's worth needs no order)
+        const uint32_t n_item = w.start < np ? min(w.count, np - w.start) : 0u;
+        uint32_t n_cur = n_item;
+        if (n_item <= (uint32_t)WAVE) {
+            if (threadIdx.x < n_item) s_order[threadIdx.x] = (uint16_t)threadIdx.x;
+            __syncthreads();
+        } else {
+            n_cur = order_by_bin(eq);
+        }
         const Real r_cap = uni((Real)D.r_cap);
         const Real floor_f = uni((Real)D.floor);
         const double Rr = uni(D.R_ref);
@@ -1440,6 +1448,13 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             g_hi = min(nx, g_lo + (uint32_t)ITEM);   // the rest in a later round
             __syncthreads();
             if (threadIdx.x == 0) s_chunk = 0;
+            if (g_hi - g_lo <= (uint32_t)WAVE) {
+                // one wave marches them all: their order makes no difference
+                if (threadIdx.x < g_hi - g_lo) s_order[threadIdx.x] = (uint16_t)threadIdx.x;
+                __syncthreads();
+                n_cur = g_hi - g_lo;
+                continue;
+            }
             if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
             uint32_t ex[PER];
 #pragma unroll
