@@ -30,6 +30,13 @@
  *                         form, Gamma=0 recombination, dt->inf equilibrium
  *                         (Eq. equilibrium_condition), convergence to an
  *                         ODE solver (Eq. ion_balance_eqn).
+ *   chemistry_avg         x(t) and <x> against an ODE solver and its
+ *                         quadrature at fixed n_e (Eqs. xi_of_t, avg_xi),
+ *                         alpha=0 exponential decay, dt->inf equilibrium.
+ *   orc_step (averaged)   with alpha = C = 0 the iterated step ionizes as many
+ *                         atoms as its last march absorbed photons (the
+ *                         photon conservation of §4.1), to the iteration's
+ *                         convergence; ledger closure.
  *   orc_step              photon ledger closure, Stromgren I-front
  *                         (Eqs. r_of_t, rS, trec), checkpoint equality.
  *   Whole-field values beyond these properties: parity unpinned (the paper
@@ -60,6 +67,8 @@ typedef struct {
     double max_dist;         /* drop at this distance from the source, cm; 0 = off */
     double c_ray;            /* packet speed, cm/s; +inf = finish within the step */
     int n_chunks;            /* fixed source chunking for a deterministic sum */
+    int chem_iterations;     /* 0: backward Euler; K >= 1: the time-averaged update
+                                of §4.1 with K marches per step */
 } orc_params;
 
 typedef struct {
@@ -444,6 +453,28 @@ double chemistry_be(double x, double gamma, double nH, double alpha, double coll
     return 2.0 * c / (-b + sqrt(disc));
 }
 
+/* Time-averaged update of §4.1 (Eqs. xi_of_t, xeq, ti, avg_xi), for the
+ * neutral fraction x = 1 - x_i, which follows the same linear equation once
+ * the electron density n_e is held fixed over the step:
+ *   dx/dt = alpha n_e (1 - x) - (Gamma + C n_e) x        (Eq. ion_balance_eqn / n_H)
+ * with the equilibrium x_eq = alpha n_e / R and time constant t_i = 1 / R,
+ * R = Gamma + C n_e + alpha n_e.  Then
+ *   x(dt) = x_eq + (x0 - x_eq) exp(-dt/t_i)
+ *   <x>   = x_eq + (x0 - x_eq) (1 - exp(-dt/t_i)) t_i / dt.
+ * Returns <x> and stores x(dt) in *x_end.  With R = 0 nothing changes. */
+double chemistry_avg(double x0, double gamma, double ne, double alpha, double coll, double dt, double* x_end)
+{
+    const double R = gamma + coll * ne + alpha * ne;
+    const double y = R * dt;
+    if (!(y > 0.0)) {
+        *x_end = x0;
+        return x0;
+    }
+    const double xeq = alpha * ne / R;
+    *x_end = xeq + (x0 - xeq) * exp(-y);
+    return xeq + (x0 - xeq) * (-expm1(-y) / y);
+}
+
 /* ------------------------------------------------------------ state API */
 orc_state* orc_create(const orc_params* P, const float* nH, const float* kappa, const double* x0)
 {
@@ -499,7 +530,16 @@ int orc_set_sources(orc_state* S, int nsrc, const double* pos, const double* ndo
  * sphere rotation.  Order: opacity snapshot, casting, march of every packet
  * (carried and new), chemistry, ledger.  Sources are cut into n_chunks
  * fixed chunks, each with its own Gamma buffer and ledger, summed in chunk
- * order, so the result does not depend on the thread count. */
+ * order, so the result does not depend on the thread count.
+ *
+ * With chem_iterations = K >= 1 the step follows the iteration of §4.1:
+ * the first march sees n_HI of the start of the step; after march k < K the
+ * time-averaged <x> of every cell (Eq. avg_xi, with that march's Gamma and
+ * n_e = n_H (1 - <x>) of the previous estimate, first x0) gives the n_HI the
+ * next march sees (Eq. gamma_updated_standard).  Each march starts from the
+ * same packets, and only the last one's deposits, ledger and carried packets
+ * are kept; x(dt) (Eq. xi_of_t) then uses the last Gamma and n_e of the last
+ * estimate. */
 int orc_step(orc_state* S, double dt, const double* u, int nthreads)
 {
     const orc_params* P = &S->p;
@@ -511,58 +551,84 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
     chunk_ledger* Lk = (chunk_ledger*)calloc(K, sizeof(chunk_ledger));
     orc_vec* new_flight = (orc_vec*)calloc(S->nsrc > 0 ? S->nsrc : 1, sizeof(orc_vec));
     if (!nHI || !gk || !Lk || !new_flight) return -1;
-    for (long long i = 0; i < N; i++) nHI[i] = S->nH[i] * S->x[i];
+    const int n_iter = P->chem_iterations > 0 ? P->chem_iterations : 1;
+    double* xavg = NULL;
+    if (P->chem_iterations > 0) {
+        xavg = (double*)malloc(sizeof(double) * N);
+        if (!xavg) return -1;
+        memcpy(xavg, S->x, sizeof(double) * N);
+    }
     const double V = P->dx * P->dx * P->dx;
     const long long ncast = 12LL << (2 * P->base_level);
     if (nthreads < 1) nthreads = 1;
 
-#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
-    for (int k = 0; k < K; k++) {
-        orc_vec stack = {0, 0, 0};
-        march_ctx M;
-        M.S = S; M.nHI = nHI; M.gamma = gk + (size_t)k * N; M.L = Lk + k;
-        M.stack = &stack; M.inv_vdt = 1.0 / (V * dt);
-        int s0 = (int)(((long long)S->nsrc * k) / K), s1 = (int)(((long long)S->nsrc * (k + 1)) / K);
-        for (int s = s0; s < s1; s++) {
-            M.flight_out = &new_flight[s];
-            /* packets carried from the previous step get a fresh budget */
-            for (long long j = 0; j < S->flight[s].n; j++) {
-                orc_ray ray = S->flight[s].v[j];
-                ray.r_stop = ray.r + P->c_ray * dt;
-                march_one_ray(&M, &ray);
-                drain(&M);
-            }
-            /* casting on this step's rotated sphere (§3.1, Eq. Nray) */
-            double R[9];
-            shoemake_rotation(u + 3 * s, R);
-            for (long long p = 0; p < ncast; p++) {
-                orc_ray ray;
-                memset(&ray, 0, sizeof(ray));
-                ray.src = s; ray.level = P->base_level; ray.pix = p;
-                memcpy(ray.R, R, sizeof(R));
-                set_direction(&ray);
-                ray.r = 0.0;
-                ray.r_stop = P->c_ray * dt;
-                for (int b = 0; b < nb; b++) {
-                    ray.N[b] = S->ndot[(size_t)s * nb + b] * dt / (double)ncast;
-                    ray.Ninit[b] = ray.N[b];
-                    csum_add(&M.L->emitted, ray.N[b]);
-                }
-                M.L->rays_emitted++;
-                march_one_ray(&M, &ray);
-                drain(&M);
+    for (int it = 0; it < n_iter; it++) {
+        for (long long i = 0; i < N; i++) nHI[i] = S->nH[i] * (xavg ? xavg[i] : S->x[i]);
+        if (it > 0) {
+            /* the march starts again from the step's packets */
+            memset(gk, 0, sizeof(double) * (size_t)K * N);
+            memset(Lk, 0, sizeof(chunk_ledger) * K);
+            for (int s = 0; s < S->nsrc; s++) {
+                free(new_flight[s].v);
+                memset(&new_flight[s], 0, sizeof(orc_vec));
             }
         }
-        free(stack.v);
+
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+        for (int k = 0; k < K; k++) {
+            orc_vec stack = {0, 0, 0};
+            march_ctx M;
+            M.S = S; M.nHI = nHI; M.gamma = gk + (size_t)k * N; M.L = Lk + k;
+            M.stack = &stack; M.inv_vdt = 1.0 / (V * dt);
+            int s0 = (int)(((long long)S->nsrc * k) / K), s1 = (int)(((long long)S->nsrc * (k + 1)) / K);
+            for (int s = s0; s < s1; s++) {
+                M.flight_out = &new_flight[s];
+                /* packets carried from the previous step get a fresh budget */
+                for (long long j = 0; j < S->flight[s].n; j++) {
+                    orc_ray ray = S->flight[s].v[j];
+                    ray.r_stop = ray.r + P->c_ray * dt;
+                    march_one_ray(&M, &ray);
+                    drain(&M);
+                }
+                /* casting on this step's rotated sphere (§3.1, Eq. Nray) */
+                double R[9];
+                shoemake_rotation(u + 3 * s, R);
+                for (long long p = 0; p < ncast; p++) {
+                    orc_ray ray;
+                    memset(&ray, 0, sizeof(ray));
+                    ray.src = s; ray.level = P->base_level; ray.pix = p;
+                    memcpy(ray.R, R, sizeof(R));
+                    set_direction(&ray);
+                    ray.r = 0.0;
+                    ray.r_stop = P->c_ray * dt;
+                    for (int b = 0; b < nb; b++) {
+                        ray.N[b] = S->ndot[(size_t)s * nb + b] * dt / (double)ncast;
+                        ray.Ninit[b] = ray.N[b];
+                        csum_add(&M.L->emitted, ray.N[b]);
+                    }
+                    M.L->rays_emitted++;
+                    march_one_ray(&M, &ray);
+                    drain(&M);
+                }
+            }
+            free(stack.v);
+        }
+
+        /* deterministic chunk-ordered reduction */
+        for (long long i = 0; i < N; i++) {
+            double g = 0.0;
+            for (int k = 0; k < K; k++) g += gk[(size_t)k * N + i];
+            S->gamma[i] = g;
+        }
+        if (it + 1 < n_iter)
+            for (long long i = 0; i < N; i++) {
+                double xe;
+                const double ne = S->nH[i] * (1.0 - xavg[i]);
+                xavg[i] = chemistry_avg(S->x[i], S->gamma[i], ne, P->alpha_B, P->coll_ion, dt, &xe);
+            }
     }
 
-    /* deterministic chunk-ordered reduction */
     long long cross = 0;
-    for (long long i = 0; i < N; i++) {
-        double g = 0.0;
-        for (int k = 0; k < K; k++) g += gk[(size_t)k * N + i];
-        S->gamma[i] = g;
-    }
     csum tot[5];
     {
         const double prev[5] = {S->L.emitted, S->L.absorbed_HI, S->L.absorbed_sub, S->L.escaped, S->L.dropped};
@@ -601,8 +667,18 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
     S->L.n_in_flight = nfl;
 
     /* chemistry closes the step */
-    for (long long i = 0; i < N; i++)
-        S->x[i] = chemistry_be(S->x[i], S->gamma[i], S->nH[i], P->alpha_B, P->coll_ion, dt);
+    if (xavg) {
+        for (long long i = 0; i < N; i++) {
+            double xe;
+            const double ne = S->nH[i] * (1.0 - xavg[i]);
+            (void)chemistry_avg(S->x[i], S->gamma[i], ne, P->alpha_B, P->coll_ion, dt, &xe);
+            S->x[i] = xe;
+        }
+        free(xavg);
+    } else {
+        for (long long i = 0; i < N; i++)
+            S->x[i] = chemistry_be(S->x[i], S->gamma[i], S->nH[i], P->alpha_B, P->coll_ion, dt);
+    }
 
     S->step++;
     free(nHI); free(gk); free(Lk); free(new_flight);

@@ -35,7 +35,7 @@ class Params(C.Structure):
                 ("alpha_B", C.c_double), ("coll_ion", C.c_double),
                 ("base_level", C.c_int), ("max_level", C.c_int), ("n_ray_min", C.c_double),
                 ("flux_floor", C.c_double), ("max_dist", C.c_double), ("c_ray", C.c_double),
-                ("n_chunks", C.c_int)]
+                ("n_chunks", C.c_int), ("chem_iterations", C.c_int)]
 
 
 class Ledger(C.Structure):
@@ -80,6 +80,8 @@ def lib():
         L.split_radius.argtypes = [C.c_double, C.c_int, C.c_double]
         L.chemistry_be.restype = C.c_double
         L.chemistry_be.argtypes = [C.c_double] * 6
+        L.chemistry_avg.restype = C.c_double
+        L.chemistry_avg.argtypes = [C.c_double] * 6 + [C.POINTER(C.c_double)]
         L.orc_debug_transmit.restype = C.c_int
         L.orc_debug_transmit.argtypes = [C.c_void_p, dp, dp, dp, C.c_double, dp, dp]
         _lib = L
@@ -116,13 +118,20 @@ def chemistry(x, gamma, nH, alpha, coll, dt) -> float:
     return float(lib().chemistry_be(x, gamma, nH, alpha, coll, dt))
 
 
+def chemistry_avg(x0, gamma, ne, alpha, coll, dt):
+    """(<x>, x(dt)) of the time-averaged update at fixed n_e."""
+    xe = C.c_double(0.0)
+    xa = lib().chemistry_avg(x0, gamma, ne, alpha, coll, dt, C.byref(xe))
+    return float(xa), float(xe.value)
+
+
 # ------------------------------------------------------------- the solver
 class Oracle:
     """One RT problem on the CPU: grid, sources, carried packets, ledger."""
 
     def __init__(self, shape, dx_cm, sigma_bins, alpha_B, n_H, kappa=None, x_HI0=None,
                  coll_ion=0.0, base_level=0, max_level=12, n_ray_min=1.0, flux_floor=0.0,
-                 max_dist_cm=0.0, c_ray=np.inf, n_chunks=16):
+                 max_dist_cm=0.0, c_ray=np.inf, n_chunks=16, chem_iterations=0):
         nz, ny, nx = shape
         sig = list(sigma_bins)
         P = Params()
@@ -133,6 +142,7 @@ class Oracle:
         P.alpha_B, P.coll_ion = alpha_B, coll_ion
         P.base_level, P.max_level, P.n_ray_min = base_level, max_level, n_ray_min
         P.flux_floor, P.max_dist, P.c_ray, P.n_chunks = flux_floor, max_dist_cm, c_ray, n_chunks
+        P.chem_iterations = chem_iterations
         self.P = P
         self.shape = (nz, ny, nx)
         self.ncell = nx * ny * nz

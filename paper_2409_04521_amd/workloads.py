@@ -161,6 +161,7 @@ class Problem:
     alpha_B: float = ALPHA_B_1E4
     coll_ion: float = 0.0
     seed: int = 0
+    chem_iterations: int = 0          # 0: backward Euler; K: time-averaged, K marches per step
     T: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
 
@@ -184,7 +185,8 @@ class Problem:
                     alpha_B=self.alpha_B, n_H=self.n_H, kappa=self.kappa, x_HI0=self.x_HI0,
                     coll_ion=self.coll_ion, base_level=self.base_level, max_level=self.max_level,
                     n_ray_min=self.n_ray_min, flux_floor=self.flux_floor,
-                    max_dist_cm=self.max_dist_cm, c_ray=self.c_ray)
+                    max_dist_cm=self.max_dist_cm, c_ray=self.c_ray,
+                    chem_iterations=self.chem_iterations)
 
     def footprint_bytes(self) -> int:
         return int(self.ncell * 64)
