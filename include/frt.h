@@ -59,6 +59,7 @@ extern "C" {
 #define FRT_F64 1           /* FP64 march (validation) */
 
 #define FRT_MAX_BINS 8
+#define FRT_MAX_CHEM_ITERATIONS 64
 
 typedef struct frt_ctx_s* frt_ctx;
 typedef struct frt_solve_s* frt_solve;
@@ -86,6 +87,15 @@ typedef struct {
                                        of workgroups, and a full segment is an overflow */
     uint64_t queue_hint;            /* automatic sizing only: first size of the pass queues in
                                        entries (0 = from the grid and source counts) */
+    int chem_iterations;            /* hydrogen update of a step (§4.1).  0 (default): backward
+                                       Euler of Eq. ion_balance_eqn with the step's Gamma.
+                                       K in 1..FRT_MAX_CHEM_ITERATIONS: the time-averaged update
+                                       (Eqs. xi_of_t, xeq, ti, avg_xi) with K marches per step;
+                                       march k > 1 sees n_HI = n_H <x> from march k-1 (Eq.
+                                       gamma_updated_standard) and n_e = n_H (1 - <x>) of the
+                                       previous estimate (first: the start of the step); only
+                                       the last march's deposits, ledger terms and carried
+                                       packets are kept */
 } frt_params;
 
 /* Cumulative photon ledger (photons) and counters of one solve.  With
@@ -104,7 +114,8 @@ typedef struct {
 
 /* Fill *p with defaults: 1 bin at 6.3e-18 cm^2, alpha_B = 2.59e-13,
  * coll_ion = 0, base_level 0, max_level 12, n_ray_min 1, no floor, no cap,
- * c_ray = speed of light, FRT_F32, seed 0, automatic queues, no hint. */
+ * c_ray = speed of light, FRT_F32, seed 0, automatic queues, no hint,
+ * backward-Euler chemistry (chem_iterations 0). */
 int frt_params_default(frt_params* p);
 
 /* Context bound to HIP device `hip_device`.  Owns nothing else. */

@@ -181,6 +181,7 @@ struct frt_solve_s {
     void* op = nullptr;
     void* gam[2] = {nullptr, nullptr};
     double* x = nullptr;
+    double* xavg = nullptr;                  // time-averaged chemistry only
     double* nH = nullptr;
     float* T = nullptr;
     double* src_pos = nullptr;
@@ -239,8 +240,8 @@ struct frt_solve_s {
         free_recs(mark_F);
         dev_free(mark_x);
         dev_free(mark_fc);
-        dev_free(d_desc); dev_free(op); dev_free(gam[0]); dev_free(gam[1]); dev_free(x); dev_free(nH); dev_free(T);
-        dev_free(src_pos); dev_free(spec); dev_free(specd); dev_free(quat); dev_free(user_u); dev_free(fcount);
+        dev_free(d_desc); dev_free(op); dev_free(gam[0]); dev_free(gam[1]); dev_free(x); dev_free(xavg); dev_free(nH);
+        dev_free(T); dev_free(src_pos); dev_free(spec); dev_free(specd); dev_free(quat); dev_free(user_u); dev_free(fcount);
         dev_free(fcount_snap); dev_free(L); dev_free(L_snap);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         stream = nullptr;
@@ -565,33 +566,54 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
             HIPCHK(hipMemcpyAsync(ss[i]->L_snap, ss[i]->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
             HIPCHK(hipMemcpyAsync(ss[i]->fcount_snap, ss[i]->fcount, 8, hipMemcpyDeviceToDevice, st));
         }
-    {
-        Timed t(tm, st, 0);
-        w.out = 0;   // seeds fill buffer 0, the input of the first pass
-        if ((e = frt::launch_clear(w, st)) != hipSuccess) return fail(FRT_EDEVICE, "clear: %s", hipGetErrorString(e));
-        if ((e = frt::launch_seed(ws.descs, w, fp64, st)) != hipSuccess) return fail(FRT_EDEVICE, "seed: %s", hipGetErrorString(e));
+    // backward Euler: one march, then the update; time-averaged chemistry:
+    // K marches from the same packets with <x> updated between them
+    const int K = ss[0]->P.chem_iterations;   // the same for every solve of a group
+    const int n_march = K > 0 ? K : 1;
+    if (K > 0) {
+        Timed t(tm, st, 2);
+        if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 0, st)) != hipSuccess)
+            return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
     }
-    for (int p = 0; p < g.passes; p++) {
-        w.out = (p + 1) & 1;   // pass p reads buffer p & 1 and fills the other
+    for (int it = 0; it < n_march; it++) {
+        if (it > 0) {
+            Timed t(tm, st, 3);
+            if ((e = frt::launch_iter_restart(ws.descs, n, st)) != hipSuccess) return fail(FRT_EDEVICE, "restart: %s", hipGetErrorString(e));
+        }
+        {
+            Timed t(tm, st, 0);
+            w.out = 0;   // seeds fill buffer 0, the input of the first pass
+            if ((e = frt::launch_clear(w, it > 0, st)) != hipSuccess) return fail(FRT_EDEVICE, "clear: %s", hipGetErrorString(e));
+            if ((e = frt::launch_seed(ws.descs, w, fp64, st)) != hipSuccess) return fail(FRT_EDEVICE, "seed: %s", hipGetErrorString(e));
+        }
+        for (int p = 0; p < g.passes; p++) {
+            w.out = (p + 1) & 1;   // pass p reads buffer p & 1 and fills the other
+            {
+                Timed t(tm, st, 3);
+                if ((e = frt::launch_pass(ws.descs, w, fp64, 0, st)) != hipSuccess) return fail(FRT_EDEVICE, "scan: %s", hipGetErrorString(e));
+                if ((e = frt::launch_pass(ws.descs, w, fp64, 1, st)) != hipSuccess) return fail(FRT_EDEVICE, "scatter: %s", hipGetErrorString(e));
+            }
+            {
+                Timed t(tm, st, 1);
+                if ((e = frt::launch_pass(ws.descs, w, fp64, 2, st)) != hipSuccess) return fail(FRT_EDEVICE, "march: %s", hipGetErrorString(e));
+                if (tm) tm->n_march++;
+            }
+        }
         {
             Timed t(tm, st, 3);
-            if ((e = frt::launch_pass(ws.descs, w, fp64, 0, st)) != hipSuccess) return fail(FRT_EDEVICE, "scan: %s", hipGetErrorString(e));
-            if ((e = frt::launch_pass(ws.descs, w, fp64, 1, st)) != hipSuccess) return fail(FRT_EDEVICE, "scatter: %s", hipGetErrorString(e));
+            if ((e = frt::launch_finish(ws.descs, w, st)) != hipSuccess) return fail(FRT_EDEVICE, "finish: %s", hipGetErrorString(e));
         }
-        {
-            Timed t(tm, st, 1);
-            if ((e = frt::launch_pass(ws.descs, w, fp64, 2, st)) != hipSuccess) return fail(FRT_EDEVICE, "march: %s", hipGetErrorString(e));
-            if (tm) tm->n_march++;
+        if (it + 1 < n_march) {
+            Timed t(tm, st, 2);
+            if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 1, st)) != hipSuccess)
+                return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         }
-    }
-    {
-        Timed t(tm, st, 3);
-        if ((e = frt::launch_finish(ws.descs, w, st)) != hipSuccess) return fail(FRT_EDEVICE, "finish: %s", hipGetErrorString(e));
     }
     {
         Timed t(tm, st, 2);
-        if ((e = frt::launch_chem(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, st)) != hipSuccess)
-            return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
+        if (K > 0) e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 2, st);
+        else e = frt::launch_chem(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, st);
+        if (e != hipSuccess) return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         if (tm) tm->n_chem++;
     }
     if (graph && (e = frt::launch_advance(ws.descs, w, st)) != hipSuccess)
@@ -686,7 +708,8 @@ int read_counters(Workspace& ws, hipStream_t st, uint32_t* out)
 bool split_by_shape(frt_solve* ss, int n, const double* dts, std::vector<std::vector<frt_solve>>& parts,
                     std::vector<std::vector<double>>& pdts)
 {
-    auto shape = [](frt_solve s) { return s->bsh[0] * 100 + s->bsh[1] * 10 + s->bsh[2]; };
+    // solves of one launch share the brick shape and the chemistry's march count
+    auto shape = [](frt_solve s) { return s->P.chem_iterations * 1000 + s->bsh[0] * 100 + s->bsh[1] * 10 + s->bsh[2]; };
     bool mixed = false;
     for (int i = 1; i < n; i++) mixed |= shape(ss[i]) != shape(ss[0]);
     if (!mixed) return false;
@@ -954,8 +977,9 @@ uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T,
     const uint64_t rs = P.march_precision == FRT_F64 ? 8 : 4;
     const uint64_t rec = rec_bytes(rs);
     const uint64_t cast = (uint64_t)n_src * (12ull << (2 * P.base_level));
-    // resident fields: opacity pair, two rate buffers, x_HI, n_H, T
-    uint64_t b = ncell * (4 * rs + 16 + (with_T ? 4 : 0));
+    // resident fields: opacity pair, two rate buffers, x_HI, n_H, T, and <x>
+    // of the time-averaged chemistry
+    uint64_t b = ncell * (4 * rs + 16 + (with_T ? 4 : 0) + (P.chem_iterations > 0 ? 8 : 0));
     // carried-packet queues (as first sized)
     double F = (double)cast + 1024;
     if (std::isfinite(P.c_ray_cm_s)) F += std::min((double)ncell, 8.0 * cast + 65536.0);
@@ -1039,6 +1063,8 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     if (!(P->max_distance_cm >= 0) || !std::isfinite(P->max_distance_cm)) return fail(FRT_EINVAL, "max_distance_cm must be finite and >= 0");
     if (!(P->c_ray_cm_s > 0)) return fail(FRT_EINVAL, "c_ray_cm_s must be > 0 (or +inf)");
     if (P->march_precision != FRT_F32 && P->march_precision != FRT_F64) return fail(FRT_EINVAL, "march_precision must be FRT_F32 or FRT_F64");
+    if (P->chem_iterations < 0 || P->chem_iterations > FRT_MAX_CHEM_ITERATIONS)
+        return fail(FRT_EINVAL, "chem_iterations %d outside 0..%d", P->chem_iterations, FRT_MAX_CHEM_ITERATIONS);
     HIPCHK(hipSetDevice(ctx->device));
     frt_solve s = new (std::nothrow) frt_solve_s;
     if (!s) return fail(FRT_ENOMEM, "solve");
@@ -1077,6 +1103,7 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     h.sigma0 = P->sigma_bins[0];
     for (int b = 0; b < P->n_bins; b++) {
         h.sig_rel[b] = (float)(P->sigma_bins[b] / P->sigma_bins[0]);
+        h.sig_reld[b] = P->sigma_bins[b] / P->sigma_bins[0];
         h.sig_l2[b] = (float)(-1.4426950408889634 * P->sigma_bins[b] / P->sigma_bins[0]);
     }
     h.r_split0 = std::sqrt(3.0 / (PI * P->n_ray_min));
@@ -1086,6 +1113,8 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     h.seed = P->seed;
     h.fcount = s->fcount;
     h.L = s->L;
+    h.fcount_snap = s->fcount_snap;
+    h.L_snap = s->L_snap;
     *out = s;
     return FRT_OK;
 }
@@ -1126,11 +1155,13 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
             if (!(hx[i] >= 0.0 && hx[i] <= 1.0)) return fail(FRT_EINVAL, "x_HI0[%zu] = %g outside [0,1]", i, hx[i]);
     }
     if (T) RCCHK(host_view(T, n, kind, bT, &hT));
-    dev_free(s->op); dev_free(s->gam[0]); dev_free(s->gam[1]); dev_free(s->x); dev_free(s->nH); dev_free(s->T);
+    dev_free(s->op); dev_free(s->gam[0]); dev_free(s->gam[1]); dev_free(s->x); dev_free(s->xavg);
+    dev_free(s->nH); dev_free(s->T);
     RCCHK(dev_alloc(&s->op, n * 2 * s->rs));
     RCCHK(dev_alloc(&s->gam[0], n * s->rs));
     RCCHK(dev_alloc(&s->gam[1], n * s->rs));
     RCCHK(dev_alloc((void**)&s->x, n * 8));
+    if (s->P.chem_iterations > 0) RCCHK(dev_alloc((void**)&s->xavg, n * 8));
     RCCHK(dev_alloc((void**)&s->nH, n * 8));
     if (T) RCCHK(dev_alloc((void**)&s->T, n * 4));
     s->nx = nx; s->ny = ny; s->nz = nz;
@@ -1182,6 +1213,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     h.gamma[0] = s->gam[0];
     h.gamma[1] = s->gam[1];
     h.x = s->x;
+    h.xavg = s->xavg;
     h.nH = s->nH;
     s->step = 0;
     s->have_grid = true;

@@ -115,6 +115,7 @@ struct FrtSolveDesc {
     double r_cap;               // distance cap in cells (+inf = none)
     float floor;                // flux floor (0 = off)
     float sig_rel[FRT_MAX_BINS_I];
+    double sig_reld[FRT_MAX_BINS_I];  // sigma_nu / sigma_0 for the FP64 march
     float sig_l2[FRT_MAX_BINS_I];    // -log2(e) sig_rel: e^-(sig_rel t) = 2^(sig_l2 t)
     double alpha_B, coll_ion;
     // per-step block
@@ -149,6 +150,12 @@ struct FrtSolveDesc {
     FrtRecs F[2];               // carried packets, alternating by step
     uint32_t* fcount;           // [2]
     FrtLedgerDev* L;
+    // time-averaged chemistry: the latest <x> of every cell, and the ledger
+    // and carried-queue counters of the start of the step, which every march
+    // of the step starts from
+    double* xavg;               // [ncell], or null with backward-Euler chemistry
+    const FrtLedgerDev* L_snap;
+    const uint32_t* fcount_snap;
 };
 
 // One work item of a pass: up to FRT_ITEM_RAYS packets of one brick.
@@ -202,7 +209,10 @@ hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix,
 hipError_t launch_prep_opacity(FrtSolveDesc* d_desc, unsigned long long ncell, int fp64, hipStream_t s);
 // Clear the launch counters and brick histogram (a kernel, so that a step
 // captured in a HIP graph holds no memset node).
-hipError_t launch_clear(const FrtWS& ws, hipStream_t s);
+hipError_t launch_clear(const FrtWS& ws, int keep_err, hipStream_t s);
+hipError_t launch_chem_avg(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
+                           unsigned long long total_cells, int fp64, int phase, hipStream_t s);
+hipError_t launch_iter_restart(FrtSolveDesc* d, int n_solves, hipStream_t s);
 // Advance every solve's step index on the device unless the step raised an
 // error (used by steps replayed from a HIP graph).
 hipError_t launch_advance(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);

@@ -405,7 +405,11 @@ __device__ __forceinline__ void raise_error(FrtWS& ws, FrtLedgerDev* L, uint32_t
 }
 
 template <typename Real>
-__device__ __forceinline__ Real srel_of(const FrtSolveDesc& D, int b) { return (Real)D.sig_rel[b]; }
+__device__ __forceinline__ Real srel_of(const FrtSolveDesc& D, int b)
+{
+    if constexpr (sizeof(Real) == 8) return D.sig_reld[b];
+    else return D.sig_rel[b];
+}
 
 template <typename Real>
 __device__ __forceinline__ Real K_of(const FrtSolveDesc& D, int b)
@@ -1530,11 +1534,13 @@ __global__ void __launch_bounds__(4 * BLOCK) k_brick_big(const FrtSolveDesc* __r
 }
 
 // ============================================================ bookkeeping
-__global__ void k_clear(FrtWS ws)
+// Clears the launch counters and the key histogram; a later march of the
+// same step keeps the error bits and the largest pass size seen so far.
+__global__ void k_clear(FrtWS ws, int keep_err)
 {
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < C_NCTR) ws.ctr[t] = 0;
+    if (t < C_NCTR && !(keep_err && (t == C_ERR || t == C_MAXP))) ws.ctr[t] = 0;
     for (uint32_t k = t; k < ws.nkeys; k += stride) ws.hist[k] = 0;
 }
 
@@ -1650,6 +1656,90 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
         D.x[i] = xn;
         ((Real*)D.op_aw)[i] = hi_opacity<Real>(nH * xn * D.sigma0 * D.dx_cm);
         gnext[i] = Real(0);
+    }
+}
+
+// Time-averaged hydrogen update (§4.1, Eqs. xi_of_t, xeq, ti, avg_xi) for
+// x = n_HI / n_H, which follows the same linear equation as x_i once n_e is
+// held fixed over the step: dx/dt = alpha n_e (1 - x) - (Gamma + C n_e) x.
+// With R = Gamma + C n_e + alpha n_e, x_eq = alpha n_e / R and y = R dt:
+//   x(dt) = x_eq + (x0 - x_eq) e^-y,   <x> = x_eq + (x0 - x_eq) (1 - e^-y) / y.
+// phase 0, before the first march: <x> = x0 and the opacity from x0;
+// phase 1, between marches: <x> from this march's Gamma and n_e = n_H (1 - <x>)
+//   of the previous estimate; the next march sees n_HI = n_H <x> (Eq.
+//   gamma_updated_standard) and starts from a cleared deposit buffer;
+// phase 2, after the last march: x = x(dt), the next step's opacity from it
+//   and its deposit buffer cleared.
+// A step whose queues overflowed leaves the state untouched.
+template <typename Real>
+__global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const unsigned long long* prefix,
+                                                    int n_solves, unsigned long long total, int phase)
+{
+    __shared__ unsigned long long spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
+    for (int i = threadIdx.x; i <= n_solves; i += blockDim.x) spre[i] = prefix[i];
+    __syncthreads();
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long g = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
+        int lo = 0, hi = n_solves - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (spre[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        const FrtSolveDesc& D = descs[lo];
+        if (D.L->err_flags) continue;
+        const size_t i = (size_t)(g - spre[lo]);
+        const double nH = D.nH[i];
+        const double x0 = D.x[i];
+        double xo;   // the neutral fraction the opacity is built from
+        if (phase == 0) {
+            D.xavg[i] = x0;
+            xo = x0;
+        } else {
+            Real* gcur = (Real*)D.gamma[D.step & 1u];
+            const double G = (double)gcur[i];
+            const double ne = nH * (1.0 - D.xavg[i]);
+            const double R = G + D.coll_ion * ne + D.alpha_B * ne;
+            const double y = R * D.dt;
+            double xa = x0, xe = x0;
+            if (y > 0.0) {
+                const double xeq = D.alpha_B * ne / R;
+                xe = xeq + (x0 - xeq) * exp(-y);
+                xa = xeq + (x0 - xeq) * (-expm1(-y) / y);
+            }
+            if (phase == 1) {
+                D.xavg[i] = xa;
+                gcur[i] = Real(0);
+                xo = xa;
+            } else {
+                D.x[i] = xe;
+                ((Real*)D.gamma[(D.step + 1u) & 1u])[i] = Real(0);
+                xo = xe;
+            }
+        }
+        ((Real*)D.op_aw)[i] = hi_opacity<Real>(nH * xo * D.sigma0 * D.dx_cm);
+    }
+}
+
+// Every march of a step after the first starts from the step's packets: the
+// ledger and the carried-queue counters go back to their values at the
+// start of the step, keeping the device error bits.  One workgroup per solve.
+__global__ void __launch_bounds__(BLOCK) k_iter_restart(FrtSolveDesc* descs)
+{
+    const FrtSolveDesc& D = descs[blockIdx.x];
+    __shared__ uint32_t s_err;
+    if (threadIdx.x == 0) s_err = D.L->err_flags;
+    __syncthreads();
+    constexpr int NW = (int)(sizeof(FrtLedgerDev) / sizeof(unsigned long long));
+    static_assert(sizeof(FrtLedgerDev) % sizeof(unsigned long long) == 0, "ledger copied as 8-byte words");
+    const unsigned long long* src = (const unsigned long long*)D.L_snap;
+    unsigned long long* dst = (unsigned long long*)D.L;
+    for (int k = threadIdx.x; k < NW; k += blockDim.x) dst[k] = src[k];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        D.L->err_flags |= s_err;
+        D.fcount[0] = D.fcount_snap[0];
+        D.fcount[1] = D.fcount_snap[1];
     }
 }
 
@@ -1811,10 +1901,26 @@ hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix,
     return hipGetLastError();
 }
 
-hipError_t launch_clear(const FrtWS& ws, hipStream_t s)
+hipError_t launch_clear(const FrtWS& ws, int keep_err, hipStream_t s)
 {
     const uint32_t n = ws.nkeys > C_NCTR ? ws.nkeys : C_NCTR;
-    hipLaunchKernelGGL(k_clear, dim3(grid_for(n, 4)), dim3(BLOCK), 0, s, ws);
+    hipLaunchKernelGGL(k_clear, dim3(grid_for(n, 4)), dim3(BLOCK), 0, s, ws, keep_err);
+    return hipGetLastError();
+}
+
+hipError_t launch_chem_avg(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
+                           unsigned long long total_cells, int fp64, int phase, hipStream_t s)
+{
+    if (total_cells == 0) return hipSuccess;
+    const int grid = grid_for(total_cells, 16);
+    if (fp64) hipLaunchKernelGGL(k_chem_avg<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase);
+    else hipLaunchKernelGGL(k_chem_avg<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_iter_restart(FrtSolveDesc* d, int n_solves, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_iter_restart, dim3(n_solves), dim3(BLOCK), 0, s, d);
     return hipGetLastError();
 }
 

@@ -44,7 +44,8 @@ class Params(C.Structure):
                 ("alpha_B", C.c_double), ("coll_ion", C.c_double), ("base_level", C.c_int),
                 ("max_level", C.c_int), ("n_ray_min", C.c_double), ("flux_floor", C.c_double),
                 ("max_distance_cm", C.c_double), ("c_ray_cm_s", C.c_double), ("march_precision", C.c_int),
-                ("seed", C.c_uint64), ("queue_capacity", C.c_uint64), ("queue_hint", C.c_uint64)]
+                ("seed", C.c_uint64), ("queue_capacity", C.c_uint64), ("queue_hint", C.c_uint64),
+                ("chem_iterations", C.c_int)]
 
 
 class Ledger(C.Structure):
@@ -219,7 +220,7 @@ class Solve:
 
     def __init__(self, ctx: Context, *, sigma_bins, alpha_B=2.59e-13, coll_ion=0.0, base_level=0,
                  max_level=12, n_ray_min=1.0, flux_floor=0.0, max_distance_cm=0.0, c_ray=2.99792458e10,
-                 precision="f32", seed=0, queue_capacity=0, queue_hint=0, stream=None):
+                 precision="f32", seed=0, queue_capacity=0, queue_hint=0, chem_iterations=0, stream=None):
         p = params_default()
         sig = list(sigma_bins)
         p.n_bins = len(sig)
@@ -231,6 +232,7 @@ class Solve:
         p.c_ray_cm_s = c_ray if c_ray is not None else math.inf
         p.march_precision = FRT_F64 if precision == "f64" else FRT_F32
         p.seed, p.queue_capacity, p.queue_hint = seed, queue_capacity, queue_hint
+        p.chem_iterations = chem_iterations
         self.ctx = ctx
         self.params = p
         self.n_bins = p.n_bins
@@ -364,6 +366,7 @@ def _params_for(prob, precision="f32", **kw) -> Params:
     p.seed = prob.seed
     p.queue_capacity = kw.get("queue_capacity", 0)
     p.queue_hint = kw.get("queue_hint", 0)
+    p.chem_iterations = getattr(prob, "chem_iterations", 0)
     return p
 
 
@@ -476,7 +479,7 @@ def solve_from_problem(ctx: Context, prob, precision="f32", use_table=True, **kw
     s = Solve(ctx, sigma_bins=prob.sigma_bins, alpha_B=prob.alpha_B, coll_ion=prob.coll_ion,
               base_level=prob.base_level, max_level=prob.max_level, n_ray_min=prob.n_ray_min,
               flux_floor=prob.flux_floor, max_distance_cm=prob.max_dist_cm, c_ray=prob.c_ray,
-              precision=precision, seed=prob.seed, **kw)
+              precision=precision, seed=prob.seed, chem_iterations=getattr(prob, "chem_iterations", 0), **kw)
     nz, ny, nx = prob.shape
     s.load_grid(prob.n_H, prob.dx_cm * nx, kappa=prob.kappa, x_HI0=prob.x_HI0, T=prob.T)
     s.load_sources(prob.src_pos_cm, prob.ndot_bins)
