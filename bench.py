@@ -109,6 +109,56 @@ def cpu_baseline(prob, n_sample: int, threads: int):
                       f"{cross} crossings in {dt:.1f} s (FP64 C oracle, OpenMP)"}
 
 
+def avgchem_leg(frt, W, K: int, steps: int, warmup: int, stream):
+    """Standard Mode with the time-averaged chemistry (K marches per step)
+    against backward Euler (one march) on the same evolving 128^3 box with
+    finite c and sub-grid opacity: ms per step of both, and the HBM rate of
+    the chemistry kernels (per cell: 28 B before the first march, 44 B after
+    each later one: Gamma f32, n_H, x and <x> f64, opacity f32)."""
+    import numpy as np
+    import torch
+
+    prob = W.lognormal_c2(n_steps=warmup + steps)
+    out = {"workload": f"{prob.name}: {prob.shape[2]}^3, {prob.n_src} sources, 4 bins, kappa_sub, c, dt 1 Myr",
+           "iterations": K, "steps": steps, "warmup": warmup}
+    xs = {}
+    for k in (0, K):
+        prob.chem_iterations = k
+        ctx = frt.Context(0)
+        s = frt.solve_from_problem(ctx, prob, stream=stream.cuda_stream)
+        for _ in range(warmup):
+            s.step(prob.dt_s)
+        s.sync()
+        s.set_timing(True)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            s.step(prob.dt_s)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        tm = s.timing()
+        tag = "avg" if k else "be"
+        out[f"{tag}_ms_per_step"] = ms
+        out[f"{tag}_march_ms_per_step"] = tm["march_ms"] / steps
+        out[f"{tag}_chem_ms_per_step"] = tm["chem_ms"] / steps
+        if k:
+            chem_bytes = prob.ncell * (28 + 44 * k)
+            out["avg_chem_bytes_per_step"] = chem_bytes
+            out["avg_chem_GBps"] = chem_bytes / (tm["chem_ms"] / steps * 1e-3) / 1e9
+        L = s.ledger()
+        out[f"{tag}_ledger_closure"] = abs(L["emitted"] - L["absorbed_HI"] - L["absorbed_sub"] - L["escaped"]
+                                           - L["dropped"] - L["in_flight"] - L["lost"]) / L["emitted"]
+        xs[k] = s.fields()[0]
+        s.close()
+        ctx.close()
+    out["cost_ratio"] = out["avg_ms_per_step"] / out["be_ms_per_step"]
+    out["mean_x_HI"] = {"be": float(np.mean(xs[0])), "avg": float(np.mean(xs[K]))}
+    return out
+
+
 def batched_leg(frt, W, n_boxes: int, steps: int, warmup: int, stream):
     """The uneven-box batch: the same boxes stepped one solve at a time
     (the plain per-solve path) and as one batch replayed from a HIP graph
@@ -245,6 +295,9 @@ def main():
     ap.add_argument("--batched-boxes", type=int, default=64)
     ap.add_argument("--batched-steps", type=int, default=49)
     ap.add_argument("--batched-warmup", type=int, default=1)
+    ap.add_argument("--no-avgchem", action="store_true", help="skip the time-averaged chemistry leg")
+    ap.add_argument("--avgchem-iterations", type=int, default=3)
+    ap.add_argument("--avgchem-steps", type=int, default=10)
     ap.add_argument("--no-served", action="store_true", help="skip the served (request trace) leg")
     ap.add_argument("--served-requests", type=int, default=32)
     ap.add_argument("--served-steps", type=int, default=50)
@@ -363,6 +416,12 @@ def main():
         out["batched"] = batched_leg(frt, W, args.batched_boxes, args.batched_steps, args.batched_warmup, stream)
         log(f"batched: {out['batched']['batched_crossings_per_s']:.3e} crossings/s vs plain "
             f"{out['batched']['plain_crossings_per_s']:.3e} (x{out['batched']['speedup']:.2f})")
+    if not args.no_avgchem:
+        log(f"time-averaged chemistry leg: K = {args.avgchem_iterations}, {args.avgchem_steps} steps")
+        out["avg_chem"] = avgchem_leg(frt, W, args.avgchem_iterations, args.avgchem_steps, 2, stream)
+        ac = out["avg_chem"]
+        log(f"time-averaged chemistry: {ac['avg_ms_per_step']:.2f} ms/step vs backward Euler "
+            f"{ac['be_ms_per_step']:.2f} (x{ac['cost_ratio']:.2f}); chemistry kernels {ac['avg_chem_GBps']:.0f} GB/s")
     if not args.no_served:
         log(f"served leg: {args.served_requests} requests, {args.served_steps} steps each")
         out["served"] = served_leg(frt, W, args.served_requests, args.served_steps, args.served_rate,
