@@ -1168,7 +1168,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     s->ncell = n;
     s->dx = box_cm / nx;
     // brick shape: 8^3 in FP64; in FP32 16^3 with sub-grid opacity, else
-    // 32 x 32 x 16 (the 1024-thread march)
+    // 32 x 16 x 16 (the 1024-thread march)
     const bool any_kappa = hk && std::any_of(hk, hk + n, [](float v) { return v > 0.f; });
     const int* lg = s->fp64 ? FRT_BRICK_LOG_F64 : (any_kappa ? FRT_BRICK_LOG_SUB : FRT_BRICK_LOG_BIG);
     for (int a = 0; a < 3; a++) s->bsh[a] = lg[a];

@@ -1,9 +1,10 @@
-// HIP kernels for gfx950: casting, the brick-synchronous ray march,
-// backward-Euler chemistry and step bookkeeping of adaptive ray tracing of
-// ionizing photon packets (Cain & D'Aloisio, FlexRT I, §3 and §4.1).
+// HIP kernels for gfx950: casting, the brick-synchronous ray march, the
+// hydrogen update (backward Euler, or the time-averaged update) and step
+// bookkeeping of adaptive ray tracing of ionizing photon packets (Cain &
+// D'Aloisio, FlexRT I, §3 and §4.1).
 //
 // A step runs as a sequence of passes.  The grid is cut into bricks
-// (32 x 32 x 16 cells for the FP32 march without sub-grid opacity, 16^3 with
+// (32 x 16 x 16 cells for the FP32 march without sub-grid opacity, 16^3 with
 // it, 8^3 for FP64).  In each pass every brick that holds packets is given
 // to workgroups: a workgroup stages the brick's opacity in LDS, walks each
 // of its packets cell by cell until the packet leaves the brick, splits,
@@ -1525,7 +1526,7 @@ __global__ void __launch_bounds__(BLOCK) k_brick(const FrtSolveDesc* __restrict_
         brick_march<Real, NB, SUB, FRT_BRICK_LOG_F64[0], FRT_BRICK_LOG_F64[1], FRT_BRICK_LOG_F64[2], BLOCK>(descs, ws);
 }
 
-// 1024-thread march on 32 x 32 x 16 bricks (FP32 without sub-grid opacity):
+// 1024-thread march on 32 x 16 x 16 bricks (FP32 without sub-grid opacity):
 // one workgroup of 16 waves per CU, 128 registers each
 template <typename Real, int NB>
 __global__ void __launch_bounds__(4 * BLOCK) k_brick_big(const FrtSolveDesc* __restrict__ descs, FrtWS ws)
