@@ -891,7 +891,12 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
     constexpr int NBIN = FRT_KEY_BINS;
     // staged opacity: {a_i, b_i} with sub-grid opacity, a_i alone without
     using OpT = typename std::conditional<SUB, R2, Real>::type;
-    __shared__ OpT s_op[BC];
+    // the brick's opacity with one plane of guard cells on each side: the
+    // march reads the next cell's opacity one step ahead, and a step across
+    // a brick face lands at most one plane outside the brick (the value read
+    // there is never used)
+    constexpr int PADC = BX * BY;
+    __shared__ OpT s_op[BC + 2 * PADC];
     // deposits: in the FP32 march as 64-bit fixed point (LDS integer atomics
     // run at the rate of plain stores here, FP32 LDS atomics far slower),
     // in the FP64 march as FP64
@@ -992,8 +997,8 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
 #pragma unroll
         for (int k = 0; k < NST; k++) {
             const int t = k * BT + (int)threadIdx.x;
-            if constexpr (SUB) s_op[t] = st[k];
-            else s_op[t] = st[k].x;
+            if constexpr (SUB) s_op[PADC + t] = st[k];
+            else s_op[PADC + t] = st[k].x;
             s_g[t] = GT(0);
         }
         if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
@@ -1133,16 +1138,16 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
 #pragma unroll
                     for (int b = 0; b < NB; b++) sumE += NE[b];
                     // the opacity of the current cell; each step reads the next
-                    // cell's one iteration ahead (an index outside the brick, for a
-                    // packet about to leave it, reads cell 0 and is not used)
-                    OpT o_cur = s_op[(uint32_t)li < (uint32_t)BC ? li : 0];
+                    // cell's one iteration ahead (for a packet about to leave the
+                    // brick that is a guard cell, whose value is not used)
+                    OpT o_cur = s_op[PADC + ((uint32_t)li < (uint32_t)BC ? li : 0)];
                     while (end < 0) {
                         int axis = 0;
                         Real r_face = rf[0];
                         if (rf[1] < r_face) { r_face = rf[1]; axis = 1; }
                         if (rf[2] < r_face) { r_face = rf[2]; axis = 2; }
                         const int li_n = li + (axis == 0 ? inc[0] : (axis == 1 ? inc[1] : inc[2]));
-                        const OpT o_next = s_op[(uint32_t)li_n < (uint32_t)BC ? li_n : 0];
+                        const OpT o_next = s_op[PADC + li_n];
                         Real r_end;
                         if constexpr (F32) {
                             // max(min(r_face, r_lim), r) on the bit patterns: r and
@@ -1488,7 +1493,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                 Real v;
                 if constexpr (INTDEP) v = (Real)((double)q * dun);
                 else v = q;
-                if constexpr (!SUB) v = v * (KS * fast_rcp<Real>(s_op[t]));
+                if constexpr (!SUB) v = v * (KS * fast_rcp<Real>(s_op[PADC + t]));
                 const int lx = t & (BX - 1), ly = (t >> LX) & (BY - 1), lz = t >> (LX + LY);
                 const size_t ci = (size_t)(ox + lx) + (size_t)nx * ((size_t)(oy + ly) + (size_t)ny * (size_t)(oz + lz));
                 atomicAdd(gam + ci, v);
