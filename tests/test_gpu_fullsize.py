@@ -1,0 +1,101 @@
+"""The throughput workload at its full size (256^3 GRF box, 2000 sources,
+4 bins, c = inf, distance cap, flux floor) in the launch configuration the
+benchmark times, checked where the oracle can follow it:
+
+* on a sample of sources over the full grid: the GPU step of 12 sources
+  spread over the list against the oracle on the same 12 (same rotation
+  uniforms), to the usual bars (x_HI within 1e-3, Gamma within 2e-3 of its
+  largest value, ledger terms within 1e-4 of emitted);
+* at all 2000 sources, by a property that holds at any size: within a step
+  every packet sees the start-of-step opacity, so the rate field and every
+  ledger term are sums over sources; the full step must equal the sum of the
+  steps of its even and odd sources, and its ledger must close.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2409_04521_amd import frt
+from paper_2409_04521_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TERMS = ("emitted", "absorbed_HI", "absorbed_sub", "escaped", "dropped", "in_flight")
+
+
+@pytest.fixture(scope="module")
+def full():
+    p = W.grf_c3(n=256, n_src=2000, throughput=True)
+    return p, W.rotation_table(p.seed, 0, 1, p.n_src)
+
+
+def _subset(p, idx):
+    return dataclasses.replace(p, src_pos_cm=p.src_pos_cm[idx], ndot_bins=p.ndot_bins[idx],
+                               name=f"{p.name}[{len(idx)} sources]")
+
+
+def _gpu_step(ctx, p, table, **kw):
+    g = frt.solve_from_problem(ctx, p, use_table=False, **kw)
+    g.set_rotations(table)
+    g.step(p.dt_s)
+    x, gam = g.fields()
+    L = g.ledger()
+    g.close()
+    return x, gam.astype(np.float64), L
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = frt.Context(0)
+    yield c
+    c.close()      # frees the full-size pass queues before the next module
+
+
+def test_sampled_sources_on_the_full_grid_match_the_oracle(ctx, full):
+    p, table = full
+    idx = np.arange(0, 2000, 167)[:12]
+    q = _subset(p, idx)
+    xg, gg, Lg = _gpu_step(ctx, q, table[:, idx, :])
+    o = O.Oracle(**q.oracle_kwargs())
+    o.set_sources(q.src_pos_cm, q.ndot_bins)
+    o.step(q.dt_s, table[0, idx, :])
+    xo, go = o.fields()
+    Lo = o.ledger()
+    dx = float(np.abs(xo - xg).max())
+    dg = float(np.abs(go - gg).max()) / float(go.max())
+    worst = {k: abs(Lo[k] - Lg[k]) / Lo["emitted"] for k in TERMS}
+    print(f"[256^3, 12 of 2000 sources] max|dx_HI| = {dx:.3e}, max|dGamma|/max = {dg:.3e}, ledger rel = "
+          + ", ".join(f"{k}:{v:.1e}" for k, v in worst.items())
+          + f", crossings oracle={Lo['crossings']} gpu={Lg['crossings']}", flush=True)
+    assert dx <= 1e-3
+    assert dg <= 2e-3
+    for k, v in worst.items():
+        assert v <= 1e-4, k
+    assert Lg["err_flags"] == 0 and Lg["lost"] == 0
+
+
+def test_full_step_is_the_sum_of_its_source_halves(ctx, full):
+    p, table = full
+    hint = int(3.6e8)
+    _, g_all, L_all = _gpu_step(ctx, p, table, queue_hint=hint)
+    E = L_all["emitted"]
+    closure = abs(E - sum(L_all[k] for k in TERMS[1:]) - L_all["lost"]) / E
+    assert closure <= 1e-9, closure
+    assert L_all["err_flags"] == 0 and L_all["lost"] == 0
+    parts = []
+    for idx in (np.arange(0, 2000, 2), np.arange(1, 2000, 2)):
+        parts.append(_gpu_step(ctx, _subset(p, idx), table[:, idx, :]))
+    g_sum = parts[0][1] + parts[1][1]
+    dg = float(np.abs(g_all - g_sum).max())
+    rel = dg / float(g_all.max())
+    cell_rel = float(np.max(np.abs(g_all - g_sum) / np.maximum(g_all, 1e-300)))
+    print(f"[256^3, 2000 sources] closure {closure:.1e}; |Gamma_all - Gamma_even - Gamma_odd| max {rel:.2e} "
+          f"of the largest rate, {cell_rel:.2e} of the cell's own; crossings {L_all['crossings']} = "
+          f"{parts[0][2]['crossings']} + {parts[1][2]['crossings']}", flush=True)
+    assert rel <= 1e-5
+    assert L_all["crossings"] == parts[0][2]["crossings"] + parts[1][2]["crossings"]
+    for k in TERMS:
+        s = parts[0][2][k] + parts[1][2][k]
+        assert abs(L_all[k] - s) <= 1e-9 * E, k
