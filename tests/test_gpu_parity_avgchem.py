@@ -125,3 +125,25 @@ def test_iteration_count_is_checked(ctx):
         with pytest.raises(frt.FrtError) as e:
             frt.solve_from_problem(ctx, p)
         assert e.value.code == frt.FRT_EINVAL
+
+
+def test_served_mix_of_chemistries_equals_alone(ctx):
+    # the server steps its admitted requests together; requests with
+    # different chemistry settings go to different launch groups
+    probs = [r.problem for r in W.served_c5(n_requests=3, seed=73, n_steps=3, sizes=(16, 24), max_src=24)]
+    for p, K in zip(probs, (0, 2, 3)):
+        p.chem_iterations = K
+    alone = []
+    for p in probs:
+        g = _gpu(ctx, p, 3)
+        alone.append((g.fields()[0], g.ledger()))
+    srv = frt.Server(frt.Context(0), budget_bytes=64 << 30, max_slots=8)
+    ids = [srv.submit(p, 3) for p in probs]
+    for rid in ids:
+        assert srv.wait(rid, 120.0) == frt.REQ_DONE
+    mixed = [srv.take(rid) for rid in ids]
+    srv.close()
+    for p, (xa, La), (xb, Lb) in zip(probs, alone, mixed):
+        assert np.abs(xa - xb).max() <= 1e-5, p.name
+        for k in TERMS:
+            assert abs(La[k] - Lb[k]) <= 1e-6 * La["emitted"], (p.name, k)
