@@ -37,6 +37,13 @@
  *                         atoms as its last march absorbed photons (the
  *                         photon conservation of §4.1), to the iteration's
  *                         convergence; ledger closure.
+ *   orc_step (generalized) the moving screen's front radius against photon
+ *                         counting, R = (3 Ndot t / (4 pi (1+chi) n_H))^(1/3)
+ *                         (no recombination, transparent ionized gas), ionized
+ *                         atoms against front photons, Gamma in ionized gas
+ *                         against the absorbed photons (V/(sigma lambda) atoms
+ *                         per cell), equality with Standard Mode when
+ *                         kappa = n_HI sigma_0 and x_ion = 1 (§4.2), closure.
  *   orc_step              photon ledger closure, Stromgren I-front
  *                         (Eqs. r_of_t, rS, trec), checkpoint equality.
  *   Whole-field values beyond these properties: parity unpinned (the paper
@@ -69,11 +76,17 @@ typedef struct {
     int n_chunks;            /* fixed source chunking for a deterministic sum */
     int chem_iterations;     /* 0: backward Euler; K >= 1: the time-averaged update
                                 of §4.1 with K marches per step */
+    int opacity_mode;        /* 0: Standard Mode (§4.1); 1: Generalized Opacity Mode
+                                (§4.2): kappa is the ionized phase's absorption
+                                coefficient at sigma_0, x = 1 - x_ion the neutral
+                                volume fraction behind a moving screen */
+    double he_chi;           /* chi of Eq. dxidt (helium singly ionized with H) */
 } orc_params;
 
 typedef struct {
     double emitted, absorbed_HI, absorbed_sub, escaped, dropped, in_flight;
     long long crossings, rays_emitted, splits, n_escaped, n_dropped, n_in_flight;
+    double absorbed_front;   /* photons stopped by I-fronts (Generalized Opacity Mode) */
 } orc_ledger;
 
 /* Photon totals are sums of up to ~1e9 terms; they are accumulated with
@@ -92,7 +105,7 @@ static void csum_add(csum* a, double v)
 static double csum_get(const csum* a) { return a->s + a->c; }
 
 typedef struct {
-    csum emitted, absorbed_HI, absorbed_sub, escaped, dropped;
+    csum emitted, absorbed_HI, absorbed_sub, escaped, dropped, front;
     long long crossings, rays_emitted, splits, n_escaped, n_dropped, n_in_flight;
 } chunk_ledger;
 
@@ -314,6 +327,8 @@ typedef struct {
     orc_vec* stack;          /* depth-first work list */
     orc_vec* flight_out;     /* packets that end the step in flight */
     double inv_vdt;          /* 1 / (V_cell dt) */
+    const double* xion;      /* Generalized Opacity Mode: start-of-step ionized fraction */
+    double* front;           /* this chunk's photons stopped at each cell's I-front */
 } march_ctx;
 
 /* March one ray from its current radius until it is absorbed below the floor,
@@ -326,7 +341,17 @@ typedef struct {
  * which equals N_in (1 - e^-tau)/(n_HI V dt) x (HI share of tau), i.e.
  * Eq. gamma_initial_standard when kappa = 0 and Eq. gamma_avg_subgrid with
  * lambda = 1/(n_HI sigma + kappa), and tends to Eq. gamma_initial_subgrid
- * as tau -> 0. */
+ * as tau -> 0.
+ *
+ * Generalized Opacity Mode (§4.2): a cell is an ionized part of volume
+ * fraction x_ion with absorption coefficient kappa_nu = kappa sigma_nu /
+ * sigma_0 and a neutral part behind an infinitely thin front (the moving
+ * screen).  A segment crosses the ionized part first, over x_ion ds:
+ *   tau     = kappa_nu x_ion ds
+ *   Gamma_i += N_in sigma_nu ds phi(tau) / (V dt)
+ * which is Eq. gamma_avg_subgrid with ds -> x_ion ds and V -> x_ion V; in a
+ * cell that is not fully ionized the photons left then reach the front and
+ * are absorbed there (they drive Eq. dxidt), ending the packet. */
 static void march_one_ray(march_ctx* M, orc_ray* ray)
 {
     const orc_params* P = &M->S->p;
@@ -360,7 +385,28 @@ static void march_one_ray(march_ctx* M, orc_ray* ray)
         if (ray->r_stop < r_end) r_end = ray->r_stop;
         if (r_end < ray->r) r_end = ray->r;
         double ds = r_end - ray->r;
-        if (ds > 0.0) {
+        if (ds > 0.0 && P->opacity_mode == 1) {
+            long long i = c[0] + (long long)P->nx * (c[1] + (long long)P->ny * c[2]);
+            const double xi = M->xion[i], kap = M->S->kappa[i];
+            double g = 0.0;
+            for (int k = 0; k < nb; k++) {
+                double tau = kap * (P->sigma[k] / P->sigma[0]) * xi * ds;
+                double Nin = ray->N[k];
+                double Nout = Nin * exp(-tau);
+                double phi = (tau > 0.0) ? -expm1(-tau) / tau : 1.0;
+                g += Nin * P->sigma[k] * ds * phi;
+                csum_add(&M->L->absorbed_HI, Nin - Nout);
+                ray->N[k] = Nout;
+            }
+            M->gamma[i] += g * M->inv_vdt;
+            M->L->crossings++;
+            if (xi < 1.0) {
+                const double left = sum_bins(ray->N, nb);
+                M->front[i] += left;
+                csum_add(&M->L->front, left);
+                return;
+            }
+        } else if (ds > 0.0) {
             long long i = c[0] + (long long)P->nx * (c[1] + (long long)P->ny * c[2]);
             double nhi = M->nHI[i], kap = M->S->kappa[i];
             double g = 0.0;
@@ -479,6 +525,7 @@ double chemistry_avg(double x0, double gamma, double ne, double alpha, double co
 orc_state* orc_create(const orc_params* P, const float* nH, const float* kappa, const double* x0)
 {
     if (!P || P->nx < 1 || P->ny < 1 || P->nz < 1 || P->n_bins < 1 || P->n_bins > ORC_MAX_BINS) return NULL;
+    if (P->opacity_mode != 0 && (P->opacity_mode != 1 || P->chem_iterations > 0)) return NULL;
     orc_state* S = (orc_state*)calloc(1, sizeof(orc_state));
     if (!S) return NULL;
     S->p = *P;
@@ -552,6 +599,15 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
     orc_vec* new_flight = (orc_vec*)calloc(S->nsrc > 0 ? S->nsrc : 1, sizeof(orc_vec));
     if (!nHI || !gk || !Lk || !new_flight) return -1;
     const int n_iter = P->chem_iterations > 0 ? P->chem_iterations : 1;
+    const int gen = P->opacity_mode == 1;
+    double* xion = NULL;
+    double* fk = NULL;
+    if (gen) {
+        xion = (double*)malloc(sizeof(double) * N);
+        fk = (double*)calloc((size_t)K * N, sizeof(double));
+        if (!xion || !fk) return -1;
+        for (long long i = 0; i < N; i++) xion[i] = 1.0 - S->x[i];
+    }
     double* xavg = NULL;
     if (P->chem_iterations > 0) {
         xavg = (double*)malloc(sizeof(double) * N);
@@ -580,6 +636,7 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
             march_ctx M;
             M.S = S; M.nHI = nHI; M.gamma = gk + (size_t)k * N; M.L = Lk + k;
             M.stack = &stack; M.inv_vdt = 1.0 / (V * dt);
+            M.xion = xion; M.front = gen ? fk + (size_t)k * N : NULL;
             int s0 = (int)(((long long)S->nsrc * k) / K), s1 = (int)(((long long)S->nsrc * (k + 1)) / K);
             for (int s = s0; s < s1; s++) {
                 M.flight_out = &new_flight[s];
@@ -629,10 +686,11 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
     }
 
     long long cross = 0;
-    csum tot[5];
+    csum tot[6];
     {
-        const double prev[5] = {S->L.emitted, S->L.absorbed_HI, S->L.absorbed_sub, S->L.escaped, S->L.dropped};
-        for (int j = 0; j < 5; j++) { tot[j].s = prev[j]; tot[j].c = 0.0; }
+        const double prev[6] = {S->L.emitted, S->L.absorbed_HI, S->L.absorbed_sub, S->L.escaped, S->L.dropped,
+                                S->L.absorbed_front};
+        for (int j = 0; j < 6; j++) { tot[j].s = prev[j]; tot[j].c = 0.0; }
     }
     for (int k = 0; k < K; k++) {
         csum_add(&tot[0], csum_get(&Lk[k].emitted));
@@ -640,6 +698,7 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
         csum_add(&tot[2], csum_get(&Lk[k].absorbed_sub));
         csum_add(&tot[3], csum_get(&Lk[k].escaped));
         csum_add(&tot[4], csum_get(&Lk[k].dropped));
+        csum_add(&tot[5], csum_get(&Lk[k].front));
         S->L.crossings += Lk[k].crossings;
         S->L.rays_emitted += Lk[k].rays_emitted;
         S->L.splits += Lk[k].splits;
@@ -652,6 +711,7 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
     S->L.absorbed_sub = csum_get(&tot[2]);
     S->L.escaped = csum_get(&tot[3]);
     S->L.dropped = csum_get(&tot[4]);
+    S->L.absorbed_front = csum_get(&tot[5]);
     S->last_crossings = cross;
 
     /* carried packets replace the old list */
@@ -667,7 +727,20 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
     S->L.n_in_flight = nfl;
 
     /* chemistry closes the step */
-    if (xavg) {
+    if (gen) {
+        /* moving screen (§4.2, Eq. dxidt): the photons stopped at a cell's
+         * front ionize (1 + chi) atoms each; the ionized fraction is at most
+         * 1 and no recombination moves the front back */
+        for (long long i = 0; i < N; i++) {
+            double f = 0.0;
+            for (int k = 0; k < K; k++) f += fk[(size_t)k * N + i];
+            const double atoms = (1.0 + P->he_chi) * S->nH[i] * V;
+            double xi = atoms > 0.0 ? xion[i] + f / atoms : 1.0;   /* no hydrogen: nothing to ionize */
+            if (xi > 1.0) xi = 1.0;
+            S->x[i] = 1.0 - xi;
+        }
+        free(xion); free(fk);
+    } else if (xavg) {
         for (long long i = 0; i < N; i++) {
             double xe;
             const double ne = S->nH[i] * (1.0 - xavg[i]);
@@ -691,6 +764,7 @@ int orc_debug_transmit(orc_state* S, const double o[3], const double d[3], const
                        double* gamma_out, double* N_exit)
 {
     const orc_params* P = &S->p;
+    if (P->opacity_mode != 0) return -1;   /* Standard Mode only */
     orc_state T = *S;
     T.p.max_level = 0;
     T.p.base_level = 0;
@@ -708,6 +782,7 @@ int orc_debug_transmit(orc_state* S, const double o[3], const double d[3], const
     march_ctx M;
     M.S = &T; M.nHI = nHI; M.gamma = gamma_out; M.L = &L; M.stack = &stack; M.flight_out = &fl;
     M.inv_vdt = 1.0 / (P->dx * P->dx * P->dx * dt);
+    M.xion = NULL; M.front = NULL;
     orc_ray ray;
     memset(&ray, 0, sizeof(ray));
     for (int a = 0; a < 3; a++) ray.dir[a] = d[a];

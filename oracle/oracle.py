@@ -35,14 +35,16 @@ class Params(C.Structure):
                 ("alpha_B", C.c_double), ("coll_ion", C.c_double),
                 ("base_level", C.c_int), ("max_level", C.c_int), ("n_ray_min", C.c_double),
                 ("flux_floor", C.c_double), ("max_dist", C.c_double), ("c_ray", C.c_double),
-                ("n_chunks", C.c_int), ("chem_iterations", C.c_int)]
+                ("n_chunks", C.c_int), ("chem_iterations", C.c_int), ("opacity_mode", C.c_int),
+                ("he_chi", C.c_double)]
 
 
 class Ledger(C.Structure):
     _fields_ = [("emitted", C.c_double), ("absorbed_HI", C.c_double), ("absorbed_sub", C.c_double),
                 ("escaped", C.c_double), ("dropped", C.c_double), ("in_flight", C.c_double),
                 ("crossings", C.c_longlong), ("rays_emitted", C.c_longlong), ("splits", C.c_longlong),
-                ("n_escaped", C.c_longlong), ("n_dropped", C.c_longlong), ("n_in_flight", C.c_longlong)]
+                ("n_escaped", C.c_longlong), ("n_dropped", C.c_longlong), ("n_in_flight", C.c_longlong),
+                ("absorbed_front", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -131,7 +133,7 @@ class Oracle:
 
     def __init__(self, shape, dx_cm, sigma_bins, alpha_B, n_H, kappa=None, x_HI0=None,
                  coll_ion=0.0, base_level=0, max_level=12, n_ray_min=1.0, flux_floor=0.0,
-                 max_dist_cm=0.0, c_ray=np.inf, n_chunks=16, chem_iterations=0):
+                 max_dist_cm=0.0, c_ray=np.inf, n_chunks=16, chem_iterations=0, opacity_mode=0, he_chi=0.0):
         nz, ny, nx = shape
         sig = list(sigma_bins)
         P = Params()
@@ -143,6 +145,7 @@ class Oracle:
         P.base_level, P.max_level, P.n_ray_min = base_level, max_level, n_ray_min
         P.flux_floor, P.max_dist, P.c_ray, P.n_chunks = flux_floor, max_dist_cm, c_ray, n_chunks
         P.chem_iterations = chem_iterations
+        P.opacity_mode, P.he_chi = opacity_mode, he_chi
         self.P = P
         self.shape = (nz, ny, nx)
         self.ncell = nx * ny * nz

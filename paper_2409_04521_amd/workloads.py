@@ -162,6 +162,9 @@ class Problem:
     coll_ion: float = 0.0
     seed: int = 0
     chem_iterations: int = 0          # 0: backward Euler; K: time-averaged, K marches per step
+    opacity_mode: int = 0             # 0: Standard Mode; 1: Generalized Opacity Mode (kappa of the
+                                      # ionized phase, x_HI0 = 1 - ionized volume fraction)
+    he_chi: float = 0.0
     T: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
 
@@ -186,7 +189,8 @@ class Problem:
                     coll_ion=self.coll_ion, base_level=self.base_level, max_level=self.max_level,
                     n_ray_min=self.n_ray_min, flux_floor=self.flux_floor,
                     max_dist_cm=self.max_dist_cm, c_ray=self.c_ray,
-                    chem_iterations=self.chem_iterations)
+                    chem_iterations=self.chem_iterations, opacity_mode=self.opacity_mode,
+                    he_chi=self.he_chi)
 
     def footprint_bytes(self) -> int:
         return int(self.ncell * 64)

@@ -1,0 +1,133 @@
+"""Pins of the oracle's Generalized Opacity Mode (§4.2: ionized-phase
+absorption coefficient kappa, Eq. gamma_avg_subgrid, moving screen of
+Eq. dxidt), each against something other than its own formulas:
+
+* a source in uniform neutral gas with transparent ionized gas and no
+  recombination: the ionized region is a sphere about the source whose
+  radius follows photon counting, R = (3 Ndot t / (4 pi (1+chi) n_H))^(1/3);
+  the ionized atoms never exceed the photons stopped at fronts, and fall
+  short only by what a front cell receives beyond its neutral atoms in a
+  step;
+* in fully ionized gas, Gamma times the atoms subject to ionization
+  V/(sigma_0 lambda) of each cell adds up to the absorbed photons (the
+  interpretation §4.2 gives of Eq. gamma_avg_subgrid, one bin);
+* kappa = n_HI sigma_0 with x_ion = 1 gives Standard Mode's rate field and
+  ledger (§4.2: Eq. gamma_avg_subgrid reduces to Eq. gamma_updated_standard);
+* the photon ledger closes with the front term.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2409_04521_amd import workloads as W
+
+DX = W.cmpc_h_to_cm(0.15625)
+
+
+def _closure(L):
+    out = L["absorbed_HI"] + L["absorbed_sub"] + L["absorbed_front"] + L["escaped"] + L["dropped"] + L["in_flight"]
+    return abs(L["emitted"] - out) / L["emitted"]
+
+
+def test_front_is_a_sphere_that_follows_photon_counting():
+    n, nh, chi, Nd = 24, 2e-5, 0.08, 3e51
+    nH = np.full((n, n, n), nh, dtype=np.float32)
+    o = O.Oracle((n, n, n), DX, [6.3e-18], 2.59e-13, nH, kappa=np.zeros((n, n, n), np.float32),
+                 x_HI0=np.ones((n, n, n)), c_ray=np.inf, opacity_mode=1, he_chi=chi)
+    o.set_sources(np.array([[11.5, 11.5, 11.5]]) * DX, np.array([[Nd]]))
+    dt = 0.1 * W.MYR
+    steps = 60
+    for s in range(steps):
+        o.step(dt, W.rotation_uniforms(1, s, 1))
+    x, _ = o.fields()
+    L = o.ledger()
+    assert _closure(L) <= 1e-12
+    ionized = float(np.sum((1 - x) * nh * DX ** 3 * (1 + chi)))
+    assert 0.9 * L["absorbed_front"] <= ionized <= L["absorbed_front"] * (1 + 1e-12)
+    R_num = (3 * float(np.sum(1 - x)) / (4 * np.pi)) ** (1 / 3)
+    R_an = (3 * Nd * steps * dt / (4 * np.pi * (1 + chi) * nh)) ** (1 / 3) / DX
+    assert R_num == pytest.approx(R_an, rel=0.03)
+    zz, yy, xx = np.meshgrid(*(np.arange(n) + 0.5,) * 3, indexing="ij")
+    rr = np.sqrt((xx - 11.5) ** 2 + (yy - 11.5) ** 2 + (zz - 11.5) ** 2)
+    assert x[rr < R_num - 1.0].max() == 0.0          # ionized inside
+    assert x[rr > R_num + 1.0].min() == 1.0          # neutral outside
+
+
+def _ionized_box(n=20, seed=31, bins=1):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    kap = (W.lognormal_white(rng, (n, n, n), 1.0, 1.0) / (3 * DX)).astype(np.float32)
+    w, sig = W.blackbody_bins(bins)
+    pos = (rng.integers(0, n, size=(4, 3)) + 0.5) * DX
+    ndot = (10 ** rng.uniform(51, 53, size=4))[:, None] * w[None, :]
+    return kap, sig, pos, ndot
+
+
+def test_gamma_times_atoms_subject_to_ionization_is_the_absorbed_photons():
+    n = 20
+    kap, sig, pos, ndot = _ionized_box(n)
+    nH = np.full((n, n, n), 2e-4, dtype=np.float32)
+    o = O.Oracle((n, n, n), DX, sig, 2.59e-13, nH, kappa=kap, x_HI0=np.zeros((n, n, n)), c_ray=np.inf,
+                 opacity_mode=1, he_chi=0.08)
+    o.set_sources(pos, ndot)
+    dt = W.MYR
+    o.step(dt, W.rotation_uniforms(2, 0, len(pos)))
+    _, g = o.fields()
+    L = o.ledger()
+    atoms = DX ** 3 * kap.astype(np.float64) / sig[0]          # V / (sigma lambda)
+    assert float(np.sum(g * atoms * dt)) == pytest.approx(L["absorbed_HI"], rel=1e-10)
+    assert L["absorbed_front"] == 0.0                         # no front in ionized gas
+    assert _closure(L) <= 1e-12
+
+
+def test_reduces_to_standard_mode_when_kappa_is_n_HI_sigma():
+    n = 20
+    rng = np.random.Generator(np.random.PCG64(32))
+    nH = W.lognormal_white(rng, (n, n, n), 2e-4, 1.0).astype(np.float32)
+    xh = rng.uniform(1e-3, 1e-2, size=(n, n, n))
+    w, sig = W.blackbody_bins(3)
+    pos = (rng.integers(0, n, size=(3, 3)) + 0.5) * DX
+    ndot = np.array([1e52, 3e51, 2e52])[:, None] * w[None, :]
+    kap = (nH.astype(np.float64) * xh * sig[0]).astype(np.float32)
+    xh_std = kap.astype(np.float64) / (nH.astype(np.float64) * sig[0])   # the same n_HI to rounding
+    std = O.Oracle((n, n, n), DX, sig, 2.59e-13, nH, x_HI0=xh_std, c_ray=np.inf)
+    gen = O.Oracle((n, n, n), DX, sig, 2.59e-13, nH, kappa=kap, x_HI0=np.zeros((n, n, n)), c_ray=np.inf,
+                   opacity_mode=1)
+    u = W.rotation_uniforms(3, 0, 3)
+    for o in (std, gen):
+        o.set_sources(pos, ndot)
+        o.step(W.MYR, u)
+    gs, gg = std.fields()[1], gen.fields()[1]
+    assert np.abs(gs - gg).max() <= 1e-9 * gs.max()
+    Ls, Lg = std.ledger(), gen.ledger()
+    for k in ("emitted", "absorbed_HI", "escaped", "dropped", "in_flight"):
+        assert Lg[k] == pytest.approx(Ls[k], rel=1e-9, abs=1e-12 * Ls["emitted"]), k
+    assert Ls["crossings"] == Lg["crossings"]
+
+
+def test_ledger_closes_with_fronts_and_carried_packets():
+    n = 24
+    rng = np.random.Generator(np.random.PCG64(33))
+    nH = W.lognormal_white(rng, (n, n, n), 2e-4, 1.0).astype(np.float32)
+    kap = (W.lognormal_white(rng, (n, n, n), 1.0, 0.5) / (5 * DX)).astype(np.float32)
+    xi0 = np.where(rng.uniform(size=(n, n, n)) < 0.97, 1.0, rng.uniform(size=(n, n, n)))   # mostly ionized
+    w, sig = W.blackbody_bins(4)
+    pos = (rng.integers(0, n, size=(5, 3)) + 0.5) * DX
+    ndot = (10 ** rng.uniform(51, 53, size=5))[:, None] * w[None, :]
+    o = O.Oracle((n, n, n), DX, sig, 2.59e-13, nH, kappa=kap, x_HI0=1 - xi0, c_ray=W.C_LIGHT,
+                 flux_floor=1e-3, opacity_mode=1, he_chi=0.08)
+    o.set_sources(pos, ndot)
+    x_prev = 1 - xi0
+    for s in range(4):
+        o.step(W.MYR, W.rotation_uniforms(4, s, 5))
+        x, _ = o.fields()
+        assert np.all(x <= x_prev + 1e-15)                   # fronts only advance
+        x_prev = x
+    L = o.ledger()
+    assert L["absorbed_front"] > 0 and L["in_flight"] > 0
+    assert _closure(L) <= 1e-12
+
+
+def test_generalized_mode_is_exclusive_with_iterated_chemistry():
+    nH = np.full((4, 4, 4), 1e-4, dtype=np.float32)
+    with pytest.raises(ValueError):
+        O.Oracle((4, 4, 4), DX, [6.3e-18], 2.59e-13, nH, opacity_mode=1, chem_iterations=2)
