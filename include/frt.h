@@ -61,6 +61,9 @@ extern "C" {
 #define FRT_MAX_BINS 8
 #define FRT_MAX_CHEM_ITERATIONS 64
 
+#define FRT_STANDARD 0      /* opacity from n_HI = n_H x_HI and the sub-grid kappa (§4.1) */
+#define FRT_GENERALIZED 1   /* Generalized Opacity Mode (§4.2) */
+
 typedef struct frt_ctx_s* frt_ctx;
 typedef struct frt_solve_s* frt_solve;
 
@@ -96,11 +99,26 @@ typedef struct {
                                        previous estimate (first: the start of the step); only
                                        the last march's deposits, ledger terms and carried
                                        packets are kept */
+    int opacity_mode;               /* FRT_STANDARD (default) or FRT_GENERALIZED (§4.2): then
+                                       kappa_sub of frt_load_grid is the absorption coefficient
+                                       of each cell's ionized part at sigma_0 (kappa_nu = kappa
+                                       sigma_nu / sigma_0) and 1 - x_HI its ionized volume
+                                       fraction x_ion behind a moving screen: a segment crosses
+                                       x_ion ds of ionized gas, depositing Eq. gamma_avg_subgrid
+                                       with ds -> x_ion ds, V -> x_ion V; in a cell not fully
+                                       ionized the photons left stop at the front (the packet
+                                       ends, ledger term absorbed_front), and the step's front
+                                       photons advance x_ion by f / ((1 + he_chi) n_H V)
+                                       (Eq. dxidt), at most to 1.  Not with chem_iterations */
+    double he_chi;                  /* chi of Eq. dxidt: helium singly ionized per hydrogen
+                                       atom (default 0) */
 } frt_params;
 
 /* Cumulative photon ledger (photons) and counters of one solve.  With
  * E = emitted, the terms satisfy E = absorbed_HI + absorbed_sub + escaped
- * + dropped + in_flight (+ lost, which is 0 unless a queue overflowed). */
+ * + dropped + in_flight + absorbed_front (+ lost, which is 0 unless a queue
+ * overflowed).  In the Generalized Opacity Mode absorbed_HI counts the
+ * photons absorbed in ionized gas. */
 typedef struct {
     double emitted, absorbed_HI, absorbed_sub, escaped, dropped, in_flight, lost;
     uint64_t crossings;             /* cell crossings with ds > 0, all steps */
@@ -110,12 +128,13 @@ typedef struct {
     uint64_t steps;                 /* steps applied */
     uint32_t err_flags;             /* device error bits (1 = queue overflow) */
     uint32_t max_items;             /* largest round (work items) seen */
+    double absorbed_front;          /* photons stopped at I-fronts (Generalized Opacity Mode) */
 } frt_ledger;
 
 /* Fill *p with defaults: 1 bin at 6.3e-18 cm^2, alpha_B = 2.59e-13,
  * coll_ion = 0, base_level 0, max_level 12, n_ray_min 1, no floor, no cap,
  * c_ray = speed of light, FRT_F32, seed 0, automatic queues, no hint,
- * backward-Euler chemistry (chem_iterations 0). */
+ * backward-Euler chemistry (chem_iterations 0), FRT_STANDARD opacity, he_chi 0. */
 int frt_params_default(frt_params* p);
 
 /* Context bound to HIP device `hip_device`.  Owns nothing else. */

@@ -182,6 +182,7 @@ struct frt_solve_s {
     void* gam[2] = {nullptr, nullptr};
     double* x = nullptr;
     double* xavg = nullptr;                  // time-averaged chemistry only
+    double* front = nullptr;                 // Generalized Opacity Mode only
     double* nH = nullptr;
     float* T = nullptr;
     double* src_pos = nullptr;
@@ -240,8 +241,8 @@ struct frt_solve_s {
         free_recs(mark_F);
         dev_free(mark_x);
         dev_free(mark_fc);
-        dev_free(d_desc); dev_free(op); dev_free(gam[0]); dev_free(gam[1]); dev_free(x); dev_free(xavg); dev_free(nH);
-        dev_free(T); dev_free(src_pos); dev_free(spec); dev_free(specd); dev_free(quat); dev_free(user_u); dev_free(fcount);
+        dev_free(d_desc); dev_free(op); dev_free(gam[0]); dev_free(gam[1]); dev_free(x); dev_free(xavg); dev_free(front);
+        dev_free(nH); dev_free(T); dev_free(src_pos); dev_free(spec); dev_free(specd); dev_free(quat); dev_free(user_u); dev_free(fcount);
         dev_free(fcount_snap); dev_free(L); dev_free(L_snap);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
         stream = nullptr;
@@ -664,6 +665,7 @@ int recover_overflow(Workspace& ws, frt_solve* ss, int n, const uint32_t* ctr, u
         HIPCHK(hipMemcpyAsync(s->L, s->L_snap, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemcpyAsync(s->fcount, s->fcount_snap, 8, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemsetAsync(s->gam[s->step & 1u], 0, s->ncell * s->rs, st));
+        if (s->front) HIPCHK(hipMemsetAsync(s->front, 0, s->ncell * 8, st));
     }
     HIPCHK(hipStreamSynchronize(st));
     if (ctr[C_ERR] & FRT_DEVERR_QUEUE_OVERFLOW) {
@@ -856,6 +858,7 @@ int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps)
                     HIPCHK(hipMemcpyAsync(ss[i]->L, ss[i]->L_snap, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
                     HIPCHK(hipMemcpyAsync(ss[i]->fcount, ss[i]->fcount_snap, 8, hipMemcpyDeviceToDevice, st));
                     HIPCHK(hipMemsetAsync(ss[i]->gam[ss[i]->step & 1u], 0, ss[i]->ncell * ss[i]->rs, st));
+                    if (ss[i]->front) HIPCHK(hipMemsetAsync(ss[i]->front, 0, ss[i]->ncell * 8, st));
                 }
                 HIPCHK(hipStreamSynchronize(st));
                 return fail(FRT_EOVERFLOW, "a ray queue overflowed at step %u; raise queue_capacity", ss[0]->step);
@@ -922,6 +925,7 @@ int snap_restore(frt_solve s, const SolveSnap& p)
     HIPCHK(hipMemcpyAsync(s->x, p.x, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(s->gam[cur ^ 1], p.gam_last, s->ncell * s->rs, hipMemcpyDeviceToDevice, s->stream));
     HIPCHK(hipMemsetAsync(s->gam[cur], 0, s->ncell * s->rs, s->stream));
+    if (s->front) HIPCHK(hipMemsetAsync(s->front, 0, s->ncell * 8, s->stream));
     HIPCHK(hipMemcpyAsync(s->L, p.L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, s->stream));
     RCCHK(copy_recs(s->F[cur], p.F, nc, s->P.n_bins, s->rs, s->stream, hipMemcpyDeviceToDevice));
     HIPCHK(hipMemcpyAsync(s->fcount, p.fc, 8, hipMemcpyHostToDevice, s->stream));
@@ -977,9 +981,10 @@ uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T,
     const uint64_t rs = P.march_precision == FRT_F64 ? 8 : 4;
     const uint64_t rec = rec_bytes(rs);
     const uint64_t cast = (uint64_t)n_src * (12ull << (2 * P.base_level));
-    // resident fields: opacity pair, two rate buffers, x_HI, n_H, T, and <x>
-    // of the time-averaged chemistry
-    uint64_t b = ncell * (4 * rs + 16 + (with_T ? 4 : 0) + (P.chem_iterations > 0 ? 8 : 0));
+    // resident fields: opacity pair, two rate buffers, x_HI, n_H, T, <x> of
+    // the time-averaged chemistry, front photons of the Generalized Opacity Mode
+    uint64_t b = ncell * (4 * rs + 16 + (with_T ? 4 : 0) + (P.chem_iterations > 0 ? 8 : 0) +
+                          (P.opacity_mode == FRT_GENERALIZED ? 8 : 0));
     // carried-packet queues (as first sized)
     double F = (double)cast + 1024;
     if (std::isfinite(P.c_ray_cm_s)) F += std::min((double)ncell, 8.0 * cast + 65536.0);
@@ -1065,6 +1070,11 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     if (P->march_precision != FRT_F32 && P->march_precision != FRT_F64) return fail(FRT_EINVAL, "march_precision must be FRT_F32 or FRT_F64");
     if (P->chem_iterations < 0 || P->chem_iterations > FRT_MAX_CHEM_ITERATIONS)
         return fail(FRT_EINVAL, "chem_iterations %d outside 0..%d", P->chem_iterations, FRT_MAX_CHEM_ITERATIONS);
+    if (P->opacity_mode != FRT_STANDARD && P->opacity_mode != FRT_GENERALIZED)
+        return fail(FRT_EINVAL, "opacity_mode must be FRT_STANDARD or FRT_GENERALIZED");
+    if (P->opacity_mode == FRT_GENERALIZED && P->chem_iterations > 0)
+        return fail(FRT_EINVAL, "the Generalized Opacity Mode takes no chem_iterations");
+    if (!(P->he_chi >= 0) || !std::isfinite(P->he_chi)) return fail(FRT_EINVAL, "he_chi must be finite and >= 0");
     HIPCHK(hipSetDevice(ctx->device));
     frt_solve s = new (std::nothrow) frt_solve_s;
     if (!s) return fail(FRT_ENOMEM, "solve");
@@ -1156,20 +1166,23 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     }
     if (T) RCCHK(host_view(T, n, kind, bT, &hT));
     dev_free(s->op); dev_free(s->gam[0]); dev_free(s->gam[1]); dev_free(s->x); dev_free(s->xavg);
-    dev_free(s->nH); dev_free(s->T);
+    dev_free(s->front); dev_free(s->nH); dev_free(s->T);
+    const bool gen = s->P.opacity_mode == FRT_GENERALIZED;
     RCCHK(dev_alloc(&s->op, n * 2 * s->rs));
     RCCHK(dev_alloc(&s->gam[0], n * s->rs));
     RCCHK(dev_alloc(&s->gam[1], n * s->rs));
     RCCHK(dev_alloc((void**)&s->x, n * 8));
     if (s->P.chem_iterations > 0) RCCHK(dev_alloc((void**)&s->xavg, n * 8));
+    if (gen) RCCHK(dev_alloc((void**)&s->front, n * 8));
     RCCHK(dev_alloc((void**)&s->nH, n * 8));
     if (T) RCCHK(dev_alloc((void**)&s->T, n * 4));
     s->nx = nx; s->ny = ny; s->nz = nz;
     s->ncell = n;
     s->dx = box_cm / nx;
-    // brick shape: 8^3 in FP64; in FP32 16^3 with sub-grid opacity, else
+    // brick shape: 8^3 in FP64; in FP32 16^3 with sub-grid opacity (and in
+    // the Generalized Opacity Mode, which stages the same pairs), else
     // 32 x 16 x 16 (the 1024-thread march)
-    const bool any_kappa = hk && std::any_of(hk, hk + n, [](float v) { return v > 0.f; });
+    const bool any_kappa = gen || (hk && std::any_of(hk, hk + n, [](float v) { return v > 0.f; }));
     const int* lg = s->fp64 ? FRT_BRICK_LOG_F64 : (any_kappa ? FRT_BRICK_LOG_SUB : FRT_BRICK_LOG_BIG);
     for (int a = 0; a < 3; a++) s->bsh[a] = lg[a];
     s->bpx = (nx + (1 << s->bsh[0]) - 1) >> s->bsh[0];
@@ -1179,18 +1192,26 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     for (size_t i = 0; i < n; i++) nHd[i] = (double)hn[i];
     if (hx) std::copy(hx, hx + n, xd.begin());
     // opacity: the HI part (first n values) is built from x_HI on the device;
-    // the sub-grid part (next n values) is fixed
+    // the sub-grid part (next n values) is fixed.  Generalized Opacity Mode:
+    // the first part is the ionized gas's kappa dx (fixed, floored like the
+    // HI opacity), the second the ionized fraction, built on the device
+    const double floor_a = s->fp64 ? 1e-300 : 1e-30;
     if (s->fp64) {
         std::vector<double> opv(2 * n, 0.0);
         if (hk)
-            for (size_t i = 0; i < n; i++) opv[n + i] = (double)hk[i] * s->dx;
+            for (size_t i = 0; i < n; i++) opv[(gen ? 0 : n) + i] = (double)hk[i] * s->dx;
+        if (gen)
+            for (size_t i = 0; i < n; i++) opv[i] = std::max(opv[i], floor_a);
         RCCHK(scopy(s, s->op, opv.data(), n * 16, hipMemcpyHostToDevice));
     } else {
         std::vector<float> opv(2 * n, 0.f);
         if (hk)
-            for (size_t i = 0; i < n; i++) opv[n + i] = (float)((double)hk[i] * s->dx);
+            for (size_t i = 0; i < n; i++) opv[(gen ? 0 : n) + i] = (float)((double)hk[i] * s->dx);
+        if (gen)
+            for (size_t i = 0; i < n; i++) opv[i] = std::max(opv[i], (float)floor_a);
         RCCHK(scopy(s, s->op, opv.data(), n * 8, hipMemcpyHostToDevice));
     }
+    if (gen) RCCHK(sset(s, s->front, 0, n * 8));
     RCCHK(scopy(s, s->nH, nHd.data(), n * 8, hipMemcpyHostToDevice));
     RCCHK(scopy(s, s->x, xd.data(), n * 8, hipMemcpyHostToDevice));
     if (T) RCCHK(scopy(s, s->T, hT, n * 4, hipMemcpyHostToDevice));
@@ -1200,9 +1221,12 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
     FrtSolveDesc& h = s->h;
     h.nx = nx; h.ny = ny; h.nz = nz;
-    h.has_sub = 0;
+    h.has_sub = gen ? 1 : 0;
     if (hk)
         for (size_t i = 0; i < n && !h.has_sub; i++) h.has_sub = hk[i] > 0.f;
+    h.gen = gen ? 1 : 0;
+    h.front_atoms = (1.0 + s->P.he_chi) * s->dx * s->dx * s->dx;
+    h.front = s->front;
     h.bpx = s->bpx; h.bpy = s->bpy; h.bpz = s->bpz;
     for (int a = 0; a < 3; a++) h.bsh[a] = s->bsh[a];
     h.dx_cm = s->dx;
@@ -1210,6 +1234,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     h.op_a = s->op;
     h.op_b = (const char*)s->op + n * s->rs;
     h.op_aw = s->op;
+    h.op_bw = (char*)s->op + n * s->rs;
     h.gamma[0] = s->gam[0];
     h.gamma[1] = s->gam[1];
     h.x = s->x;
@@ -1512,6 +1537,7 @@ int frt_read_ledger(frt_solve s, frt_ledger* out)
     out->steps = s->step;
     out->err_flags = L.err_flags;
     out->max_items = L.max_items;
+    out->absorbed_front = L.absorbed_front;
     return FRT_OK;
 }
 
@@ -1538,7 +1564,7 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     }
     if (*bytes < need) return fail(FRT_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
     char* p = (char*)buf;
-    uint64_t hdr[8] = {0x4652544350543034ull, 5, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
+    uint64_t hdr[8] = {0x4652544350543034ull, 6, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
     RCCHK(scopy(s, p, s->L, led, hipMemcpyDeviceToHost));
@@ -1567,7 +1593,7 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     uint64_t hdr[8];
     std::memcpy(hdr, p, sizeof(hdr));
     p += sizeof(hdr);
-    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 5) return fail(FRT_EINVAL, "not a checkpoint of this library");
+    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 6) return fail(FRT_EINVAL, "not a checkpoint of this library");
     if (hdr[3] != (uint64_t)s->n_src || hdr[4] != s->ncell || hdr[5] != (uint64_t)s->P.n_bins || hdr[6] != (uint64_t)s->fp64)
         return fail(FRT_EINVAL, "checkpoint does not match this solve (sources, grid, bins or precision)");
     const uint32_t step = (uint32_t)hdr[2], nc = (uint32_t)hdr[7];
@@ -1624,6 +1650,7 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     s->h.step = step;
     RCCHK(sset(s, s->gam[0], 0, s->ncell * s->rs));
     RCCHK(sset(s, s->gam[1], 0, s->ncell * s->rs));
+    if (s->front) RCCHK(sset(s, s->front, 0, s->ncell * 8));
     RCCHK(upload_desc(s));
     hipError_t e = frt::launch_prep_opacity(s->d_desc, s->ncell, s->fp64, s->stream);
     if (e != hipSuccess) return fail(FRT_EDEVICE, "prep launch: %s", hipGetErrorString(e));
@@ -1667,6 +1694,7 @@ int frt_rewind(frt_solve s)
     RCCHK(copy_recs(s->F[cur], s->mark_F, s->mark_n, s->P.n_bins, s->rs, s->stream, hipMemcpyDeviceToDevice));
     HIPCHK(hipMemcpyAsync(s->fcount, s->mark_fc, 8, hipMemcpyDeviceToDevice, s->stream));
     HIPCHK(hipMemsetAsync(s->gam[cur], 0, s->ncell * s->rs, s->stream));
+    if (s->front) HIPCHK(hipMemsetAsync(s->front, 0, s->ncell * 8, s->stream));
     s->step = s->mark_step;
     s->h.step = s->step;
     RCCHK(upload_desc(s));

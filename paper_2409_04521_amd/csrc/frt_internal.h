@@ -52,13 +52,15 @@ enum : uint32_t {
 };
 
 // Photon terms (double) and counters (u64) accumulated during a step.
+// (In the Generalized Opacity Mode, which has no sub-grid term, the
+// LF_ABS_SUB stripe carries the photons stopped at I-fronts.)
 enum { LF_EMITTED, LF_ABS_HI, LF_ABS_SUB, LF_ESC, LF_DROP, LF_FLIGHT, LF_LOST, LF_NF };
 enum { LC_CROSS, LC_VISITS, LC_SPLITS, LC_NESC, LC_NDROP, LC_NFLIGHT, LC_EMITTED, LC_NC };
 
 // Cumulative photon ledger of one solve (device resident).  During a step
 // the kernels add into the stripes; the step-end kernel folds them in.
 struct FrtLedgerDev {
-    double emitted, absorbed_HI, absorbed_sub, escaped, dropped, in_flight, lost;
+    double emitted, absorbed_HI, absorbed_sub, escaped, dropped, in_flight, lost, absorbed_front;
     unsigned long long crossings, ray_visits, splits, n_escaped, n_dropped, n_in_flight, rays_emitted;
     unsigned long long step_crossings;
     unsigned int err_flags, max_items;
@@ -105,7 +107,7 @@ struct FrtRecs {
 struct FrtSolveDesc {
     int nx, ny, nz, n_bins;
     int base_level, max_level, n_src, fp64;
-    int has_sub;                // some cell has kappa > 0
+    int has_sub;                // some cell has kappa > 0 (always, in the Generalized Opacity Mode)
     int bpx, bpy, bpz;          // bricks per axis
     int bsh[3];                 // log2 of the brick edge per axis
     uint32_t key_base;          // first global brick key of this solve in the launch
@@ -156,6 +158,11 @@ struct FrtSolveDesc {
     double* xavg;               // [ncell], or null with backward-Euler chemistry
     const FrtLedgerDev* L_snap;
     const uint32_t* fcount_snap;
+    // Generalized Opacity Mode: op_b holds each cell's ionized fraction
+    int gen;
+    double front_atoms;         // (1 + chi) V: times n_H, the atoms a front photon ionizes
+    void* op_bw;                // op_b, written by this mode's chemistry
+    double* front;              // [ncell] photons stopped at each cell's front this step (or null)
 };
 
 // One work item of a pass: up to FRT_ITEM_RAYS packets of one brick.

@@ -1060,6 +1060,10 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         const double Rr = uni(D.R_ref);
         const int max_level = uni(D.max_level), base_level = uni(D.base_level);
         const double r_split0 = uni(D.r_split0);
+        // Generalized Opacity Mode (only with the sub-grid layout): .x of a
+        // staged cell is the ionized part's opacity per cell width at sigma_0,
+        // .y the ionized volume fraction
+        const bool gmode = SUB && uni(D.gen) != 0;
         const Real budget = uni((Real)D.budget);
         const uint32_t step = uni(D.step);
         // absorbed photons and crossings of this lane's packets, reduced
@@ -1162,6 +1166,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         // 0 for an empty segment), so that waiting for the next
                         // cell's prefetched opacity never waits for it
                         Real dep = 0;
+                        bool front = false;   // stopped at the cell's I-front
                         if (ds > Real(0)) {
                             R2 o;
                             if constexpr (SUB) {
@@ -1170,10 +1175,15 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                                 o.x = o_cur;
                                 o.y = Real(0);
                             }
-                            const Real ta = o.x * ds;
+                            // the path through absorbing gas: the ionized part
+                            // x_ion ds in the Generalized Opacity Mode (whose
+                            // rate keeps the whole ds: Eq. gamma_avg_subgrid
+                            // with ds -> x_ion ds and V -> x_ion V)
+                            const Real ta = o.x * (gmode ? o.y * ds : ds);
+                            if (gmode) front = o.y < Real(1);
                             Real absd = 0;
                             if constexpr (SUB) {
-                                const Real tk = o.y * ds;
+                                const Real tk = gmode ? Real(0) : o.y * ds;
 #pragma unroll
                                 for (int b = 0; b < NB; b++) {
                                     const Real tb = srel[b] * ta + tk;
@@ -1238,9 +1248,10 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         // floor, split, then the budget (a face reached with it is
                         // crossed first)
                         const bool floored = floor_f > Real(0) && sumE < floor_abs;
-                        const int e_pre = (h.r >= r_lim)
-                                              ? ((h.r >= r_cap || floored) ? 2 : (h.r >= r_split ? 0 : (h.r < r_face ? 3 : -1)))
-                                              : (floored ? 2 : -1);
+                        int e_pre = (h.r >= r_lim)
+                                        ? ((h.r >= r_cap || floored) ? 2 : (h.r >= r_split ? 0 : (h.r < r_face ? 3 : -1)))
+                                        : (floored ? 2 : -1);
+                        if (front) e_pre = 5;   // (only in the Generalized Opacity Mode)
                         // step to the next cell along `axis` (selects keep every
                         // per-axis value in registers); undone below for an end
                         // before the step, so that the loop has a single exit
@@ -1331,6 +1342,16 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         if (m_esc) atomicAdd(&s_lc[LC_NESC], (unsigned long long)__popcll(m_esc));
                         if (m_drop) atomicAdd(&s_lc[LC_NDROP], (unsigned long long)__popcll(m_drop));
                         if (m_fl) atomicAdd(&s_lc[LC_NFLIGHT], (unsigned long long)__popcll(m_fl));
+                    }
+                    // photons stopped at an I-front: the ledger term, and the
+                    // cell's front counter that the chemistry turns into x_ion
+                    if (gmode) {
+                        const bool fr = end == 5;
+                        if (__ballot(fr)) {
+                            const double t_fr = wave_sum(fr ? v_end : 0.0);
+                            if (lane == 0) atomicAdd(&s_lf[LF_ABS_SUB], t_fr);   // the front term here
+                            if (fr) atomicAdd(&D.front[(size_t)c[0] + (size_t)nx * ((size_t)c[1] + (size_t)ny * (size_t)c[2])], v_end);
+                        }
                     }
                 }
                 // keys of the packets entering another brick, computed while the
@@ -1580,7 +1601,10 @@ __global__ void k_finish(FrtSolveDesc* descs, FrtWS ws)
                 switch (i) {
                     case LF_EMITTED: L->emitted += v; break;
                     case LF_ABS_HI: L->absorbed_HI += v; break;
-                    case LF_ABS_SUB: L->absorbed_sub += v; break;
+                    case LF_ABS_SUB:
+                        if (D.gen) L->absorbed_front += v;
+                        else L->absorbed_sub += v;
+                        break;
                     case LF_ESC: L->escaped += v; break;
                     case LF_DROP: L->dropped += v; break;
                     case LF_FLIGHT: L->in_flight = v; break;
@@ -1649,6 +1673,19 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
         const size_t i = (size_t)(g - spre[lo]);
         Real* gcur = (Real*)D.gamma[D.step & 1u];
         Real* gnext = (Real*)D.gamma[(D.step + 1u) & 1u];
+        if (D.gen) {
+            // moving screen (§4.2, Eq. dxidt): each photon stopped at the
+            // cell's front ionizes 1 + chi atoms; x_ion is at most 1 and
+            // never decreases; x = 1 - x_ion is the neutral volume fraction
+            const double atoms = D.front_atoms * D.nH[i];
+            double xi = atoms > 0.0 ? (1.0 - D.x[i]) + D.front[i] / atoms : 1.0;
+            xi = xi < 1.0 ? xi : 1.0;
+            D.x[i] = 1.0 - xi;
+            ((Real*)D.op_bw)[i] = (Real)xi;
+            D.front[i] = 0.0;
+            gnext[i] = Real(0);
+            continue;
+        }
         const double G = (double)gcur[i];
         const double nH = D.nH[i];
         const double x = D.x[i];
@@ -1750,15 +1787,19 @@ __global__ void __launch_bounds__(BLOCK) k_iter_restart(FrtSolveDesc* descs)
 }
 
 // Opacity from the loaded state: {n_H x sigma_0 dx, kappa dx} (kappa dx is
-// written by the host beforehand into .y).
+// written by the host beforehand into .y); in the Generalized Opacity Mode
+// {kappa dx (written by the host), 1 - x}.
 template <typename Real>
 __global__ void __launch_bounds__(BLOCK) k_prep(FrtSolveDesc* desc, unsigned long long n)
 {
     const FrtSolveDesc& D = *desc;
     Real* op = (Real*)D.op_aw;
+    Real* ob = (Real*)D.op_bw;
     for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (unsigned long long)gridDim.x * blockDim.x)
-        op[i] = hi_opacity<Real>(D.nH[i] * D.x[i] * D.sigma0 * D.dx_cm);
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+        if (D.gen) ob[i] = (Real)(1.0 - D.x[i]);   // the ionized fraction; .x is kappa dx, set by the host
+        else op[i] = hi_opacity<Real>(D.nH[i] * D.x[i] * D.sigma0 * D.dx_cm);
+    }
 }
 
 int g_cu_count = 0;

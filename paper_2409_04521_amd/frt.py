@@ -45,7 +45,7 @@ class Params(C.Structure):
                 ("max_level", C.c_int), ("n_ray_min", C.c_double), ("flux_floor", C.c_double),
                 ("max_distance_cm", C.c_double), ("c_ray_cm_s", C.c_double), ("march_precision", C.c_int),
                 ("seed", C.c_uint64), ("queue_capacity", C.c_uint64), ("queue_hint", C.c_uint64),
-                ("chem_iterations", C.c_int)]
+                ("chem_iterations", C.c_int), ("opacity_mode", C.c_int), ("he_chi", C.c_double)]
 
 
 class Ledger(C.Structure):
@@ -54,7 +54,8 @@ class Ledger(C.Structure):
                 ("lost", C.c_double), ("crossings", C.c_uint64), ("ray_visits", C.c_uint64),
                 ("splits", C.c_uint64), ("n_escaped", C.c_uint64), ("n_dropped", C.c_uint64),
                 ("n_in_flight", C.c_uint64), ("rays_emitted", C.c_uint64), ("step_crossings", C.c_uint64),
-                ("steps", C.c_uint64), ("err_flags", C.c_uint32), ("max_items", C.c_uint32)]
+                ("steps", C.c_uint64), ("err_flags", C.c_uint32), ("max_items", C.c_uint32),
+                ("absorbed_front", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -220,7 +221,8 @@ class Solve:
 
     def __init__(self, ctx: Context, *, sigma_bins, alpha_B=2.59e-13, coll_ion=0.0, base_level=0,
                  max_level=12, n_ray_min=1.0, flux_floor=0.0, max_distance_cm=0.0, c_ray=2.99792458e10,
-                 precision="f32", seed=0, queue_capacity=0, queue_hint=0, chem_iterations=0, stream=None):
+                 precision="f32", seed=0, queue_capacity=0, queue_hint=0, chem_iterations=0, opacity_mode=0,
+                 he_chi=0.0, stream=None):
         p = params_default()
         sig = list(sigma_bins)
         p.n_bins = len(sig)
@@ -233,6 +235,7 @@ class Solve:
         p.march_precision = FRT_F64 if precision == "f64" else FRT_F32
         p.seed, p.queue_capacity, p.queue_hint = seed, queue_capacity, queue_hint
         p.chem_iterations = chem_iterations
+        p.opacity_mode, p.he_chi = opacity_mode, he_chi
         self.ctx = ctx
         self.params = p
         self.n_bins = p.n_bins
@@ -367,6 +370,8 @@ def _params_for(prob, precision="f32", **kw) -> Params:
     p.queue_capacity = kw.get("queue_capacity", 0)
     p.queue_hint = kw.get("queue_hint", 0)
     p.chem_iterations = getattr(prob, "chem_iterations", 0)
+    p.opacity_mode = getattr(prob, "opacity_mode", 0)
+    p.he_chi = getattr(prob, "he_chi", 0.0)
     return p
 
 
@@ -479,7 +484,8 @@ def solve_from_problem(ctx: Context, prob, precision="f32", use_table=True, **kw
     s = Solve(ctx, sigma_bins=prob.sigma_bins, alpha_B=prob.alpha_B, coll_ion=prob.coll_ion,
               base_level=prob.base_level, max_level=prob.max_level, n_ray_min=prob.n_ray_min,
               flux_floor=prob.flux_floor, max_distance_cm=prob.max_dist_cm, c_ray=prob.c_ray,
-              precision=precision, seed=prob.seed, chem_iterations=getattr(prob, "chem_iterations", 0), **kw)
+              precision=precision, seed=prob.seed, chem_iterations=getattr(prob, "chem_iterations", 0),
+              opacity_mode=getattr(prob, "opacity_mode", 0), he_chi=getattr(prob, "he_chi", 0.0), **kw)
     nz, ny, nx = prob.shape
     s.load_grid(prob.n_H, prob.dx_cm * nx, kappa=prob.kappa, x_HI0=prob.x_HI0, T=prob.T)
     s.load_sources(prob.src_pos_cm, prob.ndot_bins)

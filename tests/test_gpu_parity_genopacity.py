@@ -1,0 +1,159 @@
+"""GPU (HIP, gfx950) versus the FP64 oracle in the Generalized Opacity Mode
+(§4.2): ionized-phase absorption coefficient, rate over the ionized part of
+each cell, moving-screen fronts that stop packets and advance the ionized
+fraction.  Bars as elsewhere: x_HI (here 1 - x_ion) within 1e-3 absolute
+with the FP32 march and 1e-9 with the FP64 march, every ledger term (the
+front term included) within 1e-4 of emitted, closure 1e-9."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2409_04521_amd import frt
+from paper_2409_04521_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TERMS = ("emitted", "absorbed_HI", "absorbed_sub", "absorbed_front", "escaped", "dropped", "in_flight")
+DX = W.cmpc_h_to_cm(0.15625)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return frt.Context(0)
+
+
+def _oracle(prob, steps):
+    o = O.Oracle(**prob.oracle_kwargs())
+    o.set_sources(prob.src_pos_cm, prob.ndot_bins)
+    for s in range(steps):
+        o.step(prob.dt_s, prob.uniforms(s))
+    return o
+
+
+def _gpu(ctx, prob, steps, **kw):
+    g = frt.solve_from_problem(ctx, prob, **kw)
+    for _ in range(steps):
+        g.step(prob.dt_s)
+    return g
+
+
+def _compare(o, g, x_tol, led_tol, label):
+    xo, _ = o.fields()
+    xg, _ = g.fields()
+    dx = np.abs(xo - xg)
+    Lo, Lg = o.ledger(), g.ledger()
+    E = Lo["emitted"]
+    worst = {k: abs(Lo[k] - Lg[k]) / E for k in TERMS}
+    print(f"[{label}] max|dx_HI| = {dx.max():.3e}  ledger rel = " +
+          ", ".join(f"{k}:{v:.1e}" for k, v in worst.items()) +
+          f"  crossings oracle={Lo['crossings']} gpu={Lg['crossings']}", flush=True)
+    assert dx.max() <= x_tol, f"{label}: x_HI differs by {dx.max():.3e}"
+    for k, v in worst.items():
+        assert v <= led_tol, f"{label}: ledger term {k} differs by {v:.3e} of emitted"
+    closure = abs(Lg["emitted"] - sum(Lg[k] for k in TERMS[1:]) - Lg["lost"]) / Lg["emitted"]
+    assert closure <= 1e-9, f"{label}: GPU ledger does not close ({closure:.2e})"
+    assert Lg["err_flags"] == 0 and Lg["lost"] == 0
+
+
+def _fronts_box(n, seed, n_src=5, bins=4, c_ray=W.C_LIGHT, steps=4):
+    # lognormal gas, mostly ionized with scattered partly ionized and neutral
+    # cells, ionized-gas mean free path ~5 cells
+    rng = np.random.Generator(np.random.PCG64(seed))
+    nH = W.lognormal_white(rng, (n, n, n), 2e-4, 1.0).astype(np.float32)
+    kap = (W.lognormal_white(rng, (n, n, n), 1.0, 0.5) / (5 * DX)).astype(np.float32)
+    u = rng.uniform(size=(n, n, n))
+    xi0 = np.where(u < 0.9, 1.0, np.where(u < 0.95, 0.0, rng.uniform(size=(n, n, n))))
+    w, sig = W.blackbody_bins(bins)
+    pos = (rng.integers(0, n, size=(n_src, 3)) + 0.5) * DX
+    ndot = (10 ** rng.uniform(51, 53, size=n_src))[:, None] * w[None, :]
+    return W.Problem(name=f"gen_{n}^3", shape=(n, n, n), dx_cm=DX, n_H=nH, x_HI0=1.0 - xi0, kappa=kap,
+                     src_pos_cm=pos, ndot_bins=ndot, sigma_bins=sig, dt_s=W.MYR, n_steps=steps, c_ray=c_ray,
+                     flux_floor=1e-3, seed=seed, opacity_mode=1, he_chi=0.08)
+
+
+@pytest.mark.parametrize("precision,x_tol,led_tol", [("f32", 1e-3, 1e-4), ("f64", 1e-9, 1e-9)])
+@pytest.mark.parametrize("n,c_ray", [(24, W.C_LIGHT), (27, np.inf)])
+def test_fronts_in_clumpy_gas(ctx, precision, x_tol, led_tol, n, c_ray):
+    p = _fronts_box(n, 51 + n, c_ray=c_ray)
+    _compare(_oracle(p, 4), _gpu(ctx, p, 4, precision=precision), x_tol, led_tol,
+             f"generalized {n}^3 c={'inf' if np.isinf(c_ray) else 'c'} {precision}")
+
+
+def test_front_sphere_in_neutral_gas(ctx):
+    n, nh, Nd = 24, 2e-5, 3e51
+    p = W.Problem(name="front sphere", shape=(n, n, n), dx_cm=DX, n_H=np.full((n, n, n), nh, np.float32),
+                  x_HI0=np.ones((n, n, n)), kappa=np.zeros((n, n, n), np.float32),
+                  src_pos_cm=np.array([[11.5, 11.5, 11.5]]) * DX, ndot_bins=np.array([[Nd]]),
+                  sigma_bins=np.array([6.3e-18]), dt_s=0.1 * W.MYR, n_steps=40, c_ray=np.inf, seed=1,
+                  opacity_mode=1, he_chi=0.08)
+    g = _gpu(ctx, p, 40)
+    _compare(_oracle(p, 40), g, 1e-3, 1e-4, "front sphere")
+    x, _ = g.fields()
+    R_num = (3 * float(np.sum(1 - x)) / (4 * np.pi)) ** (1 / 3)
+    R_an = (3 * Nd * 40 * p.dt_s / (4 * np.pi * 1.08 * nh)) ** (1 / 3) / DX
+    assert R_num == pytest.approx(R_an, rel=0.03)
+
+
+def test_ionized_gas_matches_standard_mode_rates(ctx):
+    # kappa = n_HI sigma_0 with x_ion = 1: the rate field of Standard Mode
+    n = 20
+    rng = np.random.Generator(np.random.PCG64(61))
+    nH = W.lognormal_white(rng, (n, n, n), 2e-4, 1.0).astype(np.float32)
+    xh = rng.uniform(1e-3, 1e-2, size=(n, n, n))
+    w, sig = W.blackbody_bins(3)
+    kap = (nH.astype(np.float64) * xh * sig[0]).astype(np.float32)
+    xh_std = kap.astype(np.float64) / (nH.astype(np.float64) * sig[0])
+    pos = (rng.integers(0, n, size=(3, 3)) + 0.5) * DX
+    ndot = np.array([1e52, 3e51, 2e52])[:, None] * w[None, :]
+    base = dict(shape=(n, n, n), dx_cm=DX, n_H=nH, src_pos_cm=pos, ndot_bins=ndot, sigma_bins=sig, dt_s=W.MYR,
+                n_steps=1, c_ray=np.inf, seed=62)
+    std = _gpu(ctx, W.Problem(name="std", x_HI0=xh_std, kappa=None, **base), 1)
+    gen = _gpu(ctx, W.Problem(name="gen", x_HI0=np.zeros((n, n, n)), kappa=kap, opacity_mode=1, **base), 1)
+    gs, gg = std.fields()[1].astype(np.float64), gen.fields()[1].astype(np.float64)
+    assert np.abs(gs - gg).max() <= 2e-3 * gs.max()
+    Ls, Lg = std.ledger(), gen.ledger()
+    for k in ("emitted", "absorbed_HI", "escaped", "dropped"):
+        assert abs(Ls[k] - Lg[k]) <= 1e-4 * Ls["emitted"], k
+    assert Lg["absorbed_front"] == 0.0
+
+
+def test_batched_with_subgrid_standard_equals_alone(ctx):
+    # a generalized and a standard solve with sub-grid opacity share the
+    # 16^3 launch group
+    a = _fronts_box(20, 71, n_src=3, bins=2)
+    b = W.lognormal_c2(n=20, n_src=4, n_steps=3, box_cmpc_h=20.0 * 20 / 128, n_bins=2)
+    alone = [_gpu(ctx, p, 3) for p in (a, b)]
+    both = [frt.solve_from_problem(ctx, p) for p in (a, b)]
+    for _ in range(3):
+        frt.batch_step(both, [a.dt_s, b.dt_s])
+    for p, s1, s2 in zip((a, b), alone, both):
+        assert np.abs(s1.fields()[0] - s2.fields()[0]).max() <= 1e-5, p.name
+        L1, L2 = s1.ledger(), s2.ledger()
+        for k in TERMS:
+            assert abs(L1[k] - L2[k]) <= 1e-6 * L1["emitted"], (p.name, k)
+
+
+def test_checkpoint_resume_in_generalized_mode(ctx):
+    p = _fronts_box(20, 81, n_src=3, bins=2, steps=4)
+    ref = _gpu(ctx, p, 4)
+    g = _gpu(ctx, p, 2)
+    blob = g.save()
+    h = frt.solve_from_problem(ctx, p)
+    h.load(blob)
+    for _ in range(2):
+        h.step(p.dt_s)
+    # equal up to the order of the atomic deposits and front counts
+    assert np.abs(ref.fields()[0] - h.fields()[0]).max() <= 1e-5
+    La, Lh = ref.ledger(), h.ledger()
+    for k in TERMS:
+        assert abs(La[k] - Lh[k]) <= 1e-6 * La["emitted"], k
+    assert La["crossings"] == Lh["crossings"]
+
+
+def test_generalized_parameters_are_checked(ctx):
+    p = _fronts_box(8, 91, n_src=1, bins=1)
+    for bad in (dict(chem_iterations=2), dict(he_chi=-1.0), dict(opacity_mode=2)):
+        q = W.Problem(**{**p.__dict__, **bad})
+        with pytest.raises(frt.FrtError) as e:
+            frt.solve_from_problem(ctx, q)
+        assert e.value.code == frt.FRT_EINVAL
