@@ -209,10 +209,11 @@ int frt_tuning_default(frt_tuning* t);
 int frt_ctx_set_tuning(frt_ctx ctx, const frt_tuning* t);
 int frt_ctx_get_tuning(frt_ctx ctx, frt_tuning* t);
 
-/* Autotuner: times one step of the n solves (as frt_batch_step runs it)
- * under each candidate launch shape (item_rays 256/512/1024 x scatter 4/8
- * workgroups per CU), after one untimed step that sizes the
- * queues; sets the fastest on the context and returns it in *best.  Every
+/* Autotuner: times one step of the n solves (as frt_batch_step runs it,
+ * best of three runs of the same step) under each candidate launch shape
+ * (item_rays 256/512/1024 x scatter 4/8 workgroups per CU), after one
+ * untimed step that sizes the queues; sets the fastest on the context and
+ * returns it in *best.  Every
  * solve is put back exactly as it was (fields, carried packets, ledger,
  * step index, last rate field), so the call changes no result. */
 int frt_autotune(frt_solve* solves, int n, const double* dt_s, frt_tuning* best);

@@ -1447,18 +1447,25 @@ int frt_autotune(frt_solve* ss, int n, const double* dts, frt_tuning* best)
             dev_free(ctx->ws.work);
             ctx->ws.cap_work = 0;
         }
-        (void)hipEventRecord(a, st);
-        rc = step_group_locked(ss, n, dts);
-        (void)hipEventRecord(b, st);
+        // the best of three timings of the same step (one step of a small
+        // batch lasts a few ms, about as long as the launch jitter)
+        float ms = -1.f;
+        for (int rep = 0; rep < 3 && rc == FRT_OK; rep++) {
+            (void)hipEventRecord(a, st);
+            rc = step_group_locked(ss, n, dts);
+            (void)hipEventRecord(b, st);
+            if (rc != FRT_OK) break;
+            (void)hipEventSynchronize(b);
+            float t = 0.f;
+            (void)hipEventElapsedTime(&t, a, b);
+            if (ms < 0.f || t < ms) ms = t;
+            rc = restore_all();
+        }
         if (rc != FRT_OK) break;
-        (void)hipEventSynchronize(b);
-        float ms = 0.f;
-        (void)hipEventElapsedTime(&ms, a, b);
         if (best_ms < 0.f || ms < best_ms) {
             best_ms = ms;
             pick = cand[c];
         }
-        rc = restore_all();
     }
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);

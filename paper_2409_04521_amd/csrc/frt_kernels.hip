@@ -1647,6 +1647,38 @@ __device__ __forceinline__ Real hi_opacity(double v)
 }
 
 // ================================================================ chemistry
+// Every cell of every solve of a launch, one per thread, in chunks of
+// blockDim.x consecutive cells.  A chunk inside one solve (nearly all of
+// them) finds that solve once and reads its descriptor with uniform scalar
+// loads; a chunk across two solves finds each cell's solve by a binary
+// search over the per-solve cell prefix (in LDS).  f(D, i) gets the solve
+// and the cell index within it.
+template <typename F>
+__device__ __forceinline__ void for_each_cell(FrtSolveDesc* descs, const unsigned long long* spre, int n_solves,
+                                             unsigned long long total, F&& f)
+{
+    auto solve_of = [&](unsigned long long g) {
+        int lo = 0, hi = n_solves - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (spre[mid] <= g) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
+    for (unsigned long long base = (unsigned long long)blockIdx.x * blockDim.x; base < total; base += stride) {
+        const unsigned long long g = base + threadIdx.x;
+        const int s0 = uni(solve_of(base));
+        if (base + blockDim.x <= spre[s0 + 1]) {
+            f(descs[s0], (size_t)(g - spre[s0]));
+        } else if (g < total) {
+            const int s = solve_of(g);
+            f(descs[s], (size_t)(g - spre[s]));
+        }
+    }
+}
+
 // Backward Euler for x = n_HI / n_H, pure H, n_e = n_HII = n_H (1 - x):
 //   x' - x = dt [ -Gamma x' - C n_H (1-x') x' + alpha n_H (1-x')^2 ]
 // (Eq. ion_balance_eqn), i.e. a x'^2 + b x' + c = 0 with the root in [0,1]
@@ -1660,17 +1692,8 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
     __shared__ unsigned long long spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
     for (int i = threadIdx.x; i <= n_solves; i += blockDim.x) spre[i] = prefix[i];
     __syncthreads();
-    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-    for (unsigned long long g = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-        int lo = 0, hi = n_solves - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (spre[mid] <= g) lo = mid;
-            else hi = mid - 1;
-        }
-        const FrtSolveDesc& D = descs[lo];
-        if (D.L->err_flags) continue;
-        const size_t i = (size_t)(g - spre[lo]);
+    for_each_cell(descs, spre, n_solves, total, [&](const FrtSolveDesc& D, size_t i) {
+        if (D.L->err_flags) return;
         Real* gcur = (Real*)D.gamma[D.step & 1u];
         Real* gnext = (Real*)D.gamma[(D.step + 1u) & 1u];
         if (D.gen) {
@@ -1684,7 +1707,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
             ((Real*)D.op_bw)[i] = (Real)xi;
             D.front[i] = 0.0;
             gnext[i] = Real(0);
-            continue;
+            return;
         }
         const double G = (double)gcur[i];
         const double nH = D.nH[i];
@@ -1699,7 +1722,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
         D.x[i] = xn;
         ((Real*)D.op_aw)[i] = hi_opacity<Real>(nH * xn * D.sigma0 * D.dx_cm);
         gnext[i] = Real(0);
-    }
+    });
 }
 
 // Time-averaged hydrogen update (§4.1, Eqs. xi_of_t, xeq, ti, avg_xi) for
@@ -1721,17 +1744,8 @@ __global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const u
     __shared__ unsigned long long spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
     for (int i = threadIdx.x; i <= n_solves; i += blockDim.x) spre[i] = prefix[i];
     __syncthreads();
-    const unsigned long long stride = (unsigned long long)gridDim.x * blockDim.x;
-    for (unsigned long long g = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; g < total; g += stride) {
-        int lo = 0, hi = n_solves - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (spre[mid] <= g) lo = mid;
-            else hi = mid - 1;
-        }
-        const FrtSolveDesc& D = descs[lo];
-        if (D.L->err_flags) continue;
-        const size_t i = (size_t)(g - spre[lo]);
+    for_each_cell(descs, spre, n_solves, total, [&](const FrtSolveDesc& D, size_t i) {
+        if (D.L->err_flags) return;
         const double nH = D.nH[i];
         const double x0 = D.x[i];
         double xo;   // the neutral fraction the opacity is built from
@@ -1761,7 +1775,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const u
             }
         }
         ((Real*)D.op_aw)[i] = hi_opacity<Real>(nH * xo * D.sigma0 * D.dx_cm);
-    }
+    });
 }
 
 // Every march of a step after the first starts from the step's packets: the
