@@ -562,11 +562,9 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
     FrtWS w = g.w;
     frt_solve tm = (!graph && ss[0]->timing) ? ss[0] : nullptr;
     hipError_t e;
-    if (graph)
-        for (int i = 0; i < n; i++) {
-            HIPCHK(hipMemcpyAsync(ss[i]->L_snap, ss[i]->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync(ss[i]->fcount_snap, ss[i]->fcount, 8, hipMemcpyDeviceToDevice, st));
-        }
+    // every solve's ledger and carried-queue counters as the step starts, for
+    // a re-run after an overflow (one kernel for the whole group)
+    if ((e = frt::launch_snapshot(ws.descs, n, st)) != hipSuccess) return fail(FRT_EDEVICE, "snapshot: %s", hipGetErrorString(e));
     // backward Euler: one march, then the update; time-averaged chemistry:
     // K marches from the same packets with <x> updated between them
     const int K = ss[0]->P.chem_iterations;   // the same for every solve of a group
@@ -758,10 +756,6 @@ int step_group_locked(frt_solve* ss, int n, const double* dts)
     }
     for (int attempt = 0; attempt < 16; attempt++) {
         RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.pcap)));
-        for (int i = 0; i < n; i++) {
-            HIPCHK(hipMemcpyAsync(ss[i]->L_snap, ss[i]->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
-            HIPCHK(hipMemcpyAsync(ss[i]->fcount_snap, ss[i]->fcount, 8, hipMemcpyDeviceToDevice, st));
-        }
         Group g;
         plan_group(ws, ss, n, g);
         RCCHK(upload_group(ws, g, n, st));

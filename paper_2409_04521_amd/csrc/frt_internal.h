@@ -156,8 +156,8 @@ struct FrtSolveDesc {
     // and carried-queue counters of the start of the step, which every march
     // of the step starts from
     double* xavg;               // [ncell], or null with backward-Euler chemistry
-    const FrtLedgerDev* L_snap;
-    const uint32_t* fcount_snap;
+    FrtLedgerDev* L_snap;
+    uint32_t* fcount_snap;
     // Generalized Opacity Mode: op_b holds each cell's ionized fraction
     int gen;
     double front_atoms;         // (1 + chi) V: times n_H, the atoms a front photon ionizes
@@ -220,6 +220,7 @@ hipError_t launch_clear(const FrtWS& ws, int keep_err, hipStream_t s);
 hipError_t launch_chem_avg(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
                            unsigned long long total_cells, int fp64, int phase, hipStream_t s);
 hipError_t launch_iter_restart(FrtSolveDesc* d, int n_solves, hipStream_t s);
+hipError_t launch_snapshot(FrtSolveDesc* d, int n_solves, hipStream_t s);
 // Advance every solve's step index on the device unless the step raised an
 // error (used by steps replayed from a HIP graph).
 hipError_t launch_advance(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);

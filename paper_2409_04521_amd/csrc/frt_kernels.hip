@@ -1778,6 +1778,19 @@ __global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const u
     });
 }
 
+// The ledger and carried-queue counters of every solve as a step starts, kept
+// for a re-run of the step (queue growth) and for the later marches of the
+// time-averaged chemistry.  One workgroup per solve.
+__global__ void __launch_bounds__(BLOCK) k_snapshot(FrtSolveDesc* descs)
+{
+    const FrtSolveDesc& D = descs[blockIdx.x];
+    constexpr int NW = (int)(sizeof(FrtLedgerDev) / sizeof(unsigned long long));
+    const unsigned long long* src = (const unsigned long long*)D.L;
+    unsigned long long* dst = (unsigned long long*)D.L_snap;
+    for (int k = threadIdx.x; k < NW; k += blockDim.x) dst[k] = src[k];
+    if (threadIdx.x < 2) D.fcount_snap[threadIdx.x] = D.fcount[threadIdx.x];
+}
+
 // Every march of a step after the first starts from the step's packets: the
 // ledger and the carried-queue counters go back to their values at the
 // start of the step, keeping the device error bits.  One workgroup per solve.
@@ -1976,6 +1989,12 @@ hipError_t launch_chem_avg(FrtSolveDesc* d, const unsigned long long* d_cell_pre
     const int grid = grid_for(total_cells, 16);
     if (fp64) hipLaunchKernelGGL(k_chem_avg<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase);
     else hipLaunchKernelGGL(k_chem_avg<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase);
+    return hipGetLastError();
+}
+
+hipError_t launch_snapshot(FrtSolveDesc* d, int n_solves, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_snapshot, dim3(n_solves), dim3(BLOCK), 0, s, d);
     return hipGetLastError();
 }
 
