@@ -154,7 +154,10 @@ int frt_solve_destroy(frt_solve s);
  * nx,ny,nz in 1..2048; box_cm > 0 is the x extent (cells are cubes);
  * n_H [ncell] cm^-3 (finite, >= 0); T [ncell] K is stored for the caller
  * and unused while T is fixed (may be NULL); kappa_sub [ncell] 1/cm
- * (finite, >= 0; NULL = 0); x_HI0 [ncell] in [0,1] (NULL = 1).
+ * (finite, >= 0; NULL = 0); x_HI0 [ncell] in [0,1] (NULL = 1).  With
+ * opacity_mode FRT_GENERALIZED, kappa_sub is the absorption coefficient of
+ * each cell's ionized gas at sigma_0 and x_HI0 is 1 - its ionized volume
+ * fraction (NULL = 1: all neutral).
  * Resets the step counter, ledger and carried packets. */
 int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const float* n_H, const float* T,
                   const float* kappa_sub, const double* x_HI0, int ptr_kind);
