@@ -639,7 +639,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
 // march workgroups take items from.
 __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
 {
-    __shared__ uint32_t s_a[1024], s_b[1024];
+    __shared__ uint32_t s_a[2 * WAVE + 1], s_b[2 * WAVE + 1];   // wave totals, their prefix, the total
     const uint32_t nk = ws.nkeys;
     const uint32_t per = (nk + blockDim.x - 1) / blockDim.x;
     const uint32_t k0 = threadIdx.x * per, k1 = min(nk, k0 + per);
@@ -649,21 +649,35 @@ __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
         sum += h;
         items += (h + ws.item_rays - 1) / ws.item_rays;
     }
-    s_a[threadIdx.x] = sum;
-    s_b[threadIdx.x] = items;
-    __syncthreads();
-    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
-        uint32_t va = threadIdx.x >= (unsigned)o ? s_a[threadIdx.x - o] : 0u;
-        uint32_t vb = threadIdx.x >= (unsigned)o ? s_b[threadIdx.x - o] : 0u;
-        __syncthreads();
-        s_a[threadIdx.x] += va;
-        s_b[threadIdx.x] += vb;
-        __syncthreads();
+    // exclusive scans of both counts: within each wave, then over the waves
+    uint32_t wsum, witems;
+    const uint32_t exs = wave_excl_scan(sum, &wsum);
+    const uint32_t exi = wave_excl_scan(items, &witems);
+    const int wid = (int)threadIdx.x / WAVE, nw = (int)blockDim.x / WAVE;
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        s_a[wid] = wsum;
+        s_b[wid] = witems;
     }
-    uint32_t off = s_a[threadIdx.x] - sum;
-    uint32_t it = s_b[threadIdx.x] - items;
-    const uint32_t total = s_a[blockDim.x - 1];
-    const uint32_t total_items = s_b[blockDim.x - 1];
+    __syncthreads();
+    if (threadIdx.x < WAVE) {
+        const uint32_t a = (int)threadIdx.x < nw ? s_a[threadIdx.x] : 0u;
+        const uint32_t b = (int)threadIdx.x < nw ? s_b[threadIdx.x] : 0u;
+        uint32_t ta, tb;
+        const uint32_t ea = wave_excl_scan(a, &ta), eb = wave_excl_scan(b, &tb);
+        if ((int)threadIdx.x < nw) {
+            s_a[WAVE + threadIdx.x] = ea;
+            s_b[WAVE + threadIdx.x] = eb;
+        }
+        if (threadIdx.x == 0) {
+            s_a[2 * WAVE] = ta;
+            s_b[2 * WAVE] = tb;
+        }
+    }
+    __syncthreads();
+    uint32_t off = s_a[WAVE + wid] + exs;
+    uint32_t it = s_b[WAVE + wid] + exi;
+    const uint32_t total = s_a[2 * WAVE];
+    const uint32_t total_items = s_b[2 * WAVE];
     // the previous pass's outputs in segment order; clear the fill counters
     if (threadIdx.x < WAVE) {
         const uint32_t cap = seg_cap(ws.buf[0].cap);
