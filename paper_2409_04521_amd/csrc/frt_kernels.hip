@@ -489,19 +489,27 @@ __device__ __forceinline__ void count_keys_wave(uint32_t* s_key, uint32_t* s_cnt
 // from the previous step.
 __global__ void k_seed_plan(FrtSolveDesc* descs, FrtWS ws)
 {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    // one wave: a solve per lane, the prefix by wave scans, 64 solves a round
+    if (blockIdx.x != 0 || threadIdx.x >= WAVE) return;
     uint32_t acc = 0;
-    for (int s = 0; s < ws.n_solves; s++) {
-        FrtSolveDesc& D = descs[s];
-        ws.seed_prefix[s] = acc;
-        uint32_t carried = D.fcount[D.cur];
-        if (carried > D.F[D.cur].cap) carried = D.F[D.cur].cap;
-        acc += (uint32_t)D.n_src * D.ncast + carried;
-        D.fcount[1 - D.cur] = 0;
-        D.L->step_crossings = 0;
+    for (int s0 = 0; s0 < ws.n_solves; s0 += WAVE) {
+        const int s = s0 + (int)threadIdx.x;
+        uint32_t n = 0;
+        if (s < ws.n_solves) {
+            FrtSolveDesc& D = descs[s];
+            uint32_t carried = D.fcount[D.cur];
+            if (carried > D.F[D.cur].cap) carried = D.F[D.cur].cap;
+            n = (uint32_t)D.n_src * D.ncast + carried;
+            D.fcount[1 - D.cur] = 0;
+            D.L->step_crossings = 0;
+        }
+        uint32_t tot;
+        const uint32_t ex = wave_excl_scan(n, &tot);
+        if (s < ws.n_solves) ws.seed_prefix[s] = acc + ex;
+        acc += tot;
     }
-    ws.seed_prefix[ws.n_solves] = acc;
-    for (int k = 0; k < FRT_QSEG; k++) ws.segc[k * FRT_QSEG_STRIDE] = 0;
+    if (threadIdx.x == 0) ws.seed_prefix[ws.n_solves] = acc;
+    for (int k = (int)threadIdx.x; k < FRT_QSEG; k += WAVE) ws.segc[k * FRT_QSEG_STRIDE] = 0;
 }
 
 // One lane per item: a cast packet gets r = 0 and Ndot_nu dt / (12 4^L0)
