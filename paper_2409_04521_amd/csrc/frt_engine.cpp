@@ -284,9 +284,16 @@ int passes_needed(frt_solve s)
     if (s->P.max_distance_cm > 0) reach = std::min(reach, s->P.max_distance_cm / s->dx);
     int l = s->P.base_level;
     while (l < s->P.max_level && split_radius_cells(s->P, l) < reach) l++;
-    const int splits = l - s->P.base_level;
+    int splits = l - s->P.base_level;
     double travel = reach;
     if (std::isfinite(s->P.c_ray_cm_s)) travel = std::min(travel, s->P.c_ray_cm_s * s->h.dt / s->dx + 1.0);
+    // A lineage's distance from its source grows by at most `travel` in a
+    // step, so it splits at most at the split radii inside one window of
+    // that length: the radii no larger than the window, and at most one
+    // more (radii above it are more than its length apart, as they double)
+    int small = 0;
+    for (int k = s->P.base_level; k < s->P.max_level && split_radius_cells(s->P, k) <= travel; k++) small++;
+    splits = std::min(splits, small + 1);
     int cross = 0;
     for (int a = 0; a < 3; a++) cross += (int)std::ceil(travel / (double)(1 << s->bsh[a])) + 1;
     return cross + 2 * splits + 6;
