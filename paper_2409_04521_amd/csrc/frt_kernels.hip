@@ -23,6 +23,7 @@
 #include <stdint.h>
 
 #include <type_traits>
+#include <limits>
 #include <mutex>
 #include <unordered_map>
 #include <utility>
@@ -1669,6 +1670,17 @@ __device__ __forceinline__ Real hi_opacity(double v)
 }
 
 // ================================================================ chemistry
+// The ionized fraction as staged for the march (Generalized Opacity Mode): a
+// cell not fully ionized in FP64 stays below 1 in FP32 too, so that the
+// march stops packets at its front exactly when the FP64 state has one.
+template <typename Real>
+__device__ __forceinline__ Real staged_ionized_fraction(double xi)
+{
+    Real v = (Real)xi;
+    if (xi < 1.0 && !(v < Real(1))) v = Real(1) - Real(0.5) * std::numeric_limits<Real>::epsilon();
+    return v;
+}
+
 // Every cell of every solve of a launch, one per thread, in chunks of
 // blockDim.x consecutive cells.  A chunk inside one solve (nearly all of
 // them) finds that solve once and reads its descriptor with uniform scalar
@@ -1726,7 +1738,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
             double xi = atoms > 0.0 ? (1.0 - D.x[i]) + D.front[i] / atoms : 1.0;
             xi = xi < 1.0 ? xi : 1.0;
             D.x[i] = 1.0 - xi;
-            ((Real*)D.op_bw)[i] = (Real)xi;
+            ((Real*)D.op_bw)[i] = staged_ionized_fraction<Real>(xi);
             D.front[i] = 0.0;
             gnext[i] = Real(0);
             return;
@@ -1846,7 +1858,7 @@ __global__ void __launch_bounds__(BLOCK) k_prep(FrtSolveDesc* desc, unsigned lon
     Real* ob = (Real*)D.op_bw;
     for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (unsigned long long)gridDim.x * blockDim.x) {
-        if (D.gen) ob[i] = (Real)(1.0 - D.x[i]);   // the ionized fraction; .x is kappa dx, set by the host
+        if (D.gen) ob[i] = staged_ionized_fraction<Real>(1.0 - D.x[i]);   // .x is kappa dx, set by the host
         else op[i] = hi_opacity<Real>(D.nH[i] * D.x[i] * D.sigma0 * D.dx_cm);
     }
 }

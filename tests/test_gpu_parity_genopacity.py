@@ -157,3 +157,23 @@ def test_generalized_parameters_are_checked(ctx):
         with pytest.raises(frt.FrtError) as e:
             frt.solve_from_problem(ctx, q)
         assert e.value.code == frt.FRT_EINVAL
+
+
+def test_nearly_ionized_cells_still_stop_packets(ctx):
+    # cells ionized to within 1e-9 of 1 keep their fronts in the FP32 march
+    # as in the FP64 state: a shell of them around the source stops every
+    # packet
+    n = 16
+    xi = np.ones((n, n, n))
+    zz, yy, xx = np.meshgrid(*(np.arange(n) + 0.5,) * 3, indexing="ij")
+    rr = np.sqrt((xx - 8.0) ** 2 + (yy - 8.0) ** 2 + (zz - 8.0) ** 2)
+    xi[(rr > 4.0) & (rr < 6.0)] = 1.0 - 1e-9
+    p = W.Problem(name="thin fronts", shape=(n, n, n), dx_cm=DX, n_H=np.full((n, n, n), 2e-4, np.float32),
+                  x_HI0=1.0 - xi, kappa=np.full((n, n, n), 0.01 / DX, np.float32),
+                  src_pos_cm=np.array([[8.0, 8.0, 8.0]]) * DX, ndot_bins=np.array([[1e52]]),
+                  sigma_bins=np.array([6.3e-18]), dt_s=W.MYR, n_steps=1, c_ray=np.inf, seed=5,
+                  opacity_mode=1, he_chi=0.08)
+    g = _gpu(ctx, p, 1)
+    _compare(_oracle(p, 1), g, 1e-3, 1e-4, "nearly ionized shell")
+    L = g.ledger()
+    assert L["escaped"] == 0.0 and L["absorbed_front"] > 0.9 * L["emitted"]
