@@ -17,6 +17,11 @@
  *      reaches the distance cap, or has travelled c_ray * dt this step;
  *   4. a backward-Euler update of the neutral fraction x_HI per cell closes
  *      the step (Eq. ion_balance_eqn discretized implicitly).
+ * Per solve, two further forms of §4 (frt_params): the time-averaged update
+ * of §4.1 iterated over several marches of the step (chem_iterations), and
+ * the Generalized Opacity Mode of §4.2 (opacity_mode), in which each cell's
+ * ionized part absorbs with a given kappa and packets stop at moving-screen
+ * I-fronts that the step's stopped photons advance.
  *
  * Conventions
  *   - Every function returns an int status: FRT_OK (0) or a negative
