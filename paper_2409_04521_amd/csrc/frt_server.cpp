@@ -1,8 +1,9 @@
 // Serving layer of the ray-tracing library (include/frt.h, "serving"):
 // requests arrive with their inputs, wait in arrival order until a slot
 // and enough of the device-memory budget are free, are loaded as solves by
-// a loader thread (each solve on its own stream, so uploads overlap the
-// running steps) and then advance one step per tick together with every
+// loader threads (several requests at once, each solve on its own stream, so
+// uploads overlap each other and the running steps) and then advance one
+// step per tick together with every
 // other admitted solve (one batched step per tick and per n_bins/precision
 // group, driven by the worker thread).  A finished request's x_HI and ledger
 // are copied to host memory and its solve is destroyed, which frees its
@@ -115,7 +116,8 @@ struct frt_server_s {
     uint64_t next_id = 1;
     bool stop = false;
     frt_server_stats st{};
-    std::thread worker, loader;
+    std::thread worker;
+    std::vector<std::thread> loaders;   // requests are loaded this many at a time
 
     void finish(Req* r, int state)
     {
@@ -327,7 +329,10 @@ int frt_server_create(frt_ctx ctx, size_t hbm_budget_bytes, int max_slots, frt_s
     s->t0 = Clock::now();
     frt_server_s* raw = s.get();
     s->worker = std::thread([raw] { raw->run(); });
-    s->loader = std::thread([raw] { raw->run_loader(); });
+    // the host side of a load (input checks and conversions, pageable
+    // copies) takes longer than a step of a small solve: several loaders
+    // keep the admitted requests flowing when many arrive at once
+    for (int k = 0; k < 4; k++) s->loaders.emplace_back([raw] { raw->run_loader(); });
     *out = s.release();
     return FRT_OK;
 }
@@ -444,7 +449,8 @@ int frt_server_destroy(frt_server srv)
         srv->load_cv.notify_all();
     }
     if (srv->worker.joinable()) srv->worker.join();
-    if (srv->loader.joinable()) srv->loader.join();
+    for (std::thread& t : srv->loaders)
+        if (t.joinable()) t.join();
     srv->drop_ready();
     delete srv;
     return FRT_OK;
