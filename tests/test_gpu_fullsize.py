@@ -10,6 +10,9 @@ benchmark times, checked where the oracle can follow it:
   every packet sees the start-of-step opacity, so the rate field and every
   ledger term are sums over sources; the full step must equal the sum of the
   steps of its even and odd sources, and its ledger must close.
+The benchmark's time-averaged chemistry and Generalized Opacity Mode legs
+(128^3 lognormal box, 64 sources, finite c, 12 steps) are small enough for
+the oracle to follow in full, at the same bars.
 """
 import dataclasses
 
@@ -99,3 +102,40 @@ def test_full_step_is_the_sum_of_its_source_halves(ctx, full):
     for k in TERMS:
         s = parts[0][2][k] + parts[1][2][k]
         assert abs(L_all[k] - s) <= 1e-9 * E, k
+
+
+def _leg_parity(ctx, p, steps, label):
+    g = frt.solve_from_problem(ctx, p)
+    for _ in range(steps):
+        g.step(p.dt_s)
+    o = O.Oracle(**p.oracle_kwargs())
+    o.set_sources(p.src_pos_cm, p.ndot_bins)
+    for s in range(steps):
+        o.step(p.dt_s, p.uniforms(s))
+    xo, _ = o.fields()
+    xg, _ = g.fields()
+    Lo, Lg = o.ledger(), g.ledger()
+    terms = TERMS + ("absorbed_front",)
+    dx = float(np.abs(xo - xg).max())
+    worst = {k: abs(Lo[k] - Lg[k]) / Lo["emitted"] for k in terms}
+    print(f"[{label}] max|dx_HI| = {dx:.3e}, ledger rel = " + ", ".join(f"{k}:{v:.1e}" for k, v in worst.items())
+          + f", crossings oracle={Lo['crossings']} gpu={Lg['crossings']}", flush=True)
+    g.close()
+    assert dx <= 1e-3
+    for k, v in worst.items():
+        assert v <= 1e-4, k
+    assert Lg["err_flags"] == 0 and Lg["lost"] == 0
+
+
+def test_time_averaged_chemistry_bench_workload(ctx):
+    # the benchmark's leg at its size: 128^3, 64 sources, finite c, K = 3,
+    # its 12 steps (2 untimed and 10 timed)
+    p = W.lognormal_c2(n_steps=12)
+    p.chem_iterations = 3
+    _leg_parity(ctx, p, 12, "128^3 time-averaged K=3")
+
+
+def test_generalized_opacity_bench_workload(ctx):
+    p = W.lognormal_c2(n_steps=12)
+    p.opacity_mode, p.he_chi = 1, 0.08
+    _leg_parity(ctx, p, 12, "128^3 generalized opacity")
