@@ -177,3 +177,17 @@ def test_nearly_ionized_cells_still_stop_packets(ctx):
     _compare(_oracle(p, 1), g, 1e-3, 1e-4, "nearly ionized shell")
     L = g.ledger()
     assert L["escaped"] == 0.0 and L["absorbed_front"] > 0.9 * L["emitted"]
+
+
+def test_graph_replay_equals_stepwise(ctx):
+    # the front counts are cleared by the chemistry kernel, not by a memset,
+    # so the step can be captured and replayed
+    boxes = [_fronts_box(16, 101, n_src=2, bins=2, steps=3), _fronts_box(20, 102, n_src=3, bins=2, steps=3)]
+    alone = [_gpu(ctx, b, 3) for b in boxes]
+    replayed = [frt.solve_from_problem(ctx, b) for b in boxes]
+    frt.batch_run(replayed, [b.dt_s for b in boxes], 3, graph=True)
+    for b, a, r in zip(boxes, alone, replayed):
+        assert np.abs(a.fields()[0] - r.fields()[0]).max() <= 1e-5, b.name
+        La, Lr = a.ledger(), r.ledger()
+        for k in TERMS:
+            assert abs(La[k] - Lr[k]) <= 1e-6 * La["emitted"], (b.name, k)
