@@ -167,6 +167,16 @@ int frt_solve_destroy(frt_solve s);
 int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const float* n_H, const float* T,
                   const float* kappa_sub, const double* x_HI0, int ptr_kind);
 
+/* Replace the absorption-coefficient field between steps, keeping the rest
+ * of the state: kappa [ncell] 1/cm (finite, >= 0), the same layout as
+ * kappa_sub of frt_load_grid.  In the Generalized Opacity Mode this is the
+ * ionized gas's kappa that the caller's opacity model recomputes from the
+ * rates and history (§4.2, Eq. lambda_nu_general); in Standard Mode the
+ * sub-grid kappa, allowed only if the grid was loaded with a kappa field
+ * that has some kappa > 0 (the sub-grid march).  Takes effect at the next
+ * step.  FRT_ESTATE before a grid is loaded. */
+int frt_set_opacity(frt_solve s, const float* kappa, int ptr_kind);
+
 /* Load n_src >= 0 point sources: pos_cm [n_src][3] (x,y,z) inside
  * [0, n*dx] per axis; ndot_bins [n_src][n_bins] photons/s per bin (finite,
  * >= 0).  Requires the grid.  Sizes the ray queues. */

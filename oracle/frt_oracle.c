@@ -544,6 +544,13 @@ orc_state* orc_create(const orc_params* P, const float* nH, const float* kappa, 
     return S;
 }
 
+/* New absorption-coefficient field, the rest of the state kept (the caller's
+ * opacity model between steps, §4.2 Eq. lambda_nu_general). */
+void orc_set_kappa(orc_state* S, const float* kappa)
+{
+    for (long long i = 0; i < S->ncell; i++) S->kappa[i] = kappa[i];
+}
+
 void orc_destroy(orc_state* S)
 {
     if (!S) return;

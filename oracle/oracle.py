@@ -64,6 +64,7 @@ def lib():
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [C.POINTER(Params), C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_destroy.argtypes = [C.c_void_p]
+        L.orc_set_kappa.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_set_sources.argtypes = [C.c_void_p, C.c_int, dp, dp]
         L.orc_step.argtypes = [C.c_void_p, C.c_double, dp, C.c_int]
         L.orc_read.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
@@ -168,6 +169,11 @@ class Oracle:
 
     def __del__(self):
         self.close()
+
+    def set_kappa(self, kappa):
+        self._kap = np.ascontiguousarray(kappa, dtype=np.float32).reshape(-1)
+        assert self._kap.size == self.ncell
+        lib().orc_set_kappa(self.h, self._kap.ctypes.data)
 
     def set_sources(self, pos_cm, ndot_bins):
         pos = np.ascontiguousarray(pos_cm, dtype=np.float64).reshape(-1, 3)

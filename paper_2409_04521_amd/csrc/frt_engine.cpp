@@ -1251,6 +1251,45 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     return FRT_OK;
 }
 
+int frt_set_opacity(frt_solve s, const float* kappa, int kind)
+{
+    if (!s) return fail(FRT_EINVAL, "null solve");
+    if (!s->have_grid) return fail(FRT_ESTATE, "load the grid before its opacity");
+    if (!kappa) return fail(FRT_EINVAL, "null kappa");
+    const bool gen = s->P.opacity_mode == FRT_GENERALIZED;
+    if (!gen && !s->h.has_sub)
+        return fail(FRT_EINVAL, "the grid was loaded without sub-grid opacity (its march has no kappa term)");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    const size_t n = s->ncell;
+    std::vector<float> bk;
+    const float* hk = nullptr;
+    RCCHK(host_view(kappa, n, kind, bk, &hk));
+    RCCHK(check_inputs_finite(hk, n, "kappa"));
+    for (size_t i = 0; i < n; i++)
+        if (hk[i] < 0.f) return fail(FRT_EINVAL, "kappa[%zu] < 0", i);
+    // the kappa half of the opacity pair: the first in the Generalized
+    // Opacity Mode (floored like the HI opacity), else the second
+    char* dst = (char*)s->op + (gen ? 0 : n * s->rs);
+    const double floor_a = s->fp64 ? 1e-300 : 1e-30;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    if (s->fp64) {
+        std::vector<double> v(n);
+        for (size_t i = 0; i < n; i++) {
+            v[i] = (double)hk[i] * s->dx;
+            if (gen) v[i] = std::max(v[i], floor_a);
+        }
+        RCCHK(scopy(s, dst, v.data(), n * 8, hipMemcpyHostToDevice));
+    } else {
+        std::vector<float> v(n);
+        for (size_t i = 0; i < n; i++) {
+            v[i] = (float)((double)hk[i] * s->dx);
+            if (gen) v[i] = std::max(v[i], (float)floor_a);
+        }
+        RCCHK(scopy(s, dst, v.data(), n * 4, hipMemcpyHostToDevice));
+    }
+    return FRT_OK;
+}
+
 int frt_load_sources(frt_solve s, int n_src, const double* pos_cm, const double* ndot, int kind)
 {
     if (!s) return fail(FRT_EINVAL, "null solve");

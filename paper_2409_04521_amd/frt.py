@@ -23,7 +23,7 @@ MAX_BINS = 8
 
 # Symbols declared in include/frt.h.
 EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_error", "frt_solve_create",
-           "frt_solve_destroy", "frt_load_grid", "frt_load_sources", "frt_set_rotations", "frt_step",
+           "frt_solve_destroy", "frt_load_grid", "frt_set_opacity", "frt_load_sources", "frt_set_rotations", "frt_step",
            "frt_batch_step", "frt_sync", "frt_read_fields", "frt_read_ledger", "frt_save_state",
            "frt_load_state", "frt_mark", "frt_rewind", "frt_set_timing", "frt_read_timing",
            "frt_rotation_uniforms", "frt_batch_run", "frt_tuning_default", "frt_ctx_set_tuning",
@@ -115,6 +115,7 @@ def lib():
         L.frt_solve_destroy.argtypes = [vp]
         L.frt_load_grid.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, vp, vp, vp, C.c_int]
         L.frt_load_sources.argtypes = [vp, C.c_int, vp, vp, C.c_int]
+        L.frt_set_opacity.argtypes = [vp, vp, C.c_int]
         L.frt_set_rotations.argtypes = [vp, C.c_int, vp]
         L.frt_step.argtypes = [vp, C.c_double]
         L.frt_batch_step.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_double)]
@@ -264,6 +265,10 @@ class Solve:
         pt, _, k4 = _ptr(T)
         _check(lib().frt_load_grid(self.h, nx, ny, nz, box_cm, pn, pt, pk, px, kind))
         self.shape = shape
+
+    def set_opacity(self, kappa):
+        pk, kind, k = _ptr(kappa)
+        _check(lib().frt_set_opacity(self.h, pk, kind))
 
     def load_sources(self, pos_cm, ndot_bins):
         pos = np.ascontiguousarray(pos_cm, dtype=np.float64).reshape(-1, 3) if isinstance(pos_cm, np.ndarray) else pos_cm

@@ -77,6 +77,7 @@ def test_binding_marshals_every_call(monkeypatch):
     p = W.lognormal_c2(n=8, n_src=3, n_steps=2, box_cmpc_h=1.25)
     ctx = frt.Context(0)
     s = frt.solve_from_problem(ctx, p)
+    s.set_opacity(p.kappa)
     s.step(p.dt_s)
     frt.batch_step([s], [p.dt_s])
     frt.batch_run([s], [p.dt_s], 2, graph=True)
@@ -95,7 +96,8 @@ def test_binding_marshals_every_call(monkeypatch):
     s.fields()
     s.ledger()
     s.load(b"x" * 16)
-    for name in ("frt_ctx_create", "frt_solve_create", "frt_load_grid", "frt_load_sources", "frt_set_rotations",
+    for name in ("frt_ctx_create", "frt_solve_create", "frt_load_grid", "frt_set_opacity", "frt_load_sources",
+                 "frt_set_rotations",
                  "frt_step", "frt_batch_step", "frt_sync", "frt_read_fields", "frt_read_ledger", "frt_load_state",
                  "frt_batch_run", "frt_autotune", "frt_ctx_set_tuning", "frt_ctx_get_tuning",
                  "frt_server_create", "frt_server_submit", "frt_server_poll", "frt_server_wait", "frt_server_take",

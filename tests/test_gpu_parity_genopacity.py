@@ -191,3 +191,32 @@ def test_graph_replay_equals_stepwise(ctx):
         La, Lr = a.ledger(), r.ledger()
         for k in TERMS:
             assert abs(La[k] - Lr[k]) <= 1e-6 * La["emitted"], (b.name, k)
+
+
+def test_opacity_updated_between_steps(ctx):
+    # the caller's opacity model changes kappa between steps (§4.2, Eq.
+    # lambda_nu_general): the library and the oracle take the same new field
+    p = _fronts_box(20, 111, n_src=3, bins=2, steps=4)
+    rng = np.random.Generator(np.random.PCG64(112))
+    new_kap = [(p.kappa * rng.uniform(0.3, 3.0, size=p.shape)).astype(np.float32) for _ in range(3)]
+    g = frt.solve_from_problem(ctx, p)
+    o = O.Oracle(**p.oracle_kwargs())
+    o.set_sources(p.src_pos_cm, p.ndot_bins)
+    for s in range(4):
+        if s > 0:
+            g.set_opacity(new_kap[s - 1])
+            o.set_kappa(new_kap[s - 1])
+        g.step(p.dt_s)
+        o.step(p.dt_s, p.uniforms(s))
+    _compare(o, g, 1e-3, 1e-4, "kappa updated between steps")
+    # and the update matters: the same steps without it end elsewhere
+    h = _gpu(ctx, p, 4)
+    assert np.abs(h.fields()[0] - g.fields()[0]).max() > 1e-3
+
+
+def test_opacity_update_needs_a_kappa_term(ctx):
+    p = W.stromgren_c1(n=8, n_steps=1)      # Standard Mode without sub-grid opacity
+    g = frt.solve_from_problem(ctx, p)
+    with pytest.raises(frt.FrtError) as e:
+        g.set_opacity(np.ones(p.shape, np.float32))
+    assert e.value.code == frt.FRT_EINVAL
