@@ -238,3 +238,22 @@ def test_invalid_inputs_are_rejected(ctx):
     with pytest.raises(frt.FrtError) as e:
         s.step(1e13)
     assert e.value.code == frt.FRT_ESTATE
+
+
+def test_many_splits_per_step_at_finite_c(ctx):
+    # N_min = 16: split radius 0.24 * 2^l cells, so a packet cast this step
+    # splits six times within its 13-cell travel; the pass count bounded by
+    # the split radii one step's travel can cross must still finish the step
+    rng = np.random.Generator(np.random.PCG64(123))
+    n = 24
+    dx = W.cmpc_h_to_cm(0.15625)
+    nH = W.lognormal_white(rng, (n, n, n), 2e-4, 0.7).astype(np.float32)
+    pos = (rng.integers(2, n - 2, size=(3, 3)) + 0.5) * dx
+    w, sig = W.blackbody_bins(2)
+    ndot = np.array([3e52, 1e52, 5e51])[:, None] * w[None, :]
+    p = W.Problem(name="many splits", shape=(n, n, n), dx_cm=dx, n_H=nH, x_HI0=np.full((n, n, n), 1e-3), kappa=None,
+                  src_pos_cm=pos, ndot_bins=ndot, sigma_bins=sig, dt_s=W.MYR, n_steps=3, c_ray=W.C_LIGHT,
+                  flux_floor=1e-3, max_level=9, n_ray_min=16.0, seed=124)
+    g = _gpu(ctx, p, 3)
+    assert g.ledger()["splits"] > 0
+    _compare(_oracle(p, 3), g, 1e-3, 1e-4, "N_min 16 finite c")
