@@ -1863,17 +1863,18 @@ __global__ void __launch_bounds__(BLOCK) k_prep(FrtSolveDesc* desc, unsigned lon
     }
 }
 
-int g_cu_count = 0;
-
+// Compute units of the current device, queried once (the server's loader
+// threads may ask for it at the same time: a function-local static is
+// initialized exactly once)
 int cu_count()
 {
-    if (g_cu_count == 0) {
-        int dev = 0;
+    static const int n = [] {
+        int dev = 0, c = 0;
         (void)hipGetDevice(&dev);
-        (void)hipDeviceGetAttribute(&g_cu_count, hipDeviceAttributeMultiprocessorCount, dev);
-        if (g_cu_count <= 0) g_cu_count = 256;
-    }
-    return g_cu_count;
+        (void)hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev);
+        return c > 0 ? c : 256;
+    }();
+    return n;
 }
 
 int grid_for(unsigned long long items, int per_cu)
