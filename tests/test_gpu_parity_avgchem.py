@@ -147,3 +147,20 @@ def test_served_mix_of_chemistries_equals_alone(ctx):
         assert np.abs(xa - xb).max() <= 1e-5, p.name
         for k in TERMS:
             assert abs(La[k] - Lb[k]) <= 1e-6 * La["emitted"], (p.name, k)
+
+
+def test_no_sources_is_pure_recombination_at_the_largest_k(ctx):
+    # Gamma = 0 everywhere: every march deposits nothing and x relaxes by
+    # recombination alone, the same on both sides; K at its maximum
+    p = W.stromgren_c1(n=8, n_steps=3)
+    p.src_pos_cm = p.src_pos_cm[:0]
+    p.ndot_bins = p.ndot_bins[:0]
+    p.x_HI0 = np.full(p.shape, 0.2)
+    p.chem_iterations = 64
+    g = _gpu(ctx, p, 3, precision="f64")
+    o = O.Oracle(**p.oracle_kwargs())
+    for s in range(3):
+        o.step(p.dt_s, np.zeros(0))
+    xg, xo = g.fields()[0], o.fields()[0]
+    assert np.abs(xg - xo).max() <= 1e-12
+    assert np.all(xg > 0.2)                       # recombination raised x_HI

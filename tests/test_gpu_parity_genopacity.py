@@ -220,3 +220,26 @@ def test_opacity_update_needs_a_kappa_term(ctx):
     with pytest.raises(frt.FrtError) as e:
         g.set_opacity(np.ones(p.shape, np.float32))
     assert e.value.code == frt.FRT_EINVAL
+
+
+def test_no_sources_and_empty_cells(ctx):
+    # without photons the screen stays put, except in cells without
+    # hydrogen, which count as ionized from the first step (the same reading
+    # on both sides)
+    n = 12
+    rng = np.random.Generator(np.random.PCG64(131))
+    nH = W.lognormal_white(rng, (n, n, n), 2e-4, 1.0).astype(np.float32)
+    nH[rng.uniform(size=nH.shape) < 0.05] = 0.0
+    xi0 = rng.uniform(size=(n, n, n))
+    p = W.Problem(name="dark", shape=(n, n, n), dx_cm=DX, n_H=nH, x_HI0=1.0 - xi0,
+                  kappa=np.full((n, n, n), 0.1 / DX, np.float32), src_pos_cm=np.zeros((0, 3)),
+                  ndot_bins=np.zeros((0, 1)), sigma_bins=np.array([6.3e-18]), dt_s=W.MYR, n_steps=2,
+                  c_ray=W.C_LIGHT, seed=7, opacity_mode=1)
+    g = _gpu(ctx, p, 2)
+    o = O.Oracle(**p.oracle_kwargs())
+    for s in range(2):
+        o.step(p.dt_s, np.zeros(0))
+    xg, xo = g.fields()[0], o.fields()[0]
+    assert np.array_equal(xg, xo)
+    assert np.abs(xg[nH > 0] - (1.0 - xi0)[nH > 0]).max() <= 1e-15
+    assert np.all(xg[nH == 0] == 0.0)
