@@ -148,6 +148,7 @@ def avgchem_leg(frt, W, K: int, steps: int, warmup: int, stream):
             chem_bytes = prob.ncell * (28 + 44 * k)
             out["avg_chem_bytes_per_step"] = chem_bytes
             out["avg_chem_GBps"] = chem_bytes / (tm["chem_ms"] / steps * 1e-3) / 1e9
+            out["avg_chem_hbm_frac"] = out["avg_chem_GBps"] / HBM_PEAK_GBS
         L = s.ledger()
         out[f"{tag}_ledger_closure"] = abs(L["emitted"] - L["absorbed_HI"] - L["absorbed_sub"] - L["escaped"]
                                            - L["dropped"] - L["in_flight"] - L["lost"]) / L["emitted"]
@@ -198,6 +199,7 @@ def genopacity_leg(frt, W, steps: int, warmup: int, stream):
                                f"all cells neutral at the start, ionized-gas kappa from the sub-grid recipe, chi 0.08")
             out["front_share_of_emitted"] = (L["absorbed_front"] - L0["absorbed_front"]) / (L["emitted"] - L0["emitted"])
             out["chem_GBps"] = prob.ncell * 48 / (tm["chem_ms"] / steps * 1e-3) / 1e9
+            out["chem_hbm_frac"] = out["chem_GBps"] / HBM_PEAK_GBS
             out["mean_x_ion"] = float(1.0 - s.fields()[0].mean())
         out[f"{tag}_ms_per_step"] = ms
         out[f"{tag}_crossings_per_s"] = (L["crossings"] - L0["crossings"]) / (ms * steps * 1e-3)
