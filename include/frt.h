@@ -35,8 +35,9 @@
  *     context's HIP device.  Inputs are always copied into buffers the
  *     library owns; the caller keeps ownership of its arrays.
  *   - Work is enqueued on the solve's HIP stream (the one given at
- *     creation, else a stream the library creates).  Device-side failures
- *     (queue overflow) surface at the next frt_sync / frt_read_* call.
+ *     creation, else a stream the library creates).  Steps wait for their
+ *     own end and report a queue overflow themselves; frt_sync reports any
+ *     other device error bit left behind.
  *   - A solve handle is not thread-safe; different solves may be driven from
  *     different threads.
  */
@@ -142,8 +143,22 @@ typedef struct {
  * backward-Euler chemistry (chem_iterations 0), FRT_STANDARD opacity, he_chi 0. */
 int frt_params_default(frt_params* p);
 
-/* Context bound to HIP device `hip_device`.  Owns nothing else. */
-int frt_ctx_create(int hip_device, frt_ctx* out);
+/* Device memory hooks: alloc returns `bytes` of device memory of the
+ * context's device (NULL on failure, which the calling function reports as
+ * FRT_ENOMEM); free gives a block back.  They let a caller route the
+ * library's device memory through its own allocator (PyTorch's caching
+ * allocator, say); the library frees a block only after the work using it
+ * has finished on the device.  Either may be called from any thread that
+ * calls into the library, including the server's worker and loader threads. */
+typedef void* (*frt_alloc_fn)(size_t bytes, void* user);
+typedef void (*frt_free_fn)(void* ptr, void* user);
+
+/* Context bound to HIP device `hip_device`: the pass queues shared by the
+ * solves stepped on it, its launch shape, and its device memory hooks
+ * (alloc_fn and free_fn both NULL: hipMalloc / hipFree; giving only one is
+ * FRT_EINVAL).  Every device buffer of the context and of its solves comes
+ * from the hooks; `user` is passed to them. */
+int frt_ctx_create(int hip_device, frt_alloc_fn alloc_fn, frt_free_fn free_fn, void* user, frt_ctx* out);
 int frt_ctx_destroy(frt_ctx ctx);
 
 /* Message of the calling thread's last failing call ("" if none). */
@@ -190,12 +205,28 @@ int frt_load_sources(frt_solve s, int n_src, const double* pos_cm, const double*
  * sqrt(u0) sin 2pi u2) rotates the source's sphere (Shoemake 1992). */
 int frt_set_rotations(frt_solve s, int n_steps, const double* uniforms);
 
-/* Enqueue one step of length dt_s > 0.  With automatic queues the call
- * waits for the step and re-runs it with larger queues if it overflowed. */
+/* One step of length dt_s > 0: the time step of §3.1 (packets travel
+ * c_ray dt_s, i.e. one cell per step when dt = dx / c_ray as in the paper),
+ * in the order of the method: casting (§3.1, Eq. Nray), the march with
+ * attenuation, deposition, splitting and termination (§3.1-§3.2, §4.1 Eqs.
+ * tau_cell, gamma_initial_standard, r_split, lhpx), then the hydrogen
+ * update of the chosen form (Eq. ion_balance_eqn by backward Euler, or
+ * Eqs. xi_of_t-gamma_updated_standard) and the ledger.  Every packet of the
+ * step sees the opacity of the start of the step.  The call waits for the
+ * step (it reads the queue counters back).  With automatic queues a step
+ * that overflowed is re-run with larger queues; with a fixed queue_capacity
+ * the call returns FRT_EOVERFLOW and the solve is left exactly at the start
+ * of the step (fields, carried packets, ledger, step index), so stepping may
+ * go on with other parameters.  FRT_ESTATE before grid and sources are
+ * loaded. */
 int frt_step(frt_solve s, double dt_s);
 
-/* Enqueue one step of each of n solves as one set of launches (the solves
- * must share n_bins and march_precision).  dt_s[i] is solve i's step. */
+/* One step (as frt_step) of each of n solves as one set of launches: the
+ * solves' bricks share one pass queue and one march launch per pass, so a
+ * batch of small boxes fills the GPU as one large box does.  The solves must
+ * share a context, n_bins, march_precision and queue mode (all automatic or
+ * all fixed); dt_s[i] is solve i's step.  A failed batch leaves every solve
+ * at the start of the step.  Waits for the step. */
 int frt_batch_step(frt_solve* solves, int n, const double* dt_s);
 
 /* n_steps steps of each of n solves (as n_steps calls of frt_batch_step).
@@ -217,12 +248,9 @@ typedef struct {
                                        opacity) takes 8 times as many */
     int scatter_blocks_per_cu;      /* workgroups per CU of the pass that sorts the
                                        queue by brick (queue chunking), 1..16 */
-    int split_blocks_per_cu;        /* 1..16; validated and kept, but unused: the
-                                       march writes the split children itself */
 } frt_tuning;
 
-/* Defaults: 1024 packets per item, 8 scatter workgroups per CU (and 4 in
- * the unused split field). */
+/* Defaults: 1024 packets per item, 8 scatter workgroups per CU. */
 int frt_tuning_default(frt_tuning* t);
 int frt_ctx_set_tuning(frt_ctx ctx, const frt_tuning* t);
 int frt_ctx_get_tuning(frt_ctx ctx, frt_tuning* t);
@@ -236,11 +264,18 @@ int frt_ctx_get_tuning(frt_ctx ctx, frt_tuning* t);
  * step index, last rate field), so the call changes no result. */
 int frt_autotune(frt_solve* solves, int n, const double* dt_s, frt_tuning* best);
 
-/* Wait for the solve's stream; report deferred device errors. */
+/* Wait for the solve's stream (work enqueued by frt_rewind, loads and
+ * reads); report device error bits left in the ledger: FRT_EDEVICE if a
+ * step left packets after its last pass (never expected). */
 int frt_sync(frt_solve s);
 
-/* Copy out x_HI [ncell] (double) and the last step's photo-ionization rate
- * gamma [ncell] (float, 1/s).  Either pointer may be NULL.  Synchronizes. */
+/* Copy out the fields the problem statement asks for (§4.1): the neutral
+ * fraction x_HI [ncell] (double; in the Generalized Opacity Mode 1 minus the
+ * ionized volume fraction of §4.2) and the photo-ionization rate of the last
+ * step, gamma [ncell] (float, 1/s; Eq. gamma_initial_standard, or Eq.
+ * gamma_avg_subgrid with sub-grid opacity; zero before the first step).
+ * Either pointer may be NULL; ptr_kind says where both point.  Synchronizes
+ * and returns any error frt_sync would. */
 int frt_read_fields(frt_solve s, double* x_HI, float* gamma, int ptr_kind);
 
 /* Copy out the ledger.  Synchronizes. */
@@ -315,8 +350,13 @@ typedef struct {
  * size.  Host-side arithmetic only; the same estimate the server admits by. */
 int frt_request_bytes(const frt_request* req, size_t* bytes);
 
-/* hbm_budget_bytes: device bytes the admitted requests may hold together
- * (a request larger than the budget fails at admission); max_slots: most
+/* hbm_budget_bytes: device bytes the admitted requests may hold together:
+ * their own buffers plus the context's shared pass queues, which the server
+ * lets grow only up to what the budget leaves (a step needing more fails with
+ * FRT_ENOMEM for the solves that need it, the others step on) and gives back
+ * when they block an admission while nothing runs.  The context's fixed
+ * march scratch (2 x 8192 packet records per compute unit) is not counted.
+ * A request larger than the budget fails at admission.  max_slots: most
  * requests in flight, 1..1024.  A loader thread uploads admitted requests,
  * each solve on a HIP stream of its own, while the worker thread steps the
  * others; the solves use ctx's pass queues, which grow as the batches need. */
@@ -355,6 +395,23 @@ int frt_server_get_stats(frt_server srv, frt_server_stats* out);
 /* Stop the worker (requests still queued or running are dropped) and free
  * everything the server holds. */
 int frt_server_destroy(frt_server srv);
+
+/* One ray through the solve's current opacity, for checking the march
+ * against exact transmission (§4.1 Eq. tau_cell: a segment ds of cell i
+ * passes exp(-(n_HI sigma_nu + kappa) ds) of its photons) and the deposits
+ * of Eq. gamma_initial_standard / gamma_avg_subgrid.  The packet starts at
+ * o_cm (cm, inside the box) on the unit direction d (normalized here) with
+ * N_bins[n_bins] photons (>= 0), and is marched by the same kernels as a
+ * step (seeding, brick passes, ledger) at level 12, so it never splits; it
+ * has no flux floor, distance cap or travel budget and ends when it leaves
+ * the box.  Outputs: gamma_out [ncell] (float, 1/s, may be NULL; ptr_kind
+ * says where it points) the rate it deposits for a step of dt_s seconds,
+ * *absorbed and *escaped its photons absorbed in the box and leaving it,
+ * *crossings the cells it crossed with ds > 0.  The solve's state (fields,
+ * packets, ledger, step) is not changed.  FRT_ESTATE before a grid is
+ * loaded; FRT_EINVAL for an origin outside the box or a zero direction. */
+int frt_debug_cast(frt_solve s, const double o_cm[3], const double d[3], const double* N_bins, double dt_s,
+                   float* gamma_out, int ptr_kind, double* absorbed, double* escaped, uint64_t* crossings);
 
 /* Rotation uniforms the library would use for (step, src) — the same
  * counter-based generator the device runs — for checking a table against. */

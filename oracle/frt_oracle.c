@@ -812,6 +812,25 @@ void orc_read(const orc_state* S, double* x, double* gamma)
     if (gamma) memcpy(gamma, S->gamma, sizeof(double) * S->ncell);
 }
 
+/* Distances from their sources (cm) of the packets carried into the next
+ * step, in source order; returns how many there are (at most cap written). */
+long long orc_flight_radii(const orc_state* S, double* out, long long cap)
+{
+    long long k = 0;
+    for (int s = 0; s < S->nsrc; s++)
+        for (long long j = 0; j < S->flight[s].n; j++, k++)
+            if (k < cap) out[k] = S->flight[s].v[j].r;
+    return k;
+}
+
+/* Backward-Euler update of a whole field (chemistry_be per cell): x_out[i]
+ * from x[i], gamma[i], nH[i]. */
+void orc_chemistry_field(long long n, const double* x, const double* gamma, const double* nH, double alpha,
+                         double coll, double dt, double* x_out)
+{
+    for (long long i = 0; i < n; i++) x_out[i] = chemistry_be(x[i], gamma[i], nH[i], alpha, coll, dt);
+}
+
 void orc_ledger_get(const orc_state* S, orc_ledger* L) { *L = S->L; }
 long long orc_last_crossings(const orc_state* S) { return S->last_crossings; }
 long long orc_step_index(const orc_state* S) { return S->step; }

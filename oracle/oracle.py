@@ -85,6 +85,9 @@ def lib():
         L.chemistry_be.argtypes = [C.c_double] * 6
         L.chemistry_avg.restype = C.c_double
         L.chemistry_avg.argtypes = [C.c_double] * 6 + [C.POINTER(C.c_double)]
+        L.orc_flight_radii.restype = C.c_longlong
+        L.orc_flight_radii.argtypes = [C.c_void_p, C.c_void_p, C.c_longlong]
+        L.orc_chemistry_field.argtypes = [C.c_longlong, dp, dp, dp, C.c_double, C.c_double, C.c_double, dp]
         L.orc_debug_transmit.restype = C.c_int
         L.orc_debug_transmit.argtypes = [C.c_void_p, dp, dp, dp, C.c_double, dp, dp]
         _lib = L
@@ -119,6 +122,16 @@ def split_radius(dx: float, level: int, n_ray_min: float) -> float:
 
 def chemistry(x, gamma, nH, alpha, coll, dt) -> float:
     return float(lib().chemistry_be(x, gamma, nH, alpha, coll, dt))
+
+
+def chemistry_field(x, gamma, nH, alpha, coll, dt) -> np.ndarray:
+    """Backward-Euler update of whole fields (arrays of one shape)."""
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    g = np.ascontiguousarray(gamma, dtype=np.float64).reshape(x.shape)
+    n = np.ascontiguousarray(nH, dtype=np.float64).reshape(x.shape)
+    out = np.empty_like(x)
+    lib().orc_chemistry_field(x.size, x.reshape(-1), g.reshape(-1), n.reshape(-1), alpha, coll, dt, out.reshape(-1))
+    return out
 
 
 def chemistry_avg(x0, gamma, ne, alpha, coll, dt):
@@ -200,6 +213,14 @@ class Oracle:
         L = Ledger()
         lib().orc_ledger_get(self.h, C.byref(L))
         return L.as_dict()
+
+    def flight_radii(self) -> np.ndarray:
+        """Distances from their sources (cm) of the packets carried into the
+        next step."""
+        n = int(lib().orc_flight_radii(self.h, None, 0))
+        out = np.empty(max(n, 1))
+        lib().orc_flight_radii(self.h, out.ctypes.data, n)
+        return out[:n]
 
     def last_crossings(self) -> int:
         return int(lib().orc_last_crossings(self.h))

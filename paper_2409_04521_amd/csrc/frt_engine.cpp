@@ -13,8 +13,10 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 namespace {
@@ -54,10 +56,40 @@ uint64_t mix64_host(uint64_t x)
 
 constexpr double PI = 3.14159265358979323846;
 
+// Device memory comes from the allocator hooks of the context a library
+// call works on (frt_ctx_create), else from hipMalloc.  Each entry point
+// that allocates names its context with an AllocScope for the calling
+// thread; every block remembers the hooks that gave it, so it goes back to
+// them whichever call frees it.
+struct Allocator {
+    frt_alloc_fn alloc = nullptr;
+    frt_free_fn release = nullptr;
+    void* user = nullptr;
+};
+
+thread_local const Allocator* t_alloc = nullptr;
+
+struct AllocScope {
+    const Allocator* prev;
+    explicit AllocScope(const Allocator* a) : prev(t_alloc) { t_alloc = a; }
+    ~AllocScope() { t_alloc = prev; }
+};
+
+std::mutex g_hooked_mu;
+std::unordered_map<void*, Allocator> g_hooked;   // blocks from allocator hooks
+
 int dev_alloc(void** p, size_t bytes)
 {
     *p = nullptr;
     if (bytes == 0) bytes = 16;
+    if (t_alloc && t_alloc->alloc) {
+        void* q = t_alloc->alloc(bytes, t_alloc->user);
+        if (!q) return fail(FRT_ENOMEM, "the context's allocator returned no memory for %zu bytes", bytes);
+        std::lock_guard<std::mutex> lock(g_hooked_mu);
+        g_hooked[q] = *t_alloc;
+        *p = q;
+        return FRT_OK;
+    }
     hipError_t e = hipMalloc(p, bytes);
     if (e != hipSuccess) {
         *p = nullptr;
@@ -67,15 +99,43 @@ int dev_alloc(void** p, size_t bytes)
     return FRT_OK;
 }
 
+void dev_free_ptr(void* p)
+{
+    if (!p) return;
+    Allocator a;
+    bool hooked = false;
+    {
+        std::lock_guard<std::mutex> lock(g_hooked_mu);
+        auto it = g_hooked.find(p);
+        if (it != g_hooked.end()) {
+            a = it->second;
+            hooked = true;
+            g_hooked.erase(it);
+        }
+    }
+    if (hooked) a.release(p, a.user);
+    else (void)hipFree(p);
+}
+
 template <typename T>
 void dev_free(T*& p)
 {
-    if (p) (void)hipFree((void*)p);
+    dev_free_ptr((void*)p);
     p = nullptr;
 }
 
 // Bytes of one packet record.
 size_t rec_bytes(size_t rs) { return rs == 8 ? sizeof(FrtRec<double>) : sizeof(FrtRec<float>); }
+
+// Device bytes of the pass queues for `records` packets per pass and
+// `nkeys` brick keys (at least 4096 are held): two output buffers with their
+// keys, the sorted index and the work list (items of at least 64 packets,
+// plus one per brick).
+uint64_t pass_queue_bytes(uint64_t records, size_t rs, uint64_t nkeys)
+{
+    return records * (2 * rec_bytes(rs) + 2 * 4 + sizeof(uint2)) +
+           (records / 64 + std::max<uint64_t>(nkeys, 4096) + 64) * sizeof(FrtWork);
+}
 
 void free_recs(FrtRecs& q)
 {
@@ -118,7 +178,7 @@ struct Workspace {
     uint32_t* segc = nullptr;
     uint32_t* segp = nullptr;
     uint32_t* ctr_host = nullptr;   // pinned copy of the counters
-    frt_tuning tune{sizeof(frt_tuning), (int)FRT_ITEM_RAYS, 8, 4};
+    frt_tuning tune{sizeof(frt_tuning), (int)FRT_ITEM_RAYS, 8};
     uint32_t* ctr = nullptr;
     uint32_t* hist = nullptr;
     uint32_t* cursor = nullptr;
@@ -130,6 +190,16 @@ struct Workspace {
     unsigned long long* cell_prefix = nullptr;
     FrtSolveDesc* descs = nullptr;
     int solves_cap = 0;
+    uint64_t limit = 0;             // most device bytes the workspace may hold (0: no limit)
+
+    // device bytes of the pass queues (the part that grows with the largest
+    // pass; the march scratch and the small tables are a fixed cost)
+    uint64_t bytes() const
+    {
+        if (fp64 < 0) return 0;
+        const size_t rs = fp64 ? 8 : 4;
+        return (uint64_t)pcap * (2 * rec_bytes(rs) + 2 * 4 + sizeof(uint2)) + (uint64_t)cap_work * sizeof(FrtWork);
+    }
 
     void free_pass()
     {
@@ -158,8 +228,13 @@ struct Workspace {
 struct frt_ctx_s {
     int device = 0;
     std::mutex mu;
+    Allocator al;                   // device memory hooks (none: hipMalloc / hipFree)
     Workspace ws;
-    ~frt_ctx_s() { ws.release(); }
+    ~frt_ctx_s()
+    {
+        AllocScope scope(&al);
+        ws.release();
+    }
 };
 
 struct frt_solve_s {
@@ -309,7 +384,7 @@ int ensure_quat(frt_solve s, uint32_t step)
         HIPCHK(hipMemcpyAsync(nq, s->quat, (size_t)s->quat_steps * s->n_src * 4 * sizeof(double), hipMemcpyDeviceToDevice,
                               s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
-        (void)hipFree(s->quat);
+        dev_free(s->quat);
     }
     s->quat = nq;
     s->quat_steps = nsteps;
@@ -412,6 +487,14 @@ int ensure_ws(Workspace& ws, int fp64, int nb, int n, uint32_t nkeys, uint64_t w
     }
     want_p = std::min<uint64_t>(want_p, 2147483647ull);
     if (ws.pcap < want_p) {
+        if (ws.limit) {
+            const uint64_t nk = std::max<uint64_t>(ws.nkeys_cap, std::max<uint32_t>(nkeys, 4096));
+            const uint64_t grown = want_p * (2 * rec_bytes(rs) + 2 * 4 + sizeof(uint2)) +
+                                   (want_p / (uint64_t)ws.tune.item_rays + nk + 64) * sizeof(FrtWork);
+            if (grown > ws.limit)
+                return fail(FRT_ENOMEM, "pass queues of %llu records need %llu bytes, more than the %llu the context allows",
+                            (unsigned long long)want_p, (unsigned long long)grown, (unsigned long long)ws.limit);
+        }
         ws.free_pass();
         for (int k = 0; k < 2; k++) {
             RCCHK(alloc_recs(ws.O[k], (uint32_t)want_p, nb, rs));
@@ -537,7 +620,6 @@ void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
     // FRT_BIG_ITEM_SCALE times the tuned item size
     w.item_rays = (uint32_t)ws.tune.item_rays * ((!ss[0]->fp64 && !w.has_sub) ? FRT_BIG_ITEM_SCALE : 1u);
     w.scatter_bpc = ws.tune.scatter_blocks_per_cu;
-    w.split_bpc = ws.tune.split_blocks_per_cu;
     if (ss[0]->P.queue_capacity) {
         // fixed capacities: the shared workspace is used up to the solves' limit
         uint64_t lim = 0;
@@ -647,9 +729,26 @@ int group_sizes(frt_solve* ss, int n, uint32_t* nkeys, uint64_t* want_p)
     return FRT_OK;
 }
 
+// Put every solve of a step that overflowed back to the start of that step:
+// ledger (with its error bits), carried-packet counts, this step's rate
+// buffer and front counts.  The chemistry of an overflowed step does not run
+// (its kernels skip a solve whose ledger has error bits), so the neutral
+// fraction is already the one of the start of the step.
+int restore_step_start(frt_solve* ss, int n, hipStream_t st)
+{
+    for (int i = 0; i < n; i++) {
+        frt_solve s = ss[i];
+        HIPCHK(hipMemcpyAsync(s->L, s->L_snap, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(s->fcount, s->fcount_snap, 8, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemsetAsync(s->gam[s->step & 1u], 0, s->ncell * s->rs, st));
+        if (s->front) HIPCHK(hipMemsetAsync(s->front, 0, s->ncell * 8, st));
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return FRT_OK;
+}
+
 // After a step that overflowed: put every solve back to the start of the
-// step (ledger, carried count, this step's rate buffer; the chemistry of an
-// overflowed step does not run) and enlarge what overflowed.
+// step and enlarge what overflowed.
 int recover_overflow(Workspace& ws, frt_solve* ss, int n, const uint32_t* ctr, uint64_t* want_p, hipStream_t st)
 {
     // packets each solve tried to carry into the next step (the counter
@@ -664,15 +763,9 @@ int recover_overflow(Workspace& ws, frt_solve* ss, int n, const uint32_t* ctr, u
             if (nxt > ss[i]->F[0].cap) fneed[i] = nxt;
         }
     }
-    for (int i = 0; i < n; i++) {
-        frt_solve s = ss[i];
-        if (s->timing) s->reset_timing();
-        HIPCHK(hipMemcpyAsync(s->L, s->L_snap, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(s->fcount, s->fcount_snap, 8, hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemsetAsync(s->gam[s->step & 1u], 0, s->ncell * s->rs, st));
-        if (s->front) HIPCHK(hipMemsetAsync(s->front, 0, s->ncell * 8, st));
-    }
-    HIPCHK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; i++)
+        if (ss[i]->timing) ss[i]->reset_timing();
+    RCCHK(restore_step_start(ss, n, st));
     if (ctr[C_ERR] & FRT_DEVERR_QUEUE_OVERFLOW) {
         if (ws.pcap >= 2147483647u) return fail(FRT_EOVERFLOW, "pass buffers at their maximum size still overflow");
         const uint64_t need = std::max<uint64_t>(2ull * ws.pcap, (uint64_t)ctr[C_MAXP] + (ctr[C_MAXP] >> 2) + 65536);
@@ -767,12 +860,14 @@ int step_group_locked(frt_solve* ss, int n, const double* dts)
         plan_group(ws, ss, n, g);
         RCCHK(upload_group(ws, g, n, st));
         RCCHK(enqueue_step(ws, ss, n, g, st, false));
-        if (!auto_grow) {
-            for (int i = 0; i < n; i++) ss[i]->step++;
-            return FRT_OK;
-        }
         uint32_t ctr[C_NCTR];
         RCCHK(read_counters(ws, st, ctr));
+        if (!auto_grow && (ctr[C_ERR] & (FRT_DEVERR_QUEUE_OVERFLOW | FRT_DEVERR_CARRY_OVERFLOW))) {
+            // fixed capacities: the step is not applied
+            RCCHK(restore_step_start(ss, n, st));
+            return fail(FRT_EOVERFLOW, "a ray queue overflowed at step %u; raise queue_capacity (the step was not applied)",
+                        ss[0]->step);
+        }
         if (!(ctr[C_ERR] & (FRT_DEVERR_QUEUE_OVERFLOW | FRT_DEVERR_CARRY_OVERFLOW))) {
             if (ctr[C_ERR] & FRT_DEVERR_UNFINISHED) return fail(FRT_EDEVICE, "a step left packets after its last pass");
             for (int i = 0; i < n; i++) ss[i]->step++;
@@ -855,14 +950,14 @@ int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps)
         if (ctr[C_ERR] & (FRT_DEVERR_QUEUE_OVERFLOW | FRT_DEVERR_CARRY_OVERFLOW)) {
             if (!auto_grow) {
                 // fixed capacities: the step is not applied
+                RCCHK(restore_step_start(ss, n, st));
                 for (int i = 0; i < n; i++) {
-                    HIPCHK(hipMemcpyAsync(ss[i]->L, ss[i]->L_snap, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, st));
-                    HIPCHK(hipMemcpyAsync(ss[i]->fcount, ss[i]->fcount_snap, 8, hipMemcpyDeviceToDevice, st));
-                    HIPCHK(hipMemsetAsync(ss[i]->gam[ss[i]->step & 1u], 0, ss[i]->ncell * ss[i]->rs, st));
-                    if (ss[i]->front) HIPCHK(hipMemsetAsync(ss[i]->front, 0, ss[i]->ncell * 8, st));
+                    ss[i]->h.step = ss[i]->step;
+                    ss[i]->h.cur = ss[i]->step & 1u;
+                    RCCHK(upload_desc(ss[i]));
                 }
-                HIPCHK(hipStreamSynchronize(st));
-                return fail(FRT_EOVERFLOW, "a ray queue overflowed at step %u; raise queue_capacity", ss[0]->step);
+                return fail(FRT_EOVERFLOW, "a ray queue overflowed at step %u; raise queue_capacity (the step was not applied)",
+                            ss[0]->step);
             }
             if (++retries > 16) return fail(FRT_EOVERFLOW, "step kept overflowing its queues");
             RCCHK(recover_overflow(ws, ss, n, ctr, &want_p, st));
@@ -958,14 +1053,194 @@ int check_batch(frt_solve* ss, int n, const double* dts)
     return FRT_OK;
 }
 
+// One packet marched through a solve's current opacity by the production
+// kernels (seeding of a carried packet, the brick passes, the ledger fold),
+// in a solve object of its own: its descriptor, packet queues, ledger and
+// rate buffer are temporary, while the opacity, n_H and x_HI it reads are
+// the solve's (read only: no chemistry runs).  The packet is at level 12 and
+// so never splits; it has no flux floor, distance cap or travel budget.
+// The caller holds the context lock.
+int debug_cast_locked(frt_solve s, const double o_cm[3], const double d_in[3], const double* N, double dt,
+                      float* gamma_out, int kind, double* absorbed, double* escaped, uint64_t* crossings)
+{
+    const int nb = s->P.n_bins;
+    double d[3], nrm = 0;
+    for (int a = 0; a < 3; a++) nrm += d_in[a] * d_in[a];
+    nrm = std::sqrt(nrm);
+    for (int a = 0; a < 3; a++) d[a] = d_in[a] / nrm;
+    double Rref = 0, total = 0;
+    for (int b = 0; b < nb; b++) {
+        Rref = std::max(Rref, N[b]);
+        total += N[b];
+    }
+    if (!(Rref > 0)) Rref = 1.0;
+    // the packet's cell: floor per axis, a point on a face belongs to the
+    // cell being entered (the same rule as the march)
+    int c[3];
+    bool inside = true;
+    const int dims[3] = {s->nx, s->ny, s->nz};
+    for (int a = 0; a < 3; a++) {
+        const double pc = o_cm[a] / s->dx;
+        double f = std::floor(pc);
+        if (pc == f && d[a] < 0) f -= 1.0;
+        inside &= f >= 0 && f < dims[a];
+        c[a] = inside ? (int)f : 0;
+    }
+    *absorbed = 0;
+    *escaped = 0;
+    *crossings = 0;
+    std::unique_ptr<frt_solve_s> t(new (std::nothrow) frt_solve_s);
+    if (!t) return fail(FRT_ENOMEM, "debug cast");
+    t->ctx = s->ctx;
+    t->stream = s->stream;
+    t->own_stream = false;
+    t->P = s->P;
+    t->P.flux_floor = 0.0;
+    t->P.max_distance_cm = 0.0;
+    t->P.c_ray_cm_s = HUGE_VAL;
+    t->P.chem_iterations = 0;
+    t->P.queue_capacity = 0;
+    t->fp64 = s->fp64;
+    t->rs = s->rs;
+    for (int a = 0; a < 3; a++) t->bsh[a] = s->bsh[a];
+    t->have_grid = t->have_src = true;
+    t->nx = s->nx; t->ny = s->ny; t->nz = s->nz;
+    t->bpx = s->bpx; t->bpy = s->bpy; t->bpz = s->bpz;
+    t->dx = s->dx;
+    t->ncell = s->ncell;
+    t->n_src = 1;
+    t->h = s->h;
+    RCCHK(dev_alloc((void**)&t->d_desc, sizeof(FrtSolveDesc)));
+    RCCHK(dev_alloc((void**)&t->fcount, 8));
+    RCCHK(dev_alloc((void**)&t->fcount_snap, 8));
+    RCCHK(dev_alloc((void**)&t->L, sizeof(FrtLedgerDev)));
+    RCCHK(dev_alloc((void**)&t->L_snap, sizeof(FrtLedgerDev)));
+    RCCHK(dev_alloc(&t->gam[0], s->ncell * s->rs));
+    RCCHK(dev_alloc((void**)&t->src_pos, 24));
+    RCCHK(dev_alloc((void**)&t->spec, 4 * nb));
+    RCCHK(dev_alloc((void**)&t->specd, 8 * nb));
+    RCCHK(dev_alloc((void**)&t->quat, 32));
+    RCCHK(alloc_recs(t->F[0], 1, nb, s->rs));
+    RCCHK(alloc_recs(t->F[1], 1, nb, s->rs));
+    if (s->front) RCCHK(dev_alloc((void**)&t->front, s->ncell * 8));
+    const double pos_cells[3] = {o_cm[0] / s->dx, o_cm[1] / s->dx, o_cm[2] / s->dx};
+    std::vector<float> spec(nb);
+    std::vector<double> specd(nb);
+    for (int b = 0; b < nb; b++) {
+        specd[b] = N[b] / Rref;
+        spec[b] = (float)specd[b];
+    }
+    const double q1[4] = {1, 0, 0, 0};
+    RCCHK(scopy(t.get(), t->src_pos, pos_cells, 24, hipMemcpyHostToDevice));
+    RCCHK(scopy(t.get(), t->spec, spec.data(), 4 * nb, hipMemcpyHostToDevice));
+    RCCHK(scopy(t.get(), t->specd, specd.data(), 8 * nb, hipMemcpyHostToDevice));
+    RCCHK(scopy(t.get(), t->quat, q1, 32, hipMemcpyHostToDevice));
+    RCCHK(sset(t.get(), t->gam[0], 0, s->ncell * s->rs));
+    RCCHK(sset(t.get(), t->L, 0, sizeof(FrtLedgerDev)));
+    if (t->front) RCCHK(sset(t.get(), t->front, 0, s->ncell * 8));
+    const uint32_t fc[2] = {inside ? 1u : 0u, 0u};
+    RCCHK(scopy(t.get(), t->fcount, fc, 8, hipMemcpyHostToDevice));
+    if (inside) {
+        const uint32_t key = (uint32_t)((c[0] >> s->bsh[0]) + s->bpx * ((c[1] >> s->bsh[1]) + s->bpy * (c[2] >> s->bsh[2])));
+        const uint32_t cell = (uint32_t)c[0] | ((uint32_t)c[1] << 11) | ((uint32_t)c[2] << 22);
+        if (s->fp64) {
+            FrtRec<double> r{};
+            r.src = 0; r.estep = 0; r.lp = 12u << 28; r.cell = cell; r.key = key;
+            r.r = 0; r.rstop = HUGE_VAL; r.w0 = 1.0;
+            for (int a = 0; a < 3; a++) r.dir[a] = d[a];
+            RCCHK(scopy(t.get(), t->F[0].rec, &r, sizeof(r), hipMemcpyHostToDevice));
+        } else {
+            FrtRec<float> r{};
+            r.src = 0; r.estep = 0; r.lp = 12u << 28; r.cell = cell; r.key = key;
+            r.r = 0.f; r.rstop = HUGE_VALF; r.w0 = 1.f;
+            for (int a = 0; a < 3; a++) r.dir[a] = (float)d[a];
+            RCCHK(scopy(t.get(), t->F[0].rec, &r, sizeof(r), hipMemcpyHostToDevice));
+        }
+    }
+    FrtSolveDesc& h = t->h;
+    h.n_src = 1;
+    h.ncast = 0;                 // nothing is cast: the queue holds the one packet
+    h.floor = 0.f;
+    h.r_cap = HUGE_VAL;
+    h.R_ref = Rref;
+    h.src_pos = t->src_pos;
+    h.spec = t->spec;
+    h.specd = t->specd;
+    h.quat = t->quat;
+    h.quat_steps = 1;
+    h.user_u = nullptr;
+    h.user_steps = 0;
+    h.F[0] = t->F[0];
+    h.F[1] = t->F[1];
+    h.fcount = t->fcount;
+    h.fcount_snap = t->fcount_snap;
+    h.L = t->L;
+    h.L_snap = t->L_snap;
+    h.gamma[0] = t->gam[0];
+    h.gamma[1] = t->gam[0];
+    h.front = t->front;
+    h.xavg = nullptr;
+    t->step = 0;
+    set_step_fields(t.get(), dt);
+    h.budget = HUGE_VAL;
+    // the one packet has weight 1 and photon rates of at most 1 per bin: the
+    // fixed-point deposit scale of the brightest packet is that of this one
+    double kmax = 0.0;
+    for (int b = 0; b < nb; b++) kmax = std::max(kmax, h.Kd[b]);
+    h.dep_scale = (float)(std::ldexp(1.0, 46) / (h.has_sub ? 2.0 * kmax * nb : (double)nb));
+    Workspace& ws = s->ctx->ws;
+    frt_solve one = t.get();
+    uint32_t nkeys = 0;
+    uint64_t want_p = 0;
+    RCCHK(group_sizes(&one, 1, &nkeys, &want_p));
+    RCCHK(ensure_ws(ws, s->fp64, nb, 1, nkeys, std::max<uint64_t>(ws.pcap, 4096)));
+    Group g;
+    plan_group(ws, &one, 1, g);
+    hipStream_t st = s->stream;
+    RCCHK(upload_group(ws, g, 1, st));
+    FrtWS w = g.w;
+    hipError_t e;
+    w.out = 0;
+    if ((e = frt::launch_clear(w, 0, st)) != hipSuccess) return fail(FRT_EDEVICE, "clear: %s", hipGetErrorString(e));
+    if ((e = frt::launch_seed(ws.descs, w, s->fp64, st)) != hipSuccess) return fail(FRT_EDEVICE, "seed: %s", hipGetErrorString(e));
+    for (int p = 0; p < g.passes; p++) {
+        w.out = (p + 1) & 1;
+        for (int part = 0; part < 3; part++)
+            if ((e = frt::launch_pass(ws.descs, w, s->fp64, part, st)) != hipSuccess)
+                return fail(FRT_EDEVICE, "pass: %s", hipGetErrorString(e));
+    }
+    if ((e = frt::launch_finish(ws.descs, w, st)) != hipSuccess) return fail(FRT_EDEVICE, "finish: %s", hipGetErrorString(e));
+    FrtLedgerDev L;
+    RCCHK(read_device_ledger(t.get(), &L));
+    if (L.err_flags) return fail(FRT_EDEVICE, "debug cast raised device error bits 0x%x", L.err_flags);
+    *absorbed = L.absorbed_HI + L.absorbed_sub + L.absorbed_front;
+    *escaped = L.escaped + (inside ? 0.0 : total);
+    *crossings = L.crossings;
+    if (gamma_out) {
+        const size_t n = s->ncell;
+        const hipMemcpyKind k = kind == FRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        if (!s->fp64) {
+            RCCHK(scopy(t.get(), gamma_out, t->gam[0], n * 4, k));
+        } else {
+            std::vector<double> tmp(n);
+            RCCHK(scopy(t.get(), tmp.data(), t->gam[0], n * 8, hipMemcpyDeviceToHost));
+            std::vector<float> f(n);
+            for (size_t i = 0; i < n; i++) f[i] = (float)tmp[i];
+            if (kind == FRT_DEVICE) RCCHK(scopy(t.get(), gamma_out, f.data(), n * 4, hipMemcpyHostToDevice));
+            else std::memcpy(gamma_out, f.data(), n * 4);
+        }
+    }
+    HIPCHK(hipStreamSynchronize(st));
+    return FRT_OK;
+}
+
 int check_tuning(const frt_tuning* t)
 {
     if (!t || t->size != sizeof(frt_tuning)) return fail(FRT_EINVAL, "frt_tuning.size must be sizeof(frt_tuning)");
     if (t->item_rays < 64 || t->item_rays > (int)FRT_ITEM_RAYS || t->item_rays % 64)
         return fail(FRT_EINVAL, "item_rays %d must be a multiple of 64 in 64..%u", t->item_rays, FRT_ITEM_RAYS);
-    if (t->scatter_blocks_per_cu < 1 || t->scatter_blocks_per_cu > 16 || t->split_blocks_per_cu < 1 ||
-        t->split_blocks_per_cu > 16)
-        return fail(FRT_EINVAL, "workgroups per CU must be in 1..16");
+    if (t->scatter_blocks_per_cu < 1 || t->scatter_blocks_per_cu > 16)
+        return fail(FRT_EINVAL, "scatter workgroups per CU must be in 1..16");
     return FRT_OK;
 }
 
@@ -977,7 +1252,8 @@ int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
 
 int ctx_device(frt_ctx ctx) { return ctx->device; }
 
-uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T, uint64_t* pass_records)
+uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T, uint64_t* pass_records,
+                     uint64_t* pass_bytes)
 {
     const uint64_t rs = P.march_precision == FRT_F64 ? 8 : 4;
     const uint64_t rec = rec_bytes(rs);
@@ -998,8 +1274,31 @@ uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T,
     const uint64_t wp = P.queue_capacity ? P.queue_capacity
                                          : (P.queue_hint ? P.queue_hint : std::max<uint64_t>(4 * cast + 65536, ncell / 2));
     if (pass_records) *pass_records = wp;
-    b += wp * (2 * rec + 8 + sizeof(uint2)) + wp / 64 * sizeof(FrtWork);
-    return b;
+    // brick keys: at most one per 8^3 cells (the smallest brick)
+    const uint64_t pq = pass_queue_bytes(wp, rs, ncell / 512 + 1);
+    if (pass_bytes) *pass_bytes = pq;
+    return b + pq;
+}
+
+uint64_t ctx_workspace_bytes(frt_ctx ctx)
+{
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    return ctx->ws.bytes();
+}
+
+void ctx_set_workspace_limit(frt_ctx ctx, uint64_t bytes)
+{
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->ws.limit = bytes;
+}
+
+void ctx_trim_workspace(frt_ctx ctx)
+{
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    (void)hipDeviceSynchronize();
+    ctx->ws.free_pass();
+    dev_free(ctx->ws.work);
+    ctx->ws.cap_work = 0;
 }
 
 }  // namespace frt
@@ -1031,9 +1330,10 @@ int frt_params_default(frt_params* p)
     return FRT_OK;
 }
 
-int frt_ctx_create(int hip_device, frt_ctx* out)
+int frt_ctx_create(int hip_device, frt_alloc_fn alloc_fn, frt_free_fn free_fn, void* user, frt_ctx* out)
 {
     if (!out) return fail(FRT_EINVAL, "null output");
+    if ((alloc_fn == nullptr) != (free_fn == nullptr)) return fail(FRT_EINVAL, "give both allocator hooks or neither");
     int n = 0;
     hipError_t e = hipGetDeviceCount(&n);
     if (e != hipSuccess || n == 0) return fail(FRT_EDEVICE, "no HIP device available (%s)", hipGetErrorString(e));
@@ -1042,6 +1342,9 @@ int frt_ctx_create(int hip_device, frt_ctx* out)
     frt_ctx c = new (std::nothrow) frt_ctx_s;
     if (!c) return fail(FRT_ENOMEM, "context");
     c->device = hip_device;
+    c->al.alloc = alloc_fn;
+    c->al.release = free_fn;
+    c->al.user = user;
     *out = c;
     return FRT_OK;
 }
@@ -1076,6 +1379,7 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     if (P->opacity_mode == FRT_GENERALIZED && P->chem_iterations > 0)
         return fail(FRT_EINVAL, "the Generalized Opacity Mode takes no chem_iterations");
     if (!(P->he_chi >= 0) || !std::isfinite(P->he_chi)) return fail(FRT_EINVAL, "he_chi must be finite and >= 0");
+    AllocScope scope(&ctx->al);
     HIPCHK(hipSetDevice(ctx->device));
     frt_solve s = new (std::nothrow) frt_solve_s;
     if (!s) return fail(FRT_ENOMEM, "solve");
@@ -1150,6 +1454,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     HIPCHK(hipSetDevice(s->ctx->device));
     HIPCHK(hipStreamSynchronize(s->stream));
     const size_t n = (size_t)nx * ny * nz;
+    AllocScope scope(&s->ctx->al);
     std::vector<float> bn, bk, bT;
     std::vector<double> bx;
     const float *hn = nullptr, *hk = nullptr, *hT = nullptr;
@@ -1296,6 +1601,7 @@ int frt_load_sources(frt_solve s, int n_src, const double* pos_cm, const double*
     if (!s->have_grid) return fail(FRT_ESTATE, "load the grid before the sources");
     if (n_src < 0) return fail(FRT_EINVAL, "n_src < 0");
     if (n_src > 0 && (!pos_cm || !ndot)) return fail(FRT_EINVAL, "null source arrays");
+    AllocScope scope(&s->ctx->al);
     HIPCHK(hipSetDevice(s->ctx->device));
     HIPCHK(hipStreamSynchronize(s->stream));
     const int nb = s->P.n_bins;
@@ -1370,6 +1676,7 @@ int frt_set_rotations(frt_solve s, int n_steps, const double* u)
     if (!s) return fail(FRT_EINVAL, "null solve");
     if (!s->have_src) return fail(FRT_ESTATE, "load the sources before the rotation table");
     if (n_steps < 0 || (n_steps > 0 && !u)) return fail(FRT_EINVAL, "bad rotation table");
+    AllocScope scope(&s->ctx->al);
     const size_t n = (size_t)n_steps * s->n_src * 3;
     for (size_t i = 0; i < n; i++)
         if (!(u[i] >= 0.0 && u[i] < 1.0)) return fail(FRT_EINVAL, "uniform %zu = %g outside [0,1)", i, u[i]);
@@ -1386,6 +1693,7 @@ int frt_set_rotations(frt_solve s, int n_steps, const double* u)
 int frt_step(frt_solve s, double dt)
 {
     RCCHK(ready(s));
+    AllocScope scope(&s->ctx->al);
     if (!(dt > 0) || !std::isfinite(dt)) return fail(FRT_EINVAL, "dt must be finite and > 0");
     HIPCHK(hipSetDevice(s->ctx->device));
     return step_group(&s, 1, &dt);
@@ -1394,6 +1702,7 @@ int frt_step(frt_solve s, double dt)
 int frt_batch_step(frt_solve* ss, int n, const double* dts)
 {
     RCCHK(check_batch(ss, n, dts));
+    AllocScope scope(&ss[0]->ctx->al);
     HIPCHK(hipSetDevice(ss[0]->ctx->device));
     for (int i = 1; i < n; i++) HIPCHK(hipStreamSynchronize(ss[i]->stream));
     RCCHK(step_group(ss, n, dts));
@@ -1404,6 +1713,7 @@ int frt_batch_step(frt_solve* ss, int n, const double* dts)
 int frt_batch_run(frt_solve* ss, int n, const double* dts, int n_steps, int use_graph)
 {
     RCCHK(check_batch(ss, n, dts));
+    AllocScope scope(&ss[0]->ctx->al);
     if (n_steps < 0) return fail(FRT_EINVAL, "n_steps must be >= 0");
     if (n_steps == 0) return FRT_OK;
     HIPCHK(hipSetDevice(ss[0]->ctx->device));
@@ -1424,7 +1734,6 @@ int frt_tuning_default(frt_tuning* t)
     t->size = sizeof(frt_tuning);
     t->item_rays = (int)FRT_ITEM_RAYS;
     t->scatter_blocks_per_cu = 8;
-    t->split_blocks_per_cu = 4;
     return FRT_OK;
 }
 
@@ -1455,6 +1764,7 @@ int frt_autotune(frt_solve* ss, int n, const double* dts, frt_tuning* best)
     RCCHK(check_batch(ss, n, dts));
     if (!best) return fail(FRT_EINVAL, "null output");
     frt_ctx ctx = ss[0]->ctx;
+    AllocScope scope(&ctx->al);
     HIPCHK(hipSetDevice(ctx->device));
     for (int i = 0; i < n; i++) HIPCHK(hipStreamSynchronize(ss[i]->stream));
     std::lock_guard<std::mutex> lock(ctx->mu);
@@ -1467,7 +1777,7 @@ int frt_autotune(frt_solve* ss, int n, const double* dts, frt_tuning* best)
     const frt_tuning keep = ctx->ws.tune;
     std::vector<frt_tuning> cand;
     for (int item : {256, 512, 1024})
-        for (int sc : {4, 8}) cand.push_back(frt_tuning{sizeof(frt_tuning), item, sc, keep.split_blocks_per_cu});
+        for (int sc : {4, 8}) cand.push_back(frt_tuning{sizeof(frt_tuning), item, sc});
     hipStream_t st = ss[0]->stream;
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
@@ -1537,8 +1847,7 @@ int frt_read_fields(frt_solve s, double* x_HI, float* gamma, int kind)
 {
     if (!s) return fail(FRT_EINVAL, "null solve");
     if (!s->have_grid) return fail(FRT_ESTATE, "no grid loaded");
-    int rc;
-    if ((rc = frt_sync(s)) && rc != FRT_EOVERFLOW) return rc;
+    RCCHK(frt_sync(s));
     const size_t n = s->ncell;
     const hipMemcpyKind k = kind == FRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
     if (x_HI) RCCHK(scopy(s, x_HI, s->x, n * 8, k));
@@ -1641,6 +1950,7 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     std::memcpy(hdr, p, sizeof(hdr));
     p += sizeof(hdr);
     if (hdr[0] != 0x4652544350543034ull || hdr[1] != 6) return fail(FRT_EINVAL, "not a checkpoint of this library");
+    AllocScope scope(&s->ctx->al);
     if (hdr[3] != (uint64_t)s->n_src || hdr[4] != s->ncell || hdr[5] != (uint64_t)s->P.n_bins || hdr[6] != (uint64_t)s->fp64)
         return fail(FRT_EINVAL, "checkpoint does not match this solve (sources, grid, bins or precision)");
     const uint32_t step = (uint32_t)hdr[2], nc = (uint32_t)hdr[7];
@@ -1708,6 +2018,7 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
 int frt_mark(frt_solve s)
 {
     RCCHK(ready(s));
+    AllocScope scope(&s->ctx->al);
     HIPCHK(hipStreamSynchronize(s->stream));
     uint32_t fc[2];
     RCCHK(scopy(s, fc, s->fcount, 8, hipMemcpyDeviceToHost));
@@ -1772,6 +2083,30 @@ int frt_read_timing(frt_solve s, frt_timing* out)
     out->chem_launches = s->n_chem;
     out->steps = s->n_steps_timed;
     return FRT_OK;
+}
+
+int frt_debug_cast(frt_solve s, const double o_cm[3], const double d[3], const double* N_bins, double dt_s,
+                   float* gamma_out, int ptr_kind, double* absorbed, double* escaped, uint64_t* crossings)
+{
+    if (!s || !o_cm || !d || !N_bins || !absorbed || !escaped || !crossings) return fail(FRT_EINVAL, "null argument");
+    if (!s->have_grid) return fail(FRT_ESTATE, "load the grid before casting through it");
+    if (!(dt_s > 0) || !std::isfinite(dt_s)) return fail(FRT_EINVAL, "dt must be finite and > 0");
+    if (ptr_kind != FRT_HOST && ptr_kind != FRT_DEVICE) return fail(FRT_EINVAL, "ptr_kind must be FRT_HOST or FRT_DEVICE");
+    const double ext[3] = {s->nx * s->dx, s->ny * s->dx, s->nz * s->dx};
+    double nrm = 0;
+    for (int a = 0; a < 3; a++) {
+        if (!std::isfinite(o_cm[a]) || o_cm[a] < 0 || o_cm[a] > ext[a]) return fail(FRT_EINVAL, "origin outside the box");
+        if (!std::isfinite(d[a])) return fail(FRT_EINVAL, "direction not finite");
+        nrm += d[a] * d[a];
+    }
+    if (!(nrm > 0)) return fail(FRT_EINVAL, "zero direction");
+    for (int b = 0; b < s->P.n_bins; b++)
+        if (!std::isfinite(N_bins[b]) || N_bins[b] < 0) return fail(FRT_EINVAL, "N_bins[%d] is negative or not finite", b);
+    HIPCHK(hipSetDevice(s->ctx->device));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    AllocScope scope(&s->ctx->al);
+    std::lock_guard<std::mutex> lock(s->ctx->mu);
+    return debug_cast_locked(s, o_cm, d, N_bins, dt_s, gamma_out, ptr_kind, absorbed, escaped, crossings);
 }
 
 int frt_rotation_uniforms(uint64_t seed, uint32_t step, uint32_t src, double out[3])

@@ -202,7 +202,6 @@ struct FrtWS {
     // launch shape (tunable)
     uint32_t item_rays;         // packets per work item, 64..FRT_ITEM_RAYS
     int scatter_bpc;            // workgroups per CU of the scatter pass
-    int split_bpc;              // accepted for compatibility; no kernel uses it
 };
 
 namespace frt {
@@ -232,6 +231,16 @@ int device_cu_count();
 int set_error(int code, const char* msg);
 int ctx_device(frt_ctx ctx);
 // Device bytes a solve with these parameters and sizes holds, and the first
-// pass-queue size it asks for (records).
-uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T, uint64_t* pass_records);
+// pass-queue size it asks for (records, and their bytes, which are part of
+// the total: the pass queues are shared by the solves of a context and grow
+// with the largest pass).
+uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T, uint64_t* pass_records,
+                     uint64_t* pass_bytes);
+// Device bytes the context's shared pass queues hold now, and the most they
+// may grow to (0: no limit; a step that needs more fails with FRT_ENOMEM
+// before anything runs).  Trimming frees them (the next step allocates them
+// again at its own size); only while no step of the context is running.
+uint64_t ctx_workspace_bytes(frt_ctx ctx);
+void ctx_set_workspace_limit(frt_ctx ctx, uint64_t bytes);
+void ctx_trim_workspace(frt_ctx ctx);
 }  // namespace frt

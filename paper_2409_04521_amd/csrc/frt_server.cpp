@@ -25,6 +25,7 @@
 #include <mutex>
 #include <string>
 #include <thread>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -42,7 +43,8 @@ struct Req {
     double box_cm = 0.0, dt = 0.0;
     std::vector<float> nH, T, kappa;
     std::vector<double> x0, pos, ndot, rot;
-    size_t bytes = 0;
+    size_t resident = 0;              // device bytes of the solve's own buffers
+    size_t pass = 0;                  // its share of the context's pass queues at their first size
     frt_solve solve = nullptr;
     int steps_done = 0;
     std::vector<double> x_out;
@@ -116,24 +118,42 @@ struct frt_server_s {
     uint64_t next_id = 1;
     bool stop = false;
     frt_server_stats st{};
+    // device bytes: the admitted solves' own buffers, the sum of their
+    // pass-queue shares, and what the context's shared pass workspace holds
+    // (it grows with the largest pass and never shrinks); in use is the
+    // first plus the larger of the other two
+    size_t resident_in_use = 0, pass_in_use = 0, ws_bytes = 0;
     std::thread worker;
     std::vector<std::thread> loaders;   // requests are loaded this many at a time
 
+    // caller holds mu
+    void update_bytes()
+    {
+        st.bytes_in_use = resident_in_use + std::max(pass_in_use, ws_bytes);
+        st.peak_bytes = std::max(st.peak_bytes, st.bytes_in_use);
+    }
+
+    // Publish a request's end.  After this call the request may be taken
+    // (and deleted) by a client at any time: the calling thread must not
+    // touch it again, and no list of the worker may still hold it.
     void finish(Req* r, int state)
     {
         std::lock_guard<std::mutex> lock(mu);
         r->state = state;
         r->t_done = seconds_since(t0);
-        st.bytes_in_use -= r->bytes;
+        resident_in_use -= r->resident;
+        pass_in_use -= r->pass;
+        update_bytes();
         if (state == FRT_REQ_DONE) st.completed++;
         else st.failed++;
         done_cv.notify_all();
     }
 
-    void fail_req(Req* r, int code)
+    // code and message of the failing call, taken by the thread that made it
+    void fail_req(Req* r, int code, const std::string& msg)
     {
         r->err = code;
-        r->msg = frt_last_error();
+        r->msg = msg;
         if (r->solve) {
             frt_solve_destroy(r->solve);
             r->solve = nullptr;
@@ -171,10 +191,12 @@ struct frt_server_s {
             const int rc = load(r);
             r->free_inputs();
             if (rc != FRT_OK) {
-                fail_req(r, rc);
-                std::lock_guard<std::mutex> lock(mu);
-                loading--;
-                cv.notify_all();
+                {
+                    std::lock_guard<std::mutex> lock(mu);
+                    loading--;
+                    cv.notify_all();
+                }
+                fail_req(r, rc, frt_last_error());
                 continue;
             }
             std::lock_guard<std::mutex> lock(mu);
@@ -189,8 +211,9 @@ struct frt_server_s {
         r->x_out.resize(ncell);
         int rc = frt_read_fields(r->solve, r->x_out.data(), nullptr, FRT_HOST);
         if (rc == FRT_OK) rc = frt_read_ledger(r->solve, &r->led);
+        if (rc == FRT_OK && r->led.err_flags) rc = frt::set_error(FRT_EDEVICE, "the solve ended with device error bits set");
         if (rc != FRT_OK) {
-            fail_req(r, rc);
+            fail_req(r, rc, frt_last_error());
             return;
         }
         frt_solve_destroy(r->solve);
@@ -211,7 +234,7 @@ struct frt_server_s {
                 // admission in arrival order: a slot and the request's bytes
                 while (!queue.empty() && (int)active.size() + loading < max_slots) {
                     Req* r = queue.front();
-                    if (r->bytes > budget) {
+                    if (r->resident + r->pass > budget) {
                         queue.pop_front();
                         r->err = FRT_ENOMEM;
                         r->msg = "request needs more device memory than the server's whole budget";
@@ -222,10 +245,21 @@ struct frt_server_s {
                         done_cv.notify_all();
                         continue;
                     }
-                    if (st.bytes_in_use + r->bytes > budget) break;
+                    if (resident_in_use + r->resident + std::max(ws_bytes, pass_in_use + r->pass) > budget) {
+                        // pass queues grown by earlier requests and kept while
+                        // idle: give them back, so the request sees its own
+                        if (active.empty() && loading == 0 && ready.empty() && ws_bytes > 0) {
+                            frt::ctx_trim_workspace(ctx);
+                            ws_bytes = 0;
+                            update_bytes();
+                            continue;
+                        }
+                        break;
+                    }
                     queue.pop_front();
-                    st.bytes_in_use += r->bytes;
-                    st.peak_bytes = std::max(st.peak_bytes, st.bytes_in_use);
+                    resident_in_use += r->resident;
+                    pass_in_use += r->pass;
+                    update_bytes();
                     r->state = FRT_REQ_RUNNING;
                     r->t_start = seconds_since(t0);
                     to_load.push_back(r);
@@ -250,9 +284,18 @@ struct frt_server_s {
                 st.max_in_flight = std::max<uint32_t>(st.max_in_flight, (uint32_t)active.size());
             }
             if (active.empty()) continue;
-            // one tick: a batched step per (n_bins, precision) group
-            std::map<std::pair<int, int>, std::vector<Req*>> groups;
-            for (Req* r : active) groups[{r->params.n_bins, r->params.march_precision}].push_back(r);
+            // the shared pass queues may grow up to what the budget leaves
+            // beside the admitted solves' own buffers
+            {
+                std::lock_guard<std::mutex> lock(mu);
+                frt::ctx_set_workspace_limit(ctx, budget > resident_in_use ? budget - resident_in_use : 1);
+            }
+            // one tick: a batched step per group of solves that one launch
+            // sequence can take (same n_bins, precision and queue mode)
+            std::map<std::tuple<int, int, int>, std::vector<Req*>> groups;
+            for (Req* r : active)
+                groups[{r->params.n_bins, r->params.march_precision, r->params.queue_capacity == 0}].push_back(r);
+            std::vector<std::pair<Req*, std::pair<int, std::string>>> failed;
             for (auto& kv : groups) {
                 std::vector<Req*>& g = kv.second;
                 for (size_t at = 0; at < g.size(); at += FRT_MAX_SOLVES_PER_LAUNCH) {
@@ -263,24 +306,53 @@ struct frt_server_s {
                         ss[i] = g[at + i]->solve;
                         dts[i] = g[at + i]->dt;
                     }
-                    const int rc = frt_batch_step(ss.data(), (int)n, dts.data());
-                    for (size_t i = 0; i < n; i++) {
-                        Req* r = g[at + i];
-                        if (rc != FRT_OK) fail_req(r, rc);
-                        else r->steps_done++;
+                    int rc = frt_batch_step(ss.data(), (int)n, dts.data());
+                    size_t stepped = 0;
+                    if (rc == FRT_OK) {
+                        for (size_t i = 0; i < n; i++) g[at + i]->steps_done++;
+                        stepped = n;
+                    } else if (n == 1 || rc == FRT_EDEVICE) {
+                        const std::string msg = frt_last_error();
+                        for (size_t i = 0; i < n; i++) failed.push_back({g[at + i], {rc, msg}});
+                    } else {
+                        // a failed batched step leaves every solve at the start of
+                        // the step: step them one by one, so that only those that
+                        // fail alone (too large for what is left, say) fail
+                        for (size_t i = 0; i < n; i++) {
+                            Req* r = g[at + i];
+                            const int rc1 = frt_batch_step(&ss[i], 1, &dts[i]);
+                            if (rc1 == FRT_OK) {
+                                r->steps_done++;
+                                stepped++;
+                            } else {
+                                failed.push_back({r, {rc1, frt_last_error()}});
+                            }
+                        }
                     }
                     std::lock_guard<std::mutex> lock(mu);
                     st.ticks++;
-                    if (rc == FRT_OK) st.solve_steps += n;
+                    st.solve_steps += stepped;
                 }
             }
-            std::vector<Req*> still;
+            {
+                std::lock_guard<std::mutex> lock(mu);
+                ws_bytes = frt::ctx_workspace_bytes(ctx);
+                update_bytes();
+            }
+            // drop finished and failed requests from `active` before their
+            // end is published (a client may take, and so delete, them
+            // as soon as it is)
+            std::vector<Req*> still, done;
             for (Req* r : active) {
-                if (r->state == FRT_REQ_FAILED) continue;
-                if (r->steps_done >= r->n_steps) complete(r);
+                bool bad = false;
+                for (auto& f : failed) bad |= f.first == r;
+                if (bad) continue;
+                if (r->steps_done >= r->n_steps) done.push_back(r);
                 else still.push_back(r);
             }
             active.swap(still);
+            for (auto& f : failed) fail_req(f.first, f.second.first, f.second.second);
+            for (Req* r : done) complete(r);
         }
         for (Req* r : active)
             if (r->solve) {
@@ -310,7 +382,7 @@ int frt_request_bytes(const frt_request* req, size_t* bytes)
     int rc = validate(req);
     if (rc) return rc;
     const uint64_t ncell = (uint64_t)req->nx * req->ny * req->nz;
-    *bytes = (size_t)frt::solve_bytes(req->params, ncell, req->n_src, req->T != nullptr, nullptr);
+    *bytes = (size_t)frt::solve_bytes(req->params, ncell, req->n_src, req->T != nullptr, nullptr, nullptr);
     return FRT_OK;
 }
 
@@ -363,7 +435,10 @@ int frt_server_submit(frt_server srv, const frt_request* req, uint64_t* req_id)
     if (req->rotation_steps > 0 &&
         (rc = copy_in(req->rotation_uniforms, (size_t)req->rotation_steps * req->n_src * 3, req->ptr_kind, r->rot)))
         return rc;
-    r->bytes = (size_t)frt::solve_bytes(req->params, ncell, req->n_src, req->T != nullptr, nullptr);
+    uint64_t pass_bytes = 0;
+    const uint64_t total = frt::solve_bytes(req->params, ncell, req->n_src, req->T != nullptr, nullptr, &pass_bytes);
+    r->resident = (size_t)(total - pass_bytes);
+    r->pass = (size_t)pass_bytes;
     std::lock_guard<std::mutex> lock(srv->mu);
     r->id = srv->next_id++;
     r->t_submit = seconds_since(srv->t0);

@@ -29,7 +29,7 @@ EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_
            "frt_rotation_uniforms", "frt_batch_run", "frt_tuning_default", "frt_ctx_set_tuning",
            "frt_ctx_get_tuning", "frt_autotune", "frt_request_bytes", "frt_server_create", "frt_server_submit",
            "frt_server_poll", "frt_server_wait", "frt_server_take", "frt_server_times", "frt_server_get_stats",
-           "frt_server_destroy")
+           "frt_server_destroy", "frt_debug_cast")
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
@@ -71,8 +71,7 @@ class Timing(C.Structure):
 
 
 class Tuning(C.Structure):
-    _fields_ = [("size", C.c_size_t), ("item_rays", C.c_int), ("scatter_blocks_per_cu", C.c_int),
-                ("split_blocks_per_cu", C.c_int)]
+    _fields_ = [("size", C.c_size_t), ("item_rays", C.c_int), ("scatter_blocks_per_cu", C.c_int)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
@@ -95,6 +94,45 @@ class ServerStats(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+# Device memory hooks of a context (include/frt.h, frt_alloc_fn / frt_free_fn).
+ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class TorchAllocator:
+    """Device memory of a context from PyTorch's caching allocator on
+    `device`: the library's buffers then count in torch.cuda.memory_allocated()
+    and reuse the cache.  Keeps its callbacks alive while any block is out."""
+
+    def __init__(self, device: int = 0):
+        import torch
+
+        self.device = device
+        self.live = {}
+
+        def alloc(nbytes, user):
+            try:
+                ptr = torch.cuda.caching_allocator_alloc(int(nbytes), self.device)
+            except RuntimeError:
+                return None
+            self.live[ptr] = int(nbytes)
+            return ptr
+
+        def free(ptr, user):
+            if self.live.pop(ptr, None) is not None:
+                torch.cuda.caching_allocator_delete(ptr)
+
+        self.alloc_fn = ALLOC_FN(alloc)
+        self.free_fn = FREE_FN(free)
+
+    def bytes_out(self) -> int:
+        return sum(self.live.values())
+
+
+# allocators whose blocks the library may still hand back (a solve can
+# outlive its Context object on the Python side)
+_ALLOCATORS = []
+
 _lib = None
 
 
@@ -109,7 +147,7 @@ def lib():
         vp = C.c_void_p
         L.frt_last_error.restype = C.c_char_p
         L.frt_params_default.argtypes = [C.POINTER(Params)]
-        L.frt_ctx_create.argtypes = [C.c_int, C.POINTER(vp)]
+        L.frt_ctx_create.argtypes = [C.c_int, ALLOC_FN, FREE_FN, vp, C.POINTER(vp)]
         L.frt_ctx_destroy.argtypes = [vp]
         L.frt_solve_create.argtypes = [vp, C.POINTER(Params), vp, C.POINTER(vp)]
         L.frt_solve_destroy.argtypes = [vp]
@@ -143,6 +181,9 @@ def lib():
         L.frt_server_times.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double)]
         L.frt_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.frt_server_destroy.argtypes = [vp]
+        L.frt_debug_cast.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.c_double, vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                     C.POINTER(C.c_uint64)]
         _lib = L
     return _lib
 
@@ -181,9 +222,18 @@ def rotation_uniforms(seed: int, step: int, src: int):
 
 
 class Context:
-    def __init__(self, device: int = 0):
+    """frt_ctx on HIP device `device`; allocator=None uses hipMalloc, a
+    TorchAllocator (or anything with alloc_fn / free_fn ctypes callbacks)
+    routes the library's device memory through it."""
+
+    def __init__(self, device: int = 0, allocator=None):
         h = C.c_void_p()
-        _check(lib().frt_ctx_create(device, C.byref(h)))
+        self.allocator = allocator
+        if allocator is None:
+            _check(lib().frt_ctx_create(device, ALLOC_FN(), FREE_FN(), None, C.byref(h)))
+        else:
+            _ALLOCATORS.append(allocator)
+            _check(lib().frt_ctx_create(device, allocator.alloc_fn, allocator.free_fn, None, C.byref(h)))
         self.h = h
         self.device = device
 
@@ -193,7 +243,7 @@ class Context:
         _check(lib().frt_ctx_get_tuning(self.h, C.byref(t)))
         return t.as_dict()
 
-    def set_tuning(self, item_rays=None, scatter_blocks_per_cu=None, split_blocks_per_cu=None):
+    def set_tuning(self, item_rays=None, scatter_blocks_per_cu=None):
         t = Tuning()
         t.size = C.sizeof(Tuning)
         _check(lib().frt_ctx_get_tuning(self.h, C.byref(t)))
@@ -201,8 +251,6 @@ class Context:
             t.item_rays = item_rays
         if scatter_blocks_per_cu is not None:
             t.scatter_blocks_per_cu = scatter_blocks_per_cu
-        if split_blocks_per_cu is not None:
-            t.split_blocks_per_cu = split_blocks_per_cu
         _check(lib().frt_ctx_set_tuning(self.h, C.byref(t)))
 
     def close(self):
@@ -305,6 +353,18 @@ class Solve:
         L = Ledger()
         _check(lib().frt_read_ledger(self.h, C.byref(L)))
         return L.as_dict()
+
+    def debug_cast(self, origin_cm, direction, N_bins, dt_s=1.0):
+        """March one packet through the current opacity (frt_debug_cast).
+        Returns (absorbed photons, escaped photons, crossings, rate field)."""
+        o = (C.c_double * 3)(*[float(v) for v in origin_cm])
+        d = (C.c_double * 3)(*[float(v) for v in direction])
+        N = (C.c_double * MAX_BINS)(*[float(v) for v in N_bins])
+        g = np.zeros(int(np.prod(self.shape)), dtype=np.float32)
+        ab, es, nc = C.c_double(), C.c_double(), C.c_uint64()
+        _check(lib().frt_debug_cast(self.h, o, d, N, float(dt_s), g.ctypes.data, FRT_HOST, C.byref(ab),
+                                    C.byref(es), C.byref(nc)))
+        return ab.value, es.value, int(nc.value), g.reshape(self.shape)
 
     def mark(self):
         _check(lib().frt_mark(self.h))

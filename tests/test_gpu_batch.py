@@ -132,7 +132,7 @@ def test_tuning_is_validated_and_changes_no_result():
     a = frt.solve_from_problem(ctx, p)
     for _ in range(3):
         a.step(p.dt_s)
-    ctx.set_tuning(item_rays=64, scatter_blocks_per_cu=1, split_blocks_per_cu=1)
+    ctx.set_tuning(item_rays=64, scatter_blocks_per_cu=1)
     b = frt.solve_from_problem(ctx, p)
     for _ in range(3):
         b.step(p.dt_s)

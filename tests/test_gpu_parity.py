@@ -212,15 +212,27 @@ def test_queue_growth_reruns_the_step(ctx):
 
 
 def test_fixed_capacity_overflow_is_reported_and_not_applied(ctx):
+    # a step that overflows a fixed queue is reported by the step call and
+    # leaves the solve exactly at the start of that step (fields, ledger,
+    # step index, no error bits left behind), so that stepping can go on
     p = _dense_ray_problem()
     g = frt.solve_from_problem(ctx, p, queue_capacity=2000)
     x0, _ = g.fields()
-    g.step(p.dt_s)
-    with pytest.raises(frt.FrtError) as e:
-        g.sync()
-    assert e.value.code == frt.FRT_EOVERFLOW
-    x1, _ = g.fields()
-    assert np.array_equal(x0, x1)
+    L0 = g.ledger()
+    for attempt in range(2):
+        with pytest.raises(frt.FrtError) as e:
+            g.step(p.dt_s)
+        assert e.value.code == frt.FRT_EOVERFLOW
+        g.sync()                                   # nothing deferred
+        x1, _ = g.fields()
+        L1 = g.ledger()
+        assert np.array_equal(x0, x1), attempt
+        assert L1["steps"] == L0["steps"] and L1["emitted"] == L0["emitted"] and L1["err_flags"] == 0
+    # a fixed capacity that holds the step gives the oracle's result
+    big = frt.solve_from_problem(ctx, p, queue_capacity=16_000_000)
+    for _ in range(2):
+        big.step(p.dt_s)
+    _compare(_oracle(p, 2), big, 1e-3, 1e-4, "fixed capacity")
 
 
 def test_invalid_inputs_are_rejected(ctx):
@@ -257,3 +269,80 @@ def test_many_splits_per_step_at_finite_c(ctx):
     g = _gpu(ctx, p, 3)
     assert g.ledger()["splits"] > 0
     _compare(_oracle(p, 3), g, 1e-3, 1e-4, "N_min 16 finite c")
+
+
+def _carried_radii(g, n_src, ncell, fp64):
+    """Distances from their sources (cells) of the packets a solve carries,
+    read from its checkpoint: 8 u64 header (the carried count last), the
+    ledger (136 bytes), x_HI, the rotation quaternions of the steps so far,
+    then the packet records (64 bytes in FP32 with r at byte 20, 112 in FP64
+    with r at byte 24)."""
+    blob = g.save()
+    hdr = np.frombuffer(blob[:64], dtype=np.uint64)
+    step, nc = int(hdr[2]), int(hdr[7])
+    off = 64 + 136 + 8 * ncell + 32 * step * n_src
+    size, at, dt = (112, 24, np.float64) if fp64 else (64, 20, np.float32)
+    recs = np.frombuffer(blob[off: off + nc * size], dtype=np.uint8).reshape(nc, size)
+    return recs[:, at: at + np.dtype(dt).itemsize].copy().view(dt).reshape(-1).astype(np.float64)
+
+
+@pytest.mark.parametrize("precision,rtol", [("f64", 1e-12), ("f32", 2e-6)])
+def test_carried_packets_travel_exactly_c_dt_per_step(ctx, precision, rtol):
+    # §3.1 packets move c dt per step: in a transparent box the packets cast
+    # at step j sit at (k - j + 1) c dt from their source after step k, each
+    # shell with the HEALPix count of the level reached at its radius
+    n, dx, dt, step_cells = 64, 1e21, 1e13, 3.7
+    shape = (n, n, n)
+    p = W.Problem(name="transparent", shape=shape, dx_cm=dx, n_H=np.full(shape, 1e-3, np.float32),
+                  x_HI0=np.zeros(shape), kappa=None, src_pos_cm=np.array([[32.5 * dx] * 3]),
+                  ndot_bins=np.array([[1e50]]), sigma_bins=np.array([6.3e-18]), dt_s=dt, n_steps=4,
+                  c_ray=step_cells * dx / dt, alpha_B=0.0, max_level=12, seed=3)
+    g = frt.solve_from_problem(ctx, p, precision=precision)
+    for k in range(1, 5):
+        g.step(dt)
+        r = _carried_radii(g, 1, n ** 3, precision == "f64")
+        assert r.size == g.ledger()["n_in_flight"]
+        shells = np.rint(r / step_cells)
+        assert np.allclose(r, shells * step_cells, rtol=rtol, atol=0), (k, np.abs(r / (shells * step_cells) - 1).max())
+        for m in range(1, k + 1):
+            levels = sum(1 for l in range(13) if O.split_radius(1.0, l, 1.0) <= m * step_cells)
+            assert int((shells == m).sum()) == 12 * 4 ** levels, (k, m)
+
+
+@pytest.mark.parametrize("precision,rtol", [("f64", 1e-10), ("f32", 2e-3)])
+def test_flux_floor_drops_where_the_photons_fall_below_it(ctx, precision, rtol):
+    # Uniform neutral gas, n_H sigma_0 dx = 1, two bins (cross-section ratio
+    # 1 and 1/3, photons 0.6 / 0.4), floor 1e-3 (reading R9): the summed
+    # photons of a packet fall below the floor at r* = 17.97 cells, after
+    # its last split (level 5): all 12 4^5 packets are dropped, each with
+    # S(r_drop) = 0.6 e^-r + 0.4 e^-(r/3) of its cast photons at the first
+    # face it crosses beyond r*, and everything else is absorbed.
+    from scipy.optimize import brentq
+    n, dx, sig0 = 64, 1e21, 6.3e-18
+    shape = (n, n, n)
+    nH = np.full(shape, 1.0 / (sig0 * dx), np.float32)
+    w = np.array([0.6, 0.4])
+    src = np.array([32.5, 32.5, 32.5])
+    p = W.Problem(name="floor", shape=shape, dx_cm=dx, n_H=nH, x_HI0=np.ones(shape), kappa=None,
+                  src_pos_cm=src[None, :] * dx, ndot_bins=(1e50 * w)[None, :], sigma_bins=np.array([sig0, sig0 / 3]),
+                  dt_s=1e13, n_steps=1, c_ray=np.inf, flux_floor=1e-3, alpha_B=0.0, max_level=12, seed=11)
+    g = _gpu(ctx, p, 1, precision=precision)
+    L = g.ledger()
+    tau_cell = float(nH[0, 0, 0]) * sig0 * dx
+    S = lambda r: w[0] * np.exp(-tau_cell * r) + w[1] * np.exp(-tau_cell * r / 3)
+    r_star = brentq(lambda r: S(r) - 1e-3, 10, 30)
+    R = O.rotation(p.uniforms(0)[0])
+    d = np.stack([R @ O.healpix_center(5, q) for q in range(12 * 4 ** 5)])
+    # the first face beyond r* along each packet's line from the source
+    r_drop = np.full(d.shape[0], np.inf)
+    for a in range(3):
+        da = d[:, a]
+        pos = src[a] + r_star * da
+        k = np.where(da > 0, np.floor(pos) + 1, np.ceil(pos) - 1)
+        r_drop = np.minimum(r_drop, np.where(da != 0, (k - src[a]) / np.where(da != 0, da, 1), np.inf))
+    emitted = 1e50 * p.dt_s
+    expect = (emitted / (12 * 4 ** 5) * S(r_drop)).sum()
+    print(f"[floor {precision}] dropped {L['dropped']:.6e} expected {expect:.6e}", flush=True)
+    assert L["n_dropped"] == 12 * 4 ** 5 and L["n_escaped"] == 0
+    assert L["dropped"] == pytest.approx(expect, rel=rtol)
+    assert L["absorbed_HI"] + L["dropped"] == pytest.approx(L["emitted"], rel=1e-9)

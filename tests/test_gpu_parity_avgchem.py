@@ -164,3 +164,14 @@ def test_no_sources_is_pure_recombination_at_the_largest_k(ctx):
     xg, xo = g.fields()[0], o.fields()[0]
     assert np.abs(xg - xo).max() <= 1e-12
     assert np.all(xg > 0.2)                       # recombination raised x_HI
+
+
+@pytest.mark.parametrize("precision,x_tol,led_tol", [("f64", 1e-9, 1e-9), ("f32", 1e-3, 1e-4)])
+def test_c1_as_configured_with_the_time_averaged_update(ctx, precision, x_tol, led_tol):
+    # C1 as configured (corner vertex source, 2 Myr x 50 steps) with the
+    # chemistry that meets its Stromgren gate on the oracle (K = 20): the HIP
+    # path against the oracle over the whole run
+    p = W.stromgren_c1()
+    p.chem_iterations = 20
+    _compare(_oracle(p, p.n_steps), _gpu(ctx, p, p.n_steps, precision=precision), x_tol, led_tol,
+             f"C1 K=20 {precision}")

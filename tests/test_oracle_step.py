@@ -131,3 +131,64 @@ def test_result_independent_of_thread_count():
     b = _run(p, threads=5)
     assert np.array_equal(a.fields()[0], b.fields()[0])
     assert a.ledger() == b.ledger()
+
+
+def _c1_front(chem_iterations, n_steps=50):
+    """C1 as configured (source on the corner vertex, 2 Myr steps to 100
+    Myr): per step t >= t_rec/2 the raw ratio r(t)/r_analytic(t) (Eqs. r_of_t,
+    rS, trec; octant volume times 8) and the ratio of the ionized volume to
+    the injection-corrected analytic volume, which integrates
+    dV/dt = Ndot_in / n_H - alpha n_H V exactly over each step with the
+    photons that entered the box in that step (emitted minus escaped): the
+    12 level-0 packets of a vertex source put k/12 of the photons into the
+    octant, not 1/8, so only this form isolates the chemistry."""
+    p = W.stromgren_c1()
+    p.chem_iterations = chem_iterations
+    nH = float(np.float32(2e-3))
+    a, Nd = p.alpha_B, 1e49
+    rS = (3 * Nd / (4 * math.pi * a * nH ** 2)) ** (1 / 3)
+    trec = 1 / (a * nH)
+    o = O.Oracle(**p.oracle_kwargs())
+    o.set_sources(p.src_pos_cm, p.ndot_bins)
+    V = 0.0
+    raw, cor = [], []
+    for s in range(n_steps):
+        L0 = o.ledger()
+        o.step(p.dt_s, p.uniforms(s))
+        L1 = o.ledger()
+        injected = (L1["emitted"] - L0["emitted"]) - (L1["escaped"] - L0["escaped"])
+        Veq = injected / p.dt_s / (a * nH * nH)
+        V = Veq + (V - Veq) * math.exp(-a * nH * p.dt_s)
+        t = (s + 1) * p.dt_s
+        if t >= 0.5 * trec:
+            x, _ = o.fields()
+            Vion = (1 - x).sum() * p.dx_cm ** 3
+            r = (3 * 8 * Vion / (4 * math.pi)) ** (1 / 3)
+            raw.append(r / (rS * (1 - math.exp(-t / trec)) ** (1 / 3)) - 1)
+            cor.append((Vion / V) ** (1 / 3) - 1)
+    return np.array(raw), np.array(cor)
+
+
+def test_c1_time_averaged_chemistry_meets_the_stromgren_gate():
+    # The paper's own update (§4.1, Eqs. xi_of_t-gamma_updated_standard,
+    # iterated; exact without recombinations) at C1's 2 Myr step: the front
+    # follows the injection-corrected analytic solution within 3% from
+    # t_rec/2 on (measured 1.5%).  The raw ratio is set by the vertex
+    # sampling of the level-0 packets (measured 17%), reported, not gated.
+    raw, cor = _c1_front(20)
+    print(f"C1 K=20: worst raw {np.abs(raw).max():.3f}, worst corrected {np.abs(cor).max():.4f}")
+    assert np.abs(cor).max() <= 0.03
+    assert np.abs(raw).max() <= 0.25
+
+
+def test_c1_backward_euler_is_not_photon_conserving_at_2_myr():
+    # Backward Euler with the start-of-step opacity (the default chemistry):
+    # a cell absorbs Gamma x n_H V dt photons in a step but, without
+    # recombinations, ionizes x Gamma dt / (1 + Gamma dt) n_H V atoms, a
+    # fraction 1 / (1 + Gamma dt) of what it absorbed; cells at the front of
+    # C1 have Gamma dt >> 1 at 2 Myr, so the ionized volume falls far behind
+    # the photons that entered (measured 37% in radius).  The time-averaged
+    # update above is the one that meets the C1 gate.
+    raw, cor = _c1_front(0)
+    print(f"C1 backward Euler: worst raw {np.abs(raw).max():.3f}, worst corrected {np.abs(cor).max():.3f}")
+    assert np.abs(cor).max() > 0.25 and np.all(cor < 0)

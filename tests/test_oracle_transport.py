@@ -248,3 +248,99 @@ def test_pure_recombination_matches_analytic():
         x = O.chemistry(x, 0.0, nH, a, 0.0, T / n)
     exact = 1 - 1 / (1 / (1 - x0) + a * nH * T)
     assert x == pytest.approx(exact, rel=2e-3)
+
+
+# ---------------------------------------------------------- flux floor, travel
+def _first_face_after(src_cells, d, r_lo, r_hi):
+    """For each direction d[k], the smallest distance r in (r_lo, r_hi) at
+    which the line src + r d crosses a cell face (integer coordinate), by
+    the slab geometry of each axis; inf if none."""
+    best = np.full(d.shape[0], np.inf)
+    for a in range(3):
+        da = d[:, a]
+        ok = da != 0
+        s = src_cells[a]
+        # crossings s + r d = k for integers k; the first one beyond r_lo
+        pos_lo = s + r_lo * da
+        k = np.where(da > 0, np.floor(pos_lo) + 1, np.ceil(pos_lo) - 1)
+        r = np.where(ok, (k - s) / np.where(ok, da, 1.0), np.inf)
+        # the next crossing along this axis after r_lo (a crossing exactly at
+        # r_lo belongs to the segment that ended there)
+        r = np.where(r <= r_lo, r + np.abs(1.0 / np.where(ok, da, 1.0)), r)
+        best = np.minimum(best, np.where(r < r_hi, r, np.inf))
+    return best
+
+
+def test_flux_floor_drops_at_the_first_segment_end_below_the_floor():
+    # Uniform neutral gas with n_H sigma_0 dx = 1 and two bins (sigma ratio
+    # 1 and 1/3, photons 0.6 / 0.4): a packet's photons relative to its cast
+    # photons are S(r) = 0.6 e^-r + 0.4 e^-(r/3) at r cells from its source
+    # (the optical depth depends only on the path length in uniform gas, also
+    # across splits, which re-centre children at the same radius).  With the
+    # floor f = 1e-3 (reading R9: the summed photons against f times the cast
+    # photons divided by 4 per split) S crosses f at r* = 17.97 cells, after
+    # the last split radius below it (r_split(4) = 15.6, r_split(5) = 31.3):
+    # every level-5 packet is dropped at the first face it crosses beyond r*,
+    # with S(r_drop) of its photons.  A per-bin floor test would drop at
+    # 20.7 cells, a floor without the 4^-dl division right after the split.
+    n, dx = 64, 1e21
+    sig0 = 6.3e-18
+    nH = 1.0 / (sig0 * dx)
+    w = np.array([0.6, 0.4])
+    ndot = 1e50 * w
+    shape = (n, n, n)
+    src = np.array([32.5, 32.5, 32.5])
+    o = O.Oracle(shape=shape, dx_cm=dx, sigma_bins=[sig0, sig0 / 3], alpha_B=0.0,
+                 n_H=np.full(shape, nH, np.float32), x_HI0=np.ones(shape), max_level=12,
+                 flux_floor=1e-3, c_ray=np.inf)
+    o.set_sources(src[None, :] * dx, ndot[None, :])
+    u = W.rotation_uniforms(11, 0, 1)
+    dt = 1e13
+    o.step(dt, u)
+    L = o.ledger()
+
+    nH32 = float(np.float32(nH))
+    tau_cell = nH32 * sig0 * dx                       # as the oracle sees the float32 density
+    S = lambda r: w[0] * np.exp(-tau_cell * r) + w[1] * np.exp(-tau_cell * r / 3)
+    from scipy.optimize import brentq
+    r_star = brentq(lambda r: S(r) - 1e-3, 10, 30)
+    r_split = [O.split_radius(1.0, l, 1.0) for l in range(7)]
+    assert r_split[4] < r_star < r_split[5]
+    R = O.rotation(u[0])
+    dirs = np.stack([R @ O.healpix_center(5, p) for p in range(12 * 4 ** 5)])
+    r_drop = _first_face_after(src, dirs, r_star, r_split[5])
+    assert np.all(np.isfinite(r_drop))
+    # no face crossing is so close to r* that rounding could move the drop
+    just_before = _first_face_after(src, dirs, r_split[4], r_star)
+    assert np.min(np.abs(r_drop - r_star)) > 1e-6 and np.min(np.abs(just_before[np.isfinite(just_before)] - r_star)) > 1e-6
+
+    emitted = ndot.sum() * dt
+    per_ray = emitted / (12 * 4 ** 5)
+    expect_dropped = (per_ray * S(r_drop)).sum()
+    assert L["n_dropped"] == 12 * 4 ** 5 and L["n_escaped"] == 0
+    assert L["splits"] == sum(12 * 4 ** l for l in range(5))
+    assert L["dropped"] == pytest.approx(expect_dropped, rel=1e-10)
+    assert L["absorbed_HI"] == pytest.approx(emitted - expect_dropped, rel=1e-12)
+
+
+def test_carried_packets_travel_exactly_c_dt_per_step():
+    # §3.1: a packet moves c dt per step whatever it crosses.  In a
+    # transparent box the packets cast at step j sit at (k - j + 1) c dt from
+    # their source after step k (children are re-centred at their parent's
+    # radius), and each such shell holds the HEALPix count of the level
+    # reached at that radius (Eqs. Nray, r_split).
+    n, dx, dt = 64, 1e21, 1e13
+    step_cells = 3.7
+    o, _ = _transparent(n, c_ray=step_cells * dx / dt)
+    for k in range(1, 5):
+        o.step(dt, W.rotation_uniforms(3, k - 1, 1))
+        r = o.flight_radii() / dx
+        L = o.ledger()
+        assert r.size == L["n_in_flight"]
+        shells = np.rint(r / step_cells)
+        assert np.allclose(r, shells * step_cells, rtol=1e-13, atol=0)
+        for m in range(1, k + 1):
+            levels = sum(1 for l in range(20) if O.split_radius(1.0, l, 1.0) <= m * step_cells)
+            assert int((shells == m).sum()) == 12 * 4 ** levels, (k, m)
+        assert int(shells.min()) == 1 and int(shells.max()) == k
+        assert L["in_flight"] == pytest.approx(L["emitted"], rel=1e-13)
