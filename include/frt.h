@@ -221,6 +221,23 @@ int frt_set_rotations(frt_solve s, int n_steps, const double* uniforms);
  * loaded. */
 int frt_step(frt_solve s, double dt_s);
 
+/* frt_step without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The pass queues live in a static device array of
+ * FRT_STATIC_SCRATCH_BYTES = 48 MiB that every GPU the library runs on holds
+ * until the process ends (at most 4096 bricks, and about 3.2e5 packets per
+ * pass in FP32, 2e5 in FP64); the solve's own buffers are those its loading
+ * calls allocated.  Results equal frt_step's up to the order of floating-
+ * point additions.  A step that needs more than the array holds returns
+ * FRT_EOVERFLOW and is not applied (the solve stays at the start of the
+ * step); a grid of more bricks is FRT_EINVAL; a solve whose rotation table
+ * (64 steps from frt_load_sources, extended by frt_step) is used up is
+ * FRT_ESTATE.  Kernel timing is not recorded.  Calls in one process take the
+ * array one at a time, each to its end (the call waits for its step); the
+ * array keeps the last call's contents, and every call clears what it needs
+ * cleared. */
+int frt_step_static(frt_solve s, double dt_s);
+
 /* One step (as frt_step) of each of n solves as one set of launches: the
  * solves' bricks share one pass queue and one march launch per pass, so a
  * batch of small boxes fills the GPU as one large box does.  The solves must

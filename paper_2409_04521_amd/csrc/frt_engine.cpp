@@ -645,11 +645,11 @@ int upload_group(Workspace& ws, const Group& g, int n, hipStream_t st)
 // being captured: it starts by saving each solve's ledger and carried count
 // (for a re-run after an overflow) and ends by advancing the step index on
 // the device; nothing in it reads host memory or records events.
-int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_t st, bool graph)
+int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_t st, bool graph, bool timed = true)
 {
     const int fp64 = ss[0]->fp64;
     FrtWS w = g.w;
-    frt_solve tm = (!graph && ss[0]->timing) ? ss[0] : nullptr;
+    frt_solve tm = (timed && !graph && ss[0]->timing) ? ss[0] : nullptr;
     hipError_t e;
     // every solve's ledger and carried-queue counters as the step starts, for
     // a re-run after an overflow (one kernel for the whole group)
@@ -1339,6 +1339,10 @@ int frt_ctx_create(int hip_device, frt_alloc_fn alloc_fn, frt_free_fn free_fn, v
     if (e != hipSuccess || n == 0) return fail(FRT_EDEVICE, "no HIP device available (%s)", hipGetErrorString(e));
     if (hip_device < 0 || hip_device >= n) return fail(FRT_EINVAL, "device %d out of range [0,%d)", hip_device, n);
     HIPCHK(hipSetDevice(hip_device));
+    // the allocation-free step's scratch: its device address on this device
+    void* scratch = nullptr;
+    const hipError_t es = frt::static_scratch(hip_device, &scratch);
+    if (es != hipSuccess) return fail(FRT_EDEVICE, "static scratch lookup: %s", hipGetErrorString(es));
     frt_ctx c = new (std::nothrow) frt_ctx_s;
     if (!c) return fail(FRT_ENOMEM, "context");
     c->device = hip_device;
@@ -1697,6 +1701,100 @@ int frt_step(frt_solve s, double dt)
     if (!(dt > 0) || !std::isfinite(dt)) return fail(FRT_EINVAL, "dt must be finite and > 0");
     HIPCHK(hipSetDevice(s->ctx->device));
     return step_group(&s, 1, &dt);
+}
+
+int frt_step_static(frt_solve s, double dt)
+{
+    RCCHK(ready(s));
+    if (!(dt > 0) || !std::isfinite(dt)) return fail(FRT_EINVAL, "dt must be finite and > 0");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    if (s->step >= s->quat_steps)
+        return fail(FRT_ESTATE, "the solve's rotation table holds %u steps; an allocating call (frt_step) extends it",
+                    s->quat_steps);
+    const uint64_t nkeys = (uint64_t)s->bpx * s->bpy * s->bpz;
+    if (nkeys > FRT_STATIC_MAX_KEYS)
+        return fail(FRT_EINVAL, "the grid holds %llu bricks; the allocation-free step takes at most %u",
+                    (unsigned long long)nkeys, FRT_STATIC_MAX_KEYS);
+    void* base = nullptr;
+    const hipError_t es = frt::static_scratch(s->ctx->device, &base);
+    if (es != hipSuccess) return fail(FRT_EDEVICE, "static scratch lookup: %s", hipGetErrorString(es));
+    // every call in this process shares the array: one at a time, each to its end
+    static std::mutex scratch_mu;
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    // the smallest work items: a pass of a small solve is then spread over
+    // many workgroups, and so over all the output segments (each holds a
+    // 64th of the queue)
+    Workspace sw;
+    sw.tune.item_rays = 64;
+    sw.tune.scatter_blocks_per_cu = 8;
+    sw.fp64 = s->fp64;
+    sw.nb = s->P.n_bins;
+    // carve the scratch: small tables first, then the march scratch records,
+    // then the pass queues in what is left
+    const size_t rb = rec_bytes(s->rs);
+    char* p = (char*)base;
+    size_t left = FRT_STATIC_SCRATCH_BYTES;
+    auto take = [&](size_t bytes) -> void* {
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (bytes > left) return nullptr;
+        void* q = p;
+        p += bytes;
+        left -= bytes;
+        return q;
+    };
+    sw.descs = (FrtSolveDesc*)take(sizeof(FrtSolveDesc));
+    sw.solves_cap = 1;
+    sw.key_prefix = (uint32_t*)take(8);
+    sw.seed_prefix = (uint32_t*)take(8);
+    sw.cell_prefix = (unsigned long long*)take(16);
+    sw.ctr = (uint32_t*)take(C_NCTR * 4);
+    sw.segc = (uint32_t*)take((size_t)FRT_QSEG * FRT_QSEG_STRIDE * 4);
+    sw.segp = (uint32_t*)take((FRT_QSEG + 1) * 4);
+    sw.hist = (uint32_t*)take(FRT_STATIC_MAX_KEYS * 4);
+    sw.cursor = (uint32_t*)take(FRT_STATIC_MAX_KEYS * 4);
+    sw.nkeys_cap = FRT_STATIC_MAX_KEYS;
+    const uint32_t xcap = (uint32_t)frt::device_cu_count() * FRT_STATIC_XREC_PER_CU;
+    sw.X.rec = take((size_t)xcap * rb);
+    sw.X.cap = xcap;
+    // pass queues: per record two output records, two keys, a sorted entry
+    // and a share of the work list (items of at least 64 packets, plus one
+    // per brick)
+    const size_t work_fixed = ((size_t)FRT_STATIC_MAX_KEYS + 64) * sizeof(FrtWork) + 6 * 256;
+    if (!sw.X.rec || left < work_fixed) return fail(FRT_EINVAL, "static scratch too small");
+    const size_t per = 2 * rb + 2 * 4 + sizeof(uint2) + sizeof(FrtWork) / 64 + 1;
+    const uint32_t pcap = (uint32_t)((left - work_fixed) / per);
+    sw.pcap = pcap;
+    for (int k = 0; k < 2; k++) {
+        sw.O[k].rec = take((size_t)pcap * rb);
+        sw.O[k].cap = pcap;
+        sw.okey[k] = (uint32_t*)take((size_t)pcap * 4);
+    }
+    sw.sorted = (uint2*)take((size_t)pcap * sizeof(uint2));
+    sw.cap_work = pcap / (uint32_t)sw.tune.item_rays + FRT_STATIC_MAX_KEYS + 64;
+    sw.work = (FrtWork*)take((size_t)sw.cap_work * sizeof(FrtWork));
+    if (!sw.O[0].rec || !sw.O[1].rec || !sw.okey[0] || !sw.okey[1] || !sw.sorted || !sw.work)
+        return fail(FRT_EINVAL, "static scratch layout does not fit");
+    hipStream_t st = s->stream;
+    set_step_fields(s, dt);
+    Group g;
+    frt_solve one = s;
+    plan_group(sw, &one, 1, g);
+    RCCHK(upload_group(sw, g, 1, st));
+    RCCHK(enqueue_step(sw, &one, 1, g, st, false, false));
+    uint32_t ctr[C_NCTR];
+    HIPCHK(hipMemcpyAsync(ctr, sw.ctr, sizeof(ctr), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (ctr[C_ERR] & (FRT_DEVERR_QUEUE_OVERFLOW | FRT_DEVERR_CARRY_OVERFLOW)) {
+        RCCHK(restore_step_start(&one, 1, st));
+        if (ctr[C_ERR] & FRT_DEVERR_QUEUE_OVERFLOW)
+            return fail(FRT_EOVERFLOW, "a pass of the step needs more than the static scratch's queue (%u packets, a "
+                        "64th per output segment; largest pass %u); the step was not applied", pcap, ctr[C_MAXP]);
+        return fail(FRT_EOVERFLOW, "the solve's carried-packet queue (%u) is too small for the step; it was not "
+                    "applied (frt_step grows it)", s->F[0].cap);
+    }
+    if (ctr[C_ERR] & FRT_DEVERR_UNFINISHED) return fail(FRT_EDEVICE, "a step left packets after its last pass");
+    s->step++;
+    return FRT_OK;
 }
 
 int frt_batch_step(frt_solve* ss, int n, const double* dts)

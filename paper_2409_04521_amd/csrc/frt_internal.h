@@ -204,7 +204,18 @@ struct FrtWS {
     int scatter_bpc;            // workgroups per CU of the scatter pass
 };
 
+// Scratch of the allocation-free step (frt_step_static): the pass workspace
+// of one small solve in a file-scope device array of this many bytes, which
+// every GPU the library runs on holds until the process ends; at most this
+// many brick keys and this many march scratch records per compute unit.
+constexpr size_t FRT_STATIC_SCRATCH_BYTES = size_t(48) << 20;
+constexpr uint32_t FRT_STATIC_MAX_KEYS = 4096;
+constexpr uint32_t FRT_STATIC_XREC_PER_CU = 256;
+
 namespace frt {
+// Device address of the static scratch on `device` (which must be current),
+// looked up with hipGetSymbolAddress on the first call per device and kept.
+hipError_t static_scratch(int device, void** ptr);
 hipError_t launch_seed(FrtSolveDesc* d, const FrtWS& ws, int fp64, hipStream_t s);
 // part 0: counting scan, 1: scatter into brick order, 2: brick march
 // (which also writes the children of the packets that split)

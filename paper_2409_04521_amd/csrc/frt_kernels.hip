@@ -1863,6 +1863,11 @@ __global__ void __launch_bounds__(BLOCK) k_prep(FrtSolveDesc* desc, unsigned lon
     }
 }
 
+// The allocation-free step's scratch (FRT_STATIC_SCRATCH_BYTES per GPU).  In
+// host code `scratch` names a host-side stand-in, not device memory: host code
+// uses the device address that static_scratch() looks up, never the name.
+static __device__ __align__(256) unsigned char scratch[FRT_STATIC_SCRATCH_BYTES];
+
 // Compute units of the current device, queried once (the server's loader
 // threads may ask for it at the same time: a function-local static is
 // initialized exactly once)
@@ -1983,6 +1988,27 @@ hipError_t pass_t(FrtSolveDesc* d, const FrtWS& ws, int part, hipStream_t s)
 namespace frt {
 
 int device_cu_count() { return cu_count(); }
+
+hipError_t static_scratch(int device, void** ptr)
+{
+    constexpr int MAX_DEVICES = 64;
+    static std::mutex mu;
+    static void* addr[MAX_DEVICES] = {};
+    *ptr = nullptr;
+    if (device < 0 || device >= MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!addr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        addr[device] = p;
+    }
+    *ptr = addr[device];
+    return hipSuccess;
+}
 
 hipError_t launch_seed(FrtSolveDesc* d, const FrtWS& ws, int fp64, hipStream_t s)
 {

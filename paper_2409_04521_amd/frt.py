@@ -29,7 +29,7 @@ EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_
            "frt_rotation_uniforms", "frt_batch_run", "frt_tuning_default", "frt_ctx_set_tuning",
            "frt_ctx_get_tuning", "frt_autotune", "frt_request_bytes", "frt_server_create", "frt_server_submit",
            "frt_server_poll", "frt_server_wait", "frt_server_take", "frt_server_times", "frt_server_get_stats",
-           "frt_server_destroy", "frt_debug_cast")
+           "frt_server_destroy", "frt_debug_cast", "frt_step_static")
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
@@ -156,6 +156,7 @@ def lib():
         L.frt_set_opacity.argtypes = [vp, vp, C.c_int]
         L.frt_set_rotations.argtypes = [vp, C.c_int, vp]
         L.frt_step.argtypes = [vp, C.c_double]
+        L.frt_step_static.argtypes = [vp, C.c_double]
         L.frt_batch_step.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_double)]
         L.frt_sync.argtypes = [vp]
         L.frt_read_fields.argtypes = [vp, vp, vp, C.c_int]
@@ -332,6 +333,10 @@ class Solve:
 
     def step(self, dt_s: float):
         _check(lib().frt_step(self.h, float(dt_s)))
+
+    def step_static(self, dt_s: float):
+        """One step that allocates no device memory (frt_step_static)."""
+        _check(lib().frt_step_static(self.h, float(dt_s)))
 
     def sync(self):
         _check(lib().frt_sync(self.h))
