@@ -199,7 +199,8 @@ class Oracle:
         u = np.ascontiguousarray(uniforms, dtype=np.float64).reshape(-1)
         assert u.size == 3 * self.n_src
         if threads is None:
-            threads = os.cpu_count() or 1
+            # the host's share of cores where a launcher states it, else all
+            threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
         if lib().orc_step(self.h, dt_s, u if u.size else np.zeros(3), int(threads)) != 0:
             raise MemoryError("oracle: step")
 

@@ -10,6 +10,13 @@ benchmark times, checked where the oracle can follow it:
   every packet sees the start-of-step opacity, so the rate field and every
   ledger term are sums over sources; the full step must equal the sum of the
   steps of its even and odd sources, and its ledger must close.
+* at all 2000 sources against the oracle: the oracle marches the same step
+  in eight calls of 250 sources each on the same start-of-step state (the
+  rate field and the ledger of a step are sums over sources, since every
+  packet sees the start-of-step opacity), the rates are summed and the
+  oracle's backward-Euler chemistry is applied to the sum;
+* the neutral, finite-c form of the workload at 128^3 with 200 sources for
+  its 20 steps against the oracle in full.
 The benchmark's time-averaged chemistry and Generalized Opacity Mode legs
 (128^3 lognormal box, 64 sources, finite c, 12 steps) are small enough for
 the oracle to follow in full, at the same bars.
@@ -79,10 +86,56 @@ def test_sampled_sources_on_the_full_grid_match_the_oracle(ctx, full):
     assert Lg["err_flags"] == 0 and Lg["lost"] == 0
 
 
-def test_full_step_is_the_sum_of_its_source_halves(ctx, full):
+@pytest.fixture(scope="module")
+def gpu_full(ctx, full):
+    """The benchmark's step on the GPU: all 2000 sources, its queue size."""
     p, table = full
-    hint = int(3.6e8)
-    _, g_all, L_all = _gpu_step(ctx, p, table, queue_hint=hint)
+    return _gpu_step(ctx, p, table, queue_hint=int(3.6e8))
+
+
+def test_full_step_all_sources_match_the_oracle(full, gpu_full, capfd):
+    p, table = full
+    xg, gg, Lg = gpu_full
+    chunks = np.array_split(np.arange(p.n_src), 8)
+    gamma = np.zeros(p.shape)
+    Lo = {k: 0.0 for k in TERMS}
+    Lo["crossings"] = 0
+    for k, idx in enumerate(chunks):
+        q = _subset(p, idx)
+        o = O.Oracle(**q.oracle_kwargs())
+        o.set_sources(q.src_pos_cm, q.ndot_bins)
+        o.step(q.dt_s, table[0, idx, :])
+        gamma += o.fields()[1]
+        L = o.ledger()
+        for t in Lo:
+            Lo[t] += L[t]
+        o.close()
+        with capfd.disabled():
+            print(f"  oracle: sources {idx[0]}-{idx[-1]} marched, {L['crossings']} crossings", flush=True)
+    xo = O.chemistry_field(p.x_HI0, gamma, p.n_H.astype(np.float64), p.alpha_B, p.coll_ion, p.dt_s)
+    dx = float(np.abs(xo - xg).max())
+    dg = float(np.abs(gamma - gg).max()) / float(gamma.max())
+    worst = {k: abs(Lo[k] - Lg[k]) / Lo["emitted"] for k in TERMS}
+    with capfd.disabled():
+        print(f"[256^3, all 2000 sources] max|dx_HI| = {dx:.3e}, max|dGamma|/max = {dg:.3e}, ledger rel = "
+              + ", ".join(f"{k}:{v:.1e}" for k, v in worst.items())
+              + f", crossings oracle={Lo['crossings']} gpu={Lg['crossings']}", flush=True)
+    assert dx <= 1e-3
+    assert dg <= 2e-3
+    for k, v in worst.items():
+        assert v <= 1e-4, k
+
+
+def test_c3a_neutral_finite_c_128_cubed_200_sources(ctx):
+    # the parity form of the workload at the survey's parity size: neutral
+    # start, packets at c carried between 1 Myr steps, same cell size
+    p = W.grf_c3(n=128, n_src=200, throughput=False, n_steps=20, box_cmpc_h=50.0)
+    _leg_parity(ctx, p, 20, "C3a 128^3 200 sources c")
+
+
+def test_full_step_is_the_sum_of_its_source_halves(ctx, full, gpu_full):
+    p, table = full
+    _, g_all, L_all = gpu_full
     E = L_all["emitted"]
     closure = abs(E - sum(L_all[k] for k in TERMS[1:]) - L_all["lost"]) / E
     assert closure <= 1e-9, closure
