@@ -46,6 +46,14 @@
  *                         kappa = n_HI sigma_0 and x_ion = 1 (§4.2), closure.
  *   orc_step              photon ledger closure, Stromgren I-front
  *                         (Eqs. r_of_t, rS, trec), checkpoint equality.
+ *   merge_carried         (§3.3 ray merging) photons conserved per bin, the
+ *                         exempt set is the N_ex N_RT brightest packets, at
+ *                         most 12 4^l_merge merged packets per cell, and every
+ *                         merged packet equals a brute-force regrouping of
+ *                         the packets before the merge (photon sums,
+ *                         photon-weighted positions, distances and levels,
+ *                         the merging pixel's direction); merging with every
+ *                         packet exempt changes nothing.
  *   Whole-field values beyond these properties: parity unpinned (the paper
  *   prints no per-cell numbers).
  */
@@ -81,12 +89,17 @@ typedef struct {
                                 coefficient at sigma_0, x = 1 - x_ion the neutral
                                 volume fraction behind a moving screen */
     double he_chi;           /* chi of Eq. dxidt (helium singly ionized with H) */
+    int merge;               /* 1: merge the carried packets at the end of each step (§3.3) */
+    int merge_level;         /* l_merge: level of each cell's merging HEALPix sphere */
+    double merge_exempt;     /* N_ex: floor(N_ex N_RT) brightest packets are exempt */
 } orc_params;
 
 typedef struct {
     double emitted, absorbed_HI, absorbed_sub, escaped, dropped, in_flight;
     long long crossings, rays_emitted, splits, n_escaped, n_dropped, n_in_flight;
     double absorbed_front;   /* photons stopped by I-fronts (Generalized Opacity Mode) */
+    double merge_residual;   /* photons held before minus after the merges (rounding only) */
+    long long merges, rays_merged; /* merged packets made, and packets merged into them */
 } orc_ledger;
 
 /* Photon totals are sums of up to ~1e9 terms; they are accumulated with
@@ -109,15 +122,17 @@ typedef struct {
     long long crossings, rays_emitted, splits, n_escaped, n_dropped, n_in_flight;
 } chunk_ledger;
 
-/* One ray (photon packet).  Its position is always src + r * dir: children
- * are re-centred on their own pixel directions at the split radius
- * (§3.2), so the distance from the source fully fixes the position. */
+/* One ray (photon packet).  Its position is always origin + r * dir:
+ * children are re-centred on their own pixel directions at the split radius
+ * (§3.2), so the distance from the origin fully fixes the position. */
 typedef struct {
-    int src;
+    int src;                 /* emitting source, or -1 for a merged packet */
     int level;
     long long pix;
     double dir[3];
     double R[9];             /* rotation of the emitting step, inherited (§3.1, §3.2) */
+    double origin[3];        /* the point the packet travels from, cm: its source, or the
+                                virtual origin of a merged packet (position - r dir) */
     double r;                /* distance travelled from the source, cm */
     double r_stop;           /* distance at which this step's travel budget ends */
     double N[ORC_MAX_BINS];      /* photons carried per bin */
@@ -139,7 +154,7 @@ typedef struct {
     int nsrc;
     double* src_pos;         /* nsrc*3, cm */
     double* ndot;            /* nsrc*n_bins, photons/s */
-    orc_vec* flight;         /* per-source in-flight packets carried between steps */
+    orc_vec carried;         /* packets carried into the next step, in a fixed order */
     orc_ledger L;
     long long step;
     long long last_crossings;
@@ -356,7 +371,7 @@ static void march_one_ray(march_ctx* M, orc_ray* ray)
 {
     const orc_params* P = &M->S->p;
     const int nb = P->n_bins;
-    const double* o = M->S->src_pos + 3 * ray->src;
+    const double* o = ray->origin;
     const double r_split = (ray->level < P->max_level) ? split_radius(P->dx, ray->level, P->n_ray_min) : INFINITY;
     const double r_cap = (P->max_dist > 0.0) ? P->max_dist : INFINITY;
     double pos[3];
@@ -521,6 +536,171 @@ double chemistry_avg(double x0, double gamma, double ne, double alpha, double co
     return xeq + (x0 - xeq) * (-expm1(-y) / y);
 }
 
+/* ------------------------------------------------------------- merging */
+/* §3.3: at the end of a step the carried packets are ranked by their
+ * photons; the floor(N_ex N_RT) brightest are exempt (every packet with at
+ * least the photons of the last of them: ties at the threshold are all
+ * exempt).  The others are grouped by the cell they are in and by the pixel,
+ * on a HEALPix sphere of level l_merge rotated at random for that cell and
+ * step, that holds their direction.  A group of one is left as it is; a
+ * larger group becomes one packet with the summed photons of every bin,
+ * travelling along the pixel's centre, its position, distance from its origin
+ * and level the photon-weighted means of its members' (the level rounded to
+ * the nearest integer), its initial photons its photons at the merge.  So
+ * that it moves and splits like any packet, it gets the virtual origin
+ * position - r dir and a rotation that takes the centre of its level-l pixel
+ * pix_v (the descendant or ancestor of the merging pixel p along the first
+ * nested sub-pixel) onto the merged direction: the cell's sphere rotation
+ * after the shortest rotation from n(l, pix_v) to n(l_merge, p). */
+
+/* The merging sphere of each cell is rotated by a uniform rotation drawn
+ * from three uniforms per (step, cell), passed in as inputs (umerge[3 cell]). */
+
+/* Shortest rotation taking unit vector a onto unit vector b (Rodrigues):
+ * R = I + [v]x + [v]x^2 / (1 + c), v = a x b, c = a . b (a != -b). */
+static void rotation_between(const double a[3], const double b[3], double R[9])
+{
+    const double v[3] = {a[1] * b[2] - a[2] * b[1], a[2] * b[0] - a[0] * b[2], a[0] * b[1] - a[1] * b[0]};
+    const double c = a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+    const double K[9] = {0, -v[2], v[1], v[2], 0, -v[0], -v[1], v[0], 0};
+    const double f = 1.0 / (1.0 + c);
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double k2 = 0.0;
+            for (int m = 0; m < 3; m++) k2 += K[3 * i + m] * K[3 * m + j];
+            R[3 * i + j] = (i == j ? 1.0 : 0.0) + K[3 * i + j] + f * k2;
+        }
+}
+
+static void mat_mul(const double A[9], const double B[9], double C[9])
+{
+    for (int i = 0; i < 3; i++)
+        for (int j = 0; j < 3; j++) {
+            double v = 0.0;
+            for (int m = 0; m < 3; m++) v += A[3 * i + m] * B[3 * m + j];
+            C[3 * i + j] = v;
+        }
+}
+
+typedef struct {
+    long long key;           /* cell * 2^20 + merging pixel */
+    long long idx;
+} merge_key;
+
+static int cmp_desc_double(const void* a, const void* b)
+{
+    const double x = *(const double*)a, y = *(const double*)b;
+    return (x < y) - (x > y);
+}
+
+static int cmp_merge_key(const void* a, const void* b)
+{
+    const merge_key* x = (const merge_key*)a;
+    const merge_key* y = (const merge_key*)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+/* Merge the carried packets in *list (in place: exempt and ungrouped packets
+ * keep their order, the merged packets follow in (cell, pixel) order). */
+static int merge_carried(const orc_state* S, orc_vec* list, const double* umerge, orc_ledger* L)
+{
+    const orc_params* P = &S->p;
+    const int nb = P->n_bins;
+    const long long n = list->n;
+    const long long E = (long long)floor(P->merge_exempt * (double)S->ncell);
+    if (n == 0 || E >= n) return 0;
+    double* ph = (double*)malloc(sizeof(double) * n);
+    double* sorted = (double*)malloc(sizeof(double) * n);
+    merge_key* keys = (merge_key*)malloc(sizeof(merge_key) * n);
+    orc_ray* out = (orc_ray*)malloc(sizeof(orc_ray) * n);
+    if (!ph || !sorted || !keys || !out) return -1;
+    for (long long j = 0; j < n; j++) ph[j] = sum_bins(list->v[j].N, nb);
+    memcpy(sorted, ph, sizeof(double) * n);
+    qsort(sorted, n, sizeof(double), cmp_desc_double);
+    const double T = E >= 1 ? sorted[E - 1] : INFINITY;
+    csum before = {0, 0}, after = {0, 0};
+    long long nk = 0, m = 0;
+    for (long long j = 0; j < n; j++) {
+        csum_add(&before, ph[j]);
+        const orc_ray* r = &list->v[j];
+        if (ph[j] >= T) continue;
+        double pos[3];
+        long long c[3];
+        for (int a = 0; a < 3; a++) pos[a] = r->origin[a] + r->r * r->dir[a];
+        locate(P, pos, r->dir, c);
+        const long long cell = c[0] + (long long)P->nx * (c[1] + (long long)P->ny * c[2]);
+        double R[9], nloc[3];
+        shoemake_rotation(umerge + 3 * cell, R);
+        for (int a = 0; a < 3; a++) nloc[a] = R[a] * r->dir[0] + R[3 + a] * r->dir[1] + R[6 + a] * r->dir[2];
+        const long long pix = healpix_nest_pixel(P->merge_level, nloc);
+        keys[nk].key = cell * (1LL << 20) + pix;
+        keys[nk].idx = j;
+        nk++;
+    }
+    qsort(keys, nk, sizeof(merge_key), cmp_merge_key);
+    /* the exempt packets and the groups of one keep their place in the list */
+    char* keep = (char*)calloc(n, 1);
+    if (!keep) return -1;
+    for (long long j = 0; j < n; j++) keep[j] = ph[j] >= T;
+    for (long long g = 0; g < nk;) {
+        long long h = g + 1;
+        while (h < nk && keys[h].key == keys[g].key) h++;
+        if (h - g == 1) keep[keys[g].idx] = 1;
+        g = h;
+    }
+    m = 0;
+    for (long long j = 0; j < n; j++)
+        if (keep[j]) out[m++] = list->v[j];
+    free(keep);
+    for (long long g = 0; g < nk;) {
+        long long h = g + 1;
+        while (h < nk && keys[h].key == keys[g].key) h++;
+        if (h - g >= 2) {
+            orc_ray mr;
+            memset(&mr, 0, sizeof(mr));
+            double W = 0.0, pos[3] = {0, 0, 0}, rsum = 0.0, lsum = 0.0;
+            for (long long q = g; q < h; q++) {
+                const orc_ray* r = &list->v[keys[q].idx];
+                const double w = ph[keys[q].idx];
+                W += w;
+                for (int a = 0; a < 3; a++) pos[a] += w * (r->origin[a] + r->r * r->dir[a]);
+                rsum += w * r->r;
+                lsum += w * (double)r->level;
+                for (int b = 0; b < nb; b++) mr.N[b] += r->N[b];
+            }
+            const long long cell = keys[g].key >> 20;
+            const long long p = keys[g].key & ((1LL << 20) - 1);
+            for (int a = 0; a < 3; a++) pos[a] /= W;
+            mr.r = rsum / W;
+            mr.r_stop = mr.r;
+            mr.level = (int)floor(lsum / W + 0.5);
+            const int lm = P->merge_level;
+            mr.pix = mr.level >= lm ? p << (2 * (mr.level - lm)) : p >> (2 * (lm - mr.level));
+            double Rc[9], nb_m[3], nb_v[3], RA[9];
+            shoemake_rotation(umerge + 3 * cell, Rc);
+            healpix_nest_center(lm, p, nb_m);
+            healpix_nest_center(mr.level, mr.pix, nb_v);
+            rotation_between(nb_v, nb_m, RA);
+            mat_mul(Rc, RA, mr.R);
+            set_direction(&mr);
+            for (int a = 0; a < 3; a++) mr.origin[a] = pos[a] - mr.r * mr.dir[a];
+            for (int b = 0; b < nb; b++) mr.Ninit[b] = mr.N[b];
+            mr.src = -1;
+            out[m++] = mr;
+            L->merges++;
+            L->rays_merged += h - g;
+        }
+        g = h;
+    }
+    for (long long j = 0; j < m; j++) csum_add(&after, sum_bins(out[j].N, nb));
+    L->merge_residual += csum_get(&before) - csum_get(&after);
+    memcpy(list->v, out, sizeof(orc_ray) * m);
+    list->n = m;
+    free(ph); free(sorted); free(keys); free(out);
+    return 0;
+}
+
 /* ------------------------------------------------------------ state API */
 orc_state* orc_create(const orc_params* P, const float* nH, const float* kappa, const double* x0)
 {
@@ -554,10 +734,7 @@ void orc_set_kappa(orc_state* S, const float* kappa)
 void orc_destroy(orc_state* S)
 {
     if (!S) return;
-    if (S->flight) {
-        for (int s = 0; s < S->nsrc; s++) free(S->flight[s].v);
-        free(S->flight);
-    }
+    free(S->carried.v);
     free(S->nH); free(S->kappa); free(S->x); free(S->gamma);
     free(S->src_pos); free(S->ndot);
     free(S);
@@ -565,16 +742,13 @@ void orc_destroy(orc_state* S)
 
 int orc_set_sources(orc_state* S, int nsrc, const double* pos, const double* ndot)
 {
-    if (S->flight) {
-        for (int s = 0; s < S->nsrc; s++) free(S->flight[s].v);
-        free(S->flight);
-    }
+    free(S->carried.v);
+    memset(&S->carried, 0, sizeof(S->carried));
     free(S->src_pos); free(S->ndot);
     S->nsrc = nsrc;
     S->src_pos = (double*)malloc(sizeof(double) * 3 * (nsrc > 0 ? nsrc : 1));
     S->ndot = (double*)malloc(sizeof(double) * S->p.n_bins * (nsrc > 0 ? nsrc : 1));
-    S->flight = (orc_vec*)calloc(nsrc > 0 ? nsrc : 1, sizeof(orc_vec));
-    if (!S->src_pos || !S->ndot || !S->flight) return -1;
+    if (!S->src_pos || !S->ndot) return -1;
     memcpy(S->src_pos, pos, sizeof(double) * 3 * nsrc);
     memcpy(S->ndot, ndot, sizeof(double) * S->p.n_bins * nsrc);
     return 0;
@@ -594,7 +768,7 @@ int orc_set_sources(orc_state* S, int nsrc, const double* pos, const double* ndo
  * same packets, and only the last one's deposits, ledger and carried packets
  * are kept; x(dt) (Eq. xi_of_t) then uses the last Gamma and n_e of the last
  * estimate. */
-int orc_step(orc_state* S, double dt, const double* u, int nthreads)
+int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int nthreads)
 {
     const orc_params* P = &S->p;
     const int nb = P->n_bins;
@@ -603,7 +777,7 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
     double* nHI = (double*)malloc(sizeof(double) * N);
     double* gk = (double*)calloc((size_t)K * N, sizeof(double));
     chunk_ledger* Lk = (chunk_ledger*)calloc(K, sizeof(chunk_ledger));
-    orc_vec* new_flight = (orc_vec*)calloc(S->nsrc > 0 ? S->nsrc : 1, sizeof(orc_vec));
+    orc_vec* new_flight = (orc_vec*)calloc(K, sizeof(orc_vec));   /* per chunk */
     if (!nHI || !gk || !Lk || !new_flight) return -1;
     const int n_iter = P->chem_iterations > 0 ? P->chem_iterations : 1;
     const int gen = P->opacity_mode == 1;
@@ -631,9 +805,9 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
             /* the march starts again from the step's packets */
             memset(gk, 0, sizeof(double) * (size_t)K * N);
             memset(Lk, 0, sizeof(chunk_ledger) * K);
-            for (int s = 0; s < S->nsrc; s++) {
-                free(new_flight[s].v);
-                memset(&new_flight[s], 0, sizeof(orc_vec));
+            for (int k = 0; k < K; k++) {
+                free(new_flight[k].v);
+                memset(&new_flight[k], 0, sizeof(orc_vec));
             }
         }
 
@@ -644,16 +818,17 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
             M.S = S; M.nHI = nHI; M.gamma = gk + (size_t)k * N; M.L = Lk + k;
             M.stack = &stack; M.inv_vdt = 1.0 / (V * dt);
             M.xion = xion; M.front = gen ? fk + (size_t)k * N : NULL;
+            M.flight_out = &new_flight[k];
+            /* packets carried from the previous step get a fresh budget */
+            const long long nc = S->carried.n;
+            for (long long j = nc * k / K; j < nc * (k + 1) / K; j++) {
+                orc_ray ray = S->carried.v[j];
+                ray.r_stop = ray.r + P->c_ray * dt;
+                march_one_ray(&M, &ray);
+                drain(&M);
+            }
             int s0 = (int)(((long long)S->nsrc * k) / K), s1 = (int)(((long long)S->nsrc * (k + 1)) / K);
             for (int s = s0; s < s1; s++) {
-                M.flight_out = &new_flight[s];
-                /* packets carried from the previous step get a fresh budget */
-                for (long long j = 0; j < S->flight[s].n; j++) {
-                    orc_ray ray = S->flight[s].v[j];
-                    ray.r_stop = ray.r + P->c_ray * dt;
-                    march_one_ray(&M, &ray);
-                    drain(&M);
-                }
                 /* casting on this step's rotated sphere (§3.1, Eq. Nray) */
                 double R[9];
                 shoemake_rotation(u + 3 * s, R);
@@ -662,6 +837,7 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
                     memset(&ray, 0, sizeof(ray));
                     ray.src = s; ray.level = P->base_level; ray.pix = p;
                     memcpy(ray.R, R, sizeof(R));
+                    for (int a = 0; a < 3; a++) ray.origin[a] = S->src_pos[3 * s + a];
                     set_direction(&ray);
                     ray.r = 0.0;
                     ray.r_stop = P->c_ray * dt;
@@ -721,17 +897,19 @@ int orc_step(orc_state* S, double dt, const double* u, int nthreads)
     S->L.absorbed_front = csum_get(&tot[5]);
     S->last_crossings = cross;
 
-    /* carried packets replace the old list */
+    /* carried packets replace the old list, in chunk order, then merge */
+    orc_vec list = {0, 0, 0};
+    for (int k = 0; k < K; k++)
+        for (long long j = 0; j < new_flight[k].n; j++)
+            if (vec_push(&list, &new_flight[k].v[j])) return -1;
+    for (int k = 0; k < K; k++) free(new_flight[k].v);
+    if (P->merge && umerge && merge_carried(S, &list, umerge, &S->L)) return -1;
+    free(S->carried.v);
+    S->carried = list;
     csum inflight = {0.0, 0.0};
-    long long nfl = 0;
-    for (int s = 0; s < S->nsrc; s++) {
-        free(S->flight[s].v);
-        S->flight[s] = new_flight[s];
-        for (long long j = 0; j < S->flight[s].n; j++) csum_add(&inflight, sum_bins(S->flight[s].v[j].N, nb));
-        nfl += S->flight[s].n;
-    }
+    for (long long j = 0; j < list.n; j++) csum_add(&inflight, sum_bins(list.v[j].N, nb));
     S->L.in_flight = csum_get(&inflight);
-    S->L.n_in_flight = nfl;
+    S->L.n_in_flight = list.n;
 
     /* chemistry closes the step */
     if (gen) {
@@ -792,7 +970,10 @@ int orc_debug_transmit(orc_state* S, const double o[3], const double d[3], const
     M.xion = NULL; M.front = NULL;
     orc_ray ray;
     memset(&ray, 0, sizeof(ray));
-    for (int a = 0; a < 3; a++) ray.dir[a] = d[a];
+    for (int a = 0; a < 3; a++) {
+        ray.dir[a] = d[a];
+        ray.origin[a] = o[a];
+    }
     ray.r = 0.0; ray.r_stop = INFINITY;
     for (int b = 0; b < P->n_bins; b++) { ray.N[b] = N[b]; ray.Ninit[b] = N[b]; }
     /* march with the exit photons captured per bin */
@@ -816,11 +997,43 @@ void orc_read(const orc_state* S, double* x, double* gamma)
  * step, in source order; returns how many there are (at most cap written). */
 long long orc_flight_radii(const orc_state* S, double* out, long long cap)
 {
-    long long k = 0;
-    for (int s = 0; s < S->nsrc; s++)
-        for (long long j = 0; j < S->flight[s].n; j++, k++)
-            if (k < cap) out[k] = S->flight[s].v[j].r;
-    return k;
+    for (long long j = 0; j < S->carried.n && j < cap; j++) out[j] = S->carried.v[j].r;
+    return S->carried.n;
+}
+
+/* The carried packets, one row of 9 + n_bins doubles each: r, origin (3),
+ * direction (3), level, pixel, photons per bin; returns how many there are
+ * (rows written up to cap). */
+long long orc_flight_dump(const orc_state* S, double* out, long long cap)
+{
+    const int w = 9 + S->p.n_bins;
+    for (long long j = 0; j < S->carried.n && j < cap; j++) {
+        const orc_ray* r = &S->carried.v[j];
+        double* o = out + j * w;
+        o[0] = r->r;
+        for (int a = 0; a < 3; a++) {
+            o[1 + a] = r->origin[a];
+            o[4 + a] = r->dir[a];
+        }
+        o[7] = r->level;
+        o[8] = (double)r->pix;
+        for (int b = 0; b < S->p.n_bins; b++) o[9 + b] = r->N[b];
+    }
+    return S->carried.n;
+}
+
+/* Merge the carried packets now, as the end of a step does (for tests: a
+ * step run without merging, then this). */
+int orc_merge_now(orc_state* S, const double* umerge)
+{
+    const double before = S->L.in_flight;
+    if (merge_carried(S, &S->carried, umerge, &S->L)) return -1;
+    csum inflight = {0.0, 0.0};
+    for (long long j = 0; j < S->carried.n; j++) csum_add(&inflight, sum_bins(S->carried.v[j].N, S->p.n_bins));
+    S->L.in_flight = csum_get(&inflight);
+    S->L.n_in_flight = S->carried.n;
+    (void)before;
+    return 0;
 }
 
 /* Backward-Euler update of a whole field (chemistry_be per cell): x_out[i]
@@ -838,9 +1051,8 @@ long long orc_step_index(const orc_state* S) { return S->step; }
 /* Checkpoint: neutral fraction, carried packets, ledger, step index. */
 long long orc_state_bytes(const orc_state* S)
 {
-    long long n = sizeof(long long) * 2 + sizeof(orc_ledger) + sizeof(double) * S->ncell;
-    for (int s = 0; s < S->nsrc; s++) n += sizeof(long long) + sizeof(orc_ray) * S->flight[s].n;
-    return n;
+    return (long long)(sizeof(long long) * 3 + sizeof(orc_ledger) + sizeof(double) * S->ncell +
+                       sizeof(orc_ray) * S->carried.n);
 }
 
 int orc_save(const orc_state* S, unsigned char* buf)
@@ -850,11 +1062,9 @@ int orc_save(const orc_state* S, unsigned char* buf)
     memcpy(p, hdr, sizeof(hdr)); p += sizeof(hdr);
     memcpy(p, &S->L, sizeof(orc_ledger)); p += sizeof(orc_ledger);
     memcpy(p, S->x, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
-    for (int s = 0; s < S->nsrc; s++) {
-        long long n = S->flight[s].n;
-        memcpy(p, &n, sizeof(n)); p += sizeof(n);
-        memcpy(p, S->flight[s].v, sizeof(orc_ray) * n); p += sizeof(orc_ray) * n;
-    }
+    long long n = S->carried.n;
+    memcpy(p, &n, sizeof(n)); p += sizeof(n);
+    memcpy(p, S->carried.v, sizeof(orc_ray) * n);
     return 0;
 }
 
@@ -867,16 +1077,14 @@ int orc_load(orc_state* S, const unsigned char* buf)
     S->step = hdr[0];
     memcpy(&S->L, p, sizeof(orc_ledger)); p += sizeof(orc_ledger);
     memcpy(S->x, p, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
-    for (int s = 0; s < S->nsrc; s++) {
-        long long n;
-        memcpy(&n, p, sizeof(n)); p += sizeof(n);
-        free(S->flight[s].v);
-        S->flight[s].v = NULL; S->flight[s].n = 0; S->flight[s].cap = 0;
-        for (long long j = 0; j < n; j++) {
-            orc_ray r;
-            memcpy(&r, p, sizeof(r)); p += sizeof(r);
-            vec_push(&S->flight[s], &r);
-        }
+    long long n;
+    memcpy(&n, p, sizeof(n)); p += sizeof(n);
+    free(S->carried.v);
+    memset(&S->carried, 0, sizeof(S->carried));
+    for (long long j = 0; j < n; j++) {
+        orc_ray r;
+        memcpy(&r, p, sizeof(r)); p += sizeof(r);
+        if (vec_push(&S->carried, &r)) return -1;
     }
     return 0;
 }

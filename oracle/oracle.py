@@ -36,7 +36,8 @@ class Params(C.Structure):
                 ("base_level", C.c_int), ("max_level", C.c_int), ("n_ray_min", C.c_double),
                 ("flux_floor", C.c_double), ("max_dist", C.c_double), ("c_ray", C.c_double),
                 ("n_chunks", C.c_int), ("chem_iterations", C.c_int), ("opacity_mode", C.c_int),
-                ("he_chi", C.c_double)]
+                ("he_chi", C.c_double), ("merge", C.c_int), ("merge_level", C.c_int),
+                ("merge_exempt", C.c_double)]
 
 
 class Ledger(C.Structure):
@@ -44,7 +45,8 @@ class Ledger(C.Structure):
                 ("escaped", C.c_double), ("dropped", C.c_double), ("in_flight", C.c_double),
                 ("crossings", C.c_longlong), ("rays_emitted", C.c_longlong), ("splits", C.c_longlong),
                 ("n_escaped", C.c_longlong), ("n_dropped", C.c_longlong), ("n_in_flight", C.c_longlong),
-                ("absorbed_front", C.c_double)]
+                ("absorbed_front", C.c_double), ("merge_residual", C.c_double), ("merges", C.c_longlong),
+                ("rays_merged", C.c_longlong)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -66,7 +68,10 @@ def lib():
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_set_kappa.argtypes = [C.c_void_p, C.c_void_p]
         L.orc_set_sources.argtypes = [C.c_void_p, C.c_int, dp, dp]
-        L.orc_step.argtypes = [C.c_void_p, C.c_double, dp, C.c_int]
+        L.orc_step.argtypes = [C.c_void_p, C.c_double, dp, C.c_void_p, C.c_int]
+        L.orc_flight_dump.restype = C.c_longlong
+        L.orc_flight_dump.argtypes = [C.c_void_p, C.c_void_p, C.c_longlong]
+        L.orc_merge_now.argtypes = [C.c_void_p, dp]
         L.orc_read.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p]
         L.orc_ledger_get.argtypes = [C.c_void_p, C.POINTER(Ledger)]
         L.orc_last_crossings.restype = C.c_longlong
@@ -147,7 +152,8 @@ class Oracle:
 
     def __init__(self, shape, dx_cm, sigma_bins, alpha_B, n_H, kappa=None, x_HI0=None,
                  coll_ion=0.0, base_level=0, max_level=12, n_ray_min=1.0, flux_floor=0.0,
-                 max_dist_cm=0.0, c_ray=np.inf, n_chunks=16, chem_iterations=0, opacity_mode=0, he_chi=0.0):
+                 max_dist_cm=0.0, c_ray=np.inf, n_chunks=16, chem_iterations=0, opacity_mode=0, he_chi=0.0,
+                 merge=False, merge_level=0, merge_exempt=0.0):
         nz, ny, nx = shape
         sig = list(sigma_bins)
         P = Params()
@@ -160,6 +166,7 @@ class Oracle:
         P.flux_floor, P.max_dist, P.c_ray, P.n_chunks = flux_floor, max_dist_cm, c_ray, n_chunks
         P.chem_iterations = chem_iterations
         P.opacity_mode, P.he_chi = opacity_mode, he_chi
+        P.merge, P.merge_level, P.merge_exempt = int(bool(merge)), merge_level, merge_exempt
         self.P = P
         self.shape = (nz, ny, nx)
         self.ncell = nx * ny * nz
@@ -195,13 +202,22 @@ class Oracle:
         if lib().orc_set_sources(self.h, self.n_src, pos.reshape(-1), nd.reshape(-1)) != 0:
             raise MemoryError("oracle: set_sources")
 
-    def step(self, dt_s, uniforms, threads=None):
+    def step(self, dt_s, uniforms, threads=None, merge_uniforms=None):
+        """One step; uniforms: three per source for the sphere rotations;
+        merge_uniforms: three per cell for the merging spheres (required
+        when merging)."""
         u = np.ascontiguousarray(uniforms, dtype=np.float64).reshape(-1)
         assert u.size == 3 * self.n_src
+        um = None
+        if self.P.merge:
+            assert merge_uniforms is not None, "merging needs the cells' sphere uniforms"
+            um = np.ascontiguousarray(merge_uniforms, dtype=np.float64).reshape(-1)
+            assert um.size == 3 * self.ncell
         if threads is None:
             # the host's share of cores where a launcher states it, else all
             threads = int(os.environ.get("OMP_NUM_THREADS", 0)) or os.cpu_count() or 1
-        if lib().orc_step(self.h, dt_s, u if u.size else np.zeros(3), int(threads)) != 0:
+        if lib().orc_step(self.h, dt_s, u if u.size else np.zeros(3), None if um is None else um.ctypes.data,
+                          int(threads)) != 0:
             raise MemoryError("oracle: step")
 
     def fields(self):
@@ -222,6 +238,24 @@ class Oracle:
         out = np.empty(max(n, 1))
         lib().orc_flight_radii(self.h, out.ctypes.data, n)
         return out[:n]
+
+    def flight(self) -> dict:
+        """The carried packets: r, origin (n, 3), dir (n, 3), level, pixel
+        and photons per bin (n, n_bins)."""
+        w = 9 + self.n_bins
+        n = int(lib().orc_flight_dump(self.h, None, 0))
+        a = np.empty((max(n, 1), w))
+        lib().orc_flight_dump(self.h, a.ctypes.data, n)
+        a = a[:n]
+        return {"r": a[:, 0], "origin": a[:, 1:4], "dir": a[:, 4:7], "level": a[:, 7].astype(int),
+                "pix": a[:, 8].astype(np.int64), "N": a[:, 9:]}
+
+    def merge_now(self, merge_uniforms):
+        """Merge the carried packets as the end of a step does."""
+        um = np.ascontiguousarray(merge_uniforms, dtype=np.float64).reshape(-1)
+        assert um.size == 3 * self.ncell
+        if lib().orc_merge_now(self.h, um) != 0:
+            raise MemoryError("oracle: merge")
 
     def last_crossings(self) -> int:
         return int(lib().orc_last_crossings(self.h))

@@ -68,6 +68,21 @@ def rotation_uniforms(seed: int, step: int, n_src: int) -> np.ndarray:
     return (bits >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
 
 
+MERGE_STREAM = 0x6D65726765          # ASCII "merge": the cells' merging-sphere stream
+
+
+def merge_uniforms(seed: int, step: int, ncell: int) -> np.ndarray:
+    """Three uniforms in [0,1) per cell for the randomly rotated merging
+    sphere of each cell at the end of `step`: shape (ncell, 3).
+    u = (splitmix64(key ^ (step<<34 | cell<<2 | k)) >> 11) * 2^-53 with
+    key = splitmix64(splitmix64(seed) ^ 0x6D65726765)."""
+    cell = np.arange(ncell, dtype=np.uint64)[:, None]
+    k = np.arange(3, dtype=np.uint64)[None, :]
+    ctr = (np.uint64(step) << np.uint64(34)) | (cell << np.uint64(2)) | k
+    key = splitmix64(splitmix64(np.uint64(seed)) ^ np.uint64(MERGE_STREAM))
+    return (splitmix64(ctr ^ key) >> np.uint64(11)).astype(np.float64) * (2.0 ** -53)
+
+
 def rotation_table(seed: int, step0: int, n_steps: int, n_src: int) -> np.ndarray:
     """Uniforms for n_steps consecutive steps: shape (n_steps, n_src, 3)."""
     return np.stack([rotation_uniforms(seed, step0 + s, n_src) for s in range(n_steps)])
@@ -165,6 +180,9 @@ class Problem:
     opacity_mode: int = 0             # 0: Standard Mode; 1: Generalized Opacity Mode (kappa of the
                                       # ionized phase, x_HI0 = 1 - ionized volume fraction)
     he_chi: float = 0.0
+    merge: bool = False               # ray merging at the end of each step (§3.3)
+    merge_level: int = 0              # l_merge
+    merge_exempt: float = 0.0         # N_ex (exempt packets per cell)
     T: np.ndarray | None = None
     meta: dict = field(default_factory=dict)
 
@@ -190,7 +208,12 @@ class Problem:
                     n_ray_min=self.n_ray_min, flux_floor=self.flux_floor,
                     max_dist_cm=self.max_dist_cm, c_ray=self.c_ray,
                     chem_iterations=self.chem_iterations, opacity_mode=self.opacity_mode,
-                    he_chi=self.he_chi)
+                    he_chi=self.he_chi, merge=self.merge, merge_level=self.merge_level,
+                    merge_exempt=self.merge_exempt)
+
+    def merge_uniforms(self, step: int):
+        """The cells' merging-sphere uniforms of `step`, or None without merging."""
+        return merge_uniforms(self.seed, step, self.ncell) if self.merge else None
 
     def footprint_bytes(self) -> int:
         return int(self.ncell * 64)
