@@ -118,12 +118,25 @@ typedef struct {
                                        (Eq. dxidt), at most to 1.  Not with chem_iterations */
     double he_chi;                  /* chi of Eq. dxidt: helium singly ionized per hydrogen
                                        atom (default 0) */
+    int merge;                      /* ray merging (§3.3), 0 (default) or 1: at the end of each
+                                       step the floor(merge_exempt N_cells) brightest carried
+                                       packets are exempt and the others are merged per cell
+                                       and per pixel of that cell's randomly rotated HEALPix
+                                       sphere of level merge_level (Eq. Nray_per_cell_max:
+                                       at most merge_exempt + 12 4^merge_level packets per
+                                       cell); a merged packet sums the photons of its
+                                       members, travels along the pixel's centre from their
+                                       photon-weighted mean position, distance and level, and
+                                       splits like any packet.  Only carried packets merge
+                                       (nothing with c_ray = +INFINITY) */
+    int merge_level;                /* l_merge, 0..8 (default 0) */
+    double merge_exempt;            /* N_ex, exempt packets per cell, >= 0 (default 4) */
 } frt_params;
 
 /* Cumulative photon ledger (photons) and counters of one solve.  With
  * E = emitted, the terms satisfy E = absorbed_HI + absorbed_sub + escaped
- * + dropped + in_flight + absorbed_front (+ lost, which is 0 unless a queue
- * overflowed).  In the Generalized Opacity Mode absorbed_HI counts the
+ * + dropped + in_flight + absorbed_front + merge_residual (+ lost, which is
+ * 0 unless a queue overflowed).  In the Generalized Opacity Mode absorbed_HI counts the
  * photons absorbed in ionized gas. */
 typedef struct {
     double emitted, absorbed_HI, absorbed_sub, escaped, dropped, in_flight, lost;
@@ -135,12 +148,16 @@ typedef struct {
     uint32_t err_flags;             /* device error bits (1 = queue overflow) */
     uint32_t max_items;             /* largest round (work items) seen */
     double absorbed_front;          /* photons stopped at I-fronts (Generalized Opacity Mode) */
+    double merge_residual;          /* photons the merged packets held minus those their
+                                       records hold in the march's precision (rounding) */
+    uint64_t merges, rays_merged;   /* merged packets made, and packets merged into them */
 } frt_ledger;
 
 /* Fill *p with defaults: 1 bin at 6.3e-18 cm^2, alpha_B = 2.59e-13,
  * coll_ion = 0, base_level 0, max_level 12, n_ray_min 1, no floor, no cap,
  * c_ray = speed of light, FRT_F32, seed 0, automatic queues, no hint,
- * backward-Euler chemistry (chem_iterations 0), FRT_STANDARD opacity, he_chi 0. */
+ * backward-Euler chemistry (chem_iterations 0), FRT_STANDARD opacity, he_chi 0,
+ * no merging (merge 0; merge_level 0 and merge_exempt 4 when it is on). */
 int frt_params_default(frt_params* p);
 
 /* Device memory hooks: alloc returns `bytes` of device memory of the
@@ -429,6 +446,12 @@ int frt_server_destroy(frt_server srv);
  * loaded; FRT_EINVAL for an origin outside the box or a zero direction. */
 int frt_debug_cast(frt_solve s, const double o_cm[3], const double d[3], const double* N_bins, double dt_s,
                    float* gamma_out, int ptr_kind, double* absorbed, double* escaped, uint64_t* crossings);
+
+/* Uniforms of a cell's merging sphere at the end of `step` (§3.3), as the
+ * library draws them: u = (splitmix64(key ^ (step<<34 | cell<<2 | k)) >> 11)
+ * * 2^-53, key = splitmix64(splitmix64(seed) ^ 0x6D65726765), rotation by
+ * Shoemake's quaternion as for the sources. */
+int frt_merge_uniforms(uint64_t seed, uint32_t step, uint32_t cell, double out[3]);
 
 /* Rotation uniforms the library would use for (step, src) — the same
  * counter-based generator the device runs — for checking a table against. */

@@ -191,6 +191,17 @@ struct Workspace {
     FrtSolveDesc* descs = nullptr;
     int solves_cap = 0;
     uint64_t limit = 0;             // most device bytes the workspace may hold (0: no limit)
+    // ray merging: per-packet keys, flags and scans, the output queue and the
+    // sort storage, for up to mcap carried packets and mold table entries
+    struct Merge {
+        uint32_t mcap = 0, mold = 0;
+        size_t rec = 0, temp_bytes = 0;
+        void *pkey = nullptr, *pkey_sorted = nullptr, *dst = nullptr, *temp = nullptr;
+        unsigned long long *gkey = nullptr, *gkey_s = nullptr, *stats = nullptr;
+        uint32_t *idx = nullptr, *idx_s = nullptr, *flag_out = nullptr, *slot = nullptr, *flag_lead = nullptr,
+                 *gid = nullptr, *ref = nullptr, *vmap = nullptr, *counts = nullptr;
+        double* residual = nullptr;
+    } mg;
 
     // device bytes of the pass queues (the part that grows with the largest
     // pass; the march scratch and the small tables are a fixed cost)
@@ -211,9 +222,19 @@ struct Workspace {
         pcap = 0;
     }
 
+    void free_merge()
+    {
+        dev_free(mg.pkey); dev_free(mg.pkey_sorted); dev_free(mg.dst); dev_free(mg.temp); dev_free(mg.gkey);
+        dev_free(mg.gkey_s); dev_free(mg.stats); dev_free(mg.idx); dev_free(mg.idx_s); dev_free(mg.flag_out);
+        dev_free(mg.slot); dev_free(mg.flag_lead); dev_free(mg.gid); dev_free(mg.ref); dev_free(mg.vmap);
+        dev_free(mg.counts); dev_free(mg.residual);
+        mg = Merge{};
+    }
+
     void release()
     {
         free_pass();
+        free_merge();
         free_recs(X);
         dev_free(segc);
         dev_free(segp);
@@ -269,6 +290,12 @@ struct frt_solve_s {
     uint32_t user_steps = 0;
     int n_src = 0;
     FrtRecs F[2]{};
+    FrtVSrc* vt[2] = {nullptr, nullptr};     // virtual origins of merged packets (merging only)
+    uint32_t vt_cap[2] = {0, 0};
+    uint32_t* vcount = nullptr;              // [2] entries of each table
+    float* w0_merged = nullptr;              // largest w0 of a merged packet
+    FrtVSrc* mark_vt = nullptr;              // bookmark of the table the carried packets refer to
+    uint32_t mark_vn = 0;
     uint32_t* fcount = nullptr;
     uint32_t* fcount_snap = nullptr;
     FrtLedgerDev* L = nullptr;
@@ -314,6 +341,7 @@ struct frt_solve_s {
         free_recs(F[0]);
         free_recs(F[1]);
         free_recs(mark_F);
+        dev_free(vt[0]); dev_free(vt[1]); dev_free(vcount); dev_free(w0_merged); dev_free(mark_vt);
         dev_free(mark_x);
         dev_free(mark_fc);
         dev_free(d_desc); dev_free(op); dev_free(gam[0]); dev_free(gam[1]); dev_free(x); dev_free(xavg); dev_free(front);
@@ -412,13 +440,18 @@ void set_step_fields(frt_solve s, double dt)
     }
     h.KSd = h.R_ref * s->P.sigma_bins[0] / (s->dx * s->dx * dt);
     h.KS = (float)h.KSd;
+    h.dep_base = std::ldexp(1.0, 46) / s->P.n_bins;
     if (h.has_sub) {
         // with sub-grid opacity a crossing deposits K_nu N_nu ds phi, at most
         // the largest K_nu times the packet's photons times sqrt(3) < 2
         double kmax = 0.0;
         for (int b = 0; b < s->P.n_bins; b++) kmax = std::max(kmax, h.Kd[b]);
-        h.dep_scale = (float)(std::ldexp(1.0, 46) / (2.0 * kmax * s->w0_max * s->P.n_bins));
+        h.dep_base = std::ldexp(1.0, 46) / (2.0 * kmax * s->P.n_bins);
+        h.dep_scale = (float)(h.dep_base / s->w0_max);
     }
+    // merged packets' w0 are known on the device only: the seeding plan takes
+    // the larger of the two
+    h.w0_hi = s->w0_max;
 }
 
 int check_inputs_finite(const float* v, size_t n, const char* what)
@@ -660,7 +693,7 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
     const int n_march = K > 0 ? K : 1;
     if (K > 0) {
         Timed t(tm, st, 2);
-        if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 0, st)) != hipSuccess)
+        if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 0, w.ctr + C_ERR, st)) != hipSuccess)
             return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
     }
     for (int it = 0; it < n_march; it++) {
@@ -693,14 +726,14 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
         }
         if (it + 1 < n_march) {
             Timed t(tm, st, 2);
-            if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 1, st)) != hipSuccess)
+            if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 1, w.ctr + C_ERR, st)) != hipSuccess)
                 return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         }
     }
     {
         Timed t(tm, st, 2);
-        if (K > 0) e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 2, st);
-        else e = frt::launch_chem(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, st);
+        if (K > 0) e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 2, w.ctr + C_ERR, st);
+        else e = frt::launch_chem(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.ctr + C_ERR, st);
         if (e != hipSuccess) return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         if (tm) tm->n_chem++;
     }
@@ -828,6 +861,127 @@ bool split_by_shape(frt_solve* ss, int n, const double* dts, std::vector<std::ve
     return true;
 }
 
+// Room in the context's merge scratch for n carried packets referring to a
+// table of n_old entries.
+int ensure_merge(Workspace& ws, uint32_t n, uint32_t n_old, int fp64)
+{
+    Workspace::Merge& m = ws.mg;
+    const size_t rs = fp64 ? 8 : 4, rec = rec_bytes(rs);
+    if (m.mcap < n || m.rec != rec || m.mold < n_old) {
+        const uint32_t cap = std::max<uint32_t>(std::max(n, m.rec == rec ? m.mcap : 0u), 1024);
+        const uint32_t old = std::max<uint32_t>(std::max(n_old, m.mold), 1024);
+        ws.free_merge();
+        RCCHK(dev_alloc(&m.pkey, (size_t)cap * rs));
+        RCCHK(dev_alloc(&m.pkey_sorted, (size_t)cap * rs));
+        RCCHK(dev_alloc(&m.dst, (size_t)cap * rec));
+        RCCHK(dev_alloc((void**)&m.gkey, (size_t)cap * 8));
+        RCCHK(dev_alloc((void**)&m.gkey_s, (size_t)cap * 8));
+        RCCHK(dev_alloc((void**)&m.idx, (size_t)cap * 4));
+        RCCHK(dev_alloc((void**)&m.idx_s, (size_t)cap * 4));
+        RCCHK(dev_alloc((void**)&m.flag_out, (size_t)cap * 4));
+        RCCHK(dev_alloc((void**)&m.slot, (size_t)cap * 4));
+        RCCHK(dev_alloc((void**)&m.flag_lead, (size_t)cap * 4));
+        RCCHK(dev_alloc((void**)&m.gid, (size_t)cap * 4));
+        RCCHK(dev_alloc((void**)&m.ref, (size_t)old * 4));
+        RCCHK(dev_alloc((void**)&m.vmap, (size_t)old * 4));
+        RCCHK(dev_alloc((void**)&m.counts, 16));
+        RCCHK(dev_alloc((void**)&m.residual, 8));
+        RCCHK(dev_alloc((void**)&m.stats, 16));
+        m.temp_bytes = frt::merge_temp_bytes(cap, old, fp64);
+        RCCHK(dev_alloc(&m.temp, m.temp_bytes));
+        m.mcap = cap;
+        m.mold = old;
+        m.rec = rec;
+    }
+    return FRT_OK;
+}
+
+// A solve's table of virtual origins `k` with room for `cap` entries (its
+// contents are not kept: only the table the next merge writes grows).
+int ensure_vtable(frt_solve s, int k, uint32_t cap)
+{
+    if (s->vt_cap[k] >= cap) return FRT_OK;
+    dev_free(s->vt[k]);
+    const uint32_t c = std::max<uint32_t>(cap, 2 * s->vt_cap[k]);
+    RCCHK(dev_alloc((void**)&s->vt[k], (size_t)c * sizeof(FrtVSrc)));
+    s->vt_cap[k] = c;
+    s->h.vt[k] = s->vt[k];
+    return FRT_OK;
+}
+
+// Room for the merge after the next step of a merging solve, taken before the
+// step so that a step that ran is never left unmerged: the merge scratch for
+// every packet its carried queue can hold and every entry of the current
+// table of virtual origins, and the next table for one entry per carried
+// packet (a merge keeps at most one entry per packet carried as it is and
+// makes one per group of two or more, so never more entries than packets).
+int prepare_merge(Workspace& ws, frt_solve s)
+{
+    const int cur = (int)(s->step & 1u), nxt = cur ^ 1;
+    RCCHK(ensure_merge(ws, s->F[nxt].cap, s->vt_cap[cur], s->fp64));
+    return ensure_vtable(s, nxt, s->F[nxt].cap);
+}
+
+// Ray merging (§3.3) of a solve after a step that ran without error: the
+// packets it carries into the next step are merged, and the virtual origins
+// they refer to renumbered into the table of the next step.  `d` is the
+// solve's descriptor of that step on the device (its step index not yet
+// advanced).  Waits for the merge.
+int merge_after_step(Workspace& ws, frt_solve s, FrtSolveDesc* d, hipStream_t st)
+{
+    const int cur = (int)(s->step & 1u), nxt = cur ^ 1;
+    uint32_t fc[2], vc[2];
+    HIPCHK(hipMemcpyAsync(fc, s->fcount, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(vc, s->vcount, 8, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    const uint32_t n = std::min(fc[nxt], s->F[nxt].cap);
+    const uint32_t n_old = vc[cur];
+    const uint64_t E = (uint64_t)std::floor(s->P.merge_exempt * (double)s->ncell);
+    const bool all_exempt = E >= n;
+    if (n == 0 || (all_exempt && n_old == 0)) {
+        vc[nxt] = 0;
+        HIPCHK(hipMemcpyAsync(s->vcount + nxt, &vc[nxt], 4, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return FRT_OK;
+    }
+    // reserved before the step (prepare_merge): nothing allocates here
+    if (ws.mg.mcap < n || ws.mg.mold < n_old || s->vt_cap[nxt] < n)
+        return fail(FRT_EDEVICE, "merge scratch smaller than reserved");
+    Workspace::Merge& m = ws.mg;
+    FrtMergeArgs a{};
+    a.n = n;
+    a.n_old = n_old;
+    a.E = E;
+    a.level = s->P.merge_level;
+    a.all_exempt = all_exempt ? 1 : 0;
+    int cell_bits = 0;
+    while (cell_bits < 40 && (1ull << cell_bits) < (uint64_t)s->ncell) cell_bits++;
+    a.end_bit = 20 + cell_bits;
+    a.key_mask = (a.end_bit >= 64) ? ~0ull : ((1ull << a.end_bit) - 1ull);
+    a.pkey = m.pkey;
+    a.pkey_sorted = m.pkey_sorted;
+    a.gkey = m.gkey;
+    a.gkey_s = m.gkey_s;
+    a.idx = m.idx;
+    a.idx_s = m.idx_s;
+    a.flag_out = m.flag_out;
+    a.slot = m.slot;
+    a.flag_lead = m.flag_lead;
+    a.gid = m.gid;
+    a.ref = m.ref;
+    a.vmap = m.vmap;
+    a.counts = m.counts;
+    a.residual = m.residual;
+    a.stats = m.stats;
+    a.dst = m.dst;
+    a.temp = m.temp;
+    a.temp_bytes = m.temp_bytes;
+    const hipError_t e = frt::launch_merge(d, a, s->fp64, s->P.n_bins, st);
+    if (e != hipSuccess) return fail(FRT_EDEVICE, "merge: %s", hipGetErrorString(e));
+    HIPCHK(hipStreamSynchronize(st));
+    return FRT_OK;
+}
+
 int step_group_locked(frt_solve* ss, int n, const double* dts);
 
 // One step of a group with automatic queue growth: snapshot, run, check,
@@ -856,6 +1010,8 @@ int step_group_locked(frt_solve* ss, int n, const double* dts)
     }
     for (int attempt = 0; attempt < 16; attempt++) {
         RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.pcap)));
+        for (int i = 0; i < n; i++)
+            if (ss[i]->P.merge) RCCHK(prepare_merge(ws, ss[i]));
         Group g;
         plan_group(ws, ss, n, g);
         RCCHK(upload_group(ws, g, n, st));
@@ -870,6 +1026,8 @@ int step_group_locked(frt_solve* ss, int n, const double* dts)
         }
         if (!(ctr[C_ERR] & (FRT_DEVERR_QUEUE_OVERFLOW | FRT_DEVERR_CARRY_OVERFLOW))) {
             if (ctr[C_ERR] & FRT_DEVERR_UNFINISHED) return fail(FRT_EDEVICE, "a step left packets after its last pass");
+            for (int i = 0; i < n; i++)
+                if (ss[i]->P.merge) RCCHK(merge_after_step(ws, ss[i], ws.descs + i, st));
             for (int i = 0; i < n; i++) ss[i]->step++;
             return FRT_OK;
         }
@@ -1100,6 +1258,7 @@ int debug_cast_locked(frt_solve s, const double o_cm[3], const double d_in[3], c
     t->P.c_ray_cm_s = HUGE_VAL;
     t->P.chem_iterations = 0;
     t->P.queue_capacity = 0;
+    t->P.merge = 0;
     t->fp64 = s->fp64;
     t->rs = s->rs;
     for (int a = 0; a < 3; a++) t->bsh[a] = s->bsh[a];
@@ -1180,6 +1339,7 @@ int debug_cast_locked(frt_solve s, const double o_cm[3], const double d_in[3], c
     h.gamma[1] = t->gam[0];
     h.front = t->front;
     h.xavg = nullptr;
+    h.merge = 0;
     t->step = 0;
     set_step_fields(t.get(), dt);
     h.budget = HUGE_VAL;
@@ -1327,6 +1487,9 @@ int frt_params_default(frt_params* p)
     p->seed = 0;
     p->queue_capacity = 0;
     p->queue_hint = 0;
+    p->merge = 0;
+    p->merge_level = 0;
+    p->merge_exempt = 4.0;
     return FRT_OK;
 }
 
@@ -1383,6 +1546,9 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     if (P->opacity_mode == FRT_GENERALIZED && P->chem_iterations > 0)
         return fail(FRT_EINVAL, "the Generalized Opacity Mode takes no chem_iterations");
     if (!(P->he_chi >= 0) || !std::isfinite(P->he_chi)) return fail(FRT_EINVAL, "he_chi must be finite and >= 0");
+    if (P->merge != 0 && P->merge != 1) return fail(FRT_EINVAL, "merge must be 0 or 1");
+    if (P->merge_level < 0 || P->merge_level > 8) return fail(FRT_EINVAL, "merge_level %d outside 0..8", P->merge_level);
+    if (!(P->merge_exempt >= 0) || !std::isfinite(P->merge_exempt)) return fail(FRT_EINVAL, "merge_exempt must be finite and >= 0");
     AllocScope scope(&ctx->al);
     HIPCHK(hipSetDevice(ctx->device));
     frt_solve s = new (std::nothrow) frt_solve_s;
@@ -1402,6 +1568,10 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
         s->own_stream = true;
     }
     int rc;
+    if (P->merge && ((rc = dev_alloc((void**)&s->vcount, 8)) || (rc = dev_alloc((void**)&s->w0_merged, 4)))) {
+        delete s;
+        return rc;
+    }
     if ((rc = dev_alloc((void**)&s->d_desc, sizeof(FrtSolveDesc))) || (rc = dev_alloc((void**)&s->fcount, 8)) ||
         (rc = dev_alloc((void**)&s->fcount_snap, 8)) || (rc = dev_alloc((void**)&s->L, sizeof(FrtLedgerDev))) ||
         (rc = dev_alloc((void**)&s->L_snap, sizeof(FrtLedgerDev)))) {
@@ -1434,6 +1604,14 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     h.L = s->L;
     h.fcount_snap = s->fcount_snap;
     h.L_snap = s->L_snap;
+    h.merge = P->merge;
+    h.vcount = s->vcount;
+    h.w0_merged = s->w0_merged;
+    if (P->merge) {
+        HIPCHK(hipMemsetAsync(s->vcount, 0, 8, s->stream));
+        HIPCHK(hipMemsetAsync(s->w0_merged, 0, 4, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
     *out = s;
     return FRT_OK;
 }
@@ -1527,6 +1705,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     if (T) RCCHK(scopy(s, s->T, hT, n * 4, hipMemcpyHostToDevice));
     RCCHK(sset(s, s->gam[0], 0, n * s->rs));
     RCCHK(sset(s, s->gam[1], 0, n * s->rs));
+    if (s->vcount) RCCHK(sset(s, s->vcount, 0, 8));
     RCCHK(sset(s, s->fcount, 0, 8));
     RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
     FrtSolveDesc& h = s->h;
@@ -1668,6 +1847,10 @@ int frt_load_sources(frt_solve s, int n_src, const double* pos_cm, const double*
     RCCHK(ensure_quat(s, 0));
     RCCHK(sset(s, s->fcount, 0, 8));
     RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
+    if (s->P.merge) {
+        RCCHK(sset(s, s->vcount, 0, 8));
+        RCCHK(sset(s, s->w0_merged, 0, 4));
+    }
     s->step = 0;
     s->have_src = true;
     RCCHK(upload_desc(s));
@@ -1711,6 +1894,7 @@ int frt_step_static(frt_solve s, double dt)
     if (s->step >= s->quat_steps)
         return fail(FRT_ESTATE, "the solve's rotation table holds %u steps; an allocating call (frt_step) extends it",
                     s->quat_steps);
+    if (s->P.merge) return fail(FRT_EINVAL, "the allocation-free step does not merge packets (frt_step does)");
     const uint64_t nkeys = (uint64_t)s->bpx * s->bpy * s->bpz;
     if (nkeys > FRT_STATIC_MAX_KEYS)
         return fail(FRT_EINVAL, "the grid holds %llu bricks; the allocation-free step takes at most %u",
@@ -1816,7 +2000,11 @@ int frt_batch_run(frt_solve* ss, int n, const double* dts, int n_steps, int use_
     if (n_steps == 0) return FRT_OK;
     HIPCHK(hipSetDevice(ss[0]->ctx->device));
     for (int i = 0; i < n; i++) HIPCHK(hipStreamSynchronize(ss[i]->stream));
-    if (!use_graph) {
+    bool merging = false;
+    for (int i = 0; i < n; i++) merging |= ss[i]->P.merge != 0;
+    // a merge is sized from the carried count the step leaves, read on the
+    // host: groups with merging solves are stepped launch by launch
+    if (!use_graph || merging) {
         for (int k = 0; k < n_steps; k++) RCCHK(step_group(ss, n, dts));
     } else {
         std::lock_guard<std::mutex> lock(ss[0]->ctx->mu);
@@ -1992,6 +2180,9 @@ int frt_read_ledger(frt_solve s, frt_ledger* out)
     out->err_flags = L.err_flags;
     out->max_items = L.max_items;
     out->absorbed_front = L.absorbed_front;
+    out->merge_residual = L.merge_residual;
+    out->merges = L.merges;
+    out->rays_merged = L.rays_merged;
     return FRT_OK;
 }
 
@@ -2011,14 +2202,17 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     const size_t rec = rec_bytes(s->rs);
     const size_t led = offsetof(FrtLedgerDev, sd);
     const size_t nq = (size_t)s->step * s->n_src * 4;
-    const size_t need = 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec;
+    uint32_t vc[2] = {0, 0};
+    if (s->vcount) RCCHK(scopy(s, vc, s->vcount, 8, hipMemcpyDeviceToHost));
+    const uint64_t nv = vc[cur];
+    const size_t need = 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec + 8 + nv * sizeof(FrtVSrc);
     if (!buf) {
         *bytes = need;
         return FRT_OK;
     }
     if (*bytes < need) return fail(FRT_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
     char* p = (char*)buf;
-    uint64_t hdr[8] = {0x4652544350543034ull, 6, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
+    uint64_t hdr[8] = {0x4652544350543034ull, 7, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
     RCCHK(scopy(s, p, s->L, led, hipMemcpyDeviceToHost));
@@ -2034,6 +2228,10 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
         RCCHK(copy_recs(hv, s->F[cur], nc, nb, s->rs, s->stream, hipMemcpyDeviceToHost));
         HIPCHK(hipStreamSynchronize(s->stream));
     }
+    p += (size_t)nc * rec;
+    std::memcpy(p, &nv, 8);
+    p += 8;
+    if (nv) RCCHK(scopy(s, p, s->vt[cur], nv * sizeof(FrtVSrc), hipMemcpyDeviceToHost));
     *bytes = need;
     return FRT_OK;
 }
@@ -2047,7 +2245,7 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     uint64_t hdr[8];
     std::memcpy(hdr, p, sizeof(hdr));
     p += sizeof(hdr);
-    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 6) return fail(FRT_EINVAL, "not a checkpoint of this library");
+    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 7) return fail(FRT_EINVAL, "not a checkpoint of this library");
     AllocScope scope(&s->ctx->al);
     if (hdr[3] != (uint64_t)s->n_src || hdr[4] != s->ncell || hdr[5] != (uint64_t)s->P.n_bins || hdr[6] != (uint64_t)s->fp64)
         return fail(FRT_EINVAL, "checkpoint does not match this solve (sources, grid, bins or precision)");
@@ -2055,7 +2253,12 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     const int nb = s->P.n_bins;
     const size_t rec = rec_bytes(s->rs);
     const size_t nq = (size_t)step * s->n_src * 4;
-    if (bytes < 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec) return fail(FRT_EINVAL, "checkpoint truncated");
+    if (bytes < 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec + 8) return fail(FRT_EINVAL, "checkpoint truncated");
+    uint64_t nv = 0;
+    std::memcpy(&nv, p + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec, 8);
+    if (bytes < 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec + 8 + nv * sizeof(FrtVSrc))
+        return fail(FRT_EINVAL, "checkpoint truncated");
+    if (nv && !s->P.merge) return fail(FRT_EINVAL, "checkpoint holds merged packets; this solve does not merge");
     HIPCHK(hipStreamSynchronize(s->stream));
     RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
     RCCHK(scopy(s, s->L, p, led, hipMemcpyHostToDevice));
@@ -2098,6 +2301,14 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
         RCCHK(copy_recs(s->F[cur], hv, nc, nb, s->rs, s->stream, hipMemcpyHostToDevice));
         HIPCHK(hipStreamSynchronize(s->stream));
     }
+    p += (size_t)nc * rec + 8;
+    if (s->P.merge) {
+        RCCHK(ensure_vtable(s, cur, (uint32_t)nv));
+        if (nv) RCCHK(scopy(s, s->vt[cur], p, nv * sizeof(FrtVSrc), hipMemcpyHostToDevice));
+        uint32_t vc[2] = {0, 0};
+        vc[cur] = (uint32_t)nv;
+        RCCHK(scopy(s, s->vcount, vc, 8, hipMemcpyHostToDevice));
+    }
     uint32_t fc[2] = {0, 0};
     fc[cur] = nc;
     RCCHK(scopy(s, s->fcount, fc, 8, hipMemcpyHostToDevice));
@@ -2134,6 +2345,15 @@ int frt_mark(frt_solve s)
     HIPCHK(hipMemcpyAsync(s->mark_x, s->x, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
     RCCHK(copy_recs(s->mark_F, s->F[cur], nc, s->P.n_bins, s->rs, s->stream, hipMemcpyDeviceToDevice));
     HIPCHK(hipStreamSynchronize(s->stream));
+    dev_free(s->mark_vt);
+    s->mark_vn = 0;
+    if (s->vcount) {
+        uint32_t vc[2];
+        RCCHK(scopy(s, vc, s->vcount, 8, hipMemcpyDeviceToHost));
+        s->mark_vn = vc[cur];
+        RCCHK(dev_alloc((void**)&s->mark_vt, std::max<size_t>(s->mark_vn, 1) * sizeof(FrtVSrc)));
+        if (s->mark_vn) RCCHK(scopy(s, s->mark_vt, s->vt[cur], (size_t)s->mark_vn * sizeof(FrtVSrc), hipMemcpyDeviceToDevice));
+    }
     s->mark_n = nc;
     s->mark_step = s->step;
     s->marked = true;
@@ -2149,6 +2369,13 @@ int frt_rewind(frt_solve s)
     HIPCHK(hipMemcpyAsync(s->x, s->mark_x, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
     RCCHK(copy_recs(s->F[cur], s->mark_F, s->mark_n, s->P.n_bins, s->rs, s->stream, hipMemcpyDeviceToDevice));
     HIPCHK(hipMemcpyAsync(s->fcount, s->mark_fc, 8, hipMemcpyDeviceToDevice, s->stream));
+    if (s->vcount) {
+        if (s->vt_cap[cur] < s->mark_vn) return fail(FRT_ESTATE, "virtual-origin table shrank below the bookmark");
+        if (s->mark_vn)
+            HIPCHK(hipMemcpyAsync(s->vt[cur], s->mark_vt, (size_t)s->mark_vn * sizeof(FrtVSrc), hipMemcpyDeviceToDevice,
+                                  s->stream));
+        HIPCHK(hipMemcpyAsync(s->vcount + cur, &s->mark_vn, 4, hipMemcpyHostToDevice, s->stream));
+    }
     HIPCHK(hipMemsetAsync(s->gam[cur], 0, s->ncell * s->rs, s->stream));
     if (s->front) HIPCHK(hipMemsetAsync(s->front, 0, s->ncell * 8, s->stream));
     s->step = s->mark_step;
@@ -2205,6 +2432,17 @@ int frt_debug_cast(frt_solve s, const double o_cm[3], const double d[3], const d
     AllocScope scope(&s->ctx->al);
     std::lock_guard<std::mutex> lock(s->ctx->mu);
     return debug_cast_locked(s, o_cm, d, N_bins, dt_s, gamma_out, ptr_kind, absorbed, escaped, crossings);
+}
+
+int frt_merge_uniforms(uint64_t seed, uint32_t step, uint32_t cell, double out[3])
+{
+    if (!out) return fail(FRT_EINVAL, "null output");
+    const uint64_t key = mix64_host(mix64_host(seed) ^ 0x6D65726765ull);
+    for (uint32_t k = 0; k < 3; k++) {
+        const uint64_t ctr = ((uint64_t)step << 34) | ((uint64_t)cell << 2) | (uint64_t)k;
+        out[k] = (double)(mix64_host(ctr ^ key) >> 11) * 0x1.0p-53;
+    }
+    return FRT_OK;
 }
 
 int frt_rotation_uniforms(uint64_t seed, uint32_t step, uint32_t src, double out[3])

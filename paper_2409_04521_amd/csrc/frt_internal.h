@@ -64,6 +64,8 @@ struct FrtLedgerDev {
     unsigned long long crossings, ray_visits, splits, n_escaped, n_dropped, n_in_flight, rays_emitted;
     unsigned long long step_crossings;
     unsigned int err_flags, max_items;
+    double merge_residual;                      // photons before minus after the merges (rounding)
+    unsigned long long merges, rays_merged;     // merged packets made, packets merged into them
     double sd[FRT_STRIPES][LF_NF];
     unsigned long long sc[FRT_STRIPES][LC_NC];
 };
@@ -94,6 +96,17 @@ static_assert(sizeof(FrtRec<float>) == 64, "FP32 packet record is 64 bytes");
 static_assert(sizeof(FrtRec<double>) == 112, "FP64 packet record is 112 bytes");
 static_assert(offsetof(FrtRec<float>, key) == 16 && offsetof(FrtRec<double>, key) == 16,
               "the key is the first word of a record's second 16 bytes");
+
+// Virtual origin of a packet made by merging (§3.3): the point it travels
+// from, the rotation of its HEALPix pixels and its photons per bin relative
+// to R_ref w0 (at most 1).  Packets refer to an entry through their source
+// index with FRT_VSRC set.
+struct alignas(16) FrtVSrc {
+    double pos[3];              // cells
+    double q[4];                // (w, x, y, z)
+    double spec[FRT_MAX_BINS_I];
+};
+constexpr uint32_t FRT_VSRC = 0x80000000u;
 
 // A queue of packet records (FrtRec<float> or FrtRec<double>).
 struct FrtRecs {
@@ -163,6 +176,15 @@ struct FrtSolveDesc {
     double front_atoms;         // (1 + chi) V: times n_H, the atoms a front photon ionizes
     void* op_bw;                // op_b, written by this mode's chemistry
     double* front;              // [ncell] photons stopped at each cell's front this step (or null)
+    // ray merging (§3.3): virtual origins of merged packets in two tables used
+    // in turn like the carried queues (the packets carried into step k, and
+    // their children, refer to table k & 1); vcount [2] their entries
+    int merge;
+    FrtVSrc* vt[2];
+    uint32_t* vcount;
+    double dep_base;            // dep_scale times the largest w0 held (merging solves)
+    double w0_hi;               // largest w0 of a cast packet so far
+    float* w0_merged;           // largest w0 of a merged packet (device, merging solves)
 };
 
 // One work item of a pass: up to FRT_ITEM_RAYS packets of one brick.
@@ -212,7 +234,41 @@ constexpr size_t FRT_STATIC_SCRATCH_BYTES = size_t(48) << 20;
 constexpr uint32_t FRT_STATIC_MAX_KEYS = 4096;
 constexpr uint32_t FRT_STATIC_XREC_PER_CU = 256;
 
+// Arguments of the merge launches of one solve (device buffers of the
+// context's merge scratch; n carried packets, n_old entries in the table
+// they refer to, E exempt packets).
+struct FrtMergeArgs {
+    uint32_t n, n_old;
+    uint64_t E;
+    int level;                  // l_merge
+    int all_exempt;             // E >= n: nothing merges, entries are only renumbered
+    int end_bit;                // bits of the group key the sort uses
+    unsigned long long key_mask;
+    void* pkey;                 // [n] photons (march precision)
+    void* pkey_sorted;          // [n] the same, descending
+    unsigned long long* gkey;   // [n] cell << 20 | pixel, or all ones for exempt packets
+    unsigned long long* gkey_s; // [n] sorted
+    uint32_t* idx;              // [n] packet index
+    uint32_t* idx_s;            // [n] in group-key order
+    uint32_t* flag_out;         // [n] 1: writes an output packet
+    uint32_t* slot;             // [n] its output slot
+    uint32_t* flag_lead;        // [n] 1: first packet of a group of two or more
+    uint32_t* gid;              // [n] the group's merged-packet ordinal
+    uint32_t* ref;              // [n_old] 1: an old table entry still referred to
+    uint32_t* vmap;             // [n_old] its entry in the new table
+    uint32_t* counts;           // [4] outputs, merged packets, kept entries
+    double* residual;           // [1] photons before minus after
+    unsigned long long* stats;  // [2] merged packets, packets merged into them
+    void* dst;                  // [n] output records
+    void* temp;                 // sort and scan storage
+    size_t temp_bytes;
+};
+
 namespace frt {
+// Merge the packets a solve carries into the next step (§3.3); d is the
+// solve's descriptor of the step just run.
+hipError_t launch_merge(FrtSolveDesc* d, const FrtMergeArgs& a, int fp64, int n_bins, hipStream_t st);
+size_t merge_temp_bytes(uint32_t n, uint32_t n_old, int fp64);
 // Device address of the static scratch on `device` (which must be current),
 // looked up with hipGetSymbolAddress on the first call per device and kept.
 hipError_t static_scratch(int device, void** ptr);
@@ -221,14 +277,17 @@ hipError_t launch_seed(FrtSolveDesc* d, const FrtWS& ws, int fp64, hipStream_t s
 // (which also writes the children of the packets that split)
 hipError_t launch_pass(FrtSolveDesc* d, const FrtWS& ws, int fp64, int part, hipStream_t s);
 hipError_t launch_finish(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
+// The chemistry of every solve of a launch; `launch_err` is the launch's
+// error word (device): when it is set no solve's state changes.
 hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
-                       unsigned long long total_cells, int fp64, hipStream_t s);
+                       unsigned long long total_cells, int fp64, const uint32_t* launch_err, hipStream_t s);
 hipError_t launch_prep_opacity(FrtSolveDesc* d_desc, unsigned long long ncell, int fp64, hipStream_t s);
 // Clear the launch counters and brick histogram (a kernel, so that a step
 // captured in a HIP graph holds no memset node).
 hipError_t launch_clear(const FrtWS& ws, int keep_err, hipStream_t s);
 hipError_t launch_chem_avg(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
-                           unsigned long long total_cells, int fp64, int phase, hipStream_t s);
+                           unsigned long long total_cells, int fp64, int phase, const uint32_t* launch_err,
+                           hipStream_t s);
 hipError_t launch_iter_restart(FrtSolveDesc* d, int n_solves, hipStream_t s);
 hipError_t launch_snapshot(FrtSolveDesc* d, int n_solves, hipStream_t s);
 // Advance every solve's step index on the device unless the step raised an

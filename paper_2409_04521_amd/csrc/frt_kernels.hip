@@ -17,6 +17,7 @@
 // so the host launches a fixed number of passes without reading anything
 // back.
 #include "frt_internal.h"
+#include "frt_device.h"
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -30,116 +31,10 @@
 
 namespace {
 
+using namespace frt_dev;
+
 constexpr int WAVE = 64;
 constexpr int BLOCK = 256;
-
-// ------------------------------------------------------------------ HEALPix
-// Centre of NESTED pixel p at level l (Nside = 2^l), Gorski et al. 2005:
-// the pixel index splits into base face f and in-face coordinates (ix, iy)
-// (bits interleaved, ix in the even bits); the ring index counted from the
-// north pole is j = jr(f) Nside - ix - iy - 1 and the pixel's longitude
-// index within its ring is jp(f) nr + ix - iy, with nr the ring's
-// half-width.  z follows from j on the polar caps (j < Nside, j > 3 Nside)
-// and on the equatorial belt.
-__device__ __forceinline__ uint32_t squeeze_even_bits(uint32_t v)
-{
-    v &= 0x55555555u;
-    v = (v | (v >> 1)) & 0x33333333u;
-    v = (v | (v >> 2)) & 0x0f0f0f0fu;
-    v = (v | (v >> 4)) & 0x00ff00ffu;
-    v = (v | (v >> 8)) & 0x0000ffffu;
-    return v;
-}
-
-template <typename Real>
-__device__ void nest_pixel_centre(int level, uint32_t pix, Real v[3])
-{
-    const int nside = 1 << level;
-    const uint32_t face = pix >> (2 * level);
-    // ring of the face's southern corner (in units of Nside) and its
-    // longitude index: faces 0-3 are the northern row, 4-7 the equatorial
-    // row (shifted by half a face), 8-11 the southern row
-    const int jr_face = (int)(face >> 2) + 2;
-    const int jp_face = 2 * (int)(face & 3u) + ((face >> 2) == 1u ? 0 : 1);
-    const uint32_t sub = pix & ((1u << (2 * level)) - 1u);
-    const int ix = (int)squeeze_even_bits(sub);
-    const int iy = (int)squeeze_even_bits(sub >> 1);
-    const int j = jr_face * nside - ix - iy - 1;
-    int nr;
-    Real z, st;
-    const Real inv3n2 = Real(1) / (Real(3) * Real(nside) * Real(nside));
-    if (j < nside) {
-        nr = j;
-        Real t = Real(nr) * Real(nr) * inv3n2;   // 1 - z
-        z = Real(1) - t;
-        st = sqrt(t * (Real(2) - t));
-    } else if (j > 3 * nside) {
-        nr = 4 * nside - j;
-        Real t = Real(nr) * Real(nr) * inv3n2;   // 1 + z
-        z = t - Real(1);
-        st = sqrt(t * (Real(2) - t));
-    } else {
-        nr = nside;
-        z = Real(2 * nside - j) * (Real(2) / Real(3 * nside));
-        st = sqrt((Real(1) - z) * (Real(1) + z));
-    }
-    int k = jp_face * nr + ix - iy;
-    if (k < 0) k += 8 * nr;
-    else if (k >= 8 * nr) k -= 8 * nr;
-    // phi = (pi/4) k / nr, evaluated as sincospi(k / (4 nr))
-    Real s, c;
-    if constexpr (sizeof(Real) == 8) sincospi(Real(k) / Real(4 * nr), &s, &c);
-    else sincospif(Real(k) / Real(4 * nr), &s, &c);
-    v[0] = st * c;
-    v[1] = st * s;
-    v[2] = z;
-}
-
-// ----------------------------------------------------------------- rotation
-// Counter-based uniforms: SplitMix64 output function (Steele, Lea & Flood
-// 2014) of (step<<32 | src<<2 | k) xor a key derived from the seed.
-__device__ __forceinline__ uint64_t mix64(uint64_t x)
-{
-    uint64_t z = x + 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-__device__ __forceinline__ double counter_uniform(uint64_t seed, uint32_t step, uint32_t src, uint32_t k)
-{
-    uint64_t ctr = ((uint64_t)step << 32) | ((uint64_t)src << 2) | (uint64_t)k;
-    return (double)(mix64(ctr ^ mix64(seed)) >> 11) * 0x1.0p-53;
-}
-
-// Uniform random rotation as a unit quaternion (w, x, y, z) from three
-// uniforms (Shoemake 1992).
-__device__ void shoemake_quat(const double u[3], double q[4])
-{
-    double a = sqrt(1.0 - u[0]), b = sqrt(u[0]);
-    double s2, c2, s3, c3;
-    sincospi(2.0 * u[1], &s2, &c2);
-    sincospi(2.0 * u[2], &s3, &c3);
-    q[0] = b * c3;
-    q[1] = a * s2;
-    q[2] = a * c2;
-    q[3] = b * s3;
-}
-
-// v' = q v q*, written with the vector part u of q:  t = 2 u x v,
-// v' = v + w t + u x t.
-template <typename Real>
-__device__ __forceinline__ void quat_rotate(const double* qd, Real v[3])
-{
-    const Real w = (Real)qd[0], ux = (Real)qd[1], uy = (Real)qd[2], uz = (Real)qd[3];
-    Real tx = Real(2) * (uy * v[2] - uz * v[1]);
-    Real ty = Real(2) * (uz * v[0] - ux * v[2]);
-    Real tz = Real(2) * (ux * v[1] - uy * v[0]);
-    Real ox = v[0] + w * tx + (uy * tz - uz * ty);
-    Real oy = v[1] + w * ty + (uz * tx - ux * tz);
-    Real oz = v[2] + w * tz + (ux * ty - uy * tx);
-    v[0] = ox; v[1] = oy; v[2] = oz;
-}
 
 // ------------------------------------------------------------- wave helpers
 __device__ __forceinline__ double wave_sum(double v)
@@ -290,20 +185,6 @@ struct Pkt {
 
 // T[0] = A (HI optical depth at sigma_0), T[1] = K (sub-grid optical depth),
 // T[2], T[3] their Kahan compensations.
-// A packet's cell as packed coordinates x | y << 11 | z << 22 (grids have at
-// most 2048 cells per axis), so that no division recovers them.
-__device__ __forceinline__ uint32_t pack_cell(const int c[3])
-{
-    return (uint32_t)c[0] | ((uint32_t)c[1] << 11) | ((uint32_t)c[2] << 22);
-}
-
-__device__ __forceinline__ void unpack_cell(uint32_t p, int c[3])
-{
-    c[0] = (int)(p & 2047u);
-    c[1] = (int)((p >> 11) & 2047u);
-    c[2] = (int)(p >> 22);
-}
-
 template <typename Real>
 __device__ __forceinline__ FrtRec<Real>* recs(const FrtRecs& q) { return (FrtRec<Real>*)q.rec; }
 
@@ -361,7 +242,7 @@ template <typename Real>
 __device__ __forceinline__ void packet_dir(const FrtSolveDesc& D, uint32_t lp, uint32_t estep, uint32_t src, Real d[3])
 {
     nest_pixel_centre<Real>((int)(lp >> 28), lp & 0x0fffffffu, d);
-    quat_rotate<Real>(D.quat + ((size_t)estep * D.n_src + src) * 4, d);
+    quat_rotate<Real>(rot_of(D, estep, src), d);
 }
 
 // Cell of the point s + r d for a packet moving along d: floor per axis,
@@ -503,6 +384,9 @@ __global__ void k_seed_plan(FrtSolveDesc* descs, FrtWS ws)
             n = (uint32_t)D.n_src * D.ncast + carried;
             D.fcount[1 - D.cur] = 0;
             D.L->step_crossings = 0;
+            // merged packets can hold more photons than any cast one: the
+            // fixed-point deposit scale follows the brightest packet held
+            if (D.merge) D.dep_scale = (float)(D.dep_base / fmax(D.w0_hi, (double)*D.w0_merged));
         }
         uint32_t tot;
         const uint32_t ex = wave_excl_scan(n, &tot);
@@ -606,7 +490,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
                 const uint32_t i = local - n_emit;
                 load_pkt<Real>(D.F[D.cur], i, h, T);
                 key = D.key_base + recs<Real>(D.F[D.cur])[i].key;   // carried keys are solve-local
-                const double* sp = D.src_pos + (size_t)h.src * 3;
+                const double* sp = src_pos_of(D, h.src);
                 const Real s3[3] = {(Real)sp[0], (Real)sp[1], (Real)sp[2]};
                 int c[3];
                 unpack_cell(h.cell, c);
@@ -1119,7 +1003,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                     if (gen == 0) load_pkt<Real>(in_q, ws.sorted[w.start + s_order[p]].x, h, T);
                     else load_pkt<Real>(x_q, x_base + g_lo + s_order[p], h, T);
                     level = (int)(h.lp >> 28);
-                    const double* sp = D.src_pos + (size_t)h.src * 3;
+                    const double* sp = src_pos_of(D, h.src);
                     s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
                     if (h.estep != step && h.rstop <= h.r) h.rstop = h.r + budget;   // carried: fresh budget
                     if (h.estep == step && h.r == Real(0) && level == base_level) h.rstop = budget;
@@ -1127,9 +1011,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                     double n_start = 0.0;
 #pragma unroll
                     for (int b = 0; b < NB; b++) {
-                        Real spec;
-                        if constexpr (F32) spec = D.spec[(size_t)h.src * NB + b];
-                        else spec = D.specd[(size_t)h.src * NB + b];
+                        const Real spec = spec_of<Real>(D, h.src, NB, b);
                         N0[b] = h.w0 * spec;
                         NE[b] = N0[b] * (SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0]));
                         sum0 += N0[b];
@@ -1717,13 +1599,15 @@ __device__ __forceinline__ void for_each_cell(FrtSolveDesc* descs, const unsigne
 //   x' - x = dt [ -Gamma x' - C n_H (1-x') x' + alpha n_H (1-x')^2 ]
 // (Eq. ion_balance_eqn), i.e. a x'^2 + b x' + c = 0 with the root in [0,1]
 // taken as 2c / (-b + sqrt(b^2 - 4ac)).  Also rebuilds the opacity of the
-// next step and clears the next step's deposit buffer.  A step whose queues
-// overflowed leaves the state untouched.
+// next step (in place) and clears the next step's deposit buffer.  A launch
+// in which any solve's queues overflowed leaves every solve's state
+// untouched: the whole launch is run again from the start of the step.
 template <typename Real>
 __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsigned long long* prefix,
-                                                int n_solves, unsigned long long total)
+                                                int n_solves, unsigned long long total, const uint32_t* launch_err)
 {
     __shared__ unsigned long long spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
+    if (*launch_err) return;
     for (int i = threadIdx.x; i <= n_solves; i += blockDim.x) spre[i] = prefix[i];
     __syncthreads();
     for_each_cell(descs, spre, n_solves, total, [&](const FrtSolveDesc& D, size_t i) {
@@ -1770,12 +1654,16 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
 //   gamma_updated_standard) and starts from a cleared deposit buffer;
 // phase 2, after the last march: x = x(dt), the next step's opacity from it
 //   and its deposit buffer cleared.
-// A step whose queues overflowed leaves the state untouched.
+// A launch in which any solve's queues overflowed leaves every solve's state
+// untouched (phases 1 and 2 do nothing); phase 0 starts every run of the
+// step, the first and any re-run, from the state the step began with.
 template <typename Real>
 __global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const unsigned long long* prefix,
-                                                    int n_solves, unsigned long long total, int phase)
+                                                    int n_solves, unsigned long long total, int phase,
+                                                    const uint32_t* launch_err)
 {
     __shared__ unsigned long long spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
+    if (phase != 0 && *launch_err) return;
     for (int i = threadIdx.x; i <= n_solves; i += blockDim.x) spre[i] = prefix[i];
     __syncthreads();
     for_each_cell(descs, spre, n_solves, total, [&](const FrtSolveDesc& D, size_t i) {
@@ -2027,12 +1915,12 @@ hipError_t launch_finish(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
 }
 
 hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
-                       unsigned long long total_cells, int fp64, hipStream_t s)
+                       unsigned long long total_cells, int fp64, const uint32_t* launch_err, hipStream_t s)
 {
     if (total_cells == 0) return hipSuccess;
     const int grid = grid_for(total_cells, 16);
-    if (fp64) hipLaunchKernelGGL(k_chem<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells);
-    else hipLaunchKernelGGL(k_chem<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells);
+    if (fp64) hipLaunchKernelGGL(k_chem<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, launch_err);
+    else hipLaunchKernelGGL(k_chem<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, launch_err);
     return hipGetLastError();
 }
 
@@ -2044,12 +1932,14 @@ hipError_t launch_clear(const FrtWS& ws, int keep_err, hipStream_t s)
 }
 
 hipError_t launch_chem_avg(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
-                           unsigned long long total_cells, int fp64, int phase, hipStream_t s)
+                           unsigned long long total_cells, int fp64, int phase, const uint32_t* launch_err, hipStream_t s)
 {
     if (total_cells == 0) return hipSuccess;
     const int grid = grid_for(total_cells, 16);
-    if (fp64) hipLaunchKernelGGL(k_chem_avg<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase);
-    else hipLaunchKernelGGL(k_chem_avg<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase);
+    if (fp64)
+        hipLaunchKernelGGL(k_chem_avg<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase, launch_err);
+    else
+        hipLaunchKernelGGL(k_chem_avg<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase, launch_err);
     return hipGetLastError();
 }
 

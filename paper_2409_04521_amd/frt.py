@@ -29,7 +29,7 @@ EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_
            "frt_rotation_uniforms", "frt_batch_run", "frt_tuning_default", "frt_ctx_set_tuning",
            "frt_ctx_get_tuning", "frt_autotune", "frt_request_bytes", "frt_server_create", "frt_server_submit",
            "frt_server_poll", "frt_server_wait", "frt_server_take", "frt_server_times", "frt_server_get_stats",
-           "frt_server_destroy", "frt_debug_cast", "frt_step_static")
+           "frt_server_destroy", "frt_debug_cast", "frt_step_static", "frt_merge_uniforms")
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
@@ -45,7 +45,8 @@ class Params(C.Structure):
                 ("max_level", C.c_int), ("n_ray_min", C.c_double), ("flux_floor", C.c_double),
                 ("max_distance_cm", C.c_double), ("c_ray_cm_s", C.c_double), ("march_precision", C.c_int),
                 ("seed", C.c_uint64), ("queue_capacity", C.c_uint64), ("queue_hint", C.c_uint64),
-                ("chem_iterations", C.c_int), ("opacity_mode", C.c_int), ("he_chi", C.c_double)]
+                ("chem_iterations", C.c_int), ("opacity_mode", C.c_int), ("he_chi", C.c_double),
+                ("merge", C.c_int), ("merge_level", C.c_int), ("merge_exempt", C.c_double)]
 
 
 class Ledger(C.Structure):
@@ -55,7 +56,8 @@ class Ledger(C.Structure):
                 ("splits", C.c_uint64), ("n_escaped", C.c_uint64), ("n_dropped", C.c_uint64),
                 ("n_in_flight", C.c_uint64), ("rays_emitted", C.c_uint64), ("step_crossings", C.c_uint64),
                 ("steps", C.c_uint64), ("err_flags", C.c_uint32), ("max_items", C.c_uint32),
-                ("absorbed_front", C.c_double)]
+                ("absorbed_front", C.c_double), ("merge_residual", C.c_double), ("merges", C.c_uint64),
+                ("rays_merged", C.c_uint64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -168,6 +170,7 @@ def lib():
         L.frt_set_timing.argtypes = [vp, C.c_int]
         L.frt_read_timing.argtypes = [vp, C.POINTER(Timing)]
         L.frt_rotation_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_double)]
+        L.frt_merge_uniforms.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.POINTER(C.c_double)]
         L.frt_batch_run.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(C.c_double), C.c_int, C.c_int]
         L.frt_tuning_default.argtypes = [C.POINTER(Tuning)]
         L.frt_ctx_set_tuning.argtypes = [vp, C.POINTER(Tuning)]
@@ -222,6 +225,12 @@ def rotation_uniforms(seed: int, step: int, src: int):
     return np.array(out[:])
 
 
+def merge_uniforms(seed: int, step: int, cell: int):
+    out = (C.c_double * 3)()
+    _check(lib().frt_merge_uniforms(seed, step, cell, out))
+    return np.array(out[:])
+
+
 class Context:
     """frt_ctx on HIP device `device`; allocator=None uses hipMalloc, a
     TorchAllocator (or anything with alloc_fn / free_fn ctypes callbacks)
@@ -272,7 +281,7 @@ class Solve:
     def __init__(self, ctx: Context, *, sigma_bins, alpha_B=2.59e-13, coll_ion=0.0, base_level=0,
                  max_level=12, n_ray_min=1.0, flux_floor=0.0, max_distance_cm=0.0, c_ray=2.99792458e10,
                  precision="f32", seed=0, queue_capacity=0, queue_hint=0, chem_iterations=0, opacity_mode=0,
-                 he_chi=0.0, stream=None):
+                 he_chi=0.0, merge=False, merge_level=0, merge_exempt=4.0, stream=None):
         p = params_default()
         sig = list(sigma_bins)
         p.n_bins = len(sig)
@@ -286,6 +295,7 @@ class Solve:
         p.seed, p.queue_capacity, p.queue_hint = seed, queue_capacity, queue_hint
         p.chem_iterations = chem_iterations
         p.opacity_mode, p.he_chi = opacity_mode, he_chi
+        p.merge, p.merge_level, p.merge_exempt = int(bool(merge)), merge_level, merge_exempt
         self.ctx = ctx
         self.params = p
         self.n_bins = p.n_bins
@@ -442,6 +452,9 @@ def _params_for(prob, precision="f32", **kw) -> Params:
     p.chem_iterations = getattr(prob, "chem_iterations", 0)
     p.opacity_mode = getattr(prob, "opacity_mode", 0)
     p.he_chi = getattr(prob, "he_chi", 0.0)
+    p.merge = int(bool(getattr(prob, "merge", False)))
+    p.merge_level = getattr(prob, "merge_level", 0)
+    p.merge_exempt = getattr(prob, "merge_exempt", 4.0)
     return p
 
 
@@ -555,7 +568,9 @@ def solve_from_problem(ctx: Context, prob, precision="f32", use_table=True, **kw
               base_level=prob.base_level, max_level=prob.max_level, n_ray_min=prob.n_ray_min,
               flux_floor=prob.flux_floor, max_distance_cm=prob.max_dist_cm, c_ray=prob.c_ray,
               precision=precision, seed=prob.seed, chem_iterations=getattr(prob, "chem_iterations", 0),
-              opacity_mode=getattr(prob, "opacity_mode", 0), he_chi=getattr(prob, "he_chi", 0.0), **kw)
+              opacity_mode=getattr(prob, "opacity_mode", 0), he_chi=getattr(prob, "he_chi", 0.0),
+              merge=getattr(prob, "merge", False), merge_level=getattr(prob, "merge_level", 0),
+              merge_exempt=getattr(prob, "merge_exempt", 4.0), **kw)
     nz, ny, nx = prob.shape
     s.load_grid(prob.n_H, prob.dx_cm * nx, kappa=prob.kappa, x_HI0=prob.x_HI0, T=prob.T)
     s.load_sources(prob.src_pos_cm, prob.ndot_bins)

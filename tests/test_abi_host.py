@@ -42,6 +42,11 @@ def test_library_generator_matches_inputs_module(seed, step, src):
     assert np.array_equal(frt.rotation_uniforms(seed, step, src), W.rotation_uniforms(seed, step, src + 1)[src])
 
 
+@pytest.mark.parametrize("seed,step,cell", [(0, 0, 0), (21, 2, 13823), (2 ** 40 + 5, 99, 16777215)])
+def test_library_merge_generator_matches_inputs_module(seed, step, cell):
+    assert np.array_equal(frt.merge_uniforms(seed, step, cell), W.merge_uniforms(seed, step, cell + 1)[cell])
+
+
 def test_no_device_fails_loudly():
     import torch
 

@@ -1,0 +1,166 @@
+"""Ray merging (§3.3) on the GPU against the FP64 oracle on the same seeded
+inputs: nearly ionized lognormal boxes with packets carried at a finite
+speed and merged at the end of every step (N_ex small enough that most
+packets merge; l_merge 0 and 1; with and without sub-grid opacity).  Bars as
+elsewhere: neutral fraction within 1e-3 and ledger terms within 1e-4 of the
+emitted photons in FP32, 1e-9 in FP64; the ledger closes with the merge
+residual; merged-packet counts agree; the carried packets respect Eq.
+Nray_per_cell_max; checkpoints, bookmarks and batches keep merged packets."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2409_04521_amd import frt
+from paper_2409_04521_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TERMS = ("emitted", "absorbed_HI", "absorbed_sub", "escaped", "dropped", "in_flight")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return frt.Context(0)
+
+
+def _box(n=24, n_src=5, exempt=0.02, level=0, seed=21, steps=6, kappa=False, merge=True):
+    p = W.lognormal_c2(n=n, n_src=n_src, n_steps=steps, box_cmpc_h=20.0 * n / 128, seed=seed)
+    p.x_HI0 = np.full(p.shape, 1e-3)
+    if not kappa:
+        p.kappa = None
+    p.c_ray = 5.0 * p.dx_cm / p.dt_s
+    p.merge, p.merge_level, p.merge_exempt = merge, level, exempt
+    return p
+
+
+def _oracle(p, steps):
+    o = O.Oracle(**p.oracle_kwargs())
+    o.set_sources(p.src_pos_cm, p.ndot_bins)
+    for s in range(steps):
+        o.step(p.dt_s, p.uniforms(s), merge_uniforms=p.merge_uniforms(s))
+    return o
+
+
+def _gpu(ctx, p, steps, **kw):
+    g = frt.solve_from_problem(ctx, p, **kw)
+    for _ in range(steps):
+        g.step(p.dt_s)
+    return g
+
+
+def _compare(o, g, x_tol, led_tol, label):
+    xo, _ = o.fields()
+    xg, _ = g.fields()
+    Lo, Lg = o.ledger(), g.ledger()
+    E = Lo["emitted"]
+    dx = float(np.abs(xo - xg).max())
+    worst = {k: abs(Lo[k] - Lg[k]) / E for k in TERMS}
+    print(f"[{label}] max|dx_HI| = {dx:.3e}  ledger rel = " + ", ".join(f"{k}:{v:.1e}" for k, v in worst.items())
+          + f"  merges oracle={Lo['merges']} gpu={Lg['merges']}, merged in {Lo['rays_merged']} / {Lg['rays_merged']}, "
+          f"carried {Lo['n_in_flight']} / {Lg['n_in_flight']}, residual {Lg['merge_residual'] / E:.1e}", flush=True)
+    assert dx <= x_tol, label
+    for k, v in worst.items():
+        assert v <= led_tol, (label, k)
+    closure = abs(Lg["emitted"] - sum(Lg[k] for k in TERMS[1:]) - Lg["lost"] - Lg["merge_residual"]) / Lg["emitted"]
+    assert closure <= 1e-9, (label, closure)
+    assert Lg["err_flags"] == 0 and Lg["lost"] == 0
+    assert Lg["merges"] > 0
+    return Lo, Lg
+
+
+@pytest.mark.parametrize("level", [0, 1])
+@pytest.mark.parametrize("precision,x_tol,led_tol", [("f64", 1e-9, 1e-9), ("f32", 1e-3, 1e-4)])
+def test_merging_matches_the_oracle(ctx, level, precision, x_tol, led_tol):
+    p = _box(level=level)
+    Lo, Lg = _compare(_oracle(p, p.n_steps), _gpu(ctx, p, p.n_steps, precision=precision), x_tol, led_tol,
+                      f"merge l={level} {precision}")
+    if precision == "f64":
+        assert Lg["merges"] == Lo["merges"] and Lg["rays_merged"] == Lo["rays_merged"]
+    else:
+        assert abs(Lg["merges"] / Lo["merges"] - 1) < 0.01
+
+
+@pytest.mark.parametrize("precision,x_tol,led_tol", [("f64", 1e-9, 1e-9), ("f32", 1e-3, 1e-4)])
+def test_merging_with_subgrid_opacity(ctx, precision, x_tol, led_tol):
+    p = _box(kappa=True, seed=23, level=1, exempt=0.03)
+    _compare(_oracle(p, p.n_steps), _gpu(ctx, p, p.n_steps, precision=precision), x_tol, led_tol,
+             f"merge kappa {precision}")
+
+
+def _carried(g, p, fp64):
+    """Cells of the carried packets, from the checkpoint (records after the
+    header, the 160-byte ledger, x_HI and the quaternions)."""
+    blob = g.save()
+    hdr = np.frombuffer(blob[:64], dtype=np.uint64)
+    step, nc = int(hdr[2]), int(hdr[7])
+    off = 64 + 160 + 8 * p.ncell + 32 * step * p.n_src
+    size = 112 if fp64 else 64
+    recs = np.frombuffer(blob[off: off + nc * size], dtype=np.uint8).reshape(nc, size)
+    cell = recs[:, 12:16].copy().view(np.uint32).reshape(-1)
+    x, y, z = cell & 2047, (cell >> 11) & 2047, cell >> 22
+    nz, ny, nx = p.shape
+    return x + nx * (y + ny * z)
+
+
+def test_carried_packets_respect_the_per_cell_bound(ctx):
+    # Eq. Nray_per_cell_max: after a merge every cell holds at most 12 4^l
+    # merged or lone packets besides the floor(N_ex N_RT) exempt ones
+    p = _box(level=0, exempt=0.02, steps=5)
+    g = _gpu(ctx, p, p.n_steps)
+    cells = _carried(g, p, False)
+    E = int(math.floor(p.merge_exempt * p.ncell))
+    assert cells.size == g.ledger()["n_in_flight"]
+    per = np.bincount(cells, minlength=p.ncell)
+    excess = np.clip(per - 12, 0, None).sum()
+    print(f"carried {cells.size}, exempt allowance {E}, packets above 12 per cell {excess}", flush=True)
+    assert excess <= E
+
+
+def test_checkpoint_and_bookmark_keep_merged_packets(ctx):
+    p = _box(steps=5)
+    ref = _gpu(ctx, p, 5, precision="f64")
+    a = _gpu(ctx, p, 3, precision="f64")
+    blob = a.save()
+    b = frt.solve_from_problem(ctx, p, precision="f64")
+    b.load(blob)
+    for _ in range(2):
+        b.step(p.dt_s)
+    assert np.abs(ref.fields()[0] - b.fields()[0]).max() <= 1e-12
+    La, Lb = ref.ledger(), b.ledger()
+    for k in TERMS + ("merges", "rays_merged"):
+        assert La[k] == pytest.approx(Lb[k], rel=1e-12), k
+    # mark / rewind repeats the same two steps
+    a.mark()
+    for _ in range(2):
+        a.step(p.dt_s)
+    x1 = a.fields()[0]
+    a.rewind()
+    for _ in range(2):
+        a.step(p.dt_s)
+    assert np.abs(a.fields()[0] - x1).max() <= 1e-12
+
+
+def test_batch_of_merging_and_plain_solves_equals_each_alone(ctx):
+    pm = _box(steps=4)
+    pp = _box(steps=4, merge=False, seed=29)
+    am, ap = _gpu(ctx, pm, 4, precision="f64"), _gpu(ctx, pp, 4, precision="f64")
+    bm = frt.solve_from_problem(ctx, pm, precision="f64")
+    bp = frt.solve_from_problem(ctx, pp, precision="f64")
+    frt.batch_run([bm, bp], [pm.dt_s, pp.dt_s], 4, graph=True)   # stepped launch by launch (merging)
+    for a, b in ((am, bm), (ap, bp)):
+        assert np.abs(a.fields()[0] - b.fields()[0]).max() <= 1e-12
+        assert a.ledger()["merges"] == b.ledger()["merges"]
+
+
+def test_merge_parameters_are_checked(ctx):
+    for kw in ({"merge_level": 9}, {"merge_exempt": -1.0}, {"merge_exempt": float("nan")}):
+        with pytest.raises(frt.FrtError) as e:
+            frt.Solve(ctx, sigma_bins=[6.3e-18], merge=True, **kw)
+        assert e.value.code == frt.FRT_EINVAL
+    p = _box(steps=1)
+    g = frt.solve_from_problem(ctx, p)
+    with pytest.raises(frt.FrtError) as e:
+        g.step_static(p.dt_s)
+    assert e.value.code == frt.FRT_EINVAL

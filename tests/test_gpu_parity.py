@@ -235,6 +235,76 @@ def test_fixed_capacity_overflow_is_reported_and_not_applied(ctx):
     _compare(_oracle(p, 2), big, 1e-3, 1e-4, "fixed capacity")
 
 
+def _lognormal_24(seed, ionized, c_cells=5.0, n_ray_min=None):
+    p = W.lognormal_c2(n=24, n_src=5, n_steps=2, box_cmpc_h=20.0 * 24 / 128, seed=seed)
+    if ionized:
+        p.x_HI0 = np.full(p.shape, 1e-3)
+    p.kappa = None
+    p.c_ray = c_cells * p.dx_cm / p.dt_s
+    if n_ray_min is not None:
+        p.n_ray_min = n_ray_min
+    return p
+
+
+@pytest.mark.parametrize("K", [0, 3])
+def test_a_batch_run_again_after_an_overflow_leaves_each_solve_as_alone(K):
+    # a batch whose second solve overflows its carried-packet queue is run
+    # again from the start of the step with that queue enlarged; the first
+    # solve's chemistry of the failed run (x and opacity are updated in
+    # place) must not be kept, so each solve ends as if stepped alone
+    a = _lognormal_24(31, ionized=False)
+    b = _lognormal_24(37, ionized=True, c_cells=12.0, n_ray_min=4.0)
+    for p in (a, b):
+        p.chem_iterations = K
+    c1 = frt.Context(0)
+    ga = frt.solve_from_problem(c1, a, precision="f64")
+    gb = frt.solve_from_problem(c1, b, precision="f64")
+    frt.batch_step([ga, gb], [a.dt_s, b.dt_s])
+    # more packets carried than the carried queue first held (the cast
+    # packets, 1024 more and the cells): the step was run again
+    cast = b.n_src * 12 * 4 ** b.base_level
+    first_cap = cast + 1024 + min(b.ncell, 8 * cast + 65536)
+    assert gb.ledger()["n_in_flight"] > first_cap
+    frt.batch_step([ga, gb], [a.dt_s, b.dt_s])
+    c2 = frt.Context(0)
+    for p, g in ((a, ga), (b, gb)):
+        r = _gpu(c2, p, 2, precision="f64")
+        dx = float(np.abs(r.fields()[0] - g.fields()[0]).max())
+        Lr, Lg = r.ledger(), g.ledger()
+        print(f"[{p.name} K={K}] batched vs alone max|dx_HI| = {dx:.1e}, crossings {Lg['crossings']} / {Lr['crossings']}",
+              flush=True)
+        assert dx <= 1e-12
+        assert Lg["crossings"] == Lr["crossings"]
+        for k in ("emitted", "absorbed_HI", "escaped", "dropped", "in_flight"):
+            assert Lg[k] == pytest.approx(Lr[k], rel=1e-12, abs=1e-12 * Lr["emitted"]), k
+        r.close()
+    for g in (ga, gb):
+        g.close()
+    c1.close()
+    c2.close()
+
+
+def test_fixed_capacity_overflow_in_a_batch_applies_no_solve(ctx):
+    # one solve's carried queue is too small: the batch step fails and no
+    # solve of the batch changes, also those whose own queues held
+    a = _lognormal_24(31, ionized=False)
+    b = _lognormal_24(37, ionized=True, c_cells=12.0, n_ray_min=4.0)
+    ga = frt.solve_from_problem(ctx, a, precision="f64", queue_capacity=8_000_000)
+    gb = frt.solve_from_problem(ctx, b, precision="f64", queue_capacity=1000)
+    xa0, xb0 = ga.fields()[0], gb.fields()[0]
+    with pytest.raises(frt.FrtError) as e:
+        frt.batch_step([ga, gb], [a.dt_s, b.dt_s])
+    assert e.value.code == frt.FRT_EOVERFLOW
+    for g, x0 in ((ga, xa0), (gb, xb0)):
+        L = g.ledger()
+        assert np.array_equal(g.fields()[0], x0)
+        assert L["steps"] == 0 and L["emitted"] == 0 and L["err_flags"] == 0
+    # the solve that fits then steps as it does alone
+    ga.step(a.dt_s)
+    r = _gpu(ctx, a, 1, precision="f64", queue_capacity=8_000_000)
+    assert float(np.abs(r.fields()[0] - ga.fields()[0]).max()) <= 1e-12
+
+
 def test_invalid_inputs_are_rejected(ctx):
     p = W.stromgren_c1(n=8)
     s = frt.Solve(ctx, sigma_bins=[W.SIGMA_HI_0])
@@ -274,13 +344,13 @@ def test_many_splits_per_step_at_finite_c(ctx):
 def _carried_radii(g, n_src, ncell, fp64):
     """Distances from their sources (cells) of the packets a solve carries,
     read from its checkpoint: 8 u64 header (the carried count last), the
-    ledger (136 bytes), x_HI, the rotation quaternions of the steps so far,
+    ledger (160 bytes), x_HI, the rotation quaternions of the steps so far,
     then the packet records (64 bytes in FP32 with r at byte 20, 112 in FP64
     with r at byte 24)."""
     blob = g.save()
     hdr = np.frombuffer(blob[:64], dtype=np.uint64)
     step, nc = int(hdr[2]), int(hdr[7])
-    off = 64 + 136 + 8 * ncell + 32 * step * n_src
+    off = 64 + 160 + 8 * ncell + 32 * step * n_src
     size, at, dt = (112, 24, np.float64) if fp64 else (64, 20, np.float32)
     recs = np.frombuffer(blob[off: off + nc * size], dtype=np.uint8).reshape(nc, size)
     return recs[:, at: at + np.dtype(dt).itemsize].copy().view(dt).reshape(-1).astype(np.float64)
