@@ -210,6 +210,91 @@ def genopacity_leg(frt, W, steps: int, warmup: int, stream):
     return out
 
 
+def merge_leg(frt, W, steps: int, stream):
+    """Ray merging (§3.3) where it pays: packets carried at c for many steps
+    through ionized gas lit by many sources, so that every cell sees packets
+    of many sources.  The C3 density field and source recipe at 128^3 with
+    the C3 cell size and 2000 sources, x_HI = 1e-4 at the start, c_hat = c
+    and dt = dx / c (one cell per step, the paper's stepping), N_min = 2, and
+    the paper's merging-test parameters l_merge = 0, N_ex = 4.  Without and
+    with merging: time of the whole run (the merge included) once a first
+    pass has grown every queue (the run is repeated from a bookmark), packets
+    carried and the largest pass at the end, the peak device memory of the
+    library, and the change of the global means of x_HI and Gamma."""
+    import numpy as np
+    import torch
+
+    out = {"steps": steps}
+    res = {}
+    for merge in (False, True):
+        prob = W.grf_c3(n=128, n_src=2000, throughput=True, n_steps=steps, box_cmpc_h=50.0)
+        prob.c_ray = W.C_LIGHT
+        prob.dt_s = prob.dx_cm / W.C_LIGHT
+        prob.n_ray_min = 2.0
+        prob.merge, prob.merge_level, prob.merge_exempt = merge, 0, 4.0
+        out["workload"] = (f"C3 field and sources at 128^3, 50 cMpc/h, 2000 sources, 4 bins, x_HI 1e-4 at the start, "
+                           f"c, dt = dx/c = {prob.dt_s / 3.15576e13:.2f} Myr, N_min 2, l_merge 0, N_ex 4")
+        # the library's device memory through torch's allocator, so that
+        # torch's peak counter sees every buffer it holds
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        torch.cuda.reset_peak_memory_stats()
+        base = torch.cuda.memory_allocated()
+        ctx = frt.Context(0, allocator=frt.TorchAllocator(0))
+        s = frt.solve_from_problem(ctx, prob, stream=stream.cuda_stream)
+        # a first, untimed pass over the run grows every queue to its size;
+        # the timed pass repeats it from the bookmarked start
+        s.mark()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            s.step(prob.dt_s)
+        s.sync()
+        first_s = time.perf_counter() - t0
+        L0 = s.ledger()
+        s.rewind()
+        s.set_timing(True)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(steps):
+            s.step(prob.dt_s)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        tm = s.timing()
+        L = s.ledger()
+        x, g = s.fields()
+        tag = "merged" if merge else "plain"
+        out[f"{tag}_ms"] = ms
+        out[f"{tag}_first_pass_ms"] = first_s * 1e3
+        out[f"{tag}_march_ms"] = tm["march_ms"]
+        out[f"{tag}_chem_ms"] = tm["chem_ms"]
+        out[f"{tag}_other_ms"] = tm["emit_ms"] + tm["other_ms"]
+        out[f"{tag}_carried_at_end"] = L["n_in_flight"]
+        out[f"{tag}_largest_pass"] = L["max_items"]
+        out[f"{tag}_ray_visits"] = L["ray_visits"] - L0["ray_visits"]
+        out[f"{tag}_crossings"] = L["crossings"] - L0["crossings"]
+        out[f"{tag}_device_peak_GB"] = (torch.cuda.max_memory_allocated() - base) / 1e9
+        # the ledger of the first pass (it keeps counting across the rewind)
+        out[f"{tag}_ledger_closure"] = abs(L0["emitted"] - L0["absorbed_HI"] - L0["absorbed_sub"] - L0["escaped"]
+                                           - L0["dropped"] - L0["in_flight"] - L0["lost"]
+                                           - L0["merge_residual"]) / L0["emitted"]
+        if merge:
+            out["merge_ms"] = tm["merge_ms"]
+            out["merges"] = L["merges"] - L0["merges"]
+            out["rays_merged"] = L["rays_merged"] - L0["rays_merged"]
+        res[merge] = (float(np.mean(x)), float(np.mean(g.astype(np.float64))))
+        s.close()
+        ctx.close()
+    out["speedup"] = out["plain_ms"] / out["merged_ms"]
+    out["carried_ratio"] = out["plain_carried_at_end"] / max(1, out["merged_carried_at_end"])
+    out["memory_ratio"] = out["plain_device_peak_GB"] / max(1e-9, out["merged_device_peak_GB"])
+    out["mean_x_HI_rel_change"] = res[True][0] / res[False][0] - 1.0
+    out["mean_gamma_rel_change"] = res[True][1] / res[False][1] - 1.0
+    return out
+
+
 def batched_leg(frt, W, n_boxes: int, steps: int, warmup: int, stream):
     """The uneven-box batch: the same boxes stepped one solve at a time
     (the plain per-solve path) and as one batch replayed from a HIP graph
@@ -350,6 +435,8 @@ def main():
     ap.add_argument("--avgchem-iterations", type=int, default=3)
     ap.add_argument("--avgchem-steps", type=int, default=10)
     ap.add_argument("--no-genopacity", action="store_true", help="skip the Generalized Opacity Mode leg")
+    ap.add_argument("--no-merge", action="store_true", help="skip the ray-merging leg")
+    ap.add_argument("--merge-steps", type=int, default=60)
     ap.add_argument("--no-served", action="store_true", help="skip the served (request trace) leg")
     ap.add_argument("--served-requests", type=int, default=32)
     ap.add_argument("--served-steps", type=int, default=50)
@@ -482,6 +569,14 @@ def main():
             f"{go['generalized_crossings_per_s']:.3e} crossings/s (standard mode on the same box "
             f"{go['standard_ms_per_step']:.2f} ms/step); {go['front_share_of_emitted']:.2f} of photons stopped "
             f"at fronts, mean x_ion {go['mean_x_ion']:.3f}")
+    if not args.no_merge:
+        log(f"ray-merging leg: {args.merge_steps} steps without and with merging")
+        out["merge"] = merge_leg(frt, W, args.merge_steps, stream)
+        mg = out["merge"]
+        log(f"ray merging: {mg['merged_ms']:.0f} ms vs {mg['plain_ms']:.0f} ms without (x{mg['speedup']:.2f}); "
+            f"carried {mg['merged_carried_at_end']} vs {mg['plain_carried_at_end']}, device "
+            f"{mg['merged_device_peak_GB']:.1f} vs {mg['plain_device_peak_GB']:.1f} GB at peak; mean x_HI {mg['mean_x_HI_rel_change']:+.1e}, "
+            f"mean Gamma {mg['mean_gamma_rel_change']:+.1e}")
     if not args.no_served:
         log(f"served leg: {args.served_requests} requests, {args.served_steps} steps each")
         out["served"] = served_leg(frt, W, args.served_requests, args.served_steps, args.served_rate,

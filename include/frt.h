@@ -332,10 +332,12 @@ int frt_rewind(frt_solve s);
 /* Per-kernel device time, measured with HIP events on the solve's stream
  * around each launch while timing is enabled (cumulative since enabling).
  * march_ms covers every march round; chem_ms the chemistry kernel; other_ms
- * casting, round planning and step bookkeeping. */
+ * casting, round planning and step bookkeeping; merge_ms the ray merging
+ * after each step of a merging solve (§3.3). */
 typedef struct {
     double emit_ms, march_ms, chem_ms, other_ms;
     uint64_t march_launches, chem_launches, steps;
+    double merge_ms;
 } frt_timing;
 
 int frt_set_timing(frt_solve s, int enable);

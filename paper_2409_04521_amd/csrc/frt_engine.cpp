@@ -196,10 +196,11 @@ struct Workspace {
     struct Merge {
         uint32_t mcap = 0, mold = 0;
         size_t rec = 0, temp_bytes = 0;
-        void *pkey = nullptr, *pkey_sorted = nullptr, *dst = nullptr, *temp = nullptr;
+        void *pkey = nullptr, *pkey_sorted = nullptr, *temp = nullptr;
         unsigned long long *gkey = nullptr, *gkey_s = nullptr, *stats = nullptr;
         uint32_t *idx = nullptr, *idx_s = nullptr, *flag_out = nullptr, *slot = nullptr, *flag_lead = nullptr,
-                 *gid = nullptr, *ref = nullptr, *vmap = nullptr, *counts = nullptr;
+                 *gid = nullptr, *ref = nullptr, *vmap = nullptr, *counts = nullptr, *acc_head = nullptr;
+        double* acc = nullptr;
         double* residual = nullptr;
     } mg;
 
@@ -224,9 +225,10 @@ struct Workspace {
 
     void free_merge()
     {
-        dev_free(mg.pkey); dev_free(mg.pkey_sorted); dev_free(mg.dst); dev_free(mg.temp); dev_free(mg.gkey);
+        dev_free(mg.pkey); dev_free(mg.pkey_sorted); dev_free(mg.temp); dev_free(mg.gkey);
         dev_free(mg.gkey_s); dev_free(mg.stats); dev_free(mg.idx); dev_free(mg.idx_s); dev_free(mg.flag_out);
         dev_free(mg.slot); dev_free(mg.flag_lead); dev_free(mg.gid); dev_free(mg.ref); dev_free(mg.vmap);
+        dev_free(mg.acc); dev_free(mg.acc_head);
         dev_free(mg.counts); dev_free(mg.residual);
         mg = Merge{};
     }
@@ -311,7 +313,7 @@ struct frt_solve_s {
     bool timing = false;
     struct Ev { hipEvent_t a, b; int kind; };
     std::vector<Ev> pending;
-    double t_ms[4] = {0, 0, 0, 0};          // seed, brick march, chem, other (scan, scatter, fold)
+    double t_ms[5] = {0, 0, 0, 0, 0};       // seed, brick march, chem, other (scan, scatter, fold), merge
     uint64_t n_march = 0, n_chem = 0, n_steps_timed = 0;
 
     ~frt_solve_s() { release_all(); }
@@ -861,9 +863,18 @@ bool split_by_shape(frt_solve* ss, int n, const double* dts, std::vector<std::ve
     return true;
 }
 
+int alloc_merge(Workspace& ws, uint32_t n, uint32_t n_old, int fp64);
+
 // Room in the context's merge scratch for n carried packets referring to a
-// table of n_old entries.
+// table of n_old entries; on failure no scratch is held.
 int ensure_merge(Workspace& ws, uint32_t n, uint32_t n_old, int fp64)
+{
+    const int rc = alloc_merge(ws, n, n_old, fp64);
+    if (rc != FRT_OK) ws.free_merge();
+    return rc;
+}
+
+int alloc_merge(Workspace& ws, uint32_t n, uint32_t n_old, int fp64)
 {
     Workspace::Merge& m = ws.mg;
     const size_t rs = fp64 ? 8 : 4, rec = rec_bytes(rs);
@@ -873,7 +884,6 @@ int ensure_merge(Workspace& ws, uint32_t n, uint32_t n_old, int fp64)
         ws.free_merge();
         RCCHK(dev_alloc(&m.pkey, (size_t)cap * rs));
         RCCHK(dev_alloc(&m.pkey_sorted, (size_t)cap * rs));
-        RCCHK(dev_alloc(&m.dst, (size_t)cap * rec));
         RCCHK(dev_alloc((void**)&m.gkey, (size_t)cap * 8));
         RCCHK(dev_alloc((void**)&m.gkey_s, (size_t)cap * 8));
         RCCHK(dev_alloc((void**)&m.idx, (size_t)cap * 4));
@@ -882,6 +892,10 @@ int ensure_merge(Workspace& ws, uint32_t n, uint32_t n_old, int fp64)
         RCCHK(dev_alloc((void**)&m.slot, (size_t)cap * 4));
         RCCHK(dev_alloc((void**)&m.flag_lead, (size_t)cap * 4));
         RCCHK(dev_alloc((void**)&m.gid, (size_t)cap * 4));
+        // sums of the groups that reach across a wave of 64 packets: one slot per wave
+        const size_t slots = (size_t)cap / 64 + 2;
+        RCCHK(dev_alloc((void**)&m.acc, slots * (7 + FRT_MAX_BINS_I) * sizeof(double)));
+        RCCHK(dev_alloc((void**)&m.acc_head, slots * 4));
         RCCHK(dev_alloc((void**)&m.ref, (size_t)old * 4));
         RCCHK(dev_alloc((void**)&m.vmap, (size_t)old * 4));
         RCCHK(dev_alloc((void**)&m.counts, 16));
@@ -897,36 +911,55 @@ int ensure_merge(Workspace& ws, uint32_t n, uint32_t n_old, int fp64)
 }
 
 // A solve's table of virtual origins `k` with room for `cap` entries (its
-// contents are not kept: only the table the next merge writes grows).
-int ensure_vtable(frt_solve s, int k, uint32_t cap)
+// contents are not kept: only the table the next merge writes grows), grown
+// to at least twice its size unless `exact`.  The old table is freed only
+// once the new one is held.
+int ensure_vtable(frt_solve s, int k, uint32_t cap, bool exact = false)
 {
     if (s->vt_cap[k] >= cap) return FRT_OK;
+    const uint32_t c = exact ? cap : std::max<uint32_t>(cap, 2 * s->vt_cap[k]);
+    FrtVSrc* t = nullptr;
+    RCCHK(dev_alloc((void**)&t, (size_t)c * sizeof(FrtVSrc)));
     dev_free(s->vt[k]);
-    const uint32_t c = std::max<uint32_t>(cap, 2 * s->vt_cap[k]);
-    RCCHK(dev_alloc((void**)&s->vt[k], (size_t)c * sizeof(FrtVSrc)));
+    s->vt[k] = t;
     s->vt_cap[k] = c;
-    s->h.vt[k] = s->vt[k];
+    s->h.vt[k] = t;
     return FRT_OK;
 }
 
-// Room for the merge after the next step of a merging solve, taken before the
-// step so that a step that ran is never left unmerged: the merge scratch for
-// every packet its carried queue can hold and every entry of the current
-// table of virtual origins, and the next table for one entry per carried
-// packet (a merge keeps at most one entry per packet carried as it is and
-// makes one per group of two or more, so never more entries than packets).
-int prepare_merge(Workspace& ws, frt_solve s)
+// Taken before a step of a merging solve, so that the step's packets can
+// always be carried, merged or not: room in the next table for every entry
+// of the current one.  The merge itself sizes its scratch and the next
+// table from what the step left (merge_after_step).
+int prepare_merge(frt_solve s)
 {
     const int cur = (int)(s->step & 1u), nxt = cur ^ 1;
-    RCCHK(ensure_merge(ws, s->F[nxt].cap, s->vt_cap[cur], s->fp64));
-    return ensure_vtable(s, nxt, s->F[nxt].cap);
+    uint32_t vc[2];
+    HIPCHK(hipMemcpyAsync(vc, s->vcount, 8, hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return ensure_vtable(s, nxt, vc[cur], true);
+}
+
+// The packets a merging solve carries into the next step, left unmerged:
+// the current table of virtual origins becomes the next one as it is.
+int carry_unmerged(frt_solve s, uint32_t n_old, hipStream_t st)
+{
+    const int cur = (int)(s->step & 1u), nxt = cur ^ 1;
+    if (n_old)
+        HIPCHK(hipMemcpyAsync(s->vt[nxt], s->vt[cur], (size_t)n_old * sizeof(FrtVSrc), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(s->vcount + nxt, &n_old, 4, hipMemcpyHostToDevice, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return FRT_OK;
 }
 
 // Ray merging (§3.3) of a solve after a step that ran without error: the
 // packets it carries into the next step are merged, and the virtual origins
 // they refer to renumbered into the table of the next step.  `d` is the
 // solve's descriptor of that step on the device (its step index not yet
-// advanced).  Waits for the merge.
+// advanced).  The merge scratch and the next table are sized from the
+// step's own counts; if the device cannot hold them the packets are carried
+// unmerged this step (the room for that was taken before the step).  Waits
+// for the merge.
 int merge_after_step(Workspace& ws, frt_solve s, FrtSolveDesc* d, hipStream_t st)
 {
     const int cur = (int)(s->step & 1u), nxt = cur ^ 1;
@@ -944,9 +977,8 @@ int merge_after_step(Workspace& ws, frt_solve s, FrtSolveDesc* d, hipStream_t st
         HIPCHK(hipStreamSynchronize(st));
         return FRT_OK;
     }
-    // reserved before the step (prepare_merge): nothing allocates here
-    if (ws.mg.mcap < n || ws.mg.mold < n_old || s->vt_cap[nxt] < n)
-        return fail(FRT_EDEVICE, "merge scratch smaller than reserved");
+    if (s->vt_cap[nxt] < n_old) return fail(FRT_EDEVICE, "next table of virtual origins smaller than reserved");
+    if (ensure_merge(ws, n, n_old, s->fp64) != FRT_OK) return carry_unmerged(s, n_old, st);
     Workspace::Merge& m = ws.mg;
     FrtMergeArgs a{};
     a.n = n;
@@ -973,12 +1005,33 @@ int merge_after_step(Workspace& ws, frt_solve s, FrtSolveDesc* d, hipStream_t st
     a.counts = m.counts;
     a.residual = m.residual;
     a.stats = m.stats;
-    a.dst = m.dst;
+    a.dst = s->F[cur].rec;   // read by the step's seeding, free now; as large as F[nxt]
+    a.acc = m.acc;
+    a.acc_head = m.acc_head;
+    a.n_slots = (n + 63) / 64;
     a.temp = m.temp;
     a.temp_bytes = m.temp_bytes;
-    const hipError_t e = frt::launch_merge(d, a, s->fp64, s->P.n_bins, st);
+    Timed t(s->timing ? s : nullptr, st, 4);
+    hipError_t e = frt::launch_merge(d, a, s->fp64, s->P.n_bins, 0, st);
+    if (e != hipSuccess) return fail(FRT_EDEVICE, "merge: %s", hipGetErrorString(e));
+    uint32_t counts[3];
+    HIPCHK(hipMemcpyAsync(counts, m.counts, 12, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (counts[0] > s->F[cur].cap) return fail(FRT_EDEVICE, "merged queue larger than the carried queue");
+    // the next table: the entries still referred to and one per merged group
+    const uint32_t need = counts[1] + counts[2];
+    if (s->vt_cap[nxt] < need) {
+        if (ensure_vtable(s, nxt, need) != FRT_OK) return carry_unmerged(s, n_old, st);
+        HIPCHK(hipMemcpyAsync((char*)d + offsetof(FrtSolveDesc, vt) + nxt * sizeof(FrtVSrc*), &s->vt[nxt],
+                              sizeof(FrtVSrc*), hipMemcpyHostToDevice, st));
+    }
+    e = frt::launch_merge(d, a, s->fp64, s->P.n_bins, 1, st);
     if (e != hipSuccess) return fail(FRT_EDEVICE, "merge: %s", hipGetErrorString(e));
     HIPCHK(hipStreamSynchronize(st));
+    // the merged queue is the next step's carried queue
+    std::swap(s->F[0], s->F[1]);
+    s->h.F[0] = s->F[0];
+    s->h.F[1] = s->F[1];
     return FRT_OK;
 }
 
@@ -1011,7 +1064,7 @@ int step_group_locked(frt_solve* ss, int n, const double* dts)
     for (int attempt = 0; attempt < 16; attempt++) {
         RCCHK(ensure_ws(ws, ss[0]->fp64, ss[0]->P.n_bins, n, nkeys, std::max<uint64_t>(want_p, ws.pcap)));
         for (int i = 0; i < n; i++)
-            if (ss[i]->P.merge) RCCHK(prepare_merge(ws, ss[i]));
+            if (ss[i]->P.merge) RCCHK(prepare_merge(ss[i]));
         Group g;
         plan_group(ws, ss, n, g);
         RCCHK(upload_group(ws, g, n, st));
@@ -2407,6 +2460,7 @@ int frt_read_timing(frt_solve s, frt_timing* out)
     out->march_launches = s->n_march;
     out->chem_launches = s->n_chem;
     out->steps = s->n_steps_timed;
+    out->merge_ms = s->t_ms[4];
     return FRT_OK;
 }
 

@@ -259,15 +259,20 @@ struct FrtMergeArgs {
     uint32_t* counts;           // [4] outputs, merged packets, kept entries
     double* residual;           // [1] photons before minus after
     unsigned long long* stats;  // [2] merged packets, packets merged into them
-    void* dst;                  // [n] output records
+    void* dst;                  // [n] output records (the solve's other carried queue)
+    double* acc;                // [n_slots][7 + FRT_MAX_BINS_I] sums of the groups that span waves
+    uint32_t* acc_head;         // [n_slots] sorted position of such a group's first packet, or all ones
+    uint32_t n_slots;           // (n + 63) / 64
     void* temp;                 // sort and scan storage
     size_t temp_bytes;
 };
 
 namespace frt {
 // Merge the packets a solve carries into the next step (§3.3); d is the
-// solve's descriptor of the step just run.
-hipError_t launch_merge(FrtSolveDesc* d, const FrtMergeArgs& a, int fp64, int n_bins, hipStream_t st);
+// solve's descriptor of the step just run.  Phase 0 counts (a.counts:
+// output packets, merged packets, kept table entries), phase 1 writes the
+// next table of virtual origins, which must hold counts[1] + counts[2].
+hipError_t launch_merge(FrtSolveDesc* d, const FrtMergeArgs& a, int fp64, int n_bins, int phase, hipStream_t st);
 size_t merge_temp_bytes(uint32_t n, uint32_t n_old, int fp64);
 // Device address of the static scratch on `device` (which must be current),
 // looked up with hipGetSymbolAddress on the first call per device and kept.

@@ -10,12 +10,14 @@
 // own level-l pixel onto the merged direction, so that the march moves and
 // splits it like any packet.
 //
-// One launch sequence per solve, after the step: keys (photons, and cell x
-// 2^20 + pixel), the exemption threshold from a descending sort of the
-// photons, a sort of the packets by group key, group flags and three scans
-// (output slots, merged packets, virtual-origin entries still referred to),
-// the merged packets and the carried ones written to a scratch queue, then
-// copied back over the solve's carried queue.
+// Two launch sequences per solve, after the step.  Counting: keys (photons,
+// and cell x 2^20 + pixel), the exemption threshold from a descending sort
+// of the photons, a sort of the packets by group key, group flags and three
+// scans (output slots, merged packets, virtual-origin entries still referred
+// to).  Writing, once the host has sized the next table from the counts:
+// the kept entries, the merged packets and the carried ones to the queue the
+// step's carried-in packets were read from (free once the step has run),
+// which then becomes the solve's carried queue.
 #include "frt_internal.h"
 #include "frt_device.h"
 
@@ -168,124 +170,245 @@ __device__ __forceinline__ void atomic_max_pos_float(float* p, float v)
     atomicMax((int*)p, __float_as_int(v));
 }
 
-// Output: a packet carried as it is (its table entry renumbered), or the
-// packet merged from a group, written by the group's first packet.
+// Per group member, the sums a merged packet is built from: photons W,
+// photon-weighted position (3), distance and level, the member count, then
+// the photons of each bin.
+constexpr int ACC_FIXED = 7;
+constexpr int ACC_N = ACC_FIXED + FRT_MAX_BINS_I;
+constexpr int WAVE = 64;
+
+// The packet merged from the group whose first packet is at sorted position
+// h, from the group's sums v: direction the centre of its merging pixel
+// (rotated), position, distance and level the photon-weighted means, photons
+// per bin summed; it refers to a new virtual origin (position - r dir, the
+// rotation that takes the centre of its own level-l pixel onto its
+// direction, photons per bin relative to R_ref w0).
 template <typename Real, int NB>
-__global__ void __launch_bounds__(BLOCK) k_merge_emit(const FrtSolveDesc* __restrict__ dp, FrtMergeArgs a)
+__device__ void write_merged(const FrtSolveDesc& D, const FrtMergeArgs& a, uint32_t h, const double* v, double& res,
+                             unsigned long long& merged_in, unsigned long long& groups, float& w0_hi)
 {
-    const FrtSolveDesc& D = *dp;
-    const FrtRec<Real>* F = (const FrtRec<Real>*)D.F[1 - D.cur].rec;
     FrtRec<Real>* dst = (FrtRec<Real>*)a.dst;
-    const uint32_t n_kept = a.counts[2];
-    double res = 0.0;
-    unsigned long long merged_in = 0, groups = 0;
-    for (uint32_t j = blockIdx.x * BLOCK + threadIdx.x; j < a.n; j += gridDim.x * BLOCK) {
-        if (!a.flag_out[j]) continue;
-        const uint32_t s = a.slot[j];
-        if (!a.flag_lead[j]) {
-            FrtRec<Real> r = F[a.idx_s[j]];
-            if (is_virtual(r.src) && (r.src & ~FRT_VSRC) < a.n_old) r.src = FRT_VSRC | a.vmap[r.src & ~FRT_VSRC];
-            dst[s] = r;
-            continue;
-        }
-        // a group: photon sums and photon-weighted means in FP64
-        const unsigned long long k = a.gkey_s[j];
-        double W = 0.0, pos[3] = {0.0, 0.0, 0.0}, rs = 0.0, ls = 0.0, Nb[NB];
+    const unsigned long long k = a.gkey_s[h];
+    const double W = v[0];
+    double pos[3];
+    for (int c = 0; c < 3; c++) pos[c] = v[1 + c] / W;
+    const double rbar = v[4] / W;
+    const int level = (int)floor(v[5] / W + 0.5);
+    const uint32_t cell = (uint32_t)(k >> PIX_BITS);
+    const uint32_t p = (uint32_t)(k & PIX_MASK);
+    const int lm = a.level;
+    const uint32_t pix_v = level >= lm ? p << (2 * (level - lm)) : p >> (2 * (lm - level));
+    double qc[4], dm[3], dv[3], qa[4], qv[4];
+    cell_rotation(D, cell, qc);
+    nest_pixel_centre<double>(lm, p, dm);
+    nest_pixel_centre<double>(level, pix_v, dv);
+    quat_between(dv, dm, qa);
+    quat_mul(qc, qa, qv);
+    quat_rotate<double>(qc, dm);            // the merged direction
+    // photons per bin relative to R_ref w0, at most 1
+    double mx = 0.0;
 #pragma unroll
-        for (int b = 0; b < NB; b++) Nb[b] = 0.0;
-        uint32_t m = 0;
-        for (uint32_t q = j; q < a.n && a.gkey_s[q] == k; q++, m++) {
-            const FrtRec<Real> r = F[a.idx_s[q]];
-            double N[NB];
-            packet_photons<Real, NB>(D, r, N);
-            double w = 0.0;
-#pragma unroll
-            for (int b = 0; b < NB; b++) {
-                w += N[b];
-                Nb[b] += N[b];
-            }
-            const double* o = src_pos_of(D, r.src);
-            for (int c = 0; c < 3; c++) pos[c] += w * (o[c] + (double)r.r * (double)r.dir[c]);
-            rs += w * (double)r.r;
-            ls += w * (double)(r.lp >> 28);
-            W += w;
-        }
-        for (int c = 0; c < 3; c++) pos[c] /= W;
-        const double rbar = rs / W;
-        int level = (int)floor(ls / W + 0.5);
-        const uint32_t cell = (uint32_t)(k >> PIX_BITS);
-        const uint32_t p = (uint32_t)(k & PIX_MASK);
-        const int lm = a.level;
-        const uint32_t pix_v = level >= lm ? p << (2 * (level - lm)) : p >> (2 * (lm - level));
-        double qc[4], dm[3], dv[3], qa[4], qv[4];
-        cell_rotation(D, cell, qc);
-        nest_pixel_centre<double>(lm, p, dm);
-        nest_pixel_centre<double>(level, pix_v, dv);
-        quat_between(dv, dm, qa);
-        quat_mul(qc, qa, qv);
-        quat_rotate<double>(qc, dm);            // the merged direction
-        // photons per bin relative to R_ref w0, at most 1
-        double mx = 0.0;
-#pragma unroll
-        for (int b = 0; b < NB; b++) mx = fmax(mx, Nb[b]);
-        const double w0 = mx / D.R_ref;
-        const uint32_t v = n_kept + a.gid[j];
-        FrtVSrc e;
-        for (int c = 0; c < 3; c++) e.pos[c] = pos[c] - rbar * dm[c];
-        for (int c = 0; c < 4; c++) e.q[c] = qv[c];
-        for (int b = 0; b < FRT_MAX_BINS_I; b++) e.spec[b] = b < NB && w0 > 0.0 ? Nb[b] / (D.R_ref * w0) : 0.0;
-        D.vt[1 - D.cur][v] = e;
-        FrtRec<Real> r{};
-        r.src = FRT_VSRC | v;
-        r.estep = D.step;
-        r.lp = ((uint32_t)level << 28) | pix_v;
-        // the merged position lies in the group's cell (a mean of points in
-        // it); on a face the packet is in the cell it enters
-        int cc[3] = {(int)(cell % (uint32_t)D.nx), (int)((cell / (uint32_t)D.nx) % (uint32_t)D.ny),
-                     (int)(cell / ((uint32_t)D.nx * (uint32_t)D.ny))};
-        const int dims[3] = {D.nx, D.ny, D.nz};
-        for (int c = 0; c < 3; c++) {
-            double f = floor(pos[c]);
-            if (pos[c] == f && dm[c] < 0.0) f -= 1.0;
-            if (f >= 0.0 && f < (double)dims[c]) cc[c] = (int)f;
-        }
-        r.cell = pack_cell(cc);
-        r.key = (uint32_t)(cc[0] >> D.bsh[0]) +
-                (uint32_t)D.bpx * ((uint32_t)(cc[1] >> D.bsh[1]) + (uint32_t)D.bpy * (uint32_t)(cc[2] >> D.bsh[2]));
-        r.r = (Real)rbar;
-        r.rstop = r.r;
-        r.w0 = (Real)w0;
-        for (int c = 0; c < 3; c++) r.dir[c] = (Real)dm[c];
-        dst[s] = r;
-        // photons the record now holds, as the march will compute them
-        double after = 0.0;
-#pragma unroll
-        for (int b = 0; b < NB; b++) {
-            const Real n0 = r.w0 * (Real)e.spec[b];
-            after += (double)n0 * D.R_ref;
-            res += Nb[b];
-        }
-        res -= after;
-        merged_in += m;
-        groups++;
-        atomic_max_pos_float(D.w0_merged, (float)w0 * 1.0000002f);
+    for (int b = 0; b < NB; b++) mx = fmax(mx, v[ACC_FIXED + b]);
+    const double w0 = mx / D.R_ref;
+    const uint32_t vi = a.counts[2] + a.gid[h];
+    FrtVSrc e;
+    for (int c = 0; c < 3; c++) e.pos[c] = pos[c] - rbar * dm[c];
+    for (int c = 0; c < 4; c++) e.q[c] = qv[c];
+    for (int b = 0; b < FRT_MAX_BINS_I; b++) e.spec[b] = b < NB && w0 > 0.0 ? v[ACC_FIXED + b] / (D.R_ref * w0) : 0.0;
+    D.vt[1 - D.cur][vi] = e;
+    FrtRec<Real> r{};
+    r.src = FRT_VSRC | vi;
+    r.estep = D.step;
+    r.lp = ((uint32_t)level << 28) | pix_v;
+    // the merged position lies in the group's cell (a mean of points in
+    // it); on a face the packet is in the cell it enters
+    int cc[3] = {(int)(cell % (uint32_t)D.nx), (int)((cell / (uint32_t)D.nx) % (uint32_t)D.ny),
+                 (int)(cell / ((uint32_t)D.nx * (uint32_t)D.ny))};
+    const int dims[3] = {D.nx, D.ny, D.nz};
+    for (int c = 0; c < 3; c++) {
+        double f = floor(pos[c]);
+        if (pos[c] == f && dm[c] < 0.0) f -= 1.0;
+        if (f >= 0.0 && f < (double)dims[c]) cc[c] = (int)f;
     }
-    if (groups) {
+    r.cell = pack_cell(cc);
+    r.key = (uint32_t)(cc[0] >> D.bsh[0]) +
+            (uint32_t)D.bpx * ((uint32_t)(cc[1] >> D.bsh[1]) + (uint32_t)D.bpy * (uint32_t)(cc[2] >> D.bsh[2]));
+    r.r = (Real)rbar;
+    r.rstop = r.r;
+    r.w0 = (Real)w0;
+    for (int c = 0; c < 3; c++) r.dir[c] = (Real)dm[c];
+    dst[a.slot[h]] = r;
+    // photons the record now holds, as the march will compute them
+    double after = 0.0;
+#pragma unroll
+    for (int b = 0; b < NB; b++) {
+        const Real n0 = r.w0 * (Real)e.spec[b];
+        after += (double)n0 * D.R_ref;
+        res += v[ACC_FIXED + b];
+    }
+    res -= after;
+    merged_in += (unsigned long long)v[6];
+    groups++;
+    w0_hi = fmaxf(w0_hi, (float)w0 * 1.0000002f);
+}
+
+// The wave's residual, counts and largest merged w0, added with one atomic
+// each by its first lane (every lane of the wave calls this).
+__device__ __forceinline__ void flush_merge_stats(const FrtSolveDesc& D, const FrtMergeArgs& a, double res,
+                                                  unsigned long long merged_in, unsigned long long groups, float w0_hi)
+{
+    for (int o = WAVE / 2; o > 0; o >>= 1) {
+        res += __shfl_xor(res, o, WAVE);
+        merged_in += __shfl_xor(merged_in, o, WAVE);
+        groups += __shfl_xor(groups, o, WAVE);
+        w0_hi = fmaxf(w0_hi, __shfl_xor(w0_hi, o, WAVE));
+    }
+    if ((threadIdx.x & (WAVE - 1)) == 0 && groups) {
         atomicAdd(a.residual, res);
         atomicAdd(&a.stats[0], groups);
         atomicAdd(&a.stats[1], merged_in);
+        atomic_max_pos_float(D.w0_merged, w0_hi);
     }
 }
 
-// The merged queue back over the carried queue; counts and ledger terms.
+// One thread per packet in group-key order.  A packet that is exempt or
+// alone in its group is carried as it is (its table entry renumbered).  The
+// members of a group of two or more add up their sums by a segmented scan
+// over the wave; the last member of a group in the wave then writes the
+// merged packet if the whole group lies in this wave, or adds the wave's
+// part to the group's accumulator otherwise (one per wave: the slot of the
+// wave that holds the group's first packet, since only the last group of a
+// wave can reach past it), which k_merge_finalize turns into the packet.
+template <typename Real, int NB>
+__global__ void __launch_bounds__(BLOCK) k_merge_emit(const FrtSolveDesc* __restrict__ dp, FrtMergeArgs a)
+{
+    static_assert(BLOCK % WAVE == 0, "waves cover whole 64-packet chunks");
+    const FrtSolveDesc& D = *dp;
+    const FrtRec<Real>* F = (const FrtRec<Real>*)D.F[1 - D.cur].rec;
+    FrtRec<Real>* dst = (FrtRec<Real>*)a.dst;
+    const int lane = (int)(threadIdx.x & (WAVE - 1));
+    double res = 0.0;
+    unsigned long long merged_in = 0, groups = 0;
+    float w0_hi = 0.f;
+    const uint32_t n_pad = (a.n + WAVE - 1) / WAVE * WAVE;   // whole waves take part in the shuffles
+    for (uint32_t j = blockIdx.x * BLOCK + threadIdx.x; j < n_pad; j += gridDim.x * BLOCK) {
+        const bool valid = j < a.n;
+        const unsigned long long k = valid ? a.gkey_s[j] : KEY_EXEMPT;
+        bool member = false, head = false, tail = false;
+        if (valid && !exempt_key(k, a.key_mask)) {
+            head = j == 0 || a.gkey_s[j - 1] != k;
+            tail = j + 1 == a.n || a.gkey_s[j + 1] != k;
+            member = !(head && tail);
+        }
+        double v[ACC_FIXED + NB];
+#pragma unroll
+        for (int c = 0; c < ACC_FIXED + NB; c++) v[c] = 0.0;
+        if (valid) {
+            FrtRec<Real> r = F[a.idx_s[j]];
+            if (!member) {
+                if (is_virtual(r.src) && (r.src & ~FRT_VSRC) < a.n_old) r.src = FRT_VSRC | a.vmap[r.src & ~FRT_VSRC];
+                dst[a.slot[j]] = r;
+            } else {
+                double N[NB];
+                packet_photons<Real, NB>(D, r, N);
+                double w = 0.0;
+#pragma unroll
+                for (int b = 0; b < NB; b++) {
+                    w += N[b];
+                    v[ACC_FIXED + b] = N[b];
+                }
+                const double* o = src_pos_of(D, r.src);
+                v[0] = w;
+                for (int c = 0; c < 3; c++) v[1 + c] = w * (o[c] + (double)r.r * (double)r.dir[c]);
+                v[4] = w * (double)r.r;
+                v[5] = w * (double)(r.lp >> 28);
+                v[6] = 1.0;
+            }
+        }
+        if (!__ballot(member)) continue;   // no group member in this wave (whole waves iterate together)
+        // the wave's runs of members with equal keys, each from its first lane
+        const unsigned long long prev_k = __shfl_up(k, 1, WAVE);
+        const int prev_member = __shfl_up((int)member, 1, WAVE);
+        const bool start = member && (lane == 0 || !prev_member || prev_k != k);
+        const unsigned long long starts = __ballot(start);
+        const unsigned long long heads = __ballot(member && head);
+        const unsigned long long upto = (lane == WAVE - 1) ? ~0ull : ((2ull << lane) - 1ull);
+        const int s0 = member ? 63 - __clzll(starts & upto) : lane;
+        for (int d = 1; d < WAVE; d <<= 1) {
+#pragma unroll
+            for (int c = 0; c < ACC_FIXED + NB; c++) {
+                const double o = __shfl_up(v[c], d, WAVE);
+                if (member && lane - d >= s0) v[c] += o;
+            }
+        }
+        const unsigned long long next_k = __shfl_down(k, 1, WAVE);
+        const int next_member = __shfl_down((int)member, 1, WAVE);
+        const bool run_end = member && (lane == WAVE - 1 || !next_member || next_k != k);
+        if (run_end) {
+            const uint32_t base = j - (uint32_t)lane;
+            const bool own_head = ((heads >> s0) & 1ull) != 0;
+            if (own_head && tail) {
+                write_merged<Real, NB>(D, a, base + (uint32_t)s0, v, res, merged_in, groups, w0_hi);
+            } else {
+                // the group's first packet: in this wave, or found by a search
+                // of the keys before it
+                uint32_t h = base + (uint32_t)s0;
+                if (!own_head) {
+                    uint32_t lo = 0, hi = base;
+                    while (lo < hi) {
+                        const uint32_t mid = (lo + hi) >> 1;
+                        if (a.gkey_s[mid] < k) lo = mid + 1;
+                        else hi = mid;
+                    }
+                    h = lo;
+                }
+                const uint32_t sl = h / WAVE;
+                double* acc = a.acc + (size_t)sl * ACC_N;
+#pragma unroll
+                for (int c = 0; c < ACC_FIXED + NB; c++) atomicAdd(acc + c, v[c]);
+                if (own_head) a.acc_head[sl] = h;
+            }
+        }
+    }
+    flush_merge_stats(D, a, res, merged_in, groups, w0_hi);
+}
+
+// The groups that reach across waves: one thread per accumulator slot.
+template <typename Real, int NB>
+__global__ void __launch_bounds__(BLOCK) k_merge_finalize(const FrtSolveDesc* __restrict__ dp, FrtMergeArgs a)
+{
+    const FrtSolveDesc& D = *dp;
+    double res = 0.0;
+    unsigned long long merged_in = 0, groups = 0;
+    float w0_hi = 0.f;
+    for (uint32_t sl = blockIdx.x * BLOCK + threadIdx.x; sl < a.n_slots; sl += gridDim.x * BLOCK) {
+        const uint32_t h = a.acc_head[sl];
+        if (h == ~0u) continue;
+        double v[ACC_FIXED + NB];
+        const double* acc = a.acc + (size_t)sl * ACC_N;
+#pragma unroll
+        for (int c = 0; c < ACC_FIXED + NB; c++) v[c] = acc[c];
+        write_merged<Real, NB>(D, a, h, v, res, merged_in, groups, w0_hi);
+    }
+    flush_merge_stats(D, a, res, merged_in, groups, w0_hi);
+}
+
+__global__ void __launch_bounds__(BLOCK) k_merge_acc_clear(FrtMergeArgs a)
+{
+    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < a.n_slots; i += gridDim.x * BLOCK) {
+        a.acc_head[i] = ~0u;
+        double* acc = a.acc + (size_t)i * ACC_N;
+        for (int c = 0; c < ACC_N; c++) acc[c] = 0.0;
+    }
+}
+
+// Counts and ledger terms of the merged queue (which the host then makes
+// the solve's carried queue).
 template <typename Real>
-__global__ void __launch_bounds__(BLOCK) k_merge_finish(FrtSolveDesc* dp, FrtMergeArgs a)
+__global__ void k_merge_finish(FrtSolveDesc* dp, FrtMergeArgs a)
 {
     FrtSolveDesc& D = *dp;
-    FrtRec<Real>* F = (FrtRec<Real>*)D.F[1 - D.cur].rec;
-    const FrtRec<Real>* src = (const FrtRec<Real>*)a.dst;
     const uint32_t m = a.counts[0];
-    for (uint32_t i = blockIdx.x * BLOCK + threadIdx.x; i < m; i += gridDim.x * BLOCK) F[i] = src[i];
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         D.fcount[1 - D.cur] = m;
         D.vcount[1 - D.cur] = a.counts[2] + a.counts[1];
@@ -307,8 +430,11 @@ __global__ void k_merge_zero(FrtMergeArgs a)
     }
 }
 
+// Counting phase: keys, the exemption, the group sort, flags, the three
+// scans and their totals (a.counts, read by the host to size the next table
+// of virtual origins before the writing phase).
 template <typename Real, int NB>
-hipError_t merge_nb(FrtSolveDesc* d, FrtMergeArgs a, hipStream_t st)
+hipError_t count_nb(FrtSolveDesc* d, FrtMergeArgs a, hipStream_t st)
 {
     hipError_t e;
     const int g = blocks_for(a.n);
@@ -347,26 +473,39 @@ hipError_t merge_nb(FrtSolveDesc* d, FrtMergeArgs a, hipStream_t st)
             return e;
     }
     hipLaunchKernelGGL(k_merge_totals, dim3(1), dim3(64), 0, st, a);
+    return hipGetLastError();
+}
+
+// Writing phase: the kept table entries, the merged packets and the queue.
+template <typename Real, int NB>
+hipError_t write_nb(FrtSolveDesc* d, FrtMergeArgs a, hipStream_t st)
+{
+    const int g = blocks_for(a.n);
     if (a.n_old) hipLaunchKernelGGL(k_merge_keep_origins, dim3(blocks_for(a.n_old)), dim3(BLOCK), 0, st, d, a);
+    hipLaunchKernelGGL(k_merge_acc_clear, dim3(blocks_for(a.n_slots)), dim3(BLOCK), 0, st, a);
     hipLaunchKernelGGL((k_merge_emit<Real, NB>), dim3(g), dim3(BLOCK), 0, st, d, a);
-    hipLaunchKernelGGL((k_merge_finish<Real>), dim3(g), dim3(BLOCK), 0, st, d, a);
+    hipLaunchKernelGGL((k_merge_finalize<Real, NB>), dim3(blocks_for(a.n_slots)), dim3(BLOCK), 0, st, d, a);
+    hipLaunchKernelGGL((k_merge_finish<Real>), dim3(1), dim3(64), 0, st, d, a);
     return hipGetLastError();
 }
 
 template <typename Real>
-hipError_t merge_t(FrtSolveDesc* d, const FrtMergeArgs& a, int nb, hipStream_t st)
+hipError_t merge_t(FrtSolveDesc* d, const FrtMergeArgs& a, int nb, int phase, hipStream_t st)
 {
+#define FRT_MERGE_NB(K) \
+    case K: return phase == 0 ? count_nb<Real, K>(d, a, st) : write_nb<Real, K>(d, a, st);
     switch (nb) {
-        case 1: return merge_nb<Real, 1>(d, a, st);
-        case 2: return merge_nb<Real, 2>(d, a, st);
-        case 3: return merge_nb<Real, 3>(d, a, st);
-        case 4: return merge_nb<Real, 4>(d, a, st);
-        case 5: return merge_nb<Real, 5>(d, a, st);
-        case 6: return merge_nb<Real, 6>(d, a, st);
-        case 7: return merge_nb<Real, 7>(d, a, st);
-        case 8: return merge_nb<Real, 8>(d, a, st);
+        FRT_MERGE_NB(1)
+        FRT_MERGE_NB(2)
+        FRT_MERGE_NB(3)
+        FRT_MERGE_NB(4)
+        FRT_MERGE_NB(5)
+        FRT_MERGE_NB(6)
+        FRT_MERGE_NB(7)
+        FRT_MERGE_NB(8)
         default: return hipErrorInvalidValue;
     }
+#undef FRT_MERGE_NB
 }
 
 template <typename Real>
@@ -392,10 +531,10 @@ size_t temp_bytes_t(uint32_t n, uint32_t n_old)
 
 namespace frt {
 
-hipError_t launch_merge(FrtSolveDesc* d, const FrtMergeArgs& a, int fp64, int n_bins, hipStream_t st)
+hipError_t launch_merge(FrtSolveDesc* d, const FrtMergeArgs& a, int fp64, int n_bins, int phase, hipStream_t st)
 {
     if (a.n == 0) return hipSuccess;
-    return fp64 ? merge_t<double>(d, a, n_bins, st) : merge_t<float>(d, a, n_bins, st);
+    return fp64 ? merge_t<double>(d, a, n_bins, phase, st) : merge_t<float>(d, a, n_bins, phase, st);
 }
 
 size_t merge_temp_bytes(uint32_t n, uint32_t n_old, int fp64)

@@ -66,7 +66,7 @@ class Ledger(C.Structure):
 class Timing(C.Structure):
     _fields_ = [("emit_ms", C.c_double), ("march_ms", C.c_double), ("chem_ms", C.c_double),
                 ("other_ms", C.c_double), ("march_launches", C.c_uint64), ("chem_launches", C.c_uint64),
-                ("steps", C.c_uint64)]
+                ("steps", C.c_uint64), ("merge_ms", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
