@@ -66,10 +66,17 @@ __device__ inline void nest_pixel_centre(int level, uint32_t pix, Real v[3])
     int k = jp_face * nr + ix - iy;
     if (k < 0) k += 8 * nr;
     else if (k >= 8 * nr) k -= 8 * nr;
-    // phi = (pi/4) k / nr, evaluated as sincospi(k / (4 nr))
+    // phi = (pi/4) k / nr: sincospi(k / (4 nr)) in FP64; in FP32 the
+    // hardware sine and cosine, which take their argument in turns
+    // (phi / 2pi = k / (8 nr)), accurate to the precision of the FP32 march
     Real s, c;
-    if constexpr (sizeof(Real) == 8) sincospi(Real(k) / Real(4 * nr), &s, &c);
-    else sincospif(Real(k) / Real(4 * nr), &s, &c);
+    if constexpr (sizeof(Real) == 8) {
+        sincospi(Real(k) / Real(4 * nr), &s, &c);
+    } else {
+        const float turns = (float)k / (float)(8 * nr);
+        s = __builtin_amdgcn_sinf(turns);
+        c = __builtin_amdgcn_cosf(turns);
+    }
     v[0] = st * c;
     v[1] = st * s;
     v[2] = z;

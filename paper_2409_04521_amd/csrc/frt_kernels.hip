@@ -315,20 +315,40 @@ __device__ __forceinline__ Real fast_rcp(Real x)
 // times |d|_1.  Only used to order the packets of a work item so that the
 // lanes of a wave march similar lengths; stored in the key's top bits.
 template <typename Real>
-__device__ __forceinline__ uint32_t crossing_bin(const FrtSolveDesc& D, const int c[3], const Real s[3], const Real d[3],
-                                                 Real r, Real rstop, int level)
+__device__ __forceinline__ Real split_radius(const FrtSolveDesc& D, int level)
+{
+    // r_split0 2^level (a power-of-two scaling, exact in either precision)
+    return (level < D.max_level) ? (Real)ldexp((Real)D.r_split0, level) : rinf<Real>();
+}
+
+// Expected crossings of a packet in the brick of cell c before it leaves
+// the brick or reaches its split radius, distance cap or budget end: the
+// distance to the nearest of those times |dx| + |dy| + |dz|, in the bins of
+// an output key.  inv[a] is 1 / d[a] (0 where d[a] is 0).
+template <typename Real>
+__device__ __forceinline__ uint32_t crossing_bin_inv(const FrtSolveDesc& D, const int c[3], const Real s[3], const Real d[3],
+                                                     const Real inv[3], Real r, Real rstop, int level)
 {
     const int dims[3] = {D.nx, D.ny, D.nz};
-    const Real r_split = (level < D.max_level) ? (Real)(D.r_split0 * (double)(1u << level)) : rinf<Real>();
-    Real lim = fmin(fmin(r_split, (Real)D.r_cap), rstop);
+    Real lim = fmin(fmin(split_radius<Real>(D, level), (Real)D.r_cap), rstop);
 #pragma unroll
     for (int a = 0; a < 3; a++) {
         const int lo = (c[a] >> D.bsh[a]) << D.bsh[a], hi = min(lo + (1 << D.bsh[a]), dims[a]);
-        if (d[a] > Real(0)) lim = fmin(lim, ((Real)hi - s[a]) * fast_rcp(d[a]));
-        else if (d[a] < Real(0)) lim = fmin(lim, ((Real)lo - s[a]) * fast_rcp(d[a]));
+        if (d[a] > Real(0)) lim = fmin(lim, ((Real)hi - s[a]) * inv[a]);
+        else if (d[a] < Real(0)) lim = fmin(lim, ((Real)lo - s[a]) * inv[a]);
     }
     const Real len = fmax(lim - r, Real(0)) * (fabs(d[0]) + fabs(d[1]) + fabs(d[2]));
     return (uint32_t)fmin(len, Real(FRT_KEY_BINS - 3)) + 1u;
+}
+
+template <typename Real>
+__device__ __forceinline__ uint32_t crossing_bin(const FrtSolveDesc& D, const int c[3], const Real s[3], const Real d[3],
+                                                 Real r, Real rstop, int level)
+{
+    Real inv[3];
+#pragma unroll
+    for (int a = 0; a < 3; a++) inv[a] = d[a] != Real(0) ? fast_rcp(d[a]) : Real(0);
+    return crossing_bin_inv<Real>(D, c, s, d, inv, r, rstop, level);
 }
 
 __device__ __forceinline__ uint32_t key_with_bin(uint32_t key, uint32_t bin) { return key | (bin << FRT_KEY_BITS); }
@@ -722,12 +742,14 @@ __device__ __forceinline__ Real absorbed(Real t, Real eb)
 // The same in terms of u = -log2(e) t (so that e^-t = 2^u): with
 // v = -u ln 2 = t, the series v (1 - v/2 + v^2/6 - v^3/24) written in u,
 // used while t < 0.03 (u > -0.03 / ln 2).
-__device__ __forceinline__ float absorbed_u(float u, float eb)
+// 1 - 2^u for -0.0144 < u <= 0 (optical depths below 0.01) from its Taylor
+// series: with w = -u ln 2, w - w^2/2 + w^3/6, relative error below 5e-8
+// there, where 1 - 2^u from a rounded 2^u loses digits.
+constexpr float ABSORBED_SERIES_U = 0.014426950f;
+__device__ __forceinline__ float absorbed_series(float u)
 {
-    constexpr float c1 = -0.69314718f, c2 = -0.24022651f, c3 = -0.05550411f, c4 = -0.00961813f;
-    const float ser = u * (c1 + u * (c2 + u * (c3 + u * c4)));
-    const float dif = 1.f - eb;
-    return u > -0.043280851f ? ser : dif;
+    constexpr float c1 = -0.69314718f, c2 = -0.24022651f, c3 = -0.05550411f;
+    return u * (c1 + u * (c2 + u * c3));
 }
 
 
@@ -866,6 +888,13 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             sl2[b] = uni((Real)D.sig_l2[b]);                // -log2(e) s_nu
         }
         const Real KS = uni(F32 ? (Real)D.KS : (Real)D.KSd);
+        // the HI optical depth per segment (at sigma_0) below which every bin's
+        // absorbed fraction comes from the series (the softest bin has the
+        // largest |u|)
+        Real smax = 0;
+#pragma unroll
+        for (int b = 0; b < NB; b++) smax = fmax(smax, -(Real)sl2[b]);
+        const Real ta_ser = uni((Real)ABSORBED_SERIES_U / smax);
         const float dsc = uni(D.dep_scale);   // fixed-point units per photon
         const uint32_t lb = w.key - uni(D.key_base);
         const int bx = (int)(lb % (uint32_t)D.bpx), by = (int)((lb / (uint32_t)D.bpx) % (uint32_t)D.bpy),
@@ -966,7 +995,6 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         const Real floor_f = uni((Real)D.floor);
         const double Rr = uni(D.R_ref);
         const int max_level = uni(D.max_level), base_level = uni(D.base_level);
-        const double r_split0 = uni(D.r_split0);
         // Generalized Opacity Mode (only with the sub-grid layout): .x of a
         // staged cell is the ionized part's opacity per cell width at sigma_0,
         // .y the ionized volume fraction
@@ -995,6 +1023,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                 const bool active = p < n_cur;
                 Pkt<Real> h;
                 Real T[4], NE[NB], N0[NB], s[3];   // NE: photons of each bin (units of the cast weight)
+                Real inv_d[3] = {Real(0), Real(0), Real(0)};   // 1 / direction, per axis
                 int level = 0, end = -1;     // -1 inactive, 0 split, 1 escaped, 2 dropped, 3 in flight, 4 next brick
                 int c[3] = {0, 0, 0};
                 double v_abs = 0.0, v_sub = 0.0, v_end = 0.0;
@@ -1018,190 +1047,220 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                         n_start += (double)NE[b];
                     }
                     unpack_cell(h.cell, c);
-                    const Real r_split = (level < max_level) ? (Real)(r_split0 * (double)(1u << level)) : rinf<Real>();
+                    const Real r_split = split_radius<Real>(D, level);
                     // the nearest of split radius, distance cap and budget end
                     const Real r_lim = fmin(fmin(r_split, r_cap), h.rstop);
                     // distance to the next face along each axis, and the distance
                     // between faces (Amanatides-Woo): the next face along an axis
                     // is reached after one more cell's distance along it
                     Real dtf[3], rf[3];
-                    int stp[3];
 #pragma unroll
                     for (int a = 0; a < 3; a++) {
-                        const Real inv = (h.d[a] != Real(0)) ? fast_rcp(h.d[a]) : Real(0);
-                        stp[a] = h.d[a] > Real(0) ? 1 : -1;
-                        dtf[a] = fabs(inv);
-                        rf[a] = (h.d[a] != Real(0)) ? ((Real)(c[a] + (h.d[a] > Real(0) ? 1 : 0)) - s[a]) * inv : rinf<Real>();
+                        inv_d[a] = (h.d[a] != Real(0)) ? fast_rcp(h.d[a]) : Real(0);
+                        dtf[a] = fabs(inv_d[a]);
+                        rf[a] = (h.d[a] != Real(0)) ? ((Real)(c[a] + (h.d[a] > Real(0) ? 1 : 0)) - s[a]) * inv_d[a] : rinf<Real>();
                     }
-                    // cell within the brick, and the change of its LDS index per step
-                    int lc[3] = {c[0] - ox, c[1] - oy, c[2] - oz};
-                    const int inc[3] = {stp[0], stp[1] * BX, stp[2] * BX * BY};
-                    int li = lc[0] + BX * (lc[1] + BY * lc[2]);
-                    Real sub_acc = 0;
-                    const bool in_brick = lc[0] >= 0 && lc[0] < BX && lc[1] >= 0 && lc[1] < BY && lc[2] >= 0 && lc[2] < BZ;
+                    // the cell's index in the staged brick, x fastest; a step along
+                    // an axis changes only that axis's bit field of the index
+                    // unless it leaves the brick (a carry or borrow out of the
+                    // field), and the z guard planes keep the next cell's
+                    // prefetch inside the array either way
+                    const int inc[3] = {h.d[0] > Real(0) ? 1 : -1, h.d[1] > Real(0) ? BX : -BX,
+                                        h.d[2] > Real(0) ? BX * BY : -(BX * BY)};
+                    constexpr int NOT_X = ~(BX - 1), NOT_Y = ~((BY - 1) << LX), NOT_Z = ~((BZ - 1) << (LX + LY));
+                    const int lc0 = c[0] - ox, lc1 = c[1] - oy, lc2 = c[2] - oz;
+                    const bool in_brick = lc0 >= 0 && lc0 < BX && lc1 >= 0 && lc1 < BY && lc2 >= 0 && lc2 < BZ;
+                    int li = in_brick ? lc0 + BX * (lc1 + BY * lc2) : 0;
                     if (!in_brick) end = 4;            // hand it to the brick that holds its cell
+                    const bool floor_on = floor_f > Real(0);
                     const Real floor_abs = floor_f * sum0;
-                    // photons left (in units of the cast weight), kept by
-                    // subtracting each segment's absorption, for the flux floor
-                    Real sumE = 0;
+                    // photons left (in units of the cast weight), for the flux floor
+                    Real S = 0;
 #pragma unroll
-                    for (int b = 0; b < NB; b++) sumE += NE[b];
-                    // the opacity of the current cell; each step reads the next
-                    // cell's one iteration ahead (for a packet about to leave the
-                    // brick that is a guard cell, whose value is not used)
-                    OpT o_cur = s_op[PADC + ((uint32_t)li < (uint32_t)BC ? li : 0)];
-                    while (end < 0) {
-                        int axis = 0;
-                        Real r_face = rf[0];
-                        if (rf[1] < r_face) { r_face = rf[1]; axis = 1; }
-                        if (rf[2] < r_face) { r_face = rf[2]; axis = 2; }
-                        const int li_n = li + (axis == 0 ? inc[0] : (axis == 1 ? inc[1] : inc[2]));
-                        const OpT o_next = s_op[PADC + li_n];
-                        Real r_end;
-                        if constexpr (F32) {
-                            // max(min(r_face, r_lim), r) on the bit patterns: r and
-                            // r_lim are >= +0, so integer order is float order there,
-                            // and a negative r_face (from rounding) loses to r
-                            r_end = __int_as_float(max(min(__float_as_int(r_face), __float_as_int(r_lim)), __float_as_int(h.r)));
-                        } else {
-                            r_end = fmax(fmin(r_face, r_lim), h.r);
-                        }
-                        const Real ds = r_end - h.r;
-                        // the deposit's LDS atomic is issued on every path (adding
-                        // 0 for an empty segment), so that waiting for the next
-                        // cell's prefetched opacity never waits for it
-                        Real dep = 0;
-                        bool front = false;   // stopped at the cell's I-front
-                        if (ds > Real(0)) {
-                            R2 o;
-                            if constexpr (SUB) {
-                                o = o_cur;
-                            } else {
-                                o.x = o_cur;
-                                o.y = Real(0);
-                            }
-                            // the path through absorbing gas: the ionized part
-                            // x_ion ds in the Generalized Opacity Mode (whose
-                            // rate keeps the whole ds: Eq. gamma_avg_subgrid
-                            // with ds -> x_ion ds and V -> x_ion V)
-                            const Real ta = o.x * (gmode ? o.y * ds : ds);
-                            if (gmode) front = o.y < Real(1);
-                            Real absd = 0;
-                            if constexpr (SUB) {
-                                const Real tk = gmode ? Real(0) : o.y * ds;
+                    for (int b = 0; b < NB; b++) S += NE[b];
+                    // this visit's optical depth (HI part at sigma_0, sub-grid
+                    // part), added to the packet's compensated sums at its end
+                    Real tsum = 0, ksum = 0;
+                    Real sub_acc = 0;
+                    if (end < 0) {
+                        // the opacity of the current cell; each step reads the next
+                        // cell's one iteration ahead
+                        OpT o_cur = s_op[PADC + li];
+                        bool front = false;   // stopped at the cell's I-front (Generalized Opacity Mode)
+                        // the loop keeps no per-step flags: at its exit, li, rf, S and
+                        // h.r are those of its last step, which the exit recomputes
+                        for (;;) {
+                            const Real r_face = fmin(fmin(rf[0], rf[1]), rf[2]);
+                            // the axis of the nearest face (ties to the lowest axis)
+                            const bool a0 = rf[0] == r_face;
+                            const bool a1 = !a0 && rf[1] == r_face;
+                            const int li_n = li + (a0 ? inc[0] : (a1 ? inc[1] : inc[2]));
+                            const bool out = ((li ^ li_n) & (a0 ? NOT_X : (a1 ? NOT_Y : NOT_Z))) != 0;
+                            const OpT o_next = s_op[PADC + li_n];
+                            Real r_end;
+                            if constexpr (F32) r_end = __builtin_amdgcn_fmed3f(r_face, r_lim, h.r);
+                            else r_end = fmax(fmin(r_face, r_lim), h.r);
+                            const Real ds = r_end - h.r;
+                            // the deposit's LDS atomic is issued on every path (adding
+                            // 0 for an empty segment), so that waiting for the next
+                            // cell's prefetched opacity never waits for it
+                            Real dep = 0;
+                            if constexpr (F32 && !SUB) {
+                                // u = -log2(e) s_nu tau_0: each bin's transmission is
+                                // 2^u.  The cell's absorbed photons: while even the
+                                // softest bin's u is above -0.0144, the sum over bins
+                                // of N_nu (1 - 2^u) from its series (valid there for
+                                // every bin); beyond it the drop of the photons' sum,
+                                // which is then at least 1% of the softest bin's
+                                // photons (an empty segment changes nothing)
+                                const Real ta = o_cur * ds;
+                                Real S_new = 0, A_ser = 0;
 #pragma unroll
                                 for (int b = 0; b < NB; b++) {
-                                    const Real tb = srel[b] * ta + tk;
-                                    const Real nin = NE[b];
-                                    const Real eb = exp_neg(tb);
-                                    const Real af = absorbed<Real>(tb, eb);
-                                    const Real rt = fast_rcp(tb);
-                                    const Real phi = (tb > Real(0)) ? af * rt : Real(1);
-                                    dep += Kb[b] * nin * ds * phi;
-                                    absd += nin * af;
-                                    if (tk > Real(0)) sub_acc += nin * af * tk * rt;
-                                    NE[b] *= eb;
+                                    const Real u = sl2[b] * ta;
+                                    A_ser += NE[b] * absorbed_series(u);
+                                    NE[b] *= __builtin_amdgcn_exp2f(u);
+                                    S_new += NE[b];
                                 }
-                                if (tk > Real(0)) {
-                                    const Real y = tk - T[3];
-                                    const Real t = T[1] + y;
-                                    T[3] = (t - T[1]) - y;
-                                    T[1] = t;
+                                dep = ta < ta_ser ? A_ser : S - S_new;
+                                S = S_new;
+                                tsum += ta;
+                                v_cross += ds > Real(0) ? 1u : 0u;
+                            } else if (ds > Real(0)) {
+                                R2 o;
+                                if constexpr (SUB) {
+                                    o = o_cur;
+                                } else {
+                                    o.x = o_cur;
+                                    o.y = Real(0);
                                 }
-                            } else {
+                                // the path through absorbing gas: the ionized part
+                                // x_ion ds in the Generalized Opacity Mode (whose
+                                // rate keeps the whole ds: Eq. gamma_avg_subgrid
+                                // with ds -> x_ion ds and V -> x_ion V)
+                                const Real ta = o.x * (gmode ? o.y * ds : ds);
+                                if (gmode) front = o.y < Real(1);
+                                Real absd = 0;
+                                if constexpr (SUB) {
+                                    const Real tk = gmode ? Real(0) : o.y * ds;
 #pragma unroll
-                                for (int b = 0; b < NB; b++) {
-                                    if constexpr (F32) {
-                                        // u = -log2(e) tau: e^-tau = 2^u
-                                        const Real u = sl2[b] * ta;
-                                        const Real eb = __builtin_amdgcn_exp2f(u);
-                                        absd += NE[b] * absorbed_u(u, eb);
+                                    for (int b = 0; b < NB; b++) {
+                                        const Real tb = srel[b] * ta + tk;
+                                        const Real nin = NE[b];
+                                        const Real eb = exp_neg(tb);
+                                        const Real af = absorbed<Real>(tb, eb);
+                                        const Real rt = fast_rcp(tb);
+                                        const Real phi = (tb > Real(0)) ? af * rt : Real(1);
+                                        dep += Kb[b] * nin * ds * phi;
+                                        absd += nin * af;
+                                        if (tk > Real(0)) sub_acc += nin * af * tk * rt;
                                         NE[b] *= eb;
-                                    } else {
+                                    }
+                                    ksum += tk;
+                                } else {
+#pragma unroll
+                                    for (int b = 0; b < NB; b++) {
                                         const Real tb = srel[b] * ta;
                                         const Real eb = exp_neg(tb);
                                         absd += NE[b] * absorbed<Real>(tb, eb);
                                         NE[b] *= eb;
                                     }
+                                    // the cell's absorbed photons; times KS / a_i when
+                                    // the brick's deposits are added
+                                    dep = absd;
                                 }
-                                // the cell's absorbed photons; times KS / a_i when the
-                                // brick's deposits are added
-                                dep = absd;
+                                S -= absd;
+                                tsum += ta;
+                                v_cross++;
                             }
-                            sumE -= absd;
-                            // Kahan-compensated optical depth carried by the packet
-                            {
-                                const Real y = ta - T[2];
-                                const Real t = T[0] + y;
-                                T[2] = (t - T[0]) - y;
-                                T[0] = t;
+                            if constexpr (INTDEP) {
+                                // whole units of the fixed point (dep <= 2^46 units),
+                                // split exactly into the two words of the 64-bit add
+                                const float x = __builtin_rintf(dep * dsc);
+                                const uint32_t hi = (uint32_t)(x * 0x1p-32f);
+                                const uint32_t lo = (uint32_t)__builtin_fmaf(-(float)hi, 0x1p32f, x);
+                                atomicAdd(&s_g[li], ((unsigned long long)hi << 32) | lo);
+                            } else {
+                                atomicAdd(&s_g[li], dep);
                             }
-                            v_cross++;
+                            h.r = r_end;
+                            Real o_n;   // HI opacity of the next cell (< 0 outside the grid)
+                            if constexpr (SUB) o_n = o_next.x;
+                            else o_n = o_next;
+                            // any end before or after the step: the exit below sorts it
+                            // out (one test of all conditions, so that the next cell's
+                            // opacity is read ahead of it rather than inside it)
+                            const bool stop = front | (floor_on & (S < floor_abs)) | (h.r >= r_lim) | out | (o_n < Real(0));
+                            if (stop) break;
+                            li = li_n;
+                            const Real rfa = r_face + (a0 ? dtf[0] : (a1 ? dtf[1] : dtf[2]));
+                            rf[0] = a0 ? rfa : rf[0];
+                            rf[1] = a1 ? rfa : rf[1];
+                            rf[2] = (a0 || a1) ? rf[2] : rfa;
+                            o_cur = o_next;
                         }
-                        if constexpr (INTDEP) {
-                            // whole units of the fixed point (dep <= 2^46 units),
-                            // split exactly into the two words of the 64-bit add
-                            const float x = __builtin_rintf(dep * dsc);
-                            const uint32_t hi = (uint32_t)(x * 0x1p-32f);
-                            const uint32_t lo = (uint32_t)__builtin_fmaf(-(float)hi, 0x1p32f, x);
-                            atomicAdd(&s_g[li], ((unsigned long long)hi << 32) | lo);
-                        } else {
-                            atomicAdd(&s_g[li], dep);
-                        }
-                        h.r = r_end;
+                        // the last step's face, axis, next cell and floor test,
+                        // recomputed here (the empty asm keeps the compiler from
+                        // carrying the loop's per-step flags out of it instead)
+                        Real rx = rf[0], ry = rf[1], rz = rf[2];
+                        asm volatile("" : "+v"(rx), "+v"(ry), "+v"(rz));
+                        const Real r_face = fmin(fmin(rx, ry), rz);
+                        const bool a0 = rx == r_face;
+                        const bool a1 = !a0 && ry == r_face;
+                        const int li_n = li + (a0 ? inc[0] : (a1 ? inc[1] : inc[2]));
+                        const bool out = ((li ^ li_n) & (a0 ? NOT_X : (a1 ? NOT_Y : NOT_Z))) != 0;
+                        const OpT o_next = s_op[PADC + li_n];
+                        const bool floored = floor_on && S < floor_abs;
                         // end states before the step, in order: distance cap, flux
                         // floor, split, then the budget (a face reached with it is
                         // crossed first)
-                        const bool floored = floor_f > Real(0) && sumE < floor_abs;
                         int e_pre = (h.r >= r_lim)
                                         ? ((h.r >= r_cap || floored) ? 2 : (h.r >= r_split ? 0 : (h.r < r_face ? 3 : -1)))
                                         : (floored ? 2 : -1);
                         if (front) e_pre = 5;   // (only in the Generalized Opacity Mode)
-                        // step to the next cell along `axis` (selects keep every
-                        // per-axis value in registers); undone below for an end
-                        // before the step, so that the loop has a single exit
-                        const int st = axis == 0 ? stp[0] : (axis == 1 ? stp[1] : stp[2]);
-                        if (axis == 0) lc[0] += st;
-                        else if (axis == 1) lc[1] += st;
-                        else lc[2] += st;
-                        li = li_n;
-                        const Real rfa = r_face + (axis == 0 ? dtf[0] : (axis == 1 ? dtf[1] : dtf[2]));
-                        if (axis == 0) rf[0] = rfa;
-                        else if (axis == 1) rf[1] = rfa;
-                        else rf[2] = rfa;
-                        const int la = axis == 0 ? lc[0] : (axis == 1 ? lc[1] : lc[2]);
-                        const int ba = axis == 0 ? BX : (axis == 1 ? BY : BZ);
-                        // after the step: leaving the brick (and the box, when the
-                        // brick's face is the box's), a cell outside the grid
-                        // within the brick (the box left), the budget spent
-                        const bool spent = h.r >= h.rstop;
-                        const bool out_brick = la < 0 || la >= ba;
-                        Real o_n;   // HI opacity of the cell entered
-                        if constexpr (SUB) o_n = o_next.x;
-                        else o_n = o_next;
-                        const int e_post = out_brick ? (spent ? 3 : 4) : (o_n < Real(0) ? 1 : (spent ? 3 : -1));
-                        if ((e_pre & e_post) >= 0) {      // either is an end state
-                            if (e_pre >= 0) {
-                                end = e_pre;
-                                if (axis == 0) lc[0] -= st;
-                                else if (axis == 1) lc[1] -= st;
-                                else lc[2] -= st;
+                        int lc[3] = {li & (BX - 1), (li >> LX) & (BY - 1), li >> (LX + LY)};
+                        if (e_pre >= 0) {
+                            end = e_pre;
+                        } else {
+                            // the face is crossed: leaving the brick (and the box,
+                            // when the brick's face is the box's), a cell outside
+                            // the grid within the brick (the box left), or the
+                            // budget spent on the face
+                            const int axis = a0 ? 0 : (a1 ? 1 : 2);
+                            const int sgn = (axis == 0 ? h.d[0] : (axis == 1 ? h.d[1] : h.d[2])) > Real(0) ? 1 : -1;
+                            lc[0] += axis == 0 ? sgn : 0;
+                            lc[1] += axis == 1 ? sgn : 0;
+                            lc[2] += axis == 2 ? sgn : 0;
+                            const bool spent = h.r >= h.rstop;
+                            Real o_n;
+                            if constexpr (SUB) o_n = o_next.x;
+                            else o_n = o_next;
+                            if (out) {
+                                const int ca = axis == 0 ? ox + lc[0] : (axis == 1 ? oy + lc[1] : oz + lc[2]);
+                                const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
+                                end = (ca < 0 || ca >= dima) ? 1 : (spent ? 3 : 4);
                             } else {
-                                end = e_post;
-                                if (out_brick) {
-                                    const int ca = (axis == 0 ? ox : (axis == 1 ? oy : oz)) + la;
-                                    const int dima = axis == 0 ? nx : (axis == 1 ? ny : nz);
-                                    if (ca < 0 || ca >= dima) end = 1;
-                                }
+                                end = o_n < Real(0) ? 1 : 3;
                             }
-                            break;
                         }
-                        o_cur = o_next;
-                    }
-                    if (in_brick) {
                         c[0] = ox + lc[0];
                         c[1] = oy + lc[1];
                         c[2] = oz + lc[2];
+                        // the visit's optical depth into the packet's compensated sums
+                        {
+                            const Real y = tsum - T[2];
+                            const Real t = T[0] + y;
+                            T[2] = (t - T[0]) - y;
+                            T[0] = t;
+                        }
+                        if constexpr (SUB) {
+                            if (ksum > Real(0)) {
+                                const Real y = ksum - T[3];
+                                const Real t = T[1] + y;
+                                T[3] = (t - T[1]) - y;
+                                T[1] = t;
+                            }
+                        }
                     }
                     // photons at the end of the visit from the carried optical
                     // depth, exactly as the next visit will recompute them
@@ -1262,7 +1321,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                 // keys of the packets entering another brick, computed while the
                 // reservation flies
                 uint32_t key = 0;
-                if (end == 4) key = key_with_bin(brick_key(D, c), crossing_bin<Real>(D, c, s, h.d, h.r, h.rstop, level));
+                if (end == 4) key = key_with_bin(brick_key(D, c), crossing_bin_inv<Real>(D, c, s, h.d, inv_d, h.r, h.rstop, level));
                 const uint32_t o_base = n_out ? reserve_end(o_raw, 0u) : 0u;
                 // ---- packets entering another brick go to the next pass
                 {
