@@ -24,6 +24,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, published
+# one VALU operation per lane per cycle: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# (the published 157.3 TFLOP/s counts an FMA as two and packed FP32 as two
+# lanes, which this build does not emit)
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+VALU_SIMDS, CLOCK_HZ = 256 * 4, 2.4e9
+ALG_OPS_PER_CROSSING = 120          # FP32 operations of one crossing at 4 bins
+ALG_BYTES_PER_CROSSING = 12         # opacity gather 8 B + one FP32 deposit 4 B
+def alg_bytes_per_visit(nb):        # the packet record read and written
+    return 2 * (36 + 8 * nb)
 METRIC = "cell crossings/s at 256^3 + p50/p99 solve latency, batched vs plain per-solve"
 
 
@@ -36,6 +45,57 @@ def kernel_source_hash() -> str:
     for f in ("frt_kernels.hip", "frt_internal.h"):
         h.update(open(os.path.join(ROOT, "paper_2409_04521_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
+
+
+def measured_valu(workload: str):
+    """VALU figures of the march from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"march_{workload}_valu.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return {k: d[k] for k in ("lane_instr_per_crossing", "wave_instr_per_crossing", "lane_utilisation",
+                              "valu_issue_frac", "trans_per_crossing")}
+
+
+def valu_summary(db_dir: str, crossings_per_step: float, out_path: str):
+    """VALU instructions of the march per crossing and the share of the
+    SIMDs' issue cycles they take (4 cycles per wave64 instruction, 16 per
+    transcendental one, over 1024 SIMDs at 2.4 GHz for the kernels' own
+    duration), over the march launches of the last step of a rocprofv3 run
+    with SQ_INSTS_VALU, SQ_THREAD_CYCLES_VALU and SQ_INSTS_VALU_TRANS_F32."""
+    import glob
+    import sqlite3
+    dbs = glob.glob(os.path.join(db_dir, "**", "*.db"), recursive=True)
+    con = sqlite3.connect(dbs[0])
+    q = ("select dispatch_id, kernel_name, counter_name, sum(value), min(start), max(end) from counters_collection "
+         "group by dispatch_id, counter_name order by dispatch_id")
+    per = {}
+    for did, name, cname, val, t0, t1 in con.execute(q):
+        d = per.setdefault(did, {"name": name, "t0": t0, "t1": t1, "c": {}})
+        d["c"][cname] = val
+    ds = [per[k] for k in sorted(per)]
+    last_seed = max(i for i, d in enumerate(ds) if "k_seed<" in d["name"])
+    brick = [d for d in ds[last_seed:] if "k_brick" in d["name"]]
+    tot = {c: sum(d["c"].get(c, 0.0) for d in brick) for c in ("SQ_INSTS_VALU", "SQ_THREAD_CYCLES_VALU",
+                                                                  "SQ_INSTS_VALU_TRANS_F32")}
+    secs = sum((d["t1"] - d["t0"]) * 1e-9 for d in brick)
+    cycles = (tot["SQ_INSTS_VALU"] - tot["SQ_INSTS_VALU_TRANS_F32"]) * 4 + tot["SQ_INSTS_VALU_TRANS_F32"] * 16
+    out = {"kernel": "k_brick (march)", "kernel_source_hash": kernel_source_hash(), "launches": len(brick),
+           "crossings_per_step": crossings_per_step, "kernel_seconds": secs,
+           "sq_insts_valu": tot["SQ_INSTS_VALU"], "sq_thread_cycles_valu": tot["SQ_THREAD_CYCLES_VALU"],
+           "sq_insts_valu_trans_f32": tot["SQ_INSTS_VALU_TRANS_F32"],
+           "lane_instr_per_crossing": tot["SQ_THREAD_CYCLES_VALU"] / crossings_per_step,
+           "wave_instr_per_crossing": tot["SQ_INSTS_VALU"] * 64 / crossings_per_step,
+           "lane_utilisation": tot["SQ_THREAD_CYCLES_VALU"] / (64 * tot["SQ_INSTS_VALU"]),
+           "trans_per_crossing": tot["SQ_INSTS_VALU_TRANS_F32"] * 64 / crossings_per_step,
+           "valu_issue_frac": cycles / (VALU_SIMDS * CLOCK_HZ * secs)}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
 
 
 def measured_traffic(workload: str):
@@ -446,10 +506,15 @@ def main():
     ap.add_argument("--copy-calibration-mib", type=int, default=1024,
                     help="size of a plain device copy run before timing; its hardware byte counters "
                          "calibrate the march kernel's (0 = skip)")
+    ap.add_argument("--pmc-valu", nargs=2, metavar=("DB_DIR", "CROSSINGS_PER_STEP"),
+                    help="write profiles/march_c3b_valu.json from a rocprofv3 --pmc run of the VALU counters")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/march_c3b_traffic.json from two rocprofv3 --pmc runs of this "
                          "benchmark (FETCH_SIZE, WRITE_SIZE) and exit")
     args = ap.parse_args()
+    if args.pmc_valu:
+        valu_summary(args.pmc_valu[0], float(args.pmc_valu[1]), os.path.join(ROOT, "profiles", "march_c3b_valu.json"))
+        return
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_calibration_mib,
                     os.path.join(ROOT, "profiles", "march_c3b_traffic.json"))
@@ -516,21 +581,27 @@ def main():
 
     nb = prob.n_bins
     d_visits = L1["ray_visits"] - L0["ray_visits"]
-    rec = 64                                            # one packet record (FrtRec<float>)
-    # per crossing: opacity gather and one FP32 deposit; per visit: the sorted
-    # entry (8 B) and the record read, the record and its key (4 B) written
-    # once (by the march, as a continuing packet or a split child)
-    march_bytes = 12.0 * cross + (2.0 * rec + 12.0) * d_visits
+    # per crossing: opacity gather and one FP32 deposit; per visit: the packet
+    # record read and written (2 (36 + 8 n_b) B)
+    march_bytes = ALG_BYTES_PER_CROSSING * cross + alg_bytes_per_visit(nb) * d_visits
     closure = abs(L1["emitted"] - L1["absorbed_HI"] - L1["absorbed_sub"] - L1["escaped"] - L1["dropped"]
                   - L1["in_flight"] - L1["lost"]) / L1["emitted"]
-    per_launch = march_bytes / max(tm["march_launches"], 1)
-    avg_launch_s = tm["march_ms"] * 1e-3 / max(tm["march_launches"], 1)
-    achieved = per_launch / avg_launch_s / 1e9
-    traffic = measured_traffic("c3b")
-    roof = {"bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-            "kernel": "k_brick", "avg_launch_ms": round(avg_launch_s * 1e3, 4),
-            "algorithmic_bytes_per_launch": round(per_launch), "launches": tm["march_launches"]}
+    launches = max(tm["march_launches"], 1)
+    per_launch = march_bytes / launches
+    avg_launch_s = tm["march_ms"] * 1e-3 / launches
+    hbm_achieved = per_launch / avg_launch_s / 1e9
+    # the march issues vector ALU work, not memory traffic, at its limit: the
+    # roofline is the ALU one, with the algorithmic operations per crossing
+    ops_per_launch = ALG_OPS_PER_CROSSING * cross / launches
+    achieved = ops_per_launch / avg_launch_s / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(VALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
+            "frac": round(achieved / VALU_PEAK_TOPS, 4), "traffic": measured_traffic("c3b"),
+            "kernel": "k_brick", "avg_launch_ms": round(avg_launch_s * 1e3, 4), "launches": tm["march_launches"],
+            "algorithmic_ops_per_crossing": ALG_OPS_PER_CROSSING, "algorithmic_ops_per_launch": round(ops_per_launch),
+            "hbm": {"achieved": round(hbm_achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_achieved / HBM_PEAK_GBS, 5), "algorithmic_bytes_per_launch": round(per_launch),
+                    "bytes": f"{ALG_BYTES_PER_CROSSING} B per crossing + {alg_bytes_per_visit(nb)} B per visit"},
+            "valu": measured_valu("c3b")}
 
     out = {"metric": METRIC, "value": value, "unit": "crossings/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,
