@@ -100,6 +100,9 @@ typedef struct {
     double absorbed_front;   /* photons stopped by I-fronts (Generalized Opacity Mode) */
     double merge_residual;   /* photons held before minus after the merges (rounding only) */
     long long merges, rays_merged; /* merged packets made, and packets merged into them */
+    double front_excess;     /* photons stopped at a front beyond the neutral atoms its
+                                cell had left (they ionize nothing); absorbed_front
+                                counts only the photons that ionized atoms */
 } orc_ledger;
 
 /* Photon totals are sums of up to ~1e9 terms; they are accumulated with
@@ -343,6 +346,7 @@ typedef struct {
     orc_vec* flight_out;     /* packets that end the step in flight */
     double inv_vdt;          /* 1 / (V_cell dt) */
     const double* xion;      /* Generalized Opacity Mode: start-of-step ionized fraction */
+    const double* kappa;     /* Generalized Opacity Mode: the ionized gas's absorption coefficient at sigma_0 */
     double* front;           /* this chunk's photons stopped at each cell's I-front */
 } march_ctx;
 
@@ -402,7 +406,7 @@ static void march_one_ray(march_ctx* M, orc_ray* ray)
         double ds = r_end - ray->r;
         if (ds > 0.0 && P->opacity_mode == 1) {
             long long i = c[0] + (long long)P->nx * (c[1] + (long long)P->ny * c[2]);
-            const double xi = M->xion[i], kap = M->S->kappa[i];
+            const double xi = M->xion[i], kap = M->kappa[i];
             double g = 0.0;
             for (int k = 0; k < nb; k++) {
                 double tau = kap * (P->sigma[k] / P->sigma[0]) * xi * ds;
@@ -705,7 +709,7 @@ static int merge_carried(const orc_state* S, orc_vec* list, const double* umerge
 orc_state* orc_create(const orc_params* P, const float* nH, const float* kappa, const double* x0)
 {
     if (!P || P->nx < 1 || P->ny < 1 || P->nz < 1 || P->n_bins < 1 || P->n_bins > ORC_MAX_BINS) return NULL;
-    if (P->opacity_mode != 0 && (P->opacity_mode != 1 || P->chem_iterations > 0)) return NULL;
+    if (P->opacity_mode != 0 && P->opacity_mode != 1) return NULL;
     orc_state* S = (orc_state*)calloc(1, sizeof(orc_state));
     if (!S) return NULL;
     S->p = *P;
@@ -767,7 +771,21 @@ int orc_set_sources(orc_state* S, int nsrc, const double* pos, const double* ndo
  * next march sees (Eq. gamma_updated_standard).  Each march starts from the
  * same packets, and only the last one's deposits, ledger and carried packets
  * are kept; x(dt) (Eq. xi_of_t) then uses the last Gamma and n_e of the last
- * estimate. */
+ * estimate.
+ *
+ * In the Generalized Opacity Mode chem_iterations = K >= 1 iterates the
+ * ionized gas's opacity with Gamma (§4.2: Eq. lambda_nu_general and Eq.
+ * gamma_avg_subgrid updated in turn), with the equilibrium opacity of §5.1:
+ * kappa_nu = sigma_nu n_HI (Eq. subgrid_lambda), n_HI from photo-ionization
+ * equilibrium, alpha n_H^2 / Gamma (Eqs. equilibrium_condition and
+ * subgrid_nHI), at most n_H (no photons: neutral), added to the input kappa.
+ * Each march sees n_HI from the Gamma of the march before it, the first
+ * march of a step the last Gamma of the previous step (the iteration runs
+ * to a self-consistent solution, so its first guess only sets how many
+ * marches that takes); where no rate is known yet (no photons so far) the
+ * first guess is the optically thin one of Eq. gamma_initial_subgrid
+ * (n_HI = 0).  Each march starts from the same packets, and only the last
+ * one's deposits, front photons, ledger and carried packets are kept. */
 int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int nthreads)
 {
     const orc_params* P = &S->p;
@@ -783,14 +801,19 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
     const int gen = P->opacity_mode == 1;
     double* xion = NULL;
     double* fk = NULL;
+    double* kap = NULL;   /* the ionized gas's kappa each march sees (Generalized Opacity Mode) */
     if (gen) {
         xion = (double*)malloc(sizeof(double) * N);
         fk = (double*)calloc((size_t)K * N, sizeof(double));
-        if (!xion || !fk) return -1;
-        for (long long i = 0; i < N; i++) xion[i] = 1.0 - S->x[i];
+        kap = (double*)malloc(sizeof(double) * N);
+        if (!xion || !fk || !kap) return -1;
+        for (long long i = 0; i < N; i++) {
+            xion[i] = 1.0 - S->x[i];
+            kap[i] = S->kappa[i];
+        }
     }
     double* xavg = NULL;
-    if (P->chem_iterations > 0) {
+    if (P->chem_iterations > 0 && !gen) {
         xavg = (double*)malloc(sizeof(double) * N);
         if (!xavg) return -1;
         memcpy(xavg, S->x, sizeof(double) * N);
@@ -801,9 +824,20 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
 
     for (int it = 0; it < n_iter; it++) {
         for (long long i = 0; i < N; i++) nHI[i] = S->nH[i] * (xavg ? xavg[i] : S->x[i]);
+        if (gen && P->chem_iterations > 0)
+            for (long long i = 0; i < N; i++) {
+                /* equilibrium n_HI of the ionized gas from the last march's
+                 * Gamma (the previous step's at the first march); where no
+                 * rate is known yet the optically thin guess */
+                const double nH = S->nH[i], g = S->gamma[i];
+                double nhi = 0.0;
+                if (g > 0.0) nhi = (P->alpha_B * nH * nH < g * nH) ? P->alpha_B * nH * nH / g : nH;
+                kap[i] = S->kappa[i] + P->sigma[0] * nhi;
+            }
         if (it > 0) {
             /* the march starts again from the step's packets */
             memset(gk, 0, sizeof(double) * (size_t)K * N);
+            if (gen) memset(fk, 0, sizeof(double) * (size_t)K * N);
             memset(Lk, 0, sizeof(chunk_ledger) * K);
             for (int k = 0; k < K; k++) {
                 free(new_flight[k].v);
@@ -817,7 +851,7 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
             march_ctx M;
             M.S = S; M.nHI = nHI; M.gamma = gk + (size_t)k * N; M.L = Lk + k;
             M.stack = &stack; M.inv_vdt = 1.0 / (V * dt);
-            M.xion = xion; M.front = gen ? fk + (size_t)k * N : NULL;
+            M.xion = xion; M.front = gen ? fk + (size_t)k * N : NULL; M.kappa = kap;
             M.flight_out = &new_flight[k];
             /* packets carried from the previous step get a fresh budget */
             const long long nc = S->carried.n;
@@ -860,7 +894,7 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
             for (int k = 0; k < K; k++) g += gk[(size_t)k * N + i];
             S->gamma[i] = g;
         }
-        if (it + 1 < n_iter)
+        if (it + 1 < n_iter && !gen)
             for (long long i = 0; i < N; i++) {
                 double xe;
                 const double ne = S->nH[i] * (1.0 - xavg[i]);
@@ -915,16 +949,32 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
     if (gen) {
         /* moving screen (§4.2, Eq. dxidt): the photons stopped at a cell's
          * front ionize (1 + chi) atoms each; the ionized fraction is at most
-         * 1 and no recombination moves the front back */
+         * 1 and no recombination moves the front back.  Photons beyond the
+         * atoms the cell had left ionize nothing: they move from
+         * absorbed_front to front_excess */
+        csum excess = {0.0, 0.0};
         for (long long i = 0; i < N; i++) {
             double f = 0.0;
             for (int k = 0; k < K; k++) f += fk[(size_t)k * N + i];
             const double atoms = (1.0 + P->he_chi) * S->nH[i] * V;
-            double xi = atoms > 0.0 ? xion[i] + f / atoms : 1.0;   /* no hydrogen: nothing to ionize */
-            if (xi > 1.0) xi = 1.0;
+            double xi;
+            if (atoms > 0.0) {
+                xi = xion[i] + f / atoms;
+                if (xi > 1.0) {
+                    const double left = (1.0 - xion[i]) * atoms;
+                    if (f > left) csum_add(&excess, f - left);
+                    xi = 1.0;
+                }
+            } else {
+                if (f > 0.0) csum_add(&excess, f);   /* no hydrogen: nothing to ionize */
+                xi = 1.0;
+            }
             S->x[i] = 1.0 - xi;
         }
-        free(xion); free(fk);
+        const double ex = csum_get(&excess);
+        S->L.absorbed_front -= ex;
+        S->L.front_excess += ex;
+        free(xion); free(fk); free(kap);
     } else if (xavg) {
         for (long long i = 0; i < N; i++) {
             double xe;
@@ -967,7 +1017,7 @@ int orc_debug_transmit(orc_state* S, const double o[3], const double d[3], const
     march_ctx M;
     M.S = &T; M.nHI = nHI; M.gamma = gamma_out; M.L = &L; M.stack = &stack; M.flight_out = &fl;
     M.inv_vdt = 1.0 / (P->dx * P->dx * P->dx * dt);
-    M.xion = NULL; M.front = NULL;
+    M.xion = NULL; M.front = NULL; M.kappa = NULL;
     orc_ray ray;
     memset(&ray, 0, sizeof(ray));
     for (int a = 0; a < 3; a++) {

@@ -46,7 +46,7 @@ class Ledger(C.Structure):
                 ("crossings", C.c_longlong), ("rays_emitted", C.c_longlong), ("splits", C.c_longlong),
                 ("n_escaped", C.c_longlong), ("n_dropped", C.c_longlong), ("n_in_flight", C.c_longlong),
                 ("absorbed_front", C.c_double), ("merge_residual", C.c_double), ("merges", C.c_longlong),
-                ("rays_merged", C.c_longlong)]
+                ("rays_merged", C.c_longlong), ("front_excess", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -5,9 +5,9 @@ Eq. dxidt), each against something other than its own formulas:
 * a source in uniform neutral gas with transparent ionized gas and no
   recombination: the ionized region is a sphere about the source whose
   radius follows photon counting, R = (3 Ndot t / (4 pi (1+chi) n_H))^(1/3);
-  the ionized atoms never exceed the photons stopped at fronts, and fall
-  short only by what a front cell receives beyond its neutral atoms in a
-  step;
+  the ionized atoms equal the front photons that ionized atoms, and what a
+  front cell receives beyond its neutral atoms in a step is booked apart
+  (and is small);
 * in fully ionized gas, Gamma times the atoms subject to ionization
   V/(sigma_0 lambda) of each cell adds up to the absorbed photons (the
   interpretation §4.2 gives of Eq. gamma_avg_subgrid, one bin);
@@ -25,7 +25,8 @@ DX = W.cmpc_h_to_cm(0.15625)
 
 
 def _closure(L):
-    out = L["absorbed_HI"] + L["absorbed_sub"] + L["absorbed_front"] + L["escaped"] + L["dropped"] + L["in_flight"]
+    out = (L["absorbed_HI"] + L["absorbed_sub"] + L["absorbed_front"] + L["front_excess"] + L["escaped"] + L["dropped"]
+           + L["in_flight"])
     return abs(L["emitted"] - out) / L["emitted"]
 
 
@@ -42,8 +43,9 @@ def test_front_is_a_sphere_that_follows_photon_counting():
     x, _ = o.fields()
     L = o.ledger()
     assert _closure(L) <= 1e-12
-    ionized = float(np.sum((1 - x) * nh * DX ** 3 * (1 + chi)))
-    assert 0.9 * L["absorbed_front"] <= ionized <= L["absorbed_front"] * (1 + 1e-12)
+    ionized = float(np.sum((1 - x) * float(np.float32(nh)) * DX ** 3 * (1 + chi)))   # n_H as loaded (float32)
+    assert ionized == pytest.approx(L["absorbed_front"], rel=1e-12)
+    assert 0.0 < L["front_excess"] <= 0.1 * (L["absorbed_front"] + L["front_excess"])
     R_num = (3 * float(np.sum(1 - x)) / (4 * np.pi)) ** (1 / 3)
     R_an = (3 * Nd * steps * dt / (4 * np.pi * (1 + chi) * nh)) ** (1 / 3) / DX
     assert R_num == pytest.approx(R_an, rel=0.03)
@@ -127,7 +129,65 @@ def test_ledger_closes_with_fronts_and_carried_packets():
     assert _closure(L) <= 1e-12
 
 
-def test_generalized_mode_is_exclusive_with_iterated_chemistry():
-    nH = np.full((4, 4, 4), 1e-4, dtype=np.float32)
-    with pytest.raises(ValueError):
-        O.Oracle((4, 4, 4), DX, [6.3e-18], 2.59e-13, nH, opacity_mode=1, chem_iterations=2)
+KPC = 3.0857e21
+
+
+def test_equilibrium_opacity_stromgren_front():
+    # the paper's Test 1 (§5.1) in the Generalized Opacity Mode with the
+    # equilibrium opacity of Eqs. subgrid_lambda and subgrid_nHI iterated with
+    # Gamma: n_H = 1e-3, Ndot = 5e48, 13.6 eV, alpha_B at 1e4 K, 13.2 kpc box,
+    # source at the centre.  The ionized gas's absorptions then balance its
+    # recombinations, so the ionized volume follows V_S (1 - e^-t/t_rec) and
+    # the front radius the analytic r(t) = r_S (1 - e^-t/t_rec)^(1/3) (Eqs.
+    # r_of_t, rS, trec), which the paper's run meets within well under 1% at
+    # t > 2 t_rec; here within 0.5% at 24^3 with 1 Myr steps
+    n, nh, Nd, alpha = 24, 1e-3, 5e48, 2.59e-13
+    dx = 13.2 * KPC / n
+    nH = np.full((n, n, n), nh, dtype=np.float32)
+    o = O.Oracle((n, n, n), dx, [6.3e-18], alpha, nH, kappa=np.zeros((n, n, n), np.float32),
+                 x_HI0=np.ones((n, n, n)), c_ray=np.inf, opacity_mode=1, chem_iterations=2, n_ray_min=4.0)
+    o.set_sources(np.array([[n / 2, n / 2, n / 2]]) * dx, np.array([[Nd]]))
+    n32 = float(np.float32(nh))
+    t_rec = 1.0 / (alpha * n32)
+    r_S = (3 * Nd / (4 * np.pi * alpha * n32 ** 2)) ** (1 / 3)
+    dt = 1.0 * W.MYR
+    steps = int(round(3.0 * t_rec / dt))
+    worst, prev = 0.0, None
+    for s in range(steps):
+        o.step(dt, W.rotation_uniforms(7, s, 1))
+        t = (s + 1) * dt
+        if t > 2 * t_rec:
+            x, _ = o.fields()
+            r = (3 * float(np.sum(1 - x)) * dx ** 3 / (4 * np.pi)) ** (1 / 3)
+            worst = max(worst, abs(r / (r_S * (1 - np.exp(-t / t_rec)) ** (1 / 3)) - 1))
+        if s == steps - 2:
+            prev = o.ledger()
+    L = o.ledger()
+    print(f"worst |r/r(t) - 1| for t > 2 t_rec: {worst:.3%}", flush=True)
+    assert worst <= 0.005
+    assert _closure(L) <= 1e-12
+    # photo-ionization equilibrium: in the last step the photons absorbed in
+    # the ionized gas match its recombinations, alpha n_H^2 V_ion dt
+    x, _ = o.fields()
+    recomb = alpha * n32 * n32 * float(np.sum(1 - x)) * dx ** 3 * dt
+    absorbed = L["absorbed_HI"] - prev["absorbed_HI"]
+    assert absorbed == pytest.approx(recomb, rel=0.03)
+
+
+def test_equilibrium_iteration_count_changes_little_once_converged():
+    # the iteration runs to a self-consistent (Gamma, kappa): a second march
+    # per step changes the front, and a third changes it by well under a
+    # quarter of that (it contracts)
+    n, nh, Nd, alpha = 16, 1e-3, 5e48, 2.59e-13
+    dx = 13.2 * KPC / n
+    nH = np.full((n, n, n), nh, dtype=np.float32)
+    xs = {}
+    for K in (1, 2, 3):
+        o = O.Oracle((n, n, n), dx, [6.3e-18], alpha, nH, kappa=np.zeros((n, n, n), np.float32),
+                     x_HI0=np.ones((n, n, n)), c_ray=np.inf, opacity_mode=1, chem_iterations=K, n_ray_min=4.0)
+        o.set_sources(np.array([[n / 2, n / 2, n / 2]]) * dx, np.array([[Nd]]))
+        for s in range(40):
+            o.step(4 * W.MYR, W.rotation_uniforms(7, s, 1))
+        xs[K] = float(np.sum(1 - o.fields()[0]))
+    assert abs(xs[2] - xs[1]) > 1e-6 * xs[1]
+    assert abs(xs[3] - xs[2]) <= 0.25 * abs(xs[2] - xs[1])
