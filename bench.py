@@ -258,13 +258,16 @@ def genopacity_leg(frt, W, steps: int, warmup: int, stream):
             out["workload"] = (f"{prob.name}: {prob.shape[2]}^3, {prob.n_src} sources, 4 bins, c, dt 1 Myr, "
                                f"all cells neutral at the start, ionized-gas kappa from the sub-grid recipe, chi 0.08")
             out["front_share_of_emitted"] = (L["absorbed_front"] - L0["absorbed_front"]) / (L["emitted"] - L0["emitted"])
+            out["front_excess_share_of_emitted"] = ((L["front_excess"] - L0["front_excess"])
+                                                    / (L["emitted"] - L0["emitted"]))
             out["chem_GBps"] = prob.ncell * 48 / (tm["chem_ms"] / steps * 1e-3) / 1e9
             out["chem_hbm_frac"] = out["chem_GBps"] / HBM_PEAK_GBS
             out["mean_x_ion"] = float(1.0 - s.fields()[0].mean())
         out[f"{tag}_ms_per_step"] = ms
         out[f"{tag}_crossings_per_s"] = (L["crossings"] - L0["crossings"]) / (ms * steps * 1e-3)
         out[f"{tag}_ledger_closure"] = abs(L["emitted"] - L["absorbed_HI"] - L["absorbed_sub"] - L["absorbed_front"]
-                                           - L["escaped"] - L["dropped"] - L["in_flight"] - L["lost"]) / L["emitted"]
+                                           - L["front_excess"] - L["escaped"] - L["dropped"] - L["in_flight"]
+                                           - L["lost"]) / L["emitted"]
         s.close()
         ctx.close()
     return out

@@ -104,7 +104,16 @@ typedef struct {
                                        gamma_updated_standard) and n_e = n_H (1 - <x>) of the
                                        previous estimate (first: the start of the step); only
                                        the last march's deposits, ledger terms and carried
-                                       packets are kept */
+                                       packets are kept.  In the Generalized Opacity Mode, K
+                                       marches per step iterate the ionized gas's opacity with
+                                       Gamma (§4.2) using photo-ionization equilibrium (§5.1,
+                                       Eqs. subgrid_lambda, equilibrium_condition, subgrid_nHI):
+                                       kappa = kappa_sub + sigma_0 min(n_H, alpha_B n_H^2 / Gamma)
+                                       with Gamma of the march before, at a step's first march
+                                       the previous step's (optically thin, n_HI = 0, where no
+                                       rate is known yet); the previous step's rate field is
+                                       then part of the state (checkpoints and bookmarks keep
+                                       it) */
     int opacity_mode;               /* FRT_STANDARD (default) or FRT_GENERALIZED (§4.2): then
                                        kappa_sub of frt_load_grid is the absorption coefficient
                                        of each cell's ionized part at sigma_0 (kappa_nu = kappa
@@ -115,7 +124,10 @@ typedef struct {
                                        ionized the photons left stop at the front (the packet
                                        ends, ledger term absorbed_front), and the step's front
                                        photons advance x_ion by f / ((1 + he_chi) n_H V)
-                                       (Eq. dxidt), at most to 1.  Not with chem_iterations */
+                                       (Eq. dxidt), at most to 1 (photons beyond the atoms a
+                                       cell had left are ledger term front_excess).  With
+                                       chem_iterations K >= 1 the opacity of the ionized gas is
+                                       iterated with Gamma (see chem_iterations) */
     double he_chi;                  /* chi of Eq. dxidt: helium singly ionized per hydrogen
                                        atom (default 0) */
     int merge;                      /* ray merging (§3.3), 0 (default) or 1: at the end of each
@@ -135,8 +147,8 @@ typedef struct {
 
 /* Cumulative photon ledger (photons) and counters of one solve.  With
  * E = emitted, the terms satisfy E = absorbed_HI + absorbed_sub + escaped
- * + dropped + in_flight + absorbed_front + merge_residual (+ lost, which is
- * 0 unless a queue overflowed).  In the Generalized Opacity Mode absorbed_HI counts the
+ * + dropped + in_flight + absorbed_front + front_excess + merge_residual
+ * (+ lost, which is 0 unless a queue overflowed).  In the Generalized Opacity Mode absorbed_HI counts the
  * photons absorbed in ionized gas. */
 typedef struct {
     double emitted, absorbed_HI, absorbed_sub, escaped, dropped, in_flight, lost;
@@ -151,6 +163,9 @@ typedef struct {
     double merge_residual;          /* photons the merged packets held minus those their
                                        records hold in the march's precision (rounding) */
     uint64_t merges, rays_merged;   /* merged packets made, and packets merged into them */
+    double front_excess;            /* photons stopped at I-fronts beyond the neutral atoms their
+                                       cells had left; they ionize nothing (absorbed_front counts
+                                       the photons that did) */
 } frt_ledger;
 
 /* Fill *p with defaults: 1 bin at 6.3e-18 cm^2, alpha_B = 2.59e-13,

@@ -305,6 +305,8 @@ struct frt_solve_s {
     uint32_t step = 0;
     // bookmark for frt_mark / frt_rewind
     double* mark_x = nullptr;
+    void* kin = nullptr;                     // Generalized Opacity Mode with K marches: the input kappa dx
+    void* mark_g = nullptr;                  // bookmark of the previous step's rate (see warm_rate)
     uint32_t* mark_fc = nullptr;
     FrtRecs mark_F{};
     uint32_t mark_n = 0, mark_step = 0;
@@ -347,6 +349,7 @@ struct frt_solve_s {
         dev_free(mark_x);
         dev_free(mark_fc);
         dev_free(d_desc); dev_free(op); dev_free(gam[0]); dev_free(gam[1]); dev_free(x); dev_free(xavg); dev_free(front);
+        dev_free(kin); dev_free(mark_g);
         dev_free(nH); dev_free(T); dev_free(src_pos); dev_free(spec); dev_free(specd); dev_free(quat); dev_free(user_u); dev_free(fcount);
         dev_free(fcount_snap); dev_free(L); dev_free(L_snap);
         if (own_stream && stream) (void)hipStreamDestroy(stream);
@@ -490,6 +493,11 @@ int read_device_ledger(frt_solve s, FrtLedgerDev* out)
     HIPCHK(hipStreamSynchronize(s->stream));
     return FRT_OK;
 }
+
+// A Generalized Opacity Mode solve with K >= 1 marches per step starts each
+// step's opacity iteration from the previous step's rate field, which is
+// then part of its state (checkpoints and bookmarks keep it).
+bool warm_rate(frt_solve s) { return s->P.opacity_mode == FRT_GENERALIZED && s->P.chem_iterations > 0; }
 
 int ready(frt_solve s)
 {
@@ -1596,8 +1604,6 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
         return fail(FRT_EINVAL, "chem_iterations %d outside 0..%d", P->chem_iterations, FRT_MAX_CHEM_ITERATIONS);
     if (P->opacity_mode != FRT_STANDARD && P->opacity_mode != FRT_GENERALIZED)
         return fail(FRT_EINVAL, "opacity_mode must be FRT_STANDARD or FRT_GENERALIZED");
-    if (P->opacity_mode == FRT_GENERALIZED && P->chem_iterations > 0)
-        return fail(FRT_EINVAL, "the Generalized Opacity Mode takes no chem_iterations");
     if (!(P->he_chi >= 0) || !std::isfinite(P->he_chi)) return fail(FRT_EINVAL, "he_chi must be finite and >= 0");
     if (P->merge != 0 && P->merge != 1) return fail(FRT_EINVAL, "merge must be 0 or 1");
     if (P->merge_level < 0 || P->merge_level > 8) return fail(FRT_EINVAL, "merge_level %d outside 0..8", P->merge_level);
@@ -1707,7 +1713,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     }
     if (T) RCCHK(host_view(T, n, kind, bT, &hT));
     dev_free(s->op); dev_free(s->gam[0]); dev_free(s->gam[1]); dev_free(s->x); dev_free(s->xavg);
-    dev_free(s->front); dev_free(s->nH); dev_free(s->T);
+    dev_free(s->front); dev_free(s->nH); dev_free(s->T); dev_free(s->kin); dev_free(s->mark_g);
     const bool gen = s->P.opacity_mode == FRT_GENERALIZED;
     RCCHK(dev_alloc(&s->op, n * 2 * s->rs));
     RCCHK(dev_alloc(&s->gam[0], n * s->rs));
@@ -1753,6 +1759,11 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
         RCCHK(scopy(s, s->op, opv.data(), n * 8, hipMemcpyHostToDevice));
     }
     if (gen) RCCHK(sset(s, s->front, 0, n * 8));
+    if (warm_rate(s)) {
+        // the input kappa dx, from which each march's opacity is rebuilt
+        RCCHK(dev_alloc(&s->kin, n * s->rs));
+        HIPCHK(hipMemcpyAsync(s->kin, s->op, n * s->rs, hipMemcpyDeviceToDevice, s->stream));
+    }
     RCCHK(scopy(s, s->nH, nHd.data(), n * 8, hipMemcpyHostToDevice));
     RCCHK(scopy(s, s->x, xd.data(), n * 8, hipMemcpyHostToDevice));
     if (T) RCCHK(scopy(s, s->T, hT, n * 4, hipMemcpyHostToDevice));
@@ -1769,6 +1780,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     h.gen = gen ? 1 : 0;
     h.front_atoms = (1.0 + s->P.he_chi) * s->dx * s->dx * s->dx;
     h.front = s->front;
+    h.kin = s->kin;
     h.bpx = s->bpx; h.bpy = s->bpy; h.bpz = s->bpz;
     for (int a = 0; a < 3; a++) h.bsh[a] = s->bsh[a];
     h.dx_cm = s->dx;
@@ -1820,6 +1832,7 @@ int frt_set_opacity(frt_solve s, const float* kappa, int kind)
             if (gen) v[i] = std::max(v[i], floor_a);
         }
         RCCHK(scopy(s, dst, v.data(), n * 8, hipMemcpyHostToDevice));
+        if (s->kin) RCCHK(scopy(s, s->kin, v.data(), n * 8, hipMemcpyHostToDevice));
     } else {
         std::vector<float> v(n);
         for (size_t i = 0; i < n; i++) {
@@ -1827,6 +1840,7 @@ int frt_set_opacity(frt_solve s, const float* kappa, int kind)
             if (gen) v[i] = std::max(v[i], (float)floor_a);
         }
         RCCHK(scopy(s, dst, v.data(), n * 4, hipMemcpyHostToDevice));
+        if (s->kin) RCCHK(scopy(s, s->kin, v.data(), n * 4, hipMemcpyHostToDevice));
     }
     return FRT_OK;
 }
@@ -2236,12 +2250,16 @@ int frt_read_ledger(frt_solve s, frt_ledger* out)
     out->merge_residual = L.merge_residual;
     out->merges = L.merges;
     out->rays_merged = L.rays_merged;
+    out->front_excess = L.front_excess;
     return FRT_OK;
 }
 
 // Checkpoint layout: 8 u64 header (magic, version, step, n_src, ncell, nb,
 // fp64, n_carried), ledger (without stripes), x[ncell], quaternions of the
-// steps so far, then the carried packets as FrtRec structs.
+// steps so far, the carried packets as FrtRec structs, the count and
+// entries of the virtual-origin table, then the count (ncell or 0) and
+// values of the previous step's rate field (solves that start their opacity
+// iteration from it).
 int frt_save_state(frt_solve s, void* buf, size_t* bytes)
 {
     RCCHK(ready(s));
@@ -2258,14 +2276,15 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     uint32_t vc[2] = {0, 0};
     if (s->vcount) RCCHK(scopy(s, vc, s->vcount, 8, hipMemcpyDeviceToHost));
     const uint64_t nv = vc[cur];
-    const size_t need = 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec + 8 + nv * sizeof(FrtVSrc);
+    const uint64_t ng = warm_rate(s) ? s->ncell : 0;
+    const size_t need = 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec + 8 + nv * sizeof(FrtVSrc) + 8 + ng * s->rs;
     if (!buf) {
         *bytes = need;
         return FRT_OK;
     }
     if (*bytes < need) return fail(FRT_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
     char* p = (char*)buf;
-    uint64_t hdr[8] = {0x4652544350543034ull, 7, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
+    uint64_t hdr[8] = {0x4652544350543034ull, 8, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
     RCCHK(scopy(s, p, s->L, led, hipMemcpyDeviceToHost));
@@ -2285,6 +2304,10 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     std::memcpy(p, &nv, 8);
     p += 8;
     if (nv) RCCHK(scopy(s, p, s->vt[cur], nv * sizeof(FrtVSrc), hipMemcpyDeviceToHost));
+    p += nv * sizeof(FrtVSrc);
+    std::memcpy(p, &ng, 8);
+    p += 8;
+    if (ng) RCCHK(scopy(s, p, s->gam[(s->step + 1u) & 1u], ng * s->rs, hipMemcpyDeviceToHost));
     *bytes = need;
     return FRT_OK;
 }
@@ -2298,7 +2321,7 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     uint64_t hdr[8];
     std::memcpy(hdr, p, sizeof(hdr));
     p += sizeof(hdr);
-    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 7) return fail(FRT_EINVAL, "not a checkpoint of this library");
+    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 8) return fail(FRT_EINVAL, "not a checkpoint of this library");
     AllocScope scope(&s->ctx->al);
     if (hdr[3] != (uint64_t)s->n_src || hdr[4] != s->ncell || hdr[5] != (uint64_t)s->P.n_bins || hdr[6] != (uint64_t)s->fp64)
         return fail(FRT_EINVAL, "checkpoint does not match this solve (sources, grid, bins or precision)");
@@ -2309,8 +2332,13 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     if (bytes < 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec + 8) return fail(FRT_EINVAL, "checkpoint truncated");
     uint64_t nv = 0;
     std::memcpy(&nv, p + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec, 8);
-    if (bytes < 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec + 8 + nv * sizeof(FrtVSrc))
-        return fail(FRT_EINVAL, "checkpoint truncated");
+    const size_t at_ng = led + s->ncell * 8 + nq * 8 + (size_t)nc * rec + 8 + nv * sizeof(FrtVSrc);
+    if (bytes < 64 + at_ng + 8) return fail(FRT_EINVAL, "checkpoint truncated");
+    uint64_t ng = 0;
+    std::memcpy(&ng, p + at_ng, 8);
+    if (ng != (warm_rate(s) ? s->ncell : 0))
+        return fail(FRT_EINVAL, "checkpoint's previous rate field does not match this solve's opacity iteration");
+    if (bytes < 64 + at_ng + 8 + ng * s->rs) return fail(FRT_EINVAL, "checkpoint truncated");
     if (nv && !s->P.merge) return fail(FRT_EINVAL, "checkpoint holds merged packets; this solve does not merge");
     HIPCHK(hipStreamSynchronize(s->stream));
     RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
@@ -2369,6 +2397,10 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     s->h.step = step;
     RCCHK(sset(s, s->gam[0], 0, s->ncell * s->rs));
     RCCHK(sset(s, s->gam[1], 0, s->ncell * s->rs));
+    if (ng) {
+        const char* pg = (const char*)buf + 64 + at_ng + 8;
+        RCCHK(scopy(s, s->gam[(step + 1u) & 1u], pg, ng * s->rs, hipMemcpyHostToDevice));
+    }
     if (s->front) RCCHK(sset(s, s->front, 0, s->ncell * 8));
     RCCHK(upload_desc(s));
     hipError_t e = frt::launch_prep_opacity(s->d_desc, s->ncell, s->fp64, s->stream);
@@ -2407,6 +2439,12 @@ int frt_mark(frt_solve s)
         RCCHK(dev_alloc((void**)&s->mark_vt, std::max<size_t>(s->mark_vn, 1) * sizeof(FrtVSrc)));
         if (s->mark_vn) RCCHK(scopy(s, s->mark_vt, s->vt[cur], (size_t)s->mark_vn * sizeof(FrtVSrc), hipMemcpyDeviceToDevice));
     }
+    dev_free(s->mark_g);
+    if (warm_rate(s)) {
+        RCCHK(dev_alloc(&s->mark_g, s->ncell * s->rs));
+        HIPCHK(hipMemcpyAsync(s->mark_g, s->gam[(s->step + 1u) & 1u], s->ncell * s->rs, hipMemcpyDeviceToDevice,
+                              s->stream));
+    }
     s->mark_n = nc;
     s->mark_step = s->step;
     s->marked = true;
@@ -2430,6 +2468,8 @@ int frt_rewind(frt_solve s)
         HIPCHK(hipMemcpyAsync(s->vcount + cur, &s->mark_vn, 4, hipMemcpyHostToDevice, s->stream));
     }
     HIPCHK(hipMemsetAsync(s->gam[cur], 0, s->ncell * s->rs, s->stream));
+    if (s->mark_g)
+        HIPCHK(hipMemcpyAsync(s->gam[cur ^ 1], s->mark_g, s->ncell * s->rs, hipMemcpyDeviceToDevice, s->stream));
     if (s->front) HIPCHK(hipMemsetAsync(s->front, 0, s->ncell * 8, s->stream));
     s->step = s->mark_step;
     s->h.step = s->step;

@@ -66,6 +66,7 @@ struct FrtLedgerDev {
     unsigned int err_flags, max_items;
     double merge_residual;                      // photons before minus after the merges (rounding)
     unsigned long long merges, rays_merged;     // merged packets made, packets merged into them
+    double front_excess;                        // front photons beyond the atoms their cells had left
     double sd[FRT_STRIPES][LF_NF];
     unsigned long long sc[FRT_STRIPES][LC_NC];
 };
@@ -185,6 +186,10 @@ struct FrtSolveDesc {
     double dep_base;            // dep_scale times the largest w0 held (merging solves)
     double w0_hi;               // largest w0 of a cast packet so far
     float* w0_merged;           // largest w0 of a merged packet (device, merging solves)
+    // Generalized Opacity Mode with K >= 1 marches per step: the input kappa
+    // dx (march precision), from which each march's ionized-gas opacity is
+    // rebuilt with the equilibrium n_HI of the last rate
+    const void* kin;
 };
 
 // One work item of a pass: up to FRT_ITEM_RAYS packets of one brick.

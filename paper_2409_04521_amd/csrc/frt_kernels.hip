@@ -1611,6 +1611,7 @@ __device__ __forceinline__ Real hi_opacity(double v)
 }
 
 // ================================================================ chemistry
+
 // The ionized fraction as staged for the march (Generalized Opacity Mode): a
 // cell not fully ionized in FP64 stays below 1 in FP32 too, so that the
 // march stops packets at its front exactly when the FP64 state has one.
@@ -1620,6 +1621,37 @@ __device__ __forceinline__ Real staged_ionized_fraction(double xi)
     Real v = (Real)xi;
     if (xi < 1.0 && !(v < Real(1))) v = Real(1) - Real(0.5) * std::numeric_limits<Real>::epsilon();
     return v;
+}
+
+// Moving screen (§4.2, Eq. dxidt) of one cell at the end of a step: each
+// photon stopped at the cell's front ionizes 1 + chi atoms; x_ion is at
+// most 1 and never decreases; x = 1 - x_ion is the neutral volume fraction.
+// Photons beyond the atoms the cell had left ionize nothing: they move from
+// the ledger's absorbed_front to front_excess.  Clears the front count.
+template <typename Real>
+__device__ __forceinline__ void moving_screen(const FrtSolveDesc& D, size_t i)
+{
+    const double atoms = D.front_atoms * D.nH[i];
+    const double f = D.front[i];
+    const double xion = 1.0 - D.x[i];
+    double xi = 1.0, excess = 0.0;
+    if (atoms > 0.0) {
+        xi = xion + f / atoms;
+        if (xi > 1.0) {
+            const double left = (1.0 - xion) * atoms;
+            excess = f > left ? f - left : 0.0;
+            xi = 1.0;
+        }
+    } else {
+        excess = f;   // no hydrogen: nothing to ionize
+    }
+    if (excess > 0.0) {
+        atomicAdd(&D.L->front_excess, excess);
+        atomicAdd(&D.L->absorbed_front, -excess);
+    }
+    D.x[i] = 1.0 - xi;
+    ((Real*)D.op_bw)[i] = staged_ionized_fraction<Real>(xi);
+    D.front[i] = 0.0;
 }
 
 // Every cell of every solve of a launch, one per thread, in chunks of
@@ -1674,15 +1706,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
         Real* gcur = (Real*)D.gamma[D.step & 1u];
         Real* gnext = (Real*)D.gamma[(D.step + 1u) & 1u];
         if (D.gen) {
-            // moving screen (§4.2, Eq. dxidt): each photon stopped at the
-            // cell's front ionizes 1 + chi atoms; x_ion is at most 1 and
-            // never decreases; x = 1 - x_ion is the neutral volume fraction
-            const double atoms = D.front_atoms * D.nH[i];
-            double xi = atoms > 0.0 ? (1.0 - D.x[i]) + D.front[i] / atoms : 1.0;
-            xi = xi < 1.0 ? xi : 1.0;
-            D.x[i] = 1.0 - xi;
-            ((Real*)D.op_bw)[i] = staged_ionized_fraction<Real>(xi);
-            D.front[i] = 0.0;
+            moving_screen<Real>(D, i);
             gnext[i] = Real(0);
             return;
         }
@@ -1727,6 +1751,30 @@ __global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const u
     __syncthreads();
     for_each_cell(descs, spre, n_solves, total, [&](const FrtSolveDesc& D, size_t i) {
         if (D.L->err_flags) return;
+        if (D.gen) {
+            Real* gcur = (Real*)D.gamma[D.step & 1u];
+            if (phase == 2) {
+                moving_screen<Real>(D, i);
+                ((Real*)D.gamma[(D.step + 1u) & 1u])[i] = Real(0);
+                return;
+            }
+            // the opacity iteration of the Generalized Opacity Mode: the
+            // ionized gas's kappa dx for the next march is the input plus
+            // sigma_0 dx n_HI of photo-ionization equilibrium (§5.1, Eqs.
+            // subgrid_lambda and subgrid_nHI) with the last rate, the
+            // previous step's before the first march; where no rate is
+            // known the optically thin guess (n_HI = 0)
+            const double g = (double)((const Real*)D.gamma[phase == 0 ? (D.step + 1u) & 1u : D.step & 1u])[i];
+            const double nH = D.nH[i];
+            double nhi = 0.0;
+            if (g > 0.0) nhi = (D.alpha_B * nH * nH < g * nH) ? D.alpha_B * nH * nH / g : nH;
+            ((Real*)D.op_aw)[i] = hi_opacity<Real>((double)((const Real*)D.kin)[i] + D.sigma0 * nhi * D.dx_cm);
+            if (phase == 1) {
+                gcur[i] = Real(0);
+                D.front[i] = 0.0;
+            }
+            return;
+        }
         const double nH = D.nH[i];
         const double x0 = D.x[i];
         double xo;   // the neutral fraction the opacity is built from

@@ -57,7 +57,7 @@ class Ledger(C.Structure):
                 ("n_in_flight", C.c_uint64), ("rays_emitted", C.c_uint64), ("step_crossings", C.c_uint64),
                 ("steps", C.c_uint64), ("err_flags", C.c_uint32), ("max_items", C.c_uint32),
                 ("absorbed_front", C.c_double), ("merge_residual", C.c_double), ("merges", C.c_uint64),
-                ("rays_merged", C.c_uint64)]
+                ("rays_merged", C.c_uint64), ("front_excess", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

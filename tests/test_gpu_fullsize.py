@@ -168,7 +168,7 @@ def _leg_parity(ctx, p, steps, label):
     xo, _ = o.fields()
     xg, _ = g.fields()
     Lo, Lg = o.ledger(), g.ledger()
-    terms = TERMS + ("absorbed_front",)
+    terms = TERMS + ("absorbed_front", "front_excess")
     dx = float(np.abs(xo - xg).max())
     worst = {k: abs(Lo[k] - Lg[k]) / Lo["emitted"] for k in terms}
     print(f"[{label}] max|dx_HI| = {dx:.3e}, ledger rel = " + ", ".join(f"{k}:{v:.1e}" for k, v in worst.items())

@@ -13,7 +13,7 @@ from paper_2409_04521_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-TERMS = ("emitted", "absorbed_HI", "absorbed_sub", "absorbed_front", "escaped", "dropped", "in_flight")
+TERMS = ("emitted", "absorbed_HI", "absorbed_sub", "absorbed_front", "front_excess", "escaped", "dropped", "in_flight")
 DX = W.cmpc_h_to_cm(0.15625)
 
 
@@ -152,7 +152,7 @@ def test_checkpoint_resume_in_generalized_mode(ctx):
 
 def test_generalized_parameters_are_checked(ctx):
     p = _fronts_box(8, 91, n_src=1, bins=1)
-    for bad in (dict(chem_iterations=2), dict(he_chi=-1.0), dict(opacity_mode=2)):
+    for bad in (dict(chem_iterations=-1), dict(he_chi=-1.0), dict(opacity_mode=2)):
         q = W.Problem(**{**p.__dict__, **bad})
         with pytest.raises(frt.FrtError) as e:
             frt.solve_from_problem(ctx, q)
@@ -176,7 +176,9 @@ def test_nearly_ionized_cells_still_stop_packets(ctx):
     g = _gpu(ctx, p, 1)
     _compare(_oracle(p, 1), g, 1e-3, 1e-4, "nearly ionized shell")
     L = g.ledger()
-    assert L["escaped"] == 0.0 and L["absorbed_front"] > 0.9 * L["emitted"]
+    # the shell has almost no atoms left: its front photons are nearly all excess
+    assert L["escaped"] == 0.0 and L["absorbed_front"] + L["front_excess"] > 0.9 * L["emitted"]
+    assert L["front_excess"] > 0.99 * (L["absorbed_front"] + L["front_excess"])
 
 
 def test_graph_replay_equals_stepwise(ctx):
@@ -243,3 +245,83 @@ def test_no_sources_and_empty_cells(ctx):
     assert np.array_equal(xg, xo)
     assert np.abs(xg[nH > 0] - (1.0 - xi0)[nH > 0]).max() <= 1e-15
     assert np.all(xg[nH == 0] == 0.0)
+
+
+KPC = 3.0857e21
+
+
+def _test1(n, steps, dt_myr=1.0, K=2):
+    """The paper's Test 1 (§5.1) for the equilibrium opacity: n_H = 1e-3,
+    Ndot = 5e48 at 13.6 eV, alpha_B at 1e4 K, 13.2 kpc box, source at the
+    centre, no input kappa, Generalized Opacity Mode with K marches a step."""
+    dx = 13.2 * KPC / n
+    return W.Problem(name=f"test1 {n}^3", shape=(n, n, n), dx_cm=dx, n_H=np.full((n, n, n), 1e-3, np.float32),
+                     x_HI0=np.ones((n, n, n)), kappa=np.zeros((n, n, n), np.float32),
+                     src_pos_cm=np.array([[n / 2, n / 2, n / 2]]) * dx, ndot_bins=np.array([[5e48]]),
+                     sigma_bins=np.array([6.3e-18]), dt_s=dt_myr * W.MYR, n_steps=steps, c_ray=np.inf,
+                     n_ray_min=4.0, seed=7, opacity_mode=1, chem_iterations=K)
+
+
+@pytest.mark.parametrize("precision,x_tol,led_tol", [("f32", 1e-3, 1e-4), ("f64", 1e-9, 1e-9)])
+def test_equilibrium_opacity_matches_the_oracle(ctx, precision, x_tol, led_tol):
+    # the opacity of the ionized gas iterated with Gamma (photo-ionization
+    # equilibrium, §5.1): the front of Test 1 on 16^3, and the clumpy box with
+    # its input kappa added, both at K = 2 and 3 marches a step
+    p = _test1(16, 12, dt_myr=4.0)
+    _compare(_oracle(p, 12), _gpu(ctx, p, 12, precision=precision), x_tol, led_tol, f"equilibrium test1 {precision}")
+    q = _fronts_box(20, 77, c_ray=W.C_LIGHT)
+    q.chem_iterations = 3
+    _compare(_oracle(q, 4), _gpu(ctx, q, 4, precision=precision), x_tol, led_tol, f"equilibrium clumpy {precision}")
+
+
+@pytest.mark.parametrize("precision", ["f32", "f64"])
+def test_equilibrium_stromgren_front(ctx, precision):
+    # Test 1 to 3 t_rec on the GPU: the front within 0.5% of the analytic
+    # r(t) = r_S (1 - e^-t/t_rec)^(1/3) after 2 t_rec (Eqs. r_of_t, rS, trec)
+    n = 24
+    alpha, nh, Nd = 2.59e-13, float(np.float32(1e-3)), 5e48
+    t_rec = 1.0 / (alpha * nh)
+    r_S = (3 * Nd / (4 * np.pi * alpha * nh * nh)) ** (1 / 3)
+    steps = int(round(3.0 * t_rec / W.MYR))
+    p = _test1(n, steps)
+    g = frt.solve_from_problem(ctx, p, precision=precision)
+    worst = 0.0
+    for s in range(steps):
+        g.step(p.dt_s)
+        t = (s + 1) * p.dt_s
+        if t > 2 * t_rec and s % 10 == 0:
+            x, _ = g.fields()
+            r = (3 * float(np.sum(1 - x)) * p.dx_cm ** 3 / (4 * np.pi)) ** (1 / 3)
+            worst = max(worst, abs(r / (r_S * (1 - np.exp(-t / t_rec)) ** (1 / 3)) - 1))
+    print(f"[test1 {precision}] worst |r/r(t) - 1| after 2 t_rec: {worst:.3%}", flush=True)
+    assert worst <= 0.005
+    L = g.ledger()
+    closure = abs(L["emitted"] - sum(L[k] for k in TERMS[1:]) - L["lost"]) / L["emitted"]
+    assert closure <= 1e-9
+
+
+def test_equilibrium_checkpoint_and_bookmark_keep_the_rate(ctx):
+    # the previous step's rate starts each step's iteration, so it is part of
+    # the state: a resumed or rewound run repeats the continuous one
+    p = _test1(16, 8, dt_myr=4.0, K=2)
+    a = _gpu(ctx, p, 8, precision="f64")
+    b = _gpu(ctx, p, 5, precision="f64")
+    blob = b.save()
+    c = frt.solve_from_problem(ctx, p, precision="f64")
+    c.load(blob)
+    for _ in range(3):
+        c.step(p.dt_s)
+    assert np.abs(a.fields()[0] - c.fields()[0]).max() <= 1e-12
+    La, Lc = a.ledger(), c.ledger()
+    for k in TERMS:
+        assert La[k] == pytest.approx(Lc[k], rel=1e-12, abs=1e-12 * La["emitted"]), k
+    # bookmark at step 5, three steps, rewind, the same three steps again
+    b.mark()
+    for _ in range(3):
+        b.step(p.dt_s)
+    x1 = b.fields()[0]
+    b.rewind()
+    for _ in range(3):
+        b.step(p.dt_s)
+    assert np.abs(b.fields()[0] - x1).max() <= 1e-12
+    assert np.abs(b.fields()[0] - a.fields()[0]).max() <= 1e-12
