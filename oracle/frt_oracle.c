@@ -1098,10 +1098,12 @@ void orc_ledger_get(const orc_state* S, orc_ledger* L) { *L = S->L; }
 long long orc_last_crossings(const orc_state* S) { return S->last_crossings; }
 long long orc_step_index(const orc_state* S) { return S->step; }
 
-/* Checkpoint: neutral fraction, carried packets, ledger, step index. */
+/* Checkpoint: neutral fraction, the last step's rate (the first guess of
+ * the equilibrium iteration of the Generalized Opacity Mode), carried
+ * packets, ledger, step index. */
 long long orc_state_bytes(const orc_state* S)
 {
-    return (long long)(sizeof(long long) * 3 + sizeof(orc_ledger) + sizeof(double) * S->ncell +
+    return (long long)(sizeof(long long) * 3 + sizeof(orc_ledger) + 2 * sizeof(double) * S->ncell +
                        sizeof(orc_ray) * S->carried.n);
 }
 
@@ -1112,9 +1114,10 @@ int orc_save(const orc_state* S, unsigned char* buf)
     memcpy(p, hdr, sizeof(hdr)); p += sizeof(hdr);
     memcpy(p, &S->L, sizeof(orc_ledger)); p += sizeof(orc_ledger);
     memcpy(p, S->x, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
+    memcpy(p, S->gamma, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
     long long n = S->carried.n;
     memcpy(p, &n, sizeof(n)); p += sizeof(n);
-    memcpy(p, S->carried.v, sizeof(orc_ray) * n);
+    if (n > 0) memcpy(p, S->carried.v, sizeof(orc_ray) * n);
     return 0;
 }
 
@@ -1127,6 +1130,7 @@ int orc_load(orc_state* S, const unsigned char* buf)
     S->step = hdr[0];
     memcpy(&S->L, p, sizeof(orc_ledger)); p += sizeof(orc_ledger);
     memcpy(S->x, p, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
+    memcpy(S->gamma, p, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
     long long n;
     memcpy(&n, p, sizeof(n)); p += sizeof(n);
     free(S->carried.v);

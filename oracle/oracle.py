@@ -14,19 +14,26 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "frt_oracle.c")
-LIB = os.path.join(HERE, "liboracle.so")
+# FRT_ORACLE_LIB names another build of the same source (the sanitizer
+# build of the CPU tests, say)
+LIB = os.environ.get("FRT_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
 MAX_BINS = 8
+SANITIZE = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc: -O2, OpenMP, IEEE double (no fast-math)."""
-    if force or not os.path.exists(LIB):
-        tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-std=c11", "-O2", "-fno-fast-math", "-ffp-contract=off",
+def build(force: bool = True, out: str | None = None, sanitize: bool = False) -> str:
+    """Compile the oracle with gcc: -O2, OpenMP, IEEE double (no fast-math);
+    with sanitize=True an AddressSanitizer + UBSan build of the same source
+    (into `out`)."""
+    out = out or LIB
+    if force or not os.path.exists(out):
+        tmp = out + ".tmp"
+        opt = SANITIZE if sanitize else ["-O2"]
+        subprocess.check_call(["gcc", "-std=c11", *opt, "-fno-fast-math", "-ffp-contract=off",
                                "-fopenmp", "-fPIC", "-shared", "-D_DEFAULT_SOURCE",
                                SRC, "-o", tmp, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+        os.replace(tmp, out)
+    return out
 
 
 class Params(C.Structure):

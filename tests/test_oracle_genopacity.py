@@ -191,3 +191,30 @@ def test_equilibrium_iteration_count_changes_little_once_converged():
         xs[K] = float(np.sum(1 - o.fields()[0]))
     assert abs(xs[2] - xs[1]) > 1e-6 * xs[1]
     assert abs(xs[3] - xs[2]) <= 0.25 * abs(xs[2] - xs[1])
+
+
+def test_equilibrium_iteration_resumes_bitwise_from_a_checkpoint():
+    # the iteration starts from the previous step's Gamma, so a checkpoint
+    # holds it: a run saved and resumed after 4 of 8 steps ends where the
+    # uninterrupted run ends
+    n, nh, Nd, alpha = 12, 1e-3, 5e48, 2.59e-13
+    dx = 13.2 * KPC / n
+    nH = np.full((n, n, n), nh, dtype=np.float32)
+
+    def make():
+        o = O.Oracle((n, n, n), dx, [6.3e-18], alpha, nH, kappa=np.zeros((n, n, n), np.float32),
+                     x_HI0=np.ones((n, n, n)), c_ray=np.inf, opacity_mode=1, chem_iterations=2, n_ray_min=4.0)
+        o.set_sources(np.array([[n / 2, n / 2, n / 2]]) * dx, np.array([[Nd]]))
+        return o
+
+    a, b = make(), make()
+    for s in range(8):
+        a.step(4 * W.MYR, W.rotation_uniforms(7, s, 1))
+    for s in range(4):
+        b.step(4 * W.MYR, W.rotation_uniforms(7, s, 1))
+    c = make()
+    c.load(b.save())
+    for s in range(4, 8):
+        c.step(4 * W.MYR, W.rotation_uniforms(7, s, 1))
+    assert np.array_equal(a.fields()[0], c.fields()[0]) and np.array_equal(a.fields()[1], c.fields()[1])
+    assert a.ledger() == c.ledger()
