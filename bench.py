@@ -164,9 +164,20 @@ def cpu_baseline(prob, n_sample: int, threads: int):
     o.step(prob.dt_s, W.rotation_uniforms(prob.seed, 0, n_sample), threads=threads)
     dt = time.perf_counter() - t0
     cross = o.last_crossings()
-    return {"value": cross / dt, "unit": "crossings/s", "cores": threads, "kind": "oracle",
-            "sample": f"first {n_sample} of {prob.n_src} sources, full {prob.shape[2]}^3 grid, 1 step, "
-                      f"{cross} crossings in {dt:.1f} s (FP64 C oracle, OpenMP)"}
+    out = {"value": cross / dt, "unit": "crossings/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n_sample} of {prob.n_src} sources, full {prob.shape[2]}^3 grid, 1 step, "
+                     f"{cross} crossings in {dt:.1f} s (FP64 C oracle, OpenMP)"}
+    # the same oracle on one thread, over a sixteenth of the sample
+    n1 = max(1, n_sample // 16)
+    o1 = O.Oracle(**prob.oracle_kwargs(), n_chunks=1)
+    o1.set_sources(prob.src_pos_cm[:n1], prob.ndot_bins[:n1])
+    t0 = time.perf_counter()
+    o1.step(prob.dt_s, W.rotation_uniforms(prob.seed, 0, n1), threads=1)
+    dt1 = time.perf_counter() - t0
+    c1 = o1.last_crossings()
+    out["single_thread"] = {"value": c1 / dt1, "unit": "crossings/s", "cores": 1,
+                            "sample": f"first {n1} sources, same grid, 1 step, {c1} crossings in {dt1:.1f} s"}
+    return out
 
 
 def avgchem_leg(frt, W, K: int, steps: int, warmup: int, stream):
@@ -359,10 +370,12 @@ def merge_leg(frt, W, steps: int, stream):
 
 
 def batched_leg(frt, W, n_boxes: int, steps: int, warmup: int, stream):
-    """The uneven-box batch: the same boxes stepped one solve at a time
-    (the plain per-solve path) and as one batch replayed from a HIP graph
-    with the autotuned launch shape.  Returns whole-run crossings/s of both
-    and the largest x_HI difference between them."""
+    """The uneven-box batch: the same boxes stepped one solve at a time (the
+    plain per-solve path, once step by step with a host wait per step and
+    once with each solve's steps replayed from its own HIP graph and checked
+    only at the end) and as one batch replayed from a HIP graph with the
+    autotuned launch shape, also checked only at the end.  Returns whole-run
+    crossings/s of each and the largest x_HI difference between them."""
     import numpy as np
     import torch
 
@@ -395,12 +408,28 @@ def batched_leg(frt, W, n_boxes: int, steps: int, warmup: int, stream):
         s.close()
     del plain
 
+    ctx_g = frt.Context(0)
+    plain_g = [frt.solve_from_problem(ctx_g, b, stream=stream.cuda_stream) for b in boxes]
+    for s, dt in zip(plain_g, dts):
+        frt.batch_run([s], [dt], warmup, graph=True)
+    c0 = sum(s.ledger()["crossings"] for s in plain_g)
+
+    def run_plain_graph():
+        for s, dt in zip(plain_g, dts):
+            frt.batch_run([s], [dt], steps, graph=True, check_every=steps)
+    t_plain_g = timed(run_plain_graph)
+    c_plain_g = sum(s.ledger()["crossings"] for s in plain_g) - c0
+    dx_g = max(float(np.abs(a - s.fields()[0]).max()) for a, s in zip(x_plain, plain_g))
+    for s in plain_g:
+        s.close()
+    del plain_g
+
     ctx_b = frt.Context(0)
     batch = [frt.solve_from_problem(ctx_b, b, stream=stream.cuda_stream) for b in boxes]
     frt.batch_run(batch, dts, warmup, graph=True)
     tuning = frt.autotune(batch, dts)
     c0 = sum(s.ledger()["crossings"] for s in batch)
-    t_batch = timed(lambda: frt.batch_run(batch, dts, steps, graph=True))
+    t_batch = timed(lambda: frt.batch_run(batch, dts, steps, graph=True, check_every=steps))
     c_batch = sum(s.ledger()["crossings"] for s in batch) - c0
     dx = max(float(np.abs(a - s.fields()[0]).max()) for a, s in zip(x_plain, batch))
     cells = sum(int(np.prod(b.shape)) for b in boxes)
@@ -410,10 +439,17 @@ def batched_leg(frt, W, n_boxes: int, steps: int, warmup: int, stream):
     return {"workload": f"{n_boxes} boxes, edges 32-128, {cells} cells, {srcs} sources, 3 bins, c, dt 1 Myr",
             "steps": steps, "warmup": warmup,
             "plain_crossings_per_s": c_plain / t_plain, "plain_s": t_plain,
+            "plain_form": "one solve at a time, frt_step per step (waits on the host every step)",
+            "plain_graph_crossings_per_s": c_plain_g / t_plain_g, "plain_graph_s": t_plain_g,
+            "plain_graph_form": "one solve at a time, its steps replayed from its own HIP graph, "
+                                "queue counters read once at the end of the run",
             "batched_crossings_per_s": c_batch / t_batch, "batched_s": t_batch,
             "speedup": (c_batch / t_batch) / (c_plain / t_plain) if c_plain else None,
+            "speedup_vs_plain_graph": (c_batch / t_batch) / (c_plain_g / t_plain_g) if c_plain_g else None,
             "crossings": c_batch, "max_abs_dx_HI_batched_vs_plain": dx,
-            "batched_form": "one launch sequence per step over all boxes, replayed from a HIP graph",
+            "max_abs_dx_HI_plain_graph_vs_plain": dx_g,
+            "batched_form": "one launch sequence per step over all boxes, replayed from a HIP graph, "
+                            "queue counters read once at the end of the run",
             "tuning": tuning}
 
 
@@ -627,8 +663,10 @@ def main():
     if not args.no_batched:
         log(f"batched leg: {args.batched_boxes} boxes, {args.batched_steps} steps")
         out["batched"] = batched_leg(frt, W, args.batched_boxes, args.batched_steps, args.batched_warmup, stream)
-        log(f"batched: {out['batched']['batched_crossings_per_s']:.3e} crossings/s vs plain "
-            f"{out['batched']['plain_crossings_per_s']:.3e} (x{out['batched']['speedup']:.2f})")
+        bt = out["batched"]
+        log(f"batched: {bt['batched_crossings_per_s']:.3e} crossings/s vs plain {bt['plain_crossings_per_s']:.3e} "
+            f"(x{bt['speedup']:.2f}) and plain from per-solve graphs {bt['plain_graph_crossings_per_s']:.3e} "
+            f"(x{bt['speedup_vs_plain_graph']:.2f})")
     if not args.no_avgchem:
         log(f"time-averaged chemistry leg: K = {args.avgchem_iterations}, {args.avgchem_steps} steps")
         out["avg_chem"] = avgchem_leg(frt, W, args.avgchem_iterations, args.avgchem_steps, 2, stream)

@@ -279,13 +279,18 @@ int frt_step_static(frt_solve s, double dt_s);
 int frt_batch_step(frt_solve* solves, int n, const double* dt_s);
 
 /* n_steps steps of each of n solves (as n_steps calls of frt_batch_step).
- * With use_graph != 0 one step of the group is captured into a HIP graph
- * and replayed n_steps times: the descriptors and rotation tables are
- * prepared before the capture, and the step index advances on the device.
- * Each replay is checked; with automatic queues an overflowed step is
- * restored, the queues grow, the step is captured again and repeated, and
- * with fixed queues the call returns FRT_EOVERFLOW with the failed step not
- * applied.  dt_s[i] is solve i's step for every step of the run. */
+ * With use_graph = 0 the steps are launched one by one, each waited for.
+ * With use_graph = w > 0 one step of the group is captured into a HIP graph
+ * and replayed n_steps times, w replays enqueued at a time with no host wait
+ * between them: the descriptors and rotation tables are prepared before the
+ * capture, and the step index advances on the device.  The queue counters
+ * are read back after each w replays; a replayed step that overflowed makes
+ * the replays after it in the same w do nothing, so the solves stay at the
+ * start of that step.  With automatic queues the step is then restored, the
+ * queues grow, the step is captured again and the run goes on from it; with
+ * fixed queues the call returns FRT_EOVERFLOW with the failed step not
+ * applied (the steps before it are).  dt_s[i] is solve i's step for every
+ * step of the run.  FRT_EINVAL for use_graph < 0. */
 int frt_batch_run(frt_solve* solves, int n, const double* dt_s, int n_steps, int use_graph);
 
 /* Launch shape of the passes, shared by the solves stepped on a context. */

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdarg>
 #include <cstddef>
@@ -693,28 +694,33 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
     const int fp64 = ss[0]->fp64;
     FrtWS w = g.w;
     frt_solve tm = (timed && !graph && ss[0]->timing) ? ss[0] : nullptr;
+    // a replayed step does nothing after a replay that failed; a step
+    // launched on its own starts by resetting every launch counter
+    const uint32_t* halt = graph ? w.ctr + C_HALT : nullptr;
     hipError_t e;
     // every solve's ledger and carried-queue counters as the step starts, for
     // a re-run after an overflow (one kernel for the whole group)
-    if ((e = frt::launch_snapshot(ws.descs, n, st)) != hipSuccess) return fail(FRT_EDEVICE, "snapshot: %s", hipGetErrorString(e));
+    if ((e = frt::launch_snapshot(ws.descs, n, halt, st)) != hipSuccess) return fail(FRT_EDEVICE, "snapshot: %s", hipGetErrorString(e));
     // backward Euler: one march, then the update; time-averaged chemistry:
     // K marches from the same packets with <x> updated between them
     const int K = ss[0]->P.chem_iterations;   // the same for every solve of a group
     const int n_march = K > 0 ? K : 1;
     if (K > 0) {
         Timed t(tm, st, 2);
-        if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 0, w.ctr + C_ERR, st)) != hipSuccess)
+        if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 0, w.ctr + C_ERR, halt, st)) != hipSuccess)
             return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
     }
     for (int it = 0; it < n_march; it++) {
         if (it > 0) {
             Timed t(tm, st, 3);
-            if ((e = frt::launch_iter_restart(ws.descs, n, st)) != hipSuccess) return fail(FRT_EDEVICE, "restart: %s", hipGetErrorString(e));
+            if ((e = frt::launch_iter_restart(ws.descs, n, halt, st)) != hipSuccess)
+                return fail(FRT_EDEVICE, "restart: %s", hipGetErrorString(e));
         }
         {
             Timed t(tm, st, 0);
             w.out = 0;   // seeds fill buffer 0, the input of the first pass
-            if ((e = frt::launch_clear(w, it > 0, st)) != hipSuccess) return fail(FRT_EDEVICE, "clear: %s", hipGetErrorString(e));
+            const int mode = it > 0 ? CLEAR_ITER : (graph ? CLEAR_STEP : CLEAR_ALL);
+            if ((e = frt::launch_clear(w, mode, st)) != hipSuccess) return fail(FRT_EDEVICE, "clear: %s", hipGetErrorString(e));
             if ((e = frt::launch_seed(ws.descs, w, fp64, st)) != hipSuccess) return fail(FRT_EDEVICE, "seed: %s", hipGetErrorString(e));
         }
         for (int p = 0; p < g.passes; p++) {
@@ -736,13 +742,13 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
         }
         if (it + 1 < n_march) {
             Timed t(tm, st, 2);
-            if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 1, w.ctr + C_ERR, st)) != hipSuccess)
+            if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 1, w.ctr + C_ERR, halt, st)) != hipSuccess)
                 return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         }
     }
     {
         Timed t(tm, st, 2);
-        if (K > 0) e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 2, w.ctr + C_ERR, st);
+        if (K > 0) e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 2, w.ctr + C_ERR, halt, st);
         else e = frt::launch_chem(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.ctr + C_ERR, st);
         if (e != hipSuccess) return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         if (tm) tm->n_chem++;
@@ -1118,16 +1124,19 @@ struct StepGraph {
 };
 
 // n_steps steps of a group; each step is one replay of a captured graph.
-// Every replay is checked: an overflow restores the step's start, grows the
-// queues, captures again and repeats the step.  The caller holds the lock.
-int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps)
+// Replays are enqueued `window` at a time and the launch counters are read
+// back after each window: the replays after one that failed do nothing
+// (C_HALT), C_DONE tells how many steps were applied, and an overflow
+// restores the failed step's start, grows the queues, captures again and
+// repeats the step.  The caller holds the lock.
+int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps, int window)
 {
     {
         std::vector<std::vector<frt_solve>> parts;
         std::vector<std::vector<double>> pdts;
         if (split_by_shape(ss, n, dts, parts, pdts)) {
             for (size_t k = 0; k < parts.size(); k++)
-                RCCHK(run_group_graph_locked(parts[k].data(), (int)parts[k].size(), pdts[k].data(), n_steps));
+                RCCHK(run_group_graph_locked(parts[k].data(), (int)parts[k].size(), pdts[k].data(), n_steps, window));
             return FRT_OK;
         }
     }
@@ -1163,9 +1172,18 @@ int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps)
             if (ec != hipSuccess) return fail(FRT_EDEVICE, "graph capture: %s", hipGetErrorString(ec));
             HIPCHK(hipGraphInstantiate(&sg.exec, sg.graph, nullptr, nullptr, 0));
         }
-        HIPCHK(hipGraphLaunch(sg.exec, st));
+        const int k = std::min(window, n_steps - done);
+        hipError_t e;
+        if ((e = frt::launch_clear(g.w, CLEAR_ALL, st)) != hipSuccess) return fail(FRT_EDEVICE, "clear: %s", hipGetErrorString(e));
+        for (int r = 0; r < k; r++) HIPCHK(hipGraphLaunch(sg.exec, st));
         uint32_t ctr[C_NCTR];
         RCCHK(read_counters(ws, st, ctr));
+        const uint32_t applied = ctr[C_DONE];
+        if (applied > (uint32_t)k || (applied < (uint32_t)k && !ctr[C_HALT]))
+            return fail(FRT_EDEVICE, "%u of %d replayed steps reported applied", applied, k);
+        for (int i = 0; i < n; i++) ss[i]->step += applied;
+        done += (int)applied;
+        if (applied) retries = 0;
         if (ctr[C_ERR] & (FRT_DEVERR_QUEUE_OVERFLOW | FRT_DEVERR_CARRY_OVERFLOW)) {
             if (!auto_grow) {
                 // fixed capacities: the step is not applied
@@ -1184,9 +1202,6 @@ int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps)
             continue;
         }
         if (ctr[C_ERR] & FRT_DEVERR_UNFINISHED) return fail(FRT_EDEVICE, "a step left packets after its last pass");
-        retries = 0;
-        for (int i = 0; i < n; i++) ss[i]->step++;
-        done++;
     }
     for (int i = 0; i < n; i++) {
         ss[i]->h.step = ss[i]->step;
@@ -1422,7 +1437,7 @@ int debug_cast_locked(frt_solve s, const double o_cm[3], const double d_in[3], c
     FrtWS w = g.w;
     hipError_t e;
     w.out = 0;
-    if ((e = frt::launch_clear(w, 0, st)) != hipSuccess) return fail(FRT_EDEVICE, "clear: %s", hipGetErrorString(e));
+    if ((e = frt::launch_clear(w, CLEAR_ALL, st)) != hipSuccess) return fail(FRT_EDEVICE, "clear: %s", hipGetErrorString(e));
     if ((e = frt::launch_seed(ws.descs, w, s->fp64, st)) != hipSuccess) return fail(FRT_EDEVICE, "seed: %s", hipGetErrorString(e));
     for (int p = 0; p < g.passes; p++) {
         w.out = (p + 1) & 1;
@@ -1470,6 +1485,25 @@ int check_tuning(const frt_tuning* t)
 namespace frt {
 
 int set_error(int code, const char* msg) { return fail(code, "%s", msg); }
+
+int use_device(int device)
+{
+    HIPCHK(hipSetDevice(device));
+    return FRT_OK;
+}
+
+int copy_device_to_host(void* dst, const void* src, size_t bytes)
+{
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipMemcpy(dst, src, bytes, hipMemcpyDeviceToHost));
+    return FRT_OK;
+}
+
+double clock_s()
+{
+    static const auto t0 = std::chrono::steady_clock::now();
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
 
 int ctx_device(frt_ctx ctx) { return ctx->device; }
 
@@ -2064,6 +2098,7 @@ int frt_batch_run(frt_solve* ss, int n, const double* dts, int n_steps, int use_
     RCCHK(check_batch(ss, n, dts));
     AllocScope scope(&ss[0]->ctx->al);
     if (n_steps < 0) return fail(FRT_EINVAL, "n_steps must be >= 0");
+    if (use_graph < 0) return fail(FRT_EINVAL, "use_graph must be >= 0 (0: no graph, w > 0: replays per host check)");
     if (n_steps == 0) return FRT_OK;
     HIPCHK(hipSetDevice(ss[0]->ctx->device));
     for (int i = 0; i < n; i++) HIPCHK(hipStreamSynchronize(ss[i]->stream));
@@ -2075,7 +2110,7 @@ int frt_batch_run(frt_solve* ss, int n, const double* dts, int n_steps, int use_
         for (int k = 0; k < n_steps; k++) RCCHK(step_group(ss, n, dts));
     } else {
         std::lock_guard<std::mutex> lock(ss[0]->ctx->mu);
-        RCCHK(run_group_graph_locked(ss, n, dts, n_steps));
+        RCCHK(run_group_graph_locked(ss, n, dts, n_steps, use_graph));
     }
     HIPCHK(hipStreamSynchronize(ss[0]->stream));
     return FRT_OK;

@@ -6,9 +6,9 @@
 #include <cstdint>
 
 #include "frt.h"
+#include "frt_serving.h"
 
 #define FRT_MAX_BINS_I 8
-#define FRT_MAX_SOLVES_PER_LAUNCH 1024
 
 // Bricks of the LDS-staged march, edges 2^l per axis (x, y, z).  The FP32
 // march without sub-grid opacity stages 32 x 16 x 16 cells (32 KiB of HI
@@ -197,7 +197,18 @@ struct FrtWork {
     uint32_t key, start, count, solve;
 };
 
-enum { C_NOS = 0, C_NP, C_NWORK, C_ERR, C_MAXP, C_NEXT, C_NCTR = 8 };
+// Launch counters.  C_HALT and C_DONE serve steps replayed from a HIP graph
+// several times between host reads: the end of a replayed step that raised
+// an error sets C_HALT, after which every kernel of the later replays returns
+// at once (the failed step's start stays as the step left it, for the
+// restore); C_DONE counts the replayed steps that were applied.  Both are
+// reset only by a CLEAR_ALL.
+enum { C_NOS = 0, C_NP, C_NWORK, C_ERR, C_MAXP, C_NEXT, C_HALT, C_DONE, C_NCTR = 8 };
+
+// k_clear modes: the first march of a step (keeps C_HALT and C_DONE), a
+// later march of the same step (also keeps the error bits and the largest
+// pass), and a full reset (every counter, also under a halt).
+enum { CLEAR_STEP = 0, CLEAR_ITER = 1, CLEAR_ALL = 2 };
 
 // Per-launch workspace: unsorted pass outputs O, packets sorted by brick P,
 // packets that reached their split radius S (with their photons), per-key
@@ -293,34 +304,20 @@ hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix,
                        unsigned long long total_cells, int fp64, const uint32_t* launch_err, hipStream_t s);
 hipError_t launch_prep_opacity(FrtSolveDesc* d_desc, unsigned long long ncell, int fp64, hipStream_t s);
 // Clear the launch counters and brick histogram (a kernel, so that a step
-// captured in a HIP graph holds no memset node).
-hipError_t launch_clear(const FrtWS& ws, int keep_err, hipStream_t s);
+// captured in a HIP graph holds no memset node); mode is a CLEAR_* value.
+hipError_t launch_clear(const FrtWS& ws, int mode, hipStream_t s);
+// `halt` (device, may be null) is the launch's C_HALT word: when it is set
+// the kernel does nothing.  Steps launched one by one pass null.
 hipError_t launch_chem_avg(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
                            unsigned long long total_cells, int fp64, int phase, const uint32_t* launch_err,
-                           hipStream_t s);
-hipError_t launch_iter_restart(FrtSolveDesc* d, int n_solves, hipStream_t s);
-hipError_t launch_snapshot(FrtSolveDesc* d, int n_solves, hipStream_t s);
-// Advance every solve's step index on the device unless the step raised an
-// error (used by steps replayed from a HIP graph).
+                           const uint32_t* halt, hipStream_t s);
+hipError_t launch_iter_restart(FrtSolveDesc* d, int n_solves, const uint32_t* halt, hipStream_t s);
+hipError_t launch_snapshot(FrtSolveDesc* d, int n_solves, const uint32_t* halt, hipStream_t s);
+// End of a step replayed from a HIP graph: advance every solve's step index
+// on the device and count the step in C_DONE, or, if the step raised an
+// error, set C_HALT instead.
 hipError_t launch_advance(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
 // Query launch shapes once, outside any stream capture.
 void prime_launch_shapes(int fp64, int n_bins, int has_sub);
 int device_cu_count();
-// Set the calling thread's error message (returned by frt_last_error) and
-// return code; for the serving layer, which sits above the ABI.
-int set_error(int code, const char* msg);
-int ctx_device(frt_ctx ctx);
-// Device bytes a solve with these parameters and sizes holds, and the first
-// pass-queue size it asks for (records, and their bytes, which are part of
-// the total: the pass queues are shared by the solves of a context and grow
-// with the largest pass).
-uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T, uint64_t* pass_records,
-                     uint64_t* pass_bytes);
-// Device bytes the context's shared pass queues hold now, and the most they
-// may grow to (0: no limit; a step that needs more fails with FRT_ENOMEM
-// before anything runs).  Trimming frees them (the next step allocates them
-// again at its own size); only while no step of the context is running.
-uint64_t ctx_workspace_bytes(frt_ctx ctx);
-void ctx_set_workspace_limit(frt_ctx ctx, uint64_t bytes);
-void ctx_trim_workspace(frt_ctx ctx);
 }  // namespace frt

@@ -90,6 +90,9 @@ __device__ __forceinline__ uint32_t wave_reserve(uint32_t* ctr, uint32_t n_lane)
 
 // Fill counters and sizes of the output segments (see FRT_QSEG).
 __device__ __forceinline__ uint32_t* o_ctr(const FrtWS& ws, int k) { return ws.segc + k * FRT_QSEG_STRIDE; }
+// A replayed step after one that failed: every kernel of the step returns
+// at once (the same value for the whole grid, read before any barrier).
+__device__ __forceinline__ bool halted(const FrtWS& ws) { return ws.ctr[C_HALT] != 0u; }
 __device__ __forceinline__ uint32_t seg_cap(uint32_t cap) { return cap / FRT_QSEG; }
 __device__ __forceinline__ int my_seg() { return (int)(blockIdx.x % FRT_QSEG); }
 
@@ -392,7 +395,7 @@ __device__ __forceinline__ void count_keys_wave(uint32_t* s_key, uint32_t* s_cnt
 __global__ void k_seed_plan(FrtSolveDesc* descs, FrtWS ws)
 {
     // one wave: a solve per lane, the prefix by wave scans, 64 solves a round
-    if (blockIdx.x != 0 || threadIdx.x >= WAVE) return;
+    if (blockIdx.x != 0 || threadIdx.x >= WAVE || halted(ws)) return;
     uint32_t acc = 0;
     for (int s0 = 0; s0 < ws.n_solves; s0 += WAVE) {
         const int s = s0 + (int)threadIdx.x;
@@ -426,6 +429,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
 {
     __shared__ uint32_t spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
     __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];   // output keys counted per round
+    if (halted(ws)) return;
     for (int i = threadIdx.x; i <= ws.n_solves; i += blockDim.x) spre[i] = ws.seed_prefix[i];
     if (threadIdx.x < KEY_SLOTS) { s_key[threadIdx.x] = 0xffffffffu; s_cnt[threadIdx.x] = 0; }
     __syncthreads();
@@ -553,6 +557,7 @@ __global__ void __launch_bounds__(BLOCK) k_seed(FrtSolveDesc* descs, FrtWS ws)
 __global__ void __launch_bounds__(1024) k_scan(FrtWS ws)
 {
     __shared__ uint32_t s_a[2 * WAVE + 1], s_b[2 * WAVE + 1];   // wave totals, their prefix, the total
+    if (halted(ws)) return;
     const uint32_t nk = ws.nkeys;
     const uint32_t per = (nk + blockDim.x - 1) / blockDim.x;
     const uint32_t k0 = threadIdx.x * per, k1 = min(nk, k0 + per);
@@ -650,6 +655,7 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
     constexpr uint32_t EMPTY = 0xffffffffu;
     __shared__ uint32_t s_key[SLOTS], s_cnt[SLOTS], s_base[SLOTS];
     __shared__ uint32_t s_sp[FRT_QSEG + 1];
+    if (halted(ws)) return;
     for (int i = threadIdx.x; i <= FRT_QSEG; i += blockDim.x) s_sp[i] = ws.segp[i];
     const uint32_t n = ws.ctr[C_NOS];
     const uint32_t scap = seg_cap(ws.buf[0].cap);
@@ -1510,6 +1516,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
 template <typename Real, int NB, bool SUB>
 __global__ void __launch_bounds__(BLOCK) k_brick(const FrtSolveDesc* __restrict__ descs, FrtWS ws)
 {
+    if (halted(ws)) return;
     if constexpr (sizeof(Real) == 4)
         brick_march<Real, NB, SUB, FRT_BRICK_LOG_SUB[0], FRT_BRICK_LOG_SUB[1], FRT_BRICK_LOG_SUB[2], BLOCK>(descs, ws);
     else
@@ -1521,27 +1528,38 @@ __global__ void __launch_bounds__(BLOCK) k_brick(const FrtSolveDesc* __restrict_
 template <typename Real, int NB>
 __global__ void __launch_bounds__(4 * BLOCK) k_brick_big(const FrtSolveDesc* __restrict__ descs, FrtWS ws)
 {
+    if (halted(ws)) return;
     brick_march<Real, NB, false, FRT_BRICK_LOG_BIG[0], FRT_BRICK_LOG_BIG[1], FRT_BRICK_LOG_BIG[2], 4 * BLOCK>(descs, ws);
 }
 
 // ============================================================ bookkeeping
 // Clears the launch counters and the key histogram; a later march of the
 // same step keeps the error bits and the largest pass size seen so far.
-__global__ void k_clear(FrtWS ws, int keep_err)
+// Only CLEAR_ALL touches C_HALT and C_DONE, and only it runs under a halt.
+__global__ void k_clear(FrtWS ws, int mode)
 {
+    if (mode != CLEAR_ALL && halted(ws)) return;
     const uint32_t stride = gridDim.x * blockDim.x;
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t < C_NCTR && !(keep_err && (t == C_ERR || t == C_MAXP))) ws.ctr[t] = 0;
+    const bool keep = (mode == CLEAR_ITER && (t == C_ERR || t == C_MAXP)) ||
+                      (mode != CLEAR_ALL && (t == C_HALT || t == C_DONE));
+    if (t < C_NCTR && !keep) ws.ctr[t] = 0;
     for (uint32_t k = t; k < ws.nkeys; k += stride) ws.hist[k] = 0;
 }
 
+// One workgroup of one wave.
 __global__ void k_advance(FrtSolveDesc* descs, FrtWS ws)
 {
-    if (ws.ctr[C_ERR] != 0) return;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ws.n_solves; i += gridDim.x * blockDim.x) {
+    if (halted(ws)) return;
+    if (ws.ctr[C_ERR] != 0) {
+        if (threadIdx.x == 0) ws.ctr[C_HALT] = 1u;
+        return;
+    }
+    for (int i = threadIdx.x; i < ws.n_solves; i += blockDim.x) {
         descs[i].step += 1u;
         descs[i].cur ^= 1u;
     }
+    if (threadIdx.x == 0) ws.ctr[C_DONE] += 1u;
 }
 
 // =============================================================== step close
@@ -1550,6 +1568,7 @@ __global__ void k_advance(FrtSolveDesc* descs, FrtWS ws)
 __global__ void k_finish(FrtSolveDesc* descs, FrtWS ws)
 {
     __shared__ int s_left;
+    if (halted(ws)) return;
     if (threadIdx.x == 0) s_left = 0;
     __syncthreads();
     if (threadIdx.x < FRT_QSEG && *o_ctr(ws, threadIdx.x) > 0) s_left = 1;
@@ -1743,10 +1762,10 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
 template <typename Real>
 __global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const unsigned long long* prefix,
                                                     int n_solves, unsigned long long total, int phase,
-                                                    const uint32_t* launch_err)
+                                                    const uint32_t* launch_err, const uint32_t* halt)
 {
     __shared__ unsigned long long spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
-    if (phase != 0 && *launch_err) return;
+    if ((halt && *halt) || (phase != 0 && *launch_err)) return;
     for (int i = threadIdx.x; i <= n_solves; i += blockDim.x) spre[i] = prefix[i];
     __syncthreads();
     for_each_cell(descs, spre, n_solves, total, [&](const FrtSolveDesc& D, size_t i) {
@@ -1810,8 +1829,9 @@ __global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const u
 // The ledger and carried-queue counters of every solve as a step starts, kept
 // for a re-run of the step (queue growth) and for the later marches of the
 // time-averaged chemistry.  One workgroup per solve.
-__global__ void __launch_bounds__(BLOCK) k_snapshot(FrtSolveDesc* descs)
+__global__ void __launch_bounds__(BLOCK) k_snapshot(FrtSolveDesc* descs, const uint32_t* halt)
 {
+    if (halt && *halt) return;
     const FrtSolveDesc& D = descs[blockIdx.x];
     constexpr int NW = (int)(sizeof(FrtLedgerDev) / sizeof(unsigned long long));
     const unsigned long long* src = (const unsigned long long*)D.L;
@@ -1823,8 +1843,9 @@ __global__ void __launch_bounds__(BLOCK) k_snapshot(FrtSolveDesc* descs)
 // Every march of a step after the first starts from the step's packets: the
 // ledger and the carried-queue counters go back to their values at the
 // start of the step, keeping the device error bits.  One workgroup per solve.
-__global__ void __launch_bounds__(BLOCK) k_iter_restart(FrtSolveDesc* descs)
+__global__ void __launch_bounds__(BLOCK) k_iter_restart(FrtSolveDesc* descs, const uint32_t* halt)
 {
+    if (halt && *halt) return;
     const FrtSolveDesc& D = descs[blockIdx.x];
     __shared__ uint32_t s_err;
     if (threadIdx.x == 0) s_err = D.L->err_flags;
@@ -2031,34 +2052,37 @@ hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix,
     return hipGetLastError();
 }
 
-hipError_t launch_clear(const FrtWS& ws, int keep_err, hipStream_t s)
+hipError_t launch_clear(const FrtWS& ws, int mode, hipStream_t s)
 {
     const uint32_t n = ws.nkeys > C_NCTR ? ws.nkeys : C_NCTR;
-    hipLaunchKernelGGL(k_clear, dim3(grid_for(n, 4)), dim3(BLOCK), 0, s, ws, keep_err);
+    hipLaunchKernelGGL(k_clear, dim3(grid_for(n, 4)), dim3(BLOCK), 0, s, ws, mode);
     return hipGetLastError();
 }
 
 hipError_t launch_chem_avg(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
-                           unsigned long long total_cells, int fp64, int phase, const uint32_t* launch_err, hipStream_t s)
+                           unsigned long long total_cells, int fp64, int phase, const uint32_t* launch_err,
+                           const uint32_t* halt, hipStream_t s)
 {
     if (total_cells == 0) return hipSuccess;
     const int grid = grid_for(total_cells, 16);
     if (fp64)
-        hipLaunchKernelGGL(k_chem_avg<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase, launch_err);
+        hipLaunchKernelGGL(k_chem_avg<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase,
+                           launch_err, halt);
     else
-        hipLaunchKernelGGL(k_chem_avg<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase, launch_err);
+        hipLaunchKernelGGL(k_chem_avg<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase,
+                           launch_err, halt);
     return hipGetLastError();
 }
 
-hipError_t launch_snapshot(FrtSolveDesc* d, int n_solves, hipStream_t s)
+hipError_t launch_snapshot(FrtSolveDesc* d, int n_solves, const uint32_t* halt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_snapshot, dim3(n_solves), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_snapshot, dim3(n_solves), dim3(BLOCK), 0, s, d, halt);
     return hipGetLastError();
 }
 
-hipError_t launch_iter_restart(FrtSolveDesc* d, int n_solves, hipStream_t s)
+hipError_t launch_iter_restart(FrtSolveDesc* d, int n_solves, const uint32_t* halt, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_iter_restart, dim3(n_solves), dim3(BLOCK), 0, s, d);
+    hipLaunchKernelGGL(k_iter_restart, dim3(n_solves), dim3(BLOCK), 0, s, d, halt);
     return hipGetLastError();
 }
 

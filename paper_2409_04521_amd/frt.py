@@ -14,7 +14,8 @@ import os
 import numpy as np
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libfrt.so")
+# FRT_LIB names another build of the library (the host-sanitized one, say)
+LIB_PATH = os.environ.get("FRT_LIB") or os.path.join(PKG, "libfrt.so")
 
 FRT_OK, FRT_EINVAL, FRT_ENOMEM, FRT_EDEVICE, FRT_EOVERFLOW, FRT_ESTATE = 0, -1, -2, -3, -4, -5
 FRT_HOST, FRT_DEVICE = 0, 1
@@ -145,6 +146,13 @@ def lib():
         if not os.path.exists(LIB_PATH):
             raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
                               "(python -m paper_2409_04521_amd.build)")
+        try:
+            # PyTorch brings a HIP runtime of its own: loaded first, it is the
+            # one the library binds to, so tensors, streams and allocator
+            # hooks are shared (loaded after the library's, torch finds no GPU)
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = C.CDLL(LIB_PATH)
         vp = C.c_void_p
         L.frt_last_error.restype = C.c_char_p
@@ -418,11 +426,12 @@ def batch_step(solves, dts):
     _check(lib().frt_batch_step(arr, len(solves), d))
 
 
-def batch_run(solves, dts, n_steps: int, graph: bool = True):
+def batch_run(solves, dts, n_steps: int, graph: bool = True, check_every: int = 1):
     """n_steps steps of every solve, one captured HIP graph replayed per step
-    (graph=True) or launched step by step."""
+    (graph=True; the queue counters are read back after every `check_every`
+    replays) or launched step by step."""
     arr, d = _group(solves, dts)
-    _check(lib().frt_batch_run(arr, len(solves), d, int(n_steps), 1 if graph else 0))
+    _check(lib().frt_batch_run(arr, len(solves), d, int(n_steps), int(check_every) if graph else 0))
 
 
 def autotune(solves, dts) -> dict:

@@ -73,16 +73,89 @@ def test_graph_run_equals_stepwise_and_oracle():
         _same(a, g, b.name + " +1")
 
 
-def test_graph_run_grows_its_queues():
+@pytest.mark.parametrize("check_every", [1, 2])
+def test_graph_run_grows_its_queues(check_every):
     p = _dense_ray_problem()
     a = frt.solve_from_problem(frt.Context(0), p)
     for _ in range(2):
         a.step(p.dt_s)
     small = frt.Context(0)            # own workspace, first sized from the hint
     g = frt.solve_from_problem(small, p, queue_hint=4096)
-    frt.batch_run([g], [p.dt_s], 2, graph=True)
-    _same(a, g, "grown in a graph run")
+    frt.batch_run([g], [p.dt_s], 2, graph=True, check_every=check_every)
+    _same(a, g, f"grown in a graph run, checked every {check_every}")
     _versus_oracle(p, g, 2, "grown in a graph run")
+
+
+def _carrying_box(seed=51, kappa=False):
+    # packets carried at a finite speed pile up over the steps, so the passes
+    # grow from step to step
+    p = W.lognormal_c2(n=24, n_src=6, n_steps=7, box_cmpc_h=20.0 * 24 / 128, seed=seed)
+    p.x_HI0 = np.full(p.shape, 1e-4)
+    if not kappa:
+        p.kappa = None
+    p.c_ray = 2.0 * p.dx_cm / p.dt_s
+    return p
+
+
+@pytest.mark.parametrize("check_every", [3, 7])
+def test_windowed_graph_run_equals_a_check_per_step(check_every):
+    # several replays between host reads change nothing: FP64, so the only
+    # difference allowed is the order of the ledger's atomic additions
+    ctx = frt.Context(0)
+    boxes = [_carrying_box(51), _carrying_box(52), _carrying_box(53, kappa=True)]
+    dts = [b.dt_s for b in boxes]
+    each = [frt.solve_from_problem(ctx, b, precision="f64") for b in boxes]
+    win = [frt.solve_from_problem(ctx, b, precision="f64") for b in boxes]
+    frt.batch_run(each, dts, 7, graph=True, check_every=1)
+    frt.batch_run(win, dts, 7, graph=True, check_every=check_every)
+    for b, a, w in zip(boxes, each, win):
+        assert np.abs(a.fields()[0] - w.fields()[0]).max() <= 1e-12, b.name
+        La, Lw = a.ledger(), w.ledger()
+        assert La["steps"] == Lw["steps"] == 7
+        for k in TERMS:
+            assert abs(La[k] - Lw[k]) <= 1e-12 * La["emitted"], (b.name, k)
+        assert Lw["err_flags"] == 0 and Lw["crossings"] == La["crossings"]
+    _versus_oracle(boxes[0], win[0], 7, f"windowed graph run, checked every {check_every}")
+
+
+def test_overflow_inside_a_window_stops_at_the_failed_step():
+    # a fixed capacity that the first steps fit and a later one does not:
+    # the windowed graph run applies the steps before the failed one and
+    # leaves the solve exactly where stepping one by one stops
+    p = _carrying_box()
+    steps = p.n_steps
+    found = None
+    cap = 512
+    while cap < (1 << 26):
+        # the smallest capacity (in steps of 1.5x) that the first step fits
+        probe = frt.solve_from_problem(frt.Context(0), p, precision="f64", queue_capacity=cap)
+        fail_at = None
+        for k in range(steps):
+            try:
+                probe.step(p.dt_s)
+            except frt.FrtError as e:
+                assert e.code == frt.FRT_EOVERFLOW
+                fail_at = k
+                break
+        if fail_at is None:
+            break
+        if fail_at >= 1:
+            found = (cap, fail_at, probe)
+            break
+        cap = int(cap * 1.5)
+    assert found is not None, "no capacity that a later step overflows"
+    cap, fail_at, probe = found
+    print(f"capacity {cap}: stepping one by one stops at step {fail_at}", flush=True)
+    g = frt.solve_from_problem(frt.Context(0), p, precision="f64", queue_capacity=cap)
+    with pytest.raises(frt.FrtError) as e:
+        frt.batch_run([g], [p.dt_s], steps, graph=True, check_every=steps)
+    assert e.value.code == frt.FRT_EOVERFLOW
+    Lg, Lp = g.ledger(), probe.ledger()
+    assert Lg["steps"] == Lp["steps"] == fail_at and Lg["err_flags"] == 0
+    assert np.abs(g.fields()[0] - probe.fields()[0]).max() <= 1e-12
+    for k in TERMS:
+        assert abs(Lg[k] - Lp[k]) <= 1e-12 * Lp["emitted"], k
+    assert Lg["n_in_flight"] == Lp["n_in_flight"]
 
 
 def test_graph_run_fixed_capacity_overflow_is_not_applied():
