@@ -8,11 +8,9 @@
 // group, driven by the worker thread).  A finished request's x_HI and ledger
 // are copied to host memory and its solve is destroyed, which frees its
 // share of the budget for the next arrivals.  The layer uses only the
-// public C ABI of the library.
+// public C ABI of the library and the host services of frt_serving.h.
 #include "frt.h"
-#include "frt_internal.h"
-
-#include <hip/hip_runtime.h>
+#include "frt_serving.h"
 
 #include <algorithm>
 #include <chrono>
@@ -30,8 +28,6 @@
 #include <vector>
 
 namespace {
-
-using Clock = std::chrono::steady_clock;
 
 struct Req {
     uint64_t id = 0;
@@ -72,7 +68,7 @@ int copy_in(const T* p, size_t n, int kind, std::vector<T>& out)
         std::memcpy(out.data(), p, n * sizeof(T));
         return FRT_OK;
     }
-    if (hipDeviceSynchronize() != hipSuccess || hipMemcpy(out.data(), p, n * sizeof(T), hipMemcpyDeviceToHost) != hipSuccess)
+    if (frt::copy_device_to_host(out.data(), p, n * sizeof(T)) != FRT_OK)
         return frt::set_error(FRT_EDEVICE, "copying a request's device input failed");
     return FRT_OK;
 }
@@ -95,7 +91,6 @@ int validate(const frt_request* r)
     return FRT_OK;
 }
 
-double seconds_since(Clock::time_point t0) { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 
 }  // namespace
 
@@ -104,7 +99,7 @@ struct frt_server_s {
     int device = 0;
     size_t budget = 0;
     int max_slots = 1;
-    Clock::time_point t0;
+    double t0 = 0.0;                  // frt::clock_s() at creation
     std::mutex mu;
     std::condition_variable cv;       // worker: work arrived, a solve loaded, or stop
     std::condition_variable load_cv;  // loader: a request was admitted, or stop
@@ -113,6 +108,7 @@ struct frt_server_s {
     std::deque<Req*> to_load;         // admitted, waiting for the loader
     std::vector<Req*> ready;          // loaded, joining the next tick
     int loading = 0;                  // admitted requests not yet in `active`
+    bool admit_check = false;         // a submission or freed bytes since the last admission pass
     std::unordered_map<uint64_t, std::unique_ptr<Req>> all;
     std::vector<Req*> active;         // worker thread only
     uint64_t next_id = 1;
@@ -140,12 +136,14 @@ struct frt_server_s {
     {
         std::lock_guard<std::mutex> lock(mu);
         r->state = state;
-        r->t_done = seconds_since(t0);
+        r->t_done = (frt::clock_s() - t0);
         resident_in_use -= r->resident;
         pass_in_use -= r->pass;
         update_bytes();
         if (state == FRT_REQ_DONE) st.completed++;
         else st.failed++;
+        admit_check = true;
+        cv.notify_all();
         done_cv.notify_all();
     }
 
@@ -178,7 +176,7 @@ struct frt_server_s {
 
     void run_loader()
     {
-        (void)hipSetDevice(device);
+        (void)frt::use_device(device);
         for (;;) {
             Req* r = nullptr;
             {
@@ -224,7 +222,7 @@ struct frt_server_s {
 
     void run()
     {
-        (void)hipSetDevice(device);
+        (void)frt::use_device(device);
         for (;;) {
             std::vector<Req*> joined;
             {
@@ -232,6 +230,7 @@ struct frt_server_s {
                 cv.wait(lock, [&] { return stop || !queue.empty() || !active.empty() || !ready.empty(); });
                 if (stop) break;
                 // admission in arrival order: a slot and the request's bytes
+                admit_check = false;
                 while (!queue.empty() && (int)active.size() + loading < max_slots) {
                     Req* r = queue.front();
                     if (r->resident + r->pass > budget) {
@@ -239,7 +238,7 @@ struct frt_server_s {
                         r->err = FRT_ENOMEM;
                         r->msg = "request needs more device memory than the server's whole budget";
                         r->state = FRT_REQ_FAILED;
-                        r->t_done = seconds_since(t0);
+                        r->t_done = (frt::clock_s() - t0);
                         r->free_inputs();
                         st.failed++;
                         done_cv.notify_all();
@@ -261,7 +260,7 @@ struct frt_server_s {
                     pass_in_use += r->pass;
                     update_bytes();
                     r->state = FRT_REQ_RUNNING;
-                    r->t_start = seconds_since(t0);
+                    r->t_start = (frt::clock_s() - t0);
                     to_load.push_back(r);
                     loading++;
                     load_cv.notify_all();
@@ -269,8 +268,10 @@ struct frt_server_s {
                 joined.swap(ready);
                 loading -= (int)joined.size();
                 if (active.empty() && joined.empty()) {
-                    // nothing to step yet: wait for a load (or a finish freeing room)
-                    cv.wait(lock, [&] { return stop || !ready.empty() || (loading == 0 && !queue.empty()); });
+                    // nothing to step yet: wait for a load, or for a submission
+                    // or freed bytes that may admit another request meanwhile
+                    // (its upload then overlaps the ones under way)
+                    cv.wait(lock, [&] { return stop || !ready.empty() || admit_check; });
                     if (stop) break;
                     continue;
                 }
@@ -392,13 +393,13 @@ int frt_server_create(frt_ctx ctx, size_t hbm_budget_bytes, int max_slots, frt_s
     if (max_slots < 1 || max_slots > FRT_MAX_SOLVES_PER_LAUNCH) return frt::set_error(FRT_EINVAL, "max_slots outside 1..1024");
     if (hbm_budget_bytes == 0) return frt::set_error(FRT_EINVAL, "zero memory budget");
     const int dev = frt::ctx_device(ctx);
-    if (hipSetDevice(dev) != hipSuccess) return frt::set_error(FRT_EDEVICE, "cannot select the context's device");
+    if (frt::use_device(dev) != FRT_OK) return frt::set_error(FRT_EDEVICE, "cannot select the context's device");
     std::unique_ptr<frt_server_s> s(new frt_server_s());
     s->ctx = ctx;
     s->device = dev;
     s->budget = hbm_budget_bytes;
     s->max_slots = max_slots;
-    s->t0 = Clock::now();
+    s->t0 = frt::clock_s();
     frt_server_s* raw = s.get();
     s->worker = std::thread([raw] { raw->run(); });
     // the host side of a load (input checks and conversions, pageable
@@ -441,11 +442,12 @@ int frt_server_submit(frt_server srv, const frt_request* req, uint64_t* req_id)
     r->pass = (size_t)pass_bytes;
     std::lock_guard<std::mutex> lock(srv->mu);
     r->id = srv->next_id++;
-    r->t_submit = seconds_since(srv->t0);
+    r->t_submit = (frt::clock_s() - srv->t0);
     *req_id = r->id;
     srv->queue.push_back(r.get());
     srv->all[r->id] = std::move(r);
     srv->st.submitted++;
+    srv->admit_check = true;
     srv->cv.notify_all();
     return FRT_OK;
 }
