@@ -537,7 +537,7 @@ def main():
     ap.add_argument("--no-merge", action="store_true", help="skip the ray-merging leg")
     ap.add_argument("--merge-steps", type=int, default=60)
     ap.add_argument("--no-served", action="store_true", help="skip the served (request trace) leg")
-    ap.add_argument("--served-requests", type=int, default=32)
+    ap.add_argument("--served-requests", type=int, default=128)
     ap.add_argument("--served-steps", type=int, default=50)
     ap.add_argument("--served-rate", type=float, default=4.0)
     ap.add_argument("--served-budget-gb", type=float, default=64.0)

@@ -172,7 +172,7 @@ def test_allocation_failure_inside_a_step_leaves_the_solve_at_its_start():
 
 
 def test_server_allocation_failure_fails_one_request():
-    reqs = W.served_c5(n_requests=4, n_steps=3, sizes=(24, 32), max_src=12, seed=64)
+    reqs = W.served_c5(n_requests=4, n_steps=3, sizes=(24, 32), max_src=20, seed=64)
     alloc = _FailingAllocator()
     ctx = frt.Context(0, allocator=alloc)
     srv = frt.Server(ctx, 8 << 30, 1)              # one slot: the requests load one after another
