@@ -54,6 +54,18 @@
  *                         photon-weighted positions, distances and levels,
  *                         the merging pixel's direction); merging with every
  *                         packet exempt changes nothing.
+ *   temperature_update    (§4.1, Eq. temp_evolution_standard) the Hubble
+ *                         term alone gives T0 e^(-2 H t); without heating
+ *                         or cooling n_tot T is kept as the gas ionizes; the
+ *                         thermal energy gained equals the photo-heating,
+ *                         which equals heat_ev times the photons HI absorbed
+ *                         (the photon ledger; per bin along one ray,
+ *                         exactly); the paper's Test 2 (front beyond the
+ *                         isothermal radius, ionized gas near 1e4 K).
+ *   orc_rates             alpha_B(1e4 K) is the paper's 2.59e-13; the other
+ *                         fits are those of the papers it cites (Hui &
+ *                         Gnedin 1997, Cen 1992), restated, and beyond the
+ *                         Test 2 check their values are parity unpinned.
  *   Whole-field values beyond these properties: parity unpinned (the paper
  *   prints no per-cell numbers).
  */
@@ -92,6 +104,13 @@ typedef struct {
     int merge;               /* 1: merge the carried packets at the end of each step (§3.3) */
     int merge_level;         /* l_merge: level of each cell's merging HEALPix sphere */
     double merge_exempt;     /* N_ex: floor(N_ex N_RT) brightest packets are exempt */
+    int temperature;         /* 1: T evolves (§4.1, Eq. temp_evolution_standard) and the
+                                recombination and collisional ionization rates follow it;
+                                0: alpha_B and coll_ion as given */
+    double heat_ev[ORC_MAX_BINS]; /* mean energy above 13.6 eV left in the gas per photon
+                                of each bin that HI absorbs, eV */
+    double hubble;           /* H(z) of the adiabatic cooling term, 1/s (0: none) */
+    double cmb_z;            /* redshift of the CMB for Compton cooling (< 0: none) */
 } orc_params;
 
 typedef struct {
@@ -103,6 +122,7 @@ typedef struct {
     double front_excess;     /* photons stopped at a front beyond the neutral atoms its
                                 cell had left (they ionize nothing); absorbed_front
                                 counts only the photons that ionized atoms */
+    double heat_in;          /* photo-heating energy given to the gas, erg (temperature on) */
 } orc_ledger;
 
 /* Photon totals are sums of up to ~1e9 terms; they are accumulated with
@@ -154,6 +174,7 @@ typedef struct {
     double* kappa;           /* sub-grid absorption coefficient, 1/cm */
     double* x;               /* neutral fraction x_HI */
     double* gamma;           /* last step's photo-ionization rate, 1/s */
+    double* T;               /* gas temperature, K (1e4 until set) */
     int nsrc;
     double* src_pos;         /* nsrc*3, cm */
     double* ndot;            /* nsrc*n_bins, photons/s */
@@ -348,6 +369,7 @@ typedef struct {
     const double* xion;      /* Generalized Opacity Mode: start-of-step ionized fraction */
     const double* kappa;     /* Generalized Opacity Mode: the ionized gas's absorption coefficient at sigma_0 */
     double* front;           /* this chunk's photons stopped at each cell's I-front */
+    double* heat;            /* this chunk's photo-heating per cell, eV (temperature on), or NULL */
 } march_ctx;
 
 /* March one ray from its current radius until it is absorbed below the floor,
@@ -360,7 +382,9 @@ typedef struct {
  * which equals N_in (1 - e^-tau)/(n_HI V dt) x (HI share of tau), i.e.
  * Eq. gamma_initial_standard when kappa = 0 and Eq. gamma_avg_subgrid with
  * lambda = 1/(n_HI sigma + kappa), and tends to Eq. gamma_initial_subgrid
- * as tau -> 0.
+ * as tau -> 0.  With the temperature on, each bin's photons absorbed by HI
+ * (the HI share of N_in - N_out) leave heat_ev of that bin each in the cell
+ * (photo-heating of Eq. temp_evolution_standard).
  *
  * Generalized Opacity Mode (§4.2): a cell is an ionized part of volume
  * fraction x_ion with absorption coefficient kappa_nu = kappa sigma_nu /
@@ -428,7 +452,7 @@ static void march_one_ray(march_ctx* M, orc_ray* ray)
         } else if (ds > 0.0) {
             long long i = c[0] + (long long)P->nx * (c[1] + (long long)P->ny * c[2]);
             double nhi = M->nHI[i], kap = M->S->kappa[i];
-            double g = 0.0;
+            double g = 0.0, heat = 0.0;
             for (int k = 0; k < nb; k++) {
                 double tau_h = nhi * P->sigma[k] * ds;
                 double tau = tau_h + kap * ds;
@@ -440,10 +464,12 @@ static void march_one_ray(march_ctx* M, orc_ray* ray)
                 if (tau > 0.0) {
                     csum_add(&M->L->absorbed_HI, dA * (tau_h / tau));
                     csum_add(&M->L->absorbed_sub, dA * ((kap * ds) / tau));
+                    heat += P->heat_ev[k] * dA * (tau_h / tau);
                 }
                 ray->N[k] = Nout;
             }
             M->gamma[i] += g * M->inv_vdt;
+            if (M->heat) M->heat[i] += heat;
             M->L->crossings++;
         }
         ray->r = r_end;
@@ -538,6 +564,95 @@ double chemistry_avg(double x0, double gamma, double ne, double alpha, double co
     const double xeq = alpha * ne / R;
     *x_end = xeq + (x0 - xeq) * exp(-y);
     return xeq + (x0 - xeq) * (-expm1(-y) / y);
+}
+
+/* ---------------------------------------------------------- temperature */
+/* Rates of pure hydrogen gas at temperature T (K) that the temperature
+ * evolution uses (§4.1 cites Hui & Gnedin 1997 for them), with
+ * lambda = 2 T_HI / T and T_HI = 157807 K:
+ *   [0] alpha_B, case-B recombination coefficient, cm^3/s
+ *       (Hui & Gnedin 1997 fit: 2.753e-14 lambda^1.5 / (1 + (lambda/2.740)^0.407)^2.242)
+ *   [1] C_HI, collisional ionization coefficient, cm^3/s
+ *       (21.11 T^-1.5 e^(-lambda/2) lambda^-1.089 / (1 + (lambda/0.354)^0.874)^1.101)
+ *   [2] case-B recombination cooling coefficient, erg cm^3/s (times n_e n_HII)
+ *       (3.435e-30 T lambda^1.970 / (1 + (lambda/2.250)^0.376)^3.720)
+ *   [3] collisional ionization cooling, erg cm^3/s (times n_e n_HI): the
+ *       ionization energy k T_HI per collisional ionization, k T_HI C_HI
+ *   [4] collisional excitation cooling, erg cm^3/s (times n_e n_HI)
+ *       (Cen 1992: 7.5e-19 e^(-118348/T) / (1 + (T/1e5)^0.5))
+ *   [5] free-free cooling, erg cm^3/s (times n_e n_HII)
+ *       (1.42e-27 g_ff T^0.5, g_ff = 1.1 + 0.34 exp(-(5.5 - log10 T)^2 / 3))
+ * Compton cooling off the CMB is 4 sigma_T a k T_CMB^4 (T - T_CMB) n_e /
+ * (m_e c) with T_CMB = 2.725 (1 + z) K. */
+#define ORC_T_HI 157807.0
+#define ORC_K_B 1.380649e-16
+#define ORC_EV 1.602176634e-12
+void orc_rates(double T, double* out)
+{
+    const double lam = 2.0 * ORC_T_HI / T;
+    out[0] = 2.753e-14 * pow(lam, 1.5) / pow(1.0 + pow(lam / 2.740, 0.407), 2.242);
+    out[1] = 21.11 * pow(T, -1.5) * exp(-0.5 * lam) * pow(lam, -1.089) / pow(1.0 + pow(lam / 0.354, 0.874), 1.101);
+    out[2] = 3.435e-30 * T * pow(lam, 1.970) / pow(1.0 + pow(lam / 2.250, 0.376), 3.720);
+    out[3] = ORC_K_B * ORC_T_HI * out[1];
+    out[4] = 7.5e-19 * exp(-118348.0 / T) / (1.0 + sqrt(T / 1e5));
+    const double lg = 5.5 - log10(T);
+    out[5] = 1.42e-27 * (1.1 + 0.34 * exp(-lg * lg / 3.0)) * sqrt(T);
+}
+
+static double compton_coefficient(void)
+{
+    const double sigma_T = 6.6524587321e-25, a_rad = 7.565733e-15, m_e = 9.1093837015e-28, c = 2.99792458e10;
+    const double T0 = 2.725;
+    return 4.0 * sigma_T * a_rad * ORC_K_B * T0 * T0 * T0 * T0 / (m_e * c);
+}
+
+/* Net heating minus cooling, erg/cm^3/s, of a cell with n_H, neutral
+ * fraction x and photo-heating h (erg/cm^3/s) at temperature T. */
+static double net_heating(const orc_params* P, double T, double nH, double x, double h)
+{
+    double r[6];
+    orc_rates(T, r);
+    const double nHI = nH * x, ne = nH * (1.0 - x), nHII = ne;
+    double L = r[2] * ne * nHII + (r[3] + r[4]) * ne * nHI + r[5] * ne * nHII;
+    if (P->cmb_z >= 0.0) {
+        const double z1 = 1.0 + P->cmb_z;
+        L += compton_coefficient() * z1 * z1 * z1 * z1 * (T - 2.725 * z1) * ne;
+    }
+    return h - L;
+}
+
+/* Temperature over one step (§4.1, Eq. temp_evolution_standard, static
+ * density: no compression term) once the neutral fraction went from x0 to
+ * x1, for pure H (n_tot = n_H (2 - x)), in three parts taken in turn:
+ *  - the particle-number term -T/n_tot dn_tot/dt, exactly: n_tot T is kept,
+ *    T -> T n_tot(x0) / n_tot(x1);
+ *  - the Hubble term -2 H T, exactly: T -> T e^(-2 H dt);
+ *  - heating minus cooling, dT/dt = 2 (H - Lambda(T)) / (3 k n_tot), with
+ *    the step's photo-heating H and x = x1, in sub-steps that change T by at
+ *    most a tenth, each the exact solution of the equation linearized about
+ *    its start (T += f (e^(f' h) - 1) / f', f' from a relative difference of
+ *    1e-6 in T), at most 4096 sub-steps, T >= 1 K.
+ * h_heat is the step's photo-heating, erg/cm^3/s. */
+double temperature_update(const orc_params* P, double T, double nH, double x0, double x1, double h_heat, double dt)
+{
+    const double nt0 = nH * (2.0 - x0), nt1 = nH * (2.0 - x1);
+    if (nt1 > 0.0) T *= nt0 / nt1;
+    if (P->hubble > 0.0) T *= exp(-2.0 * P->hubble * dt);
+    if (!(nt1 > 0.0)) return T;
+    const double cth = 2.0 / (3.0 * ORC_K_B * nt1);
+    double t = 0.0;
+    for (int k = 0; k < 4096 && t < dt; k++) {
+        const double f = cth * net_heating(P, T, nH, x1, h_heat);
+        const double Te = T * (1.0 + 1e-6);
+        const double fp = (cth * net_heating(P, Te, nH, x1, h_heat) - f) / (Te - T);
+        double h = dt - t;
+        if (fabs(f) * h > 0.1 * T) h = 0.1 * T / fabs(f);
+        const double y = fp * h;
+        T += (fabs(y) > 1e-8) ? f * expm1(y) / fp : f * h;
+        if (T < 1.0) T = 1.0;
+        t += h;
+    }
+    return T;
 }
 
 /* ------------------------------------------------------------- merging */
@@ -710,6 +825,7 @@ orc_state* orc_create(const orc_params* P, const float* nH, const float* kappa, 
 {
     if (!P || P->nx < 1 || P->ny < 1 || P->nz < 1 || P->n_bins < 1 || P->n_bins > ORC_MAX_BINS) return NULL;
     if (P->opacity_mode != 0 && P->opacity_mode != 1) return NULL;
+    if (P->temperature && P->opacity_mode != 0) return NULL;   /* Standard Mode only */
     orc_state* S = (orc_state*)calloc(1, sizeof(orc_state));
     if (!S) return NULL;
     S->p = *P;
@@ -719,14 +835,25 @@ orc_state* orc_create(const orc_params* P, const float* nH, const float* kappa, 
     S->kappa = (double*)malloc(sizeof(double) * S->ncell);
     S->x = (double*)malloc(sizeof(double) * S->ncell);
     S->gamma = (double*)calloc(S->ncell, sizeof(double));
-    if (!S->nH || !S->kappa || !S->x || !S->gamma) return NULL;
+    S->T = (double*)malloc(sizeof(double) * S->ncell);
+    if (!S->nH || !S->kappa || !S->x || !S->gamma || !S->T) return NULL;
     for (long long i = 0; i < S->ncell; i++) {
         S->nH[i] = nH[i];
         S->kappa[i] = kappa ? kappa[i] : 0.0;
         S->x[i] = x0 ? x0[i] : 1.0;
+        S->T[i] = 1e4;
     }
     return S;
 }
+
+/* Gas temperature of every cell, K (the state keeps it; it evolves when
+ * the temperature is on). */
+void orc_set_temperature(orc_state* S, const double* T)
+{
+    for (long long i = 0; i < S->ncell; i++) S->T[i] = T[i];
+}
+
+void orc_read_temperature(const orc_state* S, double* T) { memcpy(T, S->T, sizeof(double) * S->ncell); }
 
 /* New absorption-coefficient field, the rest of the state kept (the caller's
  * opacity model between steps, §4.2 Eq. lambda_nu_general). */
@@ -739,7 +866,7 @@ void orc_destroy(orc_state* S)
 {
     if (!S) return;
     free(S->carried.v);
-    free(S->nH); free(S->kappa); free(S->x); free(S->gamma);
+    free(S->nH); free(S->kappa); free(S->x); free(S->gamma); free(S->T);
     free(S->src_pos); free(S->ndot);
     free(S);
 }
@@ -812,6 +939,26 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
             kap[i] = S->kappa[i];
         }
     }
+    double* hk = NULL;    /* per-chunk photo-heating, eV per cell (temperature on) */
+    if (P->temperature) {
+        hk = (double*)calloc((size_t)K * N, sizeof(double));
+        if (!hk) return -1;
+    }
+    /* the rates of the step, at its starting temperature */
+    double* alpha_c = (double*)malloc(sizeof(double) * N);
+    double* coll_c = (double*)malloc(sizeof(double) * N);
+    if (!alpha_c || !coll_c) return -1;
+    for (long long i = 0; i < N; i++) {
+        if (P->temperature) {
+            double r[6];
+            orc_rates(S->T[i], r);
+            alpha_c[i] = r[0];
+            coll_c[i] = r[1];
+        } else {
+            alpha_c[i] = P->alpha_B;
+            coll_c[i] = P->coll_ion;
+        }
+    }
     double* xavg = NULL;
     if (P->chem_iterations > 0 && !gen) {
         xavg = (double*)malloc(sizeof(double) * N);
@@ -838,6 +985,7 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
             /* the march starts again from the step's packets */
             memset(gk, 0, sizeof(double) * (size_t)K * N);
             if (gen) memset(fk, 0, sizeof(double) * (size_t)K * N);
+            if (hk) memset(hk, 0, sizeof(double) * (size_t)K * N);
             memset(Lk, 0, sizeof(chunk_ledger) * K);
             for (int k = 0; k < K; k++) {
                 free(new_flight[k].v);
@@ -852,6 +1000,7 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
             M.S = S; M.nHI = nHI; M.gamma = gk + (size_t)k * N; M.L = Lk + k;
             M.stack = &stack; M.inv_vdt = 1.0 / (V * dt);
             M.xion = xion; M.front = gen ? fk + (size_t)k * N : NULL; M.kappa = kap;
+            M.heat = hk ? hk + (size_t)k * N : NULL;
             M.flight_out = &new_flight[k];
             /* packets carried from the previous step get a fresh budget */
             const long long nc = S->carried.n;
@@ -898,7 +1047,7 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
             for (long long i = 0; i < N; i++) {
                 double xe;
                 const double ne = S->nH[i] * (1.0 - xavg[i]);
-                xavg[i] = chemistry_avg(S->x[i], S->gamma[i], ne, P->alpha_B, P->coll_ion, dt, &xe);
+                xavg[i] = chemistry_avg(S->x[i], S->gamma[i], ne, alpha_c[i], coll_c[i], dt, &xe);
             }
     }
 
@@ -975,20 +1124,33 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
         S->L.absorbed_front -= ex;
         S->L.front_excess += ex;
         free(xion); free(fk); free(kap);
-    } else if (xavg) {
-        for (long long i = 0; i < N; i++) {
-            double xe;
-            const double ne = S->nH[i] * (1.0 - xavg[i]);
-            (void)chemistry_avg(S->x[i], S->gamma[i], ne, P->alpha_B, P->coll_ion, dt, &xe);
-            S->x[i] = xe;
-        }
-        free(xavg);
     } else {
-        for (long long i = 0; i < N; i++)
-            S->x[i] = chemistry_be(S->x[i], S->gamma[i], S->nH[i], P->alpha_B, P->coll_ion, dt);
+        /* the hydrogen update, then (temperature on) the temperature from
+         * the step's photo-heating with the new neutral fraction */
+        csum heat_in = {S->L.heat_in, 0.0};
+        for (long long i = 0; i < N; i++) {
+            const double x0 = S->x[i];
+            if (xavg) {
+                double xe;
+                const double ne = S->nH[i] * (1.0 - xavg[i]);
+                (void)chemistry_avg(x0, S->gamma[i], ne, alpha_c[i], coll_c[i], dt, &xe);
+                S->x[i] = xe;
+            } else {
+                S->x[i] = chemistry_be(x0, S->gamma[i], S->nH[i], alpha_c[i], coll_c[i], dt);
+            }
+            if (hk) {
+                double e = 0.0;
+                for (int k = 0; k < K; k++) e += hk[(size_t)k * N + i];
+                csum_add(&heat_in, e * ORC_EV);
+                S->T[i] = temperature_update(P, S->T[i], S->nH[i], x0, S->x[i], e * ORC_EV / (V * dt), dt);
+            }
+        }
+        S->L.heat_in = csum_get(&heat_in);
+        free(xavg);
     }
 
     S->step++;
+    free(hk); free(alpha_c); free(coll_c);
     free(nHI); free(gk); free(Lk); free(new_flight);
     return 0;
 }
@@ -996,7 +1158,7 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
 /* Per-bin transmitted photons of one ray through the current field (no
  * floor, no cap, no split), for the exact exp(-tau) test. */
 int orc_debug_transmit(orc_state* S, const double o[3], const double d[3], const double* N, double dt,
-                       double* gamma_out, double* N_exit)
+                       double* gamma_out, double* N_exit, double* heat_out)
 {
     const orc_params* P = &S->p;
     if (P->opacity_mode != 0) return -1;   /* Standard Mode only */
@@ -1017,7 +1179,7 @@ int orc_debug_transmit(orc_state* S, const double o[3], const double d[3], const
     march_ctx M;
     M.S = &T; M.nHI = nHI; M.gamma = gamma_out; M.L = &L; M.stack = &stack; M.flight_out = &fl;
     M.inv_vdt = 1.0 / (P->dx * P->dx * P->dx * dt);
-    M.xion = NULL; M.front = NULL; M.kappa = NULL;
+    M.xion = NULL; M.front = NULL; M.kappa = NULL; M.heat = heat_out;
     orc_ray ray;
     memset(&ray, 0, sizeof(ray));
     for (int a = 0; a < 3; a++) {
@@ -1099,11 +1261,11 @@ long long orc_last_crossings(const orc_state* S) { return S->last_crossings; }
 long long orc_step_index(const orc_state* S) { return S->step; }
 
 /* Checkpoint: neutral fraction, the last step's rate (the first guess of
- * the equilibrium iteration of the Generalized Opacity Mode), carried
- * packets, ledger, step index. */
+ * the equilibrium iteration of the Generalized Opacity Mode), temperature,
+ * carried packets, ledger, step index. */
 long long orc_state_bytes(const orc_state* S)
 {
-    return (long long)(sizeof(long long) * 3 + sizeof(orc_ledger) + 2 * sizeof(double) * S->ncell +
+    return (long long)(sizeof(long long) * 3 + sizeof(orc_ledger) + 3 * sizeof(double) * S->ncell +
                        sizeof(orc_ray) * S->carried.n);
 }
 
@@ -1115,6 +1277,7 @@ int orc_save(const orc_state* S, unsigned char* buf)
     memcpy(p, &S->L, sizeof(orc_ledger)); p += sizeof(orc_ledger);
     memcpy(p, S->x, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
     memcpy(p, S->gamma, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
+    memcpy(p, S->T, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
     long long n = S->carried.n;
     memcpy(p, &n, sizeof(n)); p += sizeof(n);
     if (n > 0) memcpy(p, S->carried.v, sizeof(orc_ray) * n);
@@ -1131,6 +1294,7 @@ int orc_load(orc_state* S, const unsigned char* buf)
     memcpy(&S->L, p, sizeof(orc_ledger)); p += sizeof(orc_ledger);
     memcpy(S->x, p, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
     memcpy(S->gamma, p, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
+    memcpy(S->T, p, sizeof(double) * S->ncell); p += sizeof(double) * S->ncell;
     long long n;
     memcpy(&n, p, sizeof(n)); p += sizeof(n);
     free(S->carried.v);

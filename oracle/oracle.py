@@ -44,7 +44,8 @@ class Params(C.Structure):
                 ("flux_floor", C.c_double), ("max_dist", C.c_double), ("c_ray", C.c_double),
                 ("n_chunks", C.c_int), ("chem_iterations", C.c_int), ("opacity_mode", C.c_int),
                 ("he_chi", C.c_double), ("merge", C.c_int), ("merge_level", C.c_int),
-                ("merge_exempt", C.c_double)]
+                ("merge_exempt", C.c_double), ("temperature", C.c_int), ("heat_ev", C.c_double * MAX_BINS),
+                ("hubble", C.c_double), ("cmb_z", C.c_double)]
 
 
 class Ledger(C.Structure):
@@ -53,7 +54,7 @@ class Ledger(C.Structure):
                 ("crossings", C.c_longlong), ("rays_emitted", C.c_longlong), ("splits", C.c_longlong),
                 ("n_escaped", C.c_longlong), ("n_dropped", C.c_longlong), ("n_in_flight", C.c_longlong),
                 ("absorbed_front", C.c_double), ("merge_residual", C.c_double), ("merges", C.c_longlong),
-                ("rays_merged", C.c_longlong), ("front_excess", C.c_double)]
+                ("rays_merged", C.c_longlong), ("front_excess", C.c_double), ("heat_in", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -101,7 +102,13 @@ def lib():
         L.orc_flight_radii.argtypes = [C.c_void_p, C.c_void_p, C.c_longlong]
         L.orc_chemistry_field.argtypes = [C.c_longlong, dp, dp, dp, C.c_double, C.c_double, C.c_double, dp]
         L.orc_debug_transmit.restype = C.c_int
-        L.orc_debug_transmit.argtypes = [C.c_void_p, dp, dp, dp, C.c_double, dp, dp]
+        L.orc_debug_transmit.argtypes = [C.c_void_p, dp, dp, dp, C.c_double, dp, dp, C.c_void_p]
+        L.orc_rates.argtypes = [C.c_double, dp]
+        L.orc_set_temperature.argtypes = [C.c_void_p, dp]
+        L.orc_read_temperature.argtypes = [C.c_void_p, dp]
+        L.temperature_update.restype = C.c_double
+        L.temperature_update.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double, C.c_double,
+                                         C.c_double, C.c_double]
         _lib = L
     return _lib
 
@@ -153,6 +160,14 @@ def chemistry_avg(x0, gamma, ne, alpha, coll, dt):
     return float(xa), float(xe.value)
 
 
+def rates(T: float) -> dict:
+    """The temperature-dependent rates of pure H at T (K): alpha_B and C_HI
+    (cm^3/s) and the cooling coefficients (erg cm^3/s)."""
+    out = np.zeros(6)
+    lib().orc_rates(float(T), out)
+    return dict(zip(("alpha_B", "coll_ion", "rec_cool", "ci_cool", "ce_cool", "ff_cool"), out))
+
+
 # ------------------------------------------------------------- the solver
 class Oracle:
     """One RT problem on the CPU: grid, sources, carried packets, ledger."""
@@ -160,7 +175,8 @@ class Oracle:
     def __init__(self, shape, dx_cm, sigma_bins, alpha_B, n_H, kappa=None, x_HI0=None,
                  coll_ion=0.0, base_level=0, max_level=12, n_ray_min=1.0, flux_floor=0.0,
                  max_dist_cm=0.0, c_ray=np.inf, n_chunks=16, chem_iterations=0, opacity_mode=0, he_chi=0.0,
-                 merge=False, merge_level=0, merge_exempt=0.0):
+                 merge=False, merge_level=0, merge_exempt=0.0, temperature=False, heat_ev=None, hubble_s=0.0,
+                 cmb_z=-1.0, T0=None):
         nz, ny, nx = shape
         sig = list(sigma_bins)
         P = Params()
@@ -174,6 +190,9 @@ class Oracle:
         P.chem_iterations = chem_iterations
         P.opacity_mode, P.he_chi = opacity_mode, he_chi
         P.merge, P.merge_level, P.merge_exempt = int(bool(merge)), merge_level, merge_exempt
+        P.temperature, P.hubble, P.cmb_z = int(bool(temperature)), hubble_s, cmb_z
+        for i, e in enumerate(heat_ev if heat_ev is not None else []):
+            P.heat_ev[i] = e
         self.P = P
         self.shape = (nz, ny, nx)
         self.ncell = nx * ny * nz
@@ -188,6 +207,17 @@ class Oracle:
         if not self.h:
             raise ValueError("oracle: invalid parameters")
         self.n_src = 0
+        if T0 is not None:
+            self.set_temperature(T0)
+
+    def set_temperature(self, T):
+        t = np.ascontiguousarray(np.broadcast_to(np.asarray(T, dtype=np.float64), self.shape)).reshape(-1)
+        lib().orc_set_temperature(self.h, t)
+
+    def temperature(self):
+        t = np.empty(self.ncell)
+        lib().orc_read_temperature(self.h, t)
+        return t.reshape(self.shape)
 
     def close(self):
         if getattr(self, "h", None):
@@ -278,13 +308,19 @@ class Oracle:
         if lib().orc_load(self.h, buf) != 0:
             raise ValueError("oracle: state does not match this problem")
 
-    def transmit(self, origin_cm, direction, N_bins, dt_s=1.0):
+    def transmit(self, origin_cm, direction, N_bins, dt_s=1.0, heat=False):
         """March one ray (no split, floor or cap) through the current field.
-        Returns (photons left per bin when it leaves the box, Gamma field, crossings)."""
+        Returns (photons left per bin when it leaves the box, Gamma field,
+        crossings), and with heat=True also the photo-heating field (eV per
+        cell, heat_ev per photon of each bin that HI absorbs)."""
         g = np.zeros(self.ncell)
         out = np.zeros(MAX_BINS)
         N = np.zeros(MAX_BINS)
         N[: self.n_bins] = N_bins
+        h = np.zeros(self.ncell) if heat else None
         nc = lib().orc_debug_transmit(self.h, np.ascontiguousarray(origin_cm, dtype=np.float64),
-                                      np.ascontiguousarray(direction, dtype=np.float64), N, dt_s, g, out)
+                                      np.ascontiguousarray(direction, dtype=np.float64), N, dt_s, g, out,
+                                      None if h is None else h.ctypes.data)
+        if heat:
+            return out[: self.n_bins], g.reshape(self.shape), nc, h.reshape(self.shape)
         return out[: self.n_bins], g.reshape(self.shape), nc

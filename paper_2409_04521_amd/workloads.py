@@ -111,6 +111,22 @@ def blackbody_bins(n_bins: int, T_bb: float = 5e4, e_lo: float = E_HI, e_hi: flo
     return w / w.sum(), s
 
 
+def blackbody_heat(n_bins: int, T_bb: float = 5e4, e_lo: float = E_HI, e_hi: float = 4 * E_HI) -> np.ndarray:
+    """Mean energy above 13.6 eV (eV) of the photons HI absorbs in each bin
+    of blackbody_bins (absorption-weighted: n(E) sigma(E) over the bin)."""
+    from scipy.integrate import quad
+
+    kT = K_B * T_bb / EV
+    edges = e_lo * (e_hi / e_lo) ** (np.arange(n_bins + 1) / n_bins)
+    absorbed = lambda e: e * e / math.expm1(e / kT) * (e / E_HI) ** (-SIGMA_SLOPE)
+    out = np.empty(n_bins)
+    for i in range(n_bins):
+        a, b = edges[i], edges[i + 1]
+        out[i] = (quad(lambda e: absorbed(e) * (e - E_HI), a, b, epsabs=0, epsrel=1e-12)[0]
+                  / quad(absorbed, a, b, epsabs=0, epsrel=1e-12)[0])
+    return out
+
+
 # -------------------------------------------------------------- fields
 def lognormal_white(rng, shape, mean: float, ln_sigma: float) -> np.ndarray:
     """Mean-preserving white lognormal field: mean * exp(s g - s^2/2)."""
