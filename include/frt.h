@@ -143,6 +143,28 @@ typedef struct {
                                        (nothing with c_ray = +INFINITY) */
     int merge_level;                /* l_merge, 0..8 (default 0) */
     double merge_exempt;            /* N_ex, exempt packets per cell, >= 0 (default 4) */
+    int temperature;                /* 1: the gas temperature evolves (§4.1, Eq.
+                                       temp_evolution_standard, static density; Standard Mode
+                                       only): each bin's photons absorbed by HI (not by the
+                                       sub-grid absorbers) leave heat_ev of the bin each in the
+                                       cell; the hydrogen update takes case-B recombination and
+                                       collisional ionization at the cell's temperature of the
+                                       start of the step (Hui & Gnedin 1997) instead of alpha_B
+                                       and coll_ion; after it, T keeps n_tot T as the particle
+                                       number n_tot = n_H (2 - x_HI) changes, cools by e^(-2 H dt)
+                                       with hubble_s, and follows photo-heating minus recombination,
+                                       collisional ionization and excitation, free-free and (with
+                                       cmb_z >= 0) Compton cooling over the step, in sub-steps of at
+                                       most a tenth change in T, each solved exactly for the
+                                       equation linearized about its start.  With chem_iterations K
+                                       only the last march's heating counts.  A solve with the
+                                       temperature on marches with 16^3 bricks in FP32.
+                                       0 (default): T fixed */
+    double heat_ev[FRT_MAX_BINS];   /* energy above 13.6 eV left in the gas per photon of each
+                                       bin that HI absorbs, eV (finite, >= 0) */
+    double hubble_s;                /* H(z) of the adiabatic term, 1/s (finite, >= 0; default 0) */
+    double cmb_z;                   /* redshift of the CMB for Compton cooling; < 0: none
+                                       (default -1) */
 } frt_params;
 
 /* Cumulative photon ledger (photons) and counters of one solve.  With
@@ -166,6 +188,7 @@ typedef struct {
     double front_excess;            /* photons stopped at I-fronts beyond the neutral atoms their
                                        cells had left; they ionize nothing (absorbed_front counts
                                        the photons that did) */
+    double heat_in;                 /* photo-heating given to the gas, erg (temperature on) */
 } frt_ledger;
 
 /* Fill *p with defaults: 1 bin at 6.3e-18 cm^2, alpha_B = 2.59e-13,
@@ -204,8 +227,9 @@ int frt_solve_destroy(frt_solve s);
 
 /* Load the grid (§4.1 Standard Mode state, §4.2 sub-grid opacity):
  * nx,ny,nz in 1..2048; box_cm > 0 is the x extent (cells are cubes);
- * n_H [ncell] cm^-3 (finite, >= 0); T [ncell] K is stored for the caller
- * and unused while T is fixed (may be NULL); kappa_sub [ncell] 1/cm
+ * n_H [ncell] cm^-3 (finite, >= 0); T [ncell] K (finite, > 0; may be
+ * NULL): with the temperature on, the starting temperature (NULL: 1e4 K),
+ * else stored for the caller and unused; kappa_sub [ncell] 1/cm
  * (finite, >= 0; NULL = 0); x_HI0 [ncell] in [0,1] (NULL = 1).  With
  * opacity_mode FRT_GENERALIZED, kappa_sub is the absorption coefficient of
  * each cell's ionized gas at sigma_0 and x_HI0 is 1 - its ionized volume
@@ -334,6 +358,12 @@ int frt_read_fields(frt_solve s, double* x_HI, float* gamma, int ptr_kind);
 
 /* Copy out the ledger.  Synchronizes. */
 int frt_read_ledger(frt_solve s, frt_ledger* out);
+
+/* Copy out the gas temperature T [ncell] (double, K; §4.1 Eq.
+ * temp_evolution_standard) to host or device memory (ptr_kind).  FRT_ESTATE
+ * when the solve holds no temperature (none loaded and the temperature off).
+ * Synchronizes. */
+int frt_read_temperature(frt_solve s, double* T, int ptr_kind);
 
 /* Checkpoint: x_HI, carried packets, ledger, step index and rotation state.
  * With buf == NULL, *bytes receives the size needed. */

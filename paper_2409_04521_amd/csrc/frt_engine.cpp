@@ -283,7 +283,9 @@ struct frt_solve_s {
     double* xavg = nullptr;                  // time-averaged chemistry only
     double* front = nullptr;                 // Generalized Opacity Mode only
     double* nH = nullptr;
-    float* T = nullptr;
+    double* T = nullptr;                     // temperature (loaded, or evolving), K
+    void* heat = nullptr;                    // this step's photo-heating, eV (temperature on)
+    double* mark_T = nullptr;                // bookmark of T (temperature on)
     double* src_pos = nullptr;
     float* spec = nullptr;
     double* specd = nullptr;
@@ -348,6 +350,8 @@ struct frt_solve_s {
         free_recs(mark_F);
         dev_free(vt[0]); dev_free(vt[1]); dev_free(vcount); dev_free(w0_merged); dev_free(mark_vt);
         dev_free(mark_x);
+        dev_free(heat);
+        dev_free(mark_T);
         dev_free(mark_fc);
         dev_free(d_desc); dev_free(op); dev_free(gam[0]); dev_free(gam[1]); dev_free(x); dev_free(xavg); dev_free(front);
         dev_free(kin); dev_free(mark_g);
@@ -435,6 +439,8 @@ void set_step_fields(frt_solve s, double dt)
     h.dt = dt;
     h.budget = std::isfinite(s->P.c_ray_cm_s) ? s->P.c_ray_cm_s * dt / s->dx : HUGE_VAL;
     h.w0_cast = dt / (double)(12ull << (2 * s->P.base_level));
+    // photo-heating rate (erg/cm^3/s) per eV left in a cell during the step
+    h.heat_scale = 1.602176634e-12 / (s->dx * s->dx * s->dx * dt);
     // a packet holds at most w0 photons per bin (the rates are scaled to at
     // most 1), and no packet's w0 exceeds the largest cast weight so far
     s->w0_max = std::max(s->w0_max, h.w0_cast);
@@ -659,7 +665,11 @@ void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
     w.n_solves = n;
     w.n_bins = ss[0]->P.n_bins;
     w.has_sub = 0;
-    for (int i = 0; i < n; i++) w.has_sub |= ss[i]->h.has_sub;
+    w.has_heat = 0;
+    for (int i = 0; i < n; i++) {
+        w.has_sub |= ss[i]->h.has_sub;
+        w.has_heat |= ss[i]->h.temp;
+    }
     // the 1024-thread march (FP32 without sub-grid opacity) takes
     // FRT_BIG_ITEM_SCALE times the tuned item size
     w.item_rays = (uint32_t)ws.tune.item_rays * ((!ss[0]->fp64 && !w.has_sub) ? FRT_BIG_ITEM_SCALE : 1u);
@@ -791,6 +801,7 @@ int restore_step_start(frt_solve* ss, int n, hipStream_t st)
         HIPCHK(hipMemcpyAsync(s->fcount, s->fcount_snap, 8, hipMemcpyDeviceToDevice, st));
         HIPCHK(hipMemsetAsync(s->gam[s->step & 1u], 0, s->ncell * s->rs, st));
         if (s->front) HIPCHK(hipMemsetAsync(s->front, 0, s->ncell * 8, st));
+        if (s->heat) HIPCHK(hipMemsetAsync(s->heat, 0, s->ncell * s->rs, st));
     }
     HIPCHK(hipStreamSynchronize(st));
     return FRT_OK;
@@ -1146,13 +1157,14 @@ int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps,
     uint32_t nkeys = 0;
     uint64_t want_p = 0;
     RCCHK(group_sizes(ss, n, &nkeys, &want_p));
-    int has_sub = 0;
+    int has_sub = 0, has_heat = 0;
     for (int i = 0; i < n; i++) {
         // rotations of every step of the run exist before the capture
         RCCHK(ensure_quat(ss[i], ss[i]->step + (uint32_t)n_steps));
         has_sub |= ss[i]->h.has_sub;
+        has_heat |= ss[i]->h.temp;
     }
-    frt::prime_launch_shapes(ss[0]->fp64, ss[0]->P.n_bins, has_sub);
+    frt::prime_launch_shapes(ss[0]->fp64, ss[0]->P.n_bins, has_sub, has_heat);
     StepGraph sg;
     Group g;
     int done = 0, retries = 0;
@@ -1214,6 +1226,7 @@ int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps,
 // Device copy of everything a step changes in a solve, for the autotuner.
 struct SolveSnap {
     double* x = nullptr;
+    double* T = nullptr;
     void* gam_last = nullptr;
     FrtRecs F{};
     FrtLedgerDev* L = nullptr;
@@ -1222,6 +1235,7 @@ struct SolveSnap {
     void release()
     {
         dev_free(x);
+        dev_free(T);
         dev_free(gam_last);
         free_recs(F);
         dev_free(L);
@@ -1239,6 +1253,10 @@ int snap_take(frt_solve s, SolveSnap& p)
     RCCHK(dev_alloc((void**)&p.L, sizeof(FrtLedgerDev)));
     RCCHK(alloc_recs(p.F, std::max<uint32_t>(nc, 1), s->P.n_bins, s->rs));
     HIPCHK(hipMemcpyAsync(p.x, s->x, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
+    if (s->h.temp) {
+        RCCHK(dev_alloc((void**)&p.T, s->ncell * 8));
+        HIPCHK(hipMemcpyAsync(p.T, s->T, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
+    }
     HIPCHK(hipMemcpyAsync(p.gam_last, s->gam[cur ^ 1], s->ncell * s->rs, hipMemcpyDeviceToDevice, s->stream));
     HIPCHK(hipMemcpyAsync(p.L, s->L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, s->stream));
     RCCHK(copy_recs(p.F, s->F[cur], nc, s->P.n_bins, s->rs, s->stream, hipMemcpyDeviceToDevice));
@@ -1256,6 +1274,8 @@ int snap_restore(frt_solve s, const SolveSnap& p)
     HIPCHK(hipMemcpyAsync(s->gam[cur ^ 1], p.gam_last, s->ncell * s->rs, hipMemcpyDeviceToDevice, s->stream));
     HIPCHK(hipMemsetAsync(s->gam[cur], 0, s->ncell * s->rs, s->stream));
     if (s->front) HIPCHK(hipMemsetAsync(s->front, 0, s->ncell * 8, s->stream));
+    if (p.T) HIPCHK(hipMemcpyAsync(s->T, p.T, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
+    if (s->heat) HIPCHK(hipMemsetAsync(s->heat, 0, s->ncell * s->rs, s->stream));
     HIPCHK(hipMemcpyAsync(s->L, p.L, sizeof(FrtLedgerDev), hipMemcpyDeviceToDevice, s->stream));
     RCCHK(copy_recs(s->F[cur], p.F, nc, s->P.n_bins, s->rs, s->stream, hipMemcpyDeviceToDevice));
     HIPCHK(hipMemcpyAsync(s->fcount, p.fc, 8, hipMemcpyHostToDevice, s->stream));
@@ -1335,6 +1355,7 @@ int debug_cast_locked(frt_solve s, const double o_cm[3], const double d_in[3], c
     t->P.chem_iterations = 0;
     t->P.queue_capacity = 0;
     t->P.merge = 0;
+    t->P.temperature = 0;
     t->fp64 = s->fp64;
     t->rs = s->rs;
     for (int a = 0; a < 3; a++) t->bsh[a] = s->bsh[a];
@@ -1345,6 +1366,10 @@ int debug_cast_locked(frt_solve s, const double o_cm[3], const double d_in[3], c
     t->ncell = s->ncell;
     t->n_src = 1;
     t->h = s->h;
+    // the solve's temperature and heating stay as they are
+    t->h.temp = 0;
+    t->h.T = nullptr;
+    t->h.heat = nullptr;
     RCCHK(dev_alloc((void**)&t->d_desc, sizeof(FrtSolveDesc)));
     RCCHK(dev_alloc((void**)&t->fcount, 8));
     RCCHK(dev_alloc((void**)&t->fcount_snap, 8));
@@ -1514,9 +1539,10 @@ uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T,
     const uint64_t rec = rec_bytes(rs);
     const uint64_t cast = (uint64_t)n_src * (12ull << (2 * P.base_level));
     // resident fields: opacity pair, two rate buffers, x_HI, n_H, T, <x> of
-    // the time-averaged chemistry, front photons of the Generalized Opacity Mode
-    uint64_t b = ncell * (4 * rs + 16 + (with_T ? 4 : 0) + (P.chem_iterations > 0 ? 8 : 0) +
-                          (P.opacity_mode == FRT_GENERALIZED ? 8 : 0));
+    // the time-averaged chemistry, front photons of the Generalized Opacity
+    // Mode, photo-heating of the temperature evolution
+    uint64_t b = ncell * (4 * rs + 16 + ((with_T || P.temperature) ? 8 : 0) + (P.chem_iterations > 0 ? 8 : 0) +
+                          (P.opacity_mode == FRT_GENERALIZED ? 8 : 0) + (P.temperature ? rs : 0));
     // carried-packet queues (as first sized)
     double F = (double)cast + 1024;
     if (std::isfinite(P.c_ray_cm_s)) F += std::min((double)ncell, 8.0 * cast + 65536.0);
@@ -1585,6 +1611,9 @@ int frt_params_default(frt_params* p)
     p->merge = 0;
     p->merge_level = 0;
     p->merge_exempt = 4.0;
+    p->temperature = 0;
+    p->hubble_s = 0.0;
+    p->cmb_z = -1.0;
     return FRT_OK;
 }
 
@@ -1642,6 +1671,13 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     if (P->merge != 0 && P->merge != 1) return fail(FRT_EINVAL, "merge must be 0 or 1");
     if (P->merge_level < 0 || P->merge_level > 8) return fail(FRT_EINVAL, "merge_level %d outside 0..8", P->merge_level);
     if (!(P->merge_exempt >= 0) || !std::isfinite(P->merge_exempt)) return fail(FRT_EINVAL, "merge_exempt must be finite and >= 0");
+    if (P->temperature != 0 && P->temperature != 1) return fail(FRT_EINVAL, "temperature must be 0 or 1");
+    if (P->temperature && P->opacity_mode != FRT_STANDARD)
+        return fail(FRT_EINVAL, "temperature evolution is for the Standard Mode only");
+    for (int b = 0; b < P->n_bins; b++)
+        if (!(P->heat_ev[b] >= 0) || !std::isfinite(P->heat_ev[b])) return fail(FRT_EINVAL, "heat_ev[%d] must be finite and >= 0", b);
+    if (!(P->hubble_s >= 0) || !std::isfinite(P->hubble_s)) return fail(FRT_EINVAL, "hubble_s must be finite and >= 0");
+    if (!std::isfinite(P->cmb_z)) return fail(FRT_EINVAL, "cmb_z must be finite");
     AllocScope scope(&ctx->al);
     HIPCHK(hipSetDevice(ctx->device));
     frt_solve s = new (std::nothrow) frt_solve_s;
@@ -1745,7 +1781,13 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
         for (size_t i = 0; i < n; i++)
             if (!(hx[i] >= 0.0 && hx[i] <= 1.0)) return fail(FRT_EINVAL, "x_HI0[%zu] = %g outside [0,1]", i, hx[i]);
     }
-    if (T) RCCHK(host_view(T, n, kind, bT, &hT));
+    if (T) {
+        RCCHK(host_view(T, n, kind, bT, &hT));
+        for (size_t i = 0; i < n; i++)
+            if (!(hT[i] > 0.f) || !std::isfinite(hT[i])) return fail(FRT_EINVAL, "T[%zu] = %g is not finite and > 0", i, (double)hT[i]);
+    }
+    const bool temp = s->P.temperature != 0;
+    dev_free(s->heat); dev_free(s->mark_T);
     dev_free(s->op); dev_free(s->gam[0]); dev_free(s->gam[1]); dev_free(s->x); dev_free(s->xavg);
     dev_free(s->front); dev_free(s->nH); dev_free(s->T); dev_free(s->kin); dev_free(s->mark_g);
     const bool gen = s->P.opacity_mode == FRT_GENERALIZED;
@@ -1756,14 +1798,16 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     if (s->P.chem_iterations > 0) RCCHK(dev_alloc((void**)&s->xavg, n * 8));
     if (gen) RCCHK(dev_alloc((void**)&s->front, n * 8));
     RCCHK(dev_alloc((void**)&s->nH, n * 8));
-    if (T) RCCHK(dev_alloc((void**)&s->T, n * 4));
+    if (T || temp) RCCHK(dev_alloc((void**)&s->T, n * 8));
+    if (temp) RCCHK(dev_alloc(&s->heat, n * s->rs));
     s->nx = nx; s->ny = ny; s->nz = nz;
     s->ncell = n;
     s->dx = box_cm / nx;
     // brick shape: 8^3 in FP64; in FP32 16^3 with sub-grid opacity (and in
-    // the Generalized Opacity Mode, which stages the same pairs), else
+    // the Generalized Opacity Mode, which stages the same pairs, and with the
+    // temperature on, whose heating march uses that layout), else
     // 32 x 16 x 16 (the 1024-thread march)
-    const bool any_kappa = gen || (hk && std::any_of(hk, hk + n, [](float v) { return v > 0.f; }));
+    const bool any_kappa = gen || temp || (hk && std::any_of(hk, hk + n, [](float v) { return v > 0.f; }));
     const int* lg = s->fp64 ? FRT_BRICK_LOG_F64 : (any_kappa ? FRT_BRICK_LOG_SUB : FRT_BRICK_LOG_BIG);
     for (int a = 0; a < 3; a++) s->bsh[a] = lg[a];
     s->bpx = (nx + (1 << s->bsh[0]) - 1) >> s->bsh[0];
@@ -1800,7 +1844,13 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     }
     RCCHK(scopy(s, s->nH, nHd.data(), n * 8, hipMemcpyHostToDevice));
     RCCHK(scopy(s, s->x, xd.data(), n * 8, hipMemcpyHostToDevice));
-    if (T) RCCHK(scopy(s, s->T, hT, n * 4, hipMemcpyHostToDevice));
+    if (T || temp) {
+        std::vector<double> Td(n, 1e4);
+        if (hT)
+            for (size_t i = 0; i < n; i++) Td[i] = (double)hT[i];
+        RCCHK(scopy(s, s->T, Td.data(), n * 8, hipMemcpyHostToDevice));
+    }
+    if (temp) RCCHK(sset(s, s->heat, 0, n * s->rs));
     RCCHK(sset(s, s->gam[0], 0, n * s->rs));
     RCCHK(sset(s, s->gam[1], 0, n * s->rs));
     if (s->vcount) RCCHK(sset(s, s->vcount, 0, 8));
@@ -1808,9 +1858,15 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
     FrtSolveDesc& h = s->h;
     h.nx = nx; h.ny = ny; h.nz = nz;
-    h.has_sub = gen ? 1 : 0;
+    h.has_sub = (gen || temp) ? 1 : 0;
     if (hk)
         for (size_t i = 0; i < n && !h.has_sub; i++) h.has_sub = hk[i] > 0.f;
+    h.temp = temp ? 1 : 0;
+    h.T = temp ? s->T : nullptr;
+    h.heat = s->heat;
+    for (int b = 0; b < FRT_MAX_BINS_I; b++) h.heat_ev[b] = b < s->P.n_bins ? s->P.heat_ev[b] : 0.0;
+    h.hubble = s->P.hubble_s;
+    h.cmb_z = s->P.cmb_z;
     h.gen = gen ? 1 : 0;
     h.front_atoms = (1.0 + s->P.he_chi) * s->dx * s->dx * s->dx;
     h.front = s->front;
@@ -2286,6 +2342,19 @@ int frt_read_ledger(frt_solve s, frt_ledger* out)
     out->merges = L.merges;
     out->rays_merged = L.rays_merged;
     out->front_excess = L.front_excess;
+    out->heat_in = L.heat_in * 1.602176634e-12;   // eV -> erg
+    return FRT_OK;
+}
+
+int frt_read_temperature(frt_solve s, double* T, int kind)
+{
+    if (!s || !T) return fail(FRT_EINVAL, "null argument");
+    if (kind != FRT_HOST && kind != FRT_DEVICE) return fail(FRT_EINVAL, "ptr_kind must be FRT_HOST or FRT_DEVICE");
+    if (!s->T) return fail(FRT_ESTATE, "the solve holds no temperature (none loaded, temperature off)");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    RCCHK(scopy(s, T, s->T, s->ncell * 8, kind == FRT_DEVICE ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost));
+    HIPCHK(hipStreamSynchronize(s->stream));
     return FRT_OK;
 }
 
@@ -2312,14 +2381,16 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     if (s->vcount) RCCHK(scopy(s, vc, s->vcount, 8, hipMemcpyDeviceToHost));
     const uint64_t nv = vc[cur];
     const uint64_t ng = warm_rate(s) ? s->ncell : 0;
-    const size_t need = 64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec + 8 + nv * sizeof(FrtVSrc) + 8 + ng * s->rs;
+    const uint64_t nt = s->h.temp ? s->ncell : 0;
+    const size_t need =
+        64 + led + s->ncell * 8 + nq * 8 + (size_t)nc * rec + 8 + nv * sizeof(FrtVSrc) + 8 + ng * s->rs + 8 + nt * 8;
     if (!buf) {
         *bytes = need;
         return FRT_OK;
     }
     if (*bytes < need) return fail(FRT_EINVAL, "checkpoint buffer too small (%zu < %zu)", *bytes, need);
     char* p = (char*)buf;
-    uint64_t hdr[8] = {0x4652544350543034ull, 8, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
+    uint64_t hdr[8] = {0x4652544350543034ull, 9, s->step, (uint64_t)s->n_src, s->ncell, (uint64_t)nb, (uint64_t)s->fp64, nc};
     std::memcpy(p, hdr, sizeof(hdr));
     p += sizeof(hdr);
     RCCHK(scopy(s, p, s->L, led, hipMemcpyDeviceToHost));
@@ -2343,6 +2414,10 @@ int frt_save_state(frt_solve s, void* buf, size_t* bytes)
     std::memcpy(p, &ng, 8);
     p += 8;
     if (ng) RCCHK(scopy(s, p, s->gam[(s->step + 1u) & 1u], ng * s->rs, hipMemcpyDeviceToHost));
+    p += ng * s->rs;
+    std::memcpy(p, &nt, 8);
+    p += 8;
+    if (nt) RCCHK(scopy(s, p, s->T, nt * 8, hipMemcpyDeviceToHost));
     *bytes = need;
     return FRT_OK;
 }
@@ -2356,7 +2431,7 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     uint64_t hdr[8];
     std::memcpy(hdr, p, sizeof(hdr));
     p += sizeof(hdr);
-    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 8) return fail(FRT_EINVAL, "not a checkpoint of this library");
+    if (hdr[0] != 0x4652544350543034ull || hdr[1] != 9) return fail(FRT_EINVAL, "not a checkpoint of this library");
     AllocScope scope(&s->ctx->al);
     if (hdr[3] != (uint64_t)s->n_src || hdr[4] != s->ncell || hdr[5] != (uint64_t)s->P.n_bins || hdr[6] != (uint64_t)s->fp64)
         return fail(FRT_EINVAL, "checkpoint does not match this solve (sources, grid, bins or precision)");
@@ -2373,7 +2448,12 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
     std::memcpy(&ng, p + at_ng, 8);
     if (ng != (warm_rate(s) ? s->ncell : 0))
         return fail(FRT_EINVAL, "checkpoint's previous rate field does not match this solve's opacity iteration");
-    if (bytes < 64 + at_ng + 8 + ng * s->rs) return fail(FRT_EINVAL, "checkpoint truncated");
+    if (bytes < 64 + at_ng + 8 + ng * s->rs + 8) return fail(FRT_EINVAL, "checkpoint truncated");
+    const size_t at_nt = at_ng + 8 + ng * s->rs;
+    uint64_t nt = 0;
+    std::memcpy(&nt, p + at_nt, 8);
+    if (nt != (s->h.temp ? s->ncell : 0)) return fail(FRT_EINVAL, "checkpoint's temperature field does not match this solve");
+    if (bytes < 64 + at_nt + 8 + nt * 8) return fail(FRT_EINVAL, "checkpoint truncated");
     if (nv && !s->P.merge) return fail(FRT_EINVAL, "checkpoint holds merged packets; this solve does not merge");
     HIPCHK(hipStreamSynchronize(s->stream));
     RCCHK(sset(s, s->L, 0, sizeof(FrtLedgerDev)));
@@ -2437,6 +2517,8 @@ int frt_load_state(frt_solve s, const void* buf, size_t bytes)
         RCCHK(scopy(s, s->gam[(step + 1u) & 1u], pg, ng * s->rs, hipMemcpyHostToDevice));
     }
     if (s->front) RCCHK(sset(s, s->front, 0, s->ncell * 8));
+    if (nt) RCCHK(scopy(s, s->T, (const char*)buf + 64 + at_nt + 8, nt * 8, hipMemcpyHostToDevice));
+    if (s->heat) RCCHK(sset(s, s->heat, 0, s->ncell * s->rs));
     RCCHK(upload_desc(s));
     hipError_t e = frt::launch_prep_opacity(s->d_desc, s->ncell, s->fp64, s->stream);
     if (e != hipSuccess) return fail(FRT_EDEVICE, "prep launch: %s", hipGetErrorString(e));
@@ -2480,6 +2562,12 @@ int frt_mark(frt_solve s)
         HIPCHK(hipMemcpyAsync(s->mark_g, s->gam[(s->step + 1u) & 1u], s->ncell * s->rs, hipMemcpyDeviceToDevice,
                               s->stream));
     }
+    dev_free(s->mark_T);
+    if (s->h.temp) {
+        RCCHK(dev_alloc((void**)&s->mark_T, s->ncell * 8));
+        HIPCHK(hipMemcpyAsync(s->mark_T, s->T, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
     s->mark_n = nc;
     s->mark_step = s->step;
     s->marked = true;
@@ -2506,6 +2594,8 @@ int frt_rewind(frt_solve s)
     if (s->mark_g)
         HIPCHK(hipMemcpyAsync(s->gam[cur ^ 1], s->mark_g, s->ncell * s->rs, hipMemcpyDeviceToDevice, s->stream));
     if (s->front) HIPCHK(hipMemsetAsync(s->front, 0, s->ncell * 8, s->stream));
+    if (s->mark_T) HIPCHK(hipMemcpyAsync(s->T, s->mark_T, s->ncell * 8, hipMemcpyDeviceToDevice, s->stream));
+    if (s->heat) HIPCHK(hipMemsetAsync(s->heat, 0, s->ncell * s->rs, s->stream));
     s->step = s->mark_step;
     s->h.step = s->step;
     RCCHK(upload_desc(s));

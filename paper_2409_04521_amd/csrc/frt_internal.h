@@ -54,7 +54,7 @@ enum : uint32_t {
 // Photon terms (double) and counters (u64) accumulated during a step.
 // (In the Generalized Opacity Mode, which has no sub-grid term, the
 // LF_ABS_SUB stripe carries the photons stopped at I-fronts.)
-enum { LF_EMITTED, LF_ABS_HI, LF_ABS_SUB, LF_ESC, LF_DROP, LF_FLIGHT, LF_LOST, LF_NF };
+enum { LF_EMITTED, LF_ABS_HI, LF_ABS_SUB, LF_ESC, LF_DROP, LF_FLIGHT, LF_LOST, LF_HEAT, LF_NF };
 enum { LC_CROSS, LC_VISITS, LC_SPLITS, LC_NESC, LC_NDROP, LC_NFLIGHT, LC_EMITTED, LC_NC };
 
 // Cumulative photon ledger of one solve (device resident).  During a step
@@ -67,6 +67,7 @@ struct FrtLedgerDev {
     double merge_residual;                      // photons before minus after the merges (rounding)
     unsigned long long merges, rays_merged;     // merged packets made, packets merged into them
     double front_excess;                        // front photons beyond the atoms their cells had left
+    double heat_in;                             // photo-heating given to the gas, eV (temperature on)
     double sd[FRT_STRIPES][LF_NF];
     unsigned long long sc[FRT_STRIPES][LC_NC];
 };
@@ -190,6 +191,17 @@ struct FrtSolveDesc {
     // dx (march precision), from which each march's ionized-gas opacity is
     // rebuilt with the equilibrium n_HI of the last rate
     const void* kin;
+    // temperature evolution (§4.1, Eq. temp_evolution_standard): T of every
+    // cell, this step's photo-heating rate of every cell (march precision;
+    // cleared by the chemistry) and the energy above 13.6 eV left per photon
+    // of each bin that HI absorbs
+    int temp;
+    double* T;                  // [ncell] K, or null
+    void* heat;                 // [ncell] photo-heating rate of the step, erg/cm^3/s, or null
+    double heat_scale;          // erg/cm^3/s per eV left in a cell during the step
+    double heat_ev[FRT_MAX_BINS_I];
+    double hubble;              // H(z) of the adiabatic term, 1/s
+    double cmb_z;               // CMB redshift of Compton cooling (< 0: none)
 };
 
 // One work item of a pass: up to FRT_ITEM_RAYS packets of one brick.
@@ -237,6 +249,7 @@ struct FrtWS {
     int n_solves;
     int n_bins;
     int has_sub;                // some solve of the launch has sub-grid opacity
+    int has_heat;               // some solve of the launch evolves its temperature
     // launch shape (tunable)
     uint32_t item_rays;         // packets per work item, 64..FRT_ITEM_RAYS
     int scatter_bpc;            // workgroups per CU of the scatter pass
@@ -318,6 +331,6 @@ hipError_t launch_snapshot(FrtSolveDesc* d, int n_solves, const uint32_t* halt, 
 // error, set C_HALT instead.
 hipError_t launch_advance(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
 // Query launch shapes once, outside any stream capture.
-void prime_launch_shapes(int fp64, int n_bins, int has_sub);
+void prime_launch_shapes(int fp64, int n_bins, int has_sub, int has_heat);
 int device_cu_count();
 }  // namespace frt

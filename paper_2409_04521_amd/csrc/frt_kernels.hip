@@ -811,7 +811,7 @@ __device__ __forceinline__ uint32_t reserve_end(uint32_t raw, uint32_t off) { re
 // leaving the brick hands the packet to the next pass.  Ledger terms are
 // reduced per wave and added into LDS; output keys are counted in an LDS
 // table and added to the histogram once per work item.
-template <typename Real, int NB, bool SUB, int LX, int LY, int LZ, int BT>
+template <typename Real, int NB, bool SUB, int LX, int LY, int LZ, int BT, bool HEAT = false>
 __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ descs, FrtWS& ws)
 {
     using R2 = typename Vec2<Real>::T;
@@ -838,6 +838,11 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
     constexpr bool INTDEP = F32;
     using GT = typename std::conditional<INTDEP, unsigned long long, Real>::type;
     __shared__ GT s_g[BC];
+    // photo-heating (temperature evolution; the sub-grid layout only): each
+    // cell's energy above 13.6 eV of the photons HI absorbed, LDS atomics in
+    // the march's precision
+    static_assert(!HEAT || SUB, "the heating march uses the sub-grid layout");
+    __shared__ Real s_h[HEAT ? BC : 1];
     __shared__ double s_lf[LF_NF];
     __shared__ unsigned long long s_lc[LC_NC];
     __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
@@ -886,12 +891,13 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         }
         const FrtSolveDesc& D = descs[w.solve];
         // per-solve constants of the march, held in scalar registers
-        Real srel[NB], Kb[NB], sl2[NB];
+        Real srel[NB], Kb[NB], sl2[NB], heps[NB];
 #pragma unroll
         for (int b = 0; b < NB; b++) {
             srel[b] = uni(srel_of<Real>(D, b));
             Kb[b] = SUB ? uni(K_of<Real>(D, b)) : Real(0);
             sl2[b] = uni((Real)D.sig_l2[b]);                // -log2(e) s_nu
+            heps[b] = HEAT ? uni((Real)D.heat_ev[b]) : Real(0);   // eV per photon HI absorbs
         }
         const Real KS = uni(F32 ? (Real)D.KS : (Real)D.KSd);
         // the HI optical depth per segment (at sigma_0) below which every bin's
@@ -942,6 +948,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             if constexpr (SUB) s_op[PADC + t] = st[k];
             else s_op[PADC + t] = st[k].x;
             s_g[t] = GT(0);
+            if constexpr (HEAT) s_h[t] = Real(0);
         }
         if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
         if (threadIdx.x == 0) {
@@ -1111,6 +1118,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                             // 0 for an empty segment), so that waiting for the next
                             // cell's prefetched opacity never waits for it
                             Real dep = 0;
+                            Real hdep = 0;   // photo-heating of the segment, eV (HEAT)
                             if constexpr (F32 && !SUB) {
                                 // u = -log2(e) s_nu tau_0: each bin's transmission is
                                 // 2^u.  The cell's absorbed photons: while even the
@@ -1160,6 +1168,9 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                                         dep += Kb[b] * nin * ds * phi;
                                         absd += nin * af;
                                         if (tk > Real(0)) sub_acc += nin * af * tk * rt;
+                                        // the HI share of the bin's absorbed photons
+                                        if constexpr (HEAT)
+                                            hdep += (tb > Real(0)) ? heps[b] * nin * af * (srel[b] * ta) * rt : Real(0);
                                         NE[b] *= eb;
                                     }
                                     ksum += tk;
@@ -1189,6 +1200,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                             } else {
                                 atomicAdd(&s_g[li], dep);
                             }
+                            if constexpr (HEAT) atomicAdd(&s_h[li], hdep);
                             h.r = r_end;
                             Real o_n;   // HI opacity of the next cell (< 0 outside the grid)
                             if constexpr (SUB) o_n = o_next.x;
@@ -1490,6 +1502,28 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                 atomicAdd(gam + ci, v);
             }
         }
+        if constexpr (HEAT) {
+            // the brick's photo-heating: its energy (eV; the march's photons
+            // are in units of R_ref) summed for the ledger, and each cell's
+            // heating rate (erg/cm^3/s, a range FP32 holds)
+            Real* __restrict__ hp = (Real*)D.heat;
+            const double hsc = uni(D.heat_scale);
+            double hsum = 0.0;
+            if (hp) {
+                for (int t = threadIdx.x; t < BC; t += BT) {
+                    const Real q = s_h[t];
+                    if (q != Real(0)) {
+                        const double e = (double)q * Rr;
+                        const int lx = t & (BX - 1), ly = (t >> LX) & (BY - 1), lz = t >> (LX + LY);
+                        const size_t ci = (size_t)(ox + lx) + (size_t)nx * ((size_t)(oy + ly) + (size_t)ny * (size_t)(oz + lz));
+                        atomicAdd(hp + ci, (Real)(e * hsc));
+                        hsum += e;
+                    }
+                }
+            }
+            hsum = wave_sum(hsum);
+            if (lane == 0 && hsum != 0.0) atomicAdd(&s_lf[LF_HEAT], hsum);
+        }
         if (threadIdx.x < KEY_SLOTS) {
             const uint32_t k = s_key[threadIdx.x];
             if (k != 0xffffffffu) {
@@ -1512,15 +1546,16 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
     }
 }
 
-// 256-thread march on 16^3 (FP32 with sub-grid opacity) or 8^3 (FP64) bricks
-template <typename Real, int NB, bool SUB>
+// 256-thread march on 16^3 (FP32 with sub-grid opacity) or 8^3 (FP64)
+// bricks; HEAT adds the photo-heating deposits of temperature evolution
+template <typename Real, int NB, bool SUB, bool HEAT = false>
 __global__ void __launch_bounds__(BLOCK) k_brick(const FrtSolveDesc* __restrict__ descs, FrtWS ws)
 {
     if (halted(ws)) return;
     if constexpr (sizeof(Real) == 4)
-        brick_march<Real, NB, SUB, FRT_BRICK_LOG_SUB[0], FRT_BRICK_LOG_SUB[1], FRT_BRICK_LOG_SUB[2], BLOCK>(descs, ws);
+        brick_march<Real, NB, SUB, FRT_BRICK_LOG_SUB[0], FRT_BRICK_LOG_SUB[1], FRT_BRICK_LOG_SUB[2], BLOCK, HEAT>(descs, ws);
     else
-        brick_march<Real, NB, SUB, FRT_BRICK_LOG_F64[0], FRT_BRICK_LOG_F64[1], FRT_BRICK_LOG_F64[2], BLOCK>(descs, ws);
+        brick_march<Real, NB, SUB, FRT_BRICK_LOG_F64[0], FRT_BRICK_LOG_F64[1], FRT_BRICK_LOG_F64[2], BLOCK, HEAT>(descs, ws);
 }
 
 // 1024-thread march on 32 x 16 x 16 bricks (FP32 without sub-grid opacity):
@@ -1592,6 +1627,7 @@ __global__ void k_finish(FrtSolveDesc* descs, FrtWS ws)
                     case LF_DROP: L->dropped += v; break;
                     case LF_FLIGHT: L->in_flight = v; break;
                     case LF_LOST: L->lost += v; break;
+                    case LF_HEAT: L->heat_in += v; break;
                 }
             } else {
                 const int j = i - LF_NF;
@@ -1630,6 +1666,92 @@ __device__ __forceinline__ Real hi_opacity(double v)
 }
 
 // ================================================================ chemistry
+
+// Temperature evolution (§4.1, Eq. temp_evolution_standard), pure H gas.
+// Rates at temperature T (K), lambda = 2 T_HI / T with T_HI = 157807 K: the
+// case-B recombination and collisional ionization coefficients (cm^3/s) of
+// Hui & Gnedin 1997, which the paper cites, and cooling coefficients (erg
+// cm^3/s): case-B recombination (Hui & Gnedin 1997), collisional ionization
+// (k T_HI per ionization), collisional excitation (Cen 1992) and free-free
+// (Gaunt factor 1.1 + 0.34 exp(-(5.5 - log10 T)^2 / 3)).
+struct HRates {
+    double alpha, coll, rec, ci, ce, ff;
+};
+
+constexpr double kBoltz = 1.380649e-16;     // erg/K
+constexpr double kTHI = 157807.0;           // K
+// Compton cooling off the CMB per electron and kelvin of T - T_CMB, at z = 0:
+// 4 sigma_T a_rad k T_CMB0^4 / (m_e c), T_CMB0 = 2.725 K
+constexpr double kCompton0 = 4.0 * 6.6524587321e-25 * 7.565733e-15 * kBoltz * (2.725 * 2.725 * 2.725 * 2.725) /
+                             (9.1093837015e-28 * 2.99792458e10);
+
+__device__ HRates h_rates(double T)
+{
+    HRates r;
+    const double lam = 2.0 * kTHI / T;
+    r.alpha = 2.753e-14 * pow(lam, 1.5) / pow(1.0 + pow(lam / 2.740, 0.407), 2.242);
+    r.coll = 21.11 * pow(T, -1.5) * exp(-0.5 * lam) * pow(lam, -1.089) / pow(1.0 + pow(lam / 0.354, 0.874), 1.101);
+    r.rec = 3.435e-30 * T * pow(lam, 1.970) / pow(1.0 + pow(lam / 2.250, 0.376), 3.720);
+    r.ci = kBoltz * kTHI * r.coll;
+    r.ce = 7.5e-19 * exp(-118348.0 / T) / (1.0 + sqrt(T / 1e5));
+    const double g = 5.5 - log10(T);
+    r.ff = 1.42e-27 * (1.1 + 0.34 * exp(-g * g / 3.0)) * sqrt(T);
+    return r;
+}
+
+// Photo-heating minus cooling (erg/cm^3/s) of a cell at T with n_H and
+// neutral fraction x; `heat` is the photo-heating rate.
+__device__ double net_gain(const FrtSolveDesc& D, double T, double nH, double x, double heat)
+{
+    const HRates r = h_rates(T);
+    const double ne = nH * (1.0 - x), nHI = nH * x;
+    double cool = (r.rec + r.ff) * ne * ne + (r.ci + r.ce) * ne * nHI;
+    if (D.cmb_z >= 0.0) {
+        const double z1 = 1.0 + D.cmb_z, z4 = z1 * z1 * z1 * z1;
+        cool += kCompton0 * z4 * (T - 2.725 * z1) * ne;
+    }
+    return heat - cool;
+}
+
+// T at the end of a step in which x went from x0 to x1 (n_tot = n_H (2 - x)):
+// n_tot T kept over the change of particle number, e^(-2 H dt) for the
+// Hubble term, then dT/dt = 2 (heat - cool) / (3 k n_tot) at x1 over dt in
+// sub-steps that change T by at most a tenth, each solving the equation
+// linearized about its start exactly (the slope from a relative step of 1e-6
+// in T); at most 4096 sub-steps, T >= 1 K.
+__device__ double evolve_temperature(const FrtSolveDesc& D, double T, double nH, double x0, double x1, double heat)
+{
+    const double n0 = nH * (2.0 - x0), n1 = nH * (2.0 - x1);
+    if (n1 > 0.0) T = T * (n0 / n1);
+    if (D.hubble > 0.0) T = T * exp(-2.0 * D.hubble * D.dt);
+    if (!(n1 > 0.0)) return T;
+    const double c = 2.0 / (3.0 * kBoltz * n1);
+    const double dt = D.dt;
+    double t = 0.0;
+    for (int k = 0; k < 4096 && t < dt; k++) {
+        const double f = c * net_gain(D, T, nH, x1, heat);
+        const double Tp = T * (1.0 + 1e-6);
+        const double slope = (c * net_gain(D, Tp, nH, x1, heat) - f) / (Tp - T);
+        double h = dt - t;
+        if (fabs(f) * h > 0.1 * T) h = 0.1 * T / fabs(f);
+        const double y = slope * h;
+        T = T + ((fabs(y) > 1e-8) ? f * expm1(y) / slope : f * h);
+        if (T < 1.0) T = 1.0;
+        t += h;
+    }
+    return T;
+}
+
+// The step's photo-heating rate of cell i (erg/cm^3/s) that the march
+// deposited, which it clears.
+template <typename Real>
+__device__ __forceinline__ double take_heat(const FrtSolveDesc& D, size_t i)
+{
+    Real* hp = (Real*)D.heat;
+    const double h = (double)hp[i];
+    hp[i] = Real(0);
+    return h;
+}
 
 // The ionized fraction as staged for the march (Generalized Opacity Mode): a
 // cell not fully ionized in FP64 stays below 1 in FP32 too, so that the
@@ -1733,15 +1855,24 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
         const double nH = D.nH[i];
         const double x = D.x[i];
         const double dt = D.dt;
-        const double a = dt * nH * (D.alpha_B + D.coll_ion);
-        const double bq = -(1.0 + dt * (G + 2.0 * D.alpha_B * nH + D.coll_ion * nH));
-        const double cq = x + D.alpha_B * nH * dt;
+        // recombination and collisional ionization at the step's starting
+        // temperature when it evolves
+        double alpha = D.alpha_B, coll = D.coll_ion;
+        if (D.temp) {
+            const HRates r = h_rates(D.T[i]);
+            alpha = r.alpha;
+            coll = r.coll;
+        }
+        const double a = dt * nH * (alpha + coll);
+        const double bq = -(1.0 + dt * (G + 2.0 * alpha * nH + coll * nH));
+        const double cq = x + alpha * nH * dt;
         double disc = bq * bq - 4.0 * a * cq;
         disc = disc > 0.0 ? disc : 0.0;
         const double xn = 2.0 * cq / (-bq + sqrt(disc));
         D.x[i] = xn;
         ((Real*)D.op_aw)[i] = hi_opacity<Real>(nH * xn * D.sigma0 * D.dx_cm);
         gnext[i] = Real(0);
+        if (D.temp) D.T[i] = evolve_temperature(D, D.T[i], nH, x, xn, take_heat<Real>(D, i));
     });
 }
 
@@ -1804,21 +1935,31 @@ __global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const u
             Real* gcur = (Real*)D.gamma[D.step & 1u];
             const double G = (double)gcur[i];
             const double ne = nH * (1.0 - D.xavg[i]);
-            const double R = G + D.coll_ion * ne + D.alpha_B * ne;
+            double alpha = D.alpha_B, coll = D.coll_ion;
+            if (D.temp) {
+                // the rates of the step's starting temperature, for every march
+                const HRates r = h_rates(D.T[i]);
+                alpha = r.alpha;
+                coll = r.coll;
+            }
+            const double R = G + coll * ne + alpha * ne;
             const double y = R * D.dt;
             double xa = x0, xe = x0;
             if (y > 0.0) {
-                const double xeq = D.alpha_B * ne / R;
+                const double xeq = alpha * ne / R;
                 xe = xeq + (x0 - xeq) * exp(-y);
                 xa = xeq + (x0 - xeq) * (-expm1(-y) / y);
             }
             if (phase == 1) {
                 D.xavg[i] = xa;
                 gcur[i] = Real(0);
+                // only the last march's photo-heating counts, like its rate
+                if (D.temp) ((Real*)D.heat)[i] = Real(0);
                 xo = xa;
             } else {
                 D.x[i] = xe;
                 ((Real*)D.gamma[(D.step + 1u) & 1u])[i] = Real(0);
+                if (D.temp) D.T[i] = evolve_temperature(D, D.T[i], nH, x0, xe, take_heat<Real>(D, i));
                 xo = xe;
             }
         }
@@ -1938,7 +2079,12 @@ template <typename Real, int NB>
 BrickLaunch brick_kernel(const FrtWS& ws)
 {
     BrickLaunch b;
-    if constexpr (sizeof(Real) == 4) {
+    if (ws.has_heat) {
+        // temperature evolution: the solves of such a launch use the
+        // sub-grid layout
+        b.kernel = k_brick<Real, NB, true, true>;
+        b.threads = BLOCK;
+    } else if constexpr (sizeof(Real) == 4) {
         if (!ws.has_sub) {
             b.kernel = k_brick_big<Real, NB>;
             b.threads = 4 * BLOCK;
@@ -2092,12 +2238,13 @@ hipError_t launch_advance(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
     return hipGetLastError();
 }
 
-void prime_launch_shapes(int fp64, int n_bins, int has_sub)
+void prime_launch_shapes(int fp64, int n_bins, int has_sub, int has_heat)
 {
     (void)cu_count();
     FrtWS w{};
     w.n_bins = n_bins;
     w.has_sub = has_sub;
+    w.has_heat = has_heat;
     auto prime = [&](auto tag) {
         using Real = decltype(tag);
         switch (n_bins) {

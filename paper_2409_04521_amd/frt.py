@@ -30,7 +30,8 @@ EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_
            "frt_rotation_uniforms", "frt_batch_run", "frt_tuning_default", "frt_ctx_set_tuning",
            "frt_ctx_get_tuning", "frt_autotune", "frt_request_bytes", "frt_server_create", "frt_server_submit",
            "frt_server_poll", "frt_server_wait", "frt_server_take", "frt_server_times", "frt_server_get_stats",
-           "frt_server_destroy", "frt_debug_cast", "frt_step_static", "frt_merge_uniforms")
+           "frt_server_destroy", "frt_debug_cast", "frt_step_static", "frt_merge_uniforms",
+           "frt_read_temperature")
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
@@ -47,7 +48,9 @@ class Params(C.Structure):
                 ("max_distance_cm", C.c_double), ("c_ray_cm_s", C.c_double), ("march_precision", C.c_int),
                 ("seed", C.c_uint64), ("queue_capacity", C.c_uint64), ("queue_hint", C.c_uint64),
                 ("chem_iterations", C.c_int), ("opacity_mode", C.c_int), ("he_chi", C.c_double),
-                ("merge", C.c_int), ("merge_level", C.c_int), ("merge_exempt", C.c_double)]
+                ("merge", C.c_int), ("merge_level", C.c_int), ("merge_exempt", C.c_double),
+                ("temperature", C.c_int), ("heat_ev", C.c_double * MAX_BINS), ("hubble_s", C.c_double),
+                ("cmb_z", C.c_double)]
 
 
 class Ledger(C.Structure):
@@ -58,7 +61,7 @@ class Ledger(C.Structure):
                 ("n_in_flight", C.c_uint64), ("rays_emitted", C.c_uint64), ("step_crossings", C.c_uint64),
                 ("steps", C.c_uint64), ("err_flags", C.c_uint32), ("max_items", C.c_uint32),
                 ("absorbed_front", C.c_double), ("merge_residual", C.c_double), ("merges", C.c_uint64),
-                ("rays_merged", C.c_uint64), ("front_excess", C.c_double)]
+                ("rays_merged", C.c_uint64), ("front_excess", C.c_double), ("heat_in", C.c_double)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -171,6 +174,7 @@ def lib():
         L.frt_sync.argtypes = [vp]
         L.frt_read_fields.argtypes = [vp, vp, vp, C.c_int]
         L.frt_read_ledger.argtypes = [vp, C.POINTER(Ledger)]
+        L.frt_read_temperature.argtypes = [vp, vp, C.c_int]
         L.frt_save_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
         L.frt_load_state.argtypes = [vp, vp, C.c_size_t]
         L.frt_mark.argtypes = [vp]
@@ -289,7 +293,8 @@ class Solve:
     def __init__(self, ctx: Context, *, sigma_bins, alpha_B=2.59e-13, coll_ion=0.0, base_level=0,
                  max_level=12, n_ray_min=1.0, flux_floor=0.0, max_distance_cm=0.0, c_ray=2.99792458e10,
                  precision="f32", seed=0, queue_capacity=0, queue_hint=0, chem_iterations=0, opacity_mode=0,
-                 he_chi=0.0, merge=False, merge_level=0, merge_exempt=4.0, stream=None):
+                 he_chi=0.0, merge=False, merge_level=0, merge_exempt=4.0, temperature=False, heat_ev=None,
+                 hubble_s=0.0, cmb_z=-1.0, stream=None):
         p = params_default()
         sig = list(sigma_bins)
         p.n_bins = len(sig)
@@ -304,6 +309,9 @@ class Solve:
         p.chem_iterations = chem_iterations
         p.opacity_mode, p.he_chi = opacity_mode, he_chi
         p.merge, p.merge_level, p.merge_exempt = int(bool(merge)), merge_level, merge_exempt
+        p.temperature, p.hubble_s, p.cmb_z = int(bool(temperature)), hubble_s, cmb_z
+        for i, e in enumerate(heat_ev if heat_ev is not None else []):
+            p.heat_ev[i] = e
         self.ctx = ctx
         self.params = p
         self.n_bins = p.n_bins
@@ -376,6 +384,12 @@ class Solve:
         L = Ledger()
         _check(lib().frt_read_ledger(self.h, C.byref(L)))
         return L.as_dict()
+
+    def temperature(self):
+        """The gas temperature (K) of every cell."""
+        t = np.empty(int(np.prod(self.shape)))
+        _check(lib().frt_read_temperature(self.h, t.ctypes.data, FRT_HOST))
+        return t.reshape(self.shape)
 
     def debug_cast(self, origin_cm, direction, N_bins, dt_s=1.0):
         """March one packet through the current opacity (frt_debug_cast).
@@ -464,6 +478,11 @@ def _params_for(prob, precision="f32", **kw) -> Params:
     p.merge = int(bool(getattr(prob, "merge", False)))
     p.merge_level = getattr(prob, "merge_level", 0)
     p.merge_exempt = getattr(prob, "merge_exempt", 4.0)
+    p.temperature = int(bool(getattr(prob, "temperature", False)))
+    for i, e in enumerate(getattr(prob, "heat_ev", None) if getattr(prob, "heat_ev", None) is not None else []):
+        p.heat_ev[i] = e
+    p.hubble_s = getattr(prob, "hubble_s", 0.0)
+    p.cmb_z = getattr(prob, "cmb_z", -1.0)
     return p
 
 
@@ -579,7 +598,9 @@ def solve_from_problem(ctx: Context, prob, precision="f32", use_table=True, **kw
               precision=precision, seed=prob.seed, chem_iterations=getattr(prob, "chem_iterations", 0),
               opacity_mode=getattr(prob, "opacity_mode", 0), he_chi=getattr(prob, "he_chi", 0.0),
               merge=getattr(prob, "merge", False), merge_level=getattr(prob, "merge_level", 0),
-              merge_exempt=getattr(prob, "merge_exempt", 4.0), **kw)
+              merge_exempt=getattr(prob, "merge_exempt", 4.0), temperature=getattr(prob, "temperature", False),
+              heat_ev=getattr(prob, "heat_ev", None), hubble_s=getattr(prob, "hubble_s", 0.0),
+              cmb_z=getattr(prob, "cmb_z", -1.0), **kw)
     nz, ny, nx = prob.shape
     s.load_grid(prob.n_H, prob.dx_cm * nx, kappa=prob.kappa, x_HI0=prob.x_HI0, T=prob.T)
     s.load_sources(prob.src_pos_cm, prob.ndot_bins)

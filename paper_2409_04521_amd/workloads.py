@@ -199,7 +199,11 @@ class Problem:
     merge: bool = False               # ray merging at the end of each step (§3.3)
     merge_level: int = 0              # l_merge
     merge_exempt: float = 0.0         # N_ex (exempt packets per cell)
-    T: np.ndarray | None = None
+    T: np.ndarray | None = None       # float32 K: the starting temperature when it evolves
+    temperature: bool = False         # T evolves (§4.1, Eq. temp_evolution_standard)
+    heat_ev: np.ndarray | None = None # (n_bins,) eV above 13.6 eV per photon HI absorbs
+    hubble_s: float = 0.0             # H(z) of the adiabatic term, 1/s
+    cmb_z: float = -1.0               # CMB redshift of Compton cooling (< 0: none)
     meta: dict = field(default_factory=dict)
 
     @property
@@ -225,7 +229,9 @@ class Problem:
                     max_dist_cm=self.max_dist_cm, c_ray=self.c_ray,
                     chem_iterations=self.chem_iterations, opacity_mode=self.opacity_mode,
                     he_chi=self.he_chi, merge=self.merge, merge_level=self.merge_level,
-                    merge_exempt=self.merge_exempt)
+                    merge_exempt=self.merge_exempt, temperature=self.temperature, heat_ev=self.heat_ev,
+                    hubble_s=self.hubble_s, cmb_z=self.cmb_z,
+                    T0=None if self.T is None else np.asarray(self.T, dtype=np.float64))
 
     def merge_uniforms(self, step: int):
         """The cells' merging-sphere uniforms of `step`, or None without merging."""

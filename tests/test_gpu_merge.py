@@ -91,11 +91,11 @@ def test_merging_with_subgrid_opacity(ctx, precision, x_tol, led_tol):
 
 def _carried(g, p, fp64):
     """Cells of the carried packets, from the checkpoint (records after the
-    header, the 168-byte ledger, x_HI and the quaternions)."""
+    header, the 176-byte ledger, x_HI and the quaternions)."""
     blob = g.save()
     hdr = np.frombuffer(blob[:64], dtype=np.uint64)
     step, nc = int(hdr[2]), int(hdr[7])
-    off = 64 + 168 + 8 * p.ncell + 32 * step * p.n_src
+    off = 64 + 176 + 8 * p.ncell + 32 * step * p.n_src
     size = 112 if fp64 else 64
     recs = np.frombuffer(blob[off: off + nc * size], dtype=np.uint8).reshape(nc, size)
     cell = recs[:, 12:16].copy().view(np.uint32).reshape(-1)

@@ -344,13 +344,13 @@ def test_many_splits_per_step_at_finite_c(ctx):
 def _carried_radii(g, n_src, ncell, fp64):
     """Distances from their sources (cells) of the packets a solve carries,
     read from its checkpoint: 8 u64 header (the carried count last), the
-    ledger (168 bytes), x_HI, the rotation quaternions of the steps so far,
+    ledger (176 bytes), x_HI, the rotation quaternions of the steps so far,
     then the packet records (64 bytes in FP32 with r at byte 20, 112 in FP64
     with r at byte 24)."""
     blob = g.save()
     hdr = np.frombuffer(blob[:64], dtype=np.uint64)
     step, nc = int(hdr[2]), int(hdr[7])
-    off = 64 + 168 + 8 * ncell + 32 * step * n_src
+    off = 64 + 176 + 8 * ncell + 32 * step * n_src
     size, at, dt = (112, 24, np.float64) if fp64 else (64, 20, np.float32)
     recs = np.frombuffer(blob[off: off + nc * size], dtype=np.uint8).reshape(nc, size)
     return recs[:, at: at + np.dtype(dt).itemsize].copy().view(dt).reshape(-1).astype(np.float64)
