@@ -717,7 +717,7 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
     const int n_march = K > 0 ? K : 1;
     if (K > 0) {
         Timed t(tm, st, 2);
-        if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 0, w.ctr + C_ERR, halt, st)) != hipSuccess)
+        if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_heat, 0, w.ctr + C_ERR, halt, st)) != hipSuccess)
             return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
     }
     for (int it = 0; it < n_march; it++) {
@@ -752,14 +752,14 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
         }
         if (it + 1 < n_march) {
             Timed t(tm, st, 2);
-            if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 1, w.ctr + C_ERR, halt, st)) != hipSuccess)
+            if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_heat, 1, w.ctr + C_ERR, halt, st)) != hipSuccess)
                 return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         }
     }
     {
         Timed t(tm, st, 2);
-        if (K > 0) e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, 2, w.ctr + C_ERR, halt, st);
-        else e = frt::launch_chem(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.ctr + C_ERR, st);
+        if (K > 0) e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_heat, 2, w.ctr + C_ERR, halt, st);
+        else e = frt::launch_chem(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_heat, w.ctr + C_ERR, st);
         if (e != hipSuccess) return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         if (tm) tm->n_chem++;
     }

@@ -312,9 +312,11 @@ hipError_t launch_seed(FrtSolveDesc* d, const FrtWS& ws, int fp64, hipStream_t s
 hipError_t launch_pass(FrtSolveDesc* d, const FrtWS& ws, int fp64, int part, hipStream_t s);
 hipError_t launch_finish(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
 // The chemistry of every solve of a launch; `launch_err` is the launch's
-// error word (device): when it is set no solve's state changes.
+// error word (device): when it is set no solve's state changes.  `temp`:
+// some solve of the launch evolves its temperature (the kernels that do are
+// separate, so that the others keep their occupancy).
 hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
-                       unsigned long long total_cells, int fp64, const uint32_t* launch_err, hipStream_t s);
+                       unsigned long long total_cells, int fp64, int temp, const uint32_t* launch_err, hipStream_t s);
 hipError_t launch_prep_opacity(FrtSolveDesc* d_desc, unsigned long long ncell, int fp64, hipStream_t s);
 // Clear the launch counters and brick histogram (a kernel, so that a step
 // captured in a HIP graph holds no memset node); mode is a CLEAR_* value.
@@ -322,7 +324,7 @@ hipError_t launch_clear(const FrtWS& ws, int mode, hipStream_t s);
 // `halt` (device, may be null) is the launch's C_HALT word: when it is set
 // the kernel does nothing.  Steps launched one by one pass null.
 hipError_t launch_chem_avg(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
-                           unsigned long long total_cells, int fp64, int phase, const uint32_t* launch_err,
+                           unsigned long long total_cells, int fp64, int temp, int phase, const uint32_t* launch_err,
                            const uint32_t* halt, hipStream_t s);
 hipError_t launch_iter_restart(FrtSolveDesc* d, int n_solves, const uint32_t* halt, hipStream_t s);
 hipError_t launch_snapshot(FrtSolveDesc* d, int n_solves, const uint32_t* halt, hipStream_t s);

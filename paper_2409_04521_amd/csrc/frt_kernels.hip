@@ -745,17 +745,15 @@ __device__ __forceinline__ Real absorbed(Real t, Real eb)
     }
 }
 
-// The same in terms of u = -log2(e) t (so that e^-t = 2^u): with
-// v = -u ln 2 = t, the series v (1 - v/2 + v^2/6 - v^3/24) written in u,
-// used while t < 0.03 (u > -0.03 / ln 2).
-// 1 - 2^u for -0.0144 < u <= 0 (optical depths below 0.01) from its Taylor
-// series: with w = -u ln 2, w - w^2/2 + w^3/6, relative error below 5e-8
-// there, where 1 - 2^u from a rounded 2^u loses digits.
-constexpr float ABSORBED_SERIES_U = 0.014426950f;
+// The same in terms of u = -log2(e) t (so that e^-t = 2^u): 1 - 2^u for
+// -0.0721 < u <= 0 (optical depths below 0.05) from its Taylor series, with
+// w = -u ln 2, w - w^2/2 + w^3/6 - w^4/24: relative error below 6e-8 there,
+// where 1 - 2^u from a rounded 2^u loses digits.
+constexpr float ABSORBED_SERIES_U = 0.072134752f;
 __device__ __forceinline__ float absorbed_series(float u)
 {
-    constexpr float c1 = -0.69314718f, c2 = -0.24022651f, c3 = -0.05550411f;
-    return u * (c1 + u * (c2 + u * c3));
+    constexpr float c1 = -0.69314718f, c2 = -0.24022651f, c3 = -0.05550411f, c4 = -0.0096181291f;
+    return u * (c1 + u * (c2 + u * (c3 + u * c4)));
 }
 
 
@@ -1122,22 +1120,38 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                             if constexpr (F32 && !SUB) {
                                 // u = -log2(e) s_nu tau_0: each bin's transmission is
                                 // 2^u.  The cell's absorbed photons: while even the
-                                // softest bin's u is above -0.0144, the sum over bins
-                                // of N_nu (1 - 2^u) from its series (valid there for
-                                // every bin); beyond it the drop of the photons' sum,
-                                // which is then at least 1% of the softest bin's
-                                // photons (an empty segment changes nothing)
+                                // softest bin's u is above -0.0721 (optical depth
+                                // 0.05), the sum over bins of N_nu (1 - 2^u) from its
+                                // series (valid there for every bin); beyond it the
+                                // drop of the photons' sum, which is then at least 5%
+                                // of the softest bin's photons (an empty segment
+                                // changes nothing).  When every lane of the wave is
+                                // in the series range the photons left are N_nu
+                                // minus that series too, and no 2^u is evaluated.
                                 const Real ta = o_cur * ds;
-                                Real S_new = 0, A_ser = 0;
+                                const bool thin = ta < ta_ser;
+                                if (__ballot(!thin) == 0ull) {
+                                    Real A = 0;
 #pragma unroll
-                                for (int b = 0; b < NB; b++) {
-                                    const Real u = sl2[b] * ta;
-                                    A_ser += NE[b] * absorbed_series(u);
-                                    NE[b] *= __builtin_amdgcn_exp2f(u);
-                                    S_new += NE[b];
+                                    for (int b = 0; b < NB; b++) {
+                                        const Real d = NE[b] * absorbed_series(sl2[b] * ta);
+                                        A += d;
+                                        NE[b] -= d;
+                                    }
+                                    dep = A;
+                                    S -= A;
+                                } else {
+                                    Real S_new = 0, A_ser = 0;
+#pragma unroll
+                                    for (int b = 0; b < NB; b++) {
+                                        const Real u = sl2[b] * ta;
+                                        A_ser += NE[b] * absorbed_series(u);
+                                        NE[b] *= __builtin_amdgcn_exp2f(u);
+                                        S_new += NE[b];
+                                    }
+                                    dep = thin ? A_ser : S - S_new;
+                                    S = S_new;
                                 }
-                                dep = ta < ta_ser ? A_ser : S - S_new;
-                                S = S_new;
                                 tsum += ta;
                                 v_cross += ds > Real(0) ? 1u : 0u;
                             } else if (ds > Real(0)) {
@@ -1802,8 +1816,8 @@ __device__ __forceinline__ void moving_screen(const FrtSolveDesc& D, size_t i)
 // search over the per-solve cell prefix (in LDS).  f(D, i) gets the solve
 // and the cell index within it.
 template <typename F>
-__device__ __forceinline__ void for_each_cell(FrtSolveDesc* descs, const unsigned long long* spre, int n_solves,
-                                             unsigned long long total, F&& f)
+__device__ __forceinline__ void for_each_cell(const FrtSolveDesc* __restrict__ descs, const unsigned long long* spre,
+                                             int n_solves, unsigned long long total, F&& f)
 {
     auto solve_of = [&](unsigned long long g) {
         int lo = 0, hi = n_solves - 1;
@@ -1834,8 +1848,8 @@ __device__ __forceinline__ void for_each_cell(FrtSolveDesc* descs, const unsigne
 // next step (in place) and clears the next step's deposit buffer.  A launch
 // in which any solve's queues overflowed leaves every solve's state
 // untouched: the whole launch is run again from the start of the step.
-template <typename Real>
-__global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsigned long long* prefix,
+template <typename Real, bool TEMP>
+__global__ void __launch_bounds__(BLOCK) k_chem(const FrtSolveDesc* __restrict__ descs, const unsigned long long* prefix,
                                                 int n_solves, unsigned long long total, const uint32_t* launch_err)
 {
     __shared__ unsigned long long spre[FRT_MAX_SOLVES_PER_LAUNCH + 1];
@@ -1858,7 +1872,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
         // recombination and collisional ionization at the step's starting
         // temperature when it evolves
         double alpha = D.alpha_B, coll = D.coll_ion;
-        if (D.temp) {
+        if (TEMP && D.temp) {
             const HRates r = h_rates(D.T[i]);
             alpha = r.alpha;
             coll = r.coll;
@@ -1872,7 +1886,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
         D.x[i] = xn;
         ((Real*)D.op_aw)[i] = hi_opacity<Real>(nH * xn * D.sigma0 * D.dx_cm);
         gnext[i] = Real(0);
-        if (D.temp) D.T[i] = evolve_temperature(D, D.T[i], nH, x, xn, take_heat<Real>(D, i));
+        if (TEMP && D.temp) D.T[i] = evolve_temperature(D, D.T[i], nH, x, xn, take_heat<Real>(D, i));
     });
 }
 
@@ -1890,8 +1904,8 @@ __global__ void __launch_bounds__(BLOCK) k_chem(FrtSolveDesc* descs, const unsig
 // A launch in which any solve's queues overflowed leaves every solve's state
 // untouched (phases 1 and 2 do nothing); phase 0 starts every run of the
 // step, the first and any re-run, from the state the step began with.
-template <typename Real>
-__global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const unsigned long long* prefix,
+template <typename Real, bool TEMP>
+__global__ void __launch_bounds__(BLOCK) k_chem_avg(const FrtSolveDesc* __restrict__ descs, const unsigned long long* prefix,
                                                     int n_solves, unsigned long long total, int phase,
                                                     const uint32_t* launch_err, const uint32_t* halt)
 {
@@ -1936,7 +1950,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const u
             const double G = (double)gcur[i];
             const double ne = nH * (1.0 - D.xavg[i]);
             double alpha = D.alpha_B, coll = D.coll_ion;
-            if (D.temp) {
+            if (TEMP && D.temp) {
                 // the rates of the step's starting temperature, for every march
                 const HRates r = h_rates(D.T[i]);
                 alpha = r.alpha;
@@ -1954,12 +1968,12 @@ __global__ void __launch_bounds__(BLOCK) k_chem_avg(FrtSolveDesc* descs, const u
                 D.xavg[i] = xa;
                 gcur[i] = Real(0);
                 // only the last march's photo-heating counts, like its rate
-                if (D.temp) ((Real*)D.heat)[i] = Real(0);
+                if (TEMP && D.temp) ((Real*)D.heat)[i] = Real(0);
                 xo = xa;
             } else {
                 D.x[i] = xe;
                 ((Real*)D.gamma[(D.step + 1u) & 1u])[i] = Real(0);
-                if (D.temp) D.T[i] = evolve_temperature(D, D.T[i], nH, x0, xe, take_heat<Real>(D, i));
+                if (TEMP && D.temp) D.T[i] = evolve_temperature(D, D.T[i], nH, x0, xe, take_heat<Real>(D, i));
                 xo = xe;
             }
         }
@@ -2008,7 +2022,7 @@ __global__ void __launch_bounds__(BLOCK) k_iter_restart(FrtSolveDesc* descs, con
 // written by the host beforehand into .y); in the Generalized Opacity Mode
 // {kappa dx (written by the host), 1 - x}.
 template <typename Real>
-__global__ void __launch_bounds__(BLOCK) k_prep(FrtSolveDesc* desc, unsigned long long n)
+__global__ void __launch_bounds__(BLOCK) k_prep(const FrtSolveDesc* __restrict__ desc, unsigned long long n)
 {
     const FrtSolveDesc& D = *desc;
     Real* op = (Real*)D.op_aw;
@@ -2189,12 +2203,12 @@ hipError_t launch_finish(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s)
 }
 
 hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
-                       unsigned long long total_cells, int fp64, const uint32_t* launch_err, hipStream_t s)
+                       unsigned long long total_cells, int fp64, int temp, const uint32_t* launch_err, hipStream_t s)
 {
     if (total_cells == 0) return hipSuccess;
     const int grid = grid_for(total_cells, 16);
-    if (fp64) hipLaunchKernelGGL(k_chem<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, launch_err);
-    else hipLaunchKernelGGL(k_chem<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, launch_err);
+    auto kern = fp64 ? (temp ? k_chem<double, true> : k_chem<double, false>) : (temp ? k_chem<float, true> : k_chem<float, false>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, launch_err);
     return hipGetLastError();
 }
 
@@ -2206,17 +2220,14 @@ hipError_t launch_clear(const FrtWS& ws, int mode, hipStream_t s)
 }
 
 hipError_t launch_chem_avg(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
-                           unsigned long long total_cells, int fp64, int phase, const uint32_t* launch_err,
+                           unsigned long long total_cells, int fp64, int temp, int phase, const uint32_t* launch_err,
                            const uint32_t* halt, hipStream_t s)
 {
     if (total_cells == 0) return hipSuccess;
     const int grid = grid_for(total_cells, 16);
-    if (fp64)
-        hipLaunchKernelGGL(k_chem_avg<double>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase,
-                           launch_err, halt);
-    else
-        hipLaunchKernelGGL(k_chem_avg<float>, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase,
-                           launch_err, halt);
+    auto kern = fp64 ? (temp ? k_chem_avg<double, true> : k_chem_avg<double, false>)
+                     : (temp ? k_chem_avg<float, true> : k_chem_avg<float, false>);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(BLOCK), 0, s, d, d_cell_prefix, n_solves, total_cells, phase, launch_err, halt);
     return hipGetLastError();
 }
 
