@@ -40,8 +40,8 @@ namespace {
 
 std::mutex g_mu;                        // every piece of state below
 fake::Faults g_faults;
-int g_creates = 0, g_loads = 0, g_live = 0;
-bool g_hold = false;
+int g_creates = 0, g_loads = 0, g_loaded = 0, g_live = 0;
+bool g_hold = false, g_hold_steps = false;
 std::condition_variable g_release;
 uint64_t g_batches = 0, g_max_batch = 0;
 std::atomic<int64_t> g_clock_ns{0};
@@ -67,8 +67,8 @@ void reset(const Faults& f)
 {
     std::lock_guard<std::mutex> lock(g_mu);
     g_faults = f;
-    g_creates = g_loads = 0;
-    g_hold = false;
+    g_creates = g_loads = g_loaded = 0;
+    g_hold = g_hold_steps = false;
     g_batches = g_max_batch = 0;
 }
 
@@ -79,10 +79,23 @@ void hold_loads(bool hold)
     g_release.notify_all();
 }
 
+void hold_steps(bool hold)
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    g_hold_steps = hold;
+    g_release.notify_all();
+}
+
 int loads_started()
 {
     std::lock_guard<std::mutex> lock(g_mu);
     return g_loads;
+}
+
+int loads_done()
+{
+    std::lock_guard<std::mutex> lock(g_mu);
+    return g_loaded;
 }
 
 int live_solves()
@@ -182,6 +195,10 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double, const float* n_H,
     s->nz = nz;
     s->tag = n_H[0];
     s->grid = true;
+    {
+        std::lock_guard<std::mutex> lock(g_mu);
+        g_loaded++;
+    }
     tick(5000 + (int64_t)(0.1 * (double)ncell(s)));
     std::this_thread::yield();
     return FRT_OK;
@@ -219,7 +236,8 @@ int frt_batch_step(frt_solve* ss, int n, const double* dts)
     }
     frt_ctx ctx = ss[0]->ctx;
     {
-        std::lock_guard<std::mutex> lock(g_mu);
+        std::unique_lock<std::mutex> lock(g_mu);
+        g_release.wait(lock, [] { return !g_hold_steps; });
         const fake::Faults& f = g_faults;
         need *= (uint64_t)f.pass_growth;
         for (int i = 0; i < n; i++)

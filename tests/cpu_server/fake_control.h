@@ -17,11 +17,14 @@ struct Faults {
 
 // Install the failures and zero the call counters (not the live count).
 void reset(const Faults& f);
-// While held, grid uploads wait at their start (so that requests can be
-// lined up before any of them steps); loads_started() counts the uploads
-// that began since reset.
+// While held, grid uploads wait at their start, and batched steps at
+// theirs (so that requests can be lined up before any of them steps);
+// loads_started() and loads_done() count the uploads that began and that
+// ended since reset.
 void hold_loads(bool hold);
+void hold_steps(bool hold);
 int loads_started();
+int loads_done();
 int live_solves();                  // created and not yet destroyed
 uint64_t batches();                 // batched steps applied since reset
 uint64_t max_batch();               // most solves in one applied batched step

@@ -357,14 +357,22 @@ void pass_queue_limit_steps_solves_alone()
         auto a = make(1, 16, 30), b = make(2, 16, 3);
         Setup s(2 * bytes_of(*a), 2, f);
         fake::hold_loads(true);
+        fake::hold_steps(true);
         const uint64_t ia = submit(s.srv, *a), ib = submit(s.srv, *b);
         wait_admitted(s.srv, {ia, ib}, 2);
         fake::hold_loads(false);
+        // both uploads end before the first step does (a step of the first
+        // alone may be waiting): the two are in flight together
+        for (int k = 0; k < 20000 && fake::loads_done() < 2; k++) std::this_thread::sleep_for(std::chrono::microseconds(500));
+        CHECK(fake::loads_done() == 2);
+        fake::hold_steps(false);
         check_done(s.srv, ia, *a);
         check_done(s.srv, ib, *b);
         CHECK(fake::max_batch() == 1 && fake::batches() == 33);
         const frt_server_stats st = stats(s.srv);
-        CHECK(st.max_in_flight == 2 && st.failed == 0 && st.peak_bytes <= 2 * bytes_of(*a));
+        CHECK(st.max_in_flight == 2);
+        CHECK(st.failed == 0);
+        CHECK(st.peak_bytes <= 2 * bytes_of(*a));
     }
     end("pass_queue_limit_steps_solves_alone", f0);
 }
