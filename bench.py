@@ -98,6 +98,56 @@ def valu_summary(db_dir: str, crossings_per_step: float, out_path: str):
     print(json.dumps(out))
 
 
+def measured_atomics(workload: str):
+    """The march's L2 atomic requests against the atomic microbenchmark's, from
+    the committed rocprofv3 counter summary, if it was taken on the current
+    kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"march_{workload}_atomics.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return {k: d[k] for k in ("march_l2_atomics_per_launch", "march_l2_atomics_per_s", "microbench_l2_atomics_per_s",
+                              "frac", "march_lds_atomic_instr_per_crossing")}
+
+
+def atomics_summary(db_dir: str, crossings_per_step: float, out_path: str):
+    """The march's atomic co-roofline from a rocprofv3 --pmc run of
+    TCC_ATOMIC_sum and SQ_INSTS_LDS_ATOMIC over this benchmark: L2 atomic
+    requests per second of the march launches of the last step against those
+    of the random-address FP32 atomic microbenchmark run before timing (its
+    best dispatch), and the march's LDS atomic wave-instructions per
+    crossing (times 64)."""
+    import glob
+    import sqlite3
+    dbs = glob.glob(os.path.join(db_dir, "**", "*.db"), recursive=True)
+    con = sqlite3.connect(dbs[0])
+    q = ("select dispatch_id, kernel_name, counter_name, sum(value), min(start), max(end) from counters_collection "
+         "group by dispatch_id, counter_name order by dispatch_id")
+    per = {}
+    for did, name, cname, val, t0, t1 in con.execute(q):
+        d = per.setdefault(did, {"name": name, "t0": t0, "t1": t1, "c": {}})
+        d["c"][cname] = val
+    ds = [per[k] for k in sorted(per)]
+    mb = [d for d in ds if "k_mb_atomic" in d["name"]]
+    mb_rate = max(d["c"].get("TCC_ATOMIC_sum", 0.0) / ((d["t1"] - d["t0"]) * 1e-9) for d in mb)
+    last_seed = max(i for i, d in enumerate(ds) if "k_seed<" in d["name"])
+    brick = [d for d in ds[last_seed:] if "k_brick" in d["name"]]
+    tcc = sum(d["c"].get("TCC_ATOMIC_sum", 0.0) for d in brick)
+    lds = sum(d["c"].get("SQ_INSTS_LDS_ATOMIC", 0.0) for d in brick)
+    secs = sum((d["t1"] - d["t0"]) * 1e-9 for d in brick)
+    out = {"kernel": "k_brick (march)", "kernel_source_hash": kernel_source_hash(), "launches": len(brick),
+           "march_l2_atomics_per_launch": tcc / max(len(brick), 1), "march_l2_atomics_per_s": tcc / secs,
+           "microbench_l2_atomics_per_s": mb_rate, "frac": (tcc / secs) / mb_rate,
+           "march_lds_atomic_instr_per_crossing": lds * 64 / crossings_per_step,
+           "kernel_seconds": secs}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps(out))
+
+
 def measured_traffic(workload: str):
     """HBM bytes per march launch from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
@@ -547,12 +597,19 @@ def main():
                          "calibrate the march kernel's (0 = skip)")
     ap.add_argument("--pmc-valu", nargs=2, metavar=("DB_DIR", "CROSSINGS_PER_STEP"),
                     help="write profiles/march_c3b_valu.json from a rocprofv3 --pmc run of the VALU counters")
+    ap.add_argument("--pmc-atomics", nargs=2, metavar=("DB_DIR", "CROSSINGS_PER_STEP"),
+                    help="write profiles/march_c3b_atomics.json from a rocprofv3 --pmc run of TCC_ATOMIC_sum and "
+                         "SQ_INSTS_LDS_ATOMIC")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/march_c3b_traffic.json from two rocprofv3 --pmc runs of this "
                          "benchmark (FETCH_SIZE, WRITE_SIZE) and exit")
     args = ap.parse_args()
     if args.pmc_valu:
         valu_summary(args.pmc_valu[0], float(args.pmc_valu[1]), os.path.join(ROOT, "profiles", "march_c3b_valu.json"))
+        return
+    if args.pmc_atomics:
+        atomics_summary(args.pmc_atomics[0], float(args.pmc_atomics[1]),
+                        os.path.join(ROOT, "profiles", "march_c3b_atomics.json"))
         return
     if args.pmc_summary:
         pmc_summary(args.pmc_summary[0], args.pmc_summary[1], args.copy_calibration_mib,
@@ -575,6 +632,11 @@ def main():
     stream = torch.cuda.Stream()          # default priority; the library enqueues on it
     torch.cuda.set_stream(stream)
     ctx = frt.Context(0)
+    # achievable device rates, the denominators beside the published peaks:
+    # a 2 GiB streaming copy and random FP32 atomics over 2^24 slots (the
+    # size of this workload's rate field)
+    mb = frt.microbench(ctx, 2 << 30, 1 << 24)
+    log(f"microbench: copy {mb['copy_GBps']:.0f} GB/s, FP32 atomics {mb['atomic_per_s']:.3e}/s at random addresses")
     # first size of the pass queues: the largest pass of this workload holds
     # 2.72e8 packets (reported as max_pass_packets); with a third more the
     # warm-up step never overflows and re-runs (64-byte records: 23 GB per queue)
@@ -639,8 +701,11 @@ def main():
             "algorithmic_ops_per_crossing": ALG_OPS_PER_CROSSING, "algorithmic_ops_per_launch": round(ops_per_launch),
             "hbm": {"achieved": round(hbm_achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": round(hbm_achieved / HBM_PEAK_GBS, 5), "algorithmic_bytes_per_launch": round(per_launch),
-                    "bytes": f"{ALG_BYTES_PER_CROSSING} B per crossing + {alg_bytes_per_visit(nb)} B per visit"},
-            "valu": measured_valu("c3b")}
+                    "bytes": f"{ALG_BYTES_PER_CROSSING} B per crossing + {alg_bytes_per_visit(nb)} B per visit",
+                    "achievable": round(mb["copy_GBps"], 1),
+                    "frac_of_achievable": round(hbm_achieved / mb["copy_GBps"], 5)},
+            "valu": measured_valu("c3b"),
+            "atomic": {"microbench_fp32_random_per_s": mb["atomic_per_s"], "counters": measured_atomics("c3b")}}
 
     out = {"metric": METRIC, "value": value, "unit": "crossings/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": total_ms / args.steps, "higher_is_better": True,

@@ -482,6 +482,24 @@ int frt_server_get_stats(frt_server srv, frt_server_stats* out);
  * everything the server holds. */
 int frt_server_destroy(frt_server srv);
 
+/* Achievable device rates, the denominators of the march's rooflines: HBM
+ * bandwidth from a streaming copy of copy_bytes (a multiple of 16, at least
+ * 1 MiB) into a second buffer, counted as bytes read plus written per
+ * second (the faster of two copy kernels: one 16-byte access per lane and
+ * iteration, or four in flight with non-temporal accesses); and FP32 atomic additions per second whose result is not used, at
+ * random addresses among atomic_slots floats (1024..2^32-1; the march
+ * deposits its rates that way), 64 per lane over 8 workgroups of 256 lanes
+ * per compute unit.  Each is the best of five timed runs after an untimed
+ * one.  The buffers (2 copy_bytes + 4 atomic_slots) come from the context's
+ * allocator and are freed before the call returns. */
+typedef struct {
+    size_t size;                    /* sizeof(frt_microbench_result) */
+    double copy_bytes, copy_GBps;   /* bytes of one copy; (read + written) bytes per s / 1e9 */
+    double atomic_ops, atomic_per_s, atomic_slots;
+} frt_microbench_result;
+
+int frt_microbench(frt_ctx ctx, size_t copy_bytes, size_t atomic_slots, frt_microbench_result* out);
+
 /* One ray through the solve's current opacity, for checking the march
  * against exact transmission (§4.1 Eq. tau_cell: a segment ds of cell i
  * passes exp(-(n_HI sigma_nu + kappa) ds) of its photons) and the deposits

@@ -9,7 +9,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libfrt.so")
-SOURCES = ["frt_kernels.hip", "frt_merge.hip", "frt_engine.cpp", "frt_server.cpp"]
+SOURCES = ["frt_kernels.hip", "frt_merge.hip", "frt_microbench.hip", "frt_engine.cpp", "frt_server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-munsafe-fp-atomics",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -2653,6 +2653,71 @@ int frt_debug_cast(frt_solve s, const double o_cm[3], const double d[3], const d
     return debug_cast_locked(s, o_cm, d, N_bins, dt_s, gamma_out, ptr_kind, absorbed, escaped, crossings);
 }
 
+int frt_microbench(frt_ctx ctx, size_t copy_bytes, size_t atomic_slots, frt_microbench_result* out)
+{
+    if (!ctx || !out) return fail(FRT_EINVAL, "null argument");
+    if (out->size != sizeof(frt_microbench_result)) return fail(FRT_EINVAL, "frt_microbench_result.size must be its sizeof");
+    if (copy_bytes < (1u << 20) || copy_bytes % 16) return fail(FRT_EINVAL, "copy_bytes must be a multiple of 16, at least 1 MiB");
+    if (atomic_slots < 1024 || atomic_slots > 0xffffffffull) return fail(FRT_EINVAL, "atomic_slots outside 1024..2^32-1");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    AllocScope scope(&ctx->al);
+    HIPCHK(hipSetDevice(ctx->device));
+    struct Bufs {
+        void *a = nullptr, *b = nullptr, *c = nullptr;
+        hipStream_t st = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        ~Bufs()
+        {
+            if (st) (void)hipStreamSynchronize(st);
+            dev_free_ptr(a);
+            dev_free_ptr(b);
+            dev_free_ptr(c);
+            if (e0) (void)hipEventDestroy(e0);
+            if (e1) (void)hipEventDestroy(e1);
+            if (st) (void)hipStreamDestroy(st);
+        }
+    } m;
+    RCCHK(dev_alloc(&m.a, copy_bytes));
+    RCCHK(dev_alloc(&m.b, copy_bytes));
+    RCCHK(dev_alloc(&m.c, atomic_slots * 4));
+    HIPCHK(hipStreamCreateWithFlags(&m.st, hipStreamNonBlocking));
+    HIPCHK(hipEventCreate(&m.e0));
+    HIPCHK(hipEventCreate(&m.e1));
+    HIPCHK(hipMemsetAsync(m.a, 0, copy_bytes, m.st));
+    HIPCHK(hipMemsetAsync(m.c, 0, atomic_slots * 4, m.st));
+    // the best of five timed runs after one untimed one
+    auto best_ms = [&](auto launch, double* best) -> int {
+        *best = -1.0;
+        for (int r = 0; r < 6; r++) {
+            HIPCHK(hipEventRecord(m.e0, m.st));
+            hipError_t e = launch();
+            if (e != hipSuccess) return fail(FRT_EDEVICE, "microbench launch: %s", hipGetErrorString(e));
+            HIPCHK(hipEventRecord(m.e1, m.st));
+            HIPCHK(hipEventSynchronize(m.e1));
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, m.e0, m.e1));
+            if (r > 0 && (*best < 0.0 || ms < *best)) *best = ms;
+        }
+        return FRT_OK;
+    };
+    double copy_ms = 0.0, atomic_ms = 0.0;
+    for (int v = 0; v < 2; v++) {
+        double ms = 0.0;
+        RCCHK(best_ms([&] { return frt::microbench_copy(m.a, m.b, copy_bytes, v, m.st); }, &ms));
+        if (v == 0 || ms < copy_ms) copy_ms = ms;
+    }
+    const int grid = frt::device_cu_count() * 8, per_lane = 64;
+    const double ops = (double)grid * 256.0 * per_lane;
+    RCCHK(best_ms([&] { return frt::microbench_atomic((float*)m.c, (uint32_t)atomic_slots, per_lane, grid, 12345u, m.st); },
+                  &atomic_ms));
+    out->copy_bytes = (double)copy_bytes;
+    out->copy_GBps = 2.0 * (double)copy_bytes / (copy_ms * 1e-3) / 1e9;
+    out->atomic_ops = ops;
+    out->atomic_per_s = ops / (atomic_ms * 1e-3);
+    out->atomic_slots = (double)atomic_slots;
+    return FRT_OK;
+}
+
 int frt_merge_uniforms(uint64_t seed, uint32_t step, uint32_t cell, double out[3])
 {
     if (!out) return fail(FRT_EINVAL, "null output");

@@ -332,6 +332,12 @@ hipError_t launch_snapshot(FrtSolveDesc* d, int n_solves, const uint32_t* halt, 
 // on the device and count the step in C_DONE, or, if the step raised an
 // error, set C_HALT instead.
 hipError_t launch_advance(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
+// Device-rate measurements (frt_microbench.hip): a streaming copy of
+// `bytes` (variant 0: one 16-byte access per lane and iteration; 1: four in
+// flight, non-temporal), and `per_lane` FP32 atomic additions per lane at
+// random slots.
+hipError_t microbench_copy(const void* a, void* b, size_t bytes, int variant, hipStream_t s);
+hipError_t microbench_atomic(float* buf, uint32_t slots, int per_lane, int grid, uint32_t seed, hipStream_t s);
 // Query launch shapes once, outside any stream capture.
 void prime_launch_shapes(int fp64, int n_bins, int has_sub, int has_heat);
 int device_cu_count();

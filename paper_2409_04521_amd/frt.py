@@ -31,7 +31,7 @@ EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_
            "frt_ctx_get_tuning", "frt_autotune", "frt_request_bytes", "frt_server_create", "frt_server_submit",
            "frt_server_poll", "frt_server_wait", "frt_server_take", "frt_server_times", "frt_server_get_stats",
            "frt_server_destroy", "frt_debug_cast", "frt_step_static", "frt_merge_uniforms",
-           "frt_read_temperature")
+           "frt_read_temperature", "frt_microbench")
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
@@ -74,6 +74,14 @@ class Timing(C.Structure):
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MicrobenchResult(C.Structure):
+    _fields_ = [("size", C.c_size_t), ("copy_bytes", C.c_double), ("copy_GBps", C.c_double),
+                ("atomic_ops", C.c_double), ("atomic_per_s", C.c_double), ("atomic_slots", C.c_double)]
+
+    def as_dict(self) -> dict:
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "size"}
 
 
 class Tuning(C.Structure):
@@ -175,6 +183,7 @@ def lib():
         L.frt_read_fields.argtypes = [vp, vp, vp, C.c_int]
         L.frt_read_ledger.argtypes = [vp, C.POINTER(Ledger)]
         L.frt_read_temperature.argtypes = [vp, vp, C.c_int]
+        L.frt_microbench.argtypes = [vp, C.c_size_t, C.c_size_t, C.POINTER(MicrobenchResult)]
         L.frt_save_state.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
         L.frt_load_state.argtypes = [vp, vp, C.c_size_t]
         L.frt_mark.argtypes = [vp]
@@ -446,6 +455,15 @@ def batch_run(solves, dts, n_steps: int, graph: bool = True, check_every: int = 
     replays) or launched step by step."""
     arr, d = _group(solves, dts)
     _check(lib().frt_batch_run(arr, len(solves), d, int(n_steps), int(check_every) if graph else 0))
+
+
+def microbench(ctx: Context, copy_bytes: int = 2 << 30, atomic_slots: int = 1 << 24) -> dict:
+    """Achievable HBM bandwidth (streaming copy) and random-address FP32
+    atomic rate of the context's device (frt_microbench)."""
+    r = MicrobenchResult()
+    r.size = C.sizeof(MicrobenchResult)
+    _check(lib().frt_microbench(ctx.h, int(copy_bytes), int(atomic_slots), C.byref(r)))
+    return r.as_dict()
 
 
 def autotune(solves, dts) -> dict:
