@@ -650,7 +650,7 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
 {
     // PER outputs per thread and round; the table has a slot for every
     // output of the round, so an insertion always finds one
-    constexpr int PER = 4;
+    constexpr int PER = 8;
     constexpr int SLOTS = PER * BLOCK;
     constexpr uint32_t EMPTY = 0xffffffffu;
     __shared__ uint32_t s_key[SLOTS], s_cnt[SLOTS], s_base[SLOTS];
@@ -668,7 +668,10 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
             s_key[i] = EMPTY;
             s_cnt[i] = 0;
         }
-        // the round's keys, all loads issued together
+        // the round's keys, all loads issued together; a round inside one
+        // output segment (the common case) needs no search for it
+        const int sg0 = find_in_prefix(s_sp, FRT_QSEG, base);
+        const bool one_seg = base + SLOTS <= s_sp[sg0 + 1];
         uint32_t idx[PER], kw[PER];
 #pragma unroll
         for (int q = 0; q < PER; q++) {
@@ -676,7 +679,7 @@ __global__ void __launch_bounds__(BLOCK) k_scatter(FrtWS ws)
             idx[q] = EMPTY;
             kw[q] = EMPTY;
             if (v < n) {
-                const int sg = find_in_prefix(s_sp, FRT_QSEG, v);
+                const int sg = one_seg ? sg0 : find_in_prefix(s_sp, FRT_QSEG, v);
                 idx[q] = (uint32_t)sg * scap + (v - s_sp[sg]);
                 kw[q] = keys[idx[q]];
             }
