@@ -62,10 +62,27 @@
  *                         (the photon ledger; per bin along one ray,
  *                         exactly); the paper's Test 2 (front beyond the
  *                         isothermal radius, ionized gas near 1e4 K).
- *   orc_rates             alpha_B(1e4 K) is the paper's 2.59e-13; the other
- *                         fits are those of the papers it cites (Hui &
- *                         Gnedin 1997, Cen 1992), restated, and beyond the
- *                         Test 2 check their values are parity unpinned.
+ *   orc_rates             alpha_B(1e4 K) is the paper's 2.59e-13; alpha_A
+ *                         lies within 3% of an independent fit (Verner &
+ *                         Ferland 1996) from 1e2 to 1e6 K and of the
+ *                         textbook 4.18e-13 at 1e4 K; the other fits are
+ *                         those of the papers it cites (Hui & Gnedin 1997,
+ *                         Cen 1992), restated, and beyond the Test 2 check
+ *                         their values are parity unpinned.
+ *   reion_heat_per_recombination  (§4.2, Eq. analytical_heating_HI) the
+ *                         mean energy above 1 Ryd of the photons HI absorbs
+ *                         from the cut power law, by quadrature.
+ *   ionized_temperature_update, mixed_temperature  (Generalized Opacity
+ *                         Mode, §4.2) gas the front ionizes enters at
+ *                         T_reion and mixes by volume with the older
+ *                         ionized gas, which cools as e^(-2 H t) where the
+ *                         radiative terms vanish; neutral cells keep T; the
+ *                         equilibrium temperature of highly ionized gas is
+ *                         the same from above and below and for any n_H and
+ *                         Gamma (heating and cooling both scale as n_e^2),
+ *                         rises as the spectrum hardens and lies between
+ *                         1e4 and 1e5 K; without photons (Gamma = 0) the
+ *                         Hubble term alone gives T0 e^(-2 H t).
  *   Whole-field values beyond these properties: parity unpinned (the paper
  *   prints no per-cell numbers).
  */
@@ -105,12 +122,17 @@ typedef struct {
     int merge_level;         /* l_merge: level of each cell's merging HEALPix sphere */
     double merge_exempt;     /* N_ex: floor(N_ex N_RT) brightest packets are exempt */
     int temperature;         /* 1: T evolves (§4.1, Eq. temp_evolution_standard) and the
-                                recombination and collisional ionization rates follow it;
+                                recombination and collisional ionization rates follow it
+                                (Generalized Opacity Mode: the ionized part's T, §4.2);
                                 0: alpha_B and coll_ion as given */
     double heat_ev[ORC_MAX_BINS]; /* mean energy above 13.6 eV left in the gas per photon
                                 of each bin that HI absorbs, eV */
     double hubble;           /* H(z) of the adiabatic cooling term, 1/s (0: none) */
     double cmb_z;            /* redshift of the CMB for Compton cooling (< 0: none) */
+    double t_reion;          /* Generalized Opacity Mode: temperature of gas the front
+                                ionizes, K */
+    double spectral_index;   /* Generalized Opacity Mode: power-law index alpha of the
+                                ionizing spectrum in its photo-heating estimate */
 } orc_params;
 
 typedef struct {
@@ -582,6 +604,8 @@ double chemistry_avg(double x0, double gamma, double ne, double alpha, double co
  *       (Cen 1992: 7.5e-19 e^(-118348/T) / (1 + (T/1e5)^0.5))
  *   [5] free-free cooling, erg cm^3/s (times n_e n_HII)
  *       (1.42e-27 g_ff T^0.5, g_ff = 1.1 + 0.34 exp(-(5.5 - log10 T)^2 / 3))
+ *   [6] alpha_A, case-A recombination coefficient, cm^3/s
+ *       (Hui & Gnedin 1997 fit: 1.269e-13 lambda^1.503 / (1 + (lambda/0.522)^0.470)^1.923)
  * Compton cooling off the CMB is 4 sigma_T a k T_CMB^4 (T - T_CMB) n_e /
  * (m_e c) with T_CMB = 2.725 (1 + z) K. */
 #define ORC_T_HI 157807.0
@@ -597,6 +621,7 @@ void orc_rates(double T, double* out)
     out[4] = 7.5e-19 * exp(-118348.0 / T) / (1.0 + sqrt(T / 1e5));
     const double lg = 5.5 - log10(T);
     out[5] = 1.42e-27 * (1.1 + 0.34 * exp(-lg * lg / 3.0)) * sqrt(T);
+    out[6] = 1.269e-13 * pow(lam, 1.503) / pow(1.0 + pow(lam / 0.522, 0.470), 1.923);
 }
 
 static double compton_coefficient(void)
@@ -610,7 +635,7 @@ static double compton_coefficient(void)
  * fraction x and photo-heating h (erg/cm^3/s) at temperature T. */
 static double net_heating(const orc_params* P, double T, double nH, double x, double h)
 {
-    double r[6];
+    double r[7];
     orc_rates(T, r);
     const double nHI = nH * x, ne = nH * (1.0 - x), nHII = ne;
     double L = r[2] * ne * nHII + (r[3] + r[4]) * ne * nHI + r[5] * ne * nHII;
@@ -653,6 +678,80 @@ double temperature_update(const orc_params* P, double T, double nH, double x0, d
         t += h;
     }
     return T;
+}
+
+/* Generalized Opacity Mode (§4.2, after Eq. dxidt): T is the temperature of
+ * each cell's ionized part.  Its n_HI is not known, so the rates that need
+ * it take photo-ionization equilibrium with the step's Gamma of the ionized
+ * gas (Eqs. equilibrium_condition and subgrid_nHI with alpha_B(T)):
+ * y = n_HI / n_H = min(1, alpha_B(T) n_H / Gamma), y = 1 where Gamma = 0,
+ * n_e = n_HII = n_H (1 - y), n_tot = n_H (2 - y).  The photo-heating is that
+ * of Eq. analytical_heating_HI, pure H:
+ *   H = E_HI q alpha_A(T) n_e n_HII,  q = s/(s-1) (1 - 4^(1-s)) / (1 - 4^-s) - 1,
+ * s = alpha + beta, beta = 2.75 (sigma_HI ~ nu^-beta), alpha the spectral
+ * index, E_HI = 1 Ryd: q E_HI is the mean energy above E_HI of the photons
+ * that HI absorbs from a power law nu^-alpha cut off at 4 Ryd.  The cooling
+ * is Standard Mode's. */
+#define ORC_RYD_EV 13.605693122994
+double reion_heat_per_recombination(double spectral_index)
+{
+    const double s = spectral_index + 2.75;
+    const double q = s / (s - 1.0) * (1.0 - pow(4.0, 1.0 - s)) / (1.0 - pow(4.0, -s)) - 1.0;
+    return q * ORC_RYD_EV * ORC_EV;
+}
+
+/* (H - Lambda) 2 / (3 k n_tot), K/s, of the ionized part of a cell at T. */
+static double ionized_dTdt(const orc_params* P, double T, double nH, double gamma)
+{
+    double r[7];
+    orc_rates(T, r);
+    const double y = (gamma > r[0] * nH) ? r[0] * nH / gamma : 1.0;
+    const double ne = nH * (1.0 - y), nHI = nH * y;
+    const double H = reion_heat_per_recombination(P->spectral_index) * r[6] * ne * ne;
+    double L = (r[2] + r[5]) * ne * ne + (r[3] + r[4]) * ne * nHI;
+    if (P->cmb_z >= 0.0) {
+        const double z1 = 1.0 + P->cmb_z;
+        L += compton_coefficient() * z1 * z1 * z1 * z1 * (T - 2.725 * z1) * ne;
+    }
+    return 2.0 * (H - L) / (3.0 * ORC_K_B * nH * (2.0 - y));
+}
+
+/* Temperature of the ionized part of a cell over one step: the Hubble term
+ * exactly (T -> T e^(-2 H dt)), then dT/dt = ionized_dTdt in the sub-steps
+ * of temperature_update (a tenth change in T at most, each the exact
+ * solution of the equation linearized about its start, at most 4096,
+ * T >= 1 K).  Static density: no compression term; y is an equilibrium
+ * value, so there is no particle-number term. */
+double ionized_temperature_update(const orc_params* P, double T, double nH, double gamma, double dt)
+{
+    if (P->hubble > 0.0) T *= exp(-2.0 * P->hubble * dt);
+    if (!(nH > 0.0)) return T;
+    double t = 0.0;
+    for (int k = 0; k < 4096 && t < dt; k++) {
+        const double f = ionized_dTdt(P, T, nH, gamma);
+        const double Te = T * (1.0 + 1e-6);
+        const double fp = (ionized_dTdt(P, Te, nH, gamma) - f) / (Te - T);
+        double h = dt - t;
+        if (fabs(f) * h > 0.1 * T) h = 0.1 * T / fabs(f);
+        const double yl = fp * h;
+        T += (fabs(yl) > 1e-8) ? f * expm1(yl) / fp : f * h;
+        if (T < 1.0) T = 1.0;
+        t += h;
+    }
+    return T;
+}
+
+/* A cell's temperature at the end of a step in which its ionized fraction
+ * went from xi0 to xi1: the part ionized before the step evolved at T_ion,
+ * the part ionized during it at T_reion, mixed by volume (both are ionized
+ * gas of the cell's n_H, so by particle number too); a cell with no ionized
+ * gas keeps its temperature. */
+static double mixed_temperature(const orc_params* P, double T, double nH, double gamma, double xi0, double xi1,
+                                double dt)
+{
+    const double T_ion = xi0 > 0.0 ? ionized_temperature_update(P, T, nH, gamma, dt) : T;
+    if (xi1 > xi0) return (xi0 * T_ion + (xi1 - xi0) * P->t_reion) / xi1;
+    return xi0 > 0.0 ? T_ion : T;
 }
 
 /* ------------------------------------------------------------- merging */
@@ -825,7 +924,7 @@ orc_state* orc_create(const orc_params* P, const float* nH, const float* kappa, 
 {
     if (!P || P->nx < 1 || P->ny < 1 || P->nz < 1 || P->n_bins < 1 || P->n_bins > ORC_MAX_BINS) return NULL;
     if (P->opacity_mode != 0 && P->opacity_mode != 1) return NULL;
-    if (P->temperature && P->opacity_mode != 0) return NULL;   /* Standard Mode only */
+    if (P->temperature && P->opacity_mode == 1 && !(P->t_reion > 0.0)) return NULL;
     orc_state* S = (orc_state*)calloc(1, sizeof(orc_state));
     if (!S) return NULL;
     S->p = *P;
@@ -939,8 +1038,8 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
             kap[i] = S->kappa[i];
         }
     }
-    double* hk = NULL;    /* per-chunk photo-heating, eV per cell (temperature on) */
-    if (P->temperature) {
+    double* hk = NULL;    /* per-chunk photo-heating, eV per cell (temperature on, Standard Mode) */
+    if (P->temperature && !gen) {
         hk = (double*)calloc((size_t)K * N, sizeof(double));
         if (!hk) return -1;
     }
@@ -950,7 +1049,7 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
     if (!alpha_c || !coll_c) return -1;
     for (long long i = 0; i < N; i++) {
         if (P->temperature) {
-            double r[6];
+            double r[7];
             orc_rates(S->T[i], r);
             alpha_c[i] = r[0];
             coll_c[i] = r[1];
@@ -974,11 +1073,13 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
         if (gen && P->chem_iterations > 0)
             for (long long i = 0; i < N; i++) {
                 /* equilibrium n_HI of the ionized gas from the last march's
-                 * Gamma (the previous step's at the first march); where no
-                 * rate is known yet the optically thin guess */
+                 * Gamma (the previous step's at the first march), with
+                 * alpha_B at the step's starting temperature when it
+                 * evolves; where no rate is known yet the optically thin
+                 * guess */
                 const double nH = S->nH[i], g = S->gamma[i];
                 double nhi = 0.0;
-                if (g > 0.0) nhi = (P->alpha_B * nH * nH < g * nH) ? P->alpha_B * nH * nH / g : nH;
+                if (g > 0.0) nhi = (alpha_c[i] * nH * nH < g * nH) ? alpha_c[i] * nH * nH / g : nH;
                 kap[i] = S->kappa[i] + P->sigma[0] * nhi;
             }
         if (it > 0) {
@@ -1119,6 +1220,7 @@ int orc_step(orc_state* S, double dt, const double* u, const double* umerge, int
                 xi = 1.0;
             }
             S->x[i] = 1.0 - xi;
+            if (P->temperature) S->T[i] = mixed_temperature(P, S->T[i], S->nH[i], S->gamma[i], xion[i], xi, dt);
         }
         const double ex = csum_get(&excess);
         S->L.absorbed_front -= ex;

@@ -45,7 +45,8 @@ class Params(C.Structure):
                 ("n_chunks", C.c_int), ("chem_iterations", C.c_int), ("opacity_mode", C.c_int),
                 ("he_chi", C.c_double), ("merge", C.c_int), ("merge_level", C.c_int),
                 ("merge_exempt", C.c_double), ("temperature", C.c_int), ("heat_ev", C.c_double * MAX_BINS),
-                ("hubble", C.c_double), ("cmb_z", C.c_double)]
+                ("hubble", C.c_double), ("cmb_z", C.c_double), ("t_reion", C.c_double),
+                ("spectral_index", C.c_double)]
 
 
 class Ledger(C.Structure):
@@ -109,6 +110,11 @@ def lib():
         L.temperature_update.restype = C.c_double
         L.temperature_update.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_double]
+        L.reion_heat_per_recombination.restype = C.c_double
+        L.reion_heat_per_recombination.argtypes = [C.c_double]
+        L.ionized_temperature_update.restype = C.c_double
+        L.ionized_temperature_update.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double,
+                                                 C.c_double]
         _lib = L
     return _lib
 
@@ -161,11 +167,25 @@ def chemistry_avg(x0, gamma, ne, alpha, coll, dt):
 
 
 def rates(T: float) -> dict:
-    """The temperature-dependent rates of pure H at T (K): alpha_B and C_HI
-    (cm^3/s) and the cooling coefficients (erg cm^3/s)."""
-    out = np.zeros(6)
+    """The temperature-dependent rates of pure H at T (K): alpha_B, C_HI and
+    alpha_A (cm^3/s) and the cooling coefficients (erg cm^3/s)."""
+    out = np.zeros(7)
     lib().orc_rates(float(T), out)
-    return dict(zip(("alpha_B", "coll_ion", "rec_cool", "ci_cool", "ce_cool", "ff_cool"), out))
+    return dict(zip(("alpha_B", "coll_ion", "rec_cool", "ci_cool", "ce_cool", "ff_cool", "alpha_A"), out))
+
+
+def reion_heat_per_recombination(spectral_index: float) -> float:
+    """Photo-heating per recombination of ionized gas in photo-ionization
+    equilibrium under a power law of this index cut at 4 Ryd, erg."""
+    return float(lib().reion_heat_per_recombination(float(spectral_index)))
+
+
+def ionized_temperature(T, nH, gamma, dt, spectral_index=1.5, hubble_s=0.0, cmb_z=-1.0) -> float:
+    """One step of the ionized gas's temperature in the Generalized Opacity
+    Mode at fixed n_H and Gamma."""
+    P = Params()
+    P.temperature, P.opacity_mode, P.spectral_index, P.hubble, P.cmb_z = 1, 1, spectral_index, hubble_s, cmb_z
+    return float(lib().ionized_temperature_update(C.byref(P), float(T), float(nH), float(gamma), float(dt)))
 
 
 # ------------------------------------------------------------- the solver
@@ -176,7 +196,7 @@ class Oracle:
                  coll_ion=0.0, base_level=0, max_level=12, n_ray_min=1.0, flux_floor=0.0,
                  max_dist_cm=0.0, c_ray=np.inf, n_chunks=16, chem_iterations=0, opacity_mode=0, he_chi=0.0,
                  merge=False, merge_level=0, merge_exempt=0.0, temperature=False, heat_ev=None, hubble_s=0.0,
-                 cmb_z=-1.0, T0=None):
+                 cmb_z=-1.0, T0=None, t_reion=2e4, spectral_index=1.5):
         nz, ny, nx = shape
         sig = list(sigma_bins)
         P = Params()
@@ -191,6 +211,7 @@ class Oracle:
         P.opacity_mode, P.he_chi = opacity_mode, he_chi
         P.merge, P.merge_level, P.merge_exempt = int(bool(merge)), merge_level, merge_exempt
         P.temperature, P.hubble, P.cmb_z = int(bool(temperature)), hubble_s, cmb_z
+        P.t_reion, P.spectral_index = t_reion, spectral_index
         for i, e in enumerate(heat_ev if heat_ev is not None else []):
             P.heat_ev[i] = e
         self.P = P

@@ -204,6 +204,8 @@ class Problem:
     heat_ev: np.ndarray | None = None # (n_bins,) eV above 13.6 eV per photon HI absorbs
     hubble_s: float = 0.0             # H(z) of the adiabatic term, 1/s
     cmb_z: float = -1.0               # CMB redshift of Compton cooling (< 0: none)
+    t_reion: float = 2e4              # Generalized Opacity Mode: K of gas the front ionizes
+    spectral_index: float = 1.5       # Generalized Opacity Mode: power-law index of its heating
     meta: dict = field(default_factory=dict)
 
     @property
@@ -230,7 +232,8 @@ class Problem:
                     chem_iterations=self.chem_iterations, opacity_mode=self.opacity_mode,
                     he_chi=self.he_chi, merge=self.merge, merge_level=self.merge_level,
                     merge_exempt=self.merge_exempt, temperature=self.temperature, heat_ev=self.heat_ev,
-                    hubble_s=self.hubble_s, cmb_z=self.cmb_z,
+                    hubble_s=self.hubble_s, cmb_z=self.cmb_z, t_reion=self.t_reion,
+                    spectral_index=self.spectral_index,
                     T0=None if self.T is None else np.asarray(self.T, dtype=np.float64))
 
     def merge_uniforms(self, step: int):
