@@ -144,8 +144,8 @@ typedef struct {
     int merge_level;                /* l_merge, 0..8 (default 0) */
     double merge_exempt;            /* N_ex, exempt packets per cell, >= 0 (default 4) */
     int temperature;                /* 1: the gas temperature evolves (§4.1, Eq.
-                                       temp_evolution_standard, static density; Standard Mode
-                                       only): each bin's photons absorbed by HI (not by the
+                                       temp_evolution_standard, static density).  Standard Mode:
+                                       each bin's photons absorbed by HI (not by the
                                        sub-grid absorbers) leave heat_ev of the bin each in the
                                        cell; the hydrogen update takes case-B recombination and
                                        collisional ionization at the cell's temperature of the
@@ -157,14 +157,34 @@ typedef struct {
                                        cmb_z >= 0) Compton cooling over the step, in sub-steps of at
                                        most a tenth change in T, each solved exactly for the
                                        equation linearized about its start.  With chem_iterations K
-                                       only the last march's heating counts.  A solve with the
-                                       temperature on marches with 16^3 bricks in FP32.
+                                       only the last march's heating counts.  Generalized
+                                       Opacity Mode (§4.2): T is the temperature of each cell's
+                                       ionized part.  Gas that the front ionizes in a step
+                                       enters at t_reion_k and mixes by volume with the older
+                                       ionized gas, which cools by e^(-2 H dt) and follows
+                                       photo-heating minus the same cooling over the step (in
+                                       the same sub-steps) with n_HI / n_H = y = min(1,
+                                       alpha_B(T) n_H / Gamma) from photo-ionization equilibrium
+                                       with the step's Gamma (y = 1 where Gamma = 0), n_e =
+                                       n_HII = n_H (1 - y), n_tot = n_H (2 - y), and the
+                                       photo-heating of Eq. analytical_heating_HI for a power
+                                       law of index spectral_index cut at 4 Ryd (case-A
+                                       recombination, Hui & Gnedin 1997); heat_ev is unused and
+                                       the opacity iteration takes alpha_B(T); cells with no
+                                       ionized gas keep T.  A solve with the temperature on
+                                       marches with 16^3 bricks in FP32.
                                        0 (default): T fixed */
     double heat_ev[FRT_MAX_BINS];   /* energy above 13.6 eV left in the gas per photon of each
                                        bin that HI absorbs, eV (finite, >= 0) */
     double hubble_s;                /* H(z) of the adiabatic term, 1/s (finite, >= 0; default 0) */
     double cmb_z;                   /* redshift of the CMB for Compton cooling; < 0: none
                                        (default -1) */
+    double t_reion_k;               /* Generalized Opacity Mode with the temperature on:
+                                       temperature of gas the front ionizes, K (finite, > 0;
+                                       default 2e4) */
+    double spectral_index;          /* Generalized Opacity Mode with the temperature on:
+                                       power-law index alpha of the ionizing spectrum in the
+                                       photo-heating estimate (finite, >= 0; default 1.5) */
 } frt_params;
 
 /* Cumulative photon ledger (photons) and counters of one solve.  With
@@ -188,14 +208,17 @@ typedef struct {
     double front_excess;            /* photons stopped at I-fronts beyond the neutral atoms their
                                        cells had left; they ionize nothing (absorbed_front counts
                                        the photons that did) */
-    double heat_in;                 /* photo-heating given to the gas, erg (temperature on) */
+    double heat_in;                 /* photo-heating the march gave the gas, erg (temperature
+                                       on, Standard Mode; 0 in the Generalized Opacity Mode) */
 } frt_ledger;
 
 /* Fill *p with defaults: 1 bin at 6.3e-18 cm^2, alpha_B = 2.59e-13,
  * coll_ion = 0, base_level 0, max_level 12, n_ray_min 1, no floor, no cap,
  * c_ray = speed of light, FRT_F32, seed 0, automatic queues, no hint,
  * backward-Euler chemistry (chem_iterations 0), FRT_STANDARD opacity, he_chi 0,
- * no merging (merge 0; merge_level 0 and merge_exempt 4 when it is on). */
+ * no merging (merge 0; merge_level 0 and merge_exempt 4 when it is on),
+ * temperature 0 (heat_ev 0, hubble_s 0, cmb_z -1, t_reion_k 2e4,
+ * spectral_index 1.5). */
 int frt_params_default(frt_params* p);
 
 /* Device memory hooks: alloc returns `bytes` of device memory of the

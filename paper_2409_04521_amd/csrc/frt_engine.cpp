@@ -506,6 +506,19 @@ int read_device_ledger(frt_solve s, FrtLedgerDev* out)
 // then part of its state (checkpoints and bookmarks keep it).
 bool warm_rate(frt_solve s) { return s->P.opacity_mode == FRT_GENERALIZED && s->P.chem_iterations > 0; }
 
+// Photo-heating per recombination of ionized gas in photo-ionization
+// equilibrium (§4.2, Eq. analytical_heating_HI), erg: 1 Ryd times the mean
+// energy above 1 Ryd, in Ryd, of the photons HI absorbs from a spectrum
+// J_nu ~ nu^-alpha cut off at 4 Ryd when sigma_HI ~ nu^-2.75.  With
+// p = alpha + 2.75 that mean is
+//   int_1^4 x^-p dx / int_1^4 x^-(p+1) dx - 1 = p/(p-1) (1 - 4^(1-p)) / (1 - 4^-p) - 1.
+double reion_heat_per_recombination(double alpha)
+{
+    const double p = alpha + 2.75;
+    const double mean = p / (p - 1.0) * (1.0 - std::pow(4.0, 1.0 - p)) / (1.0 - std::pow(4.0, -p));
+    return (mean - 1.0) * 13.605693122994 * 1.602176634e-12;
+}
+
 int ready(frt_solve s)
 {
     if (!s) return fail(FRT_EINVAL, "null solve");
@@ -666,9 +679,11 @@ void plan_group(Workspace& ws, frt_solve* ss, int n, Group& g)
     w.n_bins = ss[0]->P.n_bins;
     w.has_sub = 0;
     w.has_heat = 0;
+    w.has_temp = 0;
     for (int i = 0; i < n; i++) {
         w.has_sub |= ss[i]->h.has_sub;
-        w.has_heat |= ss[i]->h.temp;
+        w.has_heat |= ss[i]->h.heat != nullptr;
+        w.has_temp |= ss[i]->h.temp;
     }
     // the 1024-thread march (FP32 without sub-grid opacity) takes
     // FRT_BIG_ITEM_SCALE times the tuned item size
@@ -717,7 +732,7 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
     const int n_march = K > 0 ? K : 1;
     if (K > 0) {
         Timed t(tm, st, 2);
-        if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_heat, 0, w.ctr + C_ERR, halt, st)) != hipSuccess)
+        if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_temp, 0, w.ctr + C_ERR, halt, st)) != hipSuccess)
             return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
     }
     for (int it = 0; it < n_march; it++) {
@@ -752,14 +767,14 @@ int enqueue_step(Workspace& ws, frt_solve* ss, int n, const Group& g, hipStream_
         }
         if (it + 1 < n_march) {
             Timed t(tm, st, 2);
-            if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_heat, 1, w.ctr + C_ERR, halt, st)) != hipSuccess)
+            if ((e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_temp, 1, w.ctr + C_ERR, halt, st)) != hipSuccess)
                 return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         }
     }
     {
         Timed t(tm, st, 2);
-        if (K > 0) e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_heat, 2, w.ctr + C_ERR, halt, st);
-        else e = frt::launch_chem(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_heat, w.ctr + C_ERR, st);
+        if (K > 0) e = frt::launch_chem_avg(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_temp, 2, w.ctr + C_ERR, halt, st);
+        else e = frt::launch_chem(ws.descs, ws.cell_prefix, n, g.cp[n], fp64, w.has_temp, w.ctr + C_ERR, st);
         if (e != hipSuccess) return fail(FRT_EDEVICE, "chem: %s", hipGetErrorString(e));
         if (tm) tm->n_chem++;
     }
@@ -1162,7 +1177,7 @@ int run_group_graph_locked(frt_solve* ss, int n, const double* dts, int n_steps,
         // rotations of every step of the run exist before the capture
         RCCHK(ensure_quat(ss[i], ss[i]->step + (uint32_t)n_steps));
         has_sub |= ss[i]->h.has_sub;
-        has_heat |= ss[i]->h.temp;
+        has_heat |= ss[i]->h.heat != nullptr;
     }
     frt::prime_launch_shapes(ss[0]->fp64, ss[0]->P.n_bins, has_sub, has_heat);
     StepGraph sg;
@@ -1542,7 +1557,8 @@ uint64_t solve_bytes(const frt_params& P, uint64_t ncell, int n_src, int with_T,
     // the time-averaged chemistry, front photons of the Generalized Opacity
     // Mode, photo-heating of the temperature evolution
     uint64_t b = ncell * (4 * rs + 16 + ((with_T || P.temperature) ? 8 : 0) + (P.chem_iterations > 0 ? 8 : 0) +
-                          (P.opacity_mode == FRT_GENERALIZED ? 8 : 0) + (P.temperature ? rs : 0));
+                          (P.opacity_mode == FRT_GENERALIZED ? 8 : 0) +
+                          ((P.temperature && P.opacity_mode == FRT_STANDARD) ? rs : 0));
     // carried-packet queues (as first sized)
     double F = (double)cast + 1024;
     if (std::isfinite(P.c_ray_cm_s)) F += std::min((double)ncell, 8.0 * cast + 65536.0);
@@ -1614,6 +1630,8 @@ int frt_params_default(frt_params* p)
     p->temperature = 0;
     p->hubble_s = 0.0;
     p->cmb_z = -1.0;
+    p->t_reion_k = 2e4;
+    p->spectral_index = 1.5;
     return FRT_OK;
 }
 
@@ -1672,8 +1690,9 @@ int frt_solve_create(frt_ctx ctx, const frt_params* P, void* hip_stream, frt_sol
     if (P->merge_level < 0 || P->merge_level > 8) return fail(FRT_EINVAL, "merge_level %d outside 0..8", P->merge_level);
     if (!(P->merge_exempt >= 0) || !std::isfinite(P->merge_exempt)) return fail(FRT_EINVAL, "merge_exempt must be finite and >= 0");
     if (P->temperature != 0 && P->temperature != 1) return fail(FRT_EINVAL, "temperature must be 0 or 1");
-    if (P->temperature && P->opacity_mode != FRT_STANDARD)
-        return fail(FRT_EINVAL, "temperature evolution is for the Standard Mode only");
+    if (!(P->t_reion_k > 0) || !std::isfinite(P->t_reion_k)) return fail(FRT_EINVAL, "t_reion_k must be finite and > 0");
+    if (!(P->spectral_index >= 0) || !std::isfinite(P->spectral_index))
+        return fail(FRT_EINVAL, "spectral_index must be finite and >= 0");
     for (int b = 0; b < P->n_bins; b++)
         if (!(P->heat_ev[b] >= 0) || !std::isfinite(P->heat_ev[b])) return fail(FRT_EINVAL, "heat_ev[%d] must be finite and >= 0", b);
     if (!(P->hubble_s >= 0) || !std::isfinite(P->hubble_s)) return fail(FRT_EINVAL, "hubble_s must be finite and >= 0");
@@ -1799,7 +1818,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     if (gen) RCCHK(dev_alloc((void**)&s->front, n * 8));
     RCCHK(dev_alloc((void**)&s->nH, n * 8));
     if (T || temp) RCCHK(dev_alloc((void**)&s->T, n * 8));
-    if (temp) RCCHK(dev_alloc(&s->heat, n * s->rs));
+    if (temp && !gen) RCCHK(dev_alloc(&s->heat, n * s->rs));   // the march's photo-heating
     s->nx = nx; s->ny = ny; s->nz = nz;
     s->ncell = n;
     s->dx = box_cm / nx;
@@ -1850,7 +1869,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
             for (size_t i = 0; i < n; i++) Td[i] = (double)hT[i];
         RCCHK(scopy(s, s->T, Td.data(), n * 8, hipMemcpyHostToDevice));
     }
-    if (temp) RCCHK(sset(s, s->heat, 0, n * s->rs));
+    if (s->heat) RCCHK(sset(s, s->heat, 0, n * s->rs));
     RCCHK(sset(s, s->gam[0], 0, n * s->rs));
     RCCHK(sset(s, s->gam[1], 0, n * s->rs));
     if (s->vcount) RCCHK(sset(s, s->vcount, 0, 8));
@@ -1864,9 +1883,11 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     h.temp = temp ? 1 : 0;
     h.T = temp ? s->T : nullptr;
     h.heat = s->heat;
-    for (int b = 0; b < FRT_MAX_BINS_I; b++) h.heat_ev[b] = b < s->P.n_bins ? s->P.heat_ev[b] : 0.0;
+    for (int b = 0; b < FRT_MAX_BINS_I; b++) h.heat_ev[b] = (b < s->P.n_bins && !gen) ? s->P.heat_ev[b] : 0.0;
     h.hubble = s->P.hubble_s;
     h.cmb_z = s->P.cmb_z;
+    h.t_reion = s->P.t_reion_k;
+    h.heat_rec = reion_heat_per_recombination(s->P.spectral_index);
     h.gen = gen ? 1 : 0;
     h.front_atoms = (1.0 + s->P.he_chi) * s->dx * s->dx * s->dx;
     h.front = s->front;

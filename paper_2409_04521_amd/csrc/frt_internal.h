@@ -202,6 +202,10 @@ struct FrtSolveDesc {
     double heat_ev[FRT_MAX_BINS_I];
     double hubble;              // H(z) of the adiabatic term, 1/s
     double cmb_z;               // CMB redshift of Compton cooling (< 0: none)
+    // Generalized Opacity Mode: temperature of gas the front ionizes (K) and
+    // the photo-heating per case-A recombination of the ionized gas (erg)
+    double t_reion;
+    double heat_rec;
 };
 
 // One work item of a pass: up to FRT_ITEM_RAYS packets of one brick.
@@ -249,7 +253,8 @@ struct FrtWS {
     int n_solves;
     int n_bins;
     int has_sub;                // some solve of the launch has sub-grid opacity
-    int has_heat;               // some solve of the launch evolves its temperature
+    int has_heat;               // some solve of the launch takes photo-heating from the march
+    int has_temp;               // some solve of the launch evolves its temperature
     // launch shape (tunable)
     uint32_t item_rays;         // packets per work item, 64..FRT_ITEM_RAYS
     int scatter_bpc;            // workgroups per CU of the scatter pass

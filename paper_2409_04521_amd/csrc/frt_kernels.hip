@@ -1730,25 +1730,17 @@ __device__ double net_gain(const FrtSolveDesc& D, double T, double nH, double x,
     return heat - cool;
 }
 
-// T at the end of a step in which x went from x0 to x1 (n_tot = n_H (2 - x)):
-// n_tot T kept over the change of particle number, e^(-2 H dt) for the
-// Hubble term, then dT/dt = 2 (heat - cool) / (3 k n_tot) at x1 over dt in
-// sub-steps that change T by at most a tenth, each solving the equation
-// linearized about its start exactly (the slope from a relative step of 1e-6
-// in T); at most 4096 sub-steps, T >= 1 K.
-__device__ double evolve_temperature(const FrtSolveDesc& D, double T, double nH, double x0, double x1, double heat)
+// dT/dt = rate(T) over dt in sub-steps that change T by at most a tenth,
+// each solving the equation linearized about its start exactly (the slope
+// from a relative step of 1e-6 in T); at most 4096 sub-steps, T >= 1 K.
+template <typename F>
+__device__ __forceinline__ double substep_temperature(double T, double dt, F&& rate)
 {
-    const double n0 = nH * (2.0 - x0), n1 = nH * (2.0 - x1);
-    if (n1 > 0.0) T = T * (n0 / n1);
-    if (D.hubble > 0.0) T = T * exp(-2.0 * D.hubble * D.dt);
-    if (!(n1 > 0.0)) return T;
-    const double c = 2.0 / (3.0 * kBoltz * n1);
-    const double dt = D.dt;
     double t = 0.0;
     for (int k = 0; k < 4096 && t < dt; k++) {
-        const double f = c * net_gain(D, T, nH, x1, heat);
+        const double f = rate(T);
         const double Tp = T * (1.0 + 1e-6);
-        const double slope = (c * net_gain(D, Tp, nH, x1, heat) - f) / (Tp - T);
+        const double slope = (rate(Tp) - f) / (Tp - T);
         double h = dt - t;
         if (fabs(f) * h > 0.1 * T) h = 0.1 * T / fabs(f);
         const double y = slope * h;
@@ -1757,6 +1749,61 @@ __device__ double evolve_temperature(const FrtSolveDesc& D, double T, double nH,
         t += h;
     }
     return T;
+}
+
+// T at the end of a step in which x went from x0 to x1 (n_tot = n_H (2 - x)):
+// n_tot T kept over the change of particle number, e^(-2 H dt) for the
+// Hubble term, then dT/dt = 2 (heat - cool) / (3 k n_tot) at x1 over dt.
+__device__ double evolve_temperature(const FrtSolveDesc& D, double T, double nH, double x0, double x1, double heat)
+{
+    const double n0 = nH * (2.0 - x0), n1 = nH * (2.0 - x1);
+    if (n1 > 0.0) T = T * (n0 / n1);
+    if (D.hubble > 0.0) T = T * exp(-2.0 * D.hubble * D.dt);
+    if (!(n1 > 0.0)) return T;
+    const double c = 2.0 / (3.0 * kBoltz * n1);
+    return substep_temperature(T, D.dt, [&](double Tv) { return c * net_gain(D, Tv, nH, x1, heat); });
+}
+
+// Case-A recombination coefficient of H (Hui & Gnedin 1997), cm^3/s.
+__device__ double alpha_case_a(double T)
+{
+    const double lam = 2.0 * kTHI / T;
+    return 1.269e-13 * pow(lam, 1.503) / pow(1.0 + pow(lam / 0.522, 0.470), 1.923);
+}
+
+// Generalized Opacity Mode (§4.2): dT/dt of a cell's ionized part at T, K/s,
+// with n_HI from photo-ionization equilibrium with its rate G: y = n_HI /
+// n_H = min(1, alpha_B(T) n_H / G) (1 where G = 0), n_e = n_HII = n_H (1 - y);
+// photo-heating heat_rec alpha_A(T) n_e n_HII (Eq. analytical_heating_HI)
+// minus the cooling of Standard Mode, over 3/2 k n_tot, n_tot = n_H (2 - y).
+__device__ double ionized_dTdt(const FrtSolveDesc& D, double T, double nH, double G)
+{
+    const HRates r = h_rates(T);
+    const double y = G > r.alpha * nH ? r.alpha * nH / G : 1.0;
+    const double ne = nH * (1.0 - y), nHI = nH * y;
+    double gain = D.heat_rec * alpha_case_a(T) * ne * ne - (r.rec + r.ff) * ne * ne - (r.ci + r.ce) * ne * nHI;
+    if (D.cmb_z >= 0.0) {
+        const double z1 = 1.0 + D.cmb_z, z4 = z1 * z1 * z1 * z1;
+        gain -= kCompton0 * z4 * (T - 2.725 * z1) * ne;
+    }
+    return 2.0 * gain / (3.0 * kBoltz * nH * (2.0 - y));
+}
+
+// A cell's temperature at the end of a step in which its ionized fraction
+// went from xi0 to xi1 (Generalized Opacity Mode): the part ionized before
+// the step cools by e^(-2 H dt) and then follows ionized_dTdt with the
+// step's rate G; the part the front ionized during the step enters at
+// T_reion; the two mix by volume (ionized gas of one n_H: by particle number
+// too).  A cell with no ionized gas keeps its temperature.
+__device__ double front_cell_temperature(const FrtSolveDesc& D, double T, double nH, double G, double xi0, double xi1)
+{
+    double Ti = T;
+    if (xi0 > 0.0) {
+        if (D.hubble > 0.0) Ti = Ti * exp(-2.0 * D.hubble * D.dt);
+        if (nH > 0.0) Ti = substep_temperature(Ti, D.dt, [&](double Tv) { return ionized_dTdt(D, Tv, nH, G); });
+    }
+    if (xi1 > xi0) return (xi0 * Ti + (xi1 - xi0) * D.t_reion) / xi1;
+    return Ti;
 }
 
 // The step's photo-heating rate of cell i (erg/cm^3/s) that the march
@@ -1785,9 +1832,11 @@ __device__ __forceinline__ Real staged_ionized_fraction(double xi)
 // photon stopped at the cell's front ionizes 1 + chi atoms; x_ion is at
 // most 1 and never decreases; x = 1 - x_ion is the neutral volume fraction.
 // Photons beyond the atoms the cell had left ionize nothing: they move from
-// the ledger's absorbed_front to front_excess.  Clears the front count.
-template <typename Real>
-__device__ __forceinline__ void moving_screen(const FrtSolveDesc& D, size_t i)
+// the ledger's absorbed_front to front_excess.  Clears the front count.  With
+// the temperature on, the cell's T follows (front_cell_temperature, with G
+// the step's rate of the ionized gas).
+template <typename Real, bool TEMP>
+__device__ __forceinline__ void moving_screen(const FrtSolveDesc& D, size_t i, double G)
 {
     const double atoms = D.front_atoms * D.nH[i];
     const double f = D.front[i];
@@ -1810,6 +1859,7 @@ __device__ __forceinline__ void moving_screen(const FrtSolveDesc& D, size_t i)
     D.x[i] = 1.0 - xi;
     ((Real*)D.op_bw)[i] = staged_ionized_fraction<Real>(xi);
     D.front[i] = 0.0;
+    if (TEMP && D.temp) D.T[i] = front_cell_temperature(D, D.T[i], D.nH[i], G, xion, xi);
 }
 
 // Every cell of every solve of a launch, one per thread, in chunks of
@@ -1864,7 +1914,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem(const FrtSolveDesc* __restrict__
         Real* gcur = (Real*)D.gamma[D.step & 1u];
         Real* gnext = (Real*)D.gamma[(D.step + 1u) & 1u];
         if (D.gen) {
-            moving_screen<Real>(D, i);
+            moving_screen<Real, TEMP>(D, i, (double)gcur[i]);
             gnext[i] = Real(0);
             return;
         }
@@ -1921,7 +1971,7 @@ __global__ void __launch_bounds__(BLOCK) k_chem_avg(const FrtSolveDesc* __restri
         if (D.gen) {
             Real* gcur = (Real*)D.gamma[D.step & 1u];
             if (phase == 2) {
-                moving_screen<Real>(D, i);
+                moving_screen<Real, TEMP>(D, i, (double)gcur[i]);
                 ((Real*)D.gamma[(D.step + 1u) & 1u])[i] = Real(0);
                 return;
             }
@@ -1930,11 +1980,13 @@ __global__ void __launch_bounds__(BLOCK) k_chem_avg(const FrtSolveDesc* __restri
             // sigma_0 dx n_HI of photo-ionization equilibrium (§5.1, Eqs.
             // subgrid_lambda and subgrid_nHI) with the last rate, the
             // previous step's before the first march; where no rate is
-            // known the optically thin guess (n_HI = 0)
+            // known the optically thin guess (n_HI = 0); alpha_B at the
+            // step's starting temperature when it evolves
             const double g = (double)((const Real*)D.gamma[phase == 0 ? (D.step + 1u) & 1u : D.step & 1u])[i];
             const double nH = D.nH[i];
+            const double ab = (TEMP && D.temp) ? h_rates(D.T[i]).alpha : D.alpha_B;
             double nhi = 0.0;
-            if (g > 0.0) nhi = (D.alpha_B * nH * nH < g * nH) ? D.alpha_B * nH * nH / g : nH;
+            if (g > 0.0) nhi = (ab * nH * nH < g * nH) ? ab * nH * nH / g : nH;
             ((Real*)D.op_aw)[i] = hi_opacity<Real>((double)((const Real*)D.kin)[i] + D.sigma0 * nhi * D.dx_cm);
             if (phase == 1) {
                 gcur[i] = Real(0);

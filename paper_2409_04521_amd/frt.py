@@ -50,7 +50,7 @@ class Params(C.Structure):
                 ("chem_iterations", C.c_int), ("opacity_mode", C.c_int), ("he_chi", C.c_double),
                 ("merge", C.c_int), ("merge_level", C.c_int), ("merge_exempt", C.c_double),
                 ("temperature", C.c_int), ("heat_ev", C.c_double * MAX_BINS), ("hubble_s", C.c_double),
-                ("cmb_z", C.c_double)]
+                ("cmb_z", C.c_double), ("t_reion_k", C.c_double), ("spectral_index", C.c_double)]
 
 
 class Ledger(C.Structure):
@@ -303,7 +303,7 @@ class Solve:
                  max_level=12, n_ray_min=1.0, flux_floor=0.0, max_distance_cm=0.0, c_ray=2.99792458e10,
                  precision="f32", seed=0, queue_capacity=0, queue_hint=0, chem_iterations=0, opacity_mode=0,
                  he_chi=0.0, merge=False, merge_level=0, merge_exempt=4.0, temperature=False, heat_ev=None,
-                 hubble_s=0.0, cmb_z=-1.0, stream=None):
+                 hubble_s=0.0, cmb_z=-1.0, t_reion=2e4, spectral_index=1.5, stream=None):
         p = params_default()
         sig = list(sigma_bins)
         p.n_bins = len(sig)
@@ -319,6 +319,7 @@ class Solve:
         p.opacity_mode, p.he_chi = opacity_mode, he_chi
         p.merge, p.merge_level, p.merge_exempt = int(bool(merge)), merge_level, merge_exempt
         p.temperature, p.hubble_s, p.cmb_z = int(bool(temperature)), hubble_s, cmb_z
+        p.t_reion_k, p.spectral_index = t_reion, spectral_index
         for i, e in enumerate(heat_ev if heat_ev is not None else []):
             p.heat_ev[i] = e
         self.ctx = ctx
@@ -501,6 +502,8 @@ def _params_for(prob, precision="f32", **kw) -> Params:
         p.heat_ev[i] = e
     p.hubble_s = getattr(prob, "hubble_s", 0.0)
     p.cmb_z = getattr(prob, "cmb_z", -1.0)
+    p.t_reion_k = getattr(prob, "t_reion", 2e4)
+    p.spectral_index = getattr(prob, "spectral_index", 1.5)
     return p
 
 
@@ -618,7 +621,8 @@ def solve_from_problem(ctx: Context, prob, precision="f32", use_table=True, **kw
               merge=getattr(prob, "merge", False), merge_level=getattr(prob, "merge_level", 0),
               merge_exempt=getattr(prob, "merge_exempt", 4.0), temperature=getattr(prob, "temperature", False),
               heat_ev=getattr(prob, "heat_ev", None), hubble_s=getattr(prob, "hubble_s", 0.0),
-              cmb_z=getattr(prob, "cmb_z", -1.0), **kw)
+              cmb_z=getattr(prob, "cmb_z", -1.0), t_reion=getattr(prob, "t_reion", 2e4),
+              spectral_index=getattr(prob, "spectral_index", 1.5), **kw)
     nz, ny, nx = prob.shape
     s.load_grid(prob.n_H, prob.dx_cm * nx, kappa=prob.kappa, x_HI0=prob.x_HI0, T=prob.T)
     s.load_sources(prob.src_pos_cm, prob.ndot_bins)

@@ -35,6 +35,7 @@ def test_params_default_and_struct_size():
     assert p.size == C.sizeof(frt.Params)
     assert p.n_bins == 1 and p.sigma_bins[0] == 6.3e-18 and p.max_level == 12
     assert p.c_ray_cm_s == 2.99792458e10
+    assert p.temperature == 0 and p.cmb_z == -1.0 and p.t_reion_k == 2e4 and p.spectral_index == 1.5
 
 
 @pytest.mark.parametrize("seed,step,src", [(0, 0, 0), (7, 3, 11), (2 ** 40 + 5, 99, 1999)])

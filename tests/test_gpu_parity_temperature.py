@@ -140,8 +140,11 @@ def test_batch_with_and_without_temperature_equals_each_alone(ctx):
 
 
 def test_temperature_parameters_are_checked(ctx):
-    for kw in ({"temperature": True, "opacity_mode": 1}, {"temperature": True, "heat_ev": [-1.0]},
-               {"temperature": True, "hubble_s": -1e-18}, {"temperature": True, "cmb_z": float("nan")}):
+    for kw in ({"temperature": True, "heat_ev": [-1.0]}, {"temperature": True, "hubble_s": -1e-18},
+               {"temperature": True, "cmb_z": float("nan")}, {"temperature": True, "opacity_mode": 1, "t_reion": 0.0},
+               {"temperature": True, "opacity_mode": 1, "t_reion": float("inf")},
+               {"temperature": True, "opacity_mode": 1, "spectral_index": -0.5},
+               {"temperature": True, "opacity_mode": 1, "spectral_index": float("nan")}):
         with pytest.raises(frt.FrtError) as e:
             frt.Solve(ctx, sigma_bins=[6.3e-18], **kw)
         assert e.value.code == frt.FRT_EINVAL, kw
