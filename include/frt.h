@@ -271,6 +271,20 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
  * step.  FRT_ESTATE before a grid is loaded. */
 int frt_set_opacity(frt_solve s, const float* kappa, int ptr_kind);
 
+/* Replace the hydrogen density between steps, keeping the rest of the
+ * state (the density a simulation hands to the next step): n_H [ncell]
+ * cm^-3 (finite, >= 0, mean > 0), the layout of frt_load_grid.  With the
+ * temperature on, T takes the compression term of Eq.
+ * temp_evolution_standard exactly, T (Delta_new / Delta_old)^(2/3) with
+ * Delta = n_H / <n_H> over the grid (a change of the mean alone is left to
+ * the Hubble term, hubble_s), in cells whose density is > 0 before and
+ * after.  Standard Mode's opacity is rebuilt from the new n_H and the
+ * current x_HI.  Takes effect at the next step; checkpoints, bookmarks and
+ * rewinds do not hold the density (set it again after restoring).
+ * FRT_ESTATE before a grid is loaded or when the loaded density's mean is
+ * 0; FRT_EINVAL for a bad field (nothing changes). */
+int frt_set_density(frt_solve s, const float* n_H, int ptr_kind);
+
 /* Load n_src >= 0 point sources: pos_cm [n_src][3] (x,y,z) inside
  * [0, n*dx] per axis; ndot_bins [n_src][n_bins] photons/s per bin (finite,
  * >= 0).  Requires the grid.  Sizes the ray queues. */

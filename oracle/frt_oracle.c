@@ -69,6 +69,11 @@
  *                         those of the papers it cites (Hui & Gnedin 1997,
  *                         Cen 1992), restated, and beyond the Test 2 check
  *                         their values are parity unpinned.
+ *   orc_set_density       (the compression term of Eq. temp_evolution_standard)
+ *                         T Delta^(-2/3) against an ODE solver along a path
+ *                         of densities; a change of the mean alone keeps T;
+ *                         a later step sees the new density exactly as a
+ *                         grid loaded with it.
  *   reion_heat_per_recombination  (§4.2, Eq. analytical_heating_HI) the
  *                         mean energy above 1 Ryd of the photons HI absorbs
  *                         from the cut power law, by quadrature.
@@ -959,6 +964,31 @@ void orc_read_temperature(const orc_state* S, double* T) { memcpy(T, S->T, sizeo
 void orc_set_kappa(orc_state* S, const float* kappa)
 {
     for (long long i = 0; i < S->ncell; i++) S->kappa[i] = kappa[i];
+}
+
+/* New hydrogen density field between steps, the rest of the state kept
+ * (the density a simulation hands to the next step).  The temperature takes
+ * the compression term of Eq. temp_evolution_standard, dT/dt = (2 T / 3
+ * Delta) dDelta/dt, whose solution over any path is T Delta^(-2/3) constant:
+ * T -> T (Delta_new / Delta_old)^(2/3) with Delta = n_H / <n_H> over the grid
+ * (a change of the mean alone is the Hubble term's); cells with n_H = 0
+ * before or after keep T.  Returns -1 if a mean is not > 0. */
+int orc_set_density(orc_state* S, const float* nH)
+{
+    double m0 = 0.0, m1 = 0.0;
+    for (long long i = 0; i < S->ncell; i++) {
+        m0 += S->nH[i];
+        m1 += (double)nH[i];
+    }
+    if (!(m0 > 0.0) || !(m1 > 0.0)) return -1;
+    m0 /= (double)S->ncell;
+    m1 /= (double)S->ncell;
+    for (long long i = 0; i < S->ncell; i++) {
+        const double n1 = (double)nH[i];
+        if (S->p.temperature && S->nH[i] > 0.0 && n1 > 0.0) S->T[i] *= pow((n1 / m1) / (S->nH[i] / m0), 2.0 / 3.0);
+        S->nH[i] = n1;
+    }
+    return 0;
 }
 
 void orc_destroy(orc_state* S)

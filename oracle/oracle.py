@@ -110,6 +110,8 @@ def lib():
         L.temperature_update.restype = C.c_double
         L.temperature_update.argtypes = [C.POINTER(Params), C.c_double, C.c_double, C.c_double, C.c_double,
                                          C.c_double, C.c_double]
+        L.orc_set_density.restype = C.c_int
+        L.orc_set_density.argtypes = [C.c_void_p, C.c_void_p]
         L.reion_heat_per_recombination.restype = C.c_double
         L.reion_heat_per_recombination.argtypes = [C.c_double]
         L.ionized_temperature_update.restype = C.c_double
@@ -252,6 +254,12 @@ class Oracle:
         self._kap = np.ascontiguousarray(kappa, dtype=np.float32).reshape(-1)
         assert self._kap.size == self.ncell
         lib().orc_set_kappa(self.h, self._kap.ctypes.data)
+
+    def set_density(self, n_H):
+        self._nH = np.ascontiguousarray(n_H, dtype=np.float32).reshape(-1)
+        assert self._nH.size == self.ncell
+        if lib().orc_set_density(self.h, self._nH.ctypes.data) != 0:
+            raise ValueError("oracle: the mean density must be > 0")
 
     def set_sources(self, pos_cm, ndot_bins):
         pos = np.ascontiguousarray(pos_cm, dtype=np.float64).reshape(-1, 3)

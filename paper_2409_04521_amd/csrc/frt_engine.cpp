@@ -273,6 +273,7 @@ struct frt_solve_s {
     int nx = 0, ny = 0, nz = 0;
     int bpx = 0, bpy = 0, bpz = 0;
     double dx = 0;
+    double nH_mean = 0;                      // the grid's mean n_H (the density update's Delta)
     double w0_max = 0;                       // largest w0 any held packet can have
     size_t ncell = 0;
     FrtSolveDesc h{};
@@ -505,6 +506,14 @@ int read_device_ledger(frt_solve s, FrtLedgerDev* out)
 // step's opacity iteration from the previous step's rate field, which is
 // then part of its state (checkpoints and bookmarks keep it).
 bool warm_rate(frt_solve s) { return s->P.opacity_mode == FRT_GENERALIZED && s->P.chem_iterations > 0; }
+
+// Mean of a field, summed in cell order.
+double mean_of(const std::vector<double>& v)
+{
+    double sum = 0.0;
+    for (double a : v) sum += a;
+    return v.empty() ? 0.0 : sum / (double)v.size();
+}
 
 // Photo-heating per recombination of ionized gas in photo-ionization
 // equilibrium (§4.2, Eq. analytical_heating_HI), erg: 1 Ryd times the mean
@@ -1834,6 +1843,7 @@ int frt_load_grid(frt_solve s, int nx, int ny, int nz, double box_cm, const floa
     s->bpz = (nz + (1 << s->bsh[2]) - 1) >> s->bsh[2];
     std::vector<double> nHd(n), xd(n, 1.0);
     for (size_t i = 0; i < n; i++) nHd[i] = (double)hn[i];
+    s->nH_mean = mean_of(nHd);
     if (hx) std::copy(hx, hx + n, xd.begin());
     // opacity: the HI part (first n values) is built from x_HI on the device;
     // the sub-grid part (next n values) is fixed.  Generalized Opacity Mode:
@@ -1954,6 +1964,39 @@ int frt_set_opacity(frt_solve s, const float* kappa, int kind)
         if (s->kin) RCCHK(scopy(s, s->kin, v.data(), n * 4, hipMemcpyHostToDevice));
     }
     return FRT_OK;
+}
+
+int frt_set_density(frt_solve s, const float* n_H, int kind)
+{
+    if (!s) return fail(FRT_EINVAL, "null solve");
+    if (!s->have_grid) return fail(FRT_ESTATE, "load the grid before a new density");
+    if (!n_H) return fail(FRT_EINVAL, "null n_H");
+    if (kind != FRT_HOST && kind != FRT_DEVICE) return fail(FRT_EINVAL, "ptr_kind must be FRT_HOST or FRT_DEVICE");
+    HIPCHK(hipSetDevice(s->ctx->device));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    const size_t n = s->ncell;
+    AllocScope scope(&s->ctx->al);
+    std::vector<float> bn;
+    const float* hn = nullptr;
+    RCCHK(host_view(n_H, n, kind, bn, &hn));
+    RCCHK(check_inputs_finite(hn, n, "n_H"));
+    std::vector<double> nd(n);
+    for (size_t i = 0; i < n; i++) nd[i] = (double)hn[i];
+    const double m1 = mean_of(nd);
+    if (!(m1 > 0.0)) return fail(FRT_EINVAL, "the new density's mean must be > 0");
+    if (!(s->nH_mean > 0.0)) return fail(FRT_ESTATE, "the loaded density's mean is 0: load a grid instead");
+    double* dn = nullptr;
+    RCCHK(dev_alloc((void**)&dn, n * 8));
+    int rc = scopy(s, dn, nd.data(), n * 8, hipMemcpyHostToDevice);
+    if (rc == FRT_OK) {
+        hipError_t e = frt::launch_set_density(s->nH, dn, s->h.temp ? s->T : nullptr, s->nH_mean, m1, n, s->stream);
+        if (e == hipSuccess) e = frt::launch_prep_opacity(s->d_desc, n, s->fp64, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) rc = fail(FRT_EDEVICE, "density update: %s", hipGetErrorString(e));
+    }
+    dev_free(dn);
+    if (rc == FRT_OK) s->nH_mean = m1;
+    return rc;
 }
 
 int frt_load_sources(frt_solve s, int n_src, const double* pos_cm, const double* ndot, int kind)

@@ -323,6 +323,10 @@ hipError_t launch_finish(FrtSolveDesc* d, const FrtWS& ws, hipStream_t s);
 hipError_t launch_chem(FrtSolveDesc* d, const unsigned long long* d_cell_prefix, int n_solves,
                        unsigned long long total_cells, int fp64, int temp, const uint32_t* launch_err, hipStream_t s);
 hipError_t launch_prep_opacity(FrtSolveDesc* d_desc, unsigned long long ncell, int fp64, hipStream_t s);
+// n_H <- nH_new (device, double) with the compression term on T (null: none);
+// m0, m1 are the grid's mean density before and after.
+hipError_t launch_set_density(double* nH, const double* nH_new, double* T, double m0, double m1,
+                              unsigned long long ncell, hipStream_t s);
 // Clear the launch counters and brick histogram (a kernel, so that a step
 // captured in a HIP graph holds no memset node); mode is a CLEAR_* value.
 hipError_t launch_clear(const FrtWS& ws, int mode, hipStream_t s);

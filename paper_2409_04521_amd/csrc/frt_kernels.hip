@@ -2089,6 +2089,22 @@ __global__ void __launch_bounds__(BLOCK) k_prep(const FrtSolveDesc* __restrict__
     }
 }
 
+// A new hydrogen density between steps: with the temperature on, the
+// compression term of Eq. temp_evolution_standard, whose solution along any
+// path keeps T Delta^(-2/3), Delta = n_H / <n_H> (m0, m1: the grid's mean
+// before and after): T -> T (Delta_new / Delta_old)^(2/3), where both
+// densities are > 0.  The staged opacity is rebuilt afterwards (k_prep).
+__global__ void __launch_bounds__(BLOCK) k_set_density(double* __restrict__ nH, const double* __restrict__ nH_new,
+                                                      double* __restrict__ T, double m0, double m1, unsigned long long n)
+{
+    for (unsigned long long i = (unsigned long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+        const double n0 = nH[i], n1 = nH_new[i];
+        if (T && n0 > 0.0 && n1 > 0.0) T[i] = T[i] * pow((n1 / m1) / (n0 / m0), 2.0 / 3.0);
+        nH[i] = n1;
+    }
+}
+
 // The allocation-free step's scratch (FRT_STATIC_SCRATCH_BYTES per GPU).  In
 // host code `scratch` names a host-side stand-in, not device memory: host code
 // uses the device address that static_scratch() looks up, never the name.
@@ -2335,6 +2351,14 @@ hipError_t launch_prep_opacity(FrtSolveDesc* d_desc, unsigned long long ncell, i
     const int grid = grid_for(ncell, 16);
     if (fp64) hipLaunchKernelGGL(k_prep<double>, dim3(grid), dim3(BLOCK), 0, s, d_desc, ncell);
     else hipLaunchKernelGGL(k_prep<float>, dim3(grid), dim3(BLOCK), 0, s, d_desc, ncell);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_density(double* nH, const double* nH_new, double* T, double m0, double m1,
+                              unsigned long long ncell, hipStream_t s)
+{
+    if (ncell == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_set_density, dim3(grid_for(ncell, 16)), dim3(BLOCK), 0, s, nH, nH_new, T, m0, m1, ncell);
     return hipGetLastError();
 }
 

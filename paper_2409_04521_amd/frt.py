@@ -31,7 +31,7 @@ EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_
            "frt_ctx_get_tuning", "frt_autotune", "frt_request_bytes", "frt_server_create", "frt_server_submit",
            "frt_server_poll", "frt_server_wait", "frt_server_take", "frt_server_times", "frt_server_get_stats",
            "frt_server_destroy", "frt_debug_cast", "frt_step_static", "frt_merge_uniforms",
-           "frt_read_temperature", "frt_microbench")
+           "frt_read_temperature", "frt_microbench", "frt_set_density")
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
@@ -175,6 +175,7 @@ def lib():
         L.frt_load_grid.argtypes = [vp, C.c_int, C.c_int, C.c_int, C.c_double, vp, vp, vp, vp, C.c_int]
         L.frt_load_sources.argtypes = [vp, C.c_int, vp, vp, C.c_int]
         L.frt_set_opacity.argtypes = [vp, vp, C.c_int]
+        L.frt_set_density.argtypes = [vp, vp, C.c_int]
         L.frt_set_rotations.argtypes = [vp, C.c_int, vp]
         L.frt_step.argtypes = [vp, C.c_double]
         L.frt_step_static.argtypes = [vp, C.c_double]
@@ -354,6 +355,12 @@ class Solve:
     def set_opacity(self, kappa):
         pk, kind, k = _ptr(kappa)
         _check(lib().frt_set_opacity(self.h, pk, kind))
+
+    def set_density(self, n_H):
+        if isinstance(n_H, np.ndarray):
+            n_H = np.ascontiguousarray(n_H, dtype=np.float32)
+        pn, kind, k = _ptr(n_H)
+        _check(lib().frt_set_density(self.h, pn, kind))
 
     def load_sources(self, pos_cm, ndot_bins):
         pos = np.ascontiguousarray(pos_cm, dtype=np.float64).reshape(-1, 3) if isinstance(pos_cm, np.ndarray) else pos_cm

@@ -1,0 +1,118 @@
+"""The density update between steps (frt_set_density: the compression term
+of Eq. temp_evolution_standard, T (Delta_new / Delta_old)^(2/3)) on the GPU
+against the FP64 oracle: a clumpy box with the temperature on in Standard
+Mode and in the Generalized Opacity Mode, its density changed before every
+step (new lognormal fields whose mean also changes), FP64 and FP32, with the
+bars of the temperature tests (FP64: x_HI 1e-9, T 1e-8 relative; FP32: 1e-3
+and 1e-3).  A solve whose density was updated equals one loaded with the
+new density and the compressed temperature; a device-resident field works
+like a host one; bad fields are refused and change nothing."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2409_04521_amd import frt
+from paper_2409_04521_amd import workloads as W
+
+import test_gpu_parity_gentemp as GT
+import test_gpu_parity_temperature as ST
+
+pytestmark = pytest.mark.gpu
+
+TERMS = ("emitted", "absorbed_HI", "absorbed_sub", "absorbed_front", "front_excess", "escaped", "dropped", "in_flight")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return frt.Context(0)
+
+
+def _path(p, steps, seed):
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = []
+    for s in range(steps):
+        f = W.lognormal_white(rng, p.shape, 1.0, 0.3) * (0.85 ** (s + 1))
+        out.append((p.n_H.astype(np.float64) * f).astype(np.float32))
+    return out
+
+
+def _problem(mode, K=0):
+    if mode == "generalized":
+        return GT._box(n=20, seed=81, K=K, steps=3)
+    p = ST._clumpy(n=20, steps=3, K=K, seed=83)
+    p.hubble_s = 1e-16
+    return p
+
+
+@pytest.mark.parametrize("mode", ["standard", "generalized"])
+@pytest.mark.parametrize("precision,x_tol,t_rtol,led_tol", [("f64", 1e-9, 1e-8, 1e-9), ("f32", 1e-3, 1e-3, 1e-4)])
+def test_density_path_matches_the_oracle(ctx, mode, precision, x_tol, t_rtol, led_tol):
+    p = _problem(mode)
+    path = _path(p, p.n_steps, 89)
+    o = O.Oracle(**p.oracle_kwargs())
+    o.set_sources(p.src_pos_cm, p.ndot_bins)
+    g = frt.solve_from_problem(ctx, p, precision=precision)
+    for s in range(p.n_steps):
+        o.set_density(path[s])
+        g.set_density(path[s])
+        o.step(p.dt_s, p.uniforms(s))
+        g.step(p.dt_s)
+    xo, xg = o.fields()[0], g.fields()[0]
+    To, Tg = o.temperature(), g.temperature()
+    Lo, Lg = o.ledger(), g.ledger()
+    dx, dT = float(np.abs(xo - xg).max()), float(np.max(np.abs(Tg / To - 1)))
+    worst = max(abs(Lo[k] - Lg[k]) / Lo["emitted"] for k in TERMS)
+    print(f"[density {mode} {precision}] max|dx_HI| {dx:.2e}  max|dT/T| {dT:.2e}  ledger {worst:.1e}", flush=True)
+    assert dx <= x_tol and dT <= t_rtol and worst <= led_tol
+    assert Lg["err_flags"] == 0
+
+
+@pytest.mark.parametrize("mode", ["standard", "generalized"])
+def test_updated_solve_steps_like_one_loaded_with_the_new_density(ctx, mode):
+    p = _problem(mode)
+    p.temperature, p.T = False, None
+    n2 = _path(p, 1, 97)[0]
+    a = frt.solve_from_problem(ctx, p, precision="f64")
+    a.set_density(n2)
+    q = _problem(mode)
+    q.temperature, q.T, q.n_H = False, None, n2
+    c = frt.solve_from_problem(ctx, q, precision="f64")
+    for s in (a, c):
+        for _ in range(2):
+            s.step(p.dt_s)
+    (xa, ga), (xc, gc) = a.fields(), c.fields()
+    assert np.abs(xa - xc).max() <= 1e-12
+    assert np.abs(ga.astype(np.float64) - gc).max() <= 1e-10 * float(np.abs(gc).max())
+
+
+def test_temperature_takes_the_compression_term(ctx):
+    p = _problem("standard")
+    n2 = _path(p, 1, 99)[0]
+    a = frt.solve_from_problem(ctx, p, precision="f64")
+    a.set_density(n2)
+    n1d, n2d = p.n_H.astype(np.float64), n2.astype(np.float64)
+    want = p.T.astype(np.float64) * ((n2d / n2d.mean()) / (n1d / n1d.mean())) ** (2.0 / 3.0)
+    np.testing.assert_allclose(a.temperature(), want, rtol=1e-13)
+
+
+def test_device_field_and_bad_fields(ctx):
+    import torch
+
+    p = _problem("standard")
+    n2 = _path(p, 1, 101)[0]
+    a = frt.solve_from_problem(ctx, p, precision="f64")
+    b = frt.solve_from_problem(ctx, p, precision="f64")
+    a.set_density(n2)
+    b.set_density(torch.from_numpy(n2).to("cuda:0"))
+    assert np.array_equal(a.temperature(), b.temperature())
+    T0, x0 = b.temperature(), b.fields()[0]
+    for bad in (np.full(p.shape, -1.0, np.float32), np.full(p.shape, np.nan, np.float32),
+                np.zeros(p.shape, np.float32)):
+        with pytest.raises(frt.FrtError) as e:
+            b.set_density(bad)
+        assert e.value.code == frt.FRT_EINVAL
+    assert np.array_equal(b.temperature(), T0) and np.array_equal(b.fields()[0], x0)
+    fresh = frt.Solve(ctx, sigma_bins=[6.3e-18])
+    with pytest.raises(frt.FrtError) as e:
+        fresh.set_density(n2)
+    assert e.value.code == frt.FRT_ESTATE
