@@ -78,7 +78,6 @@ def test_step_after_the_update_equals_a_grid_loaded_with_it(mode, temperature):
     a.set_density(n2)
     Ta = a.temperature()
     if temperature:
-        D1, D2 = n1.astype(np.float64) / n1.astype(np.float64).mean(), n2.astype(np.float64) / n2.astype(np.float64).mean()
         assert not np.allclose(Ta, T0)
     b = O.Oracle((n, n, n), dx, [6.3e-18], 2.59e-13, n2, T0=Ta, **kw)
     src = np.array([[n / 2, n / 2, n / 2]]) * dx
