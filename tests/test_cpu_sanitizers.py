@@ -82,7 +82,10 @@ def test_oracle_under_asan_ubsan(tmp_path):
                     os.path.join(ROOT, "tests", "test_oracle_geometry.py"),
                     os.path.join(ROOT, "tests", "test_oracle_merge.py"),
                     os.path.join(ROOT, "tests", "test_oracle_step.py"),
-                    os.path.join(ROOT, "tests", "test_oracle_transport.py")],
+                    os.path.join(ROOT, "tests", "test_oracle_transport.py"),
+                    os.path.join(ROOT, "tests", "test_oracle_temperature.py"),
+                    os.path.join(ROOT, "tests", "test_oracle_gentemp.py"),
+                    os.path.join(ROOT, "tests", "test_oracle_density.py")],
                    env={"FRT_ORACLE_LIB": lib, "LD_PRELOAD": rt, "ASAN_OPTIONS": "detect_leaks=0"})
     print(out[-2000:])
     assert rc == 0, out[-4000:]
