@@ -230,6 +230,76 @@ def cpu_baseline(prob, n_sample: int, threads: int):
     return out
 
 
+def cpu_baseline_configs(threads: int, c4_boxes: int = 8):
+    """The CPU-baseline leg per configuration: the FP64 oracle on `threads`
+    host threads and on one, beside the GPU, on C1 (32^3 Stromgren box,
+    50 steps, the GPU in FP64 and FP32), C2 (128^3 lognormal box, 64
+    sources, 100 steps), C3a (256^3 GRF, 2000 sources from neutral at c, 20
+    steps) and the first `c4_boxes` boxes of C4 one at a time (50 steps
+    each).  Each row: ms per step and crossings per step of each side, whose
+    crossing counts agree up to FP32 face ties.  With host threads the
+    oracle keeps one rate field per source chunk (a deterministic sum),
+    whose clearing and reduction dominate a step whose packets die near
+    their sources; on one thread it keeps one."""
+    from oracle import oracle as O
+    from paper_2409_04521_amd import frt
+    from paper_2409_04521_amd import workloads as W
+
+    ctx = frt.Context(0)
+
+    def gpu(probs, precision, steps):
+        t, c = 0.0, 0
+        for p in probs:
+            g = frt.solve_from_problem(ctx, p, precision=precision)
+            g.sync()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                g.step(p.dt_s)
+            g.sync()
+            t += time.perf_counter() - t0
+            c += g.ledger()["crossings"]
+            g.close()
+        n = steps * len(probs)
+        return {"ms_per_step": 1e3 * t / n, "crossings_per_step": c / n, "steps": n, "precision": precision}
+
+    def oracle(probs, steps, nthreads):
+        t, c = 0.0, 0
+        for p in probs:
+            o = O.Oracle(**p.oracle_kwargs(), n_chunks=max(nthreads, 1))
+            o.set_sources(p.src_pos_cm, p.ndot_bins)
+            for k in range(steps):
+                t0 = time.perf_counter()
+                o.step(p.dt_s, p.uniforms(k), threads=nthreads)
+                t += time.perf_counter() - t0
+                c += o.last_crossings()
+            o.close()
+        n = steps * len(probs)
+        return {"ms_per_step": 1e3 * t / n, "crossings_per_step": c / n, "steps": n, "threads": nthreads}
+
+    rows = []
+    cases = [("C1", "32^3 Stromgren, corner source, 1 bin, dt 2 Myr, FP64 oracle", [W.stromgren_c1()], 50,
+              ("f64", "f32")),
+             ("C2", "128^3 lognormal, 64 sources, 4 bins, sub-grid kappa, c, dt 1 Myr", [W.lognormal_c2()], 100,
+              ("f32",)),
+             ("C3a", "256^3 GRF, 2000 peak sources, 4 bins, from neutral at c, dt 1 Myr",
+              [W.grf_c3(throughput=False)], 20, ("f32",)),
+             (f"C4 (first {c4_boxes} boxes)", "uneven boxes 32-128^3, 1-256 sources, 3 bins, c, dt 1 Myr, one at a time",
+              W.batch_c4()[:c4_boxes], 50, ("f32",))]
+    for name, what, probs, steps, precs in cases:
+        row = {"config": name, "workload": what}
+        for pr in precs:
+            row[f"gpu_{pr}"] = gpu(probs, pr, steps)
+        row["oracle"] = oracle(probs, steps, threads)
+        row["oracle_1_thread"] = oracle(probs, steps, 1)
+        g = row[f"gpu_{precs[0]}"]
+        row["oracle_over_gpu_time"] = row["oracle"]["ms_per_step"] / g["ms_per_step"]
+        log(f"{name}: GPU {g['ms_per_step']:.2f} ms/step, oracle {row['oracle']['ms_per_step']:.1f} ms/step on "
+            f"{threads} threads, {row['oracle_1_thread']['ms_per_step']:.1f} on one; crossings/step "
+            f"{g['crossings_per_step']:.4g} vs {row['oracle']['crossings_per_step']:.4g}")
+        rows.append(row)
+    return rows
+
+
 def avgchem_leg(frt, W, K: int, steps: int, warmup: int, stream):
     """Standard Mode with the time-averaged chemistry (K marches per step)
     against backward Euler (one march) on the same evolving 128^3 box with
@@ -600,6 +670,9 @@ def main():
     ap.add_argument("--pmc-atomics", nargs=2, metavar=("DB_DIR", "CROSSINGS_PER_STEP"),
                     help="write profiles/march_c3b_atomics.json from a rocprofv3 --pmc run of TCC_ATOMIC_sum and "
                          "SQ_INSTS_LDS_ATOMIC")
+    ap.add_argument("--config-table", action="store_true",
+                    help="time the FP64 oracle (host threads and one thread) beside the GPU on C1, C2, C3a and "
+                         "a C4 sample, print one JSON line and exit")
     ap.add_argument("--pmc-summary", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/march_c3b_traffic.json from two rocprofv3 --pmc runs of this "
                          "benchmark (FETCH_SIZE, WRITE_SIZE) and exit")
@@ -625,6 +698,13 @@ def main():
 
     from paper_2409_04521_amd import frt
     from paper_2409_04521_amd import workloads as W
+
+    if args.config_table:
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        rows = cpu_baseline_configs(threads)
+        print(json.dumps({"config_table": rows, "host_threads": threads, "gpu": torch.cuda.get_device_name(0)}),
+              flush=True)
+        return
 
     log("building inputs")
     prob = W.grf_c3(n=args.n, n_src=args.sources, throughput=True, box_cmpc_h=100.0 * args.n / 256)
