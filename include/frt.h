@@ -501,6 +501,13 @@ int frt_server_wait(frt_server srv, uint64_t req_id, double timeout_s, int* stat
  * returns its error code and message; an unfinished one FRT_ESTATE. */
 int frt_server_take(frt_server srv, uint64_t req_id, double* x_HI, frt_ledger* ledger);
 
+/* The gas temperature T [ncell] (host, double, K; §4.1 Eq.
+ * temp_evolution_standard) of a finished request whose params had the
+ * temperature on; call it before frt_server_take, which forgets the
+ * request.  FRT_ESTATE if the request is unfinished or did not evolve its
+ * temperature, FRT_EINVAL for an unknown request. */
+int frt_server_read_temperature(frt_server srv, uint64_t req_id, double* T);
+
 /* Seconds since the server's creation at which the request was submitted,
  * admitted and finished (t[2] = -1 while unfinished). */
 int frt_server_times(frt_server srv, uint64_t req_id, double t[3]);

@@ -44,6 +44,7 @@ struct Req {
     frt_solve solve = nullptr;
     int steps_done = 0;
     std::vector<double> x_out;
+    std::vector<double> T_out;        // with the temperature on
     frt_ledger led{};
     double t_submit = 0.0, t_start = -1.0, t_done = -1.0;
 
@@ -208,6 +209,10 @@ struct frt_server_s {
         const size_t ncell = (size_t)r->nx * r->ny * r->nz;
         r->x_out.resize(ncell);
         int rc = frt_read_fields(r->solve, r->x_out.data(), nullptr, FRT_HOST);
+        if (rc == FRT_OK && r->params.temperature) {
+            r->T_out.resize(ncell);
+            rc = frt_read_temperature(r->solve, r->T_out.data(), FRT_HOST);
+        }
         if (rc == FRT_OK) rc = frt_read_ledger(r->solve, &r->led);
         if (rc == FRT_OK && r->led.err_flags) rc = frt::set_error(FRT_EDEVICE, "the solve ended with device error bits set");
         if (rc != FRT_OK) {
@@ -493,6 +498,19 @@ int frt_server_take(frt_server srv, uint64_t req_id, double* x_HI, frt_ledger* l
     if (x_HI) std::memcpy(x_HI, r->x_out.data(), r->x_out.size() * sizeof(double));
     if (ledger) *ledger = r->led;
     srv->all.erase(it);
+    return FRT_OK;
+}
+
+int frt_server_read_temperature(frt_server srv, uint64_t req_id, double* T)
+{
+    if (!srv || !T) return frt::set_error(FRT_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lock(srv->mu);
+    auto it = srv->all.find(req_id);
+    if (it == srv->all.end()) return frt::set_error(FRT_EINVAL, "unknown request");
+    const Req* r = it->second.get();
+    if (r->state != FRT_REQ_DONE) return frt::set_error(FRT_ESTATE, "request not finished");
+    if (r->T_out.empty()) return frt::set_error(FRT_ESTATE, "the request did not evolve its temperature");
+    std::memcpy(T, r->T_out.data(), r->T_out.size() * sizeof(double));
     return FRT_OK;
 }
 

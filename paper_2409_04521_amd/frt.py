@@ -31,7 +31,7 @@ EXPORTS = ("frt_params_default", "frt_ctx_create", "frt_ctx_destroy", "frt_last_
            "frt_ctx_get_tuning", "frt_autotune", "frt_request_bytes", "frt_server_create", "frt_server_submit",
            "frt_server_poll", "frt_server_wait", "frt_server_take", "frt_server_times", "frt_server_get_stats",
            "frt_server_destroy", "frt_debug_cast", "frt_step_static", "frt_merge_uniforms",
-           "frt_read_temperature", "frt_microbench", "frt_set_density")
+           "frt_read_temperature", "frt_microbench", "frt_set_density", "frt_server_read_temperature")
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_FAILED = 0, 1, 2, 3
 
 
@@ -205,6 +205,7 @@ def lib():
         L.frt_server_wait.argtypes = [vp, C.c_uint64, C.c_double, C.POINTER(C.c_int)]
         L.frt_server_take.argtypes = [vp, C.c_uint64, vp, C.POINTER(Ledger)]
         L.frt_server_times.argtypes = [vp, C.c_uint64, C.POINTER(C.c_double)]
+        L.frt_server_read_temperature.argtypes = [vp, C.c_uint64, vp]
         L.frt_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
         L.frt_server_destroy.argtypes = [vp]
         L.frt_debug_cast.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double), C.POINTER(C.c_double),
@@ -594,6 +595,13 @@ class Server:
         _check(lib().frt_server_take(self.h, rid, x.ctypes.data, C.byref(L)))
         self.shapes.pop(rid, None)
         return x, L.as_dict()
+
+    def temperature(self, rid: int):
+        """T (K) of a finished request that evolved its temperature; before take()."""
+        import numpy as np
+        t = np.empty(self.shapes[rid], dtype=np.float64)
+        _check(lib().frt_server_read_temperature(self.h, rid, t.ctypes.data))
+        return t
 
     def times(self, rid: int):
         t = (C.c_double * 3)()

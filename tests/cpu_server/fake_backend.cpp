@@ -7,7 +7,8 @@
 // a virtual clock advanced by the work done, and failures injected on
 // request (fake_control.h).  A solve's "neutral fraction" after k steps is
 // 1 / (1 + k) + 1e-6 tag + 1e-9 cell, with tag = n_H[0] of its grid, so a
-// test can tell that every request received exactly its own steps.
+// test can tell that every request received exactly its own steps; with the
+// temperature on, its T is 1e4 + k + 1e-3 tag + 1e-6 cell.
 #include "fake_control.h"
 
 #include "frt.h"
@@ -119,6 +120,8 @@ uint64_t max_batch()
 void advance_clock(double seconds) { tick((int64_t)std::llround(seconds * 1e9)); }
 
 double expected_x(double tag, uint64_t steps, uint64_t cell) { return value(tag, steps, cell); }
+
+double expected_T(double tag, uint64_t steps, uint64_t cell) { return 1e4 + (double)steps + 1e-3 * tag + 1e-6 * (double)cell; }
 
 uint64_t cell_bytes() { return 36; }
 
@@ -262,6 +265,15 @@ int frt_read_fields(frt_solve s, double* x, float* gamma, int ptr_kind)
         for (uint64_t i = 0; i < n; i++) x[i] = value(s->tag, s->steps, i);
     if (gamma)
         for (uint64_t i = 0; i < n; i++) gamma[i] = 0.0f;
+    return FRT_OK;
+}
+
+int frt_read_temperature(frt_solve s, double* T, int ptr_kind)
+{
+    if (!s || !T || ptr_kind != FRT_HOST) return err(FRT_EINVAL, "bad temperature read");
+    if (!s->P.temperature) return err(FRT_ESTATE, "the solve holds no temperature");
+    const uint64_t n = ncell(s);
+    for (uint64_t i = 0; i < n; i++) T[i] = fake::expected_T(s->tag, s->steps, i);
     return FRT_OK;
 }
 

@@ -30,6 +30,7 @@ uint64_t batches();                 // batched steps applied since reset
 uint64_t max_batch();               // most solves in one applied batched step
 void advance_clock(double seconds); // virtual time passing outside the library (arrivals)
 double expected_x(double tag, uint64_t steps, uint64_t cell);
+double expected_T(double tag, uint64_t steps, uint64_t cell);   // with the temperature on
 uint64_t cell_bytes();              // resident bytes per cell of a solve
 uint64_t pass_bytes_per_cell();     // pass-queue bytes per cell a solve asks for
 

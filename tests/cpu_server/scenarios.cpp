@@ -409,6 +409,33 @@ void burst_latency_batched_vs_one_at_a_time()
     end("burst_latency_batched_vs_one_at_a_time", f0);
 }
 
+// A request with the temperature on hands back its T before it is taken; one
+// without it, an unfinished one and a taken one do not.
+void temperature_is_read_before_take()
+{
+    const int f0 = g_failures;
+    Setup S(size_t(1) << 30, 4);
+    auto warm = make(5.0, 6, 3);
+    warm->r.params.temperature = 1;
+    auto cold = make(6.0, 6, 3);
+    fake::hold_steps(true);
+    const uint64_t a = submit(S.srv, *warm), b = submit(S.srv, *cold);
+    std::vector<double> T(warm->ncell);
+    CHECK(frt_server_read_temperature(S.srv, a, T.data()) == FRT_ESTATE);   // not finished
+    fake::hold_steps(false);
+    CHECK(wait_state(S.srv, a) == FRT_REQ_DONE);
+    CHECK(wait_state(S.srv, b) == FRT_REQ_DONE);
+    CHECK(frt_server_read_temperature(S.srv, a, T.data()) == FRT_OK);
+    const size_t probe[3] = {0, warm->ncell / 2, warm->ncell - 1};
+    for (size_t k : probe) CHECK(T[k] == fake::expected_T(5.0, 3, k));
+    CHECK(frt_server_read_temperature(S.srv, b, T.data()) == FRT_ESTATE);   // no temperature
+    CHECK(frt_server_read_temperature(S.srv, a, nullptr) == FRT_EINVAL);
+    check_done(S.srv, a, *warm);
+    check_done(S.srv, b, *cold);
+    CHECK(frt_server_read_temperature(S.srv, a, T.data()) == FRT_EINVAL);   // taken: forgotten
+    end("temperature_is_read_before_take", f0);
+}
+
 }  // namespace
 
 int main()
@@ -422,6 +449,7 @@ int main()
     destroy_with_requests_in_flight();
     pass_queue_limit_steps_solves_alone();
     burst_latency_batched_vs_one_at_a_time();
+    temperature_is_read_before_take();
     std::printf("%s: %d failed checks\n", g_failures ? "FAILED" : "all scenarios passed", g_failures);
     return g_failures > 255 ? 255 : g_failures;
 }

@@ -5,7 +5,8 @@
   budget, failures injected into one request's creation, upload or step,
   a device failure of a batch, queue modes and bins, concurrent clients,
   destroying a server with requests in flight, batched vs one-at-a-time
-  latency on the stand-in's virtual clock) built plain, under
+  latency on the stand-in's virtual clock, the temperature of a finished
+  request) built plain, under
   ThreadSanitizer (clang's runtime, which understands the condition
   variables' clock waits) and under AddressSanitizer + UBSan;
 * the FP64 oracle under AddressSanitizer + UBSan, running its own pins;

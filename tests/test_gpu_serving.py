@@ -2,8 +2,9 @@
 same alone and in the mix (x_HI within 1e-5, ledger terms within 1e-6 of
 emitted: only the order of the atomic deposits differs), one of them matches
 the FP64 oracle at the parity tolerances, admission respects the memory
-budget and the slots, requests submitted while others run join them, and a
-request larger than the whole budget fails cleanly."""
+budget and the slots, requests submitted while others run join them, a
+request larger than the whole budget fails cleanly, and requests with the
+temperature on hand back the T they reach alone."""
 import time
 
 import numpy as np
@@ -127,4 +128,35 @@ def test_request_larger_than_the_budget_fails_cleanly():
     with pytest.raises(frt.FrtError) as e:
         srv.take(rid)
     assert e.value.code == frt.FRT_ENOMEM
+    srv.close()
+
+
+def test_temperature_requests_return_their_temperature():
+    steps = 3
+    probs = _requests(3, steps, seed=77)
+    for p in probs[:2]:
+        p.temperature = True
+        p.heat_ev = W.blackbody_heat(p.n_bins, T_bb=5e4)
+        p.T = np.full(p.shape, 2e3, np.float32)
+    ctx = frt.Context(0)
+    alone = []
+    for p in probs[:2]:
+        s = frt.solve_from_problem(ctx, p)
+        for _ in range(steps):
+            s.step(p.dt_s)
+        alone.append(s.temperature())
+    srv = frt.Server(frt.Context(0), budget_bytes=64 << 30, max_slots=8)
+    ids = [srv.submit(p, steps) for p in probs]
+    for rid in ids:
+        assert srv.wait(rid, 120.0) == frt.REQ_DONE
+    for Ta, rid in zip(alone, ids[:2]):
+        Tb = srv.temperature(rid)
+        print(f"served T vs alone: max rel {np.max(np.abs(Tb / Ta - 1)):.2e}, T {Ta.min():.0f}-{Ta.max():.0f} K",
+              flush=True)
+        assert np.max(np.abs(Tb / Ta - 1)) <= 1e-3 and Ta.max() > 2.5e3
+    with pytest.raises(frt.FrtError) as e:
+        srv.temperature(ids[2])
+    assert e.value.code == frt.FRT_ESTATE
+    for rid in ids:
+        srv.take(rid)
     srv.close()
