@@ -116,3 +116,25 @@ def test_device_field_and_bad_fields(ctx):
     with pytest.raises(frt.FrtError) as e:
         fresh.set_density(n2)
     assert e.value.code == frt.FRT_ESTATE
+
+
+@pytest.mark.parametrize("mode", ["standard", "generalized"])
+def test_cells_empty_before_or_after_keep_their_temperature(ctx, mode):
+    p = _problem(mode)
+    rng = np.random.Generator(np.random.PCG64(103))
+    p.n_H = np.where(rng.uniform(size=p.shape) < 0.05, np.float32(0), p.n_H).astype(np.float32)
+    n2 = np.where(rng.uniform(size=p.shape) < 0.05, np.float32(0), _path(p, 1, 107)[0]).astype(np.float32)
+    o = O.Oracle(**p.oracle_kwargs())
+    o.set_sources(p.src_pos_cm, p.ndot_bins)
+    g = frt.solve_from_problem(ctx, p, precision="f64")
+    T0 = g.temperature()
+    o.set_density(n2)
+    g.set_density(n2)
+    Tg = g.temperature()
+    empty = (p.n_H == 0) | (n2 == 0)
+    assert np.array_equal(Tg[empty], T0[empty]) and np.any(Tg[~empty] != T0[~empty])
+    np.testing.assert_allclose(Tg, o.temperature(), rtol=1e-13)
+    o.step(p.dt_s, p.uniforms(0))
+    g.step(p.dt_s)
+    assert np.max(np.abs(g.temperature() / o.temperature() - 1)) <= 1e-8
+    assert np.abs(g.fields()[0] - o.fields()[0]).max() <= 1e-9

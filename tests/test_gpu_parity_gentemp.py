@@ -118,3 +118,28 @@ def test_batch_of_generalized_and_standard_solves_with_temperature(ctx):
         assert np.abs(a.temperature() / b.temperature() - 1).max() <= 1e-10
         assert np.abs(a.fields()[0] - b.fields()[0]).max() <= 1e-12
     assert bs.ledger()["heat_in"] > 0 and bg.ledger()["heat_in"] == 0.0
+
+
+@pytest.mark.parametrize("precision,x_tol,t_rtol", [("f64", 1e-9, 1e-8), ("f32", 1e-3, 1e-3)])
+def test_ragged_box_with_empty_cells(ctx, precision, x_tol, t_rtol):
+    # a non-cubic grid (edges not multiples of the brick) with a tenth of the
+    # cells empty of hydrogen: no atoms to ionize there (the screen opens at
+    # once), no radiative terms in T
+    p = _box(n=16, seed=91, steps=3)
+    rng = np.random.Generator(np.random.PCG64(93))
+    shape = (9, 23, 14)
+    for name in ("n_H", "kappa", "x_HI0", "T"):
+        setattr(p, name, np.ascontiguousarray(getattr(p, name)[:9, :16, :14].repeat(2, axis=1)[:, :23, :]))
+    p.shape = shape
+    p.n_H = np.where(rng.uniform(size=shape) < 0.1, np.float32(0), p.n_H).astype(np.float32)
+    p.src_pos_cm = (rng.integers(0, [14, 23, 9], size=(3, 3)) + 0.5) * DX
+    p.ndot_bins = p.ndot_bins[:3]
+    o, g = _oracle(p, 3), _gpu(ctx, p, 3, precision=precision)
+    xo, xg = o.fields()[0], g.fields()[0]
+    To, Tg = o.temperature(), g.temperature()
+    print(f"[ragged {precision}] max|dx_HI| {np.abs(xo - xg).max():.2e}  max|dT/T| {np.max(np.abs(Tg / To - 1)):.2e}",
+          flush=True)
+    assert np.abs(xo - xg).max() <= x_tol and np.max(np.abs(Tg / To - 1)) <= t_rtol
+    empty = p.n_H == 0
+    assert np.all(xg[empty] == 0.0)                     # opened at once where photons arrived or not
+    assert g.ledger()["err_flags"] == 0
