@@ -351,6 +351,57 @@ def avgchem_leg(frt, W, K: int, steps: int, warmup: int, stream):
     return out
 
 
+def temperature_leg(frt, W, steps: int, warmup: int, stream):
+    """The cost of the temperature evolution (§4.1, §4.2) on the C2 box
+    (128^3, 64 sources, 4 bins, sub-grid kappa, finite c), each opacity mode
+    with the temperature off and on: gas from 1e4 K; in Standard Mode the
+    heat per photon of a 5e4 K blackbody, in the Generalized Opacity Mode
+    T_reion 2e4 K and spectral index 1.5; Hubble (3.3e-17 /s) and Compton
+    (z = 8) cooling.  ms per step, and the march's and the chemistry
+    kernels' ms per step, of each."""
+    import numpy as np
+    import torch
+
+    out = {"steps": steps, "warmup": warmup}
+    for mode in (0, 1):
+        for temp in (False, True):
+            prob = W.lognormal_c2(n_steps=warmup + steps)
+            prob.opacity_mode, prob.he_chi = mode, (0.08 if mode else 0.0)
+            if temp:
+                prob.temperature = True
+                prob.heat_ev = W.blackbody_heat(prob.n_bins, T_bb=5e4)
+                prob.T = np.full(prob.shape, 1e4, np.float32)
+                prob.hubble_s, prob.cmb_z = 3.3e-17, 8.0
+            ctx = frt.Context(0)
+            s = frt.solve_from_problem(ctx, prob, stream=stream.cuda_stream)
+            for _ in range(warmup):
+                s.step(prob.dt_s)
+            s.sync()
+            s.set_timing(True)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            for _ in range(steps):
+                s.step(prob.dt_s)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            tm = s.timing()
+            tag = f"{'generalized' if mode else 'standard'}_{'T' if temp else 'fixed_T'}"
+            out[tag] = {"ms_per_step": e0.elapsed_time(e1) / steps, "march_ms_per_step": tm["march_ms"] / steps,
+                        "chem_ms_per_step": tm["chem_ms"] / steps}
+            if temp:
+                T = s.temperature()
+                out[tag]["T_range_K"] = [float(T.min()), float(T.max())]
+                out["workload"] = (f"{prob.name}: {prob.shape[2]}^3, {prob.n_src} sources, 4 bins, kappa_sub, c, "
+                                   "dt 1 Myr")
+            s.close()
+            ctx.close()
+    for m in ("standard", "generalized"):
+        out[f"{m}_cost_ratio"] = out[f"{m}_T"]["ms_per_step"] / out[f"{m}_fixed_T"]["ms_per_step"]
+    return out
+
+
 def genopacity_leg(frt, W, steps: int, warmup: int, stream):
     """The Generalized Opacity Mode on the C2 box (128^3, 64 sources, 4 bins,
     finite c): every cell starts neutral behind its moving screen, the
@@ -655,6 +706,7 @@ def main():
     ap.add_argument("--avgchem-steps", type=int, default=10)
     ap.add_argument("--no-genopacity", action="store_true", help="skip the Generalized Opacity Mode leg")
     ap.add_argument("--no-merge", action="store_true", help="skip the ray-merging leg")
+    ap.add_argument("--no-temperature", action="store_true", help="skip the temperature-evolution leg")
     ap.add_argument("--merge-steps", type=int, default=60)
     ap.add_argument("--no-served", action="store_true", help="skip the served (request trace) leg")
     ap.add_argument("--served-requests", type=int, default=128)
@@ -826,6 +878,15 @@ def main():
             f"{go['generalized_crossings_per_s']:.3e} crossings/s (standard mode on the same box "
             f"{go['standard_ms_per_step']:.2f} ms/step); {go['front_share_of_emitted']:.2f} of photons stopped "
             f"at fronts, mean x_ion {go['mean_x_ion']:.3f}")
+    if not args.no_temperature:
+        log("temperature leg: 10 steps per mode, temperature fixed and evolving")
+        out["temperature"] = temperature_leg(frt, W, 10, 2, stream)
+        te = out["temperature"]
+        log("temperature: " + "; ".join(
+            f"{m} {te[m + '_fixed_T']['ms_per_step']:.2f} -> {te[m + '_T']['ms_per_step']:.2f} ms/step (chemistry "
+            f"{te[m + '_fixed_T']['chem_ms_per_step']:.3f} -> {te[m + '_T']['chem_ms_per_step']:.3f}, march "
+            f"{te[m + '_fixed_T']['march_ms_per_step']:.2f} -> {te[m + '_T']['march_ms_per_step']:.2f})"
+            for m in ("standard", "generalized")))
     if not args.no_merge:
         log(f"ray-merging leg: {args.merge_steps} steps without and with merging")
         out["merge"] = merge_leg(frt, W, args.merge_steps, stream)

@@ -1702,17 +1702,29 @@ constexpr double kTHI = 157807.0;           // K
 constexpr double kCompton0 = 4.0 * 6.6524587321e-25 * 7.565733e-15 * kBoltz * (2.725 * 2.725 * 2.725 * 2.725) /
                              (9.1093837015e-28 * 2.99792458e10);
 
-__device__ HRates h_rates(double T)
+// Each power x^a of the fits is exp(a ln x), with ln lambda taken once and
+// ln T = ln(2 T_HI) - ln lambda: under half the transcendental work of one
+// pow per power.  With CASE_A also alpha_A (Hui & Gnedin 1997 case-A fit,
+// 1.269e-13 lambda^1.503 / (1 + (lambda/0.522)^0.470)^1.923).
+constexpr double kLn2THI = 12.662275226919286;   // ln(2 T_HI)
+constexpr double kInvLn10 = 0.43429448190325176;
+
+template <bool CASE_A = false>
+__device__ HRates h_rates(double T, double* alpha_a = nullptr)
 {
     HRates r;
     const double lam = 2.0 * kTHI / T;
-    r.alpha = 2.753e-14 * pow(lam, 1.5) / pow(1.0 + pow(lam / 2.740, 0.407), 2.242);
-    r.coll = 21.11 * pow(T, -1.5) * exp(-0.5 * lam) * pow(lam, -1.089) / pow(1.0 + pow(lam / 0.354, 0.874), 1.101);
-    r.rec = 3.435e-30 * T * pow(lam, 1.970) / pow(1.0 + pow(lam / 2.250, 0.376), 3.720);
+    const double L = log(lam);
+    const double lnT = kLn2THI - L;
+    r.alpha = 2.753e-14 * exp(1.5 * L - 2.242 * log1p(exp(0.407 * (L - 1.007957920399979))));
+    r.coll = 21.11 * exp(-1.5 * lnT - 0.5 * lam - 1.089 * L - 1.101 * log1p(exp(0.874 * (L + 1.0384583658483626))));
+    r.rec = 3.435e-30 * T * exp(1.970 * L - 3.720 * log1p(exp(0.376 * (L - 0.8109302162163288))));
     r.ci = kBoltz * kTHI * r.coll;
-    r.ce = 7.5e-19 * exp(-118348.0 / T) / (1.0 + sqrt(T / 1e5));
-    const double g = 5.5 - log10(T);
-    r.ff = 1.42e-27 * (1.1 + 0.34 * exp(-g * g / 3.0)) * sqrt(T);
+    const double sT = sqrt(T);
+    r.ce = 7.5e-19 * exp(-118348.0 / T) / (1.0 + sT * 3.1622776601683795e-3);
+    const double g = 5.5 - lnT * kInvLn10;
+    r.ff = 1.42e-27 * (1.1 + 0.34 * exp(-g * g / 3.0)) * sT;
+    if constexpr (CASE_A) *alpha_a = 1.269e-13 * exp(1.503 * L - 1.923 * log1p(exp(0.470 * (L + 0.6500876910994983))));
     return r;
 }
 
@@ -1764,13 +1776,6 @@ __device__ double evolve_temperature(const FrtSolveDesc& D, double T, double nH,
     return substep_temperature(T, D.dt, [&](double Tv) { return c * net_gain(D, Tv, nH, x1, heat); });
 }
 
-// Case-A recombination coefficient of H (Hui & Gnedin 1997), cm^3/s.
-__device__ double alpha_case_a(double T)
-{
-    const double lam = 2.0 * kTHI / T;
-    return 1.269e-13 * pow(lam, 1.503) / pow(1.0 + pow(lam / 0.522, 0.470), 1.923);
-}
-
 // Generalized Opacity Mode (§4.2): dT/dt of a cell's ionized part at T, K/s,
 // with n_HI from photo-ionization equilibrium with its rate G: y = n_HI /
 // n_H = min(1, alpha_B(T) n_H / G) (1 where G = 0), n_e = n_HII = n_H (1 - y);
@@ -1778,10 +1783,11 @@ __device__ double alpha_case_a(double T)
 // minus the cooling of Standard Mode, over 3/2 k n_tot, n_tot = n_H (2 - y).
 __device__ double ionized_dTdt(const FrtSolveDesc& D, double T, double nH, double G)
 {
-    const HRates r = h_rates(T);
+    double aA;
+    const HRates r = h_rates<true>(T, &aA);
     const double y = G > r.alpha * nH ? r.alpha * nH / G : 1.0;
     const double ne = nH * (1.0 - y), nHI = nH * y;
-    double gain = D.heat_rec * alpha_case_a(T) * ne * ne - (r.rec + r.ff) * ne * ne - (r.ci + r.ce) * ne * nHI;
+    double gain = D.heat_rec * aA * ne * ne - (r.rec + r.ff) * ne * ne - (r.ci + r.ce) * ne * nHI;
     if (D.cmb_z >= 0.0) {
         const double z1 = 1.0 + D.cmb_z, z4 = z1 * z1 * z1 * z1;
         gain -= kCompton0 * z4 * (T - 2.725 * z1) * ne;
