@@ -848,7 +848,10 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
     __shared__ unsigned long long s_lc[LC_NC];
     __shared__ uint32_t s_key[KEY_SLOTS], s_cnt[KEY_SLOTS];
     __shared__ uint32_t s_bin[NBIN];
-    __shared__ uint16_t s_order[ITEM];
+    // the current generation's packets in march order, as their record
+    // indices (in the pass input for generation 0, in the scratch records
+    // after it), so that a chunk's records are one load away
+    __shared__ uint32_t s_order[ITEM];
     __shared__ uint32_t s_nv, s_chunk, s_next, s_xn;
     __shared__ uint8_t s_par[BT / WAVE][16];   // lanes of a round's split parents, per wave
     const uint32_t nwork = ws.ctr[C_NWORK];
@@ -919,12 +922,17 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         // all of the item's loads at once: its packets' crossing bins (NBIN
         // marks no packet), then the brick's opacities (-1 for cells outside
         // the grid, which a packet reaching them has left the box through)
-        uint32_t eq[PER];
+        uint32_t eq[PER], ei[PER];
 #pragma unroll
         for (int q = 0; q < PER; q++) {
             const uint32_t j = (uint32_t)q * BT + threadIdx.x;
             eq[q] = NBIN;
-            if (j < w.count && w.start + j < np) eq[q] = ws.sorted[w.start + j].y;
+            ei[q] = 0;
+            if (j < w.count && w.start + j < np) {
+                const uint2 e = ws.sorted[w.start + j];
+                eq[q] = e.y;
+                ei[q] = e.x;
+            }
         }
         R2 st[NST];
 #pragma unroll
@@ -960,7 +968,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         // ---- order packets by expected crossings: a counting sort of up to
         // ITEM packets (bin NBIN: no packet) into s_order, whose bin counts
         // are taken once per distinct bin of a wave; s_bin starts at zero
-        auto order_by_bin = [&](const uint32_t* eqv) -> uint32_t {
+        auto order_by_bin = [&](const uint32_t* eqv, const uint32_t* idxv) -> uint32_t {
             uint32_t slot_of[PER];
 #pragma unroll
             for (int q = 0; q < PER; q++) {
@@ -991,7 +999,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
 #pragma unroll
             for (int q = 0; q < PER; q++)
                 if (slot_of[q] != 0xffffffffu)
-                    s_order[s_bin[slot_of[q] >> 16] + (slot_of[q] & 0xffffu)] = (uint16_t)((uint32_t)q * BT + threadIdx.x);
+                    s_order[s_bin[slot_of[q] >> 16] + (slot_of[q] & 0xffffu)] = idxv[q];
             __syncthreads();
             return n;
         };
@@ -1000,10 +1008,10 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         const uint32_t n_item = w.start < np ? min(w.count, np - w.start) : 0u;
         uint32_t n_cur = n_item;
         if (n_item <= (uint32_t)WAVE) {
-            if (threadIdx.x < n_item) s_order[threadIdx.x] = (uint16_t)threadIdx.x;
+            if (threadIdx.x < n_item) s_order[threadIdx.x] = ei[0];
             __syncthreads();
         } else {
-            n_cur = order_by_bin(eq);
+            n_cur = order_by_bin(eq, ei);
         }
         const Real r_cap = uni((Real)D.r_cap);
         const Real floor_f = uni((Real)D.floor);
@@ -1043,8 +1051,8 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                 double v_abs = 0.0, v_sub = 0.0, v_end = 0.0;
                 uint32_t v_cross = 0;
                 if (active) {
-                    if (gen == 0) load_pkt<Real>(in_q, ws.sorted[w.start + s_order[p]].x, h, T);
-                    else load_pkt<Real>(x_q, x_base + g_lo + s_order[p], h, T);
+                    if (gen == 0) load_pkt<Real>(in_q, s_order[p], h, T);
+                    else load_pkt<Real>(x_q, s_order[p], h, T);
                     level = (int)(h.lp >> 28);
                     const double* sp = src_pos_of(D, h.src);
                     s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
@@ -1480,20 +1488,21 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
             if (threadIdx.x == 0) s_chunk = 0;
             if (g_hi - g_lo <= (uint32_t)WAVE) {
                 // one wave marches them all: their order makes no difference
-                if (threadIdx.x < g_hi - g_lo) s_order[threadIdx.x] = (uint16_t)threadIdx.x;
+                if (threadIdx.x < g_hi - g_lo) s_order[threadIdx.x] = x_base + g_lo + threadIdx.x;
                 __syncthreads();
                 n_cur = g_hi - g_lo;
                 continue;
             }
             if (threadIdx.x < NBIN) s_bin[threadIdx.x] = 0;
-            uint32_t ex[PER];
+            uint32_t ex[PER], xi[PER];
 #pragma unroll
             for (int q = 0; q < PER; q++) {
                 const uint32_t j = (uint32_t)q * BT + threadIdx.x;
-                ex[q] = j < g_hi - g_lo ? recs<Real>(x_q)[x_base + g_lo + j].key : (uint32_t)NBIN;
+                xi[q] = x_base + g_lo + j;
+                ex[q] = j < g_hi - g_lo ? recs<Real>(x_q)[xi[q]].key : (uint32_t)NBIN;
             }
             __syncthreads();
-            n_cur = order_by_bin(ex);
+            n_cur = order_by_bin(ex, xi);
         }
         {
             const double t_abs = wave_sum(acc_abs);
