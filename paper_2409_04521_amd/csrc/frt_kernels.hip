@@ -112,6 +112,35 @@ __device__ __forceinline__ double uni(double v)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// Device memory through pointers the compiler cannot prove global (they
+// come from the descriptor or a struct passed by value): their accesses
+// are made global ones here rather than flat ones, which also count
+// against the LDS wait counter, so that a later wait for an LDS result
+// would wait for them as well.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* gmem(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+template <typename T>
+__device__ __forceinline__ T ld_global(const T* p)
+{
+    return *(const __attribute__((address_space(1))) T*)p;
+}
+// atomicAdd's relaxed, device-scope add on global memory
+__device__ __forceinline__ uint32_t g_atomic_add(uint32_t* p, uint32_t v)
+{
+    return __hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_atomic_add(float* p, float v)
+{
+    (void)__hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void g_atomic_add(double* p, double v)
+{
+    (void)__hip_atomic_fetch_add(gmem(p), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <typename Real> struct Vec2;
 template <> struct Vec2<float> { using T = float2; };
 template <> struct Vec2<double> { using T = double2; };
@@ -230,7 +259,14 @@ __device__ __forceinline__ void store_pkt(const FrtRecs& q, uint32_t i, const Pk
     for (int a = 0; a < 3; a++) x.dir[a] = h.d[a];
 #pragma unroll
     for (int b = 0; b < 4; b++) x.tau[b] = T[b];
-    recs<Real>(q)[i] = x;
+    // written as whole 16-byte words, global stores
+    static_assert(sizeof(FrtRec<Real>) % 16 == 0, "records are whole 16-byte words");
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 wd[sizeof(FrtRec<Real>) / 16];
+    __builtin_memcpy(wd, &x, sizeof(x));
+    __attribute__((address_space(1))) u32x4* dst = (__attribute__((address_space(1))) u32x4*)(recs<Real>(q) + i);
+#pragma unroll
+    for (int k = 0; k < (int)(sizeof(FrtRec<Real>) / 16); k++) dst[k] = wd[k];
 }
 
 // Append slot i of the launch's output buffer: the record and its key.
@@ -238,14 +274,19 @@ template <typename Real>
 __device__ __forceinline__ void store_out(const FrtWS& ws, uint32_t i, const Pkt<Real>& h, uint32_t key, const Real* T)
 {
     store_pkt<Real>(out_recs(ws), i, h, key, T);
-    (ws.out ? ws.bkey[1] : ws.bkey[0])[i] = key;
+    *gmem((ws.out ? ws.bkey[1] : ws.bkey[0]) + i) = key;
 }
 
 template <typename Real>
 __device__ __forceinline__ void packet_dir(const FrtSolveDesc& D, uint32_t lp, uint32_t estep, uint32_t src, Real d[3])
 {
+    // the rotation's loads first, the pixel centre's arithmetic while they fly
+    const double* qp = rot_of(D, estep, src);
+    double q[4];
+#pragma unroll
+    for (int k = 0; k < 4; k++) q[k] = ld_global(qp + k);
     nest_pixel_centre<Real>((int)(lp >> 28), lp & 0x0fffffffu, d);
-    quat_rotate<Real>(rot_of(D, estep, src), d);
+    quat_rotate<Real>(q, d);
 }
 
 // Cell of the point s + r d for a packet moving along d: floor per axis,
@@ -774,7 +815,7 @@ __device__ __forceinline__ uint32_t wave_reserve_small(uint32_t* ctr, uint32_t n
     const uint32_t total = (uint32_t)__popcll(m0) + 2u * (uint32_t)__popcll(m1) + 4u * (uint32_t)__popcll(m2);
     if (total == 0) return 0;
     uint32_t base = 0;
-    if ((threadIdx.x & (WAVE - 1)) == 0) base = atomicAdd(ctr, total);
+    if ((threadIdx.x & (WAVE - 1)) == 0) base = g_atomic_add(ctr, total);
     base = __shfl(base, 0, WAVE);
     return base + lanes_below(m0) + 2u * lanes_below(m1) + 4u * lanes_below(m2);
 }
@@ -787,11 +828,35 @@ __device__ __forceinline__ uint32_t reserve_begin(uint32_t* ctr, uint32_t n_lane
     const unsigned long long m0 = __ballot(n_lane & 1u), m1 = __ballot(n_lane & 2u), m2 = __ballot(n_lane & 4u);
     const uint32_t total = (uint32_t)__popcll(m0) + 2u * (uint32_t)__popcll(m1) + 4u * (uint32_t)__popcll(m2);
     *raw = 0;
-    if ((threadIdx.x & (WAVE - 1)) == 0 && total) *raw = atomicAdd(ctr, total);
+    if ((threadIdx.x & (WAVE - 1)) == 0 && total) *raw = g_atomic_add(ctr, total);
     return lanes_below(m0) + 2u * lanes_below(m1) + 4u * lanes_below(m2);
 }
 
 __device__ __forceinline__ uint32_t reserve_end(uint32_t raw, uint32_t off) { return uni(raw) + off; }
+
+// A packet's origin and photons per bin per unit cast weight, from the
+// solve's source tables or (merged packets) its virtual-origin table, all
+// loads issued together.
+template <typename Real, int NB>
+__device__ __forceinline__ void source_of(uint32_t src, const double* pos_t, const Real* spec_t, const FrtVSrc* vt_t,
+                                          Real s[3], Real spec[NB])
+{
+    if (!is_virtual(src)) {
+        double o[3];
+#pragma unroll
+        for (int a = 0; a < 3; a++) o[a] = ld_global(pos_t + (size_t)src * 3 + a);
+#pragma unroll
+        for (int b = 0; b < NB; b++) spec[b] = ld_global(spec_t + (size_t)src * NB + b);
+#pragma unroll
+        for (int a = 0; a < 3; a++) s[a] = (Real)o[a];
+    } else {
+        const FrtVSrc* v = vt_t + (src & ~FRT_VSRC);
+#pragma unroll
+        for (int a = 0; a < 3; a++) s[a] = (Real)ld_global(&v->pos[a]);
+#pragma unroll
+        for (int b = 0; b < NB; b++) spec[b] = (Real)ld_global(&v->spec[b]);
+    }
+}
 
 // One workgroup per work item (one brick, up to FRT_ITEM_RAYS packets).
 // The item's packets are first ordered by their expected crossings (a
@@ -1023,6 +1088,12 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
         const bool gmode = SUB && uni(D.gen) != 0;
         const Real budget = uni((Real)D.budget);
         const uint32_t step = uni(D.step);
+        // the source tables, taken once per item
+        const double* const pos_t = D.src_pos;
+        const Real* spec_t;
+        if constexpr (F32) spec_t = D.spec;
+        else spec_t = D.specd;
+        const FrtVSrc* const vt_t = D.vt[D.cur];
         // absorbed photons and crossings of this lane's packets, reduced
         // over the wave once per item
         double acc_abs = 0.0;
@@ -1054,16 +1125,15 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                     if (gen == 0) load_pkt<Real>(in_q, s_order[p], h, T);
                     else load_pkt<Real>(x_q, s_order[p], h, T);
                     level = (int)(h.lp >> 28);
-                    const double* sp = src_pos_of(D, h.src);
-                    s[0] = (Real)sp[0]; s[1] = (Real)sp[1]; s[2] = (Real)sp[2];
+                    Real spec[NB];
+                    source_of<Real, NB>(h.src, pos_t, spec_t, vt_t, s, spec);
                     if (h.estep != step && h.rstop <= h.r) h.rstop = h.r + budget;   // carried: fresh budget
                     if (h.estep == step && h.r == Real(0) && level == base_level) h.rstop = budget;
                     Real sum0 = 0;
                     double n_start = 0.0;
 #pragma unroll
                     for (int b = 0; b < NB; b++) {
-                        const Real spec = spec_of<Real>(D, h.src, NB, b);
-                        N0[b] = h.w0 * spec;
+                        N0[b] = h.w0 * spec[b];
                         NE[b] = N0[b] * (SUB ? exp_neg(srel[b] * T[0] + T[1]) : exp_neg(srel[b] * T[0]));
                         sum0 += N0[b];
                         n_start += (double)NE[b];
@@ -1323,7 +1393,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                 const unsigned long long m_next = __ballot(end == 4), m_par = __ballot(end == 0);
                 const uint32_t n_out = (uint32_t)__popcll(m_next);
                 uint32_t o_raw = 0;
-                if (lane == 0 && n_out) o_raw = atomicAdd(o_ctr(ws, my_seg()), n_out);
+                if (lane == 0 && n_out) o_raw = g_atomic_add(o_ctr(ws, my_seg()), n_out);
                 const uint32_t ocap_seg = seg_cap(ws.buf[0].cap);
                 const uint32_t oseg0 = (uint32_t)my_seg() * ocap_seg;
                 // ---- ledger: counts from ballots, photon terms from wave sums
@@ -1525,7 +1595,7 @@ __device__ __forceinline__ void brick_march(const FrtSolveDesc* __restrict__ des
                 if constexpr (!SUB) v = v * (KS * fast_rcp<Real>(s_op[PADC + t]));
                 const int lx = t & (BX - 1), ly = (t >> LX) & (BY - 1), lz = t >> (LX + LY);
                 const size_t ci = (size_t)(ox + lx) + (size_t)nx * ((size_t)(oy + ly) + (size_t)ny * (size_t)(oz + lz));
-                atomicAdd(gam + ci, v);
+                g_atomic_add(gam + ci, v);
             }
         }
         if constexpr (HEAT) {
